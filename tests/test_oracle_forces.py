@@ -1,0 +1,209 @@
+"""Pins of the oracle's two force reductions (Sec. 2.3) and rigid-body update.
+
+Momentum exchange (Eq. MMEL, its sum and Eq. fluidtorque):
+  * momentum balance: for a body at rest, the momentum that streaming moves
+    into the solid cells equals the link sum exactly, for any state;
+  * the link form equals the per-destination ("pulled") form of the same
+    exchange, also for a moving body (u_G and torque arms included);
+  * zero force at rest, for a body-free uniform flow seen through a virtual
+    contour, and for a disk moving with the flow (Galilean invariance);
+  * mirror symmetry: the disk channel is symmetric about its mid row, so the
+    lift and torque vanish.
+Stress integration (Eq. defFf and the sigma definition):
+  * Poiseuille: sigma_xy = rho0 nu du/dy = G/2 (ny - 1 - 2y) at any node;
+  * Taylor-Green: deviatoric normal stress 2 rho nu du/dx and zero shear;
+  * the same zero-force and symmetry cases as above.
+Rigid body (Eqs. dep1, theta2): closed forms of uniform acceleration.
+"""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+CX, CY = O.CX, O.CY
+OPP = [0, 3, 4, 1, 2, 7, 8, 5, 6]
+MAGIC_TAU = 0.5 + math.sqrt(3.0 / 16.0)
+
+
+def random_state(lat, seed, amp=0.03):
+    ux, uy = W.smooth_random_velocity(lat.nx, lat.ny, seed=seed, amp=amp)
+    rho = W.random_density(lat.nx, lat.ny, seed=seed + 1, amp=1e-3)
+    lat.set_fields(rho, ux, uy)
+    g = np.random.default_rng(seed + 2)
+    lat.ft += 1e-4 * g.standard_normal(lat.ft.shape)  # off-equilibrium parts
+
+
+def solid_momentum(f, solid):
+    m = solid.astype(bool)
+    return np.array([(f[m] * CX).sum(), (f[m] * CY).sum()])
+
+
+def test_me_momentum_balance_identity():
+    lat = O.RefLattice(40, 36, 0.7, 1e-4)
+    lat.set_disk(19.4, 17.8, 7.3)
+    random_state(lat, 21)
+    for _ in range(3):
+        before = solid_momentum(lat.ft, lat.solid)
+        lat.step(1)
+        after = solid_momentum(lat.streamed(), lat.solid)
+        me = lat.hist_me[-1]
+        assert np.abs((after - before) - me[:2]).max() <= 1e-14 * max(1.0, np.abs(me[:2]).max())
+
+
+def pulled_form(lat, f_streamed, body):
+    """Per-destination form of the exchange: at every node, every pulled
+    population that crossed the solid/fluid boundary, signed by direction,
+    with the link midpoint measured from the link's fluid node."""
+    bx, by, th, bu, bv, bw = body
+    solid = lat.solid
+    ny, nx = solid.shape
+    F = np.zeros(2)
+    T = 0.0
+    for y in range(ny):
+        for x in range(nx):
+            for a in range(1, 9):
+                sx, sy = (x - CX[a]) % nx, (y - CY[a]) % ny
+                if solid[y, x] == solid[sy, sx]:
+                    continue
+                if solid[y, x]:   # fluid -> solid: fluid node is the source
+                    gx, gy, s = sx + 0.5 * CX[a], sy + 0.5 * CY[a], 1.0
+                else:             # solid -> fluid: fluid node is this node
+                    gx, gy, s = x - 0.5 * CX[a], y - 0.5 * CY[a], -1.0
+                ugx, ugy = bu - bw * (gy - by), bv + bw * (gx - bx)
+                lx = s * (CX[a] - ugx) * f_streamed[y, x, a]
+                ly = s * (CY[a] - ugy) * f_streamed[y, x, a]
+                F += (lx, ly)
+                T += (gx - bx) * ly - (gy - by) * lx
+    return np.array([F[0], F[1], T])
+
+
+def test_me_link_form_equals_pulled_form_moving_body():
+    lat = O.RefLattice(30, 26, 0.65, 1e-4)
+    lat.set_disk(14.6, 12.2, 6.1)
+    b = lat.body
+    b.u, b.v, b.omega = 0.013, -0.007, 0.0021  # velocities only; mask stays
+    random_state(lat, 31)
+    body = lat.body_state().copy()
+    lat.step(1)
+    me = lat.hist_me[-1]
+    ref = pulled_form(lat, lat.streamed(), body)
+    assert np.abs(me - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_zero_force_at_rest():
+    lat = O.RefLattice(40, 30, 0.8, 1e-4)
+    lat.set_disk(20.0, 15.0, 6.0)
+    xy, n, ds = W.disk_si_points(20.0, 15.0, 6.0, 64)
+    lat.set_si_points(xy, n, ds)
+    lat.init_uniform(1.0, 0.0, 0.0)
+    f0 = lat.ft.copy()
+    lat.step(20)
+    # f^eq(1, 0) = w_a; only the rounding of sum(w) = 1 moves it
+    assert np.abs(lat.ft - f0).max() <= 1e-15
+    assert np.abs(lat.me()).max() <= 1e-15
+    assert np.abs(lat.si()).max() <= 1e-15
+
+
+def test_zero_force_body_free_uniform_flow():
+    # eta = +inf: the disk only marks links and sample nodes (a virtual contour)
+    U = (0.04, -0.015)
+    lat = O.RefLattice(48, 40, 0.7, float("inf"))
+    lat.set_disk(23.3, 19.6, 8.4)
+    xy, n, ds = W.disk_si_points(23.3, 19.6, 8.4, 96)
+    lat.set_si_points(xy, n, ds)
+    one = np.ones((lat.ny, lat.nx))
+    lat.set_fields(one, U[0] * one, U[1] * one)  # inside the contour too
+    lat.step(10)
+    assert np.abs(lat.me()).max() <= 1e-13
+    assert np.abs(lat.si()).max() <= 1e-13
+
+
+def test_zero_force_disk_moving_with_the_flow():
+    U = (0.03, 0.02)
+    lat = O.RefLattice(64, 48, 0.7, 1e-4)
+    lat.set_disk(20.0, 20.0, 7.0)
+    xy, n, ds = W.disk_si_points(20.0, 20.0, 7.0, 96)
+    lat.set_si_points(xy, n, ds)
+    lat.set_motion(20.0, 20.0, 0.0, U[0], U[1], 0.0)
+    lat.init_uniform(1.0, *U)
+    lat.step(60)  # the mask moves by more than a cell
+    assert abs(lat.body.x - (20.0 + 60 * U[0])) < 1e-12
+    assert np.abs(lat.me()).max() <= 1e-13
+    assert np.abs(lat.si()).max() <= 1e-13
+
+
+def test_disk_channel_mirror_symmetry():
+    case = W.case_disk_channel(steps=600)
+    lat = O.RefLattice.from_case(case)
+    lat.step(case.steps)
+    me, si = lat.me()[-1], lat.si()[-1]
+    assert me[0] > 0 and si[0] > 0
+    assert abs(me[1]) <= 1e-10 * me[0] and abs(si[1]) <= 1e-10 * si[0]
+    assert abs(me[2]) <= 1e-10 * me[0] * 8 and abs(si[2]) <= 1e-10 * si[0] * 8
+
+
+def test_si_poiseuille_shear():
+    G, ny, nx = 1e-6, 16, 4
+    nu = (MAGIC_TAU - 0.5) / 3
+    lat = O.RefLattice(nx, ny, MAGIC_TAU, float("inf"), south=(O.VELOCITY, 0, 0), north=(O.VELOCITY, 0, 0), gx=G)
+    y0 = 3
+    xy = np.array([[x, y0] for x in range(nx)], float)
+    n = np.tile([0.0, 1.0], (nx, 1))
+    lat.set_si_points(xy, n, np.ones(nx))
+    lat.init_uniform(1.0, 0.0, 0.0)
+    lat.step(int(30 * ny * ny / nu))
+    Fx = lat.hist_si[-1][0]
+    assert abs(Fx - nx * G / 2 * (ny - 1 - 2 * y0)) <= 1e-9 * abs(Fx)
+    # lower wall line, normal pointing down: the fluid pulls the wall along +x
+    xy[:, 1] = 0
+    n[:, 1] = -1.0
+    lat.set_si_points(xy, n, np.ones(nx))
+    lat.step(1)
+    assert abs(lat.hist_si[-1][0] + nx * G / 2 * (ny - 1)) <= 1e-9 * nx * G * ny
+
+
+def test_si_taylor_green_stress():
+    L, tau, U0 = 64, 0.8, 0.01
+    nu = (tau - 0.5) / 3
+    k = 2 * math.pi / L
+    x = np.arange(L)[None, :]
+    y = np.arange(L)[:, None]
+    p = -U0 ** 2 / 4 * (np.cos(2 * k * x) + np.cos(2 * k * y))
+    lat = O.RefLattice(L, L, tau, float("inf"))
+    lat.set_fields(1 + 3 * p, -U0 * np.cos(k * x) * np.sin(k * y), U0 * np.sin(k * x) * np.cos(k * y))
+    nsteps = 40
+    lat.step(nsteps)
+    f = lat.streamed()
+    dec = math.exp(-2 * nu * k * k * nsteps)
+    for (i, j) in [(5, 9), (13, 3), (40, 22)]:
+        s = np.zeros(3)
+        O.lib().orc_node_stress(C.byref(lat.p), np.ascontiguousarray(f[j, i]), s)
+        dudx = U0 * dec * k * math.sin(k * i) * math.sin(k * j)
+        assert abs(0.5 * (s[0] - s[2]) - 2 * nu * dudx) <= 0.02 * abs(2 * nu * dudx)
+        assert abs(s[1]) <= 0.01 * abs(2 * nu * dudx) + 1e-9
+
+
+def test_newton_euler_uniform_acceleration():
+    b = O._Body()
+    b.x, b.y = 5.0, 100.0
+    rho_s, g = 1.5, -1e-4
+    a = (1 - 1 / rho_s) * g
+    for n in range(1, 200):
+        O.lib().orc_body_update(C.byref(b), np.zeros(3), 10.0, 3.0, 1.0, rho_s, 0.0, g)
+        # semi-implicit Euler: v_n = n a, y_n = y_0 + a n (n + 1) / 2
+        assert abs(b.v - n * a) <= 1e-15 * n
+        assert abs(b.y - (100.0 + a * n * (n + 1) / 2)) <= 1e-12
+    assert b.x == 5.0 and b.u == 0.0 and b.omega == 0.0
+
+
+def test_newton_euler_constant_force_and_torque():
+    b = O._Body()
+    m, inertia, F, T = 50.0, 120.0, 2e-3, -3e-4
+    for n in range(1, 100):
+        O.lib().orc_body_update(C.byref(b), np.array([F, 0.0, T]), m, inertia, 1.0, 2.0, 0.0, 0.0)
+        assert abs(b.x - F / m * n * (n + 1) / 2) <= 1e-14
+        assert abs(b.theta - T / inertia * n * (n + 1) / 2) <= 1e-14

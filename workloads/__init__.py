@@ -1,0 +1,262 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only describes *inputs*: lattice sizes, edge conditions,
+relaxation parameters, body geometry (disk, NACA 0012 polygon) and the
+quadrature points handed to stress integration.  It holds none of the
+method's arithmetic (no streaming, collision, penalization, mask test or
+force sum), so both the HIP path and the CPU oracle can draw from it without
+sharing any of the computation they are compared on.
+
+Geometry sources:
+  * NACA 0012: the standard 4-digit half-thickness polynomial with t = 0.12
+    (the paper names the airfoil in its Applications section, NACA subsection,
+    without printing the shape); the open trailing edge is closed by one
+    straight segment.
+  * Placement: the paper's NACA domain figure puts the leading edge 4 chords
+    behind the inlet and centres it vertically; the synthetic 10c x 5c
+    domain used here keeps the same layout scaled to 3c / 2.5c, rotated nose
+    up by the angle of attack about the quarter chord.
+  * Stress-integration points: segment midpoints of the body outline, the
+    outward segment normal and the segment length as integration surface
+    (the paper leaves the placement of its integration points free).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+# Edge condition kinds (the integers are part of the C ABI of both sides).
+PERIODIC, VELOCITY, FREESLIP, OUTFLOW = 0, 1, 2, 3
+EDGE_NAMES = {PERIODIC: "periodic", VELOCITY: "velocity", FREESLIP: "freeslip", OUTFLOW: "outflow"}
+
+
+@dataclasses.dataclass
+class Edge:
+    kind: int = PERIODIC
+    ux: float = 0.0
+    uy: float = 0.0
+
+
+@dataclasses.dataclass
+class Case:
+    """One synthetic VP-LBM workload (lattice + body + quadrature)."""
+
+    name: str
+    nx: int
+    ny: int
+    tau: float
+    eta: float
+    west: Edge
+    east: Edge
+    south: Edge
+    north: Edge
+    rho0: float = 1.0
+    u_init: tuple = (0.0, 0.0)
+    gx: float = 0.0  # uniform body-force density (tests only)
+    gy: float = 0.0
+    disk: Optional[tuple] = None  # (xc, yc, r)
+    polygon: Optional[np.ndarray] = None  # (nvert, 2) float64, counter-clockwise
+    ref_point: Optional[tuple] = None  # torque reference x_G for polygons
+    si_xy: Optional[np.ndarray] = None  # (npts, 2)
+    si_n: Optional[np.ndarray] = None  # (npts, 2) outward unit normals
+    si_ds: Optional[np.ndarray] = None  # (npts,)
+    steps: int = 0
+    # free body (sedimentation): density ratio, gravity, force source 0=ME 1=SI
+    rho_s: Optional[float] = None
+    grav: tuple = (0.0, 0.0)
+    force_source: int = 0
+    length_scale: float = 1.0  # chord or diameter for coefficients
+    u_ref: float = 0.0
+
+
+def tau_from_re(u: float, length: float, re: float) -> float:
+    """Relaxation time from a Reynolds number (nu = c_s^2 (tau - 1/2))."""
+    nu = u * length / re
+    return 0.5 + 3.0 * nu
+
+
+# ----------------------------------------------------------------------------
+# geometry generators
+# ----------------------------------------------------------------------------
+
+def disk_si_points(xc: float, yc: float, r: float, npts: int):
+    """npts points evenly spaced on a circle, offset by half a spacing."""
+    th = 2.0 * math.pi * (np.arange(npts) + 0.5) / npts
+    n = np.stack([np.cos(th), np.sin(th)], axis=1)
+    xy = np.stack([xc + r * n[:, 0], yc + r * n[:, 1]], axis=1)
+    ds = np.full(npts, 2.0 * math.pi * r / npts)
+    return xy, n, ds
+
+
+def naca4_half_thickness(x: np.ndarray, t: float = 0.12) -> np.ndarray:
+    """Half thickness of a symmetric NACA 4-digit section, x in chords."""
+    return 5.0 * t * (0.2969 * np.sqrt(x) - 0.1260 * x - 0.3516 * x ** 2
+                      + 0.2843 * x ** 3 - 0.1015 * x ** 4)
+
+
+def naca0012_polygon(chord: float, le_x: float, le_y: float, aoa_deg: float,
+                     n_side: int = 200) -> np.ndarray:
+    """Counter-clockwise outline: lower surface LE->TE, TE closure, upper TE->LE.
+
+    Points are cosine spaced in x/c.  The section is rotated nose up by
+    ``aoa_deg`` about its quarter chord (flow along +x, lift along +y).
+    Returns ``(2*n_side + 1, 2)`` vertices; the polygon closes implicitly.
+    """
+    k = np.arange(n_side + 1)
+    xc = 0.5 * (1.0 - np.cos(math.pi * k / n_side))  # 0 (LE) .. 1 (TE)
+    yt = naca4_half_thickness(xc)
+    lower = np.stack([xc, -yt], axis=1)               # LE .. TE
+    upper = np.stack([xc[::-1], yt[::-1]], axis=1)     # TE .. LE
+    pts = np.concatenate([lower, upper[:-1]], axis=0)  # LE shared once
+    pts = pts * chord
+    # rotate nose-up (clockwise in x-right/y-up axes) about the quarter chord
+    a = -math.radians(aoa_deg)
+    px, py = 0.25 * chord, 0.0
+    ca, sa = math.cos(a), math.sin(a)
+    dx, dy = pts[:, 0] - px, pts[:, 1] - py
+    rx = px + ca * dx - sa * dy
+    ry = py + sa * dx + ca * dy
+    return np.stack([rx + le_x, ry + le_y], axis=1)
+
+
+def polygon_si_points(poly: np.ndarray):
+    """Segment midpoints, outward normals and lengths of a CCW polygon."""
+    p0 = poly
+    p1 = np.roll(poly, -1, axis=0)
+    d = p1 - p0
+    ln = np.hypot(d[:, 0], d[:, 1])
+    n = np.stack([d[:, 1] / ln, -d[:, 0] / ln], axis=1)  # right of travel = outward
+    mid = 0.5 * (p0 + p1)
+    return mid, n, ln
+
+
+def polygon_centroid(poly: np.ndarray):
+    """Area centroid of a simple polygon (shoelace form)."""
+    x, y = poly[:, 0], poly[:, 1]
+    x1, y1 = np.roll(x, -1), np.roll(y, -1)
+    cr = x * y1 - x1 * y
+    a = 0.5 * cr.sum()
+    cx = ((x + x1) * cr).sum() / (6.0 * a)
+    cy = ((y + y1) * cr).sum() / (6.0 * a)
+    return float(cx), float(cy), float(a)
+
+
+# ----------------------------------------------------------------------------
+# named workloads
+# ----------------------------------------------------------------------------
+
+def case_disk_channel(nx: int = 128, ny: int = 64, steps: int = 2000, npts: int = 128) -> Case:
+    """FP64 correctness case: 128x64 channel, disk r=8 at (32,32), Re=20 on D.
+
+    West: uniform inflow 0.05 (half-way bounce-back), east: zero-gradient,
+    south/north: periodic, eta = 1e-4, tau = 0.62.
+    """
+    u_in, r = 0.05, 8.0
+    xy, n, ds = disk_si_points(32.0, 32.0, r, npts)
+    return Case(
+        name=f"disk_channel_{nx}x{ny}", nx=nx, ny=ny, tau=tau_from_re(u_in, 2 * r, 20.0), eta=1e-4,
+        west=Edge(VELOCITY, u_in, 0.0), east=Edge(OUTFLOW), south=Edge(PERIODIC), north=Edge(PERIODIC),
+        u_init=(u_in, 0.0), disk=(32.0, 32.0, r), si_xy=xy, si_n=n, si_ds=ds, steps=steps,
+        length_scale=2 * r, u_ref=u_in)
+
+
+def case_naca(chord: int = 200, aoa_deg: float = 10.0, steps: int = 200000, n_side: int = 200,
+              re: float = 1000.0, u_in: Optional[float] = None, eta: float = 1e-4) -> Case:
+    """NACA 0012 in a 10c x 5c channel at Re=1000.
+
+    West: uniform inflow (half-way bounce-back), east: zero-gradient,
+    south/north: free-slip.  The inflow speed is 0.05*200/c so tau = 0.53 for
+    every chord.
+    """
+    if u_in is None:
+        u_in = 0.05 * 200.0 / chord
+    nx, ny = 10 * chord, 5 * chord
+    poly = naca0012_polygon(float(chord), 3.0 * chord, 2.5 * chord, aoa_deg, n_side)
+    xy, n, ds = polygon_si_points(poly)
+    cx, cy, _ = polygon_centroid(poly)
+    return Case(
+        name=f"naca0012_c{chord}_aoa{aoa_deg:g}", nx=nx, ny=ny, tau=tau_from_re(u_in, chord, re), eta=eta,
+        west=Edge(VELOCITY, u_in, 0.0), east=Edge(OUTFLOW), south=Edge(FREESLIP), north=Edge(FREESLIP),
+        u_init=(u_in, 0.0), polygon=poly, ref_point=(cx, cy), si_xy=xy, si_n=n, si_ds=ds, steps=steps,
+        length_scale=float(chord), u_ref=u_in)
+
+
+def case_sedimentation(nx: int = 400, ny: int = 2000, d: float = 20.0, rho_r: float = 1.5,
+                       g: float = 5.5e-5, x0_frac: float = 0.4, y0: Optional[float] = None,
+                       steps: int = 100000, npts: int = 64, force_source: int = 0) -> Case:
+    """Disk settling under gravity in a vertical channel.
+
+    West/east: no-slip (velocity 0), north: velocity 0, south: zero-gradient.
+    tau = 0.6; g of about 5.5e-5 gives a terminal Reynolds number near 10
+    (estimated from a drag balance, not from the paper).
+    """
+    r = 0.5 * d
+    xc = x0_frac * nx
+    yc = (ny - 5.0 * d) if y0 is None else y0
+    xy, n, ds = disk_si_points(xc, yc, r, npts)
+    return Case(
+        name=f"sediment_{nx}x{ny}_d{d:g}", nx=nx, ny=ny, tau=0.6, eta=1e-4,
+        west=Edge(VELOCITY), east=Edge(VELOCITY), south=Edge(OUTFLOW), north=Edge(VELOCITY),
+        u_init=(0.0, 0.0), disk=(xc, yc, r), si_xy=xy, si_n=n, si_ds=ds, steps=steps,
+        rho_s=rho_r, grav=(0.0, -g), force_source=force_source, length_scale=d)
+
+
+def sweep_cases(ncases: int = 64, chords=(100, 150, 200), max_aoa: float = 20.0):
+    """Angle-of-attack sweep: case k uses chord chords[k % 3], AoA = max_aoa*k/(n-1)."""
+    out = []
+    for k in range(ncases):
+        c = chords[k % len(chords)]
+        aoa = max_aoa * k / max(ncases - 1, 1)
+        out.append(case_naca(chord=c, aoa_deg=aoa))
+    return out
+
+
+def serving_trace(nreq: int = 500, seed: int = 0, rate: float = 1.0,
+                  grids=((256, 256), (512, 256), (1024, 512), (2048, 1024)),
+                  steps_range=(1e4, 1e5)):
+    """Poisson arrivals mixing airfoil and sedimentation requests.
+
+    Returns a list of dicts (arrival time in seconds, kind, nx, ny, steps,
+    geometry parameters).  ``rate`` is requests per second.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for i in range(nreq):
+        t += rng.exponential(1.0 / rate)
+        kind = "airfoil" if rng.random() < 0.5 else "sediment"
+        nx, ny = grids[rng.integers(len(grids))]
+        steps = int(round(math.exp(rng.uniform(math.log(steps_range[0]), math.log(steps_range[1])))))
+        r = {"id": i, "arrival": t, "kind": kind, "nx": int(nx), "ny": int(ny), "steps": steps}
+        if kind == "airfoil":
+            r["aoa"] = float(rng.uniform(0.0, 20.0))
+        else:
+            r["x0"] = float(rng.uniform(0.3, 0.7))
+        reqs.append(r)
+    return reqs
+
+
+def smooth_random_velocity(nx: int, ny: int, seed: int, amp: float = 0.02, modes: int = 3):
+    """Smooth periodic random velocity field (sum of a few Fourier modes)."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(nx)[None, :]
+    y = np.arange(ny)[:, None]
+    ux = np.zeros((ny, nx))
+    uy = np.zeros((ny, nx))
+    for _ in range(modes):
+        kx = rng.integers(1, 3)
+        ky = rng.integers(1, 3)
+        ph = rng.uniform(0, 2 * math.pi, size=2)
+        a = rng.normal(size=2) * amp / modes
+        arg = 2 * math.pi * (kx * x / nx + ky * y / ny)
+        ux += a[0] * np.sin(arg + ph[0])
+        uy += a[1] * np.cos(arg + ph[1])
+    return ux, uy
+
+
+def random_density(nx: int, ny: int, seed: int, amp: float = 1e-3):
+    rng = np.random.default_rng(seed)
+    return 1.0 + amp * rng.standard_normal((ny, nx))
