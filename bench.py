@@ -1,0 +1,137 @@
+#!/usr/bin/env python3
+"""Throughput of the fused VP-LBM step on one MI355X.
+
+Workload: NACA 0012 (4-digit thickness form, chord 200 cells) at 10 degrees
+angle of attack in a 2000 x 1000 channel (inflow 0.05, tau = 0.53, Re = 1000,
+eta = 1e-4), 401 stress-integration points, FP32 deviation storage.  One
+"step" is one full time step of the path: the fused stream / penalize /
+collide / momentum-exchange / stress-integration kernel plus the force
+finalize.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (metric, MLUPS value, roofline of the step kernel, CPU
+oracle baseline).  Only one GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % HBM roofline per step; p50/p99 solve latency under mixed-size load"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = {"f64": 9 * 8 * 2 + 1, "f32": 9 * 4 * 2 + 1, "f16dev": 9 * 2 * 2 + 1}
+
+
+def cpu_baseline(case, budget_s=12.0):
+    """The FP64 oracle on the host cores, on a bounded number of steps."""
+    import oracle as O
+
+    lat = O.RefLattice.from_case(case)
+    lat.step(2)  # warm-up (page-in, thread pool)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s or n < 3:
+        lat.step(1)
+        n += 1
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": case.nx * case.ny * n / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": min(threads, os.cpu_count() or 1),
+        "kind": "oracle",
+        "sample": f"{case.name} {case.nx}x{case.ny} FP64 oracle, {n} steps ({dt:.1f} s), "
+                  f"OpenMP over rows, CPU {platform.processor() or platform.machine()}",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f16dev", "f64"])
+    ap.add_argument("--tile", default=None, help="step tile BXxBY (default: library choice)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2110_00967_amd import vplbm as V
+
+    if not torch.cuda.is_available():
+        print("no GPU available", file=sys.stderr)
+        sys.exit(1)
+
+    case = W.case_naca(chord=200, aoa_deg=10.0)
+    cells = case.nx * case.ny
+    lat = V.Lattice.from_case(case, precision=args.precision)
+    if args.tile:
+        bx, by = (int(v) for v in args.tile.split("x"))
+        lat.set_tile(bx, by)
+
+    lat.step(args.warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    lat.step(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    mlups = cells / (ms_per_step * 1e-3) / 1e6
+
+    # the step kernel alone: HIP events around each launch on the lattice stream
+    kn = min(args.steps, 1000)
+    k_ms = lat.step_timed(kn) / kn
+    bpc = BYTES_PER_CELL[args.precision]
+    achieved = bpc * cells / (k_ms * 1e-3) / 1e9
+    me, si = lat.forces_me(), lat.forces_si()
+    q = 0.5 * case.u_ref ** 2 * case.length_scale
+    finite = bool(np.isfinite(me).all() and np.isfinite(si).all())
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16dev": "f32 (f16 storage)", "f64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{case.name}_{case.nx}x{case.ny}", "nx": case.nx, "ny": case.ny,
+                   "storage": args.precision, "si_points": len(case.si_ds), "tau": round(case.tau, 4),
+                   "eta": case.eta, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_step", "kernel_us": round(k_ms * 1e3, 3), "bytes_per_cell": bpc},
+        "hbm_roofline_pct_step": round(100.0 * bpc * cells / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+        "forces": {"CD_ME": me[0] / q, "CL_ME": me[1] / q, "CD_SI": si[0] / q, "CL_SI": si[1] / q,
+                   "finite": finite, "steps_run": lat.step_count},
+    }
+    lat.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W.case_naca(chord=200, aoa_deg=10.0))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

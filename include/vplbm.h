@@ -1,0 +1,205 @@
+/*
+ * vplbm.h -- C ABI of the MI355X (gfx950) VP-LBM library.
+ *
+ * One lattice = a D2Q9 lattice Boltzmann solver (Sec. 2.2 of Liberge &
+ * Beghein, "About fluid forces computation for Volume Penalization coupled
+ * with Lattice Boltzmann method") on an nx x ny grid, with one penalized
+ * rigid body described by a solid indicator chi (Eq. fcar) and penalization
+ * factor eta (Eq. 1; moment update Eqs. updatestep..updatestepm).  Each time
+ * step is one fused HIP kernel: pull streaming (Eq. eqBd) with edge
+ * conditions, moments, penalized velocity, BGK collision with the forcing
+ * term, and the two force reductions the paper compares: momentum exchange
+ * (Sec. 2.3.1, Eqs. MMEL and fluidtorque) and stress integration (Sec.
+ * 2.3.2, Eq. defFf).  A free body follows Eqs. dep1/theta2 on the device.
+ *
+ * Conventions (all entry points):
+ *   - Return 0 (VPLBM_OK) on success, a negative VPLBM_E* code on failure;
+ *     no C++ exception crosses the boundary.  vplbm_last_error() returns a
+ *     message owned by the handle, valid until the next call on it.
+ *   - Units are lattice units (dx = dt = 1, c = 1, c_s^2 = 1/3).
+ *   - Host arrays passed in are copied before the call returns; the caller
+ *     keeps ownership.  Host output arrays are caller-allocated.
+ *   - Field arrays are row-major [ny][nx] (index y*nx + x), cell centres at
+ *     integer coordinates (x, y), x to the east, y to the north.
+ *   - Work is queued on the HIP stream given at creation and runs
+ *     asynchronously; calls that return data to the host synchronize that
+ *     stream first.  Kernel faults surface as VPLBM_EHIP at the next
+ *     synchronizing call.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Step numbering: "step n" is the n-th lattice update since the last
+ *     initialization (vplbm_init_uniform / vplbm_set_fields), n >= 1.
+ */
+#ifndef VPLBM_H
+#define VPLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vplbm_lattice vplbm_lattice; /* opaque */
+
+/* Population storage.  The library stores deviations d_a = f_a - w_a rho0
+ * in every precision and computes in FP64 (VPLBM_F64) or FP32 (others). */
+enum {
+  VPLBM_F64 = 0,    /* double storage, double arithmetic */
+  VPLBM_F32 = 1,    /* float storage, float arithmetic */
+  VPLBM_F16DEV = 2  /* IEEE half storage of d_a, float arithmetic */
+};
+
+/* Edge conditions (the Applications section uses an inlet with half-way
+ * bounce-back, symmetry u.n = 0, no-slip walls and a free outflow). */
+enum {
+  VPLBM_BC_PERIODIC = 0, /* wrap around */
+  VPLBM_BC_VELOCITY = 1, /* half-way bounce-back, wall half a cell outside the
+                            edge, moving with (ux, uy); (0,0) = no-slip */
+  VPLBM_BC_FREESLIP = 2, /* specular reflection (u.n = 0) */
+  VPLBM_BC_OUTFLOW = 3   /* zero-gradient: incoming populations copied from the
+                            edge cell's own row/column */
+};
+
+typedef struct {
+  int kind;      /* VPLBM_BC_* */
+  double ux, uy; /* wall / inflow velocity, used by VPLBM_BC_VELOCITY */
+} vplbm_edge;
+
+typedef struct {
+  int nx, ny;        /* lattice size, each >= 4, nx <= 16384, 9*ny*pitch < 2^31 */
+  double tau;        /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3 (Eq. tauvisco) */
+  double eta;        /* penalization factor, > 0; +inf switches penalization off */
+  double rho0;       /* reference density (> 0; 1 in every workload here) */
+  int precision;     /* VPLBM_F64 / VPLBM_F32 / VPLBM_F16DEV */
+  vplbm_edge west, east, south, north;
+  int hist_capacity; /* length of the device force-history ring in steps; 0 = 4096 */
+  int max_si_points; /* capacity for stress-integration points; 0 = 4096 (max 4096) */
+  int max_vertices;  /* capacity for polygon vertices; 0 = 4096 */
+} vplbm_params;
+
+/* Rigid-body state in lattice units: reference point (centre of a disk,
+ * the given torque reference of a polygon), angle, translational and
+ * angular velocity.  The velocity field of the body is
+ * u_s(x) = (u - omega (y - y_G), v + omega (x - x_G)). */
+typedef struct {
+  double x, y, theta, u, v, omega;
+} vplbm_body_state;
+
+enum {
+  VPLBM_OK = 0,
+  VPLBM_EINVAL = -1,   /* invalid argument; nothing changed */
+  VPLBM_ENOMEM = -2,   /* device memory too small or allocation failed */
+  VPLBM_EHIP = -3,     /* HIP runtime error (including asynchronous kernel faults) */
+  VPLBM_ESTATE = -4,   /* call not valid in the current state */
+  VPLBM_ENOSAMPLE = -6 /* a stress-integration point found no fluid sample node */
+};
+
+enum { VPLBM_FORCE_ME = 0, VPLBM_FORCE_SI = 1 };
+enum { VPLBM_STEP_MACRO = 1 }; /* vplbm_step flag: write rho, u on the last step */
+
+/* Exact device bytes a lattice with these parameters needs (populations
+ * A and B, mask, macroscopic fields, partial sums, force history, tables);
+ * 0 if the parameters are invalid. */
+size_t vplbm_required_bytes(const vplbm_params *p);
+
+/* Create a lattice.  dev_mem: device buffer of at least
+ * vplbm_required_bytes(p) bytes, borrowed for the lifetime of the handle
+ * (the caller frees it after vplbm_destroy), or NULL to let the library
+ * allocate (and free) it.  hip_stream: a hipStream_t, or NULL for the
+ * default stream.  Populations start at rest (rho0, u = 0), the mask is
+ * all fluid, the body at rest at the origin. */
+int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *hip_stream,
+                 vplbm_lattice **out);
+int vplbm_destroy(vplbm_lattice *lat);
+const char *vplbm_last_error(const vplbm_lattice *lat);
+
+/* Set the populations to f^eq(rho, u) (second-order equilibrium, Sec. 2.2):
+ * fluid cells take (ux, uy), solid cells the body velocity u_s(x).  Resets
+ * the step counter and the force history. */
+int vplbm_init_uniform(vplbm_lattice *lat, double rho, double ux, double uy);
+/* Same with per-cell host fields rho, ux, uy ([ny][nx] each). */
+int vplbm_set_fields(vplbm_lattice *lat, const double *rho, const double *ux, const double *uy);
+
+/* Uniform external force density G added to the penalization force in every
+ * cell (Eq. updatestep); (0, 0) by default. */
+int vplbm_set_body_force(vplbm_lattice *lat, double gx, double gy);
+
+/* Body geometry -> chi (Eq. fcar), built on the device.  Coordinates are
+ * rounded to 1/4096 of a cell; a cell is solid when its centre lies inside
+ * (disk: distance <= r; polygon: even-odd rule, points on an edge inside).
+ * The reference point becomes (xc, yc) for a disk and (xref, yref) for a
+ * polygon (nvert >= 3, implicitly closed).  Replaces any previous body. */
+int vplbm_set_body_disk(vplbm_lattice *lat, double xc, double yc, double r);
+int vplbm_set_body_polygon(vplbm_lattice *lat, const double *xy, int nvert, double xref,
+                           double yref);
+/* Arbitrary solid indicator (host, [ny][nx], nonzero = solid), static. */
+int vplbm_set_mask(vplbm_lattice *lat, const uint8_t *solid);
+
+/* Prescribed rigid motion: the state is applied now, and each step advances
+ * the position and angle by the (constant) velocities; the disk's mask and
+ * its stress-integration points follow the motion.  Polygon and host-mask
+ * bodies are static: for them only the reference point and angle may be set
+ * and the velocities must be zero (VPLBM_EINVAL otherwise). */
+int vplbm_set_body_motion(vplbm_lattice *lat, const vplbm_body_state *s);
+
+/* Free disk (Eqs. dep1, theta2): mass m = rho_s pi r^2, moment of inertia
+ * m r^2 / 2, gravity (gx, gy) with buoyancy factor (1 - rho0/rho_s), driven
+ * by the momentum-exchange (force_source = VPLBM_FORCE_ME) or
+ * stress-integration (VPLBM_FORCE_SI) force of each step; semi-implicit
+ * Euler, dt = 1, in FP64 on the device. */
+int vplbm_set_body_dynamics(vplbm_lattice *lat, double rho_s, double gx, double gy,
+                            int force_source);
+
+/* Stress-integration points (Sec. 2.3.2): world coordinates xy[2*npts],
+ * outward unit normals nrm[2*npts], integration lengths ds[npts], at the
+ * current body state; they move rigidly with the body.  Each point takes
+ * its stress from a sample node: the lattice direction closest to n, walked
+ * from the nearest node for up to 5 nodes until a fluid node is met
+ * (VPLBM_ENOSAMPLE if none).  npts = 0 removes the points. */
+int vplbm_set_si_points(vplbm_lattice *lat, const double *xy, const double *nrm, const double *ds,
+                        int npts);
+
+/* Advance nsteps time steps (asynchronous).  flags: VPLBM_STEP_MACRO makes
+ * the last step also store rho and the penalized velocity u for
+ * vplbm_read_macro. */
+int vplbm_step(vplbm_lattice *lat, int nsteps, int flags);
+/* Same as vplbm_step, for measurement: HIP events bracket every launch of
+ * the fused step kernel on the lattice's stream; on return (the stream is
+ * synchronized) *kernel_ms holds the summed duration of those launches in
+ * milliseconds. */
+int vplbm_step_timed(vplbm_lattice *lat, int nsteps, int flags, double *kernel_ms);
+int vplbm_sync(vplbm_lattice *lat);
+long long vplbm_step_count(const vplbm_lattice *lat);
+/* Workgroup tile of the step kernel, bx cells along x times by rows:
+ * 64x1, 64x2, 64x4 (default), 128x1, 128x2 or 256x1.  Results do not depend
+ * on it except for the order of the per-tile force partial sums. */
+int vplbm_set_tile(vplbm_lattice *lat, int bx, int by);
+
+/* Forces of the last step, out = (Fx, Fy, Tz) on the body, torque about the
+ * reference point.  Momentum exchange of step n is evaluated on the
+ * post-collision populations of step n-1; stress integration of step n on
+ * the streamed (pre-collision) populations of step n. */
+int vplbm_forces_me(vplbm_lattice *lat, double out[3]);
+int vplbm_forces_si(vplbm_lattice *lat, double out[3]);
+/* Stress integration over the given points on the current streamed state
+ * (one-shot, not registered; sample nodes chosen as above). */
+int vplbm_forces_si_at(vplbm_lattice *lat, const double *xy, const double *nrm, const double *ds,
+                       int npts, double out[3]);
+/* History: out[3*k..3*k+2] = forces of step first_step + k, k < n.  The
+ * ring keeps the last hist_capacity steps (VPLBM_EINVAL outside it). */
+int vplbm_force_history(vplbm_lattice *lat, int which, long long first_step, int n, double *out);
+int vplbm_get_body_state(vplbm_lattice *lat, vplbm_body_state *out);
+
+/* rho and penalized u of the last step (which must have been run with
+ * VPLBM_STEP_MACRO), host arrays [ny][nx]. */
+int vplbm_read_macro(vplbm_lattice *lat, double *rho, double *ux, double *uy);
+/* Post-collision populations f_a = w_a rho0 + d_a as host doubles [9][ny][nx]. */
+int vplbm_read_populations(vplbm_lattice *lat, double *f);
+/* Mask bytes [ny][nx]: bit 0 solid, bit 6 stress-integration sample node,
+ * bit 7 interface cell (a neighbour has the other phase). */
+int vplbm_read_mask(vplbm_lattice *lat, uint8_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VPLBM_H */

@@ -1,0 +1,101 @@
+// d2q9.hpp -- D2Q9 constants, storage traits and device-side state shared by
+// the HIP kernels of the VP-LBM library (gfx950).
+//
+// Velocity set and weights: Sec. 2.2 (c_0 = 0, c_1..4 along the axes,
+// c_5..8 along the diagonals; w = 4/9, 1/9, 1/36; c_s^2 = 1/3).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vp {
+
+constexpr int Q = 9;
+
+__host__ __device__ constexpr int cx(int a) {
+  return (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int cy(int a) {
+  return (a == 2 || a == 5 || a == 6) ? 1 : ((a == 4 || a == 7 || a == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int a) {
+  return a == 0 ? 0 : (a <= 4 ? ((a + 1) % 4) + 1 : ((a - 5 + 2) % 4) + 5);
+}
+// population with the x (resp. y) velocity component reversed
+__host__ __device__ constexpr int flipx(int a) {
+  return a == 1 ? 3 : a == 3 ? 1 : a == 5 ? 6 : a == 6 ? 5 : a == 7 ? 8 : a == 8 ? 7 : a;
+}
+__host__ __device__ constexpr int flipy(int a) {
+  return a == 2 ? 4 : a == 4 ? 2 : a == 5 ? 8 : a == 8 ? 5 : a == 6 ? 7 : a == 7 ? 6 : a;
+}
+__host__ __device__ constexpr double wgt(int a) {
+  return a == 0 ? 4.0 / 9.0 : (a <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp axis");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp diag");
+
+// mask byte layout
+constexpr uint8_t M_SOLID = 0x01;   // chi = 1 (Eq. fcar)
+constexpr uint8_t M_SAMPLE = 0x40;  // stress-integration sample node
+constexpr uint8_t M_IFACE = 0x80;   // a lattice neighbour has the other phase
+
+enum { EDGE_PERIODIC = 0, EDGE_VELOCITY = 1, EDGE_FREESLIP = 2, EDGE_OUTFLOW = 3 };
+enum { WEST = 0, EAST = 1, SOUTH = 2, NORTH = 3 };
+enum { MODE_STATIC = 0, MODE_PRESCRIBED = 1, MODE_FREE = 2 };
+enum { SHAPE_NONE = 0, SHAPE_DISK = 1, SHAPE_POLYGON = 2, SHAPE_MASK = 3 };
+
+// storage of the deviations d_a = f_a - w_a rho0
+template <typename S> struct Store;
+template <> struct Store<double> {
+  using T = double;
+  static __device__ __forceinline__ double ld(const double *p) { return *p; }
+  static __device__ __forceinline__ void st(double *p, double v) { *p = v; }
+};
+template <> struct Store<float> {
+  using T = float;
+  static __device__ __forceinline__ float ld(const float *p) { return *p; }
+  static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+};
+template <> struct Store<__half> {
+  using T = float;
+  static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p); }
+  static __device__ __forceinline__ void st(__half *p, float v) { *p = __float2half_rn(v); }
+};
+
+struct BodyDev {
+  double x, y, theta, u, v, omega;
+};
+
+// Device-resident control block (one per lattice).
+struct Ctl {
+  BodyDev body;        // state used by the next step
+  int win[4];          // cell window x0, y0, x1, y1 (exclusive) holding every
+                       // interface and sample cell: the force reductions run there
+  int region[4];       // last mask region rebuilt for a moving body
+  int nrec;            // stress-integration records
+  int npts;            // registered stress-integration points
+  int si_moving;       // points stored in the body frame
+  int err;             // bit 0: a point without sample node
+  long long step;      // steps completed since initialization
+  double last[6];      // forces of the last step: ME (Fx, Fy, T), SI (Fx, Fy, T)
+  int mode, shape, source, pad;
+  double r;            // disk radius
+  double mass, inertia, gx, gy, buoy;
+  long long fq[3];     // disk centre / radius on the 1/4096 grid (mask of the current state)
+};
+
+// Aggregated stress-integration weights of one sample node:
+// F_x += s_xx ax + s_xy ay, F_y += s_xy ax + s_yy ay,
+// T   += s_xx txx + s_xy txy + s_yy tyy.
+struct SiRec {
+  int cell;  // y * nx + x
+  int pad;
+  double ax, ay, txx, txy, tyy;
+};
+
+constexpr int PART_STRIDE = 8;  // doubles per partial-sum slot (6 used)
+constexpr int FIXQ = 4096;      // fixed-point grid of geometry coordinates
+
+}  // namespace vp

@@ -1,0 +1,457 @@
+// geometry_kernels.hpp -- device kernels around the step: initialization,
+// solid indicator chi (Eq. fcar) for disks and polygons, interface flags,
+// rigid-body update (Eqs. dep1, theta2), stress-integration sample nodes and
+// weights (Sec. 2.3.2), one-shot stress integration, and readback staging.
+#pragma once
+
+#include "d2q9.hpp"
+#include "step_kernel.hpp"
+
+namespace vp {
+
+// ----------------------------------------------------------------------------
+// initialization: d_a = f^eq_a(rho, u) - w_a rho0 (second-order equilibrium)
+// ----------------------------------------------------------------------------
+template <typename S>
+__global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
+                       long long plane, int row0, int nrows, const double *__restrict__ rho_in,
+                       const double *__restrict__ ux_in, const double *__restrict__ uy_in,
+                       double rho_u, double ux_u, double uy_u, const Ctl *__restrict__ ctl, double rho0) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int yl = blockIdx.y;
+  if (x >= nx || yl >= nrows) return;
+  const int y = row0 + yl;
+  const long long c = (long long)y * pitch + x;
+  double rho, ux, uy;
+  if (rho_in) {
+    const long long k = (long long)yl * nx + x;
+    rho = rho_in[k];
+    ux = ux_in[k];
+    uy = uy_in[k];
+  } else {
+    rho = rho_u;
+    ux = ux_u;
+    uy = uy_u;
+    if (mask[c] & M_SOLID) {  // solid cells start at the body velocity
+      const BodyDev B = ctl->body;
+      ux = B.u - B.omega * (double(y) - B.y);
+      uy = B.v + B.omega * (double(x) - B.x);
+    }
+  }
+  const double uu = 1.5 * (ux * ux + uy * uy);
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const double cu = cx(a) * ux + cy(a) * uy;
+    const double d = wgt(a) * (rho - rho0) + wgt(a) * rho * (3.0 * cu + 4.5 * cu * cu - uu);
+    Store<S>::st(f + a * plane + c, (typename Store<S>::T)d);
+  }
+}
+
+// populations f_a = w_a rho0 + d_a of rows [row0, row0 + nrows) -> out[9][nrows][nx]
+template <typename S>
+__global__ void k_read_pop(const S *__restrict__ f, int nx, int pitch, long long plane, int row0,
+                           int nrows, double rho0, double *__restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int yl = blockIdx.y;
+  if (x >= nx || yl >= nrows) return;
+  const long long c = (long long)(row0 + yl) * pitch + x;
+#pragma unroll
+  for (int a = 0; a < Q; ++a)
+    out[((long long)a * nrows + yl) * nx + x] = wgt(a) * rho0 + double(Store<S>::ld(f + a * plane + c));
+}
+
+template <typename T>
+__global__ void k_read_macro(const T *__restrict__ r, const T *__restrict__ u, const T *__restrict__ v,
+                             int nx, int pitch, int row0, int nrows, double *__restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int yl = blockIdx.y;
+  if (x >= nx || yl >= nrows) return;
+  const long long c = (long long)(row0 + yl) * pitch + x;
+  const long long o = (long long)yl * nx + x;
+  const long long n = (long long)nrows * nx;
+  out[o] = double(r[c]);
+  out[n + o] = double(u[c]);
+  out[2 * n + o] = double(v[c]);
+}
+
+// ----------------------------------------------------------------------------
+// chi: exact inside tests on the 1/4096 grid (integer arithmetic)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ bool disk_inside(long long X, long long Y, long long R, int i, int j) {
+  const long long dx = (long long)i * FIXQ - X, dy = (long long)j * FIXQ - Y;
+  return dx * dx + dy * dy <= R * R;
+}
+
+// even-odd rule; a centre exactly on an edge counts as inside
+__device__ __forceinline__ bool polygon_inside(const long long *__restrict__ vx,
+                                               const long long *__restrict__ vy, int nv, int i, int j) {
+  const long long px = (long long)i * FIXQ, py = (long long)j * FIXQ;
+  bool in = false;
+  long long ax = vx[nv - 1], ay = vy[nv - 1];
+  for (int e = 0; e < nv; ++e) {
+    const long long bx = vx[e], by = vy[e];
+    const long long orient = (ax - bx) * (py - by) - (ay - by) * (px - bx);
+    // orient is the cross product of (a - b) and (p - b): zero when p is on the line
+    if (orient == 0 && px >= min(ax, bx) && px <= max(ax, bx) && py >= min(ay, by) &&
+        py <= max(ay, by))
+      return true;
+    if ((by > py) != (ay > py)) {
+      // the edge b -> a crosses the horizontal through p right of p when the
+      // orientation has the sign of (ay - by)
+      if ((orient > 0) == (ay > by)) in = !in;
+    }
+    ax = bx;
+    ay = by;
+  }
+  return in;
+}
+
+// rewrite mask bytes of a region from a disk: bit 0 = inside; flags cleared
+__global__ void k_mask_disk(uint8_t *__restrict__ mask, int pitch, int x0, int y0, int x1, int y1,
+                            long long X, long long Y, long long R) {
+  const int i = x0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = y0 + blockIdx.y;
+  if (i >= x1 || j >= y1) return;
+  mask[(long long)j * pitch + i] = disk_inside(X, Y, R, i, j) ? M_SOLID : 0;
+}
+
+__global__ void k_mask_polygon(uint8_t *__restrict__ mask, int pitch, int x0, int y0, int x1, int y1,
+                               const long long *__restrict__ vx, const long long *__restrict__ vy,
+                               int nv) {
+  const int i = x0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = y0 + blockIdx.y;
+  if (i >= x1 || j >= y1) return;
+  mask[(long long)j * pitch + i] = polygon_inside(vx, vy, nv, i, j) ? M_SOLID : 0;
+}
+
+// interface bit over a region: some lattice neighbour (periodic edges wrap,
+// none beyond other edges) has the other phase; clears the sample bit
+__global__ void k_mask_flags(uint8_t *__restrict__ mask, int nx, int ny, int pitch, int x0, int y0,
+                             int x1, int y1, int perx, int pery) {
+  const int i = x0 + blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = y0 + blockIdx.y;
+  if (i >= x1 || j >= y1) return;
+  const long long c = (long long)j * pitch + i;
+  const uint8_t own = mask[c] & M_SOLID;
+  bool iface = false;
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    int X = i + cx(a), Y = j + cy(a);
+    if (X < 0 || X >= nx) {
+      if (!perx) continue;
+      X = X < 0 ? X + nx : X - nx;
+    }
+    if (Y < 0 || Y >= ny) {
+      if (!pery) continue;
+      Y = Y < 0 ? Y + ny : Y - ny;
+    }
+    if ((mask[(long long)Y * pitch + X] & M_SOLID) != own) iface = true;
+  }
+  mask[c] = own | (iface ? M_IFACE : 0);
+}
+
+// ----------------------------------------------------------------------------
+// moving disk: rigid-body update, then rebuild chi and flags over the union of
+// the old and new regions (one workgroup)
+// ----------------------------------------------------------------------------
+constexpr int BODY_NT = 1024;
+constexpr int REGION_MARGIN = 6;  // covers links (1) and sample walks (5)
+
+__global__ void __launch_bounds__(BODY_NT)
+    k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, int nx, int ny, int pitch, int perx,
+                int pery) {
+  __shared__ int reg[4];   // union region to rewrite
+  __shared__ long long q[3];
+  if (threadIdx.x == 0) {
+    BodyDev B = ctl->body;
+    if (ctl->mode == MODE_FREE) {
+      // Eqs. dep1/theta2, semi-implicit Euler, dt = 1
+      const double *F = ctl->last + 3 * ctl->source;
+      B.u += F[0] / ctl->mass + ctl->buoy * ctl->gx;
+      B.v += F[1] / ctl->mass + ctl->buoy * ctl->gy;
+      B.omega += F[2] / ctl->inertia;
+    }
+    B.x += B.u;
+    B.y += B.v;
+    B.theta += B.omega;
+    ctl->body = B;
+    const long long X = llround(B.x * FIXQ), Y = llround(B.y * FIXQ), R = llround(ctl->r * FIXQ);
+    ctl->fq[0] = X;
+    ctl->fq[1] = Y;
+    ctl->fq[2] = R;
+    q[0] = X;
+    q[1] = Y;
+    q[2] = R;
+    // bounding box of the disk (cells whose centre can be inside)
+    const int bx0 = (int)((X - R) / FIXQ) - 1, bx1 = (int)((X + R) / FIXQ) + 2;
+    const int by0 = (int)((Y - R) / FIXQ) - 1, by1 = (int)((Y + R) / FIXQ) + 2;
+    int nr[4] = {max(bx0 - REGION_MARGIN, 0), max(by0 - REGION_MARGIN, 0),
+                 min(bx1 + REGION_MARGIN, nx), min(by1 + REGION_MARGIN, ny)};
+    reg[0] = min(nr[0], ctl->region[0]);
+    reg[1] = min(nr[1], ctl->region[1]);
+    reg[2] = max(nr[2], ctl->region[2]);
+    reg[3] = max(nr[3], ctl->region[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ctl->region[k] = nr[k];
+    // force window: interface cells lie within one cell of the disk's box;
+    // the sample-node selection extends it afterwards
+    ctl->win[0] = max(bx0 - 1, 0);
+    ctl->win[1] = max(by0 - 1, 0);
+    ctl->win[2] = min(bx1 + 1, nx);
+    ctl->win[3] = min(by1 + 1, ny);
+  }
+  __syncthreads();
+  const int x0 = reg[0], y0 = reg[1], w = reg[2] - reg[0], h = reg[3] - reg[1];
+  const long long X = q[0], Y = q[1], R = q[2];
+  for (int t = threadIdx.x; t < w * h; t += BODY_NT) {
+    const int i = x0 + t % w, j = y0 + t / w;
+    const bool own = disk_inside(X, Y, R, i, j);
+    bool iface = false;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      int I = i + cx(a), J = j + cy(a);
+      if (I < 0 || I >= nx) {
+        if (!perx) continue;
+        I = I < 0 ? I + nx : I - nx;
+      }
+      if (J < 0 || J >= ny) {
+        if (!pery) continue;
+        J = J < 0 ? J + ny : J - ny;
+      }
+      if (disk_inside(X, Y, R, I, J) != own) iface = true;
+    }
+    mask[(long long)j * pitch + i] = (own ? M_SOLID : 0) | (iface ? M_IFACE : 0);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// stress-integration sample nodes and aggregated weights (one workgroup)
+// ----------------------------------------------------------------------------
+constexpr int SI_NT = 1024;
+constexpr int SI_MAX = 4096;
+
+// Sample node of a point: the lattice direction beta maximizing
+// (c_beta . n)/|c_beta| (first on ties), then the first fluid node inside the
+// lattice among r_0 + k c_beta, k = 0..4, r_0 the node nearest to the point.
+__device__ __forceinline__ int si_node(const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
+                                       double px, double py, double n0, double n1) {
+  const double S = 0.70710678118654752440;
+  double sc[Q];
+  sc[1] = n0;
+  sc[2] = n1;
+  sc[3] = -n0;
+  sc[4] = -n1;
+  sc[5] = (n0 + n1) * S;
+  sc[6] = (-n0 + n1) * S;
+  sc[7] = (-n0 - n1) * S;
+  sc[8] = (n0 - n1) * S;
+  int best = 1;
+#pragma unroll
+  for (int a = 2; a < Q; ++a)
+    if (sc[a] > sc[best]) best = a;
+  int bx = 0, by = 0;
+#pragma unroll
+  for (int a = 1; a < Q; ++a)
+    if (a == best) { bx = cx(a); by = cy(a); }
+  const int ix = (int)floor(px + 0.5), iy = (int)floor(py + 0.5);
+  for (int k = 0; k <= 4; ++k) {
+    const int X = ix + k * bx, Y = iy + k * by;
+    if (X < 0 || X >= nx || Y < 0 || Y >= ny) continue;
+    if (!(mask[(long long)Y * pitch + X] & M_SOLID)) return Y * nx + X;
+  }
+  return -1;
+}
+
+// world position and normal of point i (points of a moving body are kept in
+// the body frame and placed with the current state)
+__device__ __forceinline__ void si_world(const double *__restrict__ pts, int maxp, int i, int moving,
+                                         const BodyDev &B, double &px, double &py, double &n0,
+                                         double &n1) {
+  const double a = pts[i], b = pts[maxp + i], c = pts[2 * maxp + i], d = pts[3 * maxp + i];
+  if (!moving) {
+    px = a; py = b; n0 = c; n1 = d;
+    return;
+  }
+  const double co = cos(B.theta), sn = sin(B.theta);
+  px = B.x + (co * a - sn * b);
+  py = B.y + (sn * a + co * b);
+  n0 = co * c - sn * d;
+  n1 = sn * c + co * d;
+}
+
+__global__ void __launch_bounds__(SI_NT)
+    k_si_select(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ pts,
+                int maxp, SiRec *__restrict__ recs, int *__restrict__ si_map, int nx, int ny,
+                int pitch) {
+  __shared__ unsigned long long key[SI_MAX];
+  __shared__ int scan[SI_NT + 1];
+  __shared__ int bb[4];
+  __shared__ int missing;
+  const int npts = ctl->npts;
+  const int moving = ctl->si_moving;
+  const BodyDev B = ctl->body;
+  int N = 2;
+  while (N < npts) N <<= 1;
+  if (threadIdx.x == 0) {
+    bb[0] = nx; bb[1] = ny; bb[2] = -1; bb[3] = -1;
+    missing = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += SI_NT) {
+    unsigned long long k = ~0ull;
+    if (i < npts) {
+      double px, py, n0, n1;
+      si_world(pts, maxp, i, moving, B, px, py, n0, n1);
+      const int node = si_node(mask, nx, ny, pitch, px, py, n0, n1);
+      if (node >= 0) {
+        k = ((unsigned long long)(unsigned)node << 32) | (unsigned)i;
+        const int X = node % nx, Y = node / nx;
+        atomicMin(&bb[0], X);
+        atomicMin(&bb[1], Y);
+        atomicMax(&bb[2], X);
+        atomicMax(&bb[3], Y);
+      } else {
+        atomicAdd(&missing, 1);
+        k = (0xFFFFFFFFull << 32) | (unsigned)i;
+      }
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  // bitonic sort of (node, point) keys
+  for (int size = 2; size <= N; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < N / 2; t += SI_NT) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const unsigned long long a = key[lo], b = key[hi];
+        if ((a > b) == up) {
+          key[lo] = b;
+          key[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // segment heads -> record indices (each thread owns a contiguous chunk)
+  const int per = (N + SI_NT - 1) / SI_NT;
+  const int j0 = threadIdx.x * per, j1 = min(j0 + per, N);
+  int cnt = 0;
+  for (int j = j0; j < j1; ++j) {
+    const unsigned node = (unsigned)(key[j] >> 32);
+    if (node != 0xFFFFFFFFu && (j == 0 || (unsigned)(key[j - 1] >> 32) != node)) ++cnt;
+  }
+  scan[threadIdx.x + 1] = cnt;
+  if (threadIdx.x == 0) scan[0] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int t = 1; t <= SI_NT; ++t) scan[t] += scan[t - 1];
+  }
+  __syncthreads();
+  int r = scan[threadIdx.x];
+  for (int j = j0; j < j1; ++j) {
+    const unsigned node = (unsigned)(key[j] >> 32);
+    if (node == 0xFFFFFFFFu || (j > 0 && (unsigned)(key[j - 1] >> 32) == node)) continue;
+    double ax = 0.0, ay = 0.0, txx = 0.0, txy = 0.0, tyy = 0.0;
+    for (int k = j; k < N && (unsigned)(key[k] >> 32) == node; ++k) {
+      const int i = (int)(key[k] & 0xFFFFFFFFu);
+      double px, py, n0, n1;
+      si_world(pts, maxp, i, moving, B, px, py, n0, n1);
+      const double s = pts[4 * maxp + i];
+      const double rx = px - B.x, ry = py - B.y;
+      ax += s * n0;
+      ay += s * n1;
+      txx += s * (-ry * n0);
+      txy += s * (rx * n0 - ry * n1);
+      tyy += s * (rx * n1);
+    }
+    SiRec R;
+    R.cell = (int)node;
+    R.pad = 0;
+    R.ax = ax; R.ay = ay; R.txx = txx; R.txy = txy; R.tyy = tyy;
+    recs[r] = R;
+    const int X = (int)node % nx, Y = (int)node / nx;
+    si_map[(long long)Y * pitch + X] = r;
+    mask[(long long)Y * pitch + X] |= M_SAMPLE;
+    ++r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ctl->nrec = scan[SI_NT];
+    if (missing) ctl->err |= 1;
+    if (bb[2] >= 0) {
+      if (ctl->win[2] <= ctl->win[0] || ctl->win[3] <= ctl->win[1]) {
+        ctl->win[0] = bb[0]; ctl->win[1] = bb[1]; ctl->win[2] = bb[2] + 1; ctl->win[3] = bb[3] + 1;
+      } else {
+        ctl->win[0] = min(ctl->win[0], bb[0]);
+        ctl->win[1] = min(ctl->win[1], bb[1]);
+        ctl->win[2] = max(ctl->win[2], bb[2] + 1);
+        ctl->win[3] = max(ctl->win[3], bb[3] + 1);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// one-shot stress integration over given world points on the populations
+// streamed from the current post-collision state (one workgroup)
+// ----------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(SI_NT)
+    k_si_at(const S *__restrict__ fin, const uint8_t *__restrict__ mask,
+            const StepArgs<typename Store<S>::T> P, const Ctl *__restrict__ ctl,
+            const double *__restrict__ pts, int maxp, int npts, double *__restrict__ out) {
+  using T = typename Store<S>::T;
+  const BodyDev B = ctl->body;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < npts; i += SI_NT) {
+    const double px = pts[i], py = pts[maxp + i], n0 = pts[2 * maxp + i], n1 = pts[3 * maxp + i];
+    const double s = pts[4 * maxp + i];
+    const int node = si_node(mask, P.nx, P.ny, P.pitch, px, py, n0, n1);
+    if (node < 0) {
+      v[5] += 1.0;  // counts points without a sample node
+      continue;
+    }
+    const int x = node % P.nx, y = node / P.nx;
+    double d[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) d[a] = double(pull_edge<S, T>(fin, P, x, y, a, cx(a), cy(a)));
+    double drho = 0.0, mx = 0.0, my = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      drho += d[a];
+      mx += cx(a) * d[a];
+      my += cy(a) * d[a];
+    }
+    const double rho = P.rho0d + drho;
+    const double ux = (mx + 0.5 * double(P.gx)) / rho, uy = (my + 0.5 * double(P.gy)) / rho;
+    const double uu = 1.5 * (ux * ux + uy * uy);
+    double pxx = 0.0, pxy = 0.0, pyy = 0.0;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const double cu = cx(a) * ux + cy(a) * uy;
+      const double deq = wgt(a) * drho + wgt(a) * rho * (3.0 * cu + 4.5 * cu * cu - uu);
+      const double ne = d[a] - deq;
+      pxx += cx(a) * cx(a) * ne;
+      pxy += cx(a) * cy(a) * ne;
+      pyy += cy(a) * cy(a) * ne;
+    }
+    const double pr = drho / 3.0;
+    const double sxx = -pr - P.facd * pxx, sxy = -P.facd * pxy, syy = -pr - P.facd * pyy;
+    const double tx = s * (sxx * n0 + sxy * n1), ty = s * (sxy * n0 + syy * n1);
+    v[0] += tx;
+    v[1] += ty;
+    v[2] += (px - B.x) * ty - (py - B.y) * tx;
+  }
+  __shared__ double lds[(SI_NT / 64) * 6];
+  block_reduce6<SI_NT>(v, lds);
+  if (threadIdx.x == 0) {
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+    out[3] = v[5];
+  }
+}
+
+}  // namespace vp

@@ -1,0 +1,971 @@
+// vplbm.hip -- host side of the VP-LBM library: the C ABI of include/vplbm.h.
+//
+// Device memory of one lattice (carved from one buffer, 256-byte aligned):
+//   A, B     : populations, [9][ny][pitch] of the storage type (ping-pong)
+//   mask     : [ny][pitch] bytes (bit 0 chi, bit 6 SI sample, bit 7 interface)
+//   macro    : rho, ux, uy [ny][pitch] of the compute type (written on request)
+//   si_map   : [ny][pitch] int, record index of a sample node
+//   partials : per-block force partial sums (8 doubles per tile)
+//   hist     : force-history ring [cap][6] doubles
+//   ctl      : control block (body state, window, counters)
+//   recs     : stress-integration records, pts: SI points [5][maxp]
+//   verts    : polygon vertices on the 1/4096 grid [2][maxv] int64
+//   staging  : bounded host<->device staging for setup and readback
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vplbm.h"
+#include "d2q9.hpp"
+#include "geometry_kernels.hpp"
+#include "step_kernel.hpp"
+
+using namespace vp;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr size_t STAGE_DOUBLES = 1 << 18;  // 2 MiB staging
+constexpr int DEFAULT_HIST = 4096;
+constexpr int DEFAULT_PTS = 4096;
+constexpr int DEFAULT_VERTS = 4096;
+constexpr int MIN_TILE_CELLS = 64;
+constexpr int MAX_NX = 16384;  // one row of 9 planes fits the staging buffer
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_size(int prec) { return prec == VPLBM_F64 ? 8 : (prec == VPLBM_F32 ? 4 : 2); }
+size_t compute_size(int prec) { return prec == VPLBM_F64 ? 8 : 4; }
+
+int pitch_of(const vplbm_params &p) {
+  // rows start on 256-byte boundaries for every storage type
+  const int q = (int)(ALIGN / elem_size(p.precision));
+  return (int)align_up((size_t)p.nx, (size_t)std::max(q, 64));
+}
+
+struct Layout {
+  size_t A, B, mask, mrho, mux, muy, si_map, partials, hist, ctl, recs, pts, verts, staging, siout, total;
+};
+
+Layout layout_of(const vplbm_params &p) {
+  Layout L{};
+  const int pitch = pitch_of(p);
+  const size_t cells = (size_t)p.ny * pitch;
+  const int cap = p.hist_capacity > 0 ? p.hist_capacity : DEFAULT_HIST;
+  const int maxp = p.max_si_points > 0 ? p.max_si_points : DEFAULT_PTS;
+  const int maxv = p.max_vertices > 0 ? p.max_vertices : DEFAULT_VERTS;
+  const size_t ntiles = (size_t)p.ny * ((p.nx + MIN_TILE_CELLS - 1) / MIN_TILE_CELLS);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, ALIGN);
+    return at;
+  };
+  L.A = take(9 * cells * elem_size(p.precision));
+  L.B = take(9 * cells * elem_size(p.precision));
+  L.mask = take(cells);
+  L.mrho = take(cells * compute_size(p.precision));
+  L.mux = take(cells * compute_size(p.precision));
+  L.muy = take(cells * compute_size(p.precision));
+  L.si_map = take(cells * sizeof(int));
+  L.partials = take(ntiles * PART_STRIDE * sizeof(double));
+  L.hist = take((size_t)cap * 6 * sizeof(double));
+  L.ctl = take(sizeof(Ctl));
+  L.recs = take((size_t)maxp * sizeof(SiRec));
+  L.pts = take((size_t)5 * maxp * sizeof(double));
+  L.verts = take((size_t)2 * maxv * sizeof(long long));
+  L.staging = take(STAGE_DOUBLES * sizeof(double));
+  L.siout = take(8 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+bool valid_edge(const vplbm_edge &e) {
+  return e.kind >= VPLBM_BC_PERIODIC && e.kind <= VPLBM_BC_OUTFLOW && std::isfinite(e.ux) &&
+         std::isfinite(e.uy);
+}
+
+const char *check_params(const vplbm_params *p) {
+  if (!p) return "params is NULL";
+  if (p->nx < 4 || p->ny < 4) return "nx and ny must be >= 4";
+  if (p->nx > MAX_NX) return "nx must be <= 16384";
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return "tau must be finite and > 1/2";
+  if (!(p->eta > 0.0)) return "eta must be > 0 (or +inf)";
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return "rho0 must be finite and > 0";
+  if (p->precision < VPLBM_F64 || p->precision > VPLBM_F16DEV) return "unknown precision";
+  if (!valid_edge(p->west) || !valid_edge(p->east) || !valid_edge(p->south) || !valid_edge(p->north))
+    return "invalid edge condition";
+  if ((p->west.kind == VPLBM_BC_PERIODIC) != (p->east.kind == VPLBM_BC_PERIODIC))
+    return "west and east must both be periodic or both not";
+  if ((p->south.kind == VPLBM_BC_PERIODIC) != (p->north.kind == VPLBM_BC_PERIODIC))
+    return "south and north must both be periodic or both not";
+  if (p->hist_capacity < 0 || p->max_si_points < 0 || p->max_vertices < 0)
+    return "capacities must be >= 0";
+  if (p->max_si_points > SI_MAX) return "max_si_points exceeds 4096";
+  const long long pitch = pitch_of(*p);
+  if (9LL * p->ny * pitch >= (1LL << 31)) return "lattice too large (9*ny*pitch must be < 2^31)";
+  return nullptr;
+}
+
+}  // namespace
+
+struct vplbm_lattice {
+  vplbm_params p{};
+  Layout L{};
+  int pitch = 0;
+  long long plane = 0;
+  hipStream_t stream = nullptr;
+  char *base = nullptr;
+  bool owns = false;
+  int cur = 0;  // 0: A holds the state, 1: B
+  long long nstep = 0;
+  bool initialized = false;
+  bool macro_valid = false;
+  int cap = 0, maxp = 0, maxv = 0;
+  int bx = 64, by = 4;  // step tile shape
+  double gx = 0.0, gy = 0.0;
+  int shape = SHAPE_NONE, mode = MODE_STATIC;
+  double disk_r = 0.0;
+  int npts = 0;
+  std::vector<double> si_world;  // host copy of the registered world points [5][npts]
+  std::string err;
+
+  char *at(size_t off) const { return base + off; }
+  void *A() const { return at(cur == 0 ? L.A : L.B); }
+  void *Bbuf() const { return at(cur == 0 ? L.B : L.A); }
+  uint8_t *mask() const { return (uint8_t *)at(L.mask); }
+  Ctl *ctl() const { return (Ctl *)at(L.ctl); }
+
+  int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+  int hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return VPLBM_OK;
+    return fail(VPLBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+  }
+  int launched(const char *what) { return hip(hipGetLastError(), what); }
+  int sync() { return hip(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
+
+  int ctl_pull(Ctl &c) {
+    int rc = hip(hipMemcpyAsync(&c, ctl(), sizeof(Ctl), hipMemcpyDeviceToHost, stream), "ctl read");
+    if (rc) return rc;
+    return sync();
+  }
+  int ctl_push(const Ctl &c) {
+    int rc = hip(hipMemcpyAsync(ctl(), &c, sizeof(Ctl), hipMemcpyHostToDevice, stream), "ctl write");
+    if (rc) return rc;
+    return sync();
+  }
+
+  bool periodic_x() const { return p.west.kind == VPLBM_BC_PERIODIC; }
+  bool periodic_y() const { return p.south.kind == VPLBM_BC_PERIODIC; }
+
+  template <typename T> StepArgs<T> step_args() const {
+    StepArgs<T> a{};
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.pitch = pitch;
+    a.plane = plane;
+    a.tiles_x = (p.nx + bx - 1) / bx;
+    const int tiles_y = (p.ny + by - 1) / by;
+    a.ntiles = a.tiles_x * tiles_y;
+    a.per_xcd = (a.ntiles + 7) / 8;
+    const vplbm_edge *E[4] = {&p.west, &p.east, &p.south, &p.north};
+    for (int e = 0; e < 4; ++e) {
+      a.kind[e] = E[e]->kind;
+      for (int q = 0; q < Q; ++q)
+        a.bb[e][q] = T(6.0 * wgt(q) * p.rho0 * (cx(q) * E[e]->ux + cy(q) * E[e]->uy));
+    }
+    a.omega = T(1.0 / p.tau);
+    a.fac = T(1.0 - 0.5 / p.tau);
+    a.facd = 1.0 - 0.5 / p.tau;
+    a.kpen = std::isinf(p.eta) ? T(0) : T(1.0 / p.eta);
+    a.rho0 = T(p.rho0);
+    a.rho0d = p.rho0;
+    a.gx = T(gx);
+    a.gy = T(gy);
+    return a;
+  }
+};
+
+// ----------------------------------------------------------------------------
+// kernel dispatch
+// ----------------------------------------------------------------------------
+namespace {
+
+template <typename S, int BX, int BY>
+int launch_step_t(vplbm_lattice *L, bool macro) {
+  using T = typename Store<S>::T;
+  const StepArgs<T> a = L->step_args<T>();
+  const int grid = 8 * a.per_xcd;
+  const S *fin = (const S *)L->A();
+  S *fout = (S *)L->Bbuf();
+  T *r = (T *)L->at(L->L.mrho), *u = (T *)L->at(L->L.mux), *v = (T *)L->at(L->L.muy);
+  const SiRec *recs = (const SiRec *)L->at(L->L.recs);
+  const int *smap = (const int *)L->at(L->L.si_map);
+  double *part = (double *)L->at(L->L.partials);
+  if (macro)
+    hipLaunchKernelGGL((k_step<S, BX, BY, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
+                       L->mask(), a, L->ctl(), recs, smap, part, r, u, v);
+  else
+    hipLaunchKernelGGL((k_step<S, BX, BY, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
+                       L->mask(), a, L->ctl(), recs, smap, part, r, u, v);
+  return L->launched("k_step");
+}
+
+template <typename S> int launch_step_s(vplbm_lattice *L, bool macro) {
+  if (L->bx == 64 && L->by == 4) return launch_step_t<S, 64, 4>(L, macro);
+  if (L->bx == 128 && L->by == 2) return launch_step_t<S, 128, 2>(L, macro);
+  if (L->bx == 256 && L->by == 1) return launch_step_t<S, 256, 1>(L, macro);
+  if (L->bx == 64 && L->by == 1) return launch_step_t<S, 64, 1>(L, macro);
+  if (L->bx == 64 && L->by == 2) return launch_step_t<S, 64, 2>(L, macro);
+  if (L->bx == 128 && L->by == 1) return launch_step_t<S, 128, 1>(L, macro);
+  return L->fail(VPLBM_EINVAL, "unsupported tile shape %dx%d", L->bx, L->by);
+}
+
+int launch_step(vplbm_lattice *L, bool macro) {
+  switch (L->p.precision) {
+    case VPLBM_F64: return launch_step_s<double>(L, macro);
+    case VPLBM_F32: return launch_step_s<float>(L, macro);
+    default: return launch_step_s<__half>(L, macro);
+  }
+}
+
+template <typename S>
+int launch_init_s(vplbm_lattice *L, int row0, int nrows, const double *r, const double *u,
+                  const double *v, double ru, double uu, double vu) {
+  dim3 blk(256), grd((L->p.nx + 255) / 256, nrows);
+  hipLaunchKernelGGL((k_init<S>), grd, blk, 0, L->stream, (S *)L->A(), L->mask(), L->p.nx, L->p.ny,
+                     L->pitch, L->plane, row0, nrows, r, u, v, ru, uu, vu, L->ctl(), L->p.rho0);
+  return L->launched("k_init");
+}
+
+int launch_init(vplbm_lattice *L, int row0, int nrows, const double *r, const double *u,
+                const double *v, double ru, double uu, double vu) {
+  switch (L->p.precision) {
+    case VPLBM_F64: return launch_init_s<double>(L, row0, nrows, r, u, v, ru, uu, vu);
+    case VPLBM_F32: return launch_init_s<float>(L, row0, nrows, r, u, v, ru, uu, vu);
+    default: return launch_init_s<__half>(L, row0, nrows, r, u, v, ru, uu, vu);
+  }
+}
+
+template <typename S> int launch_read_pop_s(vplbm_lattice *L, int row0, int nrows, double *out) {
+  dim3 blk(256), grd((L->p.nx + 255) / 256, nrows);
+  hipLaunchKernelGGL((k_read_pop<S>), grd, blk, 0, L->stream, (const S *)L->A(), L->p.nx, L->pitch,
+                     L->plane, row0, nrows, L->p.rho0, out);
+  return L->launched("k_read_pop");
+}
+
+int launch_read_pop(vplbm_lattice *L, int row0, int nrows, double *out) {
+  switch (L->p.precision) {
+    case VPLBM_F64: return launch_read_pop_s<double>(L, row0, nrows, out);
+    case VPLBM_F32: return launch_read_pop_s<float>(L, row0, nrows, out);
+    default: return launch_read_pop_s<__half>(L, row0, nrows, out);
+  }
+}
+
+template <typename S> int launch_si_at_s(vplbm_lattice *L, int npts, double *out) {
+  using T = typename Store<S>::T;
+  const StepArgs<T> a = L->step_args<T>();
+  hipLaunchKernelGGL((k_si_at<S>), dim3(1), dim3(SI_NT), 0, L->stream, (const S *)L->A(), L->mask(),
+                     a, L->ctl(), (const double *)L->at(L->L.staging), L->maxp, npts, out);
+  return L->launched("k_si_at");
+}
+
+int launch_flags(vplbm_lattice *L, int x0, int y0, int x1, int y1) {
+  if (x1 <= x0 || y1 <= y0) return VPLBM_OK;
+  dim3 blk(256), grd((x1 - x0 + 255) / 256, y1 - y0);
+  hipLaunchKernelGGL(k_mask_flags, grd, blk, 0, L->stream, L->mask(), L->p.nx, L->p.ny, L->pitch, x0,
+                     y0, x1, y1, (int)L->periodic_x(), (int)L->periodic_y());
+  return L->launched("k_mask_flags");
+}
+
+int launch_si_select(vplbm_lattice *L) {
+  hipLaunchKernelGGL(k_si_select, dim3(1), dim3(SI_NT), 0, L->stream, L->mask(), L->ctl(),
+                     (const double *)L->at(L->L.pts), L->maxp, (SiRec *)L->at(L->L.recs),
+                     (int *)L->at(L->L.si_map), L->p.nx, L->p.ny, L->pitch);
+  return L->launched("k_si_select");
+}
+
+int launch_body_step(vplbm_lattice *L) {
+  hipLaunchKernelGGL(k_body_step, dim3(1), dim3(BODY_NT), 0, L->stream, L->mask(), L->ctl(), L->p.nx,
+                     L->p.ny, L->pitch, (int)L->periodic_x(), (int)L->periodic_y());
+  return L->launched("k_body_step");
+}
+
+int launch_finalize(vplbm_lattice *L) {
+  hipLaunchKernelGGL((k_finalize<256>), dim3(1), dim3(256), 0, L->stream,
+                     (const double *)L->at(L->L.partials), L->ctl(), (double *)L->at(L->L.hist), L->cap,
+                     L->bx, L->by);
+  return L->launched("k_finalize");
+}
+
+long long fixq(double v) { return llround(v * FIXQ); }
+
+// clear the mask and SI tables, reset the force window
+int reset_geometry(vplbm_lattice *L, Ctl &c) {
+  int rc = L->hip(hipMemsetAsync(L->mask(), 0, (size_t)L->p.ny * L->pitch, L->stream), "mask clear");
+  if (rc) return rc;
+  c.win[0] = c.win[1] = c.win[2] = c.win[3] = 0;
+  c.region[0] = c.region[1] = c.region[2] = c.region[3] = 0;
+  c.nrec = 0;
+  return VPLBM_OK;
+}
+
+// reselect sample nodes after the mask or the points changed
+int refresh_si(vplbm_lattice *L) {
+  if (L->npts == 0) return VPLBM_OK;
+  return launch_si_select(L);
+}
+
+int check_sample_error(vplbm_lattice *L) {
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  if (c.err & 1) {
+    c.err = 0;
+    rc = L->ctl_push(c);
+    if (rc) return rc;
+    return L->fail(VPLBM_ENOSAMPLE, "a stress-integration point has no fluid sample node within 4 "
+                                    "nodes along its normal");
+  }
+  return VPLBM_OK;
+}
+
+// store SI points (world frame or, for a moving body, body frame) in device memory
+int upload_points(vplbm_lattice *L, const Ctl &c) {
+  const int n = L->npts, mp = L->maxp;
+  std::vector<double> buf((size_t)5 * mp, 0.0);
+  const bool moving = L->mode != MODE_STATIC;
+  const double co = std::cos(-c.body.theta), sn = std::sin(-c.body.theta);
+  for (int i = 0; i < n; ++i) {
+    const double x = L->si_world[i], y = L->si_world[n + i];
+    const double nx = L->si_world[2 * n + i], ny = L->si_world[3 * n + i];
+    if (moving) {
+      const double dx = x - c.body.x, dy = y - c.body.y;
+      buf[i] = co * dx - sn * dy;
+      buf[mp + i] = sn * dx + co * dy;
+      buf[2 * mp + i] = co * nx - sn * ny;
+      buf[3 * mp + i] = sn * nx + co * ny;
+    } else {
+      buf[i] = x;
+      buf[mp + i] = y;
+      buf[2 * mp + i] = nx;
+      buf[3 * mp + i] = ny;
+    }
+    buf[4 * mp + i] = L->si_world[4 * n + i];
+  }
+  int rc = L->hip(hipMemcpyAsync(L->at(L->L.pts), buf.data(), buf.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, L->stream),
+                  "SI points upload");
+  if (rc) return rc;
+  return L->sync();
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// C ABI
+// ----------------------------------------------------------------------------
+extern "C" {
+
+size_t vplbm_required_bytes(const vplbm_params *p) {
+  if (check_params(p)) return 0;
+  return layout_of(*p).total;
+}
+
+int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *hip_stream,
+                 vplbm_lattice **out) {
+  if (!out) return VPLBM_EINVAL;
+  *out = nullptr;
+  if (check_params(p)) return VPLBM_EINVAL;
+  auto *L = new (std::nothrow) vplbm_lattice();
+  if (!L) return VPLBM_ENOMEM;
+  L->p = *p;
+  L->L = layout_of(*p);
+  L->pitch = pitch_of(*p);
+  L->plane = (long long)p->ny * L->pitch;
+  L->stream = (hipStream_t)hip_stream;
+  L->cap = p->hist_capacity > 0 ? p->hist_capacity : DEFAULT_HIST;
+  L->maxp = p->max_si_points > 0 ? p->max_si_points : DEFAULT_PTS;
+  L->maxv = p->max_vertices > 0 ? p->max_vertices : DEFAULT_VERTS;
+  if (dev_mem) {
+    if (dev_bytes < L->L.total || ((uintptr_t)dev_mem % ALIGN) != 0) {
+      delete L;
+      return VPLBM_ENOMEM;
+    }
+    L->base = (char *)dev_mem;
+  } else {
+    if (hipMalloc((void **)&L->base, L->L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      delete L;
+      return VPLBM_ENOMEM;
+    }
+    L->owns = true;
+  }
+  Ctl c{};
+  c.mode = MODE_STATIC;
+  c.shape = SHAPE_NONE;
+  int rc = reset_geometry(L, c);
+  if (!rc) rc = L->ctl_push(c);
+  if (!rc) rc = launch_init(L, 0, L->p.ny, nullptr, nullptr, nullptr, p->rho0, 0.0, 0.0);
+  if (!rc) rc = L->sync();
+  if (rc) {
+    if (L->owns) (void)hipFree(L->base);
+    delete L;
+    return rc;
+  }
+  L->initialized = true;
+  *out = L;
+  return VPLBM_OK;
+}
+
+int vplbm_destroy(vplbm_lattice *L) {
+  if (!L) return VPLBM_EINVAL;
+  (void)hipStreamSynchronize(L->stream);
+  if (L->owns) (void)hipFree(L->base);
+  delete L;
+  return VPLBM_OK;
+}
+
+const char *vplbm_last_error(const vplbm_lattice *L) { return L ? L->err.c_str() : "null handle"; }
+
+static int reset_counters(vplbm_lattice *L) {
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  c.step = 0;
+  for (int i = 0; i < 6; ++i) c.last[i] = 0.0;
+  c.err = 0;
+  rc = L->ctl_push(c);
+  if (rc) return rc;
+  L->nstep = 0;
+  L->macro_valid = false;
+  return VPLBM_OK;
+}
+
+int vplbm_init_uniform(vplbm_lattice *L, double rho, double ux, double uy) {
+  if (!L) return VPLBM_EINVAL;
+  if (!(rho > 0.0) || !std::isfinite(rho) || !std::isfinite(ux) || !std::isfinite(uy))
+    return L->fail(VPLBM_EINVAL, "rho must be > 0 and velocities finite");
+  int rc = launch_init(L, 0, L->p.ny, nullptr, nullptr, nullptr, rho, ux, uy);
+  if (!rc) rc = reset_counters(L);
+  return rc;
+}
+
+int vplbm_set_fields(vplbm_lattice *L, const double *rho, const double *ux, const double *uy) {
+  if (!L || !rho || !ux || !uy) return L ? L->fail(VPLBM_EINVAL, "NULL field") : VPLBM_EINVAL;
+  const int nx = L->p.nx, ny = L->p.ny;
+  for (long long k = 0; k < (long long)nx * ny; ++k)
+    if (!(rho[k] > 0.0) || !std::isfinite(rho[k]) || !std::isfinite(ux[k]) || !std::isfinite(uy[k]))
+      return L->fail(VPLBM_EINVAL, "field value at %lld is invalid", k);
+  const int rows = std::max(1, (int)(STAGE_DOUBLES / (3 * (size_t)nx)));
+  double *st = (double *)L->at(L->L.staging);
+  for (int y0 = 0; y0 < ny; y0 += rows) {
+    const int nr = std::min(rows, ny - y0);
+    const size_t n = (size_t)nr * nx;
+    int rc = L->hip(hipMemcpyAsync(st, rho + (size_t)y0 * nx, n * 8, hipMemcpyHostToDevice, L->stream), "rho");
+    if (!rc) rc = L->hip(hipMemcpyAsync(st + n, ux + (size_t)y0 * nx, n * 8, hipMemcpyHostToDevice, L->stream), "ux");
+    if (!rc) rc = L->hip(hipMemcpyAsync(st + 2 * n, uy + (size_t)y0 * nx, n * 8, hipMemcpyHostToDevice, L->stream), "uy");
+    if (!rc) rc = launch_init(L, y0, nr, st, st + n, st + 2 * n, 0, 0, 0);
+    if (!rc) rc = L->sync();
+    if (rc) return rc;
+  }
+  return reset_counters(L);
+}
+
+int vplbm_set_body_force(vplbm_lattice *L, double gx, double gy) {
+  if (!L) return VPLBM_EINVAL;
+  if (!std::isfinite(gx) || !std::isfinite(gy)) return L->fail(VPLBM_EINVAL, "force must be finite");
+  L->gx = gx;
+  L->gy = gy;
+  return VPLBM_OK;
+}
+
+static int finish_geometry(vplbm_lattice *L, Ctl &c, int fx0, int fy0, int fx1, int fy1) {
+  // interface flags over the region, then the window, then sample nodes
+  int rc = launch_flags(L, fx0, fy0, fx1, fy1);
+  if (!rc) rc = L->sync();
+  if (rc) return rc;
+  Ctl d;
+  rc = L->ctl_pull(d);
+  if (rc) return rc;
+  d.win[0] = c.win[0]; d.win[1] = c.win[1]; d.win[2] = c.win[2]; d.win[3] = c.win[3];
+  for (int k = 0; k < 4; ++k) d.region[k] = c.region[k];
+  d.body = c.body;
+  d.shape = c.shape;
+  d.mode = c.mode;
+  d.r = c.r;
+  d.nrec = 0;
+  d.si_moving = L->mode != MODE_STATIC;
+  for (int k = 0; k < 3; ++k) d.fq[k] = c.fq[k];
+  rc = L->ctl_push(d);
+  if (rc) return rc;
+  if (L->npts) {
+    rc = upload_points(L, d);
+    if (!rc) rc = refresh_si(L);
+    if (!rc) rc = check_sample_error(L);
+  }
+  return rc;
+}
+
+int vplbm_set_body_disk(vplbm_lattice *L, double xc, double yc, double r) {
+  if (!L) return VPLBM_EINVAL;
+  if (!std::isfinite(xc) || !std::isfinite(yc) || !(r > 0.0) || !std::isfinite(r))
+    return L->fail(VPLBM_EINVAL, "disk needs finite centre and r > 0");
+  const int nx = L->p.nx, ny = L->p.ny;
+  if (xc - r < 1.0 || xc + r > nx - 2.0 || yc - r < 1.0 || yc + r > ny - 2.0)
+    return L->fail(VPLBM_EINVAL, "disk must stay one cell inside the lattice");
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  rc = reset_geometry(L, c);
+  if (rc) return rc;
+  const long long X = fixq(xc), Y = fixq(yc), R = fixq(r);
+  const int bx0 = (int)((X - R) / FIXQ) - 1, bx1 = (int)((X + R) / FIXQ) + 2;
+  const int by0 = (int)((Y - R) / FIXQ) - 1, by1 = (int)((Y + R) / FIXQ) + 2;
+  const int x0 = std::max(bx0, 0), x1 = std::min(bx1, nx), y0 = std::max(by0, 0), y1 = std::min(by1, ny);
+  if (x1 <= x0 || y1 <= y0) return L->fail(VPLBM_EINVAL, "empty disk region");
+  dim3 blk(256), grd((x1 - x0 + 255) / 256, y1 - y0);
+  hipLaunchKernelGGL(k_mask_disk, grd, blk, 0, L->stream, L->mask(), L->pitch, x0, y0, x1, y1, X, Y, R);
+  rc = L->launched("k_mask_disk");
+  if (rc) return rc;
+  c.body = BodyDev{xc, yc, 0.0, 0.0, 0.0, 0.0};
+  c.shape = SHAPE_DISK;
+  c.mode = MODE_STATIC;
+  c.r = r;
+  c.fq[0] = X; c.fq[1] = Y; c.fq[2] = R;
+  c.win[0] = std::max(bx0 - 1, 0); c.win[1] = std::max(by0 - 1, 0);
+  c.win[2] = std::min(bx1 + 1, nx); c.win[3] = std::min(by1 + 1, ny);
+  c.region[0] = std::max(bx0 - REGION_MARGIN, 0); c.region[1] = std::max(by0 - REGION_MARGIN, 0);
+  c.region[2] = std::min(bx1 + REGION_MARGIN, nx); c.region[3] = std::min(by1 + REGION_MARGIN, ny);
+  L->shape = SHAPE_DISK;
+  L->mode = MODE_STATIC;
+  L->disk_r = r;
+  return finish_geometry(L, c, c.win[0], c.win[1], c.win[2], c.win[3]);
+}
+
+int vplbm_set_body_polygon(vplbm_lattice *L, const double *xy, int nvert, double xref, double yref) {
+  if (!L) return VPLBM_EINVAL;
+  if (!xy || nvert < 3 || nvert > L->maxv)
+    return L->fail(VPLBM_EINVAL, "polygon needs 3..%d vertices", L->maxv);
+  if (!std::isfinite(xref) || !std::isfinite(yref)) return L->fail(VPLBM_EINVAL, "reference point");
+  const int nx = L->p.nx, ny = L->p.ny;
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+  std::vector<long long> v(2 * (size_t)L->maxv, 0);
+  for (int k = 0; k < nvert; ++k) {
+    const double x = xy[2 * k], y = xy[2 * k + 1];
+    if (!std::isfinite(x) || !std::isfinite(y)) return L->fail(VPLBM_EINVAL, "vertex %d not finite", k);
+    xmin = std::min(xmin, x); xmax = std::max(xmax, x);
+    ymin = std::min(ymin, y); ymax = std::max(ymax, y);
+    v[k] = fixq(x);
+    v[L->maxv + k] = fixq(y);
+  }
+  if (xmin < 1.0 || xmax > nx - 2.0 || ymin < 1.0 || ymax > ny - 2.0)
+    return L->fail(VPLBM_EINVAL, "polygon must stay one cell inside the lattice");
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  rc = reset_geometry(L, c);
+  if (rc) return rc;
+  long long *dv = (long long *)L->at(L->L.verts);
+  rc = L->hip(hipMemcpyAsync(dv, v.data(), v.size() * sizeof(long long), hipMemcpyHostToDevice, L->stream),
+              "vertices");
+  if (rc) return rc;
+  const int x0 = std::max((int)std::floor(xmin) - 1, 0), x1 = std::min((int)std::ceil(xmax) + 2, nx);
+  const int y0 = std::max((int)std::floor(ymin) - 1, 0), y1 = std::min((int)std::ceil(ymax) + 2, ny);
+  if (x1 <= x0 || y1 <= y0) return L->fail(VPLBM_EINVAL, "empty polygon region");
+  dim3 blk(256), grd((x1 - x0 + 255) / 256, y1 - y0);
+  hipLaunchKernelGGL(k_mask_polygon, grd, blk, 0, L->stream, L->mask(), L->pitch, x0, y0, x1, y1, dv,
+                     dv + L->maxv, nvert);
+  rc = L->launched("k_mask_polygon");
+  if (!rc) rc = L->sync();
+  if (rc) return rc;
+  c.body = BodyDev{xref, yref, 0.0, 0.0, 0.0, 0.0};
+  c.shape = SHAPE_POLYGON;
+  c.mode = MODE_STATIC;
+  c.r = 0.0;
+  c.win[0] = std::max(x0 - 1, 0); c.win[1] = std::max(y0 - 1, 0);
+  c.win[2] = std::min(x1 + 1, nx); c.win[3] = std::min(y1 + 1, ny);
+  for (int k = 0; k < 4; ++k) c.region[k] = c.win[k];
+  L->shape = SHAPE_POLYGON;
+  L->mode = MODE_STATIC;
+  return finish_geometry(L, c, c.win[0], c.win[1], c.win[2], c.win[3]);
+}
+
+int vplbm_set_mask(vplbm_lattice *L, const uint8_t *solid) {
+  if (!L || !solid) return L ? L->fail(VPLBM_EINVAL, "NULL mask") : VPLBM_EINVAL;
+  const int nx = L->p.nx, ny = L->p.ny;
+  std::vector<uint8_t> rows((size_t)ny * L->pitch, 0);
+  int x0 = nx, y0 = ny, x1 = -1, y1 = -1;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      if (solid[(size_t)j * nx + i]) {
+        rows[(size_t)j * L->pitch + i] = M_SOLID;
+        x0 = std::min(x0, i); x1 = std::max(x1, i);
+        y0 = std::min(y0, j); y1 = std::max(y1, j);
+      }
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  rc = reset_geometry(L, c);
+  if (rc) return rc;
+  rc = L->hip(hipMemcpyAsync(L->mask(), rows.data(), rows.size(), hipMemcpyHostToDevice, L->stream),
+              "mask upload");
+  if (!rc) rc = L->sync();
+  if (rc) return rc;
+  c.body = BodyDev{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  c.shape = SHAPE_MASK;
+  c.mode = MODE_STATIC;
+  if (x1 >= 0) {
+    // interface cells lie within one cell of the solid's box; a box reaching
+    // a periodic edge wraps, so the window then spans that axis
+    int w0 = x0 - 1, w1 = x1 + 2, h0 = y0 - 1, h1 = y1 + 2;
+    if (w0 < 0 || w1 > nx) { if (L->periodic_x()) { w0 = 0; w1 = nx; } else { w0 = std::max(w0, 0); w1 = std::min(w1, nx); } }
+    if (h0 < 0 || h1 > ny) { if (L->periodic_y()) { h0 = 0; h1 = ny; } else { h0 = std::max(h0, 0); h1 = std::min(h1, ny); } }
+    c.win[0] = w0; c.win[1] = h0; c.win[2] = w1; c.win[3] = h1;
+  }
+  for (int k = 0; k < 4; ++k) c.region[k] = c.win[k];
+  L->shape = SHAPE_MASK;
+  L->mode = MODE_STATIC;
+  return finish_geometry(L, c, 0, 0, nx, ny);
+}
+
+int vplbm_set_body_motion(vplbm_lattice *L, const vplbm_body_state *s) {
+  if (!L || !s) return L ? L->fail(VPLBM_EINVAL, "NULL state") : VPLBM_EINVAL;
+  const double v[6] = {s->x, s->y, s->theta, s->u, s->v, s->omega};
+  for (double e : v)
+    if (!std::isfinite(e)) return L->fail(VPLBM_EINVAL, "state not finite");
+  const bool moves = s->u != 0.0 || s->v != 0.0 || s->omega != 0.0;
+  if (L->shape == SHAPE_NONE) return L->fail(VPLBM_ESTATE, "no body");
+  if (L->shape != SHAPE_DISK && moves)
+    return L->fail(VPLBM_EINVAL, "only disks can move; polygons and masks are static");
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  if (L->shape == SHAPE_DISK) {
+    const double r = L->disk_r;
+    const int nx = L->p.nx, ny = L->p.ny;
+    if (s->x - r < 1.0 || s->x + r > nx - 2.0 || s->y - r < 1.0 || s->y + r > ny - 2.0)
+      return L->fail(VPLBM_EINVAL, "disk must stay one cell inside the lattice");
+    // rebuild the mask at the new position (same as a fresh disk)
+    const int npts = L->npts;
+    L->npts = 0;
+    rc = vplbm_set_body_disk(L, s->x, s->y, r);
+    L->npts = npts;
+    if (rc) return rc;
+    rc = L->ctl_pull(c);
+    if (rc) return rc;
+  }
+  c.body = BodyDev{s->x, s->y, s->theta, s->u, s->v, s->omega};
+  c.mode = moves ? MODE_PRESCRIBED : MODE_STATIC;
+  L->mode = c.mode;
+  rc = L->ctl_push(c);
+  if (rc) return rc;
+  if (L->npts) {
+    rc = upload_points(L, c);
+    if (rc) return rc;
+    c.si_moving = L->mode != MODE_STATIC;
+    Ctl d;
+    rc = L->ctl_pull(d);
+    if (rc) return rc;
+    d.si_moving = c.si_moving;
+    rc = L->ctl_push(d);
+    if (!rc) rc = launch_flags(L, d.region[0], d.region[1], d.region[2], d.region[3]);
+    if (!rc) rc = refresh_si(L);
+    if (!rc) rc = check_sample_error(L);
+  }
+  return rc;
+}
+
+int vplbm_set_body_dynamics(vplbm_lattice *L, double rho_s, double gx, double gy, int source) {
+  if (!L) return VPLBM_EINVAL;
+  if (L->shape != SHAPE_DISK) return L->fail(VPLBM_ESTATE, "free bodies must be disks");
+  if (!(rho_s > 0.0) || !std::isfinite(rho_s) || !std::isfinite(gx) || !std::isfinite(gy))
+    return L->fail(VPLBM_EINVAL, "rho_s > 0 and finite gravity required");
+  if (source != VPLBM_FORCE_ME && source != VPLBM_FORCE_SI)
+    return L->fail(VPLBM_EINVAL, "force_source must be ME (0) or SI (1)");
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  const double r = L->disk_r;
+  c.mass = rho_s * M_PI * r * r;
+  c.inertia = 0.5 * c.mass * r * r;
+  c.gx = gx;
+  c.gy = gy;
+  c.buoy = 1.0 - L->p.rho0 / rho_s;
+  c.source = source;
+  c.mode = MODE_FREE;
+  c.si_moving = 1;
+  L->mode = MODE_FREE;
+  rc = L->ctl_push(c);
+  if (!rc && L->npts) rc = upload_points(L, c);
+  return rc;
+}
+
+int vplbm_set_si_points(vplbm_lattice *L, const double *xy, const double *nrm, const double *ds, int npts) {
+  if (!L) return VPLBM_EINVAL;
+  if (npts < 0 || npts > L->maxp) return L->fail(VPLBM_EINVAL, "npts must be in 0..%d", L->maxp);
+  if (npts > 0 && (!xy || !nrm || !ds)) return L->fail(VPLBM_EINVAL, "NULL point arrays");
+  for (int i = 0; i < npts; ++i)
+    if (!std::isfinite(xy[2 * i]) || !std::isfinite(xy[2 * i + 1]) || !std::isfinite(nrm[2 * i]) ||
+        !std::isfinite(nrm[2 * i + 1]) || !std::isfinite(ds[i]))
+      return L->fail(VPLBM_EINVAL, "point %d not finite", i);
+  L->si_world.assign((size_t)5 * npts, 0.0);
+  for (int i = 0; i < npts; ++i) {
+    L->si_world[i] = xy[2 * i];
+    L->si_world[npts + i] = xy[2 * i + 1];
+    L->si_world[2 * npts + i] = nrm[2 * i];
+    L->si_world[3 * npts + i] = nrm[2 * i + 1];
+    L->si_world[4 * npts + i] = ds[i];
+  }
+  L->npts = npts;
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  c.npts = npts;
+  c.si_moving = L->mode != MODE_STATIC;
+  c.nrec = 0;
+  rc = L->ctl_push(c);
+  if (rc) return rc;
+  // clear old sample bits: recompute flags over the window and region
+  const int x0 = std::min(c.win[0], c.region[0]), y0 = std::min(c.win[1], c.region[1]);
+  const int x1 = std::max(c.win[2], c.region[2]), y1 = std::max(c.win[3], c.region[3]);
+  rc = launch_flags(L, x0, y0, x1, y1);
+  if (rc) return rc;
+  if (npts == 0) return L->sync();
+  rc = upload_points(L, c);
+  if (!rc) rc = refresh_si(L);
+  if (!rc) rc = check_sample_error(L);
+  return rc;
+}
+
+int vplbm_step(vplbm_lattice *L, int nsteps, int flags) {
+  if (!L) return VPLBM_EINVAL;
+  if (nsteps < 0) return L->fail(VPLBM_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return VPLBM_OK;
+  const bool moving = L->mode != MODE_STATIC;
+  for (int i = 0; i < nsteps; ++i) {
+    const bool macro = (flags & VPLBM_STEP_MACRO) && i == nsteps - 1;
+    int rc = launch_step(L, macro);
+    if (!rc) rc = launch_finalize(L);
+    if (!rc && moving) {
+      if (L->shape == SHAPE_DISK) rc = launch_body_step(L);
+      if (!rc && L->npts) rc = launch_si_select(L);
+    }
+    if (rc) return rc;
+    L->cur ^= 1;
+  }
+  L->nstep += nsteps;
+  L->macro_valid = (flags & VPLBM_STEP_MACRO) != 0;
+  return VPLBM_OK;
+}
+
+int vplbm_step_timed(vplbm_lattice *L, int nsteps, int flags, double *kernel_ms) {
+  if (!L || !kernel_ms) return VPLBM_EINVAL;
+  if (nsteps < 0) return L->fail(VPLBM_EINVAL, "nsteps must be >= 0");
+  *kernel_ms = 0.0;
+  if (nsteps == 0) return VPLBM_OK;
+  std::vector<hipEvent_t> ev(2 * (size_t)nsteps, nullptr);
+  int rc = VPLBM_OK;
+  for (auto &e : ev)
+    if (!rc) rc = L->hip(hipEventCreate(&e), "hipEventCreate");
+  const bool moving = L->mode != MODE_STATIC;
+  int done = 0;
+  for (int i = 0; i < nsteps && !rc; ++i) {
+    const bool macro = (flags & VPLBM_STEP_MACRO) && i == nsteps - 1;
+    rc = L->hip(hipEventRecord(ev[2 * i], L->stream), "hipEventRecord");
+    if (!rc) rc = launch_step(L, macro);
+    if (!rc) rc = L->hip(hipEventRecord(ev[2 * i + 1], L->stream), "hipEventRecord");
+    if (!rc) rc = launch_finalize(L);
+    if (!rc && moving) {
+      if (L->shape == SHAPE_DISK) rc = launch_body_step(L);
+      if (!rc && L->npts) rc = launch_si_select(L);
+    }
+    if (!rc) {
+      L->cur ^= 1;
+      ++done;
+    }
+  }
+  L->nstep += done;
+  L->macro_valid = (flags & VPLBM_STEP_MACRO) != 0 && done == nsteps;
+  if (!rc) rc = L->sync();
+  double total = 0.0;
+  for (int i = 0; i < done && !rc; ++i) {
+    float ms = 0.f;
+    rc = L->hip(hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]), "hipEventElapsedTime");
+    total += ms;
+  }
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
+  *kernel_ms = total;
+  return rc;
+}
+
+int vplbm_sync(vplbm_lattice *L) {
+  if (!L) return VPLBM_EINVAL;
+  int rc = L->sync();
+  if (rc) return rc;
+  if (L->npts && L->mode != MODE_STATIC) return check_sample_error(L);
+  return VPLBM_OK;
+}
+
+long long vplbm_step_count(const vplbm_lattice *L) { return L ? L->nstep : -1; }
+
+int vplbm_set_tile(vplbm_lattice *L, int bx, int by) {
+  if (!L) return VPLBM_EINVAL;
+  const bool ok = (bx == 64 && (by == 1 || by == 2 || by == 4)) || (bx == 128 && (by == 1 || by == 2)) ||
+                  (bx == 256 && by == 1);
+  if (!ok) return L->fail(VPLBM_EINVAL, "unsupported tile %dx%d", bx, by);
+  L->bx = bx;
+  L->by = by;
+  return VPLBM_OK;
+}
+
+static int read_last(vplbm_lattice *L, int which, double out[3]) {
+  if (!L || !out) return VPLBM_EINVAL;
+  if (L->nstep == 0) return L->fail(VPLBM_ESTATE, "no step taken yet");
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  for (int i = 0; i < 3; ++i) out[i] = c.last[3 * which + i];
+  if (c.err & 1) return L->fail(VPLBM_ENOSAMPLE, "a stress-integration point lost its sample node");
+  return VPLBM_OK;
+}
+
+int vplbm_forces_me(vplbm_lattice *L, double out[3]) { return read_last(L, 0, out); }
+int vplbm_forces_si(vplbm_lattice *L, double out[3]) { return read_last(L, 1, out); }
+
+int vplbm_forces_si_at(vplbm_lattice *L, const double *xy, const double *nrm, const double *ds, int npts,
+                       double out[3]) {
+  if (!L || !out) return VPLBM_EINVAL;
+  if (npts < 0 || npts > L->maxp || (npts > 0 && (!xy || !nrm || !ds)))
+    return L->fail(VPLBM_EINVAL, "bad points");
+  const int mp = L->maxp;
+  std::vector<double> buf((size_t)5 * mp, 0.0);
+  for (int i = 0; i < npts; ++i) {
+    buf[i] = xy[2 * i];
+    buf[mp + i] = xy[2 * i + 1];
+    buf[2 * mp + i] = nrm[2 * i];
+    buf[3 * mp + i] = nrm[2 * i + 1];
+    buf[4 * mp + i] = ds[i];
+  }
+  if ((size_t)5 * mp > STAGE_DOUBLES) return L->fail(VPLBM_EINVAL, "too many points");
+  double *st = (double *)L->at(L->L.staging);
+  double *o = (double *)L->at(L->L.siout);
+  int rc = L->hip(hipMemcpyAsync(st, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, L->stream), "pts");
+  if (rc) return rc;
+  switch (L->p.precision) {
+    case VPLBM_F64: rc = launch_si_at_s<double>(L, npts, o); break;
+    case VPLBM_F32: rc = launch_si_at_s<float>(L, npts, o); break;
+    default: rc = launch_si_at_s<__half>(L, npts, o); break;
+  }
+  if (rc) return rc;
+  double h[4];
+  rc = L->hip(hipMemcpyAsync(h, o, sizeof h, hipMemcpyDeviceToHost, L->stream), "si_at read");
+  if (!rc) rc = L->sync();
+  if (rc) return rc;
+  out[0] = h[0]; out[1] = h[1]; out[2] = h[2];
+  if (h[3] != 0.0) return L->fail(VPLBM_ENOSAMPLE, "%d points without a sample node", (int)h[3]);
+  return VPLBM_OK;
+}
+
+int vplbm_force_history(vplbm_lattice *L, int which, long long first, int n, double *out) {
+  if (!L || !out || n < 0) return VPLBM_EINVAL;
+  if (which != VPLBM_FORCE_ME && which != VPLBM_FORCE_SI) return L->fail(VPLBM_EINVAL, "which");
+  if (first < 1 || first + n - 1 > L->nstep || first <= L->nstep - L->cap)
+    return L->fail(VPLBM_EINVAL, "steps %lld..%lld outside the kept history", first, first + n - 1);
+  std::vector<double> h((size_t)L->cap * 6);
+  int rc = L->hip(hipMemcpyAsync(h.data(), L->at(L->L.hist), h.size() * 8, hipMemcpyDeviceToHost, L->stream),
+                  "history read");
+  if (!rc) rc = L->sync();
+  if (rc) return rc;
+  for (int k = 0; k < n; ++k) {
+    const long long s = (first + k) % L->cap;
+    for (int i = 0; i < 3; ++i) out[3 * k + i] = h[s * 6 + 3 * which + i];
+  }
+  return VPLBM_OK;
+}
+
+int vplbm_get_body_state(vplbm_lattice *L, vplbm_body_state *out) {
+  if (!L || !out) return VPLBM_EINVAL;
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  *out = vplbm_body_state{c.body.x, c.body.y, c.body.theta, c.body.u, c.body.v, c.body.omega};
+  return VPLBM_OK;
+}
+
+int vplbm_read_macro(vplbm_lattice *L, double *rho, double *ux, double *uy) {
+  if (!L || !rho || !ux || !uy) return VPLBM_EINVAL;
+  if (!L->macro_valid) return L->fail(VPLBM_ESTATE, "last step did not store rho and u (VPLBM_STEP_MACRO)");
+  const int nx = L->p.nx, ny = L->p.ny;
+  const int rows = std::max(1, (int)(STAGE_DOUBLES / (3 * (size_t)nx)));
+  double *st = (double *)L->at(L->L.staging);
+  std::vector<double> h;
+  for (int y0 = 0; y0 < ny; y0 += rows) {
+    const int nr = std::min(rows, ny - y0);
+    const size_t n = (size_t)nr * nx;
+    dim3 blk(256), grd((nx + 255) / 256, nr);
+    if (L->p.precision == VPLBM_F64)
+      hipLaunchKernelGGL((k_read_macro<double>), grd, blk, 0, L->stream, (const double *)L->at(L->L.mrho),
+                         (const double *)L->at(L->L.mux), (const double *)L->at(L->L.muy), nx, L->pitch, y0,
+                         nr, st);
+    else
+      hipLaunchKernelGGL((k_read_macro<float>), grd, blk, 0, L->stream, (const float *)L->at(L->L.mrho),
+                         (const float *)L->at(L->L.mux), (const float *)L->at(L->L.muy), nx, L->pitch, y0,
+                         nr, st);
+    int rc = L->launched("k_read_macro");
+    h.resize(3 * n);
+    if (!rc) rc = L->hip(hipMemcpyAsync(h.data(), st, 3 * n * 8, hipMemcpyDeviceToHost, L->stream), "macro");
+    if (!rc) rc = L->sync();
+    if (rc) return rc;
+    std::memcpy(rho + (size_t)y0 * nx, h.data(), n * 8);
+    std::memcpy(ux + (size_t)y0 * nx, h.data() + n, n * 8);
+    std::memcpy(uy + (size_t)y0 * nx, h.data() + 2 * n, n * 8);
+  }
+  return VPLBM_OK;
+}
+
+int vplbm_read_populations(vplbm_lattice *L, double *f) {
+  if (!L || !f) return VPLBM_EINVAL;
+  const int nx = L->p.nx, ny = L->p.ny;
+  const int rows = std::max(1, (int)(STAGE_DOUBLES / (9 * (size_t)nx)));
+  double *st = (double *)L->at(L->L.staging);
+  std::vector<double> h;
+  for (int y0 = 0; y0 < ny; y0 += rows) {
+    const int nr = std::min(rows, ny - y0);
+    const size_t n = (size_t)nr * nx;
+    int rc = launch_read_pop(L, y0, nr, st);
+    h.resize(9 * n);
+    if (!rc) rc = L->hip(hipMemcpyAsync(h.data(), st, 9 * n * 8, hipMemcpyDeviceToHost, L->stream), "pop");
+    if (!rc) rc = L->sync();
+    if (rc) return rc;
+    for (int a = 0; a < Q; ++a)
+      std::memcpy(f + (size_t)a * nx * ny + (size_t)y0 * nx, h.data() + a * n, n * 8);
+  }
+  return VPLBM_OK;
+}
+
+int vplbm_read_mask(vplbm_lattice *L, uint8_t *out) {
+  if (!L || !out) return VPLBM_EINVAL;
+  int rc = L->hip(hipMemcpy2DAsync(out, L->p.nx, L->mask(), L->pitch, L->p.nx, L->p.ny,
+                                   hipMemcpyDeviceToHost, L->stream),
+                  "mask read");
+  if (!rc) rc = L->sync();
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+"""C-ABI contract checks that run without a GPU: the library loads, exports
+every entry point include/vplbm.h declares, and its parameter validation
+(vplbm_required_bytes, pure host logic) accepts and rejects what the header
+says."""
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2110_00967_amd import vplbm as V
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vplbm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vplbm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_what_the_binding_wraps():
+    assert declared_functions() == sorted(V.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = V.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", V.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (vplbm_[a-z_]+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_library_has_no_oracle_dependency():
+    out = subprocess.run(["ldd", V.LIB_PATH], capture_output=True, text=True).stdout
+    assert "oracle" not in out
+    syms = subprocess.run(["nm", "-D", V.LIB_PATH], capture_output=True, text=True).stdout
+    assert "orc_" not in syms
+
+
+def base(**kw):
+    args = dict(nx=128, ny=64, tau=0.62, eta=1e-4, precision="f32", west=(V.VELOCITY, 0.05, 0),
+                east=(V.OUTFLOW, 0, 0), south=(V.PERIODIC, 0, 0), north=(V.PERIODIC, 0, 0))
+    args.update(kw)
+    return V.make_params(**args)
+
+
+def test_required_bytes_valid():
+    n32 = V.required_bytes(base())
+    n64 = V.required_bytes(base(precision="f64"))
+    n16 = V.required_bytes(base(precision="f16dev"))
+    assert 0 < n16 < n32 < n64
+    # A and B dominate: 2 * 9 planes of the padded lattice
+    assert n32 >= 2 * 9 * 64 * 128 * 4
+    assert V.required_bytes(base(nx=2000, ny=1000)) > 2 * 9 * 2000 * 1000 * 4
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=3), dict(ny=2), dict(tau=0.5), dict(tau=0.3), dict(tau=float("nan")), dict(eta=0.0),
+    dict(eta=-1.0), dict(eta=float("nan")), dict(precision=7), dict(west=(V.PERIODIC, 0, 0)),
+    dict(south=(V.VELOCITY, 0, 0)), dict(north=(9, 0, 0)), dict(east=(V.VELOCITY, float("inf"), 0)),
+    dict(nx=200000, ny=200000), dict(max_si_points=5000), dict(hist_capacity=-1),
+])
+def test_required_bytes_rejects(kw):
+    assert V.required_bytes(base(**kw)) == 0
+
+
+def test_eta_infinite_is_allowed():
+    assert V.required_bytes(base(eta=math.inf)) > 0
