@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f16dev", "f64"])
     ap.add_argument("--tile", default=None, help="step tile BXxBY (default: library choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path", file=sys.stderr)
@@ -128,6 +130,20 @@ def main():
                    "finite": finite, "steps_run": lat.step_count},
     }
     lat.close()
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        c1.record()
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30, "launches": 5,
+                                   "GBps": round(2 * (1 << 30) * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9, 1)}
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W.case_naca(chord=200, aoa_deg=10.0))
     print(json.dumps(out), flush=True)

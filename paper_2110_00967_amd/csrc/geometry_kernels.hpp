@@ -158,10 +158,19 @@ constexpr int BODY_NT = 1024;
 constexpr int REGION_MARGIN = 6;  // covers links (1) and sample walks (5)
 
 __global__ void __launch_bounds__(BODY_NT)
-    k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, int nx, int ny, int pitch, int perx,
+    k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ part,
+                double *__restrict__ hist, int cap, int BX, int BY, int nx, int ny, int pitch, int perx,
                 int pery) {
   __shared__ int reg[4];   // union region to rewrite
   __shared__ long long q[3];
+  __shared__ double lds[(BODY_NT / 64) * 6];
+  {
+    // forces of the step just taken (its window), needed by the update below
+    const int wx0 = ctl->win[0] / BX, wy0 = ctl->win[1] / BY;
+    const int wx1 = (ctl->win[2] + BX - 1) / BX, wy1 = (ctl->win[3] + BY - 1) / BY;
+    finalize_block<BODY_NT>(part, wx1 - wx0, wy1 - wy0, ctl, hist, cap, lds);
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     BodyDev B = ctl->body;
     if (ctl->mode == MODE_FREE) {
@@ -199,6 +208,11 @@ __global__ void __launch_bounds__(BODY_NT)
     ctl->win[1] = max(by0 - 1, 0);
     ctl->win[2] = min(bx1 + 1, nx);
     ctl->win[3] = min(by1 + 1, ny);
+    if (ctl->win[2] <= ctl->win[0] || ctl->win[3] <= ctl->win[1]) {
+      // body outside the lattice: keep a one-cell window so forces are still published
+      ctl->win[0] = ctl->win[1] = 0;
+      ctl->win[2] = ctl->win[3] = 1;
+    }
   }
   __syncthreads();
   const int x0 = reg[0], y0 = reg[1], w = reg[2] - reg[0], h = reg[3] - reg[1];

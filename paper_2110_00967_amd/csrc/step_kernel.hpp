@@ -18,7 +18,10 @@
 //   5. sample cells: stress (Sec. 2.3.2 sigma) of the streamed populations,
 //      contracted with the node's aggregated integration weights (Eq. defFf);
 //   6. blocks inside the force window reduce (ME, SI) in FP64 with wave
-//      shuffles and LDS and write one partial per block.
+//      shuffles and LDS and write one partial per block (two partial buffers,
+//      alternating by step); block 0 of the next step -- after the kernel
+//      boundary made them visible -- sums the previous step's partials in
+//      window order (deterministic) into the force-history ring.
 // HBM traffic per cell: 9 loads + 9 stores of the storage type + 1 mask byte.
 #pragma once
 
@@ -94,12 +97,38 @@ __device__ __forceinline__ void block_reduce6(double (&v)[6], double *lds /*[NT/
   }
 }
 
+// Fixed-order sum of one step's window partials -> force-history slot of the
+// next unfinished step (deterministic: same window, same order, same sum).
+template <int NT>
+__device__ __forceinline__ void finalize_block(const double *__restrict__ part, int nwx, int nwy,
+                                               Ctl *__restrict__ ctl, double *__restrict__ hist, int cap,
+                                               double *lds) {
+  const int nwin = (nwx > 0 && nwy > 0) ? nwx * nwy : 0;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < nwin; t += NT) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] += part[(long long)t * PART_STRIDE + i];
+  }
+  block_reduce6<NT>(v, lds);
+  if (threadIdx.x == 0) {
+    const long long n = ctl->step + 1;
+    double *h = hist + (n % cap) * 6;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      h[i] = v[i];
+      ctl->last[i] = v[i];
+    }
+    ctl->step = n;
+  }
+}
+
 template <typename S, int BX, int BY, bool MACRO>
 __global__ void __launch_bounds__(BX *BY)
     k_step(const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
-           const StepArgs<typename Store<S>::T> P, const Ctl *__restrict__ ctl,
+           const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl,
            const SiRec *__restrict__ recs, const int *__restrict__ si_map,
-           double *__restrict__ partials, typename Store<S>::T *__restrict__ mrho,
+           double *__restrict__ part_out, const double *__restrict__ part_prev, int fin_prev,
+           double *__restrict__ hist, int cap, typename Store<S>::T *__restrict__ mrho,
            typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy) {
   using T = typename Store<S>::T;
   constexpr int NT = BX * BY;
@@ -225,43 +254,30 @@ __global__ void __launch_bounds__(BX *BY)
     }
   }
 
+  __shared__ double lds[(NT / 64) * 6];
   if (inwin) {
-    __shared__ double lds[(NT / 64) * 6];
     block_reduce6<NT>(acc, lds);
     if (threadIdx.x == 0) {
-      double *o = partials + (long long)((ty - wy0) * (wx1 - wx0) + (tx - wx0)) * PART_STRIDE;
+      double *o = part_out + (long long)((ty - wy0) * (wx1 - wx0) + (tx - wx0)) * PART_STRIDE;
 #pragma unroll
       for (int i = 0; i < 6; ++i) o[i] = acc[i];
     }
   }
+  if (fin_prev && b == 0) {
+    // forces of the previous step (same window: only static bodies defer)
+    __syncthreads();
+    finalize_block<NT>(part_prev, wx1 - wx0, wy1 - wy0, ctl, hist, cap, lds);
+  }
 }
 
-// Fixed-order sum of the window's block partials -> force history slot of
-// the step just taken (deterministic: same window, same order, same sum).
 template <int NT>
 __global__ void __launch_bounds__(NT)
-    k_finalize(const double *__restrict__ partials, Ctl *__restrict__ ctl, double *__restrict__ hist,
-               int cap, int BX, int BY) {
+    k_finalize(const double *__restrict__ part, Ctl *__restrict__ ctl, double *__restrict__ hist, int cap,
+               int BX, int BY) {
+  __shared__ double lds[(NT / 64) * 6];
   const int wx0 = ctl->win[0] / BX, wy0 = ctl->win[1] / BY;
   const int wx1 = (ctl->win[2] + BX - 1) / BX, wy1 = (ctl->win[3] + BY - 1) / BY;
-  const int nwin = (wx1 > wx0 && wy1 > wy0) ? (wx1 - wx0) * (wy1 - wy0) : 0;
-  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int t = threadIdx.x; t < nwin; t += NT) {
-#pragma unroll
-    for (int i = 0; i < 6; ++i) v[i] += partials[(long long)t * PART_STRIDE + i];
-  }
-  __shared__ double lds[(NT / 64) * 6];
-  block_reduce6<NT>(v, lds);
-  if (threadIdx.x == 0) {
-    const long long n = ctl->step + 1;
-    double *h = hist + (n % cap) * 6;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      h[i] = v[i];
-      ctl->last[i] = v[i];
-    }
-    ctl->step = n;
-  }
+  finalize_block<NT>(part, wx1 - wx0, wy1 - wy0, ctl, hist, cap, lds);
 }
 
 }  // namespace vp

@@ -50,7 +50,8 @@ int pitch_of(const vplbm_params &p) {
 }
 
 struct Layout {
-  size_t A, B, mask, mrho, mux, muy, si_map, partials, hist, ctl, recs, pts, verts, staging, siout, total;
+  size_t A, B, mask, mrho, mux, muy, si_map, partials, partials_stride, hist, ctl, recs, pts, verts, staging,
+      siout, total;
 };
 
 Layout layout_of(const vplbm_params &p) {
@@ -67,6 +68,7 @@ Layout layout_of(const vplbm_params &p) {
     o = align_up(o + bytes, ALIGN);
     return at;
   };
+  L.partials_stride = ntiles * PART_STRIDE * sizeof(double);
   L.A = take(9 * cells * elem_size(p.precision));
   L.B = take(9 * cells * elem_size(p.precision));
   L.mask = take(cells);
@@ -74,7 +76,7 @@ Layout layout_of(const vplbm_params &p) {
   L.mux = take(cells * compute_size(p.precision));
   L.muy = take(cells * compute_size(p.precision));
   L.si_map = take(cells * sizeof(int));
-  L.partials = take(ntiles * PART_STRIDE * sizeof(double));
+  L.partials = take(2 * ntiles * PART_STRIDE * sizeof(double));  // two buffers, by step parity
   L.hist = take((size_t)cap * 6 * sizeof(double));
   L.ctl = take(sizeof(Ctl));
   L.recs = take((size_t)maxp * sizeof(SiRec));
@@ -125,6 +127,7 @@ struct vplbm_lattice {
   bool owns = false;
   int cur = 0;  // 0: A holds the state, 1: B
   long long nstep = 0;
+  bool pending = false;  // forces of the last step not yet summed into the history
   bool initialized = false;
   bool macro_valid = false;
   int cap = 0, maxp = 0, maxv = 0;
@@ -141,6 +144,8 @@ struct vplbm_lattice {
   void *Bbuf() const { return at(cur == 0 ? L.B : L.A); }
   uint8_t *mask() const { return (uint8_t *)at(L.mask); }
   Ctl *ctl() const { return (Ctl *)at(L.ctl); }
+  // partial sums written by step n live in buffer n % 2
+  double *part(long long n) const { return (double *)at(L.partials + (size_t)(n & 1) * L.partials_stride); }
 
   int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -215,13 +220,17 @@ int launch_step_t(vplbm_lattice *L, bool macro) {
   T *r = (T *)L->at(L->L.mrho), *u = (T *)L->at(L->L.mux), *v = (T *)L->at(L->L.muy);
   const SiRec *recs = (const SiRec *)L->at(L->L.recs);
   const int *smap = (const int *)L->at(L->L.si_map);
-  double *part = (double *)L->at(L->L.partials);
+  const long long n = L->nstep + 1;  // the step this launch computes
+  double *pout = L->part(n);
+  const double *pprev = L->part(n - 1);
+  const int fin_prev = L->pending ? 1 : 0;
+  double *hist = (double *)L->at(L->L.hist);
   if (macro)
     hipLaunchKernelGGL((k_step<S, BX, BY, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
-                       L->mask(), a, L->ctl(), recs, smap, part, r, u, v);
+                       L->mask(), a, L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
   else
     hipLaunchKernelGGL((k_step<S, BX, BY, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
-                       L->mask(), a, L->ctl(), recs, smap, part, r, u, v);
+                       L->mask(), a, L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
   return L->launched("k_step");
 }
 
@@ -299,17 +308,42 @@ int launch_si_select(vplbm_lattice *L) {
   return L->launched("k_si_select");
 }
 
+// after the step kernel of step n (= nstep + 1): finalize its forces, move the
+// body, rebuild the mask
 int launch_body_step(vplbm_lattice *L) {
-  hipLaunchKernelGGL(k_body_step, dim3(1), dim3(BODY_NT), 0, L->stream, L->mask(), L->ctl(), L->p.nx,
-                     L->p.ny, L->pitch, (int)L->periodic_x(), (int)L->periodic_y());
+  hipLaunchKernelGGL(k_body_step, dim3(1), dim3(BODY_NT), 0, L->stream, L->mask(), L->ctl(),
+                     (const double *)L->part(L->nstep + 1), (double *)L->at(L->L.hist), L->cap, L->bx, L->by,
+                     L->p.nx, L->p.ny, L->pitch, (int)L->periodic_x(), (int)L->periodic_y());
   return L->launched("k_body_step");
 }
 
-int launch_finalize(vplbm_lattice *L) {
-  hipLaunchKernelGGL((k_finalize<256>), dim3(1), dim3(256), 0, L->stream,
-                     (const double *)L->at(L->L.partials), L->ctl(), (double *)L->at(L->L.hist), L->cap,
-                     L->bx, L->by);
-  return L->launched("k_finalize");
+// sum the partials of the last step into the history (forces readable)
+int flush(vplbm_lattice *L) {
+  if (!L->pending) return VPLBM_OK;
+  hipLaunchKernelGGL((k_finalize<256>), dim3(1), dim3(256), 0, L->stream, (const double *)L->part(L->nstep),
+                     L->ctl(), (double *)L->at(L->L.hist), L->cap, L->bx, L->by);
+  int rc = L->launched("k_finalize");
+  if (!rc) L->pending = false;
+  return rc;
+}
+
+// one time step: the step kernel, then for a moving disk the body kernel
+// (which finalizes this step's forces) and the sample reselection; a static
+// body leaves its forces to the next step kernel or to flush()
+int one_step(vplbm_lattice *L, bool macro) {
+  int rc = launch_step(L, macro);
+  if (rc) return rc;
+  if (L->mode != MODE_STATIC) {  // only disks move
+    rc = launch_body_step(L);
+    if (!rc && L->npts) rc = launch_si_select(L);
+    if (rc) return rc;
+    L->pending = false;
+  } else {
+    L->pending = true;
+  }
+  L->cur ^= 1;
+  L->nstep += 1;
+  return VPLBM_OK;
 }
 
 long long fixq(double v) { return llround(v * FIXQ); }
@@ -318,7 +352,10 @@ long long fixq(double v) { return llround(v * FIXQ); }
 int reset_geometry(vplbm_lattice *L, Ctl &c) {
   int rc = L->hip(hipMemsetAsync(L->mask(), 0, (size_t)L->p.ny * L->pitch, L->stream), "mask clear");
   if (rc) return rc;
-  c.win[0] = c.win[1] = c.win[2] = c.win[3] = 0;
+  // the force window is never empty: with no body it is the first cell, so
+  // the step kernel still publishes (zero) forces for every step
+  c.win[0] = c.win[1] = 0;
+  c.win[2] = c.win[3] = 1;
   c.region[0] = c.region[1] = c.region[2] = c.region[3] = 0;
   c.nrec = 0;
   return VPLBM_OK;
@@ -452,6 +489,7 @@ static int reset_counters(vplbm_lattice *L) {
   rc = L->ctl_push(c);
   if (rc) return rc;
   L->nstep = 0;
+  L->pending = false;
   L->macro_valid = false;
   return VPLBM_OK;
 }
@@ -523,6 +561,10 @@ static int finish_geometry(vplbm_lattice *L, Ctl &c, int fx0, int fy0, int fx1, 
 
 int vplbm_set_body_disk(vplbm_lattice *L, double xc, double yc, double r) {
   if (!L) return VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   if (!std::isfinite(xc) || !std::isfinite(yc) || !(r > 0.0) || !std::isfinite(r))
     return L->fail(VPLBM_EINVAL, "disk needs finite centre and r > 0");
   const int nx = L->p.nx, ny = L->p.ny;
@@ -559,6 +601,10 @@ int vplbm_set_body_disk(vplbm_lattice *L, double xc, double yc, double r) {
 
 int vplbm_set_body_polygon(vplbm_lattice *L, const double *xy, int nvert, double xref, double yref) {
   if (!L) return VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   if (!xy || nvert < 3 || nvert > L->maxv)
     return L->fail(VPLBM_EINVAL, "polygon needs 3..%d vertices", L->maxv);
   if (!std::isfinite(xref) || !std::isfinite(yref)) return L->fail(VPLBM_EINVAL, "reference point");
@@ -607,6 +653,10 @@ int vplbm_set_body_polygon(vplbm_lattice *L, const double *xy, int nvert, double
 
 int vplbm_set_mask(vplbm_lattice *L, const uint8_t *solid) {
   if (!L || !solid) return L ? L->fail(VPLBM_EINVAL, "NULL mask") : VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   const int nx = L->p.nx, ny = L->p.ny;
   std::vector<uint8_t> rows((size_t)ny * L->pitch, 0);
   int x0 = nx, y0 = ny, x1 = -1, y1 = -1;
@@ -645,6 +695,10 @@ int vplbm_set_mask(vplbm_lattice *L, const uint8_t *solid) {
 
 int vplbm_set_body_motion(vplbm_lattice *L, const vplbm_body_state *s) {
   if (!L || !s) return L ? L->fail(VPLBM_EINVAL, "NULL state") : VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   const double v[6] = {s->x, s->y, s->theta, s->u, s->v, s->omega};
   for (double e : v)
     if (!std::isfinite(e)) return L->fail(VPLBM_EINVAL, "state not finite");
@@ -692,6 +746,10 @@ int vplbm_set_body_motion(vplbm_lattice *L, const vplbm_body_state *s) {
 
 int vplbm_set_body_dynamics(vplbm_lattice *L, double rho_s, double gx, double gy, int source) {
   if (!L) return VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   if (L->shape != SHAPE_DISK) return L->fail(VPLBM_ESTATE, "free bodies must be disks");
   if (!(rho_s > 0.0) || !std::isfinite(rho_s) || !std::isfinite(gx) || !std::isfinite(gy))
     return L->fail(VPLBM_EINVAL, "rho_s > 0 and finite gravity required");
@@ -717,6 +775,10 @@ int vplbm_set_body_dynamics(vplbm_lattice *L, double rho_s, double gx, double gy
 
 int vplbm_set_si_points(vplbm_lattice *L, const double *xy, const double *nrm, const double *ds, int npts) {
   if (!L) return VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   if (npts < 0 || npts > L->maxp) return L->fail(VPLBM_EINVAL, "npts must be in 0..%d", L->maxp);
   if (npts > 0 && (!xy || !nrm || !ds)) return L->fail(VPLBM_EINVAL, "NULL point arrays");
   for (int i = 0; i < npts; ++i)
@@ -756,19 +818,12 @@ int vplbm_step(vplbm_lattice *L, int nsteps, int flags) {
   if (!L) return VPLBM_EINVAL;
   if (nsteps < 0) return L->fail(VPLBM_EINVAL, "nsteps must be >= 0");
   if (nsteps == 0) return VPLBM_OK;
-  const bool moving = L->mode != MODE_STATIC;
   for (int i = 0; i < nsteps; ++i) {
     const bool macro = (flags & VPLBM_STEP_MACRO) && i == nsteps - 1;
-    int rc = launch_step(L, macro);
-    if (!rc) rc = launch_finalize(L);
-    if (!rc && moving) {
-      if (L->shape == SHAPE_DISK) rc = launch_body_step(L);
-      if (!rc && L->npts) rc = launch_si_select(L);
-    }
+    L->macro_valid = false;
+    int rc = one_step(L, macro);
     if (rc) return rc;
-    L->cur ^= 1;
   }
-  L->nstep += nsteps;
   L->macro_valid = (flags & VPLBM_STEP_MACRO) != 0;
   return VPLBM_OK;
 }
@@ -784,22 +839,25 @@ int vplbm_step_timed(vplbm_lattice *L, int nsteps, int flags, double *kernel_ms)
     if (!rc) rc = L->hip(hipEventCreate(&e), "hipEventCreate");
   const bool moving = L->mode != MODE_STATIC;
   int done = 0;
+  L->macro_valid = false;
   for (int i = 0; i < nsteps && !rc; ++i) {
     const bool macro = (flags & VPLBM_STEP_MACRO) && i == nsteps - 1;
     rc = L->hip(hipEventRecord(ev[2 * i], L->stream), "hipEventRecord");
     if (!rc) rc = launch_step(L, macro);
     if (!rc) rc = L->hip(hipEventRecord(ev[2 * i + 1], L->stream), "hipEventRecord");
-    if (!rc) rc = launch_finalize(L);
     if (!rc && moving) {
       if (L->shape == SHAPE_DISK) rc = launch_body_step(L);
       if (!rc && L->npts) rc = launch_si_select(L);
+      L->pending = false;
+    } else if (!rc) {
+      L->pending = true;
     }
     if (!rc) {
       L->cur ^= 1;
+      L->nstep += 1;
       ++done;
     }
   }
-  L->nstep += done;
   L->macro_valid = (flags & VPLBM_STEP_MACRO) != 0 && done == nsteps;
   if (!rc) rc = L->sync();
   double total = 0.0;
@@ -816,7 +874,8 @@ int vplbm_step_timed(vplbm_lattice *L, int nsteps, int flags, double *kernel_ms)
 
 int vplbm_sync(vplbm_lattice *L) {
   if (!L) return VPLBM_EINVAL;
-  int rc = L->sync();
+  int rc = flush(L);
+  if (!rc) rc = L->sync();
   if (rc) return rc;
   if (L->npts && L->mode != MODE_STATIC) return check_sample_error(L);
   return VPLBM_OK;
@@ -826,6 +885,10 @@ long long vplbm_step_count(const vplbm_lattice *L) { return L ? L->nstep : -1; }
 
 int vplbm_set_tile(vplbm_lattice *L, int bx, int by) {
   if (!L) return VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   const bool ok = (bx == 64 && (by == 1 || by == 2 || by == 4)) || (bx == 128 && (by == 1 || by == 2)) ||
                   (bx == 256 && by == 1);
   if (!ok) return L->fail(VPLBM_EINVAL, "unsupported tile %dx%d", bx, by);
@@ -836,6 +899,10 @@ int vplbm_set_tile(vplbm_lattice *L, int bx, int by) {
 
 static int read_last(vplbm_lattice *L, int which, double out[3]) {
   if (!L || !out) return VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   if (L->nstep == 0) return L->fail(VPLBM_ESTATE, "no step taken yet");
   Ctl c;
   int rc = L->ctl_pull(c);
@@ -884,6 +951,10 @@ int vplbm_forces_si_at(vplbm_lattice *L, const double *xy, const double *nrm, co
 
 int vplbm_force_history(vplbm_lattice *L, int which, long long first, int n, double *out) {
   if (!L || !out || n < 0) return VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   if (which != VPLBM_FORCE_ME && which != VPLBM_FORCE_SI) return L->fail(VPLBM_EINVAL, "which");
   if (first < 1 || first + n - 1 > L->nstep || first <= L->nstep - L->cap)
     return L->fail(VPLBM_EINVAL, "steps %lld..%lld outside the kept history", first, first + n - 1);
