@@ -31,6 +31,32 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"f64": 9 * 8 * 2 + 1, "f32": 9 * 4 * 2 + 1, "f16dev": 9 * 2 * 2 + 1}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_step_naca0012_2000x1000_f32_hbm_counters.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2110_00967_amd", "csrc", f) for f in ("d2q9.hpp", "step_kernel.hpp")]
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+
+    if not os.path.exists(COUNTERS):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    with open(COUNTERS) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(("#", "|", "`")):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if vals.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(case, budget_s=12.0):
     """The FP64 oracle on the host cores, on a bounded number of steps."""
     import oracle as O
@@ -60,7 +86,10 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="f32", choices=["f32", "f16dev", "f64"])
-    ap.add_argument("--tile", default=None, help="step tile BXxBY (default: library choice)")
+    ap.add_argument("--tile", default=None, help="step workgroup BXxBY: threads (cells) along x times rows")
+    ap.add_argument("--workload", default="naca", choices=["naca", "sediment", "roofline", "disk"],
+                    help="naca: NACA 0012 2000x1000 (default); sediment: free disk 400x2000; "
+                         "roofline: NACA 0012 chord 819 on 8192x8192; disk: 128x64 disk channel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
@@ -77,7 +106,15 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
 
-    case = W.case_naca(chord=200, aoa_deg=10.0)
+    if args.workload == "naca":
+        case = W.case_naca(chord=200, aoa_deg=10.0)
+    elif args.workload == "sediment":
+        case = W.case_sedimentation()
+    elif args.workload == "roofline":
+        case = W.case_naca(chord=819, aoa_deg=10.0)
+        case.nx = case.ny = 8192
+    else:
+        case = W.case_disk_channel()
     cells = case.nx * case.ny
     lat = V.Lattice.from_case(case, precision=args.precision)
     if args.tile:
@@ -97,11 +134,20 @@ def main():
     ms_per_step = ms / args.steps
     mlups = cells / (ms_per_step * 1e-3) / 1e6
 
-    # the step kernel alone: HIP events around each launch on the lattice stream
+    # A static body runs exactly one kernel per step (the fused step kernel;
+    # its forces are summed by the next launch), so the events around the
+    # timed region give that kernel's average duration per launch, launch
+    # gaps included.  A second pass brackets every launch with its own pair
+    # of events (reported for reference; the extra event packets add a few
+    # microseconds per launch).
     kn = min(args.steps, 1000)
-    k_ms = lat.step_timed(kn) / kn
+    k_pairs_us = lat.step_timed(kn) / kn * 1e3
+    # a moving body adds its own kernels to every step: use the per-launch pairs
+    k_us = ms_per_step * 1e3 if case.rho_s is None else k_pairs_us
     bpc = BYTES_PER_CELL[args.precision]
-    achieved = bpc * cells / (k_ms * 1e-3) / 1e9
+    achieved = bpc * cells / (k_us * 1e-6) / 1e9
+    traffic_bytes = measured_traffic() if (args.workload, args.precision) == ("naca", "f32") else None
+    traffic = None if traffic_bytes is None else round(traffic_bytes / (k_us * 1e-6) / 1e9, 1)
     me, si = lat.forces_me(), lat.forces_si()
     q = 0.5 * case.u_ref ** 2 * case.length_scale
     finite = bool(np.isfinite(me).all() and np.isfinite(si).all())
@@ -123,29 +169,35 @@ def main():
                    "storage": args.precision, "si_points": len(case.si_ds), "tau": round(case.tau, 4),
                    "eta": case.eta, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_step", "kernel_us": round(k_ms * 1e3, 3), "bytes_per_cell": bpc},
-        "hbm_roofline_pct_step": round(100.0 * bpc * cells / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_bytes_per_launch": traffic_bytes, "algorithmic_bytes_per_launch": bpc * cells,
+                     "kernel": "k_step", "kernel_us": round(k_us, 3), "kernel_us_event_pairs": round(k_pairs_us, 3),
+                     "bytes_per_cell": bpc, "cells_per_launch": cells},
         "forces": {"CD_ME": me[0] / q, "CL_ME": me[1] / q, "CD_SI": si[0] / q, "CL_SI": si[1] / q,
                    "finite": finite, "steps_run": lat.step_count},
     }
     lat.close()
     if args.copy_calibration:
-        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
-        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        c0.record()
-        for _ in range(5):
-            dst.copy_(src)
-        c1.record()
-        torch.cuda.synchronize()
-        out["copy_calibration"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30, "launches": 5,
-                                   "GBps": round(2 * (1 << 30) * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9, 1)}
-        del src, dst
+        # plain streaming kernels of known size (read n bytes, write n bytes):
+        # reference for the HBM byte counters and a measured copy ceiling
+        cal = {}
+        for nbytes in (1 << 30, 73 << 20):
+            src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            torch.add(src, 1.0, out=dst)
+            torch.cuda.synchronize()
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            c0.record()
+            for _ in range(10):
+                torch.add(src, 1.0, out=dst)
+            c1.record()
+            torch.cuda.synchronize()
+            cal[f"{nbytes >> 20}MiB"] = {"bytes_read": nbytes, "bytes_written": nbytes, "launches": 10,
+                                         "GBps": round(2 * nbytes * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9, 1)}
+            del src, dst
+        out["copy_calibration"] = cal
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W.case_naca(chord=200, aoa_deg=10.0))
+        out["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(out), flush=True)
 
 

@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvplbm.so")
+LIB_PATH = os.environ.get("VPLBM_LIBRARY") or os.path.join(HERE, "libvplbm.so")
 
 F64, F32, F16DEV = 0, 1, 2
 PRECISIONS = {"f64": F64, "f32": F32, "f16dev": F16DEV}
