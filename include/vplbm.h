@@ -75,6 +75,10 @@ typedef struct {
   int hist_capacity; /* length of the device force-history ring in steps; 0 = 4096 */
   int max_si_points; /* capacity for stress-integration points; 0 = 4096 (max 4096) */
   int max_vertices;  /* capacity for polygon vertices; 0 = 4096 */
+  double trt_lambda; /* 0: BGK collision.  > 0: two-relaxation-time collision
+                        (Eq. TRT) with tau+ = tau and tau- = trt_lambda/(tau - 1/2)
+                        + 1/2 (the paper uses 1/6); the forcing term is split the
+                        same way, its odd part weighted by 1 - 1/(2 tau-) */
 } vplbm_params;
 
 /* Rigid-body state in lattice units: reference point (centre of a disk,
@@ -111,6 +115,8 @@ size_t vplbm_required_bytes(const vplbm_params *p);
 int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *hip_stream,
                  vplbm_lattice **out);
 int vplbm_destroy(vplbm_lattice *lat);
+/* Message of the last failed call on the handle; with lat == NULL, the
+ * message of the last failed vplbm_create on the calling thread. */
 const char *vplbm_last_error(const vplbm_lattice *lat);
 
 /* Set the populations to f^eq(rho, u) (second-order equilibrium, Sec. 2.2):
@@ -193,8 +199,14 @@ int vplbm_get_body_state(vplbm_lattice *lat, vplbm_body_state *out);
 /* rho and penalized u of the last step (which must have been run with
  * VPLBM_STEP_MACRO), host arrays [ny][nx]. */
 int vplbm_read_macro(vplbm_lattice *lat, double *rho, double *ux, double *uy);
+/* The same restricted to the window of w columns from x0 and h rows from y0
+ * (host arrays [h][w]); VPLBM_EINVAL if it leaves the lattice. */
+int vplbm_read_macro_window(vplbm_lattice *lat, int x0, int y0, int w, int h, double *rho, double *ux,
+                            double *uy);
 /* Post-collision populations f_a = w_a rho0 + d_a as host doubles [9][ny][nx]. */
 int vplbm_read_populations(vplbm_lattice *lat, double *f);
+/* The same for a window, host array [9][h][w]. */
+int vplbm_read_populations_window(vplbm_lattice *lat, int x0, int y0, int w, int h, double *f);
 /* Mask bytes [ny][nx]: bit 0 solid, bit 6 stress-integration sample node,
  * bit 7 interface cell (a neighbour has the other phase). */
 int vplbm_read_mask(vplbm_lattice *lat, uint8_t *out);

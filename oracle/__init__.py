@@ -34,7 +34,7 @@ W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 class _Params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("tau", C.c_double), ("eta", C.c_double),
                 ("rho0", C.c_double), ("edge_kind", C.c_int * 4), ("edge_u", (C.c_double * 2) * 4),
-                ("gx", C.c_double), ("gy", C.c_double)]
+                ("gx", C.c_double), ("gy", C.c_double), ("trt_lambda", C.c_double)]
 
 
 class _Body(C.Structure):
@@ -124,7 +124,7 @@ class RefLattice:
     """Oracle lattice: f stored as ft[y, x, a] (post-collision), float64."""
 
     def __init__(self, nx, ny, tau, eta, rho0=1.0, west=(PERIODIC, 0.0, 0.0), east=(PERIODIC, 0.0, 0.0),
-                 south=(PERIODIC, 0.0, 0.0), north=(PERIODIC, 0.0, 0.0), gx=0.0, gy=0.0):
+                 south=(PERIODIC, 0.0, 0.0), north=(PERIODIC, 0.0, 0.0), gx=0.0, gy=0.0, trt_lambda=0.0):
         self.p = _Params()
         self.p.nx, self.p.ny, self.p.tau, self.p.eta, self.p.rho0 = nx, ny, tau, eta, rho0
         for i, e in enumerate((west, east, south, north)):
@@ -132,6 +132,7 @@ class RefLattice:
             self.p.edge_u[i][0] = float(e[1])
             self.p.edge_u[i][1] = float(e[2])
         self.p.gx, self.p.gy = gx, gy
+        self.p.trt_lambda = trt_lambda
         self.nx, self.ny = nx, ny
         self.ft = np.zeros((ny, nx, 9))
         self.fw = np.zeros((ny, nx, 9))
@@ -154,7 +155,7 @@ class RefLattice:
     def from_case(cls, case):
         e = lambda E: (E.kind, E.ux, E.uy)
         lat = cls(case.nx, case.ny, case.tau, case.eta, case.rho0, e(case.west), e(case.east),
-                  e(case.south), e(case.north), case.gx, case.gy)
+                  e(case.south), e(case.north), case.gx, case.gy, case.trt_lambda)
         if case.disk is not None:
             lat.set_disk(*case.disk)
         elif case.polygon is not None:

@@ -47,6 +47,8 @@ typedef struct {
   int edge_kind[4];      /* west, east, south, north */
   double edge_u[4][2];   /* wall / inflow velocity of VELOCITY edges */
   double gx, gy;         /* uniform external force density (tests) */
+  double trt_lambda;     /* > 0: two-relaxation-time collision with this magic
+                            parameter (Eq. TRT); <= 0: BGK */
 } orc_params;
 
 typedef struct {
@@ -352,6 +354,8 @@ int orc_step(const orc_params *p, const double *ft_prev, double *f_work, double 
       si[0] = si[1] = si[2] = 0.0;
   }
   double fac = 1.0 - 1.0 / (2.0 * p->tau);
+  /* TRT (Eq. TRT): tau+ = tau sets the viscosity, tau- = Lambda/(tau+ - 1/2) + 1/2 */
+  double tau_m = p->trt_lambda > 0.0 ? p->trt_lambda / (p->tau - 0.5) + 0.5 : p->tau;
 #pragma omp parallel for schedule(static) if ((long)nx * ny >= 65536)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
@@ -364,8 +368,23 @@ int orc_step(const orc_params *p, const double *ft_prev, double *f_work, double 
       orc_cell_macro(p, f, chi, usx, usy, &rho, &ux, &uy, &Fx, &Fy);
       orc_equilibrium(rho, ux, uy, feq);
       orc_forcing(ux, uy, Fx, Fy, Fa);
-      for (int a = 0; a < Q; ++a) /* BGK collision with forcing, Eq. eqBd */
-        ft_next[c * Q + a] = f[a] - (f[a] - feq[a]) / p->tau + fac * Fa[a];
+      if (p->trt_lambda > 0.0) {
+        /* symmetric / antisymmetric parts relax with tau+ / tau-.  The
+         * forcing term is split the same way, its odd part carrying
+         * (1 - 1/(2 tau-)): only then is the momentum put in per step exactly
+         * F, as the half-force shift of Eq. updatestep presumes (for tau- =
+         * tau+ this is the printed (1 - 1/(2 tau+)) F_alpha). */
+        double fac_m = 1.0 - 1.0 / (2.0 * tau_m);
+        for (int a = 0; a < Q; ++a) {
+          double fp = 0.5 * (f[a] + f[OPP[a]]), fm = 0.5 * (f[a] - f[OPP[a]]);
+          double ep = 0.5 * (feq[a] + feq[OPP[a]]), em = 0.5 * (feq[a] - feq[OPP[a]]);
+          double Fp = 0.5 * (Fa[a] + Fa[OPP[a]]), Fm = 0.5 * (Fa[a] - Fa[OPP[a]]);
+          ft_next[c * Q + a] = f[a] - (fp - ep) / p->tau - (fm - em) / tau_m + fac * Fp + fac_m * Fm;
+        }
+      } else {
+        for (int a = 0; a < Q; ++a) /* BGK collision with forcing, Eq. eqBd */
+          ft_next[c * Q + a] = f[a] - (f[a] - feq[a]) / p->tau + fac * Fa[a];
+      }
       if (rho_out) rho_out[c] = rho;
       if (ux_out) ux_out[c] = ux;
       if (uy_out) uy_out[c] = uy;

@@ -47,28 +47,29 @@ __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int 
   }
 }
 
-// populations f_a = w_a rho0 + d_a of rows [row0, row0 + nrows) -> out[9][nrows][nx]
+// populations f_a = w_a rho0 + d_a of the window columns [x0, x0 + w), rows
+// [row0, row0 + nrows) -> out[9][nrows][w]
 template <typename S>
-__global__ void k_read_pop(const S *__restrict__ f, int nx, int pitch, long long plane, int row0,
+__global__ void k_read_pop(const S *__restrict__ f, int x0, int w, int pitch, long long plane, int row0,
                            int nrows, double rho0, double *__restrict__ out) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int xl = blockIdx.x * blockDim.x + threadIdx.x;
   const int yl = blockIdx.y;
-  if (x >= nx || yl >= nrows) return;
-  const long long c = (long long)(row0 + yl) * pitch + x;
+  if (xl >= w || yl >= nrows) return;
+  const long long c = (long long)(row0 + yl) * pitch + x0 + xl;
 #pragma unroll
   for (int a = 0; a < Q; ++a)
-    out[((long long)a * nrows + yl) * nx + x] = wgt(a) * rho0 + double(Store<S>::ld(f + a * plane + c));
+    out[((long long)a * nrows + yl) * w + xl] = wgt(a) * rho0 + double(Store<S>::ld(f + a * plane + c));
 }
 
 template <typename T>
 __global__ void k_read_macro(const T *__restrict__ r, const T *__restrict__ u, const T *__restrict__ v,
-                             int nx, int pitch, int row0, int nrows, double *__restrict__ out) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+                             int x0, int w, int pitch, int row0, int nrows, double *__restrict__ out) {
+  const int xl = blockIdx.x * blockDim.x + threadIdx.x;
   const int yl = blockIdx.y;
-  if (x >= nx || yl >= nrows) return;
-  const long long c = (long long)(row0 + yl) * pitch + x;
-  const long long o = (long long)yl * nx + x;
-  const long long n = (long long)nrows * nx;
+  if (xl >= w || yl >= nrows) return;
+  const long long c = (long long)(row0 + yl) * pitch + x0 + xl;
+  const long long o = (long long)yl * w + xl;
+  const long long n = (long long)nrows * w;
   out[o] = double(r[c]);
   out[n + o] = double(u[c]);
   out[2 * n + o] = double(v[c]);
@@ -151,6 +152,202 @@ __global__ void k_mask_flags(uint8_t *__restrict__ mask, int nx, int ny, int pit
 }
 
 // ----------------------------------------------------------------------------
+// stress-integration sample nodes and aggregated weights (one workgroup)
+// ----------------------------------------------------------------------------
+constexpr int SI_NT = 1024;
+constexpr int SI_MAX = 4096;
+
+// Sample node of a point: the lattice direction beta maximizing
+// (c_beta . n)/|c_beta| (first on ties), then the first fluid node inside the
+// lattice among r_0 + k c_beta, k = 0..4, r_0 the node nearest to the point.
+__device__ __forceinline__ int si_node(const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
+                                       double px, double py, double n0, double n1) {
+  const double S = 0.70710678118654752440;
+  double sc[Q];
+  sc[1] = n0;
+  sc[2] = n1;
+  sc[3] = -n0;
+  sc[4] = -n1;
+  sc[5] = (n0 + n1) * S;
+  sc[6] = (-n0 + n1) * S;
+  sc[7] = (-n0 - n1) * S;
+  sc[8] = (n0 - n1) * S;
+  int best = 1;
+#pragma unroll
+  for (int a = 2; a < Q; ++a)
+    if (sc[a] > sc[best]) best = a;
+  int bx = 0, by = 0;
+#pragma unroll
+  for (int a = 1; a < Q; ++a)
+    if (a == best) { bx = cx(a); by = cy(a); }
+  const int ix = (int)floor(px + 0.5), iy = (int)floor(py + 0.5);
+  for (int k = 0; k <= 4; ++k) {
+    const int X = ix + k * bx, Y = iy + k * by;
+    if (X < 0 || X >= nx || Y < 0 || Y >= ny) continue;
+    if (!(mask[(long long)Y * pitch + X] & M_SOLID)) return Y * nx + X;
+  }
+  return -1;
+}
+
+// world position and normal of point i (points of a moving body are kept in
+// the body frame and placed with the current state)
+__device__ __forceinline__ void si_world(const double *__restrict__ pts, int maxp, int i, int moving,
+                                         const BodyDev &B, double &px, double &py, double &n0,
+                                         double &n1) {
+  const double a = pts[i], b = pts[maxp + i], c = pts[2 * maxp + i], d = pts[3 * maxp + i];
+  if (!moving) {
+    px = a; py = b; n0 = c; n1 = d;
+    return;
+  }
+  const double co = cos(B.theta), sn = sin(B.theta);
+  px = B.x + (co * a - sn * b);
+  py = B.y + (sn * a + co * b);
+  n0 = co * c - sn * d;
+  n1 = sn * c + co * d;
+}
+
+// exclusive prefix sum over the SI_NT threads of the block; *total gets the sum
+__device__ __forceinline__ int block_exclusive_scan(int v, int *wsum /*[SI_NT/64]*/, int *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += u;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < SI_NT / 64; ++w) {
+      const int t = wsum[w];
+      wsum[w] = run;
+      run += t;
+    }
+    *total = run;
+  }
+  __syncthreads();
+  return wsum[wave] + incl - v;
+}
+
+// Sample nodes and per-node weights of all registered points (one workgroup
+// of SI_NT threads; called by k_si_select and, for a moving disk, at the end
+// of k_body_step after the mask was rebuilt).
+__device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
+                                const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
+                                int *__restrict__ si_map, int nx, int ny, int pitch) {
+  __shared__ unsigned long long key[SI_MAX];
+  __shared__ int wsum[SI_NT / 64];
+  __shared__ int nrec_total;
+  __shared__ int bb[4];
+  __shared__ int missing;
+  const int npts = ctl->npts;
+  const int moving = ctl->si_moving;
+  const BodyDev B = ctl->body;
+  int N = 2;
+  while (N < npts) N <<= 1;
+  if (threadIdx.x == 0) {
+    bb[0] = nx; bb[1] = ny; bb[2] = -1; bb[3] = -1;
+    missing = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += SI_NT) {
+    unsigned long long k = ~0ull;
+    if (i < npts) {
+      double px, py, n0, n1;
+      si_world(pts, maxp, i, moving, B, px, py, n0, n1);
+      const int node = si_node(mask, nx, ny, pitch, px, py, n0, n1);
+      if (node >= 0) {
+        k = ((unsigned long long)(unsigned)node << 32) | (unsigned)i;
+        const int X = node % nx, Y = node / nx;
+        atomicMin(&bb[0], X);
+        atomicMin(&bb[1], Y);
+        atomicMax(&bb[2], X);
+        atomicMax(&bb[3], Y);
+      } else {
+        atomicAdd(&missing, 1);
+        k = (0xFFFFFFFFull << 32) | (unsigned)i;
+      }
+    }
+    key[i] = k;
+  }
+  __syncthreads();
+  // bitonic sort of (node, point) keys
+  for (int size = 2; size <= N; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < N / 2; t += SI_NT) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const unsigned long long a = key[lo], b = key[hi];
+        if ((a > b) == up) {
+          key[lo] = b;
+          key[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // segment heads -> record indices (each thread owns a contiguous chunk)
+  const int per = (N + SI_NT - 1) / SI_NT;
+  const int j0 = threadIdx.x * per, j1 = min(j0 + per, N);
+  int cnt = 0;
+  for (int j = j0; j < j1; ++j) {
+    const unsigned node = (unsigned)(key[j] >> 32);
+    if (node != 0xFFFFFFFFu && (j == 0 || (unsigned)(key[j - 1] >> 32) != node)) ++cnt;
+  }
+  int r = block_exclusive_scan(cnt, wsum, &nrec_total);
+  for (int j = j0; j < j1; ++j) {
+    const unsigned node = (unsigned)(key[j] >> 32);
+    if (node == 0xFFFFFFFFu || (j > 0 && (unsigned)(key[j - 1] >> 32) == node)) continue;
+    double ax = 0.0, ay = 0.0, txx = 0.0, txy = 0.0, tyy = 0.0;
+    for (int k = j; k < N && (unsigned)(key[k] >> 32) == node; ++k) {
+      const int i = (int)(key[k] & 0xFFFFFFFFu);
+      double px, py, n0, n1;
+      si_world(pts, maxp, i, moving, B, px, py, n0, n1);
+      const double s = pts[4 * maxp + i];
+      const double rx = px - B.x, ry = py - B.y;
+      ax += s * n0;
+      ay += s * n1;
+      txx += s * (-ry * n0);
+      txy += s * (rx * n0 - ry * n1);
+      tyy += s * (rx * n1);
+    }
+    SiRec R;
+    R.cell = (int)node;
+    R.pad = 0;
+    R.ax = ax; R.ay = ay; R.txx = txx; R.txy = txy; R.tyy = tyy;
+    recs[r] = R;
+    const int X = (int)node % nx, Y = (int)node / nx;
+    si_map[(long long)Y * pitch + X] = r;
+    mask[(long long)Y * pitch + X] |= M_SAMPLE;
+    ++r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ctl->nrec = nrec_total;
+    if (missing) ctl->err |= 1;
+    if (bb[2] >= 0) {
+      if (ctl->win[2] <= ctl->win[0] || ctl->win[3] <= ctl->win[1]) {
+        ctl->win[0] = bb[0]; ctl->win[1] = bb[1]; ctl->win[2] = bb[2] + 1; ctl->win[3] = bb[3] + 1;
+      } else {
+        ctl->win[0] = min(ctl->win[0], bb[0]);
+        ctl->win[1] = min(ctl->win[1], bb[1]);
+        ctl->win[2] = max(ctl->win[2], bb[2] + 1);
+        ctl->win[3] = max(ctl->win[3], bb[3] + 1);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(SI_NT)
+    k_si_select(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ pts,
+                int maxp, SiRec *__restrict__ recs, int *__restrict__ si_map, int nx, int ny,
+                int pitch) {
+  si_select_block(mask, ctl, pts, maxp, recs, si_map, nx, ny, pitch);
+}
+
+// ----------------------------------------------------------------------------
 // moving disk: rigid-body update, then rebuild chi and flags over the union of
 // the old and new regions (one workgroup)
 // ----------------------------------------------------------------------------
@@ -160,7 +357,8 @@ constexpr int REGION_MARGIN = 6;  // covers links (1) and sample walks (5)
 __global__ void __launch_bounds__(BODY_NT)
     k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ part,
                 double *__restrict__ hist, int cap, int BX, int BY, int nx, int ny, int pitch, int perx,
-                int pery) {
+                int pery, const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
+                int *__restrict__ si_map) {
   __shared__ int reg[4];   // union region to rewrite
   __shared__ long long q[3];
   __shared__ double lds[(BODY_NT / 64) * 6];
@@ -236,174 +434,11 @@ __global__ void __launch_bounds__(BODY_NT)
     }
     mask[(long long)j * pitch + i] = (own ? M_SOLID : 0) | (iface ? M_IFACE : 0);
   }
-}
-
-// ----------------------------------------------------------------------------
-// stress-integration sample nodes and aggregated weights (one workgroup)
-// ----------------------------------------------------------------------------
-constexpr int SI_NT = 1024;
-constexpr int SI_MAX = 4096;
-
-// Sample node of a point: the lattice direction beta maximizing
-// (c_beta . n)/|c_beta| (first on ties), then the first fluid node inside the
-// lattice among r_0 + k c_beta, k = 0..4, r_0 the node nearest to the point.
-__device__ __forceinline__ int si_node(const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
-                                       double px, double py, double n0, double n1) {
-  const double S = 0.70710678118654752440;
-  double sc[Q];
-  sc[1] = n0;
-  sc[2] = n1;
-  sc[3] = -n0;
-  sc[4] = -n1;
-  sc[5] = (n0 + n1) * S;
-  sc[6] = (-n0 + n1) * S;
-  sc[7] = (-n0 - n1) * S;
-  sc[8] = (n0 - n1) * S;
-  int best = 1;
-#pragma unroll
-  for (int a = 2; a < Q; ++a)
-    if (sc[a] > sc[best]) best = a;
-  int bx = 0, by = 0;
-#pragma unroll
-  for (int a = 1; a < Q; ++a)
-    if (a == best) { bx = cx(a); by = cy(a); }
-  const int ix = (int)floor(px + 0.5), iy = (int)floor(py + 0.5);
-  for (int k = 0; k <= 4; ++k) {
-    const int X = ix + k * bx, Y = iy + k * by;
-    if (X < 0 || X >= nx || Y < 0 || Y >= ny) continue;
-    if (!(mask[(long long)Y * pitch + X] & M_SOLID)) return Y * nx + X;
-  }
-  return -1;
-}
-
-// world position and normal of point i (points of a moving body are kept in
-// the body frame and placed with the current state)
-__device__ __forceinline__ void si_world(const double *__restrict__ pts, int maxp, int i, int moving,
-                                         const BodyDev &B, double &px, double &py, double &n0,
-                                         double &n1) {
-  const double a = pts[i], b = pts[maxp + i], c = pts[2 * maxp + i], d = pts[3 * maxp + i];
-  if (!moving) {
-    px = a; py = b; n0 = c; n1 = d;
-    return;
-  }
-  const double co = cos(B.theta), sn = sin(B.theta);
-  px = B.x + (co * a - sn * b);
-  py = B.y + (sn * a + co * b);
-  n0 = co * c - sn * d;
-  n1 = sn * c + co * d;
-}
-
-__global__ void __launch_bounds__(SI_NT)
-    k_si_select(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ pts,
-                int maxp, SiRec *__restrict__ recs, int *__restrict__ si_map, int nx, int ny,
-                int pitch) {
-  __shared__ unsigned long long key[SI_MAX];
-  __shared__ int scan[SI_NT + 1];
-  __shared__ int bb[4];
-  __shared__ int missing;
-  const int npts = ctl->npts;
-  const int moving = ctl->si_moving;
-  const BodyDev B = ctl->body;
-  int N = 2;
-  while (N < npts) N <<= 1;
-  if (threadIdx.x == 0) {
-    bb[0] = nx; bb[1] = ny; bb[2] = -1; bb[3] = -1;
-    missing = 0;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < N; i += SI_NT) {
-    unsigned long long k = ~0ull;
-    if (i < npts) {
-      double px, py, n0, n1;
-      si_world(pts, maxp, i, moving, B, px, py, n0, n1);
-      const int node = si_node(mask, nx, ny, pitch, px, py, n0, n1);
-      if (node >= 0) {
-        k = ((unsigned long long)(unsigned)node << 32) | (unsigned)i;
-        const int X = node % nx, Y = node / nx;
-        atomicMin(&bb[0], X);
-        atomicMin(&bb[1], Y);
-        atomicMax(&bb[2], X);
-        atomicMax(&bb[3], Y);
-      } else {
-        atomicAdd(&missing, 1);
-        k = (0xFFFFFFFFull << 32) | (unsigned)i;
-      }
-    }
-    key[i] = k;
-  }
-  __syncthreads();
-  // bitonic sort of (node, point) keys
-  for (int size = 2; size <= N; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = threadIdx.x; t < N / 2; t += SI_NT) {
-        const int lo = 2 * t - (t & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const unsigned long long a = key[lo], b = key[hi];
-        if ((a > b) == up) {
-          key[lo] = b;
-          key[hi] = a;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  // segment heads -> record indices (each thread owns a contiguous chunk)
-  const int per = (N + SI_NT - 1) / SI_NT;
-  const int j0 = threadIdx.x * per, j1 = min(j0 + per, N);
-  int cnt = 0;
-  for (int j = j0; j < j1; ++j) {
-    const unsigned node = (unsigned)(key[j] >> 32);
-    if (node != 0xFFFFFFFFu && (j == 0 || (unsigned)(key[j - 1] >> 32) != node)) ++cnt;
-  }
-  scan[threadIdx.x + 1] = cnt;
-  if (threadIdx.x == 0) scan[0] = 0;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int t = 1; t <= SI_NT; ++t) scan[t] += scan[t - 1];
-  }
-  __syncthreads();
-  int r = scan[threadIdx.x];
-  for (int j = j0; j < j1; ++j) {
-    const unsigned node = (unsigned)(key[j] >> 32);
-    if (node == 0xFFFFFFFFu || (j > 0 && (unsigned)(key[j - 1] >> 32) == node)) continue;
-    double ax = 0.0, ay = 0.0, txx = 0.0, txy = 0.0, tyy = 0.0;
-    for (int k = j; k < N && (unsigned)(key[k] >> 32) == node; ++k) {
-      const int i = (int)(key[k] & 0xFFFFFFFFu);
-      double px, py, n0, n1;
-      si_world(pts, maxp, i, moving, B, px, py, n0, n1);
-      const double s = pts[4 * maxp + i];
-      const double rx = px - B.x, ry = py - B.y;
-      ax += s * n0;
-      ay += s * n1;
-      txx += s * (-ry * n0);
-      txy += s * (rx * n0 - ry * n1);
-      tyy += s * (rx * n1);
-    }
-    SiRec R;
-    R.cell = (int)node;
-    R.pad = 0;
-    R.ax = ax; R.ay = ay; R.txx = txx; R.txy = txy; R.tyy = tyy;
-    recs[r] = R;
-    const int X = (int)node % nx, Y = (int)node / nx;
-    si_map[(long long)Y * pitch + X] = r;
-    mask[(long long)Y * pitch + X] |= M_SAMPLE;
-    ++r;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    ctl->nrec = scan[SI_NT];
-    if (missing) ctl->err |= 1;
-    if (bb[2] >= 0) {
-      if (ctl->win[2] <= ctl->win[0] || ctl->win[3] <= ctl->win[1]) {
-        ctl->win[0] = bb[0]; ctl->win[1] = bb[1]; ctl->win[2] = bb[2] + 1; ctl->win[3] = bb[3] + 1;
-      } else {
-        ctl->win[0] = min(ctl->win[0], bb[0]);
-        ctl->win[1] = min(ctl->win[1], bb[1]);
-        ctl->win[2] = max(ctl->win[2], bb[2] + 1);
-        ctl->win[3] = max(ctl->win[3], bb[3] + 1);
-      }
-    }
+  if (ctl->npts > 0) {
+    // the rebuilt mask must be visible to every thread of the block
+    __threadfence_block();
+    __syncthreads();
+    si_select_block(mask, ctl, pts, maxp, recs, si_map, nx, ny, pitch);
   }
 }
 

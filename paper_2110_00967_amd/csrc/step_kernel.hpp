@@ -36,6 +36,8 @@ template <typename T> struct StepArgs {
   int kind[4];          // edge kinds W, E, S, N
   T bb[4][Q];           // velocity bounce-back increment 6 w_a rho0 (c_a . u_w) per edge
   T omega, fac, kpen, rho0, gx, gy;
+  int trt;              // 0: BGK; 1: TRT with omega_m = 1/tau-, fac_m = 1 - 1/(2 tau-)
+  T omega_m, fac_m;
   double facd, rho0d;
 };
 
@@ -187,15 +189,39 @@ __global__ void __launch_bounds__(BX *BY)
     const T uu15 = T(1.5) * (ux * ux + uy * uy);
     const T uF3 = T(3) * (ux * Fx + uy * Fy);
     T deq[Q];
+    if (!P.trt) {
+      // BGK
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      const T w = T(wgt(a));
-      const T cu = T(cx(a)) * ux + T(cy(a)) * uy;
-      const T cF = T(cx(a)) * Fx + T(cy(a)) * Fy;
-      deq[a] = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - uu15);
-      const T Fa = w * (T(3) * cF - uF3 + T(9) * cu * cF);
-      const T out = d[a] - P.omega * (d[a] - deq[a]) + P.fac * Fa;
-      Store<S>::st(fout + a * P.plane + c, out);
+      for (int a = 0; a < Q; ++a) {
+        const T w = T(wgt(a));
+        const T cu = T(cx(a)) * ux + T(cy(a)) * uy;
+        const T cF = T(cx(a)) * Fx + T(cy(a)) * Fy;
+        deq[a] = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - uu15);
+        const T Fa = w * (T(3) * cF - uF3 + T(9) * cu * cF);
+        const T out = d[a] - P.omega * (d[a] - deq[a]) + P.fac * Fa;
+        Store<S>::st(fout + a * P.plane + c, out);
+      }
+    } else {
+      // TRT (Eq. TRT): even / odd parts of the non-equilibrium and of the
+      // forcing term relax with tau+ / tau-
+      T Fa[Q];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const T w = T(wgt(a));
+        const T cu = T(cx(a)) * ux + T(cy(a)) * uy;
+        const T cF = T(cx(a)) * Fx + T(cy(a)) * Fy;
+        deq[a] = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - uu15);
+        Fa[a] = w * (T(3) * cF - uF3 + T(9) * cu * cF);
+      }
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        const int o = opp(a);
+        const T nep = T(0.5) * ((d[a] - deq[a]) + (d[o] - deq[o]));
+        const T nem = T(0.5) * ((d[a] - deq[a]) - (d[o] - deq[o]));
+        const T out = d[a] - P.omega * nep - P.omega_m * nem + P.fac * (T(0.5) * (Fa[a] + Fa[o])) +
+                      P.fac_m * (T(0.5) * (Fa[a] - Fa[o]));
+        Store<S>::st(fout + a * P.plane + c, out);
+      }
     }
     if (MACRO) {
       mrho[c] = rho;

@@ -28,6 +28,14 @@
 
 using namespace vp;
 
+// launch a kernel after dropping any error an unrelated HIP call left pending,
+// so that the check right after the launch reports this launch only
+#define VP_LAUNCH(...)           \
+  do {                           \
+    (void)hipGetLastError();     \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+  } while (0)
+
 namespace {
 
 constexpr size_t ALIGN = 256;
@@ -107,6 +115,7 @@ const char *check_params(const vplbm_params *p) {
     return "west and east must both be periodic or both not";
   if ((p->south.kind == VPLBM_BC_PERIODIC) != (p->north.kind == VPLBM_BC_PERIODIC))
     return "south and north must both be periodic or both not";
+  if (!(p->trt_lambda >= 0.0) || !std::isfinite(p->trt_lambda)) return "trt_lambda must be finite and >= 0";
   if (p->hist_capacity < 0 || p->max_si_points < 0 || p->max_vertices < 0)
     return "capacities must be >= 0";
   if (p->max_si_points > SI_MAX) return "max_si_points exceeds 4096";
@@ -161,6 +170,8 @@ struct vplbm_lattice {
     return fail(VPLBM_EHIP, "%s: %s", what, hipGetErrorString(e));
   }
   int launched(const char *what) { return hip(hipGetLastError(), what); }
+  // drop an error left pending by an unrelated HIP call before our own work
+  void clear_stale() { (void)hipGetLastError(); }
   int sync() { return hip(hipStreamSynchronize(stream), "hipStreamSynchronize"); }
 
   int ctl_pull(Ctl &c) {
@@ -197,6 +208,10 @@ struct vplbm_lattice {
     a.fac = T(1.0 - 0.5 / p.tau);
     a.facd = 1.0 - 0.5 / p.tau;
     a.kpen = std::isinf(p.eta) ? T(0) : T(1.0 / p.eta);
+    a.trt = p.trt_lambda > 0.0 ? 1 : 0;
+    const double tau_m = p.trt_lambda > 0.0 ? p.trt_lambda / (p.tau - 0.5) + 0.5 : p.tau;
+    a.omega_m = T(1.0 / tau_m);
+    a.fac_m = T(1.0 - 0.5 / tau_m);
     a.rho0 = T(p.rho0);
     a.rho0d = p.rho0;
     a.gx = T(gx);
@@ -226,10 +241,10 @@ int launch_step_t(vplbm_lattice *L, bool macro) {
   const int fin_prev = L->pending ? 1 : 0;
   double *hist = (double *)L->at(L->L.hist);
   if (macro)
-    hipLaunchKernelGGL((k_step<S, BX, BY, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
+    VP_LAUNCH((k_step<S, BX, BY, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
                        L->mask(), a, L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
   else
-    hipLaunchKernelGGL((k_step<S, BX, BY, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
+    VP_LAUNCH((k_step<S, BX, BY, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
                        L->mask(), a, L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
   return L->launched("k_step");
 }
@@ -256,7 +271,7 @@ template <typename S>
 int launch_init_s(vplbm_lattice *L, int row0, int nrows, const double *r, const double *u,
                   const double *v, double ru, double uu, double vu) {
   dim3 blk(256), grd((L->p.nx + 255) / 256, nrows);
-  hipLaunchKernelGGL((k_init<S>), grd, blk, 0, L->stream, (S *)L->A(), L->mask(), L->p.nx, L->p.ny,
+  VP_LAUNCH((k_init<S>), grd, blk, 0, L->stream, (S *)L->A(), L->mask(), L->p.nx, L->p.ny,
                      L->pitch, L->plane, row0, nrows, r, u, v, ru, uu, vu, L->ctl(), L->p.rho0);
   return L->launched("k_init");
 }
@@ -270,25 +285,26 @@ int launch_init(vplbm_lattice *L, int row0, int nrows, const double *r, const do
   }
 }
 
-template <typename S> int launch_read_pop_s(vplbm_lattice *L, int row0, int nrows, double *out) {
-  dim3 blk(256), grd((L->p.nx + 255) / 256, nrows);
-  hipLaunchKernelGGL((k_read_pop<S>), grd, blk, 0, L->stream, (const S *)L->A(), L->p.nx, L->pitch,
-                     L->plane, row0, nrows, L->p.rho0, out);
+template <typename S>
+int launch_read_pop_s(vplbm_lattice *L, int x0, int w, int row0, int nrows, double *out) {
+  dim3 blk(256), grd((w + 255) / 256, nrows);
+  VP_LAUNCH((k_read_pop<S>), grd, blk, 0, L->stream, (const S *)L->A(), x0, w, L->pitch, L->plane,
+                     row0, nrows, L->p.rho0, out);
   return L->launched("k_read_pop");
 }
 
-int launch_read_pop(vplbm_lattice *L, int row0, int nrows, double *out) {
+int launch_read_pop(vplbm_lattice *L, int x0, int w, int row0, int nrows, double *out) {
   switch (L->p.precision) {
-    case VPLBM_F64: return launch_read_pop_s<double>(L, row0, nrows, out);
-    case VPLBM_F32: return launch_read_pop_s<float>(L, row0, nrows, out);
-    default: return launch_read_pop_s<__half>(L, row0, nrows, out);
+    case VPLBM_F64: return launch_read_pop_s<double>(L, x0, w, row0, nrows, out);
+    case VPLBM_F32: return launch_read_pop_s<float>(L, x0, w, row0, nrows, out);
+    default: return launch_read_pop_s<__half>(L, x0, w, row0, nrows, out);
   }
 }
 
 template <typename S> int launch_si_at_s(vplbm_lattice *L, int npts, double *out) {
   using T = typename Store<S>::T;
   const StepArgs<T> a = L->step_args<T>();
-  hipLaunchKernelGGL((k_si_at<S>), dim3(1), dim3(SI_NT), 0, L->stream, (const S *)L->A(), L->mask(),
+  VP_LAUNCH((k_si_at<S>), dim3(1), dim3(SI_NT), 0, L->stream, (const S *)L->A(), L->mask(),
                      a, L->ctl(), (const double *)L->at(L->L.staging), L->maxp, npts, out);
   return L->launched("k_si_at");
 }
@@ -296,13 +312,13 @@ template <typename S> int launch_si_at_s(vplbm_lattice *L, int npts, double *out
 int launch_flags(vplbm_lattice *L, int x0, int y0, int x1, int y1) {
   if (x1 <= x0 || y1 <= y0) return VPLBM_OK;
   dim3 blk(256), grd((x1 - x0 + 255) / 256, y1 - y0);
-  hipLaunchKernelGGL(k_mask_flags, grd, blk, 0, L->stream, L->mask(), L->p.nx, L->p.ny, L->pitch, x0,
+  VP_LAUNCH(k_mask_flags, grd, blk, 0, L->stream, L->mask(), L->p.nx, L->p.ny, L->pitch, x0,
                      y0, x1, y1, (int)L->periodic_x(), (int)L->periodic_y());
   return L->launched("k_mask_flags");
 }
 
 int launch_si_select(vplbm_lattice *L) {
-  hipLaunchKernelGGL(k_si_select, dim3(1), dim3(SI_NT), 0, L->stream, L->mask(), L->ctl(),
+  VP_LAUNCH(k_si_select, dim3(1), dim3(SI_NT), 0, L->stream, L->mask(), L->ctl(),
                      (const double *)L->at(L->L.pts), L->maxp, (SiRec *)L->at(L->L.recs),
                      (int *)L->at(L->L.si_map), L->p.nx, L->p.ny, L->pitch);
   return L->launched("k_si_select");
@@ -311,16 +327,18 @@ int launch_si_select(vplbm_lattice *L) {
 // after the step kernel of step n (= nstep + 1): finalize its forces, move the
 // body, rebuild the mask
 int launch_body_step(vplbm_lattice *L) {
-  hipLaunchKernelGGL(k_body_step, dim3(1), dim3(BODY_NT), 0, L->stream, L->mask(), L->ctl(),
+  VP_LAUNCH(k_body_step, dim3(1), dim3(BODY_NT), 0, L->stream, L->mask(), L->ctl(),
                      (const double *)L->part(L->nstep + 1), (double *)L->at(L->L.hist), L->cap, L->bx, L->by,
-                     L->p.nx, L->p.ny, L->pitch, (int)L->periodic_x(), (int)L->periodic_y());
+                     L->p.nx, L->p.ny, L->pitch, (int)L->periodic_x(), (int)L->periodic_y(),
+                     (const double *)L->at(L->L.pts), L->maxp, (SiRec *)L->at(L->L.recs),
+                     (int *)L->at(L->L.si_map));
   return L->launched("k_body_step");
 }
 
 // sum the partials of the last step into the history (forces readable)
 int flush(vplbm_lattice *L) {
   if (!L->pending) return VPLBM_OK;
-  hipLaunchKernelGGL((k_finalize<256>), dim3(1), dim3(256), 0, L->stream, (const double *)L->part(L->nstep),
+  VP_LAUNCH((k_finalize<256>), dim3(1), dim3(256), 0, L->stream, (const double *)L->part(L->nstep),
                      L->ctl(), (double *)L->at(L->L.hist), L->cap, L->bx, L->by);
   int rc = L->launched("k_finalize");
   if (!rc) L->pending = false;
@@ -334,8 +352,7 @@ int one_step(vplbm_lattice *L, bool macro) {
   int rc = launch_step(L, macro);
   if (rc) return rc;
   if (L->mode != MODE_STATIC) {  // only disks move
-    rc = launch_body_step(L);
-    if (!rc && L->npts) rc = launch_si_select(L);
+    rc = launch_body_step(L);  // also reselects the sample nodes
     if (rc) return rc;
     L->pending = false;
   } else {
@@ -423,11 +440,21 @@ size_t vplbm_required_bytes(const vplbm_params *p) {
   return layout_of(*p).total;
 }
 
+// message of the last failed vplbm_create on this thread (no handle exists)
+static thread_local std::string g_create_err;
+
 int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *hip_stream,
                  vplbm_lattice **out) {
+  g_create_err.clear();
   if (!out) return VPLBM_EINVAL;
   *out = nullptr;
-  if (check_params(p)) return VPLBM_EINVAL;
+  if (const char *why = check_params(p)) {
+    g_create_err = why;
+    return VPLBM_EINVAL;
+  }
+  // an error left pending by an earlier, unrelated HIP call must not be
+  // reported as ours
+  (void)hipGetLastError();
   auto *L = new (std::nothrow) vplbm_lattice();
   if (!L) return VPLBM_ENOMEM;
   L->p = *p;
@@ -440,6 +467,7 @@ int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *h
   L->maxv = p->max_vertices > 0 ? p->max_vertices : DEFAULT_VERTS;
   if (dev_mem) {
     if (dev_bytes < L->L.total || ((uintptr_t)dev_mem % ALIGN) != 0) {
+      g_create_err = "device buffer smaller than vplbm_required_bytes or not 256-byte aligned";
       delete L;
       return VPLBM_ENOMEM;
     }
@@ -447,6 +475,7 @@ int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *h
   } else {
     if (hipMalloc((void **)&L->base, L->L.total) != hipSuccess) {
       (void)hipGetLastError();
+      g_create_err = "hipMalloc failed";
       delete L;
       return VPLBM_ENOMEM;
     }
@@ -460,6 +489,7 @@ int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *h
   if (!rc) rc = launch_init(L, 0, L->p.ny, nullptr, nullptr, nullptr, p->rho0, 0.0, 0.0);
   if (!rc) rc = L->sync();
   if (rc) {
+    g_create_err = L->err;
     if (L->owns) (void)hipFree(L->base);
     delete L;
     return rc;
@@ -477,7 +507,7 @@ int vplbm_destroy(vplbm_lattice *L) {
   return VPLBM_OK;
 }
 
-const char *vplbm_last_error(const vplbm_lattice *L) { return L ? L->err.c_str() : "null handle"; }
+const char *vplbm_last_error(const vplbm_lattice *L) { return L ? L->err.c_str() : g_create_err.c_str(); }
 
 static int reset_counters(vplbm_lattice *L) {
   Ctl c;
@@ -581,7 +611,7 @@ int vplbm_set_body_disk(vplbm_lattice *L, double xc, double yc, double r) {
   const int x0 = std::max(bx0, 0), x1 = std::min(bx1, nx), y0 = std::max(by0, 0), y1 = std::min(by1, ny);
   if (x1 <= x0 || y1 <= y0) return L->fail(VPLBM_EINVAL, "empty disk region");
   dim3 blk(256), grd((x1 - x0 + 255) / 256, y1 - y0);
-  hipLaunchKernelGGL(k_mask_disk, grd, blk, 0, L->stream, L->mask(), L->pitch, x0, y0, x1, y1, X, Y, R);
+  VP_LAUNCH(k_mask_disk, grd, blk, 0, L->stream, L->mask(), L->pitch, x0, y0, x1, y1, X, Y, R);
   rc = L->launched("k_mask_disk");
   if (rc) return rc;
   c.body = BodyDev{xc, yc, 0.0, 0.0, 0.0, 0.0};
@@ -634,7 +664,7 @@ int vplbm_set_body_polygon(vplbm_lattice *L, const double *xy, int nvert, double
   const int y0 = std::max((int)std::floor(ymin) - 1, 0), y1 = std::min((int)std::ceil(ymax) + 2, ny);
   if (x1 <= x0 || y1 <= y0) return L->fail(VPLBM_EINVAL, "empty polygon region");
   dim3 blk(256), grd((x1 - x0 + 255) / 256, y1 - y0);
-  hipLaunchKernelGGL(k_mask_polygon, grd, blk, 0, L->stream, L->mask(), L->pitch, x0, y0, x1, y1, dv,
+  VP_LAUNCH(k_mask_polygon, grd, blk, 0, L->stream, L->mask(), L->pitch, x0, y0, x1, y1, dv,
                      dv + L->maxv, nvert);
   rc = L->launched("k_mask_polygon");
   if (!rc) rc = L->sync();
@@ -846,8 +876,7 @@ int vplbm_step_timed(vplbm_lattice *L, int nsteps, int flags, double *kernel_ms)
     if (!rc) rc = launch_step(L, macro);
     if (!rc) rc = L->hip(hipEventRecord(ev[2 * i + 1], L->stream), "hipEventRecord");
     if (!rc && moving) {
-      if (L->shape == SHAPE_DISK) rc = launch_body_step(L);
-      if (!rc && L->npts) rc = launch_si_select(L);
+      rc = launch_body_step(L);  // only disks move; also reselects the sample nodes
       L->pending = false;
     } else if (!rc) {
       L->pending = true;
@@ -979,55 +1008,74 @@ int vplbm_get_body_state(vplbm_lattice *L, vplbm_body_state *out) {
   return VPLBM_OK;
 }
 
-int vplbm_read_macro(vplbm_lattice *L, double *rho, double *ux, double *uy) {
+static bool bad_window(const vplbm_lattice *L, int x0, int y0, int w, int h) {
+  return x0 < 0 || y0 < 0 || w < 1 || h < 1 || x0 > L->p.nx - w || y0 > L->p.ny - h;
+}
+
+int vplbm_read_macro_window(vplbm_lattice *L, int x0, int y0, int w, int h, double *rho, double *ux,
+                            double *uy) {
   if (!L || !rho || !ux || !uy) return VPLBM_EINVAL;
+  if (bad_window(L, x0, y0, w, h)) return L->fail(VPLBM_EINVAL, "window outside the lattice");
   if (!L->macro_valid) return L->fail(VPLBM_ESTATE, "last step did not store rho and u (VPLBM_STEP_MACRO)");
-  const int nx = L->p.nx, ny = L->p.ny;
-  const int rows = std::max(1, (int)(STAGE_DOUBLES / (3 * (size_t)nx)));
+  const int rows = std::max(1, (int)(STAGE_DOUBLES / (3 * (size_t)w)));
   double *st = (double *)L->at(L->L.staging);
-  std::vector<double> h;
-  for (int y0 = 0; y0 < ny; y0 += rows) {
-    const int nr = std::min(rows, ny - y0);
-    const size_t n = (size_t)nr * nx;
-    dim3 blk(256), grd((nx + 255) / 256, nr);
+  std::vector<double> hb;
+  for (int r0 = 0; r0 < h; r0 += rows) {
+    const int nr = std::min(rows, h - r0);
+    const size_t n = (size_t)nr * w;
+    dim3 blk(256), grd((w + 255) / 256, nr);
     if (L->p.precision == VPLBM_F64)
-      hipLaunchKernelGGL((k_read_macro<double>), grd, blk, 0, L->stream, (const double *)L->at(L->L.mrho),
-                         (const double *)L->at(L->L.mux), (const double *)L->at(L->L.muy), nx, L->pitch, y0,
-                         nr, st);
+      VP_LAUNCH((k_read_macro<double>), grd, blk, 0, L->stream, (const double *)L->at(L->L.mrho),
+                         (const double *)L->at(L->L.mux), (const double *)L->at(L->L.muy), x0, w, L->pitch,
+                         y0 + r0, nr, st);
     else
-      hipLaunchKernelGGL((k_read_macro<float>), grd, blk, 0, L->stream, (const float *)L->at(L->L.mrho),
-                         (const float *)L->at(L->L.mux), (const float *)L->at(L->L.muy), nx, L->pitch, y0,
-                         nr, st);
+      VP_LAUNCH((k_read_macro<float>), grd, blk, 0, L->stream, (const float *)L->at(L->L.mrho),
+                         (const float *)L->at(L->L.mux), (const float *)L->at(L->L.muy), x0, w, L->pitch,
+                         y0 + r0, nr, st);
     int rc = L->launched("k_read_macro");
-    h.resize(3 * n);
-    if (!rc) rc = L->hip(hipMemcpyAsync(h.data(), st, 3 * n * 8, hipMemcpyDeviceToHost, L->stream), "macro");
+    hb.resize(3 * n);
+    if (!rc) rc = L->hip(hipMemcpyAsync(hb.data(), st, 3 * n * 8, hipMemcpyDeviceToHost, L->stream), "macro");
     if (!rc) rc = L->sync();
     if (rc) return rc;
-    std::memcpy(rho + (size_t)y0 * nx, h.data(), n * 8);
-    std::memcpy(ux + (size_t)y0 * nx, h.data() + n, n * 8);
-    std::memcpy(uy + (size_t)y0 * nx, h.data() + 2 * n, n * 8);
+    std::memcpy(rho + (size_t)r0 * w, hb.data(), n * 8);
+    std::memcpy(ux + (size_t)r0 * w, hb.data() + n, n * 8);
+    std::memcpy(uy + (size_t)r0 * w, hb.data() + 2 * n, n * 8);
+  }
+  return VPLBM_OK;
+}
+
+int vplbm_read_macro(vplbm_lattice *L, double *rho, double *ux, double *uy) {
+  if (!L) return VPLBM_EINVAL;
+  return vplbm_read_macro_window(L, 0, 0, L->p.nx, L->p.ny, rho, ux, uy);
+}
+
+int vplbm_read_populations_window(vplbm_lattice *L, int x0, int y0, int w, int h, double *f) {
+  if (!L || !f) return VPLBM_EINVAL;
+  if (bad_window(L, x0, y0, w, h)) return L->fail(VPLBM_EINVAL, "window outside the lattice");
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
+  const int rows = std::max(1, (int)(STAGE_DOUBLES / (9 * (size_t)w)));
+  double *st = (double *)L->at(L->L.staging);
+  std::vector<double> hb;
+  for (int r0 = 0; r0 < h; r0 += rows) {
+    const int nr = std::min(rows, h - r0);
+    const size_t n = (size_t)nr * w;
+    int rc = launch_read_pop(L, x0, w, y0 + r0, nr, st);
+    hb.resize(9 * n);
+    if (!rc) rc = L->hip(hipMemcpyAsync(hb.data(), st, 9 * n * 8, hipMemcpyDeviceToHost, L->stream), "pop");
+    if (!rc) rc = L->sync();
+    if (rc) return rc;
+    for (int a = 0; a < Q; ++a)
+      std::memcpy(f + (size_t)a * w * h + (size_t)r0 * w, hb.data() + a * n, n * 8);
   }
   return VPLBM_OK;
 }
 
 int vplbm_read_populations(vplbm_lattice *L, double *f) {
-  if (!L || !f) return VPLBM_EINVAL;
-  const int nx = L->p.nx, ny = L->p.ny;
-  const int rows = std::max(1, (int)(STAGE_DOUBLES / (9 * (size_t)nx)));
-  double *st = (double *)L->at(L->L.staging);
-  std::vector<double> h;
-  for (int y0 = 0; y0 < ny; y0 += rows) {
-    const int nr = std::min(rows, ny - y0);
-    const size_t n = (size_t)nr * nx;
-    int rc = launch_read_pop(L, y0, nr, st);
-    h.resize(9 * n);
-    if (!rc) rc = L->hip(hipMemcpyAsync(h.data(), st, 9 * n * 8, hipMemcpyDeviceToHost, L->stream), "pop");
-    if (!rc) rc = L->sync();
-    if (rc) return rc;
-    for (int a = 0; a < Q; ++a)
-      std::memcpy(f + (size_t)a * nx * ny + (size_t)y0 * nx, h.data() + a * n, n * 8);
-  }
-  return VPLBM_OK;
+  if (!L) return VPLBM_EINVAL;
+  return vplbm_read_populations_window(L, 0, 0, L->p.nx, L->p.ny, f);
 }
 
 int vplbm_read_mask(vplbm_lattice *L, uint8_t *out) {

@@ -34,7 +34,7 @@ EXPORTS = [
     "vplbm_set_mask", "vplbm_set_body_motion", "vplbm_set_body_dynamics", "vplbm_set_si_points",
     "vplbm_step", "vplbm_step_timed", "vplbm_sync", "vplbm_step_count", "vplbm_set_tile", "vplbm_forces_me", "vplbm_forces_si",
     "vplbm_forces_si_at", "vplbm_force_history", "vplbm_get_body_state", "vplbm_read_macro",
-    "vplbm_read_populations", "vplbm_read_mask",
+    "vplbm_read_populations", "vplbm_read_mask", "vplbm_read_macro_window", "vplbm_read_populations_window",
 ]
 
 
@@ -52,7 +52,7 @@ class Params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("tau", C.c_double), ("eta", C.c_double),
                 ("rho0", C.c_double), ("precision", C.c_int), ("west", Edge), ("east", Edge),
                 ("south", Edge), ("north", Edge), ("hist_capacity", C.c_int),
-                ("max_si_points", C.c_int), ("max_vertices", C.c_int)]
+                ("max_si_points", C.c_int), ("max_vertices", C.c_int), ("trt_lambda", C.c_double)]
 
 
 class BodyState(C.Structure):
@@ -70,6 +70,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing (run paper_2110_00967_amd/build.py)")
+    # torch ships its own HIP runtime under the same soname as the system's:
+    # load it first so libvplbm.so binds to that one runtime (loading ours
+    # first would put two HIP/HSA runtimes in the process)
+    import torch  # noqa: F401
     L = C.CDLL(path)
     P = C.POINTER
     vp, dp, ip = C.c_void_p, P(C.c_double), C.c_int
@@ -101,6 +105,8 @@ def load_library(path: str = LIB_PATH):
     L.vplbm_get_body_state.argtypes = [vp, P(BodyState)]
     L.vplbm_read_macro.argtypes = [vp, dp, dp, dp]
     L.vplbm_read_populations.argtypes = [vp, dp]
+    L.vplbm_read_macro_window.argtypes = [vp, ip, ip, ip, ip, dp, dp, dp]
+    L.vplbm_read_populations_window.argtypes = [vp, ip, ip, ip, ip, dp]
     L.vplbm_read_mask.argtypes = [vp, P(C.c_uint8)]
     for name in EXPORTS:
         if name not in ("vplbm_required_bytes", "vplbm_last_error", "vplbm_step_count"):
@@ -122,13 +128,14 @@ def _f64(a, shape=None):
 
 def make_params(nx, ny, tau, eta, rho0=1.0, precision="f32", west=(PERIODIC, 0, 0), east=(PERIODIC, 0, 0),
                 south=(PERIODIC, 0, 0), north=(PERIODIC, 0, 0), hist_capacity=0, max_si_points=0,
-                max_vertices=0) -> Params:
+                max_vertices=0, trt_lambda=0.0) -> Params:
     p = Params()
     p.nx, p.ny, p.tau, p.eta, p.rho0 = int(nx), int(ny), float(tau), float(eta), float(rho0)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     for name, e in (("west", west), ("east", east), ("south", south), ("north", north)):
         setattr(p, name, Edge(int(e[0]), float(e[1]), float(e[2])))
     p.hist_capacity, p.max_si_points, p.max_vertices = hist_capacity, max_si_points, max_vertices
+    p.trt_lambda = float(trt_lambda)
     return p
 
 
@@ -162,7 +169,8 @@ class Lattice:
                                     C.c_size_t(device_buffer.numel()), C.c_void_p(stream.cuda_stream),
                                     C.byref(h))
         if rc != OK:
-            raise VplbmError(rc, "vplbm_create failed")
+            why = self._lib.vplbm_last_error(None).decode(errors="replace")
+            raise VplbmError(rc, f"vplbm_create failed: {why}")
         self._h = h
 
     @classmethod
@@ -172,7 +180,7 @@ class Lattice:
         nv = 0 if case.polygon is None else len(case.polygon)
         p = make_params(case.nx, case.ny, case.tau, case.eta, case.rho0, precision, e(case.west), e(case.east),
                         e(case.south), e(case.north), max_si_points=max(npts, 16), max_vertices=max(nv, 16),
-                        **kw)
+                        trt_lambda=case.trt_lambda, **kw)
         lat = cls(p)
         if case.gx or case.gy:
             lat.set_body_force(case.gx, case.gy)
@@ -299,6 +307,17 @@ class Lattice:
         v = np.zeros((self.ny, self.nx))
         self._chk(self._lib.vplbm_read_macro(self._h, _dptr(r), _dptr(u), _dptr(v)))
         return r, u, v
+
+    def macro_window(self, x0, y0, w, h):
+        r, u, v = np.zeros((h, w)), np.zeros((h, w)), np.zeros((h, w))
+        self._chk(self._lib.vplbm_read_macro_window(self._h, x0, y0, w, h, _dptr(r), _dptr(u), _dptr(v)))
+        return r, u, v
+
+    def populations_window(self, x0, y0, w, h):
+        """Post-collision populations of a window, float64 (9, h, w)."""
+        f = np.zeros((9, h, w))
+        self._chk(self._lib.vplbm_read_populations_window(self._h, x0, y0, w, h, _dptr(f)))
+        return f
 
     def populations(self):
         """Post-collision populations as float64, shape (9, ny, nx)."""

@@ -63,6 +63,7 @@ def test_required_bytes_valid():
     dict(eta=-1.0), dict(eta=float("nan")), dict(precision=7), dict(west=(V.PERIODIC, 0, 0)),
     dict(south=(V.VELOCITY, 0, 0)), dict(north=(9, 0, 0)), dict(east=(V.VELOCITY, float("inf"), 0)),
     dict(nx=200000, ny=200000), dict(max_si_points=5000), dict(hist_capacity=-1),
+    dict(trt_lambda=-0.1), dict(trt_lambda=float("nan")), dict(nx=20000),
 ])
 def test_required_bytes_rejects(kw):
     assert V.required_bytes(base(**kw)) == 0

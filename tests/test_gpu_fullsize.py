@@ -1,0 +1,110 @@
+"""GPU-vs-oracle parity at the workloads' full sizes, in the launch
+configuration bench.py times (FP32 deviation storage, default tile).
+
+* NACA 0012, 2000 x 1000: bit-exact solid indicator and sample nodes; 200
+  steps against the FP64 oracle (velocity relative L2 <= 1e-5, force
+  histories within 0.5% of the largest force).
+* Sedimenting disk, 400 x 2000: 200 steps of the free body driven by the
+  momentum-exchange force, mask rebuilt on the device every step.
+* Largest lattice the library accepts (16384 x 14563, 9*ny*pitch just below
+  2^31): sampled cells, each checked against one oracle step on its own
+  5 x 5 neighbourhood (the update of a cell depends only on its 3 x 3
+  neighbourhood).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_cases import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_naca_full_size_fp32():
+    from paper_2110_00967_amd import vplbm as V
+    case = W.case_naca(chord=200, aoa_deg=10.0)
+    say("naca0012 2000x1000 fp32 vs oracle, 200 steps")
+    g = V.Lattice.from_case(case, precision="f32")
+    o = O.RefLattice.from_case(case)
+    assert np.array_equal(g.mask() & 1, o.solid)
+    sample = np.zeros(o.nx * o.ny, bool)
+    sample[o.si_node] = True
+    assert np.array_equal((g.mask().ravel() & 0x40) != 0, sample)
+    g.step(200, macro=True)
+    o.step(200)
+    r, u, v = g.macro()
+    err_u = rel_l2(np.stack([u, v]), np.stack([o.ux, o.uy]))
+    err_r = rel_l2(r - 1.0, o.rho - 1.0)
+    say(f"naca u relL2 {err_u:.2e}, (rho-1) relL2 {err_r:.2e}")
+    assert err_u <= 1e-5
+    for which, ref in ((0, o.me()), (1, o.si())):
+        h = g.history(which)
+        e = np.abs(h - ref).max() / np.abs(ref).max()
+        say(f"naca force {which} max rel err {e:.2e}")
+        assert e <= 5e-3
+
+
+def test_sedimentation_full_size_fp32():
+    from paper_2110_00967_amd import vplbm as V
+    case = W.case_sedimentation()
+    say("sedimentation 400x2000 fp32 vs oracle, 200 steps")
+    g = V.Lattice.from_case(case, precision="f32")
+    o = O.RefLattice.from_case(case)
+    g.step(200, macro=True)
+    o.step(200)
+    bg, bo = g.body_state(), o.body_state()
+    say(f"body gpu {bg}, oracle {bo}")
+    dv = abs(bo[4])
+    assert abs(bg[4] - bo[4]) <= 5e-3 * dv
+    assert abs(bg[1] - bo[1]) <= 5e-3 * abs(bo[1] - case.disk[1]) + 1e-9
+    assert np.array_equal(g.mask() & 1, o.solid)
+    r, u, v = g.macro()
+    err_u = rel_l2(np.stack([u, v]), np.stack([o.ux, o.uy]))
+    say(f"sedimentation u relL2 {err_u:.2e}")
+    assert err_u <= 1e-5
+
+
+def test_largest_lattice_sampled_fp32():
+    from paper_2110_00967_amd import vplbm as V
+    nx, ny = 16384, 14563
+    assert 9 * ny * nx < 2 ** 31 and 9 * (ny + 1) * nx >= 2 ** 31
+    edges = ((V.VELOCITY, 0.05, 0.0), (V.OUTFLOW, 0, 0), (V.FREESLIP, 0, 0), (V.FREESLIP, 0, 0))
+    tau, eta = 0.56, 1e-4
+    p = V.make_params(nx, ny, tau, eta, 1.0, "f32", *edges, max_si_points=16)
+    say(f"largest lattice {nx}x{ny} fp32, {V.required_bytes(p) / 2**30:.1f} GiB")
+    g = V.Lattice(p)
+    xc, yc, rad = 5000.0, 7000.0, 300.0
+    g.set_disk(xc, yc, rad)
+    g.init_uniform(1.0, 0.05, 0.0)
+    g.step(5)
+    rng = np.random.default_rng(5)
+    cells = [(0, 0), (nx - 1, ny - 1), (0, ny - 1), (nx - 1, 0), (int(xc - rad), int(yc)),
+             (int(xc + rad), int(yc) + 1), (int(xc), int(yc + rad)), (nx // 2, 0), (0, ny // 2)]
+    cells += [(int(a), int(b)) for a, b in zip(rng.integers(0, nx, 12), rng.integers(0, ny, 12))]
+    windows = []
+    for (x, y) in cells:
+        x0, y0 = min(max(x - 2, 0), nx - 5), min(max(y - 2, 0), ny - 5)
+        windows.append((x, y, x0, y0, g.populations_window(x0, y0, 5, 5)))
+    solid_all = g.mask()
+    g.step(1, macro=True)
+    for (x, y, x0, y0, f5) in windows:
+        # oracle edges: the lattice's own where the window touches it, zero-gradient inside
+        def side(touch, kind):
+            return kind if touch else (O.OUTFLOW, 0.0, 0.0)
+        west = side(x0 == 0, edges[0])
+        east = side(x0 + 5 == nx, edges[1])
+        south = side(y0 == 0, edges[2])
+        north = side(y0 + 5 == ny, edges[3])
+        o = O.RefLattice(5, 5, tau, eta, 1.0, west, east, south, north)
+        o.set_mask(solid_all[y0:y0 + 5, x0:x0 + 5] & 1)
+        o.body.x, o.body.y = xc, yc
+        o.ft[:] = np.transpose(f5, (1, 2, 0))
+        o.step(1)
+        fg = g.populations_window(x, y, 1, 1)[:, 0, 0]
+        fo = o.ft[y - y0, x - x0, :]
+        assert np.abs(fg - fo).max() <= 2e-6, (x, y, np.abs(fg - fo).max())
+        rg, ug, vg = (a[0, 0] for a in g.macro_window(x, y, 1, 1))
+        assert abs(ug - o.ux[y - y0, x - x0]) <= 2e-6 and abs(rg - o.rho[y - y0, x - x0]) <= 2e-6
+    say(f"largest lattice: {len(windows)} sampled cells match")
+    g.close()

@@ -78,6 +78,13 @@ RAGGED = {
 _poly, _ref, _si = small_naca()
 RAGGED["inlet_outlet_freeslip_naca"] = spec(150, 75, tau=0.56, edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)),
                                             polygon=_poly, ref=_ref, si=_si, init=("uniform", 1.0, 0.05, 0.0))
+RAGGED["trt_naca_paper_lambda"] = spec(150, 75, tau=0.55, trt=1.0 / 6.0,
+                                      edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)),
+                                      polygon=_poly, ref=_ref, si=_si, init=("uniform", 1.0, 0.05, 0.0))
+RAGGED["trt_walls_force_random"] = spec(133, 41, tau=0.7, eta=1e-3, trt=3.0 / 16.0,
+                                       edges=((P, 0, 0), (P, 0, 0), (V_, 0, 0), (V_, 0.01, 0)), gx=2e-6,
+                                       disk=(60.2, 20.7, 7.4), si=W.disk_si_points(60.2, 20.7, 7.4, 40),
+                                       init=("fields",) + random_fields(133, 41, 23, amp=0.02))
 _m = np.zeros((45, 77), np.uint8)
 _m[0:6, :] = 1
 _m[20:30, 10:14] = 1

@@ -189,3 +189,47 @@ def test_mass_conservation_with_penalized_disk():
     # per cell and step (~1e-13 relative over 2000 steps); a dropped or
     # misplaced mass term would show up orders of magnitude above this bound.
     assert abs(m1 - m0) / m0 <= 5e-13
+
+
+# ---------------------------------------------------------------------------
+# two-relaxation-time collision (Eq. TRT)
+# ---------------------------------------------------------------------------
+
+def trt_channel(ny, tau, lam):
+    nu = (tau - 0.5) / 3.0
+    lat = O.RefLattice(1, ny, tau, float("inf"), south=(O.VELOCITY, 0, 0), north=(O.VELOCITY, 0, 0), gx=G,
+                       trt_lambda=lam)
+    lat.init_uniform(1.0, 0.0, 0.0)
+    lat.step(int(30 * ny * ny / nu) if tau > 0.6 else 40000)
+    y = np.arange(ny)
+    return lat.ux[:, 0], G / (2 * nu) * (y + 0.5) * (ny - 0.5 - y)
+
+
+@pytest.mark.parametrize("tau", [0.55, 1.2])
+def test_trt_poiseuille_exact_for_lambda_3_16(tau):
+    # with half-way bounce-back, TRT places the wall exactly half a link out
+    # for Lambda = 3/16, whatever tau
+    u, ex = trt_channel(16, tau, 3.0 / 16.0)
+    assert np.abs(u - ex).max() <= 1e-9 * ex.max()
+
+
+def test_trt_steady_state_depends_on_lambda_only():
+    # the paper's Lambda = 1/6: same steady profile (relative to nu) for two taus
+    u1, ex1 = trt_channel(12, 0.55, 1.0 / 6.0)
+    u2, ex2 = trt_channel(12, 1.2, 1.0 / 6.0)
+    assert np.abs(u1 / ex1.max() - u2 / ex2.max()).max() <= 1e-9
+    assert np.abs(u1 - ex1).max() > 1e-5 * ex1.max()  # not the exact case
+
+
+def test_trt_with_equal_rates_is_bgk():
+    tau = 0.7
+    lam = (tau - 0.5) ** 2  # tau- = tau+
+    a = O.RefLattice(40, 30, tau, 1e-4, trt_lambda=lam)
+    b = O.RefLattice(40, 30, tau, 1e-4)
+    for lat in (a, b):
+        lat.set_disk(19.3, 14.8, 6.1)
+        ux, uy = W.smooth_random_velocity(40, 30, seed=41, amp=0.03)
+        lat.set_fields(W.random_density(40, 30, seed=42), ux, uy)
+        lat.step(30)
+    assert np.abs(a.ft - b.ft).max() <= 1e-14
+    assert np.abs(a.me()[-1] - b.me()[-1]).max() <= 1e-12

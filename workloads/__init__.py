@@ -68,6 +68,7 @@ class Case:
     rho_s: Optional[float] = None
     grav: tuple = (0.0, 0.0)
     force_source: int = 0
+    trt_lambda: float = 0.0  # > 0: TRT collision with this magic parameter
     length_scale: float = 1.0  # chord or diameter for coefficients
     u_ref: float = 0.0
 
