@@ -80,6 +80,87 @@ def cpu_baseline(case, budget_s=12.0):
     }
 
 
+def run_sweep(args, torch, W, V):
+    """64 airfoil cases stepped by one launch per step, and the same cases
+    stepped one after the other (the plain single-case form)."""
+    cases = W.sweep_cases()
+    lats = [V.Lattice.from_case(c, precision=args.precision) for c in cases]
+    cells = sum(c.nx * c.ny for c in cases)
+    batch = V.Batch(lats)
+    n = len(lats)
+    batch.step([args.warmup] * n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    batch.step([args.steps] * n)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # serial form: each case alone, one after the other, same number of steps
+    ks = max(args.steps // 4, 1)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s0.record()
+    for lat in lats:
+        lat.step(ks)
+    s1.record()
+    torch.cuda.synchronize()
+    ms_serial = s0.elapsed_time(s1) / ks
+    bpc = BYTES_PER_CELL[args.precision]
+    achieved = bpc * cells / (ms * 1e-3) / 1e9
+    q = [0.5 * c.u_ref ** 2 * c.length_scale for c in cases]
+    cd = [lat.forces_si()[0] / qq for lat, qq in zip(lats, q)]
+    out = {
+        "metric": METRIC, "value": round(cells / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16dev": "f32 (f16 storage)", "f64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "naca0012_aoa_sweep_64cases", "cases": n, "cells": cells,
+                   "chords": [100, 150, 200], "aoa_deg": [0.0, 20.0], "storage": args.precision,
+                   "parallelism": "single GPU, one batched launch per step"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_step_batch",
+                     "kernel_us": round(ms * 1e3, 3), "bytes_per_cell": bpc, "cells_per_launch": cells},
+        "serial": {"ms_per_step": round(ms_serial, 5), "MLUPS": round(cells / (ms_serial * 1e-3) / 1e6, 1),
+                   "steps": ks},
+        "CD_SI_range": [round(min(cd), 4), round(max(cd), 4)],
+    }
+    batch.close()
+    for lat in lats:
+        lat.close()
+    return out
+
+
+def run_serve(args, W):
+    """Continuous batching of a Poisson request mix under an HBM budget, and
+    the same trace served one request at a time."""
+    from paper_2110_00967_amd.serve import GpuEngine, Server, serial_run, summarize
+
+    reqs = W.serving_trace(nreq=args.requests, seed=0, rate=args.rate, steps_range=(2e3, 2e4))
+    items = W.serving_items(reqs)
+    eng = GpuEngine(args.precision)
+    # warm the kernels up once (first launches pay code-object loading)
+    warm = items[0][2]
+    h = eng.create(warm)
+    eng.step([h], [10])
+    eng.sync()
+    eng.release(h)
+    budget = int(args.budget_gib * 2 ** 30)
+    served = summarize(Server(eng, budget, chunk=1000).run(items))
+    serial = summarize(serial_run(eng, items))
+    return {
+        "metric": METRIC, "value": round(served["aggregate_MLUPS"], 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": sum(r["steps"] for r in reqs), "warmup": 10, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16dev": "f32 (f16 storage)", "f64": "f64"}[args.precision], "data": "synthetic",
+        "config": {"workload": "serving_poisson_mix", "requests": args.requests, "rate_per_s": args.rate,
+                   "grids": [[256, 256], [512, 256], [1024, 512], [2048, 1024]], "steps_range": [2000, 20000],
+                   "hbm_budget_GiB": args.budget_gib, "chunk_steps": 1000, "storage": args.precision},
+        "serving": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in served.items()},
+        "serial": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in serial.items()},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,9 +168,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="f32", choices=["f32", "f16dev", "f64"])
     ap.add_argument("--tile", default=None, help="step workgroup BXxBY: threads (cells) along x times rows")
-    ap.add_argument("--workload", default="naca", choices=["naca", "sediment", "roofline", "disk"],
+    ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=10.0, help="serve: Poisson arrival rate (requests/s)")
+    ap.add_argument("--budget-gib", type=float, default=4.0, help="serve: HBM budget for resident lattices")
+    ap.add_argument("--workload", default="naca", choices=["naca", "sediment", "roofline", "disk", "sweep", "serve"],
                     help="naca: NACA 0012 2000x1000 (default); sediment: free disk 400x2000; "
-                         "roofline: NACA 0012 chord 819 on 8192x8192; disk: 128x64 disk channel")
+                         "roofline: NACA 0012 chord 819 on 8192x8192; disk: 128x64 disk channel; "
+                         "sweep: 64 airfoils (chords 100/150/200, AoA 0-20 deg) in one batched launch; "
+                         "serve: Poisson mix of airfoil and sedimentation requests, continuous batching")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference kernel for HBM counters)")
@@ -106,6 +192,12 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
 
+    if args.workload == "sweep":
+        print(json.dumps(run_sweep(args, torch, W, V)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args, W)), flush=True)
+        return
     if args.workload == "naca":
         case = W.case_naca(chord=200, aoa_deg=10.0)
     elif args.workload == "sediment":

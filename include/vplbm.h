@@ -211,6 +211,27 @@ int vplbm_read_populations_window(vplbm_lattice *lat, int x0, int y0, int w, int
  * bit 7 interface cell (a neighbour has the other phase). */
 int vplbm_read_mask(vplbm_lattice *lat, uint8_t *out);
 
+/* ---- batches --------------------------------------------------------------
+ * A batch steps several lattices with one launch of the fused step kernel per
+ * time step: the tiles of all active lattices are laid end to end and each
+ * workgroup finds its lattice from a device table.  Each lattice computes
+ * exactly what vplbm_step would (same tiles, same reduction order), so its
+ * results do not depend on what else is in the batch.  Moving disks add one
+ * body kernel per step (one workgroup per moving lattice).  Runs of steps
+ * are replayed from a captured HIP graph. */
+typedef struct vplbm_batch vplbm_batch;
+
+/* All lattices must share the precision, the collision (BGK or TRT), the
+ * HIP stream and the default 64x4 tile; a lattice appears once.  The handles stay owned by the caller
+ * and must outlive the batch; they must not be stepped concurrently. */
+int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out);
+int vplbm_batch_destroy(vplbm_batch *b);
+const char *vplbm_batch_last_error(const vplbm_batch *b);
+/* Advance lattice k by nsteps[k] steps (0 = idle); asynchronous.  Lattices
+ * with steps left run together; a lattice drops out when its count is
+ * reached.  Forces, histories and states are read per lattice afterwards. */
+int vplbm_batch_step(vplbm_batch *b, const int *nsteps);
+
 #ifdef __cplusplus
 }
 #endif

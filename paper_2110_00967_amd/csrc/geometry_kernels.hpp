@@ -354,11 +354,11 @@ __global__ void __launch_bounds__(SI_NT)
 constexpr int BODY_NT = 1024;
 constexpr int REGION_MARGIN = 6;  // covers links (1) and sample walks (5)
 
-__global__ void __launch_bounds__(BODY_NT)
-    k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ part,
-                double *__restrict__ hist, int cap, int BX, int BY, int nx, int ny, int pitch, int perx,
-                int pery, const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
-                int *__restrict__ si_map) {
+__device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
+                                const double *__restrict__ part, double *__restrict__ hist, int cap, int BX,
+                                int BY, int nx, int ny, int pitch, int perx, int pery,
+                                const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
+                                int *__restrict__ si_map) {
   __shared__ int reg[4];   // union region to rewrite
   __shared__ long long q[3];
   __shared__ double lds[(BODY_NT / 64) * 6];
@@ -440,6 +440,23 @@ __global__ void __launch_bounds__(BODY_NT)
     __syncthreads();
     si_select_block(mask, ctl, pts, maxp, recs, si_map, nx, ny, pitch);
   }
+}
+
+__global__ void __launch_bounds__(BODY_NT)
+    k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ part,
+                double *__restrict__ hist, int cap, int BX, int BY, int nx, int ny, int pitch, int perx,
+                int pery, const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
+                int *__restrict__ si_map) {
+  body_step_block(mask, ctl, part, hist, cap, BX, BY, nx, ny, pitch, perx, pery, pts, maxp, recs, si_map);
+}
+
+// body kernel of a batched launch: one workgroup per moving lattice
+template <typename T>
+__global__ void __launch_bounds__(BODY_NT)
+    k_body_step_batch(const CaseDesc<T> *__restrict__ cases, const int *__restrict__ moving, int flip) {
+  const CaseDesc<T> &C = cases[moving[blockIdx.x]];
+  body_step_block(C.mask, C.ctl, C.part[C.pbit0 ^ flip], C.hist, C.cap, C.tw, C.by, C.P.nx, C.P.ny, C.P.pitch,
+                  C.perx, C.pery, C.pts, C.maxp, const_cast<SiRec *>(C.recs), const_cast<int *>(C.si_map));
 }
 
 // ----------------------------------------------------------------------------

@@ -34,10 +34,10 @@ template <typename T> struct StepArgs {
   long long plane;      // ny * pitch
   int tiles_x, ntiles, per_xcd;
   int kind[4];          // edge kinds W, E, S, N
-  T bb[4][Q];           // velocity bounce-back increment 6 w_a rho0 (c_a . u_w) per edge
+  T wu[4][2];           // 6 rho0 u_w of each edge: bounce-back increment w_a c_a . wu
   T omega, fac, kpen, rho0, gx, gy;
-  int trt;              // 0: BGK; 1: TRT with omega_m = 1/tau-, fac_m = 1 - 1/(2 tau-)
-  T omega_m, fac_m;
+  int trt;              // 0: BGK; 1: TRT (the kernel is chosen accordingly)
+  T omega_m, fac_m;     // TRT: 1/tau- and 1 - 1/(2 tau-)
   double facd, rho0d;
 };
 
@@ -56,7 +56,8 @@ __device__ __forceinline__ T pull_edge(const S *__restrict__ fin, const StepArgs
     const int k = w ? P.kind[WEST] : P.kind[EAST];
     if (k == EDGE_VELOCITY)
       return Store<S>::ld(fin + (long long)opp(a) * P.plane + (long long)y * P.pitch + x) +
-             (w ? P.bb[WEST][a] : P.bb[EAST][a]);
+             T(wgt(a)) * (w ? T(cxa) * P.wu[WEST][0] + T(cya) * P.wu[WEST][1]
+                            : T(cxa) * P.wu[EAST][0] + T(cya) * P.wu[EAST][1]);
     if (k == EDGE_PERIODIC) sx = sx < 0 ? sx + P.nx : sx - P.nx;
     else if (k == EDGE_OUTFLOW) sx = sx < 0 ? 0 : P.nx - 1;
     else { sx = x; pop = flipx(pop); }
@@ -66,7 +67,8 @@ __device__ __forceinline__ T pull_edge(const S *__restrict__ fin, const StepArgs
     const int k = s_ ? P.kind[SOUTH] : P.kind[NORTH];
     if (k == EDGE_VELOCITY)
       return Store<S>::ld(fin + (long long)opp(a) * P.plane + (long long)y * P.pitch + x) +
-             (s_ ? P.bb[SOUTH][a] : P.bb[NORTH][a]);
+             T(wgt(a)) * (s_ ? T(cxa) * P.wu[SOUTH][0] + T(cya) * P.wu[SOUTH][1]
+                             : T(cxa) * P.wu[NORTH][0] + T(cya) * P.wu[NORTH][1]);
     if (k == EDGE_PERIODIC) sy = sy < 0 ? sy + P.ny : sy - P.ny;
     else if (k == EDGE_OUTFLOW) sy = sy < 0 ? 0 : P.ny - 1;
     else { sy = y; pop = flipy(pop); }
@@ -124,22 +126,18 @@ __device__ __forceinline__ void finalize_block(const double *__restrict__ part, 
   }
 }
 
-template <typename S, int BX, int BY, bool MACRO>
-__global__ void __launch_bounds__(BX *BY)
-    k_step(const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
-           const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl,
-           const SiRec *__restrict__ recs, const int *__restrict__ si_map,
-           double *__restrict__ part_out, const double *__restrict__ part_prev, int fin_prev,
-           double *__restrict__ hist, int cap, typename Store<S>::T *__restrict__ mrho,
-           typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy) {
+// One workgroup's tile of the step (tile < P.ntiles): the body of the step
+// kernel, shared by the single-lattice and the batched launch.  The
+// workgroup of tile 0 also finalizes the previous step's forces (fin_prev).
+template <typename S, int BX, int BY, bool MACRO, bool TRT>
+__device__ __forceinline__ void step_tile(
+    int tile, const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
+    const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl, const SiRec *__restrict__ recs,
+    const int *__restrict__ si_map, double *__restrict__ part_out, const double *__restrict__ part_prev,
+    int fin_prev, double *__restrict__ hist, int cap, typename Store<S>::T *__restrict__ mrho,
+    typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy) {
   using T = typename Store<S>::T;
   constexpr int NT = BX * BY;
-  // XCD-aware tile order: consecutive workgroups go round-robin over the 8
-  // XCDs, so give each XCD a contiguous band of tiles (shared halo lines stay
-  // in that XCD's L2).
-  const int b = blockIdx.x;
-  const int tile = (b & 7) * P.per_xcd + (b >> 3);
-  if (tile >= P.ntiles) return;
   const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
   const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
   const int x = tx * BX + lx, y = ty * BY + ly;
@@ -189,7 +187,7 @@ __global__ void __launch_bounds__(BX *BY)
     const T uu15 = T(1.5) * (ux * ux + uy * uy);
     const T uF3 = T(3) * (ux * Fx + uy * Fy);
     T deq[Q];
-    if (!P.trt) {
+    if constexpr (!TRT) {
       // BGK
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
@@ -289,11 +287,74 @@ __global__ void __launch_bounds__(BX *BY)
       for (int i = 0; i < 6; ++i) o[i] = acc[i];
     }
   }
-  if (fin_prev && b == 0) {
+  if (fin_prev && tile == 0) {
     // forces of the previous step (same window: only static bodies defer)
     __syncthreads();
     finalize_block<NT>(part_prev, wx1 - wx0, wy1 - wy0, ctl, hist, cap, lds);
   }
+}
+
+template <typename S, int BX, int BY, bool MACRO, bool TRT>
+__global__ void __launch_bounds__(BX *BY)
+    k_step(const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
+           const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl,
+           const SiRec *__restrict__ recs, const int *__restrict__ si_map,
+           double *__restrict__ part_out, const double *__restrict__ part_prev, int fin_prev,
+           double *__restrict__ hist, int cap, typename Store<S>::T *__restrict__ mrho,
+           typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy) {
+  // XCD-aware tile order: consecutive workgroups go round-robin over the 8
+  // XCDs, so give each XCD a contiguous band of tiles (shared halo lines stay
+  // in that XCD's L2).
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * P.per_xcd + (b >> 3);
+  if (tile >= P.ntiles) return;
+  step_tile<S, BX, BY, MACRO, TRT>(tile, fin, fout, mask, P, ctl, recs, si_map, part_out, part_prev, fin_prev,
+                                   hist, cap, mrho, mux, muy);
+}
+
+// Per-lattice description for the batched step: one launch covers the tiles
+// of every active lattice, laid end to end in tile order.
+template <typename T> struct CaseDesc {
+  StepArgs<T> P;
+  const void *buf[2];     // populations of parity 0 and 1
+  uint8_t *mask;
+  Ctl *ctl;
+  const SiRec *recs;
+  const int *si_map;
+  double *part[2];        // partial sums of steps with parity 0 and 1
+  double *hist;
+  int cap;
+  int tile0;              // first global tile of this lattice
+  int cur0;               // parity of the buffer holding the state at launch 0
+  int pbit0;              // parity of the step computed by launch 0
+  int pending0;           // launch 0 finalizes the forces of the step before it
+  int moving;             // forces are finalized by the body kernel instead
+  // body-kernel arguments
+  int tw, by, perx, pery, maxp;
+  const double *pts;
+};
+
+// Batched step: launch number `flip` (0 or 1, alternating) of a run over
+// ncases lattices; the lattice of a tile is found by binary search on tile0.
+template <typename S, int BX, int BY, bool TRT>
+__global__ void __launch_bounds__(BX *BY)
+    k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
+                 const int *__restrict__ tile_case, int total_tiles, int per_xcd, int flip, int first) {
+  using T = typename Store<S>::T;
+  const int b = blockIdx.x;
+  const int gtile = (b & 7) * per_xcd + (b >> 3);
+  if (gtile >= total_tiles) return;
+  // the lattice of this tile, then its description, read once
+  const CaseDesc<T> *__restrict__ C = cases + tile_case[gtile];
+  const StepArgs<T> P = C->P;
+  const int par = C->cur0 ^ flip, pb = C->pbit0 ^ flip;
+  const int fin_prev = C->moving ? 0 : (first ? C->pending0 : 1);
+  const S *fin = (const S *)C->buf[par];
+  S *fout = (S *)C->buf[par ^ 1];
+  double *pout = C->part[pb];
+  const double *pprev = C->part[pb ^ 1];
+  step_tile<S, BX, BY, false, TRT>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map, pout, pprev,
+                              fin_prev, C->hist, C->cap, nullptr, nullptr, nullptr);
 }
 
 template <int NT>

@@ -201,8 +201,8 @@ struct vplbm_lattice {
     const vplbm_edge *E[4] = {&p.west, &p.east, &p.south, &p.north};
     for (int e = 0; e < 4; ++e) {
       a.kind[e] = E[e]->kind;
-      for (int q = 0; q < Q; ++q)
-        a.bb[e][q] = T(6.0 * wgt(q) * p.rho0 * (cx(q) * E[e]->ux + cy(q) * E[e]->uy));
+      a.wu[e][0] = T(6.0 * p.rho0 * E[e]->ux);
+      a.wu[e][1] = T(6.0 * p.rho0 * E[e]->uy);
     }
     a.omega = T(1.0 / p.tau);
     a.fac = T(1.0 - 0.5 / p.tau);
@@ -240,12 +240,21 @@ int launch_step_t(vplbm_lattice *L, bool macro) {
   const double *pprev = L->part(n - 1);
   const int fin_prev = L->pending ? 1 : 0;
   double *hist = (double *)L->at(L->L.hist);
-  if (macro)
-    VP_LAUNCH((k_step<S, BX, BY, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
-                       L->mask(), a, L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
-  else
-    VP_LAUNCH((k_step<S, BX, BY, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout,
-                       L->mask(), a, L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
+  if (macro) {
+    if (a.trt)
+      VP_LAUNCH((k_step<S, BX, BY, true, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
+                L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
+    else
+      VP_LAUNCH((k_step<S, BX, BY, true, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
+                L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
+  } else {
+    if (a.trt)
+      VP_LAUNCH((k_step<S, BX, BY, false, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
+                L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
+    else
+      VP_LAUNCH((k_step<S, BX, BY, false, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(),
+                a, L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
+  }
   return L->launched("k_step");
 }
 
@@ -1085,6 +1094,253 @@ int vplbm_read_mask(vplbm_lattice *L, uint8_t *out) {
                   "mask read");
   if (!rc) rc = L->sync();
   return rc;
+}
+
+// ----------------------------------------------------------------------------
+// batches: several lattices stepped by one launch per step
+// ----------------------------------------------------------------------------
+}  // extern "C"
+
+struct vplbm_batch {
+  std::vector<vplbm_lattice *> cases;
+  hipStream_t stream = nullptr;  // the lattices' stream
+  hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+  int prec = 0;
+  bool trt = false;  // collision of every lattice of the batch
+  char *desc_dev = nullptr;
+  int *moving_dev = nullptr;
+  int *tile_case_dev = nullptr;  // lattice index of every global tile
+  size_t tile_case_cap = 0;
+  std::vector<char> desc_host;
+  std::vector<int> moving_host, tile_case_host;
+  hipGraphExec_t graph = nullptr;  // two steps (launch parities 1, 0) of the current active set
+  long long graph_key = -1;
+  std::string err;
+  int fail(int code, const std::string &m) {
+    err = m;
+    return code;
+  }
+  int hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return VPLBM_OK;
+    return fail(VPLBM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+};
+
+namespace {
+
+template <typename S> size_t desc_size() { return sizeof(CaseDesc<typename Store<S>::T>); }
+
+size_t desc_size_of(int prec) {
+  return prec == VPLBM_F64 ? desc_size<double>() : (prec == VPLBM_F32 ? desc_size<float>() : desc_size<__half>());
+}
+
+template <typename S>
+void fill_desc(vplbm_lattice *L, int tile0, void *out) {
+  using T = typename Store<S>::T;
+  CaseDesc<T> d{};
+  d.P = L->step_args<T>();
+  d.buf[0] = L->at(L->L.A);
+  d.buf[1] = L->at(L->L.B);
+  d.mask = L->mask();
+  d.ctl = L->ctl();
+  d.recs = (const SiRec *)L->at(L->L.recs);
+  d.si_map = (const int *)L->at(L->L.si_map);
+  d.part[0] = L->part(0);
+  d.part[1] = L->part(1);
+  d.hist = (double *)L->at(L->L.hist);
+  d.cap = L->cap;
+  d.tile0 = tile0;
+  d.cur0 = L->cur;
+  d.pbit0 = (int)((L->nstep + 1) & 1);
+  d.pending0 = L->pending ? 1 : 0;
+  d.moving = L->mode != MODE_STATIC ? 1 : 0;
+  d.tw = L->bx;
+  d.by = L->by;
+  d.perx = (int)L->periodic_x();
+  d.pery = (int)L->periodic_y();
+  d.maxp = L->maxp;
+  d.pts = (const double *)L->at(L->L.pts);
+  std::memcpy(out, &d, sizeof d);
+}
+
+template <typename S>
+void launch_batch_pair(vplbm_batch *B, hipStream_t st, int nact, int total, int nmov, int flip, int first) {
+  using T = typename Store<S>::T;
+  (void)nact;
+  const int per = (total + 7) / 8;
+  const auto *descs = (const CaseDesc<T> *)B->desc_dev;
+  if (B->trt)
+    hipLaunchKernelGGL((k_step_batch<S, 64, 4, true>), dim3(8 * per), dim3(256), 0, st, descs, B->tile_case_dev,
+                       total, per, flip, first);
+  else
+    hipLaunchKernelGGL((k_step_batch<S, 64, 4, false>), dim3(8 * per), dim3(256), 0, st, descs, B->tile_case_dev,
+                       total, per, flip, first);
+  if (nmov)
+    hipLaunchKernelGGL((k_body_step_batch<T>), dim3(nmov), dim3(BODY_NT), 0, st, descs, B->moving_dev, flip);
+}
+
+void launch_batch(vplbm_batch *B, hipStream_t st, int nact, int total, int nmov, int flip, int first) {
+  switch (B->prec) {
+    case VPLBM_F64: launch_batch_pair<double>(B, st, nact, total, nmov, flip, first); break;
+    case VPLBM_F32: launch_batch_pair<float>(B, st, nact, total, nmov, flip, first); break;
+    default: launch_batch_pair<__half>(B, st, nact, total, nmov, flip, first); break;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out) {
+  if (!out || !lats || n < 1) return VPLBM_EINVAL;
+  *out = nullptr;
+  const int prec = lats[0]->p.precision;
+  for (int k = 0; k < n; ++k) {
+    if (!lats[k] || lats[k]->p.precision != prec || lats[k]->stream != lats[0]->stream) return VPLBM_EINVAL;
+    if ((lats[k]->p.trt_lambda > 0.0) != (lats[0]->p.trt_lambda > 0.0)) return VPLBM_EINVAL;
+    if (lats[k]->bx != 64 || lats[k]->by != 4) return VPLBM_EINVAL;  // batched launches use the 64x4 tile
+    for (int j = 0; j < k; ++j)
+      if (lats[j] == lats[k]) return VPLBM_EINVAL;
+  }
+  auto *B = new (std::nothrow) vplbm_batch();
+  if (!B) return VPLBM_ENOMEM;
+  B->cases.assign(lats, lats + n);
+  B->stream = lats[0]->stream;
+  B->prec = prec;
+  B->trt = lats[0]->p.trt_lambda > 0.0;
+  B->desc_host.assign(desc_size_of(prec) * n, 0);
+  B->moving_host.assign(n, 0);
+  if (hipMalloc((void **)&B->desc_dev, B->desc_host.size()) != hipSuccess ||
+      hipMalloc((void **)&B->moving_dev, sizeof(int) * n) != hipSuccess ||
+      hipStreamCreate(&B->cap_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (B->desc_dev) (void)hipFree(B->desc_dev);
+    if (B->moving_dev) (void)hipFree(B->moving_dev);
+    delete B;
+    return VPLBM_ENOMEM;
+  }
+  *out = B;
+  return VPLBM_OK;
+}
+
+int vplbm_batch_destroy(vplbm_batch *B) {
+  if (!B) return VPLBM_EINVAL;
+  (void)hipStreamSynchronize(B->stream);
+  if (B->graph) (void)hipGraphExecDestroy(B->graph);
+  (void)hipFree(B->desc_dev);
+  (void)hipFree(B->moving_dev);
+  if (B->tile_case_dev) (void)hipFree(B->tile_case_dev);
+  (void)hipStreamDestroy(B->cap_stream);
+  delete B;
+  return VPLBM_OK;
+}
+
+const char *vplbm_batch_last_error(const vplbm_batch *B) { return B ? B->err.c_str() : "null batch"; }
+
+int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
+  if (!B || !nsteps) return VPLBM_EINVAL;
+  const int n = (int)B->cases.size();
+  std::vector<long long> rem(n);
+  for (int k = 0; k < n; ++k) {
+    if (nsteps[k] < 0) return B->fail(VPLBM_EINVAL, "negative step count");
+    rem[k] = nsteps[k];
+  }
+  const size_t dsz = desc_size_of(B->prec);
+  for (;;) {
+    // active set of this chunk and its length (every active lattice advances)
+    std::vector<int> act;
+    long long chunk = 0;
+    for (int k = 0; k < n; ++k)
+      if (rem[k] > 0) {
+        act.push_back(k);
+        chunk = chunk == 0 ? rem[k] : std::min(chunk, rem[k]);
+      }
+    if (act.empty()) break;
+    int rc = B->hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");  // host buffers reusable
+    if (rc) return rc;
+    int total = 0, nmov = 0;
+    for (size_t i = 0; i < act.size(); ++i) {
+      vplbm_lattice *L = B->cases[act[i]];
+      const int tiles = L->step_args<float>().ntiles;
+      switch (B->prec) {
+        case VPLBM_F64: fill_desc<double>(L, total, &B->desc_host[i * dsz]); break;
+        case VPLBM_F32: fill_desc<float>(L, total, &B->desc_host[i * dsz]); break;
+        default: fill_desc<__half>(L, total, &B->desc_host[i * dsz]); break;
+      }
+      if (L->mode != MODE_STATIC) B->moving_host[nmov++] = (int)i;
+      total += tiles;
+    }
+    const int nact = (int)act.size();
+    B->tile_case_host.resize(total);
+    for (int i = 0, t = 0; i < nact; ++i) {
+      const int tiles = B->cases[act[i]]->step_args<float>().ntiles;
+      for (int j = 0; j < tiles; ++j) B->tile_case_host[t++] = i;
+    }
+    if ((size_t)total > B->tile_case_cap) {
+      if (B->tile_case_dev) (void)hipFree(B->tile_case_dev);
+      B->tile_case_dev = nullptr;
+      B->tile_case_cap = 0;
+      if (B->graph) (void)hipGraphExecDestroy(B->graph);
+      B->graph = nullptr;
+      rc = B->hip(hipMalloc((void **)&B->tile_case_dev, sizeof(int) * (size_t)total), "tile table");
+      if (rc) return rc;
+      B->tile_case_cap = total;
+    }
+    rc = B->hip(hipMemcpyAsync(B->tile_case_dev, B->tile_case_host.data(), sizeof(int) * (size_t)total,
+                               hipMemcpyHostToDevice, B->stream),
+                "tile table");
+    if (rc) return rc;
+    rc = B->hip(hipMemcpyAsync(B->desc_dev, B->desc_host.data(), dsz * nact, hipMemcpyHostToDevice, B->stream),
+                "batch descriptors");
+    if (!rc && nmov)
+      rc = B->hip(hipMemcpyAsync(B->moving_dev, B->moving_host.data(), sizeof(int) * nmov, hipMemcpyHostToDevice,
+                                 B->stream),
+                  "batch moving list");
+    if (rc) return rc;
+    // launch 0 eagerly (it finalizes what the lattices left pending), then
+    // pairs of launches (parities 1, 0) from a captured graph, then a last one
+    (void)hipGetLastError();
+    launch_batch(B, B->stream, nact, total, nmov, 0, 1);
+    rc = B->hip(hipGetLastError(), "k_step_batch");
+    if (rc) return rc;
+    long long done = 1;
+    const long long pairs = (chunk - 1) / 2;
+    if (pairs > 0) {
+      const long long key = ((long long)nact << 40) ^ ((long long)total << 12) ^ nmov;
+      if (!B->graph || B->graph_key != key) {
+        if (B->graph) (void)hipGraphExecDestroy(B->graph);
+        B->graph = nullptr;
+        hipGraph_t g = nullptr;
+        rc = B->hip(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (rc) return rc;
+        launch_batch(B, B->cap_stream, nact, total, nmov, 1, 0);
+        launch_batch(B, B->cap_stream, nact, total, nmov, 0, 0);
+        rc = B->hip(hipStreamEndCapture(B->cap_stream, &g), "end capture");
+        if (!rc) rc = B->hip(hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0), "graph instantiate");
+        if (g) (void)hipGraphDestroy(g);
+        if (rc) return rc;
+        B->graph_key = key;
+      }
+      for (long long p = 0; p < pairs && !rc; ++p) rc = B->hip(hipGraphLaunch(B->graph, B->stream), "graph launch");
+      if (rc) return rc;
+      done += 2 * pairs;
+    }
+    if (done < chunk) {
+      launch_batch(B, B->stream, nact, total, nmov, 1, 0);
+      rc = B->hip(hipGetLastError(), "k_step_batch");
+      if (rc) return rc;
+      ++done;
+    }
+    for (int k : act) {
+      vplbm_lattice *L = B->cases[k];
+      L->nstep += chunk;
+      L->cur ^= (int)(chunk & 1);
+      L->pending = L->mode == MODE_STATIC;
+      L->macro_valid = false;
+      rem[k] -= chunk;
+    }
+  }
+  return VPLBM_OK;
 }
 
 }  // extern "C"

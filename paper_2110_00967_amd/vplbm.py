@@ -35,6 +35,7 @@ EXPORTS = [
     "vplbm_step", "vplbm_step_timed", "vplbm_sync", "vplbm_step_count", "vplbm_set_tile", "vplbm_forces_me", "vplbm_forces_si",
     "vplbm_forces_si_at", "vplbm_force_history", "vplbm_get_body_state", "vplbm_read_macro",
     "vplbm_read_populations", "vplbm_read_mask", "vplbm_read_macro_window", "vplbm_read_populations_window",
+    "vplbm_batch_create", "vplbm_batch_destroy", "vplbm_batch_last_error", "vplbm_batch_step",
 ]
 
 
@@ -108,8 +109,13 @@ def load_library(path: str = LIB_PATH):
     L.vplbm_read_macro_window.argtypes = [vp, ip, ip, ip, ip, dp, dp, dp]
     L.vplbm_read_populations_window.argtypes = [vp, ip, ip, ip, ip, dp]
     L.vplbm_read_mask.argtypes = [vp, P(C.c_uint8)]
+    L.vplbm_batch_create.argtypes = [P(vp), ip, P(vp)]
+    L.vplbm_batch_destroy.argtypes = [vp]
+    L.vplbm_batch_last_error.argtypes = [vp]
+    L.vplbm_batch_last_error.restype = C.c_char_p
+    L.vplbm_batch_step.argtypes = [vp, P(C.c_int)]
     for name in EXPORTS:
-        if name not in ("vplbm_required_bytes", "vplbm_last_error", "vplbm_step_count"):
+        if name not in ("vplbm_required_bytes", "vplbm_last_error", "vplbm_step_count", "vplbm_batch_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -329,3 +335,34 @@ class Lattice:
         m = np.zeros((self.ny, self.nx), np.uint8)
         self._chk(self._lib.vplbm_read_mask(self._h, m.ctypes.data_as(C.POINTER(C.c_uint8))))
         return m
+
+
+class Batch:
+    """Several lattices stepped together, one launch per time step."""
+
+    def __init__(self, lattices):
+        self._lib = load_library()
+        self.lattices = list(lattices)
+        arr = (C.c_void_p * len(self.lattices))(*[l._h.value for l in self.lattices])
+        h = C.c_void_p()
+        rc = self._lib.vplbm_batch_create(arr, len(self.lattices), C.byref(h))
+        if rc != OK:
+            raise VplbmError(rc, "vplbm_batch_create failed (same precision, stream and default tile required)")
+        self._h = h
+
+    def step(self, nsteps):
+        n = (C.c_int * len(self.lattices))(*[int(v) for v in nsteps])
+        rc = self._lib.vplbm_batch_step(self._h, n)
+        if rc != OK:
+            raise VplbmError(rc, self._lib.vplbm_batch_last_error(self._h).decode(errors="replace"))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.vplbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

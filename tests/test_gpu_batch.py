@@ -1,0 +1,125 @@
+"""Batched stepping (vplbm_batch_*): every lattice in a batch must compute
+exactly what it computes alone -- bitwise, populations and force histories --
+whatever else is in the batch and however many steps each one takes.  The
+long runs go through the captured-graph path (pairs of launches replayed).
+One lattice is also checked against the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_cases import F, OUT, P, V_, build_gpu, build_oracle, oracle_pops, random_fields, say, small_naca, spec
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_specs():
+    poly, ref, si = small_naca(nx=150, ny=75, chord=30.0, aoa=8.0)
+    return [
+        spec(150, 75, tau=0.56, edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)), polygon=poly, ref=ref,
+             si=si, init=("uniform", 1.0, 0.05, 0.0)),
+        spec(128, 64, tau=0.62, edges=((V_, 0.05, 0), (OUT, 0, 0), (P, 0, 0), (P, 0, 0)), disk=(32.0, 32.0, 8.0),
+             si=W.disk_si_points(32.0, 32.0, 8.0, 64), init=("uniform", 1.0, 0.05, 0.0)),
+        spec(80, 200, tau=0.6, edges=((V_, 0, 0), (V_, 0, 0), (OUT, 0, 0), (V_, 0, 0)), disk=(40.0, 150.0, 6.0),
+             si=W.disk_si_points(40.0, 150.0, 6.0, 40), dynamics=(1.5, 0.0, -2e-4, 1)),
+        spec(131, 37, tau=0.7, eta=1e-3, edges=((P, 0, 0), (P, 0, 0), (V_, 0, 0), (V_, 0.02, 0)),
+             gx=1e-6, disk=(40.0, 18.0, 6.0), init=("fields",) + random_fields(131, 37, 5, amp=0.01)),
+        spec(300, 130, tau=0.65, disk=(150.3, 64.6, 20.2), si=W.disk_si_points(150.3, 64.6, 20.2, 128),
+             init=("fields",) + random_fields(300, 130, 3)),
+    ]
+
+
+def state(g):
+    return g.populations(), g.history(0), g.history(1), g.body_state()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_equals_alone_bitwise(precision):
+    from paper_2110_00967_amd import vplbm as V
+    specs = mixed_specs()
+    nsteps = [40, 17, 33, 0, 26]
+    say("batch of", len(specs), "lattices,", precision, "steps", nsteps)
+    alone = []
+    for s, n in zip(specs, nsteps):
+        g = build_gpu(s, precision)
+        g.step(n)
+        alone.append(state(g) if n else None)
+        g.close()
+    lats = [build_gpu(s, precision) for s in specs]
+    b = V.Batch(lats)
+    b.step(nsteps)
+    for k, (g, ref) in enumerate(zip(lats, alone)):
+        assert g.step_count == nsteps[k]
+        if ref is None:
+            continue
+        got = state(g)
+        for a, r in zip(got, ref):
+            assert np.array_equal(a, r), (precision, k)
+    # a second round with the roles changed (chunks of different shapes)
+    b.step([5, 0, 12, 9, 1])
+    assert [g.step_count for g in lats] == [45, 17, 45, 9, 27]
+    b.close()
+
+
+def test_trt_batch_equals_alone_bitwise():
+    from paper_2110_00967_amd import vplbm as V
+    poly, ref, si = small_naca(nx=150, ny=75, chord=30.0, aoa=12.0)
+    specs = [
+        spec(150, 75, tau=0.55, trt=1.0 / 6.0, edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)),
+             polygon=poly, ref=ref, si=si, init=("uniform", 1.0, 0.05, 0.0)),
+        spec(131, 37, tau=0.7, eta=1e-3, trt=3.0 / 16.0, edges=((P, 0, 0), (P, 0, 0), (V_, 0, 0), (V_, 0.02, 0)),
+             gx=1e-6, disk=(40.0, 18.0, 6.0), init=("fields",) + random_fields(131, 37, 5, amp=0.01)),
+        spec(80, 200, tau=0.6, trt=1.0 / 6.0, edges=((V_, 0, 0), (V_, 0, 0), (OUT, 0, 0), (V_, 0, 0)),
+             disk=(40.0, 150.0, 6.0), si=W.disk_si_points(40.0, 150.0, 6.0, 40), dynamics=(1.5, 0.0, -2e-4, 0)),
+    ]
+    nsteps = [37, 52, 20]
+    say("TRT batch of", len(specs), "lattices, steps", nsteps)
+    alone = []
+    for s, n in zip(specs, nsteps):
+        g = build_gpu(s, "f64")
+        g.step(n)
+        alone.append(state(g))
+        g.close()
+    lats = [build_gpu(s, "f64") for s in specs]
+    b = V.Batch(lats)
+    b.step(nsteps)
+    for g, ref in zip(lats, alone):
+        for a, r in zip(state(g), ref):
+            assert np.array_equal(a, r)
+    # BGK and TRT lattices cannot share a launch
+    bgk = build_gpu(mixed_specs()[1], "f64")
+    with pytest.raises(V.VplbmError):
+        V.Batch([lats[0], bgk])
+    b.close()
+
+
+def test_batch_long_run_graph_replay_vs_oracle():
+    # a long uneven run: most steps come from replays of the captured pair
+    from paper_2110_00967_amd import vplbm as V
+    specs = mixed_specs()[:3]
+    say("batch graph replay, 3 lattices x up to 301 steps fp64")
+    lats = [build_gpu(s, "f64") for s in specs]
+    b = V.Batch(lats)
+    b.step([301, 250, 120])
+    orc = build_oracle(specs[1])
+    orc.step(250)
+    assert np.abs(lats[1].populations() - oracle_pops(orc)).max() <= 1e-12
+    h = lats[1].history(0)
+    assert np.abs(h - orc.me()).max() <= 1e-10 * np.abs(orc.me()).max()
+    # the same run alone, eager launches, must match bitwise
+    g = build_gpu(specs[0], "f64")
+    for _ in range(301):
+        g.step(1)
+    assert np.array_equal(g.populations(), lats[0].populations())
+    assert np.array_equal(g.history(1), lats[0].history(1))
+    b.close()
+
+
+def test_batch_rejects_mixed_precision():
+    from paper_2110_00967_amd import vplbm as V
+    specs = mixed_specs()
+    a = build_gpu(specs[1], "f64")
+    c = build_gpu(specs[1], "f32")
+    with pytest.raises(V.VplbmError):
+        V.Batch([a, c])
+    with pytest.raises(V.VplbmError):
+        V.Batch([a, a])

@@ -261,3 +261,31 @@ def smooth_random_velocity(nx: int, ny: int, seed: int, amp: float = 0.02, modes
 def random_density(nx: int, ny: int, seed: int, amp: float = 1e-3):
     rng = np.random.default_rng(seed)
     return 1.0 + amp * rng.standard_normal((ny, nx))
+
+
+def serving_case(req: dict) -> Case:
+    """Lattice of one serving request (see serving_trace).
+
+    Airfoil: NACA 0012 with chord nx/10, leading edge at (3c, ny/2), inflow
+    0.05, tau = 0.6, free-slip sides.  Sedimentation: disk of diameter nx/20
+    starting 2.5 diameters below the top at x0*nx, density ratio 1.5, small
+    gravity (1e-5) so it stays inside the lattice over the requested steps.
+    """
+    nx, ny = req["nx"], req["ny"]
+    if req["kind"] == "airfoil":
+        chord = nx / 10.0
+        poly = naca0012_polygon(chord, 3.0 * chord, 0.5 * ny, req["aoa"], n_side=50)
+        xy, n, ds = polygon_si_points(poly)
+        cx, cy, _ = polygon_centroid(poly)
+        return Case(name=f"req{req['id']}_airfoil_{nx}x{ny}", nx=nx, ny=ny, tau=0.6, eta=1e-4,
+                    west=Edge(VELOCITY, 0.05, 0.0), east=Edge(OUTFLOW), south=Edge(FREESLIP),
+                    north=Edge(FREESLIP), u_init=(0.05, 0.0), polygon=poly, ref_point=(cx, cy), si_xy=xy,
+                    si_n=n, si_ds=ds, length_scale=chord, u_ref=0.05)
+    d = nx / 20.0
+    return case_sedimentation(nx=nx, ny=ny, d=d, rho_r=1.5, g=1e-5, x0_frac=req["x0"], y0=ny - 2.5 * d,
+                              npts=64)
+
+
+def serving_items(reqs):
+    """(id, arrival, case, steps) tuples for a request loop."""
+    return [(r["id"], r["arrival"], serving_case(r), r["steps"]) for r in reqs]
