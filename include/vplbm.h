@@ -79,6 +79,12 @@ typedef struct {
                         (Eq. TRT) with tau+ = tau and tau- = trt_lambda/(tau - 1/2)
                         + 1/2 (the paper uses 1/6); the forcing term is split the
                         same way, its odd part weighted by 1 - 1/(2 tau-) */
+  int si_rule;       /* stress-integration stencil (Sec. 2.3.2): 0 = the paper's
+                        nearest fluid node in the lattice direction closest to n;
+                        1 = sigma interpolated (bilinear, 4 fluid nodes) at
+                        x + 1.5 n, falling back to rule 0 when a node is solid;
+                        rule 1 needs max_si_points in 1..1024 and keeps
+                        up to 4 sample records per point */
 } vplbm_params;
 
 /* Rigid-body state in lattice units: reference point (centre of a disk,
@@ -158,10 +164,12 @@ int vplbm_set_body_dynamics(vplbm_lattice *lat, double rho_s, double gx, double 
 
 /* Stress-integration points (Sec. 2.3.2): world coordinates xy[2*npts],
  * outward unit normals nrm[2*npts], integration lengths ds[npts], at the
- * current body state; they move rigidly with the body.  Each point takes
- * its stress from a sample node: the lattice direction closest to n, walked
- * from the nearest node for up to 5 nodes until a fluid node is met
- * (VPLBM_ENOSAMPLE if none).  npts = 0 removes the points. */
+ * current body state; they move rigidly with the body.  With si_rule 0 each
+ * point takes its stress from a sample node: the lattice direction closest
+ * to n, walked from the nearest node for up to 5 nodes until a fluid node is
+ * met (VPLBM_ENOSAMPLE if none); with si_rule 1 from the bilinear
+ * interpolation at x + 1.5 n (see vplbm_params).  npts = 0 removes the
+ * points. */
 int vplbm_set_si_points(vplbm_lattice *lat, const double *xy, const double *nrm, const double *ds,
                         int npts);
 

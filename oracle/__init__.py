@@ -62,11 +62,13 @@ def lib():
         L.orc_stream.argtypes = [P, dp, dp]
         L.orc_momentum_exchange.argtypes = [P, dp, up, B, dp]
         L.orc_node_stress.argtypes = [P, dp, dp]
-        L.orc_stress_integration.argtypes = [P, dp, C.c_int, dp, dp, dp, ip, B, dp]
+        L.orc_stress_integration.argtypes = [P, dp, C.c_int, dp, dp, dp, ip, dp, B, dp]
+        L.orc_si_stencils.argtypes = [C.c_int, C.c_int, up, C.c_int, dp, dp, C.c_int, ip, dp]
+        L.orc_si_stencils.restype = C.c_int
         L.orc_si_nodes.argtypes = [C.c_int, C.c_int, up, C.c_int, dp, dp, ip]
         L.orc_si_nodes.restype = C.c_int
         L.orc_step.argtypes = [P, dp, dp, dp, up, B, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_void_p]
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_void_p]
         L.orc_init_fields.argtypes = [P, dp, dp, dp, dp]
         L.orc_mask_disk.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, up]
         L.orc_mask_disk.restype = C.c_int
@@ -111,6 +113,17 @@ def mask_polygon(nx, ny, xy):
     return m
 
 
+def si_stencils(solid, xy, nrm, rule=0):
+    """(node4, w4, missing): up to 4 stencil nodes and weights per point."""
+    ny, nx = solid.shape
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    nrm = np.ascontiguousarray(nrm, dtype=np.float64)
+    node4 = np.zeros(4 * len(xy), np.int32)
+    w4 = np.zeros(4 * len(xy))
+    missing = lib().orc_si_stencils(nx, ny, np.ascontiguousarray(solid), len(xy), xy, nrm, int(rule), node4, w4)
+    return node4, w4, missing
+
+
 def si_nodes(solid, xy, nrm):
     ny, nx = solid.shape
     xy = np.ascontiguousarray(xy, dtype=np.float64)
@@ -124,7 +137,8 @@ class RefLattice:
     """Oracle lattice: f stored as ft[y, x, a] (post-collision), float64."""
 
     def __init__(self, nx, ny, tau, eta, rho0=1.0, west=(PERIODIC, 0.0, 0.0), east=(PERIODIC, 0.0, 0.0),
-                 south=(PERIODIC, 0.0, 0.0), north=(PERIODIC, 0.0, 0.0), gx=0.0, gy=0.0, trt_lambda=0.0):
+                 south=(PERIODIC, 0.0, 0.0), north=(PERIODIC, 0.0, 0.0), gx=0.0, gy=0.0, trt_lambda=0.0,
+                 si_rule=0):
         self.p = _Params()
         self.p.nx, self.p.ny, self.p.tau, self.p.eta, self.p.rho0 = nx, ny, tau, eta, rho0
         for i, e in enumerate((west, east, south, north)):
@@ -145,7 +159,8 @@ class RefLattice:
         self.grav = (0.0, 0.0)
         self.source = 0
         self.si_body = None  # body-frame points when the body moves
-        self.si_xy = self.si_n = self.si_ds = self.si_node = None
+        self.si_xy = self.si_n = self.si_ds = self.si_node = self.si_node4 = self.si_w4 = None
+        self.si_rule = si_rule
         self.rho = self.ux = self.uy = None
         self.hist_me = []
         self.hist_si = []
@@ -155,7 +170,7 @@ class RefLattice:
     def from_case(cls, case):
         e = lambda E: (E.kind, E.ux, E.uy)
         lat = cls(case.nx, case.ny, case.tau, case.eta, case.rho0, e(case.west), e(case.east),
-                  e(case.south), e(case.north), case.gx, case.gy, case.trt_lambda)
+                  e(case.south), e(case.north), case.gx, case.gy, case.trt_lambda, case.si_rule)
         if case.disk is not None:
             lat.set_disk(*case.disk)
         elif case.polygon is not None:
@@ -242,10 +257,11 @@ class RefLattice:
     def _select_si(self):
         if self.si_xy is None:
             return
-        node, missing = si_nodes(self.solid, self.si_xy, self.si_n)
+        node4, w4, missing = si_stencils(self.solid, self.si_xy, self.si_n, self.si_rule)
         if missing:
             raise RuntimeError(f"{missing} stress-integration points have no fluid sample node")
-        self.si_node = node
+        self.si_node4, self.si_w4 = node4, w4
+        self.si_node = np.unique(node4[node4 >= 0])  # every node a stencil reads
 
     # -- state ----------------------------------------------------------------
     def init_uniform(self, rho, ux, uy):
@@ -278,7 +294,7 @@ class RefLattice:
             si = np.zeros(3)
             npts = 0 if self.si_xy is None else len(self.si_xy)
             L.orc_step(C.byref(self.p), self.ft, self.fw, self.fn, self.solid, C.byref(self.body), npts,
-                       _ptr(self.si_xy), _ptr(self.si_n), _ptr(self.si_ds), _ptr(self.si_node),
+                       _ptr(self.si_xy), _ptr(self.si_n), _ptr(self.si_ds), _ptr(self.si_node4), _ptr(self.si_w4),
                        self.rho.ctypes.data, self.ux.ctypes.data, self.uy.ctypes.data, me, si.ctypes.data)
             self.ft, self.fn = self.fn, self.ft
             self.hist_me.append(me)

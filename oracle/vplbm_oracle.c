@@ -270,15 +270,21 @@ void orc_node_stress(const orc_params *p, const double f[Q], double s[3]) {
 }
 
 /* F = sum_i S_i sigma(x_i) . n_i,  T = sum_i S_i r_i x sigma(x_i) . n_i
- * (Eq. defFf and its discrete form), sigma taken at each point's sample node
- * node[i] (index y*nx + x, chosen by orc_si_nodes). */
+ * (Eq. defFf and its discrete form).  sigma(x_i) is the weighted sum of the
+ * stresses of the point's stencil: up to 4 nodes node4[4i..4i+3] (index
+ * y*nx + x, -1 = unused) with weights w4 (see orc_si_stencils). */
 void orc_stress_integration(const orc_params *p, const double *f, int npts, const double *xy,
-                            const double *nrm, const double *ds, const int *node,
+                            const double *nrm, const double *ds, const int *node4, const double *w4,
                             const orc_body *b, double out[3]) {
   double Fx = 0.0, Fy = 0.0, T = 0.0;
   for (int i = 0; i < npts; ++i) {
-    double s[3];
-    orc_node_stress(p, &f[(size_t)node[i] * Q], s);
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 4; ++k) {
+      if (node4[4 * i + k] < 0) continue;
+      double sk[3];
+      orc_node_stress(p, &f[(size_t)node4[4 * i + k] * Q], sk);
+      for (int m = 0; m < 3; ++m) s[m] += w4[4 * i + k] * sk[m];
+    }
     double nx_ = nrm[2 * i], ny_ = nrm[2 * i + 1];
     double tx = ds[i] * (s[0] * nx_ + s[1] * ny_);
     double ty = ds[i] * (s[1] * nx_ + s[2] * ny_);
@@ -331,6 +337,48 @@ int orc_si_nodes(int nx, int ny, const uint8_t *solid, int npts, const double *x
   return missing;
 }
 
+/* Stencil of each integration point, as (node, weight) pairs.
+ *  rule 0 -- the paper's extrapolation from the closest fluid node in the
+ *            direction close to n: one node (orc_si_nodes), weight 1;
+ *  rule 1 -- interpolation: the stress at p_i = x_i + 1.5 n_i, bilinear in
+ *            the 4 nodes around p_i; when one of them is solid or outside the
+ *            lattice the point falls back to rule 0.
+ * Unused entries have node -1 and weight 0.  Returns the number of points
+ * without a sample node. */
+int orc_si_stencils(int nx, int ny, const uint8_t *solid, int npts, const double *xy,
+                    const double *nrm, int rule, int *node4, double *w4) {
+  int missing = 0;
+  for (int i = 0; i < npts; ++i) {
+    for (int k = 0; k < 4; ++k) {
+      node4[4 * i + k] = -1;
+      w4[4 * i + k] = 0.0;
+    }
+    if (rule == 1) {
+      double px = xy[2 * i] + 1.5 * nrm[2 * i], py = xy[2 * i + 1] + 1.5 * nrm[2 * i + 1];
+      int i0 = (int)floor(px), j0 = (int)floor(py);
+      double fx = px - i0, fy = py - j0;
+      int ok = i0 >= 0 && j0 >= 0 && i0 + 1 < nx && j0 + 1 < ny;
+      for (int k = 0; k < 4 && ok; ++k) {
+        int X = i0 + (k & 1), Y = j0 + (k >> 1);
+        if (solid[(size_t)Y * nx + X]) ok = 0;
+      }
+      if (ok) {
+        for (int k = 0; k < 4; ++k) {
+          int X = i0 + (k & 1), Y = j0 + (k >> 1);
+          node4[4 * i + k] = Y * nx + X;
+          w4[4 * i + k] = ((k & 1) ? fx : 1.0 - fx) * ((k >> 1) ? fy : 1.0 - fy);
+        }
+        continue;
+      }
+    }
+    int node;
+    missing += orc_si_nodes(nx, ny, solid, 1, &xy[2 * i], &nrm[2 * i], &node);
+    node4[4 * i] = node;
+    w4[4 * i] = node >= 0 ? 1.0 : 0.0;
+  }
+  return missing;
+}
+
 /* ------------------------------------------------------------------------ */
 /* one full step                                                              */
 /* ------------------------------------------------------------------------ */
@@ -342,14 +390,15 @@ int orc_si_nodes(int nx, int ny, const uint8_t *solid, int npts, const double *x
  * me/si  : forces of step n (ME of ft^{n-1}, SI of f^n); si may be NULL.  */
 int orc_step(const orc_params *p, const double *ft_prev, double *f_work, double *ft_next,
              const uint8_t *solid, const orc_body *b, int npts, const double *si_xy,
-             const double *si_n, const double *si_ds, const int *si_node, double *rho_out,
+             const double *si_n, const double *si_ds, const int *si_node4, const double *si_w4,
+             double *rho_out,
              double *ux_out, double *uy_out, double me[3], double si[3]) {
   int nx = p->nx, ny = p->ny;
   orc_momentum_exchange(p, ft_prev, solid, b, me);
   orc_stream(p, ft_prev, f_work);
   if (si) {
     if (npts > 0)
-      orc_stress_integration(p, f_work, npts, si_xy, si_n, si_ds, si_node, b, si);
+      orc_stress_integration(p, f_work, npts, si_xy, si_n, si_ds, si_node4, si_w4, b, si);
     else
       si[0] = si[1] = si[2] = 0.0;
   }

@@ -80,7 +80,8 @@ struct Ctl {
   int err;             // bit 0: a point without sample node
   long long step;      // steps completed since initialization
   double last[6];      // forces of the last step: ME (Fx, Fy, T), SI (Fx, Fy, T)
-  int mode, shape, source, pad;
+  int mode, shape, source;
+  int si_rule;         // 0: nearest fluid node along n; 1: interpolated at x + 1.5 n
   double r;            // disk radius
   double mass, inertia, gx, gy, buoy;
   long long fq[3];     // disk centre / radius on the 1/4096 grid (mask of the current state)

@@ -189,6 +189,36 @@ __device__ __forceinline__ int si_node(const uint8_t *__restrict__ mask, int nx,
   return -1;
 }
 
+// Stencil of an integration point: rule 0, the sample node above with weight
+// 1; rule 1, the bilinear interpolation at p = x + 1.5 n over the 4 nodes
+// around p when all are fluid and inside the lattice (rule 0 otherwise).
+// Returns the number of (node, weight) pairs, 0 when there is no sample node.
+// The interpolation point is formed without FMA contraction so the floor()
+// decisions match a plain evaluation.
+__device__ __forceinline__ int si_stencil(const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
+                                          int rule, double px, double py, double n0, double n1, int (&node)[4],
+                                          double (&w)[4]) {
+  if (rule == 1) {
+    const double qx = __dadd_rn(px, __dmul_rn(1.5, n0)), qy = __dadd_rn(py, __dmul_rn(1.5, n1));
+    const int i0 = (int)floor(qx), j0 = (int)floor(qy);
+    if (i0 >= 0 && j0 >= 0 && i0 + 1 < nx && j0 + 1 < ny) {
+      const double fx = __dsub_rn(qx, (double)i0), fy = __dsub_rn(qy, (double)j0);
+      bool ok = true;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int X = i0 + (k & 1), Y = j0 + (k >> 1);
+        node[k] = Y * nx + X;
+        if (mask[(long long)Y * pitch + X] & M_SOLID) ok = false;
+        w[k] = __dmul_rn((k & 1) ? fx : __dsub_rn(1.0, fx), (k >> 1) ? fy : __dsub_rn(1.0, fy));
+      }
+      if (ok) return 4;
+    }
+  }
+  node[0] = si_node(mask, nx, ny, pitch, px, py, n0, n1);
+  w[0] = 1.0;
+  return node[0] >= 0 ? 1 : 0;
+}
+
 // world position and normal of point i (points of a moving body are kept in
 // the body frame and placed with the current state)
 __device__ __forceinline__ void si_world(const double *__restrict__ pts, int maxp, int i, int moving,
@@ -243,33 +273,37 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
   __shared__ int missing;
   const int npts = ctl->npts;
   const int moving = ctl->si_moving;
+  const int rule = ctl->si_rule;
+  const int per_pt = rule == 1 ? 4 : 1;  // stencil entries per point
   const BodyDev B = ctl->body;
-  int N = 2;
-  while (N < npts) N <<= 1;
+  const int nent = npts * per_pt;
+  int N = 4;  // >= per_pt, so every key slot below is written
+  while (N < nent) N <<= 1;
   if (threadIdx.x == 0) {
     bb[0] = nx; bb[1] = ny; bb[2] = -1; bb[3] = -1;
     missing = 0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < N; i += SI_NT) {
-    unsigned long long k = ~0ull;
+  // one key (node, entry) per stencil entry; entry = point * per_pt + k
+  for (int i = threadIdx.x; i < N / per_pt; i += SI_NT) {
+    unsigned long long kk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     if (i < npts) {
       double px, py, n0, n1;
       si_world(pts, maxp, i, moving, B, px, py, n0, n1);
-      const int node = si_node(mask, nx, ny, pitch, px, py, n0, n1);
-      if (node >= 0) {
-        k = ((unsigned long long)(unsigned)node << 32) | (unsigned)i;
-        const int X = node % nx, Y = node / nx;
+      int node[4];
+      double w[4];
+      const int c = si_stencil(mask, nx, ny, pitch, rule, px, py, n0, n1, node, w);
+      if (c == 0) atomicAdd(&missing, 1);
+      for (int k = 0; k < c; ++k) {
+        kk[k] = ((unsigned long long)(unsigned)node[k] << 32) | (unsigned)(i * per_pt + k);
+        const int X = node[k] % nx, Y = node[k] / nx;
         atomicMin(&bb[0], X);
         atomicMin(&bb[1], Y);
         atomicMax(&bb[2], X);
         atomicMax(&bb[3], Y);
-      } else {
-        atomicAdd(&missing, 1);
-        k = (0xFFFFFFFFull << 32) | (unsigned)i;
       }
     }
-    key[i] = k;
+    for (int k = 0; k < per_pt; ++k) key[i * per_pt + k] = kk[k];
   }
   __syncthreads();
   // bitonic sort of (node, point) keys
@@ -302,10 +336,14 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
     if (node == 0xFFFFFFFFu || (j > 0 && (unsigned)(key[j - 1] >> 32) == node)) continue;
     double ax = 0.0, ay = 0.0, txx = 0.0, txy = 0.0, tyy = 0.0;
     for (int k = j; k < N && (unsigned)(key[k] >> 32) == node; ++k) {
-      const int i = (int)(key[k] & 0xFFFFFFFFu);
+      const int e = (int)(key[k] & 0xFFFFFFFFu);
+      const int i = e / per_pt;
       double px, py, n0, n1;
       si_world(pts, maxp, i, moving, B, px, py, n0, n1);
-      const double s = pts[4 * maxp + i];
+      int nd[4];
+      double w[4];
+      si_stencil(mask, nx, ny, pitch, rule, px, py, n0, n1, nd, w);
+      const double s = pts[4 * maxp + i] * w[e % per_pt];
       const double rx = px - B.x, ry = py - B.y;
       ax += s * n0;
       ay += s * n1;
@@ -470,41 +508,49 @@ __global__ void __launch_bounds__(SI_NT)
             const double *__restrict__ pts, int maxp, int npts, double *__restrict__ out) {
   using T = typename Store<S>::T;
   const BodyDev B = ctl->body;
+  const int rule = ctl->si_rule;
   double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < npts; i += SI_NT) {
     const double px = pts[i], py = pts[maxp + i], n0 = pts[2 * maxp + i], n1 = pts[3 * maxp + i];
     const double s = pts[4 * maxp + i];
-    const int node = si_node(mask, P.nx, P.ny, P.pitch, px, py, n0, n1);
-    if (node < 0) {
+    int nodes[4];
+    double wts[4];
+    const int cnt = si_stencil(mask, P.nx, P.ny, P.pitch, rule, px, py, n0, n1, nodes, wts);
+    if (cnt == 0) {
       v[5] += 1.0;  // counts points without a sample node
       continue;
     }
-    const int x = node % P.nx, y = node / P.nx;
-    double d[Q];
+    double sxx = 0.0, sxy = 0.0, syy = 0.0;
+    for (int q = 0; q < cnt; ++q) {
+      const int x = nodes[q] % P.nx, y = nodes[q] / P.nx;
+      double d[Q];
 #pragma unroll
-    for (int a = 0; a < Q; ++a) d[a] = double(pull_edge<S, T>(fin, P, x, y, a, cx(a), cy(a)));
-    double drho = 0.0, mx = 0.0, my = 0.0;
+      for (int a = 0; a < Q; ++a) d[a] = double(pull_edge<S, T>(fin, P, x, y, a, cx(a), cy(a)));
+      double drho = 0.0, mx = 0.0, my = 0.0;
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-      drho += d[a];
-      mx += cx(a) * d[a];
-      my += cy(a) * d[a];
+      for (int a = 0; a < Q; ++a) {
+        drho += d[a];
+        mx += cx(a) * d[a];
+        my += cy(a) * d[a];
+      }
+      const double rho = P.rho0d + drho;
+      const double ux = (mx + 0.5 * double(P.gx)) / rho, uy = (my + 0.5 * double(P.gy)) / rho;
+      const double uu = 1.5 * (ux * ux + uy * uy);
+      double pxx = 0.0, pxy = 0.0, pyy = 0.0;
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        const double cu = cx(a) * ux + cy(a) * uy;
+        const double deq = wgt(a) * drho + wgt(a) * rho * (3.0 * cu + 4.5 * cu * cu - uu);
+        const double ne = d[a] - deq;
+        pxx += cx(a) * cx(a) * ne;
+        pxy += cx(a) * cy(a) * ne;
+        pyy += cy(a) * cy(a) * ne;
+      }
+      const double pr = drho / 3.0;
+      sxx += wts[q] * (-pr - P.facd * pxx);
+      sxy += wts[q] * (-P.facd * pxy);
+      syy += wts[q] * (-pr - P.facd * pyy);
     }
-    const double rho = P.rho0d + drho;
-    const double ux = (mx + 0.5 * double(P.gx)) / rho, uy = (my + 0.5 * double(P.gy)) / rho;
-    const double uu = 1.5 * (ux * ux + uy * uy);
-    double pxx = 0.0, pxy = 0.0, pyy = 0.0;
-#pragma unroll
-    for (int a = 1; a < Q; ++a) {
-      const double cu = cx(a) * ux + cy(a) * uy;
-      const double deq = wgt(a) * drho + wgt(a) * rho * (3.0 * cu + 4.5 * cu * cu - uu);
-      const double ne = d[a] - deq;
-      pxx += cx(a) * cx(a) * ne;
-      pxy += cx(a) * cy(a) * ne;
-      pyy += cy(a) * cy(a) * ne;
-    }
-    const double pr = drho / 3.0;
-    const double sxx = -pr - P.facd * pxx, sxy = -P.facd * pxy, syy = -pr - P.facd * pyy;
     const double tx = s * (sxx * n0 + sxy * n1), ty = s * (sxy * n0 + syy * n1);
     v[0] += tx;
     v[1] += ty;

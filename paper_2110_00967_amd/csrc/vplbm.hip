@@ -87,7 +87,8 @@ Layout layout_of(const vplbm_params &p) {
   L.partials = take(2 * ntiles * PART_STRIDE * sizeof(double));  // two buffers, by step parity
   L.hist = take((size_t)cap * 6 * sizeof(double));
   L.ctl = take(sizeof(Ctl));
-  L.recs = take((size_t)maxp * sizeof(SiRec));
+  // one record per distinct sample node: up to 4 per point with the interpolated rule
+  L.recs = take((size_t)maxp * (p.si_rule == 1 ? 4 : 1) * sizeof(SiRec));
   L.pts = take((size_t)5 * maxp * sizeof(double));
   L.verts = take((size_t)2 * maxv * sizeof(long long));
   L.staging = take(STAGE_DOUBLES * sizeof(double));
@@ -119,6 +120,9 @@ const char *check_params(const vplbm_params *p) {
   if (p->hist_capacity < 0 || p->max_si_points < 0 || p->max_vertices < 0)
     return "capacities must be >= 0";
   if (p->max_si_points > SI_MAX) return "max_si_points exceeds 4096";
+  if (p->si_rule != 0 && p->si_rule != 1) return "si_rule must be 0 or 1";
+  if (p->si_rule == 1 && (p->max_si_points == 0 || p->max_si_points > SI_MAX / 4))
+    return "si_rule 1 needs max_si_points in 1..1024";
   const long long pitch = pitch_of(*p);
   if (9LL * p->ny * pitch >= (1LL << 31)) return "lattice too large (9*ny*pitch must be < 2^31)";
   return nullptr;
@@ -493,6 +497,7 @@ int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *h
   Ctl c{};
   c.mode = MODE_STATIC;
   c.shape = SHAPE_NONE;
+  c.si_rule = p->si_rule;
   int rc = reset_geometry(L, c);
   if (!rc) rc = L->ctl_push(c);
   if (!rc) rc = launch_init(L, 0, L->p.ny, nullptr, nullptr, nullptr, p->rho0, 0.0, 0.0);

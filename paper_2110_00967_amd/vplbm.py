@@ -53,7 +53,8 @@ class Params(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("tau", C.c_double), ("eta", C.c_double),
                 ("rho0", C.c_double), ("precision", C.c_int), ("west", Edge), ("east", Edge),
                 ("south", Edge), ("north", Edge), ("hist_capacity", C.c_int),
-                ("max_si_points", C.c_int), ("max_vertices", C.c_int), ("trt_lambda", C.c_double)]
+                ("max_si_points", C.c_int), ("max_vertices", C.c_int), ("trt_lambda", C.c_double),
+                ("si_rule", C.c_int)]
 
 
 class BodyState(C.Structure):
@@ -134,7 +135,7 @@ def _f64(a, shape=None):
 
 def make_params(nx, ny, tau, eta, rho0=1.0, precision="f32", west=(PERIODIC, 0, 0), east=(PERIODIC, 0, 0),
                 south=(PERIODIC, 0, 0), north=(PERIODIC, 0, 0), hist_capacity=0, max_si_points=0,
-                max_vertices=0, trt_lambda=0.0) -> Params:
+                max_vertices=0, trt_lambda=0.0, si_rule=0) -> Params:
     p = Params()
     p.nx, p.ny, p.tau, p.eta, p.rho0 = int(nx), int(ny), float(tau), float(eta), float(rho0)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -142,6 +143,7 @@ def make_params(nx, ny, tau, eta, rho0=1.0, precision="f32", west=(PERIODIC, 0, 
         setattr(p, name, Edge(int(e[0]), float(e[1]), float(e[2])))
     p.hist_capacity, p.max_si_points, p.max_vertices = hist_capacity, max_si_points, max_vertices
     p.trt_lambda = float(trt_lambda)
+    p.si_rule = int(si_rule)
     return p
 
 
@@ -186,7 +188,7 @@ class Lattice:
         nv = 0 if case.polygon is None else len(case.polygon)
         p = make_params(case.nx, case.ny, case.tau, case.eta, case.rho0, precision, e(case.west), e(case.east),
                         e(case.south), e(case.north), max_si_points=max(npts, 16), max_vertices=max(nv, 16),
-                        trt_lambda=case.trt_lambda, **kw)
+                        trt_lambda=case.trt_lambda, si_rule=getattr(case, "si_rule", 0), **kw)
         lat = cls(p)
         if case.gx or case.gy:
             lat.set_body_force(case.gx, case.gy)

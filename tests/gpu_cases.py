@@ -20,7 +20,7 @@ def say(*a):
 
 
 def spec(nx, ny, tau=0.7, eta=1e-4, edges=((P, 0, 0),) * 4, **kw):
-    d = dict(nx=nx, ny=ny, tau=tau, eta=eta, edges=edges, rho0=1.0, gx=0.0, gy=0.0, trt=0.0, disk=None,
+    d = dict(nx=nx, ny=ny, tau=tau, eta=eta, edges=edges, rho0=1.0, gx=0.0, gy=0.0, trt=0.0, si_rule=0, disk=None,
              polygon=None, ref=None, mask=None, si=None, motion=None, dynamics=None, init=("uniform", 1.0, 0.0, 0.0))
     d.update(kw)
     return d
@@ -35,7 +35,7 @@ def random_fields(nx, ny, seed, amp=0.03):
 def build_oracle(s):
     e = s["edges"]
     lat = O.RefLattice(s["nx"], s["ny"], s["tau"], s["eta"], s["rho0"], e[0], e[1], e[2], e[3], s["gx"], s["gy"],
-                       s["trt"])
+                       s["trt"], s["si_rule"])
     _setup(lat, s, oracle=True)
     return lat
 
@@ -45,7 +45,7 @@ def build_gpu(s, precision="f64", **kw):
     e = s["edges"]
     npts = 0 if s["si"] is None else len(s["si"][2])
     p = V.make_params(s["nx"], s["ny"], s["tau"], s["eta"], s["rho0"], precision, e[0], e[1], e[2], e[3],
-                      max_si_points=max(16, npts), trt_lambda=s["trt"], **kw)
+                      max_si_points=max(16, npts), trt_lambda=s["trt"], si_rule=s["si_rule"], **kw)
     lat = V.Lattice(p)
     if s["gx"] or s["gy"]:
         lat.set_body_force(s["gx"], s["gy"])

@@ -63,10 +63,18 @@ def test_required_bytes_valid():
     dict(eta=-1.0), dict(eta=float("nan")), dict(precision=7), dict(west=(V.PERIODIC, 0, 0)),
     dict(south=(V.VELOCITY, 0, 0)), dict(north=(9, 0, 0)), dict(east=(V.VELOCITY, float("inf"), 0)),
     dict(nx=200000, ny=200000), dict(max_si_points=5000), dict(hist_capacity=-1),
-    dict(trt_lambda=-0.1), dict(trt_lambda=float("nan")), dict(nx=20000),
+    dict(trt_lambda=-0.1), dict(trt_lambda=float("nan")), dict(nx=20000), dict(si_rule=2), dict(si_rule=-1),
+    dict(si_rule=1, max_si_points=1025), dict(si_rule=1, max_si_points=0),
 ])
 def test_required_bytes_rejects(kw):
     assert V.required_bytes(base(**kw)) == 0
+
+
+def test_si_rule_interpolated_accepts_up_to_1024_points():
+    n1 = V.required_bytes(base(si_rule=1, max_si_points=1024))
+    n0 = V.required_bytes(base(si_rule=0, max_si_points=1024))
+    # room for 4 sample records (48 bytes each) per point instead of 1
+    assert n1 - n0 >= 3 * 1024 * 48
 
 
 def test_eta_infinite_is_allowed():

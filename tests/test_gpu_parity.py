@@ -85,6 +85,12 @@ RAGGED["trt_walls_force_random"] = spec(133, 41, tau=0.7, eta=1e-3, trt=3.0 / 16
                                        edges=((P, 0, 0), (P, 0, 0), (V_, 0, 0), (V_, 0.01, 0)), gx=2e-6,
                                        disk=(60.2, 20.7, 7.4), si=W.disk_si_points(60.2, 20.7, 7.4, 40),
                                        init=("fields",) + random_fields(133, 41, 23, amp=0.02))
+RAGGED["si_interpolated_disk_random"] = spec(150, 45, tau=0.65, si_rule=1, disk=(70.3, 21.6, 9.2),
+                                             si=W.disk_si_points(70.3, 21.6, 9.2, 72),
+                                             init=("fields",) + random_fields(150, 45, 3))
+RAGGED["si_interpolated_naca"] = spec(150, 75, tau=0.56, si_rule=1,
+                                      edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)),
+                                      polygon=_poly, ref=_ref, si=_si, init=("uniform", 1.0, 0.05, 0.0))
 _m = np.zeros((45, 77), np.uint8)
 _m[0:6, :] = 1
 _m[20:30, 10:14] = 1
@@ -112,11 +118,13 @@ def test_ragged_cases_fp64(name):
         assert np.array_equal((g.mask().ravel() & 0x40) != 0, sample), name
 
 
-@pytest.mark.parametrize("source", [0, 1])
-def test_free_disk_sedimentation_fp64(source):
+@pytest.mark.parametrize("source,rule", [(0, 0), (1, 0), (1, 1)])
+def test_free_disk_sedimentation_fp64(source, rule):
+    import dataclasses
     case = W.case_sedimentation(nx=80, ny=200, d=12.0, g=2e-4, y0=150.0, steps=300, npts=48,
                                 force_source=source)
-    say("sedimentation 80x200 fp64 source", source)
+    case = dataclasses.replace(case, si_rule=rule)
+    say("sedimentation 80x200 fp64 source", source, "si rule", rule)
     from gpu_cases import O
     from paper_2110_00967_amd import vplbm as V
     o = O.RefLattice.from_case(case)
@@ -145,9 +153,11 @@ def test_prescribed_motion_galilean_fp64():
     assert abs(g.body_state()[0] - (20.0 + 60 * U[0])) < 1e-12
 
 
-def test_si_at_matches_registered_points():
-    case = W.case_disk_channel(steps=200)
-    say("forces_si_at on the disk channel")
+@pytest.mark.parametrize("rule", [0, 1])
+def test_si_at_matches_registered_points(rule):
+    import dataclasses
+    case = dataclasses.replace(W.case_disk_channel(steps=200), si_rule=rule)
+    say("forces_si_at on the disk channel, si rule", rule)
     from gpu_cases import O
     from paper_2110_00967_amd import vplbm as V
     g = V.Lattice.from_case(case, precision="f64")

@@ -207,3 +207,60 @@ def test_newton_euler_constant_force_and_torque():
         O.lib().orc_body_update(C.byref(b), np.array([F, 0.0, T]), m, inertia, 1.0, 2.0, 0.0, 0.0)
         assert abs(b.x - F / m * n * (n + 1) / 2) <= 1e-14
         assert abs(b.theta - T / inertia * n * (n + 1) / 2) <= 1e-14
+
+
+# ---------------------------------------------------------------------------
+# interpolated stress-integration stencil (rule 1)
+# ---------------------------------------------------------------------------
+
+def test_si_interpolated_poiseuille_shear_exact():
+    # sigma_xy is linear in y: bilinear interpolation at p = x + 1.5 n is exact
+    G, ny, nx = 1e-6, 16, 6
+    nu = (MAGIC_TAU - 0.5) / 3
+    lat = O.RefLattice(nx, ny, MAGIC_TAU, float("inf"), south=(O.VELOCITY, 0, 0), north=(O.VELOCITY, 0, 0),
+                       gx=G, si_rule=1)
+    y0 = 2.3
+    xy = np.array([[x + 0.37, y0] for x in range(nx - 1)], float)
+    n = np.tile([0.0, 1.0], (len(xy), 1))
+    lat.set_si_points(xy, n, np.ones(len(xy)))
+    assert (lat.si_node4.reshape(-1, 4) >= 0).all()  # every point interpolates
+    lat.init_uniform(1.0, 0.0, 0.0)
+    lat.step(int(30 * ny * ny / nu))
+    yp = y0 + 1.5
+    ref = len(xy) * G / 2 * (ny - 1 - 2 * yp)
+    assert abs(lat.hist_si[-1][0] - ref) <= 1e-9 * abs(ref)
+
+
+def test_si_interpolated_stencil_properties():
+    nx = ny = 40
+    xc, yc, r = 19.6, 20.3, 7.7
+    solid = O.mask_disk(nx, ny, xc, yc, r)
+    xy, n, ds = W.disk_si_points(xc, yc, r, 96)
+    node4, w4, missing = O.si_stencils(solid, xy, n, rule=1)
+    assert missing == 0
+    node4, w4 = node4.reshape(-1, 4), w4.reshape(-1, 4)
+    ninterp = 0
+    for (px, py), (nx_, ny_), nd, w in zip(xy, n, node4, w4):
+        used = nd >= 0
+        assert abs(w.sum() - 1.0) <= 1e-14 and (w >= 0).all()
+        assert all(solid[k // nx, k % nx] == 0 for k in nd[used])
+        if used.sum() == 4:
+            ninterp += 1
+            qx, qy = px + 1.5 * nx_, py + 1.5 * ny_
+            X, Y = nd % nx, nd // nx
+            assert X.min() <= qx <= X.max() and Y.min() <= qy <= Y.max()
+            # the weights reproduce p itself (bilinear interpolation of x and y)
+            assert abs((w * X).sum() - qx) <= 1e-12 and abs((w * Y).sum() - qy) <= 1e-12
+    assert ninterp >= 80  # most points clear the surface at 1.5 cells
+
+
+def test_si_interpolated_zero_force_uniform_flow():
+    U = (0.04, -0.015)
+    lat = O.RefLattice(48, 40, 0.7, float("inf"), si_rule=1)
+    lat.set_disk(23.3, 19.6, 8.4)
+    xy, n, ds = W.disk_si_points(23.3, 19.6, 8.4, 96)
+    lat.set_si_points(xy, n, ds)
+    one = np.ones((lat.ny, lat.nx))
+    lat.set_fields(one, U[0] * one, U[1] * one)
+    lat.step(10)
+    assert np.abs(lat.si()).max() <= 1e-13

@@ -69,6 +69,7 @@ class Case:
     grav: tuple = (0.0, 0.0)
     force_source: int = 0
     trt_lambda: float = 0.0  # > 0: TRT collision with this magic parameter
+    si_rule: int = 0  # stress-integration stencil: 0 nearest fluid node along n, 1 interpolated
     length_scale: float = 1.0  # chord or diameter for coefficients
     u_ref: float = 0.0
 
