@@ -47,22 +47,69 @@ enum { MODE_STATIC = 0, MODE_PRESCRIBED = 1, MODE_FREE = 2 };
 enum { SHAPE_NONE = 0, SHAPE_DISK = 1, SHAPE_POLYGON = 2, SHAPE_MASK = 3 };
 
 // storage of the deviations d_a = f_a - w_a rho0
+// Store of v at the global-memory address base + bytes, base uniform.  The
+// empty asm makes the optimizer take the base as it is, so each plane's
+// store stays "scalar base + 32-bit lane offset" instead of being re-derived
+// from the previous plane's address with 64-bit vector arithmetic.
+#define VP_GLOBAL __attribute__((address_space(1)))
+template <typename U> __device__ __forceinline__ void st_global(const void *base, uint32_t bytes, U v) {
+  asm volatile("" : "+s"(base));
+  *(VP_GLOBAL U *)((VP_GLOBAL const char *)base + bytes) = v;
+}
+
 template <typename S> struct Store;
 template <> struct Store<double> {
   using T = double;
   static __device__ __forceinline__ double ld(const double *p) { return *p; }
   static __device__ __forceinline__ void st(double *p, double v) { *p = v; }
+  static __device__ __forceinline__ void st_at(double *base, uint32_t bytes, double v) {
+    st_global<double>(base, bytes, v);
+  }
 };
 template <> struct Store<float> {
   using T = float;
   static __device__ __forceinline__ float ld(const float *p) { return *p; }
   static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+  static __device__ __forceinline__ void st_at(float *base, uint32_t bytes, float v) {
+    st_global<float>(base, bytes, v);
+  }
 };
 template <> struct Store<__half> {
   using T = float;
   static __device__ __forceinline__ float ld(const __half *p) { return __half2float(*p); }
   static __device__ __forceinline__ void st(__half *p, float v) { *p = __float2half_rn(v); }
+  static __device__ __forceinline__ void st_at(__half *base, uint32_t bytes, float v) {
+    st_global<unsigned short>(base, bytes, __half_as_ushort(__float2half_rn(v)));
+  }
 };
+
+// p advanced by a 32-bit byte offset (scalar base + per-lane offset addressing)
+template <typename S> __device__ __forceinline__ S *at(S *p, uint32_t bytes) {
+  return (S *)((char *)p + bytes);
+}
+template <typename S> __device__ __forceinline__ const S *at(const S *p, uint32_t bytes) {
+  return (const S *)((const char *)p + bytes);
+}
+
+
+// c_a . (vx, vy) with the zero and unit components of c_a folded away
+// (exactly the same value as the full dot product for finite inputs)
+template <typename T> __device__ __forceinline__ T dotc(int a, T vx, T vy) {
+  const int X = cx(a), Y = cy(a);
+  if (X == 0 && Y == 0) return T(0);
+  if (X == 0) return Y > 0 ? vy : -vy;
+  if (Y == 0) return X > 0 ? vx : -vx;
+  return (X > 0 ? vx : -vx) + (Y > 0 ? vy : -vy);
+}
+
+// 1/x.  FP32: the hardware reciprocal (1 ulp, not unbiased) refined by one
+// Newton step r' = r + r (1 - x r), which removes the bias that would
+// otherwise drift momentum over thousands of steps.  FP64: division.
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 struct BodyDev {
   double x, y, theta, u, v, omega;

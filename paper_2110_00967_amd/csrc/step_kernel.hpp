@@ -33,47 +33,76 @@ template <typename T> struct StepArgs {
   int nx, ny, pitch;
   long long plane;      // ny * pitch
   int tiles_x, ntiles, per_xcd;
+  unsigned tx_magic;    // floor(2^32 / tiles_x) + 1 (0 when tiles_x = 1)
   int kind[4];          // edge kinds W, E, S, N
   T wu[4][2];           // 6 rho0 u_w of each edge: bounce-back increment w_a c_a . wu
   T omega, fac, kpen, rho0, gx, gy;
+  T khalf, a1, kk;      // penalization in solid cells: k/2, 1/(1 + k/2), k/(1 + k/2)
   int trt;              // 0: BGK; 1: TRT (the kernel is chosen accordingly)
-  T omega_m, fac_m;     // TRT: 1/tau- and 1 - 1/(2 tau-)
+  T omega_m, fac_m;     // TRT: 1/tau- and 1 - 1/(2 tau-) (BGK: the same as omega, fac)
+  T fo, fo9, fo3;       // tau+ - 1/2, 9 (tau+ - 1/2), 3 (tau- - 1/2)
   double facd, rho0d;
 };
 
-// Value of deviation a arriving at (x, y) when x - c_a leaves the lattice:
-// axis by axis, x first; periodic wraps, outflow clamps, free-slip takes the
-// mirrored population of the edge cell itself, velocity bounces back the
-// cell's own opposite population with the moving-wall increment.
+// Value of deviation a arriving at (x, y) (any cell, edge or not): axis by
+// axis, x first, when x - c_a leaves the lattice: periodic wraps, outflow
+// clamps, free-slip takes the mirrored population of the edge cell itself,
+// velocity bounces back the cell's own opposite population with the
+// moving-wall increment (and ends the resolution).  With c_a fixed only one
+// x edge and one y edge can be crossed; the edge kinds are uniform, so the
+// branches below are uniform and the per-lane part is selects, ending in one
+// unconditional load (no load waits inside divergent code).
 template <typename S, typename T>
 __device__ __forceinline__ T pull_edge(const S *__restrict__ fin, const StepArgs<T> &P, int x,
                                        int y, int a, int cxa, int cya) {
   int sx = x - cxa, sy = y - cya, pop = a;
+  bool bb = false;
+  T add = T(0);
   // edge parameters are selected with constant indices only (no dynamic
   // indexing of the by-value argument block, which would spill it)
-  if (sx < 0 || sx >= P.nx) {
-    const bool w = sx < 0;
+  if (cxa != 0) {
+    const bool w = cxa > 0;  // c_x > 0 can only cross the west edge
+    const bool out = w ? sx < 0 : sx >= P.nx;
     const int k = w ? P.kind[WEST] : P.kind[EAST];
-    if (k == EDGE_VELOCITY)
-      return Store<S>::ld(fin + (long long)opp(a) * P.plane + (long long)y * P.pitch + x) +
-             T(wgt(a)) * (w ? T(cxa) * P.wu[WEST][0] + T(cya) * P.wu[WEST][1]
-                            : T(cxa) * P.wu[EAST][0] + T(cya) * P.wu[EAST][1]);
-    if (k == EDGE_PERIODIC) sx = sx < 0 ? sx + P.nx : sx - P.nx;
-    else if (k == EDGE_OUTFLOW) sx = sx < 0 ? 0 : P.nx - 1;
-    else { sx = x; pop = flipx(pop); }
+    if (k == EDGE_VELOCITY) {
+      bb = out;
+      add = out ? T(wgt(a)) * (w ? T(cxa) * P.wu[WEST][0] + T(cya) * P.wu[WEST][1]
+                                 : T(cxa) * P.wu[EAST][0] + T(cya) * P.wu[EAST][1])
+                : T(0);
+    } else if (k == EDGE_PERIODIC) {
+      sx = out ? (w ? sx + P.nx : sx - P.nx) : sx;
+    } else if (k == EDGE_OUTFLOW) {
+      sx = out ? (w ? 0 : P.nx - 1) : sx;
+    } else {
+      pop = out ? flipx(pop) : pop;
+      sx = out ? x : sx;
+    }
   }
-  if (sy < 0 || sy >= P.ny) {
-    const bool s_ = sy < 0;
+  if (cya != 0) {
+    const bool s_ = cya > 0;  // c_y > 0 can only cross the south edge
+    const bool out = s_ ? sy < 0 : sy >= P.ny;
     const int k = s_ ? P.kind[SOUTH] : P.kind[NORTH];
-    if (k == EDGE_VELOCITY)
-      return Store<S>::ld(fin + (long long)opp(a) * P.plane + (long long)y * P.pitch + x) +
-             T(wgt(a)) * (s_ ? T(cxa) * P.wu[SOUTH][0] + T(cya) * P.wu[SOUTH][1]
-                             : T(cxa) * P.wu[NORTH][0] + T(cya) * P.wu[NORTH][1]);
-    if (k == EDGE_PERIODIC) sy = sy < 0 ? sy + P.ny : sy - P.ny;
-    else if (k == EDGE_OUTFLOW) sy = sy < 0 ? 0 : P.ny - 1;
-    else { sy = y; pop = flipy(pop); }
+    if (k == EDGE_VELOCITY) {
+      const bool hit = out && !bb;
+      add = hit ? T(wgt(a)) * (s_ ? T(cxa) * P.wu[SOUTH][0] + T(cya) * P.wu[SOUTH][1]
+                                  : T(cxa) * P.wu[NORTH][0] + T(cya) * P.wu[NORTH][1])
+                : add;
+      bb = bb || out;
+    } else if (k == EDGE_PERIODIC) {
+      sy = out ? (s_ ? sy + P.ny : sy - P.ny) : sy;
+    } else if (k == EDGE_OUTFLOW) {
+      sy = out ? (s_ ? 0 : P.ny - 1) : sy;
+    } else {
+      pop = out ? flipy(pop) : pop;
+      sy = out ? y : sy;
+    }
   }
-  return Store<S>::ld(fin + (long long)pop * P.plane + (long long)sy * P.pitch + sx);
+  if (bb) {  // bounce-back: the cell's own opposite population
+    pop = opp(a);
+    sx = x;
+    sy = y;
+  }
+  return Store<S>::ld(fin + (long long)pop * P.plane + (long long)sy * P.pitch + sx) + add;
 }
 
 template <int NT>
@@ -138,25 +167,32 @@ __device__ __forceinline__ void step_tile(
     typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy) {
   using T = typename Store<S>::T;
   constexpr int NT = BX * BY;
-  const int tx = tile % P.tiles_x, ty = tile / P.tiles_x;
+  // tile / tiles_x by multiply-high (exact while tile * tiles_x < 2^32, which
+  // every accepted lattice satisfies: tiles_x^2 * ny <= 58,255 * pitch < 2^30)
+  const int ty = P.tx_magic ? (int)__umulhi((unsigned)tile, P.tx_magic) : tile;
+  const int tx = tile - ty * P.tiles_x;
   const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
   const int x = tx * BX + lx, y = ty * BY + ly;
 
-  const int wx0 = ctl->win[0] / BX, wy0 = ctl->win[1] / BY;
-  const int wx1 = (ctl->win[2] + BX - 1) / BX, wy1 = (ctl->win[3] + BY - 1) / BY;
-  const bool inwin = tx >= wx0 && tx < wx1 && ty >= wy0 && ty < wy1;
-
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 
+  // Every cell of the tile has all 8 neighbours inside the lattice: the
+  // workgroup-uniform fast path.  A plane holds fewer than 2^31 / 9 cells, so
+  // byte offsets inside one plane fit 32 bits; each population then loads
+  // from (plane base shifted by -c_a, a scalar pointer) + the cell's one
+  // 32-bit byte offset, and stores to its plane base + the same offset.
+  const bool tile_interior = (tx * BX >= 1) & (tx * BX + BX <= P.nx - 1) & (ty * BY >= 1) &
+                             (ty * BY + BY <= P.ny - 1);
+
   if (x < P.nx && y < P.ny) {
-    const long long c = (long long)y * P.pitch + x;
-    const uint8_t m = mask[c];
+    const int c = y * P.pitch + x;
+    const uint32_t cb = (uint32_t)c * (uint32_t)sizeof(S);
+    const uint8_t m = mask[(uint32_t)c];
     T d[Q];
-    const bool interior = (x > 0) & (x < P.nx - 1) & (y > 0) & (y < P.ny - 1);
-    if (interior) {
+    if (tile_interior) {
 #pragma unroll
       for (int a = 0; a < Q; ++a)
-        d[a] = Store<S>::ld(fin + a * P.plane + c - (long long)cy(a) * P.pitch - cx(a));
+        d[a] = Store<S>::ld(at(fin + (long long)a * P.plane - (long long)cy(a) * P.pitch - cx(a), cb));
     } else {
 #pragma unroll
       for (int a = 0; a < Q; ++a) d[a] = pull_edge<S, T>(fin, P, x, y, a, cx(a), cy(a));
@@ -168,84 +204,101 @@ __device__ __forceinline__ void step_tile(
     const T my = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
     const T rho = P.rho0 + drho;
 
-    T k = T(0), usx = T(0), usy = T(0);
+    // penalized velocity (Eq. updatestepm) and force; k = 0 in fluid cells
+    T khalf = T(0), a1 = T(1), kk = T(0), usx = T(0), usy = T(0);
     const bool chi = (m & M_SOLID) != 0;
     if (chi) {
-      k = P.kpen;
+      khalf = P.khalf;
+      a1 = P.a1;
+      kk = P.kk;
       const BodyDev B = ctl->body;
       usx = T(B.u - B.omega * (double(y) - B.y));
       usy = T(B.v + B.omega * (double(x) - B.x));
     }
     const T hx = mx + T(0.5) * P.gx, hy = my + T(0.5) * P.gy;
-    const T den = T(1) / (rho * (T(1) + T(0.5) * k));
-    const T ux = (hx + T(0.5) * k * rho * usx) * den;
-    const T uy = (hy + T(0.5) * k * rho * usy) * den;
-    const T kk = k / (T(1) + T(0.5) * k);
+    const T den = a1 * recip(rho);  // 1 / (rho (1 + k/2))
+    const T ux = (hx + khalf * rho * usx) * den;
+    const T uy = (hy + khalf * rho * usy) * den;
     const T Fx = P.gx - kk * (hx - rho * usx);
     const T Fy = P.gy - kk * (hy - rho * usy);
 
     const T uu15 = T(1.5) * (ux * ux + uy * uy);
     const T uF3 = T(3) * (ux * Fx + uy * Fy);
-    T deq[Q];
-    if constexpr (!TRT) {
-      // BGK
+    {
+      // Collision with the forcing term (Eqs. TRT and eqBd; BGK is tau- =
+      // tau+), per pair (a, a') with c_a' = -c_a.  Since 1 - 1/(2 tau) =
+      // (tau - 1/2) / tau, the forcing term enters as a shift of the
+      // equilibrium, even part by (tau+ - 1/2) F_even and odd part by
+      // (tau- - 1/2) F_odd:
+      //   q_a = wgt_a (De + Do),  q_a' = wgt_a (De - Do),
+      //   De = drho - 1.5 rho u.u - 3 (tau+ - 1/2) u.F
+      //        + (c.u) (4.5 rho (c.u) + 9 (tau+ - 1/2) (c.F)),
+      //   Do = 3 rho (c.u) + 3 (tau- - 1/2) (c.F),
+      // and out = d - (d - q)_even / tau+ - (d - q)_odd / tau-.  The
+      // non-equilibrium part d - q is formed before it is scaled, which
+      // keeps the FP32 rounding of mass and momentum unbiased.
+      const T C1 = drho - rho * uu15 - P.fo * uF3;
+      const T R45 = T(4.5) * rho, R3 = T(3) * rho;
+      Store<S>::st_at(fout, cb, d[0] - P.omega * (d[0] - T(wgt(0)) * C1));
 #pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        const T w = T(wgt(a));
-        const T cu = T(cx(a)) * ux + T(cy(a)) * uy;
-        const T cF = T(cx(a)) * Fx + T(cy(a)) * Fy;
-        deq[a] = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - uu15);
-        const T Fa = w * (T(3) * cF - uF3 + T(9) * cu * cF);
-        const T out = d[a] - P.omega * (d[a] - deq[a]) + P.fac * Fa;
-        Store<S>::st(fout + a * P.plane + c, out);
-      }
-    } else {
-      // TRT (Eq. TRT): even / odd parts of the non-equilibrium and of the
-      // forcing term relax with tau+ / tau-
-      T Fa[Q];
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        const T w = T(wgt(a));
-        const T cu = T(cx(a)) * ux + T(cy(a)) * uy;
-        const T cF = T(cx(a)) * Fx + T(cy(a)) * Fy;
-        deq[a] = w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - uu15);
-        Fa[a] = w * (T(3) * cF - uF3 + T(9) * cu * cF);
-      }
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
+      for (int k = 0; k < 4; ++k) {
+        const int a = k < 2 ? k + 1 : k + 3;  // 1, 2, 5, 6; a' = 3, 4, 7, 8
         const int o = opp(a);
-        const T nep = T(0.5) * ((d[a] - deq[a]) + (d[o] - deq[o]));
-        const T nem = T(0.5) * ((d[a] - deq[a]) - (d[o] - deq[o]));
-        const T out = d[a] - P.omega * nep - P.omega_m * nem + P.fac * (T(0.5) * (Fa[a] + Fa[o])) +
-                      P.fac_m * (T(0.5) * (Fa[a] - Fa[o]));
-        Store<S>::st(fout + a * P.plane + c, out);
+        const T w = T(wgt(a));
+        const T cu = dotc(a, ux, uy);
+        const T cF = dotc(a, Fx, Fy);
+        const T De = cu * (R45 * cu + P.fo9 * cF) + C1;
+        const T Do = R3 * cu + P.fo3 * cF;
+        T oa, oo;
+        if constexpr (!TRT) {
+          oa = d[a] - P.omega * (d[a] - w * (De + Do));
+          oo = d[o] - P.omega * (d[o] - w * (De - Do));
+        } else {
+          const T se = T(0.5) * (d[a] + d[o]) - w * De;
+          const T so = T(0.5) * (d[a] - d[o]) - w * Do;
+          oa = d[a] - P.omega * se - P.omega_m * so;
+          oo = d[o] - P.omega * se + P.omega_m * so;
+        }
+        Store<S>::st_at(fout + (long long)a * P.plane, cb, oa);
+        Store<S>::st_at(fout + (long long)o * P.plane, cb, oo);
       }
     }
     if (MACRO) {
-      mrho[c] = rho;
-      mux[c] = ux;
-      muy[c] = uy;
+      mrho[(uint32_t)c] = rho;
+      mux[(uint32_t)c] = ux;
+      muy[(uint32_t)c] = uy;
     }
 
     if (m & M_IFACE) {
       // momentum exchange: every population pulled across the interface;
-      // the link's interface point is its midpoint seen from its fluid node
+      // the link's interface point is its midpoint seen from its fluid node.
+      // The 8 neighbour masks are loaded first, all at once (a load inside
+      // the divergent loop below would cost one memory round trip per link).
       const BodyDev B = ctl->body;
+      uint8_t nm[Q];
+      bool link[Q];
+      int wsx[Q], wsy[Q];
 #pragma unroll
       for (int a = 1; a < Q; ++a) {
         int sx = x - cx(a), sy = y - cy(a);
-        bool link = true;
+        link[a] = true;
         if (sx < 0 || sx >= P.nx) {
-          if ((sx < 0 ? P.kind[WEST] : P.kind[EAST]) != EDGE_PERIODIC) link = false;
+          if ((sx < 0 ? P.kind[WEST] : P.kind[EAST]) != EDGE_PERIODIC) link[a] = false;
           sx = sx < 0 ? sx + P.nx : sx - P.nx;
         }
         if (sy < 0 || sy >= P.ny) {
-          if ((sy < 0 ? P.kind[SOUTH] : P.kind[NORTH]) != EDGE_PERIODIC) link = false;
+          if ((sy < 0 ? P.kind[SOUTH] : P.kind[NORTH]) != EDGE_PERIODIC) link[a] = false;
           sy = sy < 0 ? sy + P.ny : sy - P.ny;
         }
-        if (!link) continue;
-        const bool schi = (mask[(long long)sy * P.pitch + sx] & M_SOLID) != 0;
-        if (schi == chi) continue;
+        nm[a] = mask[(uint32_t)(sy * P.pitch + sx)];  // wrapped: always inside the lattice
+        wsx[a] = sx;
+        wsy[a] = sy;
+      }
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        const int sx = wsx[a], sy = wsy[a];
+        const bool schi = (nm[a] & M_SOLID) != 0;
+        if (!link[a] || schi == chi) continue;
         double gx, gy, s;
         if (chi) { gx = sx + 0.5 * cx(a); gy = sy + 0.5 * cy(a); s = 1.0; }
         else { gx = x - 0.5 * cx(a); gy = y - 0.5 * cy(a); s = -1.0; }
@@ -262,7 +315,9 @@ __device__ __forceinline__ void step_tile(
       T pxx = T(0), pxy = T(0), pyy = T(0);
 #pragma unroll
       for (int a = 1; a < Q; ++a) {
-        const T ne = d[a] - deq[a];
+        const T w = T(wgt(a));
+        const T cu = dotc(a, ux, uy);
+        const T ne = d[a] - (w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - uu15));
         pxx += T(cx(a) * cx(a)) * ne;
         pxy += T(cx(a) * cy(a)) * ne;
         pyy += T(cy(a) * cy(a)) * ne;
@@ -271,13 +326,18 @@ __device__ __forceinline__ void step_tile(
       const double sxx = -pr - P.facd * double(pxx);
       const double sxy = -P.facd * double(pxy);
       const double syy = -pr - P.facd * double(pyy);
-      const SiRec R = recs[si_map[c]];
+      const SiRec R = recs[si_map[(uint32_t)c]];
       acc[3] += sxx * R.ax + sxy * R.ay;
       acc[4] += sxy * R.ax + syy * R.ay;
       acc[5] += sxx * R.txx + sxy * R.txy + syy * R.tyy;
     }
   }
 
+  // the force window is read only now, so that its load does not delay the
+  // population loads above
+  const int wx0 = ctl->win[0] / BX, wy0 = ctl->win[1] / BY;
+  const int wx1 = (ctl->win[2] + BX - 1) / BX, wy1 = (ctl->win[3] + BY - 1) / BY;
+  const bool inwin = tx >= wx0 && tx < wx1 && ty >= wy0 && ty < wy1;
   __shared__ double lds[(NT / 64) * 6];
   if (inwin) {
     block_reduce6<NT>(acc, lds);

@@ -199,6 +199,9 @@ struct vplbm_lattice {
     a.pitch = pitch;
     a.plane = plane;
     a.tiles_x = (p.nx + bx - 1) / bx;
+    // tile / tiles_x = umulhi(tile, floor(2^32 / tiles_x) + 1): the error term,
+    // below tile / 2^32, stays under 1 / tiles_x while tile * tiles_x < 2^32
+    a.tx_magic = a.tiles_x == 1 ? 0u : (unsigned)((1ull << 32) / (unsigned)a.tiles_x + 1);
     const int tiles_y = (p.ny + by - 1) / by;
     a.ntiles = a.tiles_x * tiles_y;
     a.per_xcd = (a.ntiles + 7) / 8;
@@ -211,11 +214,18 @@ struct vplbm_lattice {
     a.omega = T(1.0 / p.tau);
     a.fac = T(1.0 - 0.5 / p.tau);
     a.facd = 1.0 - 0.5 / p.tau;
-    a.kpen = std::isinf(p.eta) ? T(0) : T(1.0 / p.eta);
+    const double kpen = std::isinf(p.eta) ? 0.0 : 1.0 / p.eta;
+    a.kpen = T(kpen);
+    a.khalf = T(0.5 * kpen);
+    a.a1 = T(1.0 / (1.0 + 0.5 * kpen));
+    a.kk = T(kpen / (1.0 + 0.5 * kpen));
     a.trt = p.trt_lambda > 0.0 ? 1 : 0;
     const double tau_m = p.trt_lambda > 0.0 ? p.trt_lambda / (p.tau - 0.5) + 0.5 : p.tau;
     a.omega_m = T(1.0 / tau_m);
     a.fac_m = T(1.0 - 0.5 / tau_m);
+    a.fo = T(p.tau - 0.5);
+    a.fo9 = T(9.0 * (p.tau - 0.5));
+    a.fo3 = T(3.0 * (tau_m - 0.5));
     a.rho0 = T(p.rho0);
     a.rho0d = p.rho0;
     a.gx = T(gx);
