@@ -143,7 +143,8 @@ struct SiRec {
   double ax, ay, txx, txy, tyy;
 };
 
-constexpr int PART_STRIDE = 8;  // doubles per partial-sum slot (6 used)
+constexpr int PART_STRIDE = 8;  // doubles per partial-sum slot (3 used: ME Fx, Fy, T)
+constexpr int SIG_STRIDE = 4;   // doubles per stress slot of a sample node (xx, xy, yy)
 constexpr int FIXQ = 4096;      // fixed-point grid of geometry coordinates
 
 }  // namespace vp

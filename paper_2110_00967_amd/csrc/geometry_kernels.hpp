@@ -393,7 +393,8 @@ constexpr int BODY_NT = 1024;
 constexpr int REGION_MARGIN = 6;  // covers links (1) and sample walks (5)
 
 __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
-                                const double *__restrict__ part, double *__restrict__ hist, int cap, int BX,
+                                const double *__restrict__ part, const double *__restrict__ sig,
+                                double *__restrict__ hist, int cap, int BX,
                                 int BY, int nx, int ny, int pitch, int perx, int pery,
                                 const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
                                 int *__restrict__ si_map) {
@@ -404,7 +405,7 @@ __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
     // forces of the step just taken (its window), needed by the update below
     const int wx0 = ctl->win[0] / BX, wy0 = ctl->win[1] / BY;
     const int wx1 = (ctl->win[2] + BX - 1) / BX, wy1 = (ctl->win[3] + BY - 1) / BY;
-    finalize_block<BODY_NT>(part, wx1 - wx0, wy1 - wy0, ctl, hist, cap, lds);
+    finalize_block<BODY_NT>(part, wx1 - wx0, wy1 - wy0, sig, recs, ctl, hist, cap, lds);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -482,10 +483,10 @@ __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
 
 __global__ void __launch_bounds__(BODY_NT)
     k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ part,
-                double *__restrict__ hist, int cap, int BX, int BY, int nx, int ny, int pitch, int perx,
-                int pery, const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
-                int *__restrict__ si_map) {
-  body_step_block(mask, ctl, part, hist, cap, BX, BY, nx, ny, pitch, perx, pery, pts, maxp, recs, si_map);
+                const double *__restrict__ sig, double *__restrict__ hist, int cap, int BX, int BY, int nx,
+                int ny, int pitch, int perx, int pery, const double *__restrict__ pts, int maxp,
+                SiRec *__restrict__ recs, int *__restrict__ si_map) {
+  body_step_block(mask, ctl, part, sig, hist, cap, BX, BY, nx, ny, pitch, perx, pery, pts, maxp, recs, si_map);
 }
 
 // body kernel of a batched launch: one workgroup per moving lattice
@@ -493,7 +494,8 @@ template <typename T>
 __global__ void __launch_bounds__(BODY_NT)
     k_body_step_batch(const CaseDesc<T> *__restrict__ cases, const int *__restrict__ moving, int flip) {
   const CaseDesc<T> &C = cases[moving[blockIdx.x]];
-  body_step_block(C.mask, C.ctl, C.part[C.pbit0 ^ flip], C.hist, C.cap, C.tw, C.by, C.P.nx, C.P.ny, C.P.pitch,
+  body_step_block(C.mask, C.ctl, C.part[C.pbit0 ^ flip], C.sig[C.pbit0 ^ flip], C.hist, C.cap, C.tw, C.by,
+                  C.P.nx, C.P.ny, C.P.pitch,
                   C.perx, C.pery, C.pts, C.maxp, const_cast<SiRec *>(C.recs), const_cast<int *>(C.si_map));
 }
 
@@ -557,7 +559,7 @@ __global__ void __launch_bounds__(SI_NT)
     v[2] += (px - B.x) * ty - (py - B.y) * tx;
   }
   __shared__ double lds[(SI_NT / 64) * 6];
-  block_reduce6<SI_NT>(v, lds);
+  block_reduce<SI_NT, 6>(v, lds);
   if (threadIdx.x == 0) {
     out[0] = v[0];
     out[1] = v[1];

@@ -34,6 +34,7 @@ template <typename T> struct StepArgs {
   long long plane;      // ny * pitch
   int tiles_x, ntiles, per_xcd;
   unsigned tx_magic;    // floor(2^32 / tiles_x) + 1 (0 when tiles_x = 1)
+  int rot[8];           // per XCD: the band's tiles start this far in (see k_step)
   int kind[4];          // edge kinds W, E, S, N
   T wu[4][2];           // 6 rho0 u_w of each edge: bounce-back increment w_a c_a . wu
   T omega, fac, kpen, rho0, gx, gy;
@@ -105,11 +106,11 @@ __device__ __forceinline__ T pull_edge(const S *__restrict__ fin, const StepArgs
   return Store<S>::ld(fin + (long long)pop * P.plane + (long long)sy * P.pitch + sx) + add;
 }
 
-template <int NT>
-__device__ __forceinline__ void block_reduce6(double (&v)[6], double *lds /*[NT/64][6]*/) {
+template <int NT, int N>
+__device__ __forceinline__ void block_reduce(double (&v)[N], double *lds /*[NT/64][N]*/) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < N; ++i) {
     double s = v[i];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
@@ -117,32 +118,43 @@ __device__ __forceinline__ void block_reduce6(double (&v)[6], double *lds /*[NT/
   }
   if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) lds[wave * 6 + i] = v[i];
+    for (int i = 0; i < N; ++i) lds[wave * N + i] = v[i];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < N; ++i) {
       double s = 0.0;
-      for (int w = 0; w < NT / 64; ++w) s += lds[w * 6 + i];
+      for (int w = 0; w < NT / 64; ++w) s += lds[w * N + i];
       v[i] = s;
     }
   }
 }
 
-// Fixed-order sum of one step's window partials -> force-history slot of the
-// next unfinished step (deterministic: same window, same order, same sum).
+// Forces of one step -> its force-history slot (deterministic: fixed
+// assignment and order).  ME: the window partials of the step kernel.  SI:
+// the stress each sample node stored (sig), contracted with the node's
+// aggregated weights, record by record.
 template <int NT>
 __device__ __forceinline__ void finalize_block(const double *__restrict__ part, int nwx, int nwy,
+                                               const double *__restrict__ sig, const SiRec *__restrict__ recs,
                                                Ctl *__restrict__ ctl, double *__restrict__ hist, int cap,
                                                double *lds) {
   const int nwin = (nwx > 0 && nwy > 0) ? nwx * nwy : 0;
+  const int nrec = ctl->nrec;
   double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int t = threadIdx.x; t < nwin; t += NT) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) v[i] += part[(long long)t * PART_STRIDE + i];
+    for (int i = 0; i < 3; ++i) v[i] += part[(long long)t * PART_STRIDE + i];
   }
-  block_reduce6<NT>(v, lds);
+  for (int r = threadIdx.x; r < nrec; r += NT) {
+    const double *g = sig + (long long)r * SIG_STRIDE;
+    const SiRec R = recs[r];
+    v[3] += g[0] * R.ax + g[1] * R.ay;
+    v[4] += g[1] * R.ax + g[2] * R.ay;
+    v[5] += g[0] * R.txx + g[1] * R.txy + g[2] * R.tyy;
+  }
+  block_reduce<NT, 6>(v, lds);
   if (threadIdx.x == 0) {
     const long long n = ctl->step + 1;
     double *h = hist + (n % cap) * 6;
@@ -155,6 +167,20 @@ __device__ __forceinline__ void finalize_block(const double *__restrict__ part, 
   }
 }
 
+// Masks of the 8 lattice neighbours of (x, y), wrapped into the lattice (the
+// momentum exchange decides separately which links are real)
+template <typename T>
+__device__ __forceinline__ void nbr_masks(const uint8_t *__restrict__ mask, const StepArgs<T> &P, int x, int y,
+                                          uint8_t (&nm)[Q]) {
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    int sx = x - cx(a), sy = y - cy(a);
+    sx = sx < 0 ? sx + P.nx : (sx >= P.nx ? sx - P.nx : sx);
+    sy = sy < 0 ? sy + P.ny : (sy >= P.ny ? sy - P.ny : sy);
+    nm[a] = mask[(uint32_t)(sy * P.pitch + sx)];
+  }
+}
+
 // One workgroup's tile of the step (tile < P.ntiles): the body of the step
 // kernel, shared by the single-lattice and the batched launch.  The
 // workgroup of tile 0 also finalizes the previous step's forces (fin_prev).
@@ -163,8 +189,9 @@ __device__ __forceinline__ void step_tile(
     int tile, const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
     const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl, const SiRec *__restrict__ recs,
     const int *__restrict__ si_map, double *__restrict__ part_out, const double *__restrict__ part_prev,
-    int fin_prev, double *__restrict__ hist, int cap, typename Store<S>::T *__restrict__ mrho,
-    typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy) {
+    double *__restrict__ sig_out, const double *__restrict__ sig_prev, int fin_prev, double *__restrict__ hist,
+    int cap, typename Store<S>::T *__restrict__ mrho, typename Store<S>::T *__restrict__ mux,
+    typename Store<S>::T *__restrict__ muy) {
   using T = typename Store<S>::T;
   constexpr int NT = BX * BY;
   // tile / tiles_x by multiply-high (exact while tile * tiles_x < 2^32, which
@@ -174,7 +201,7 @@ __device__ __forceinline__ void step_tile(
   const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
   const int x = tx * BX + lx, y = ty * BY + ly;
 
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};  // momentum exchange Fx, Fy, T of this thread
 
   // Every cell of the tile has all 8 neighbours inside the lattice: the
   // workgroup-uniform fast path.  A plane holds fewer than 2^31 / 9 cells, so
@@ -272,33 +299,25 @@ __device__ __forceinline__ void step_tile(
     if (m & M_IFACE) {
       // momentum exchange: every population pulled across the interface;
       // the link's interface point is its midpoint seen from its fluid node.
-      // The 8 neighbour masks are loaded first, all at once (a load inside
-      // the divergent loop below would cost one memory round trip per link).
+      // The 8 neighbour masks are loaded all at once (a load inside the
+      // divergent loop below would cost one memory round trip per link).
       const BodyDev B = ctl->body;
       uint8_t nm[Q];
-      bool link[Q];
-      int wsx[Q], wsy[Q];
+      nbr_masks(mask, P, x, y, nm);
 #pragma unroll
       for (int a = 1; a < Q; ++a) {
         int sx = x - cx(a), sy = y - cy(a);
-        link[a] = true;
+        bool link = true;
         if (sx < 0 || sx >= P.nx) {
-          if ((sx < 0 ? P.kind[WEST] : P.kind[EAST]) != EDGE_PERIODIC) link[a] = false;
+          if ((sx < 0 ? P.kind[WEST] : P.kind[EAST]) != EDGE_PERIODIC) link = false;
           sx = sx < 0 ? sx + P.nx : sx - P.nx;
         }
         if (sy < 0 || sy >= P.ny) {
-          if ((sy < 0 ? P.kind[SOUTH] : P.kind[NORTH]) != EDGE_PERIODIC) link[a] = false;
+          if ((sy < 0 ? P.kind[SOUTH] : P.kind[NORTH]) != EDGE_PERIODIC) link = false;
           sy = sy < 0 ? sy + P.ny : sy - P.ny;
         }
-        nm[a] = mask[(uint32_t)(sy * P.pitch + sx)];  // wrapped: always inside the lattice
-        wsx[a] = sx;
-        wsy[a] = sy;
-      }
-#pragma unroll
-      for (int a = 1; a < Q; ++a) {
-        const int sx = wsx[a], sy = wsy[a];
         const bool schi = (nm[a] & M_SOLID) != 0;
-        if (!link[a] || schi == chi) continue;
+        if (!link || schi == chi) continue;
         double gx, gy, s;
         if (chi) { gx = sx + 0.5 * cx(a); gy = sy + 0.5 * cy(a); s = 1.0; }
         else { gx = x - 0.5 * cx(a); gy = y - 0.5 * cy(a); s = -1.0; }
@@ -326,10 +345,12 @@ __device__ __forceinline__ void step_tile(
       const double sxx = -pr - P.facd * double(pxx);
       const double sxy = -P.facd * double(pxy);
       const double syy = -pr - P.facd * double(pyy);
-      const SiRec R = recs[si_map[(uint32_t)c]];
-      acc[3] += sxx * R.ax + sxy * R.ay;
-      acc[4] += sxy * R.ax + syy * R.ay;
-      acc[5] += sxx * R.txx + sxy * R.txy + syy * R.tyy;
+      // the node's stress goes to its record's slot; the finalize contracts
+      // it with the aggregated weights
+      double *g = sig_out + (long long)si_map[(uint32_t)c] * SIG_STRIDE;
+      g[0] = sxx;
+      g[1] = sxy;
+      g[2] = syy;
     }
   }
 
@@ -340,17 +361,18 @@ __device__ __forceinline__ void step_tile(
   const bool inwin = tx >= wx0 && tx < wx1 && ty >= wy0 && ty < wy1;
   __shared__ double lds[(NT / 64) * 6];
   if (inwin) {
-    block_reduce6<NT>(acc, lds);
+    block_reduce<NT, 3>(acc, lds);
     if (threadIdx.x == 0) {
       double *o = part_out + (long long)((ty - wy0) * (wx1 - wx0) + (tx - wx0)) * PART_STRIDE;
 #pragma unroll
-      for (int i = 0; i < 6; ++i) o[i] = acc[i];
+      for (int i = 0; i < 3; ++i) o[i] = acc[i];
     }
   }
   if (fin_prev && tile == 0) {
-    // forces of the previous step (same window: only static bodies defer)
+    // forces of the previous step (same window and records: only static
+    // bodies defer)
     __syncthreads();
-    finalize_block<NT>(part_prev, wx1 - wx0, wy1 - wy0, ctl, hist, cap, lds);
+    finalize_block<NT>(part_prev, wx1 - wx0, wy1 - wy0, sig_prev, recs, ctl, hist, cap, lds);
   }
 }
 
@@ -359,17 +381,24 @@ __global__ void __launch_bounds__(BX *BY)
     k_step(const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
            const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl,
            const SiRec *__restrict__ recs, const int *__restrict__ si_map,
-           double *__restrict__ part_out, const double *__restrict__ part_prev, int fin_prev,
-           double *__restrict__ hist, int cap, typename Store<S>::T *__restrict__ mrho,
-           typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy) {
+           double *__restrict__ part_out, const double *__restrict__ part_prev, double *__restrict__ sig_out,
+           const double *__restrict__ sig_prev, int fin_prev, double *__restrict__ hist, int cap,
+           typename Store<S>::T *__restrict__ mrho, typename Store<S>::T *__restrict__ mux,
+           typename Store<S>::T *__restrict__ muy) {
   // XCD-aware tile order: consecutive workgroups go round-robin over the 8
   // XCDs, so give each XCD a contiguous band of tiles (shared halo lines stay
-  // in that XCD's L2).
-  const int b = blockIdx.x;
-  const int tile = (b & 7) * P.per_xcd + (b >> 3);
-  if (tile >= P.ntiles) return;
-  step_tile<S, BX, BY, MACRO, TRT>(tile, fin, fout, mask, P, ctl, recs, si_map, part_out, part_prev, fin_prev,
-                                   hist, cap, mrho, mux, muy);
+  // in that XCD's L2).  A band only a few rounds of workgroups deep is
+  // rotated to start at the first row of the force window it holds: the
+  // slower tiles there are dispatched first and overlap the rest of the band
+  // instead of extending its end.
+  const int b = blockIdx.x, xcd = b & 7, i = b >> 3;
+  const int start = xcd * P.per_xcd, len = min(P.per_xcd, P.ntiles - start);
+  if (i >= len) return;
+  int t = i + P.rot[xcd];
+  t -= t >= len ? len : 0;
+  const int tile = start + t;
+  step_tile<S, BX, BY, MACRO, TRT>(tile, fin, fout, mask, P, ctl, recs, si_map, part_out, part_prev, sig_out,
+                                   sig_prev, fin_prev, hist, cap, mrho, mux, muy);
 }
 
 // Per-lattice description for the batched step: one launch covers the tiles
@@ -382,6 +411,7 @@ template <typename T> struct CaseDesc {
   const SiRec *recs;
   const int *si_map;
   double *part[2];        // partial sums of steps with parity 0 and 1
+  double *sig[2];         // sample-node stresses of steps with parity 0 and 1
   double *hist;
   int cap;
   int tile0;              // first global tile of this lattice
@@ -414,17 +444,18 @@ __global__ void __launch_bounds__(BX *BY)
   double *pout = C->part[pb];
   const double *pprev = C->part[pb ^ 1];
   step_tile<S, BX, BY, false, TRT>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map, pout, pprev,
-                              fin_prev, C->hist, C->cap, nullptr, nullptr, nullptr);
+                                   C->sig[pb], C->sig[pb ^ 1], fin_prev, C->hist, C->cap, nullptr, nullptr,
+                                   nullptr);
 }
 
 template <int NT>
 __global__ void __launch_bounds__(NT)
-    k_finalize(const double *__restrict__ part, Ctl *__restrict__ ctl, double *__restrict__ hist, int cap,
-               int BX, int BY) {
+    k_finalize(const double *__restrict__ part, const double *__restrict__ sig, const SiRec *__restrict__ recs,
+               Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int BX, int BY) {
   __shared__ double lds[(NT / 64) * 6];
   const int wx0 = ctl->win[0] / BX, wy0 = ctl->win[1] / BY;
   const int wx1 = (ctl->win[2] + BX - 1) / BX, wy1 = (ctl->win[3] + BY - 1) / BY;
-  finalize_block<NT>(part, wx1 - wx0, wy1 - wy0, ctl, hist, cap, lds);
+  finalize_block<NT>(part, wx1 - wx0, wy1 - wy0, sig, recs, ctl, hist, cap, lds);
 }
 
 }  // namespace vp

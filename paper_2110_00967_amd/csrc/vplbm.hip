@@ -44,6 +44,8 @@ constexpr int DEFAULT_HIST = 4096;
 constexpr int DEFAULT_PTS = 4096;
 constexpr int DEFAULT_VERTS = 4096;
 constexpr int MIN_TILE_CELLS = 64;
+constexpr int WG_SLOTS_PER_XCD = 256;  // 32 CUs x 8 resident workgroups of the step kernel
+constexpr int ROT_MAX_ROUNDS = 16;
 constexpr int MAX_NX = 16384;  // one row of 9 planes fits the staging buffer
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -58,7 +60,8 @@ int pitch_of(const vplbm_params &p) {
 }
 
 struct Layout {
-  size_t A, B, mask, mrho, mux, muy, si_map, partials, partials_stride, hist, ctl, recs, pts, verts, staging,
+  size_t A, B, mask, mrho, mux, muy, si_map, partials, partials_stride, sig, sig_stride, hist, ctl, recs, pts,
+      verts, staging,
       siout, total;
 };
 
@@ -88,7 +91,11 @@ Layout layout_of(const vplbm_params &p) {
   L.hist = take((size_t)cap * 6 * sizeof(double));
   L.ctl = take(sizeof(Ctl));
   // one record per distinct sample node: up to 4 per point with the interpolated rule
-  L.recs = take((size_t)maxp * (p.si_rule == 1 ? 4 : 1) * sizeof(SiRec));
+  const size_t maxrec = (size_t)maxp * (p.si_rule == 1 ? 4 : 1);
+  L.recs = take(maxrec * sizeof(SiRec));
+  // stress of each sample node, by step parity (read back by the finalize)
+  L.sig_stride = maxrec * SIG_STRIDE * sizeof(double);
+  L.sig = take(2 * L.sig_stride);
   L.pts = take((size_t)5 * maxp * sizeof(double));
   L.verts = take((size_t)2 * maxv * sizeof(long long));
   L.staging = take(STAGE_DOUBLES * sizeof(double));
@@ -141,6 +148,10 @@ struct vplbm_lattice {
   int cur = 0;  // 0: A holds the state, 1: B
   long long nstep = 0;
   bool pending = false;  // forces of the last step not yet summed into the history
+  // force window (cells) of a static body, cached for the step kernel's tile
+  // order; refreshed from the device after geometry changes
+  int pwin[4] = {0, 0, 0, 0};
+  bool pwin_ok = false;
   bool initialized = false;
   bool macro_valid = false;
   int cap = 0, maxp = 0, maxv = 0;
@@ -159,6 +170,8 @@ struct vplbm_lattice {
   Ctl *ctl() const { return (Ctl *)at(L.ctl); }
   // partial sums written by step n live in buffer n % 2
   double *part(long long n) const { return (double *)at(L.partials + (size_t)(n & 1) * L.partials_stride); }
+  double *sig(long long n) const { return (double *)at(L.sig + (size_t)(n & 1) * L.sig_stride); }
+  const SiRec *recs() const { return (const SiRec *)at(L.recs); }
 
   int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -205,6 +218,17 @@ struct vplbm_lattice {
     const int tiles_y = (p.ny + by - 1) / by;
     a.ntiles = a.tiles_x * tiles_y;
     a.per_xcd = (a.ntiles + 7) / 8;
+    // rotate each XCD band that holds rows of a static body's force window to
+    // start at the first of them, when the band is at most ROT_MAX_ROUNDS
+    // rounds of workgroups deep (deeper bands absorb the slower tiles)
+    if (pwin_ok && mode == MODE_STATIC && pwin[3] > pwin[1] &&
+        a.per_xcd <= ROT_MAX_ROUNDS * WG_SLOTS_PER_XCD) {
+      const int w0 = (pwin[1] / by) * a.tiles_x, w1 = ((pwin[3] + by - 1) / by) * a.tiles_x;
+      for (int k = 0; k < 8; ++k) {
+        const int s0 = k * a.per_xcd, len = std::min(a.per_xcd, a.ntiles - s0);
+        if (len > 0 && w0 < s0 + len && w1 > s0) a.rot[k] = std::max(w0, s0) - s0;
+      }
+    }
     const vplbm_edge *E[4] = {&p.west, &p.east, &p.south, &p.north};
     for (int e = 0; e < 4; ++e) {
       a.kind[e] = E[e]->kind;
@@ -239,6 +263,22 @@ struct vplbm_lattice {
 // ----------------------------------------------------------------------------
 namespace {
 
+// cache the force window of a static body for the tile order of the step
+// kernel (one device read after a geometry change; a moving body's window
+// lives on the device only)
+int resolve_pwin(vplbm_lattice *L) {
+  if (L->pwin_ok) return VPLBM_OK;
+  L->pwin[0] = L->pwin[1] = L->pwin[2] = L->pwin[3] = 0;
+  if (L->mode == MODE_STATIC) {
+    Ctl c;
+    const int rc = L->ctl_pull(c);
+    if (rc) return rc;
+    for (int k = 0; k < 4; ++k) L->pwin[k] = c.win[k];
+  }
+  L->pwin_ok = true;
+  return VPLBM_OK;
+}
+
 template <typename S, int BX, int BY>
 int launch_step_t(vplbm_lattice *L, bool macro) {
   using T = typename Store<S>::T;
@@ -252,22 +292,24 @@ int launch_step_t(vplbm_lattice *L, bool macro) {
   const long long n = L->nstep + 1;  // the step this launch computes
   double *pout = L->part(n);
   const double *pprev = L->part(n - 1);
+  double *gout = L->sig(n);
+  const double *gprev = L->sig(n - 1);
   const int fin_prev = L->pending ? 1 : 0;
   double *hist = (double *)L->at(L->L.hist);
   if (macro) {
     if (a.trt)
       VP_LAUNCH((k_step<S, BX, BY, true, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
-                L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
+                L->ctl(), recs, smap, pout, pprev, gout, gprev, fin_prev, hist, L->cap, r, u, v);
     else
       VP_LAUNCH((k_step<S, BX, BY, true, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
-                L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
+                L->ctl(), recs, smap, pout, pprev, gout, gprev, fin_prev, hist, L->cap, r, u, v);
   } else {
     if (a.trt)
       VP_LAUNCH((k_step<S, BX, BY, false, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
-                L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
+                L->ctl(), recs, smap, pout, pprev, gout, gprev, fin_prev, hist, L->cap, r, u, v);
     else
       VP_LAUNCH((k_step<S, BX, BY, false, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(),
-                a, L->ctl(), recs, smap, pout, pprev, fin_prev, hist, L->cap, r, u, v);
+                a, L->ctl(), recs, smap, pout, pprev, gout, gprev, fin_prev, hist, L->cap, r, u, v);
   }
   return L->launched("k_step");
 }
@@ -283,6 +325,8 @@ template <typename S> int launch_step_s(vplbm_lattice *L, bool macro) {
 }
 
 int launch_step(vplbm_lattice *L, bool macro) {
+  const int rc = resolve_pwin(L);
+  if (rc) return rc;
   switch (L->p.precision) {
     case VPLBM_F64: return launch_step_s<double>(L, macro);
     case VPLBM_F32: return launch_step_s<float>(L, macro);
@@ -351,7 +395,8 @@ int launch_si_select(vplbm_lattice *L) {
 // body, rebuild the mask
 int launch_body_step(vplbm_lattice *L) {
   VP_LAUNCH(k_body_step, dim3(1), dim3(BODY_NT), 0, L->stream, L->mask(), L->ctl(),
-                     (const double *)L->part(L->nstep + 1), (double *)L->at(L->L.hist), L->cap, L->bx, L->by,
+                     (const double *)L->part(L->nstep + 1), (const double *)L->sig(L->nstep + 1),
+                     (double *)L->at(L->L.hist), L->cap, L->bx, L->by,
                      L->p.nx, L->p.ny, L->pitch, (int)L->periodic_x(), (int)L->periodic_y(),
                      (const double *)L->at(L->L.pts), L->maxp, (SiRec *)L->at(L->L.recs),
                      (int *)L->at(L->L.si_map));
@@ -362,7 +407,8 @@ int launch_body_step(vplbm_lattice *L) {
 int flush(vplbm_lattice *L) {
   if (!L->pending) return VPLBM_OK;
   VP_LAUNCH((k_finalize<256>), dim3(1), dim3(256), 0, L->stream, (const double *)L->part(L->nstep),
-                     L->ctl(), (double *)L->at(L->L.hist), L->cap, L->bx, L->by);
+                     (const double *)L->sig(L->nstep), L->recs(), L->ctl(), (double *)L->at(L->L.hist), L->cap,
+                     L->bx, L->by);
   int rc = L->launched("k_finalize");
   if (!rc) L->pending = false;
   return rc;
@@ -619,6 +665,7 @@ int vplbm_set_body_disk(vplbm_lattice *L, double xc, double yc, double r) {
     const int frc = flush(L);
     if (frc) return frc;
   }
+  L->pwin_ok = false;
   if (!std::isfinite(xc) || !std::isfinite(yc) || !(r > 0.0) || !std::isfinite(r))
     return L->fail(VPLBM_EINVAL, "disk needs finite centre and r > 0");
   const int nx = L->p.nx, ny = L->p.ny;
@@ -659,6 +706,7 @@ int vplbm_set_body_polygon(vplbm_lattice *L, const double *xy, int nvert, double
     const int frc = flush(L);
     if (frc) return frc;
   }
+  L->pwin_ok = false;
   if (!xy || nvert < 3 || nvert > L->maxv)
     return L->fail(VPLBM_EINVAL, "polygon needs 3..%d vertices", L->maxv);
   if (!std::isfinite(xref) || !std::isfinite(yref)) return L->fail(VPLBM_EINVAL, "reference point");
@@ -711,6 +759,7 @@ int vplbm_set_mask(vplbm_lattice *L, const uint8_t *solid) {
     const int frc = flush(L);
     if (frc) return frc;
   }
+  L->pwin_ok = false;
   const int nx = L->p.nx, ny = L->p.ny;
   std::vector<uint8_t> rows((size_t)ny * L->pitch, 0);
   int x0 = nx, y0 = ny, x1 = -1, y1 = -1;
@@ -753,6 +802,7 @@ int vplbm_set_body_motion(vplbm_lattice *L, const vplbm_body_state *s) {
     const int frc = flush(L);
     if (frc) return frc;
   }
+  L->pwin_ok = false;
   const double v[6] = {s->x, s->y, s->theta, s->u, s->v, s->omega};
   for (double e : v)
     if (!std::isfinite(e)) return L->fail(VPLBM_EINVAL, "state not finite");
@@ -804,6 +854,7 @@ int vplbm_set_body_dynamics(vplbm_lattice *L, double rho_s, double gx, double gy
     const int frc = flush(L);
     if (frc) return frc;
   }
+  L->pwin_ok = false;
   if (L->shape != SHAPE_DISK) return L->fail(VPLBM_ESTATE, "free bodies must be disks");
   if (!(rho_s > 0.0) || !std::isfinite(rho_s) || !std::isfinite(gx) || !std::isfinite(gy))
     return L->fail(VPLBM_EINVAL, "rho_s > 0 and finite gravity required");
@@ -833,6 +884,7 @@ int vplbm_set_si_points(vplbm_lattice *L, const double *xy, const double *nrm, c
     const int frc = flush(L);
     if (frc) return frc;
   }
+  L->pwin_ok = false;
   if (npts < 0 || npts > L->maxp) return L->fail(VPLBM_EINVAL, "npts must be in 0..%d", L->maxp);
   if (npts > 0 && (!xy || !nrm || !ds)) return L->fail(VPLBM_EINVAL, "NULL point arrays");
   for (int i = 0; i < npts; ++i)
@@ -1162,6 +1214,8 @@ void fill_desc(vplbm_lattice *L, int tile0, void *out) {
   d.si_map = (const int *)L->at(L->L.si_map);
   d.part[0] = L->part(0);
   d.part[1] = L->part(1);
+  d.sig[0] = L->sig(0);
+  d.sig[1] = L->sig(1);
   d.hist = (double *)L->at(L->L.hist);
   d.cap = L->cap;
   d.tile0 = tile0;
@@ -1276,6 +1330,8 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
     int total = 0, nmov = 0;
     for (size_t i = 0; i < act.size(); ++i) {
       vplbm_lattice *L = B->cases[act[i]];
+      rc = resolve_pwin(L);
+      if (rc) return B->fail(rc, "lattice " + std::to_string(act[i]) + ": " + L->err);
       const int tiles = L->step_args<float>().ntiles;
       switch (B->prec) {
         case VPLBM_F64: fill_desc<double>(L, total, &B->desc_host[i * dsz]); break;
