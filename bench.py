@@ -80,10 +80,12 @@ def cpu_baseline(case, budget_s=12.0):
     }
 
 
-def run_sweep(args, torch, W, V):
-    """64 airfoil cases stepped by one launch per step, and the same cases
-    stepped one after the other (the plain single-case form)."""
-    cases = W.sweep_cases()
+def run_sweep(args, torch, W, V, paper=False):
+    """Many airfoil cases stepped by one launch per step, and the same cases
+    stepped one after the other (the plain single-case form).  Default: 64
+    cases (chords 100/150/200, AoA 0-20 deg).  paper: the paper's full-scale
+    runs, chord 278 on 3614 x 1946, TRT, AoA 0-28 deg in steps of 2."""
+    cases = W.paper_aoa_sweep() if paper else W.sweep_cases()
     lats = [V.Lattice.from_case(c, precision=args.precision) for c in cases]
     cells = sum(c.nx * c.ny for c in cases)
     batch = V.Batch(lats)
@@ -109,15 +111,22 @@ def run_sweep(args, torch, W, V):
     achieved = bpc * cells / (ms * 1e-3) / 1e9
     q = [0.5 * c.u_ref ** 2 * c.length_scale for c in cases]
     cd = [lat.forces_si()[0] / qq for lat, qq in zip(lats, q)]
+    if paper:
+        config = {"workload": "naca0012_paper_c278_3614x1946_trt_aoa_sweep", "cases": n, "cells": cells,
+                  "chord": 278, "aoa_deg": [0.0, 2.0 * (n - 1)],
+                  "tau": 0.55, "trt_lambda": round(1.0 / 6.0, 6), "eta": 1e-6, "si_points": len(cases[0].si_ds),
+                  "storage": args.precision, "parallelism": "single GPU, one batched launch per step"}
+    else:
+        config = {"workload": "naca0012_aoa_sweep_64cases", "cases": n, "cells": cells,
+                  "chords": [100, 150, 200], "aoa_deg": [0.0, 20.0], "storage": args.precision,
+                  "parallelism": "single GPU, one batched launch per step"}
     out = {
         "metric": METRIC, "value": round(cells / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": {"f32": "f32", "f16dev": "f32 (f16 storage)", "f64": "f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": "naca0012_aoa_sweep_64cases", "cases": n, "cells": cells,
-                   "chords": [100, 150, 200], "aoa_deg": [0.0, 20.0], "storage": args.precision,
-                   "parallelism": "single GPU, one batched launch per step"},
+        "config": config,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_step_batch",
                      "kernel_us": round(ms * 1e3, 3), "bytes_per_cell": bpc, "cells_per_launch": cells},
@@ -125,6 +134,14 @@ def run_sweep(args, torch, W, V):
                    "steps": ks},
         "CD_SI_range": [round(min(cd), 4), round(max(cd), 4)],
     }
+    if paper:
+        # force coefficients after the run, per angle (both methods; the
+        # paper's own curves are not available to compare with)
+        out["coefficients"] = [
+            {"aoa_deg": 2.0 * k, "CD_ME": round(lat.forces_me()[0] / qq, 5), "CL_ME": round(lat.forces_me()[1] / qq, 5),
+             "CD_SI": round(lat.forces_si()[0] / qq, 5), "CL_SI": round(lat.forces_si()[1] / qq, 5)}
+            for k, (lat, qq) in enumerate(zip(lats, q))]
+        out["steps_run"] = lats[0].step_count
     batch.close()
     for lat in lats:
         lat.close()
@@ -171,10 +188,13 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=10.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serve: HBM budget for resident lattices")
-    ap.add_argument("--workload", default="naca", choices=["naca", "sediment", "roofline", "disk", "sweep", "serve"],
+    ap.add_argument("--workload", default="naca",
+                    choices=["naca", "sediment", "roofline", "disk", "sweep", "paper", "serve"],
                     help="naca: NACA 0012 2000x1000 (default); sediment: free disk 400x2000; "
                          "roofline: NACA 0012 chord 819 on 8192x8192; disk: 128x64 disk channel; "
                          "sweep: 64 airfoils (chords 100/150/200, AoA 0-20 deg) in one batched launch; "
+                         "paper: the paper's full-scale airfoil runs (chord 278, 3614x1946, TRT, AoA 0-28 deg, "
+                         "15 cases) in one batched launch; "
                          "serve: Poisson mix of airfoil and sedimentation requests, continuous batching")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -192,8 +212,8 @@ def main():
         print("no GPU available", file=sys.stderr)
         sys.exit(1)
 
-    if args.workload == "sweep":
-        print(json.dumps(run_sweep(args, torch, W, V)), flush=True)
+    if args.workload in ("sweep", "paper"):
+        print(json.dumps(run_sweep(args, torch, W, V, paper=args.workload == "paper")), flush=True)
         return
     if args.workload == "serve":
         print(json.dumps(run_serve(args, W)), flush=True)

@@ -500,10 +500,20 @@ int orc_mask_polygon(int nx, int ny, const double *xy, int nvert, uint8_t *solid
     vx[v] = fixq(xy[2 * v]);
     vy[v] = fixq(xy[2 * v + 1]);
   }
+  /* a centre outside the vertices' bounding box is neither inside nor on an edge */
+  long long x0 = vx[0], x1 = vx[0], y0 = vy[0], y1 = vy[0];
+  for (int v = 1; v < nvert; ++v) {
+    x0 = vx[v] < x0 ? vx[v] : x0;
+    x1 = vx[v] > x1 ? vx[v] : x1;
+    y0 = vy[v] < y0 ? vy[v] : y0;
+    y1 = vy[v] > y1 ? vy[v] : y1;
+  }
   int count = 0;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      int in = point_in_polygon((long long)i * 4096, (long long)j * 4096, nvert, vx, vy);
+      const long long X = (long long)i * 4096, Y = (long long)j * 4096;
+      int in = 0;
+      if (X >= x0 && X <= x1 && Y >= y0 && Y <= y1) in = point_in_polygon(X, Y, nvert, vx, vy);
       solid[(size_t)j * nx + i] = (uint8_t)in;
       count += in;
     }

@@ -4,6 +4,8 @@ configuration bench.py times (FP32 deviation storage, default tile).
 * NACA 0012, 2000 x 1000: bit-exact solid indicator and sample nodes; 200
   steps against the FP64 oracle (velocity relative L2 <= 1e-5, force
   histories within 0.5% of the largest force).
+* The paper's own airfoil runs (chord 278 on 3614 x 1946, TRT with
+  Lambda = 1/6, eta = 1e-6, 849 SI points): 50 steps at 20 degrees.
 * Sedimenting disk, 400 x 2000: 200 steps of the free body driven by the
   momentum-exchange force, mask rebuilt on the device every step.
 * Largest lattice the library accepts (16384 x 14563, 9*ny*pitch just below
@@ -42,6 +44,31 @@ def test_naca_full_size_fp32():
         h = g.history(which)
         e = np.abs(h - ref).max() / np.abs(ref).max()
         say(f"naca force {which} max rel err {e:.2e}")
+        assert e <= 5e-3
+
+
+def test_naca_paper_scale_trt_fp32():
+    # the paper's own airfoil configuration: chord 278, 3614 x 1946, TRT
+    # (Lambda = 1/6), eta = 1e-6, 849 SI points, at 20 degrees
+    from paper_2110_00967_amd import vplbm as V
+    case = W.case_naca_paper(aoa_deg=20.0)
+    say("naca0012 paper scale 3614x1946 TRT fp32 vs oracle, 50 steps")
+    g = V.Lattice.from_case(case, precision="f32")
+    o = O.RefLattice.from_case(case)
+    assert np.array_equal(g.mask() & 1, o.solid)
+    sample = np.zeros(o.nx * o.ny, bool)
+    sample[o.si_node] = True
+    assert np.array_equal((g.mask().ravel() & 0x40) != 0, sample)
+    g.step(50, macro=True)
+    o.step(50)
+    r, u, v = g.macro()
+    err_u = rel_l2(np.stack([u, v]), np.stack([o.ux, o.uy]))
+    say(f"paper-scale u relL2 {err_u:.2e}")
+    assert err_u <= 1e-5
+    for which, ref in ((0, o.me()), (1, o.si())):
+        h = g.history(which)
+        e = np.abs(h - ref).max() / np.abs(ref).max()
+        say(f"paper-scale force {which} max rel err {e:.2e}")
         assert e <= 5e-3
 
 

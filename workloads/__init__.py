@@ -186,6 +186,34 @@ def case_naca(chord: int = 200, aoa_deg: float = 10.0, steps: int = 200000, n_si
         length_scale=float(chord), u_ref=u_in)
 
 
+def case_naca_paper(aoa_deg: float = 0.0, chord: int = 278, steps: int = 200000, east: Optional[Edge] = None) -> Case:
+    """The airfoil runs of the paper's application section at full scale.
+
+    NACA 0012 with chord C = 278 in a 13C x 7C channel (3614 x 1946 cells),
+    leading edge 4C behind the inlet and 3.5C above the lower edge, inflow
+    U0 = 0.0599, tau+ = 0.55 (Re = U0 C / nu = 999), TRT with Lambda = 1/6,
+    eta = 1e-6, and 849 stress-integration points (segment midpoints of the
+    outline: 2 x 424 surface segments + the trailing-edge closure).  West:
+    velocity inlet; south/north: free-slip; east: zero-gradient unless given.
+    """
+    u_in = 0.0599
+    nx, ny = 13 * chord, 7 * chord
+    poly = naca0012_polygon(float(chord), 4.0 * chord, 3.5 * chord, aoa_deg, n_side=424)
+    xy, n, ds = polygon_si_points(poly)
+    cx, cy, _ = polygon_centroid(poly)
+    return Case(
+        name=f"naca0012_paper_c{chord}_aoa{aoa_deg:g}", nx=nx, ny=ny, tau=0.55, eta=1e-6,
+        west=Edge(VELOCITY, u_in, 0.0), east=east if east is not None else Edge(OUTFLOW),
+        south=Edge(FREESLIP), north=Edge(FREESLIP), u_init=(u_in, 0.0), polygon=poly, ref_point=(cx, cy),
+        si_xy=xy, si_n=n, si_ds=ds, steps=steps, trt_lambda=1.0 / 6.0, length_scale=float(chord), u_ref=u_in)
+
+
+def paper_aoa_sweep(step_deg: float = 2.0, max_deg: float = 28.0, **kw):
+    """The paper's angle-of-attack range, 0 to 28 degrees."""
+    n = int(round(max_deg / step_deg)) + 1
+    return [case_naca_paper(aoa_deg=step_deg * k, **kw) for k in range(n)]
+
+
 def case_sedimentation(nx: int = 400, ny: int = 2000, d: float = 20.0, rho_r: float = 1.5,
                        g: float = 5.5e-5, x0_frac: float = 0.4, y0: Optional[float] = None,
                        steps: int = 100000, npts: int = 64, force_source: int = 0) -> Case:
