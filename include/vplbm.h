@@ -56,13 +56,24 @@ enum {
   VPLBM_BC_VELOCITY = 1, /* half-way bounce-back, wall half a cell outside the
                             edge, moving with (ux, uy); (0,0) = no-slip */
   VPLBM_BC_FREESLIP = 2, /* specular reflection (u.n = 0) */
-  VPLBM_BC_OUTFLOW = 3   /* zero-gradient: incoming populations copied from the
+  VPLBM_BC_OUTFLOW = 3,  /* zero-gradient: incoming populations copied from the
                             edge cell's own row/column */
+  VPLBM_BC_CONVECTIVE = 4 /* convective outflow (the condition the Applications
+                            section cites): an incoming population f at an edge
+                            cell follows df/dt + U df/dn = 0, upwind and implicit,
+                            f(t+1) = (f(t) + U f_inner(t+1)) / (1 + U), with
+                            f_inner(t+1) the value the zero-gradient rule takes
+                            and f(t) its own previous value (state kept per edge
+                            cell, restarted by vplbm_init_uniform and
+                            vplbm_set_fields).  U = ux >= 0 (lattice units); U = 0
+                            freezes the incoming populations, large U tends to
+                            zero-gradient.  At a corner the x edge decides. */
 };
 
 typedef struct {
   int kind;      /* VPLBM_BC_* */
-  double ux, uy; /* wall / inflow velocity, used by VPLBM_BC_VELOCITY */
+  double ux, uy; /* wall / inflow velocity of VPLBM_BC_VELOCITY; ux is the
+                    convection speed U of VPLBM_BC_CONVECTIVE */
 } vplbm_edge;
 
 typedef struct {

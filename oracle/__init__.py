@@ -23,7 +23,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvplbm_oracle.so")
 
-PERIODIC, VELOCITY, FREESLIP, OUTFLOW = 0, 1, 2, 3
+PERIODIC, VELOCITY, FREESLIP, OUTFLOW, CONVECTIVE = 0, 1, 2, 3, 4
 
 # D2Q9 of Sec. 2.2 (restated here only for test-side moment checks)
 CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
@@ -59,7 +59,7 @@ def lib():
         L.orc_equilibrium.argtypes = [C.c_double, C.c_double, C.c_double, dp]
         L.orc_forcing.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
         L.orc_cell_macro.argtypes = [P, dp, C.c_int, C.c_double, C.c_double] + [C.POINTER(C.c_double)] * 5
-        L.orc_stream.argtypes = [P, dp, dp]
+        L.orc_stream.argtypes = [P, dp, C.c_void_p, dp]
         L.orc_momentum_exchange.argtypes = [P, dp, up, B, dp]
         L.orc_node_stress.argtypes = [P, dp, dp]
         L.orc_stress_integration.argtypes = [P, dp, C.c_int, dp, dp, dp, ip, dp, B, dp]
@@ -67,7 +67,7 @@ def lib():
         L.orc_si_stencils.restype = C.c_int
         L.orc_si_nodes.argtypes = [C.c_int, C.c_int, up, C.c_int, dp, dp, ip]
         L.orc_si_nodes.restype = C.c_int
-        L.orc_step.argtypes = [P, dp, dp, dp, up, B, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+        L.orc_step.argtypes = [P, dp, C.c_void_p, dp, dp, up, B, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_void_p]
         L.orc_init_fields.argtypes = [P, dp, dp, dp, dp]
         L.orc_mask_disk.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, up]
@@ -150,6 +150,9 @@ class RefLattice:
         self.nx, self.ny = nx, ny
         self.ft = np.zeros((ny, nx, 9))
         self.fw = np.zeros((ny, nx, 9))
+        # streamed field of the previous step, read by convective edges
+        self.conv = any(int(e[0]) == CONVECTIVE for e in (west, east, south, north))
+        self.fprev = None
         self.fn = np.zeros((ny, nx, 9))
         self.solid = np.zeros((ny, nx), np.uint8)
         self.body = _Body()
@@ -280,6 +283,8 @@ class RefLattice:
         a = np.ascontiguousarray(ux, dtype=np.float64)
         c = np.ascontiguousarray(uy, dtype=np.float64)
         lib().orc_init_fields(C.byref(self.p), r, a, c, self.ft)
+        if self.conv:
+            self.fprev = self.ft.copy()  # before the first step: the initial field
         self.nstep = 0
         self.hist_me.clear()
         self.hist_si.clear()
@@ -293,10 +298,14 @@ class RefLattice:
             me = np.zeros(3)
             si = np.zeros(3)
             npts = 0 if self.si_xy is None else len(self.si_xy)
-            L.orc_step(C.byref(self.p), self.ft, self.fw, self.fn, self.solid, C.byref(self.body), npts,
+            if self.conv and self.fprev is None:
+                self.fprev = self.ft.copy()
+            L.orc_step(C.byref(self.p), self.ft, _ptr(self.fprev), self.fw, self.fn, self.solid, C.byref(self.body), npts,
                        _ptr(self.si_xy), _ptr(self.si_n), _ptr(self.si_ds), _ptr(self.si_node4), _ptr(self.si_w4),
                        self.rho.ctypes.data, self.ux.ctypes.data, self.uy.ctypes.data, me, si.ctypes.data)
             self.ft, self.fn = self.fn, self.ft
+            if self.conv:
+                self.fprev = self.fw.copy()
             self.hist_me.append(me)
             self.hist_si.append(si)
             self.nstep += 1

@@ -38,14 +38,15 @@ static const double W[Q] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.
 static const int OPP[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 static const double CS2 = 1.0 / 3.0; /* c_s^2 = c^2/3 with c = 1 */
 
-enum { EDGE_PERIODIC = 0, EDGE_VELOCITY = 1, EDGE_FREESLIP = 2, EDGE_OUTFLOW = 3 };
+enum { EDGE_PERIODIC = 0, EDGE_VELOCITY = 1, EDGE_FREESLIP = 2, EDGE_OUTFLOW = 3, EDGE_CONVECTIVE = 4 };
 enum { WEST = 0, EAST = 1, SOUTH = 2, NORTH = 3 };
 
 typedef struct {
   int nx, ny;
   double tau, eta, rho0;
   int edge_kind[4];      /* west, east, south, north */
-  double edge_u[4][2];   /* wall / inflow velocity of VELOCITY edges */
+  double edge_u[4][2];   /* wall / inflow velocity of VELOCITY edges; [0] is the
+                            convection speed U of CONVECTIVE edges */
   double gx, gy;         /* uniform external force density (tests) */
   double trt_lambda;     /* > 0: two-relaxation-time collision with this magic
                             parameter (Eq. TRT); <= 0: BGK */
@@ -139,11 +140,21 @@ static int mirror_y(int a) { /* c -> (cx, -cy) */
  *   free-slip : specular reflection -- take the mirrored population from the
  *               edge cell itself in that axis;
  *   velocity  : half-way bounce-back with wall velocity u_w, ends the search:
- *               f_a(x) = ft_abar(x) + 2 w_a rho0 (c_a . u_w) / cs^2.          */
-double orc_stream_value(const orc_params *p, const double *ft, int x, int y, int a) {
+ *               f_a(x) = ft_abar(x) + 2 w_a rho0 (c_a . u_w) / cs^2;
+ *   convective: the convective outflow condition (cited in the application
+ *               section): the incoming population obeys df/dt + U df/dn = 0,
+ *               upwind and implicit in the inner value,
+ *                 f_a(x, t+1) = (f_a(x, t) + U f_a(x - n, t+1)) / (1 + U),
+ *               where f_a(x - n, t+1), the value streamed into the inner
+ *               neighbour, is the value the zero-gradient rule reads, and
+ *               f_a(x, t) is this population's previous streamed value at x
+ *               (fprev).  The first edge crossed (x first) decides; the other
+ *               axis then only resolves the clamped source.                  */
+double orc_stream_value(const orc_params *p, const double *ft, const double *fprev, int x, int y, int a) {
   int nx = p->nx, ny = p->ny;
   int sx = x - CX[a], sy = y - CY[a];
   int pop = a;
+  int conv = -1; /* edge whose convective condition applies */
   if (sx < 0 || sx >= nx) {
     int e = sx < 0 ? WEST : EAST;
     int kind = p->edge_kind[e];
@@ -152,8 +163,9 @@ double orc_stream_value(const orc_params *p, const double *ft, int x, int y, int
       return ft[((size_t)y * nx + x) * Q + OPP[a]] + 2.0 * W[a] * p->rho0 * cu / CS2;
     } else if (kind == EDGE_PERIODIC) {
       sx = (sx + nx) % nx;
-    } else if (kind == EDGE_OUTFLOW) {
+    } else if (kind == EDGE_OUTFLOW || kind == EDGE_CONVECTIVE) {
       sx = sx < 0 ? 0 : nx - 1;
+      if (kind == EDGE_CONVECTIVE) conv = e;
     } else { /* free-slip */
       sx = x;
       pop = mirror_x(pop);
@@ -167,23 +179,31 @@ double orc_stream_value(const orc_params *p, const double *ft, int x, int y, int
       return ft[((size_t)y * nx + x) * Q + OPP[a]] + 2.0 * W[a] * p->rho0 * cu / CS2;
     } else if (kind == EDGE_PERIODIC) {
       sy = (sy + ny) % ny;
-    } else if (kind == EDGE_OUTFLOW) {
+    } else if (kind == EDGE_OUTFLOW || kind == EDGE_CONVECTIVE) {
       sy = sy < 0 ? 0 : ny - 1;
+      if (kind == EDGE_CONVECTIVE && conv < 0) conv = e;
     } else {
       sy = y;
       pop = mirror_y(pop);
     }
   }
-  return ft[((size_t)sy * nx + sx) * Q + pop];
+  double v = ft[((size_t)sy * nx + sx) * Q + pop];
+  if (conv >= 0) {
+    double U = p->edge_u[conv][0];
+    v = (fprev[((size_t)y * nx + x) * Q + a] + U * v) / (1.0 + U);
+  }
+  return v;
 }
 
-void orc_stream(const orc_params *p, const double *ft, double *f) {
+/* fprev: the streamed field of the previous step (the initial field before
+ * the first step); read only by convective edges, may be NULL without them */
+void orc_stream(const orc_params *p, const double *ft, const double *fprev, double *f) {
   int nx = p->nx, ny = p->ny;
 #pragma omp parallel for schedule(static) if ((long)nx * ny >= 65536)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x)
       for (int a = 0; a < Q; ++a)
-        f[((size_t)y * nx + x) * Q + a] = orc_stream_value(p, ft, x, y, a);
+        f[((size_t)y * nx + x) * Q + a] = orc_stream_value(p, ft, fprev, x, y, a);
 }
 
 /* Geometric neighbour x + c: wraps periodic axes, returns 0 when the
@@ -384,18 +404,19 @@ int orc_si_stencils(int nx, int ny, const uint8_t *solid, int npts, const double
 /* ------------------------------------------------------------------------ */
 
 /* ft_prev: post-collision field of step n-1 (input)
+ * f_prev : streamed field of step n-1 (convective edges only; may be NULL)
  * f_work : scratch, receives the streamed pre-collision field f^n
  * ft_next: post-collision field of step n (output)
  * rho/ux/uy: macroscopic fields of step n (may be NULL)
  * me/si  : forces of step n (ME of ft^{n-1}, SI of f^n); si may be NULL.  */
-int orc_step(const orc_params *p, const double *ft_prev, double *f_work, double *ft_next,
-             const uint8_t *solid, const orc_body *b, int npts, const double *si_xy,
+int orc_step(const orc_params *p, const double *ft_prev, const double *f_prev, double *f_work,
+             double *ft_next, const uint8_t *solid, const orc_body *b, int npts, const double *si_xy,
              const double *si_n, const double *si_ds, const int *si_node4, const double *si_w4,
              double *rho_out,
              double *ux_out, double *uy_out, double me[3], double si[3]) {
   int nx = p->nx, ny = p->ny;
   orc_momentum_exchange(p, ft_prev, solid, b, me);
-  orc_stream(p, ft_prev, f_work);
+  orc_stream(p, ft_prev, f_prev, f_work);
   if (si) {
     if (npts > 0)
       orc_stress_integration(p, f_work, npts, si_xy, si_n, si_ds, si_node4, si_w4, b, si);

@@ -41,7 +41,16 @@ constexpr uint8_t M_SOLID = 0x01;   // chi = 1 (Eq. fcar)
 constexpr uint8_t M_SAMPLE = 0x40;  // stress-integration sample node
 constexpr uint8_t M_IFACE = 0x80;   // a lattice neighbour has the other phase
 
-enum { EDGE_PERIODIC = 0, EDGE_VELOCITY = 1, EDGE_FREESLIP = 2, EDGE_OUTFLOW = 3 };
+enum { EDGE_PERIODIC = 0, EDGE_VELOCITY = 1, EDGE_FREESLIP = 2, EDGE_OUTFLOW = 3, EDGE_CONVECTIVE = 4 };
+
+// Convective-edge state: the previous streamed value of each incoming
+// population at each edge cell, [edge][slot][cell along the edge] with the
+// west and east blocks ny long and the south and north blocks nx long.  The
+// slot of a population is its velocity component along the edge (0, +1, -1).
+__host__ __device__ constexpr int cbc_slot(int along) { return along == 0 ? 0 : (along > 0 ? 1 : 2); }
+__host__ __device__ inline long long cbc_offset(int edge, int nx, int ny) {
+  return edge < 2 ? (long long)edge * 3 * ny : 6LL * ny + (long long)(edge - 2) * 3 * nx;
+}
 enum { WEST = 0, EAST = 1, SOUTH = 2, NORTH = 3 };
 enum { MODE_STATIC = 0, MODE_PRESCRIBED = 1, MODE_FREE = 2 };
 enum { SHAPE_NONE = 0, SHAPE_DISK = 1, SHAPE_POLYGON = 2, SHAPE_MASK = 3 };

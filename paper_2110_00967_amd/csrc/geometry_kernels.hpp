@@ -47,6 +47,27 @@ __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int 
   }
 }
 
+// convective-edge state <- the current populations entering through each
+// convective edge (one thread per cell along an edge, all 4 edges)
+template <typename S>
+__global__ void k_cbc_init(const S *__restrict__ f, const StepArgs<typename Store<S>::T> P) {
+  using T = typename Store<S>::T;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, e = blockIdx.y;
+  if (P.kind[e] != EDGE_CONVECTIVE) return;
+  const int len = e < 2 ? P.ny : P.nx;
+  if (i >= len) return;
+  const int x = e == WEST ? 0 : (e == EAST ? P.nx - 1 : i);
+  const int y = e == SOUTH ? 0 : (e == NORTH ? P.ny - 1 : i);
+  const int in = (e == WEST || e == SOUTH) ? 1 : -1;  // inward component along the normal
+#pragma unroll
+  for (int a = 1; a < Q; ++a) {
+    const int cn = e < 2 ? cx(a) : cy(a), ca = e < 2 ? cy(a) : cx(a);
+    if (cn != in) continue;
+    P.cbc[cbc_offset(e, P.nx, P.ny) + (long long)cbc_slot(ca) * len + i] =
+        T(Store<S>::ld(f + (long long)a * P.plane + (long long)y * P.pitch + x));
+  }
+}
+
 // populations f_a = w_a rho0 + d_a of the window columns [x0, x0 + w), rows
 // [row0, row0 + nrows) -> out[9][nrows][w]
 template <typename S>
@@ -526,8 +547,12 @@ __global__ void __launch_bounds__(SI_NT)
     for (int q = 0; q < cnt; ++q) {
       const int x = nodes[q] % P.nx, y = nodes[q] / P.nx;
       double d[Q];
+      {
+        T dt[Q];
+        pull_edge_all<S, T, false>(fin, P, x, y, dt);
 #pragma unroll
-      for (int a = 0; a < Q; ++a) d[a] = double(pull_edge<S, T>(fin, P, x, y, a, cx(a), cy(a)));
+        for (int a = 0; a < Q; ++a) d[a] = double(dt[a]);
+      }
       double drho = 0.0, mx = 0.0, my = 0.0;
 #pragma unroll
       for (int a = 0; a < Q; ++a) {

@@ -43,22 +43,30 @@ template <typename T> struct StepArgs {
   T omega_m, fac_m;     // TRT: 1/tau- and 1 - 1/(2 tau-) (BGK: the same as omega, fac)
   T fo, fo9, fo3;       // tau+ - 1/2, 9 (tau+ - 1/2), 3 (tau- - 1/2)
   double facd, rho0d;
+  T *cbc;               // convective-edge state (see cbc_offset)
+  T cbu[4];             // convection speed U of each convective edge
+  T cbi[4];             // 1 / (1 + U)
 };
 
-// Value of deviation a arriving at (x, y) (any cell, edge or not): axis by
+// Source of deviation a arriving at (x, y) (any cell, edge or not): axis by
 // axis, x first, when x - c_a leaves the lattice: periodic wraps, outflow
 // clamps, free-slip takes the mirrored population of the edge cell itself,
 // velocity bounces back the cell's own opposite population with the
-// moving-wall increment (and ends the resolution).  With c_a fixed only one
-// x edge and one y edge can be crossed; the edge kinds are uniform, so the
-// branches below are uniform and the per-lane part is selects, ending in one
-// unconditional load (no load waits inside divergent code).
-template <typename S, typename T>
-__device__ __forceinline__ T pull_edge(const S *__restrict__ fin, const StepArgs<T> &P, int x,
-                                       int y, int a, int cxa, int cya) {
-  int sx = x - cxa, sy = y - cya, pop = a;
-  bool bb = false;
-  T add = T(0);
+// moving-wall increment `add` (and ends the resolution).  A convective edge
+// resolves its source like outflow; `conv` tells that its blend applies (the
+// first edge crossed, x first, unless a bounce-back ended the resolution).
+// With c_a fixed only one x edge and one y edge can be crossed; the edge
+// kinds are uniform, so the branches are uniform and the per-lane part is
+// selects.
+template <typename T>
+__device__ __forceinline__ void edge_source(const StepArgs<T> &P, int x, int y, int a, int &pop, int &sx,
+                                            int &sy, T &add, bool &conv) {
+  const int cxa = cx(a), cya = cy(a);
+  sx = x - cxa;
+  sy = y - cya;
+  pop = a;
+  bool bb = false, cvx = false, cvy = false;
+  add = T(0);
   // edge parameters are selected with constant indices only (no dynamic
   // indexing of the by-value argument block, which would spill it)
   if (cxa != 0) {
@@ -72,8 +80,9 @@ __device__ __forceinline__ T pull_edge(const S *__restrict__ fin, const StepArgs
                 : T(0);
     } else if (k == EDGE_PERIODIC) {
       sx = out ? (w ? sx + P.nx : sx - P.nx) : sx;
-    } else if (k == EDGE_OUTFLOW) {
+    } else if (k == EDGE_OUTFLOW || k == EDGE_CONVECTIVE) {
       sx = out ? (w ? 0 : P.nx - 1) : sx;
+      cvx = out && k == EDGE_CONVECTIVE;
     } else {
       pop = out ? flipx(pop) : pop;
       sx = out ? x : sx;
@@ -91,8 +100,9 @@ __device__ __forceinline__ T pull_edge(const S *__restrict__ fin, const StepArgs
       bb = bb || out;
     } else if (k == EDGE_PERIODIC) {
       sy = out ? (s_ ? sy + P.ny : sy - P.ny) : sy;
-    } else if (k == EDGE_OUTFLOW) {
+    } else if (k == EDGE_OUTFLOW || k == EDGE_CONVECTIVE) {
       sy = out ? (s_ ? 0 : P.ny - 1) : sy;
+      cvy = out && k == EDGE_CONVECTIVE;
     } else {
       pop = out ? flipy(pop) : pop;
       sy = out ? y : sy;
@@ -103,7 +113,69 @@ __device__ __forceinline__ T pull_edge(const S *__restrict__ fin, const StepArgs
     sx = x;
     sy = y;
   }
-  return Store<S>::ld(fin + (long long)pop * P.plane + (long long)sy * P.pitch + sx) + add;
+  conv = (cvx || cvy) && !bb;
+}
+
+// Convective-edge state slot of population a at (x, y), given that its blend
+// applies: the x edge when a crosses it and it is convective, else the y edge.
+template <typename T>
+__device__ __forceinline__ T *cbc_slot_ptr(const StepArgs<T> &P, int x, int y, int a) {
+  const int cxa = cx(a), cya = cy(a);
+  bool xe = false;
+  if (cxa != 0) {
+    const bool out = cxa > 0 ? x == 0 : x == P.nx - 1;
+    xe = out && (cxa > 0 ? P.kind[WEST] : P.kind[EAST]) == EDGE_CONVECTIVE;
+  }
+  if (xe) return P.cbc + cbc_offset(cxa > 0 ? WEST : EAST, P.nx, P.ny) + (long long)cbc_slot(cya) * P.ny + y;
+  return P.cbc + cbc_offset(cya > 0 ? SOUTH : NORTH, P.nx, P.ny) + (long long)cbc_slot(cxa) * P.nx + x;
+}
+
+template <typename T>
+__device__ __forceinline__ T cbc_speed(const StepArgs<T> &P, int x, int a, bool inv) {
+  const int cxa = cx(a), cya = cy(a);
+  bool xe = false;
+  if (cxa != 0) {
+    const bool out = cxa > 0 ? x == 0 : x == P.nx - 1;
+    xe = out && (cxa > 0 ? P.kind[WEST] : P.kind[EAST]) == EDGE_CONVECTIVE;
+  }
+  const int e = xe ? (cxa > 0 ? WEST : EAST) : (cya > 0 ? SOUTH : NORTH);
+  // constant-index selection (see edge_source)
+  const T u = e == WEST ? P.cbu[WEST] : e == EAST ? P.cbu[EAST] : e == SOUTH ? P.cbu[SOUTH] : P.cbu[NORTH];
+  const T i = e == WEST ? P.cbi[WEST] : e == EAST ? P.cbi[EAST] : e == SOUTH ? P.cbi[SOUTH] : P.cbi[NORTH];
+  return inv ? i : u;
+}
+
+// All 9 deviations arriving at (x, y).  The population loads go out first,
+// together; then convective edges blend f(t+1) = (f(t) + U f_clamped) / (1 + U)
+// with the state f(t) they left at the previous step (and store the new one
+// when UPDATE).  Keeping the state traffic out of the first loop keeps the
+// 9 loads in one memory round trip.
+template <typename S, typename T, bool UPDATE>
+__device__ __forceinline__ void pull_edge_all(const S *__restrict__ fin, const StepArgs<T> &P, int x, int y,
+                                              T (&d)[Q]) {
+  unsigned conv = 0;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    int pop, sx, sy;
+    T add;
+    bool cv;
+    edge_source(P, x, y, a, pop, sx, sy, add, cv);
+    // element index in 32 bits: 9 ny pitch < 2^31 for every accepted lattice
+    d[a] = Store<S>::ld(fin + (pop * (int)P.plane + sy * P.pitch + sx)) + add;
+    conv |= cv ? 1u << a : 0u;
+  }
+  if (conv) {  // only convective edge cells
+    T st[Q];
+#pragma unroll
+    for (int a = 1; a < Q; ++a)
+      if (conv >> a & 1u) st[a] = *cbc_slot_ptr(P, x, y, a);
+#pragma unroll
+    for (int a = 1; a < Q; ++a)
+      if (conv >> a & 1u) {
+        d[a] = (st[a] + cbc_speed(P, x, a, false) * d[a]) * cbc_speed(P, x, a, true);
+        if (UPDATE) *cbc_slot_ptr(P, x, y, a) = d[a];
+      }
+  }
 }
 
 template <int NT, int N>
@@ -221,8 +293,7 @@ __device__ __forceinline__ void step_tile(
       for (int a = 0; a < Q; ++a)
         d[a] = Store<S>::ld(at(fin + (long long)a * P.plane - (long long)cy(a) * P.pitch - cx(a), cb));
     } else {
-#pragma unroll
-      for (int a = 0; a < Q; ++a) d[a] = pull_edge<S, T>(fin, P, x, y, a, cx(a), cy(a));
+      pull_edge_all<S, T, true>(fin, P, x, y, d);
     }
 
     // moments (of the deviations: sum w = 1, sum w c = 0)
@@ -376,8 +447,13 @@ __device__ __forceinline__ void step_tile(
   }
 }
 
+// Resident waves per SIMD the step kernels are compiled for: 8 for 4- and
+// 2-byte storage (register budget 64 VGPRs and the SGPRs that allow 8 waves);
+// FP64 needs more VGPRs and is left to the compiler.
+template <typename S> constexpr int step_waves() { return sizeof(typename Store<S>::T) == 8 ? 1 : 8; }
+
 template <typename S, int BX, int BY, bool MACRO, bool TRT>
-__global__ void __launch_bounds__(BX *BY)
+__global__ void __launch_bounds__(BX *BY, step_waves<S>())
     k_step(const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
            const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl,
            const SiRec *__restrict__ recs, const int *__restrict__ si_map,
@@ -427,7 +503,7 @@ template <typename T> struct CaseDesc {
 // Batched step: launch number `flip` (0 or 1, alternating) of a run over
 // ncases lattices; the lattice of a tile is found by binary search on tile0.
 template <typename S, int BX, int BY, bool TRT>
-__global__ void __launch_bounds__(BX *BY)
+__global__ void __launch_bounds__(BX *BY, step_waves<S>())
     k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
                  const int *__restrict__ tile_case, int total_tiles, int per_xcd, int flip, int first) {
   using T = typename Store<S>::T;

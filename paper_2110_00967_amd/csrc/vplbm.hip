@@ -60,7 +60,7 @@ int pitch_of(const vplbm_params &p) {
 }
 
 struct Layout {
-  size_t A, B, mask, mrho, mux, muy, si_map, partials, partials_stride, sig, sig_stride, hist, ctl, recs, pts,
+  size_t A, B, mask, mrho, mux, muy, si_map, partials, partials_stride, sig, sig_stride, cbc, hist, ctl, recs, pts,
       verts, staging,
       siout, total;
 };
@@ -96,6 +96,8 @@ Layout layout_of(const vplbm_params &p) {
   // stress of each sample node, by step parity (read back by the finalize)
   L.sig_stride = maxrec * SIG_STRIDE * sizeof(double);
   L.sig = take(2 * L.sig_stride);
+  // convective-edge state: 3 incoming populations along each of the 4 edges
+  L.cbc = take((size_t)3 * (2 * (size_t)p.ny + 2 * (size_t)p.nx) * compute_size(p.precision));
   L.pts = take((size_t)5 * maxp * sizeof(double));
   L.verts = take((size_t)2 * maxv * sizeof(long long));
   L.staging = take(STAGE_DOUBLES * sizeof(double));
@@ -105,8 +107,8 @@ Layout layout_of(const vplbm_params &p) {
 }
 
 bool valid_edge(const vplbm_edge &e) {
-  return e.kind >= VPLBM_BC_PERIODIC && e.kind <= VPLBM_BC_OUTFLOW && std::isfinite(e.ux) &&
-         std::isfinite(e.uy);
+  return e.kind >= VPLBM_BC_PERIODIC && e.kind <= VPLBM_BC_CONVECTIVE && std::isfinite(e.ux) &&
+         std::isfinite(e.uy) && (e.kind != VPLBM_BC_CONVECTIVE || e.ux >= 0.0);
 }
 
 const char *check_params(const vplbm_params *p) {
@@ -254,6 +256,12 @@ struct vplbm_lattice {
     a.rho0d = p.rho0;
     a.gx = T(gx);
     a.gy = T(gy);
+    a.cbc = (T *)at(L.cbc);
+    for (int e = 0; e < 4; ++e) {
+      const double U = E[e]->kind == VPLBM_BC_CONVECTIVE ? E[e]->ux : 0.0;
+      a.cbu[e] = T(U);
+      a.cbi[e] = T(1.0 / (1.0 + U));
+    }
     return a;
   }
 };
@@ -349,6 +357,26 @@ int launch_init(vplbm_lattice *L, int row0, int nrows, const double *r, const do
     case VPLBM_F64: return launch_init_s<double>(L, row0, nrows, r, u, v, ru, uu, vu);
     case VPLBM_F32: return launch_init_s<float>(L, row0, nrows, r, u, v, ru, uu, vu);
     default: return launch_init_s<__half>(L, row0, nrows, r, u, v, ru, uu, vu);
+  }
+}
+
+// convective edges: their state starts from the populations just initialized
+template <typename S> int launch_cbc_init_s(vplbm_lattice *L) {
+  const StepArgs<typename Store<S>::T> a = L->step_args<typename Store<S>::T>();
+  const int len = std::max(L->p.nx, L->p.ny);
+  VP_LAUNCH((k_cbc_init<S>), dim3((len + 255) / 256, 4), dim3(256), 0, L->stream, (const S *)L->A(), a);
+  return L->launched("k_cbc_init");
+}
+
+int init_cbc(vplbm_lattice *L) {
+  const vplbm_edge *E[4] = {&L->p.west, &L->p.east, &L->p.south, &L->p.north};
+  bool any = false;
+  for (int e = 0; e < 4; ++e) any = any || E[e]->kind == VPLBM_BC_CONVECTIVE;
+  if (!any) return VPLBM_OK;
+  switch (L->p.precision) {
+    case VPLBM_F64: return launch_cbc_init_s<double>(L);
+    case VPLBM_F32: return launch_cbc_init_s<float>(L);
+    default: return launch_cbc_init_s<__half>(L);
   }
 }
 
@@ -580,8 +608,10 @@ int vplbm_destroy(vplbm_lattice *L) {
 const char *vplbm_last_error(const vplbm_lattice *L) { return L ? L->err.c_str() : g_create_err.c_str(); }
 
 static int reset_counters(vplbm_lattice *L) {
+  int rc = init_cbc(L);
+  if (rc) return rc;
   Ctl c;
-  int rc = L->ctl_pull(c);
+  rc = L->ctl_pull(c);
   if (rc) return rc;
   c.step = 0;
   for (int i = 0; i < 6; ++i) c.last[i] = 0.0;

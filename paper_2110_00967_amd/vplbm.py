@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("VPLBM_LIBRARY") or os.path.join(HERE, "libvplbm.so")
 
 F64, F32, F16DEV = 0, 1, 2
 PRECISIONS = {"f64": F64, "f32": F32, "f16dev": F16DEV}
-PERIODIC, VELOCITY, FREESLIP, OUTFLOW = 0, 1, 2, 3
+PERIODIC, VELOCITY, FREESLIP, OUTFLOW, CONVECTIVE = 0, 1, 2, 3, 4
 FORCE_ME, FORCE_SI = 0, 1
 STEP_MACRO = 1
 

@@ -11,7 +11,7 @@ import numpy as np
 import oracle as O
 import workloads as W
 
-P, V_, F, OUT = W.PERIODIC, W.VELOCITY, W.FREESLIP, W.OUTFLOW
+P, V_, F, OUT, CV = W.PERIODIC, W.VELOCITY, W.FREESLIP, W.OUTFLOW, W.CONVECTIVE
 
 
 def say(*a):

@@ -65,6 +65,7 @@ def test_required_bytes_valid():
     dict(nx=200000, ny=200000), dict(max_si_points=5000), dict(hist_capacity=-1),
     dict(trt_lambda=-0.1), dict(trt_lambda=float("nan")), dict(nx=20000), dict(si_rule=2), dict(si_rule=-1),
     dict(si_rule=1, max_si_points=1025), dict(si_rule=1, max_si_points=0),
+    dict(east=(V.CONVECTIVE, -0.01, 0)), dict(east=(V.CONVECTIVE, float("nan"), 0)), dict(east=(5, 0, 0)),
 ])
 def test_required_bytes_rejects(kw):
     assert V.required_bytes(base(**kw)) == 0
@@ -75,6 +76,11 @@ def test_si_rule_interpolated_accepts_up_to_1024_points():
     n0 = V.required_bytes(base(si_rule=0, max_si_points=1024))
     # room for 4 sample records (48 bytes each) per point instead of 1
     assert n1 - n0 >= 3 * 1024 * 48
+
+
+def test_convective_edge_accepted():
+    assert V.required_bytes(base(east=(V.CONVECTIVE, 0.05, 0))) > 0
+    assert V.required_bytes(base(east=(V.CONVECTIVE, 0.0, 0))) > 0
 
 
 def test_eta_infinite_is_allowed():

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_cases import F, OUT, P, V_, build_gpu, build_oracle, oracle_pops, random_fields, say, small_naca, spec
+from gpu_cases import CV, F, OUT, P, V_, build_gpu, build_oracle, oracle_pops, random_fields, say, small_naca, spec
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +25,8 @@ def mixed_specs():
              gx=1e-6, disk=(40.0, 18.0, 6.0), init=("fields",) + random_fields(131, 37, 5, amp=0.01)),
         spec(300, 130, tau=0.65, disk=(150.3, 64.6, 20.2), si=W.disk_si_points(150.3, 64.6, 20.2, 128),
              init=("fields",) + random_fields(300, 130, 3)),
+        spec(96, 40, tau=0.6, edges=((V_, 0.04, 0), (CV, 0.04, 0), (F, 0, 0), (V_, 0, 0)), disk=(30.0, 20.0, 5.0),
+             init=("uniform", 1.0, 0.04, 0.0)),
     ]
 
 
@@ -36,7 +38,7 @@ def state(g):
 def test_batch_equals_alone_bitwise(precision):
     from paper_2110_00967_amd import vplbm as V
     specs = mixed_specs()
-    nsteps = [40, 17, 33, 0, 26]
+    nsteps = [40, 17, 33, 0, 26, 35]
     say("batch of", len(specs), "lattices,", precision, "steps", nsteps)
     alone = []
     for s, n in zip(specs, nsteps):
@@ -55,8 +57,8 @@ def test_batch_equals_alone_bitwise(precision):
         for a, r in zip(got, ref):
             assert np.array_equal(a, r), (precision, k)
     # a second round with the roles changed (chunks of different shapes)
-    b.step([5, 0, 12, 9, 1])
-    assert [g.step_count for g in lats] == [45, 17, 45, 9, 27]
+    b.step([5, 0, 12, 9, 1, 3])
+    assert [g.step_count for g in lats] == [45, 17, 45, 9, 27, 38]
     b.close()
 
 

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_cases import (F, OUT, P, V_, build_gpu, build_oracle, oracle_pops, random_fields, rel_l2, say,
+from gpu_cases import (CV, F, OUT, P, V_, build_gpu, build_oracle, oracle_pops, random_fields, rel_l2, say,
                        small_naca, spec)
 
 pytestmark = pytest.mark.gpu
@@ -91,6 +91,20 @@ RAGGED["si_interpolated_disk_random"] = spec(150, 45, tau=0.65, si_rule=1, disk=
 RAGGED["si_interpolated_naca"] = spec(150, 75, tau=0.56, si_rule=1,
                                       edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)),
                                       polygon=_poly, ref=_ref, si=_si, init=("uniform", 1.0, 0.05, 0.0))
+RAGGED["convective_east_disk"] = spec(150, 45, tau=0.6, edges=((V_, 0.05, 0), (CV, 0.05, 0), (F, 0, 0), (F, 0, 0)),
+                                     disk=(60.3, 21.6, 8.2), si=W.disk_si_points(60.3, 21.6, 8.2, 64),
+                                     init=("fields",) + tuple(np.asarray(v) + (0.05 if k == 1 else 0.0) for k, v in
+                                                             enumerate(random_fields(150, 45, 31, amp=0.01))))
+RAGGED["convective_north_velocity_south"] = spec(70, 90, tau=0.75, edges=((F, 0, 0), (F, 0, 0), (V_, 0, 0.02),
+                                                                         (CV, 0.02, 0)),
+                                                 disk=(35.0, 45.0, 8.0), init=("uniform", 1.0, 0.0, 0.02))
+RAGGED["convective_east_and_north_corner"] = spec(67, 53, tau=0.65, edges=((V_, 0.03, 0.01), (CV, 0.04, 0), (V_, 0, 0),
+                                                                          (CV, 0.3, 0)),
+                                                  disk=(30.2, 25.1, 6.3),
+                                                  init=("fields",) + random_fields(67, 53, 41, amp=0.02))
+RAGGED["convective_trt_naca"] = spec(150, 75, tau=0.55, trt=1.0 / 6.0,
+                                     edges=((V_, 0.05, 0), (CV, 0.05, 0), (F, 0, 0), (F, 0, 0)),
+                                     polygon=_poly, ref=_ref, si=_si, init=("uniform", 1.0, 0.05, 0.0))
 _m = np.zeros((45, 77), np.uint8)
 _m[0:6, :] = 1
 _m[20:30, 10:14] = 1

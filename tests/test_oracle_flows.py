@@ -14,6 +14,10 @@ collision) against flows with closed-form solutions.
   * Penalized walls (solid bands, Eq. 1): first-order convergence to the
     parabola with walls half a cell outside the mask.
   * Mass: the penalization and forcing carry no mass, so sum rho is constant.
+  * Convective outflow f(t+1) = (f(t) + U f_inner(t+1)) / (1 + U): uniform
+    flow stays a fixed point; U -> infinity is the zero-gradient rule; U = 0
+    freezes the incoming populations at their initial values; its steady
+    state (f = f_inner) is the zero-gradient one.
 """
 import math
 
@@ -233,3 +237,88 @@ def test_trt_with_equal_rates_is_bgk():
         lat.step(30)
     assert np.abs(a.ft - b.ft).max() <= 1e-14
     assert np.abs(a.me()[-1] - b.me()[-1]).max() <= 1e-12
+
+
+# ----------------------------------------------------------------------------
+# convective outflow edge
+# ----------------------------------------------------------------------------
+
+def disk_channel_lattice(east, south=(O.FREESLIP, 0, 0), north=(O.FREESLIP, 0, 0), tau=0.6, nx=40, ny=18):
+    lat = O.RefLattice(nx, ny, tau, 1e-3, west=(O.VELOCITY, 0.04, 0), east=east, south=south, north=north)
+    lat.set_disk(14.3, 8.6, 3.7)
+    ux, uy = W.smooth_random_velocity(nx, ny, seed=4, amp=0.02)
+    lat.set_fields(W.random_density(nx, ny, seed=5, amp=1e-3), 0.04 + ux, uy)
+    return lat
+
+
+@pytest.mark.parametrize("sides", [O.FREESLIP, O.PERIODIC])
+def test_convective_uniform_flow_is_a_fixed_point(sides):
+    U = 0.05
+    lat = O.RefLattice(24, 10, 0.53, float("inf"), west=(O.VELOCITY, U, 0), east=(O.CONVECTIVE, U, 0),
+                       south=(sides, 0, 0), north=(sides, 0, 0))
+    lat.init_uniform(1.0, U, 0.0)
+    f0 = lat.ft.copy()
+    lat.step(50)
+    assert np.abs(lat.ft - f0).max() <= 1e-14
+
+
+def test_convective_vertical_uniform_flow_is_a_fixed_point():
+    V = -0.03
+    lat = O.RefLattice(8, 20, 0.6, float("inf"), west=(O.FREESLIP, 0, 0), east=(O.FREESLIP, 0, 0),
+                       south=(O.CONVECTIVE, 0.03, 0), north=(O.VELOCITY, 0, V))
+    lat.init_uniform(1.0, 0.0, V)
+    f0 = lat.ft.copy()
+    lat.step(40)
+    assert np.abs(lat.ft - f0).max() <= 1e-14
+
+
+def test_convective_infinite_speed_is_zero_gradient():
+    a = disk_channel_lattice((O.CONVECTIVE, 1e12, 0))
+    b = disk_channel_lattice((O.OUTFLOW, 0, 0))
+    for _ in range(6):
+        a.step(5)
+        b.step(5)
+        assert np.abs(a.ft - b.ft).max() <= 1e-10
+
+
+def test_convective_zero_speed_freezes_incoming_populations():
+    # U = 0: the populations entering through the east edge keep their initial
+    # streamed values exactly, while the flow inside evolves
+    lat = disk_channel_lattice((O.CONVECTIVE, 0.0, 0))
+    f0 = lat.ft.copy()
+    inflow = [3, 6, 7]  # c_x < 0
+    for _ in range(4):
+        lat.step(7)
+        assert np.array_equal(lat.streamed()[:, -1, inflow], f0[:, -1, inflow])
+    assert np.abs(lat.ft[:, :-1] - f0[:, :-1]).max() > 1e-6
+
+
+@pytest.mark.parametrize("U", [0.37, 0.02])
+def test_convective_one_step_blend(U):
+    # periodic south/north, so the inner value of incoming population a at
+    # (nx-1, y) is ft[(y - c_y) mod ny, nx-1, a] (the zero-gradient source).
+    # (i) previous value = inner value: the step equals the zero-gradient
+    # step; (ii) previous value = inner value + d: the incoming populations
+    # come out as the zero-gradient ones + d / (1 + U), nothing else changes
+    per = (O.PERIODIC, 0, 0)
+    a = disk_channel_lattice((O.CONVECTIVE, U, 0), south=per, north=per)
+    b = disk_channel_lattice((O.OUTFLOW, 0, 0), south=per, north=per)
+    a.step(9)
+    b.ft[:] = a.ft
+    ny = a.ny
+    inner = np.zeros((ny, 9))
+    for k in (3, 6, 7):
+        inner[:, k] = a.ft[(np.arange(ny) - O.CY[k]) % ny, -1, k]
+    d = np.zeros((ny, 9))
+    d[:, [3, 6, 7]] = np.random.default_rng(1).normal(0.0, 1e-3, (ny, 3))
+    for dd in (0.0 * d, d):
+        a.ft[:] = b.ft
+        a.fprev[:, -1, :] = inner + dd
+        a.step(1)
+        b2 = disk_channel_lattice((O.OUTFLOW, 0, 0), south=per, north=per)
+        b2.ft[:] = b.ft
+        b2.step(1)
+        s_a, s_b = a.streamed(), b2.streamed()
+        expect = s_b.copy()
+        expect[:, -1, :] += dd / (1.0 + U)
+        assert np.abs(s_a - expect).max() <= 2e-16

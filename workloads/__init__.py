@@ -29,8 +29,9 @@ from typing import Optional
 import numpy as np
 
 # Edge condition kinds (the integers are part of the C ABI of both sides).
-PERIODIC, VELOCITY, FREESLIP, OUTFLOW = 0, 1, 2, 3
-EDGE_NAMES = {PERIODIC: "periodic", VELOCITY: "velocity", FREESLIP: "freeslip", OUTFLOW: "outflow"}
+PERIODIC, VELOCITY, FREESLIP, OUTFLOW, CONVECTIVE = 0, 1, 2, 3, 4
+EDGE_NAMES = {PERIODIC: "periodic", VELOCITY: "velocity", FREESLIP: "freeslip", OUTFLOW: "outflow",
+              CONVECTIVE: "convective"}
 
 
 @dataclasses.dataclass
