@@ -60,15 +60,16 @@ def lib():
         L.orc_forcing.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
         L.orc_cell_macro.argtypes = [P, dp, C.c_int, C.c_double, C.c_double] + [C.POINTER(C.c_double)] * 5
         L.orc_stream.argtypes = [P, dp, C.c_void_p, dp]
-        L.orc_momentum_exchange.argtypes = [P, dp, up, B, dp]
+        L.orc_momentum_exchange.argtypes = [P, dp, up, B, C.c_int, dp]
         L.orc_node_stress.argtypes = [P, dp, dp]
-        L.orc_stress_integration.argtypes = [P, dp, C.c_int, dp, dp, dp, ip, dp, B, dp]
+        L.orc_stress_integration.argtypes = [P, dp, C.c_int, dp, dp, dp, ip, dp, ip, B, C.c_int, dp]
         L.orc_si_stencils.argtypes = [C.c_int, C.c_int, up, C.c_int, dp, dp, C.c_int, ip, dp]
         L.orc_si_stencils.restype = C.c_int
         L.orc_si_nodes.argtypes = [C.c_int, C.c_int, up, C.c_int, dp, dp, ip]
         L.orc_si_nodes.restype = C.c_int
-        L.orc_step.argtypes = [P, dp, C.c_void_p, dp, dp, up, B, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_void_p]
+        L.orc_step.argtypes = [P, dp, C.c_void_p, dp, dp, up, B, C.c_int, C.c_int, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, dp, C.c_void_p]
         L.orc_init_fields.argtypes = [P, dp, dp, dp, dp]
         L.orc_mask_disk.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, up]
         L.orc_mask_disk.restype = C.c_int
@@ -154,8 +155,8 @@ class RefLattice:
         self.conv = any(int(e[0]) == CONVECTIVE for e in (west, east, south, north))
         self.fprev = None
         self.fn = np.zeros((ny, nx, 9))
-        self.solid = np.zeros((ny, nx), np.uint8)
-        self.body = _Body()
+        self.solid = np.zeros((ny, nx), np.uint8)  # body id per cell, 0 = fluid
+        self.bodies = (_Body * 1)()                 # body 1 = bodies[0]
         self.shape = None  # ("disk", r) | ("polygon", verts_body_frame) | ("mask",)
         self.mode = "static"  # static | prescribed | free
         self.mass = self.inertia = self.rho_s = None
@@ -163,11 +164,21 @@ class RefLattice:
         self.source = 0
         self.si_body = None  # body-frame points when the body moves
         self.si_xy = self.si_n = self.si_ds = self.si_node = self.si_node4 = self.si_w4 = None
+        self.si_pbody = None   # body (1..nbody) of each registered point
+        self.si_sets = {}      # body -> (xy, n, ds) of a static multi-body lattice
         self.si_rule = si_rule
         self.rho = self.ux = self.uy = None
         self.hist_me = []
         self.hist_si = []
         self.nstep = 0
+
+    @property
+    def body(self):
+        return self.bodies[0]
+
+    @property
+    def nbody(self):
+        return len(self.bodies)
 
     @classmethod
     def from_case(cls, case):
@@ -199,6 +210,35 @@ class RefLattice:
     def set_mask(self, m):
         self.shape = ("mask",)
         self.solid[:] = (np.asarray(m) != 0).astype(np.uint8)
+        self._select_si()
+
+    def set_body_ids(self, ids, refs):
+        """Several static bodies: ids[y, x] in 0..nbody (0 = fluid) and each
+        body's reference point (torques are taken about it)."""
+        refs = np.asarray(refs, dtype=np.float64).reshape(-1, 2)
+        self.shape = ("ids",)
+        self.mode = "static"
+        self.bodies = (_Body * len(refs))()
+        for b, (x, y) in zip(self.bodies, refs):
+            b.x, b.y = float(x), float(y)
+        self.solid[:] = np.asarray(ids, dtype=np.uint8)
+        assert self.solid.max() <= len(refs)
+        self.si_sets = {}
+        self.si_xy = self.si_n = self.si_ds = self.si_pbody = None
+        self.si_node = self.si_node4 = self.si_w4 = None
+
+    def set_si_points_body(self, body, xy, nrm, ds):
+        """Stress-integration points of one body of a static multi-body lattice."""
+        assert self.mode == "static" and 1 <= body <= self.nbody
+        self.si_sets[body] = tuple(np.ascontiguousarray(a, dtype=np.float64).copy() for a in (xy, nrm, ds))
+        keys = sorted(k for k in self.si_sets if len(self.si_sets[k][2]))
+        if not keys:
+            self.si_xy = None
+            return
+        self.si_xy = np.ascontiguousarray(np.concatenate([self.si_sets[k][0] for k in keys]))
+        self.si_n = np.ascontiguousarray(np.concatenate([self.si_sets[k][1] for k in keys]))
+        self.si_ds = np.ascontiguousarray(np.concatenate([self.si_sets[k][2] for k in keys]))
+        self.si_pbody = np.concatenate([np.full(len(self.si_sets[k][2]), k, np.int32) for k in keys])
         self._select_si()
 
     def _rebuild_mask(self):
@@ -237,6 +277,7 @@ class RefLattice:
         self.si_xy = np.ascontiguousarray(xy, dtype=np.float64).copy()
         self.si_n = np.ascontiguousarray(nrm, dtype=np.float64).copy()
         self.si_ds = np.ascontiguousarray(ds, dtype=np.float64).copy()
+        self.si_pbody = np.ones(len(self.si_ds), np.int32)  # body 1
         if self.mode != "static":
             self._register_si_body_frame()
         self._select_si()
@@ -272,10 +313,11 @@ class RefLattice:
         R = np.full((self.ny, self.nx), float(rho))
         UX = np.full((self.ny, self.nx), float(ux))
         UY = np.full((self.ny, self.nx), float(uy))
-        b = self.body
         ys, xs = np.nonzero(self.solid)
-        UX[ys, xs] = b.u - b.omega * (ys - b.y)
-        UY[ys, xs] = b.v + b.omega * (xs - b.x)
+        for k, b in enumerate(self.bodies):
+            sel = self.solid[ys, xs] == k + 1
+            UX[ys[sel], xs[sel]] = b.u - b.omega * (ys[sel] - b.y)
+            UY[ys[sel], xs[sel]] = b.v + b.omega * (xs[sel] - b.x)
         self.set_fields(R, UX, UY)
 
     def set_fields(self, rho, ux, uy):
@@ -295,22 +337,24 @@ class RefLattice:
             self.rho = np.zeros((self.ny, self.nx))
             self.ux = np.zeros((self.ny, self.nx))
             self.uy = np.zeros((self.ny, self.nx))
-            me = np.zeros(3)
-            si = np.zeros(3)
+            nb = self.nbody
+            me = np.zeros(3 * nb)
+            si = np.zeros(3 * nb)
             npts = 0 if self.si_xy is None else len(self.si_xy)
             if self.conv and self.fprev is None:
                 self.fprev = self.ft.copy()
-            L.orc_step(C.byref(self.p), self.ft, _ptr(self.fprev), self.fw, self.fn, self.solid, C.byref(self.body), npts,
-                       _ptr(self.si_xy), _ptr(self.si_n), _ptr(self.si_ds), _ptr(self.si_node4), _ptr(self.si_w4),
-                       self.rho.ctypes.data, self.ux.ctypes.data, self.uy.ctypes.data, me, si.ctypes.data)
+            L.orc_step(C.byref(self.p), self.ft, _ptr(self.fprev), self.fw, self.fn, self.solid, self.bodies, nb,
+                       npts, _ptr(self.si_xy), _ptr(self.si_n), _ptr(self.si_ds), _ptr(self.si_pbody),
+                       _ptr(self.si_node4), _ptr(self.si_w4), self.rho.ctypes.data, self.ux.ctypes.data,
+                       self.uy.ctypes.data, me, si.ctypes.data)
             self.ft, self.fn = self.fn, self.ft
             if self.conv:
                 self.fprev = self.fw.copy()
-            self.hist_me.append(me)
-            self.hist_si.append(si)
+            self.hist_me.append(me.reshape(nb, 3))
+            self.hist_si.append(si.reshape(nb, 3))
             self.nstep += 1
             if self.mode == "free":
-                FT = np.ascontiguousarray(me if self.source == 0 else si)
+                FT = np.ascontiguousarray((me if self.source == 0 else si)[:3])
                 L.orc_body_update(C.byref(self.body), FT, self.mass, self.inertia, self.p.rho0,
                                   self.rho_s, self.grav[0], self.grav[1])
             elif self.mode == "prescribed":
@@ -334,8 +378,10 @@ class RefLattice:
         b = self.body
         return np.array([b.x, b.y, b.theta, b.u, b.v, b.omega])
 
-    def me(self):
-        return np.array(self.hist_me)
+    def me(self, body=1):
+        """Momentum-exchange history of one body, shape (steps, 3)."""
+        return np.array([h[body - 1] for h in self.hist_me]).reshape(-1, 3)
 
-    def si(self):
-        return np.array(self.hist_si)
+    def si(self, body=1):
+        """Stress-integration history of one body, shape (steps, 3)."""
+        return np.array([h[body - 1] for h in self.hist_si]).reshape(-1, 3)

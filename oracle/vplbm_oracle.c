@@ -235,17 +235,22 @@ static int neighbour(const orc_params *p, int x, int y, int cx, int cy, int *ox,
  * fluidtorque).  The interface point of a link is its midpoint,
  * x_f + c_a/2, measured from the fluid node; u_G there is the rigid-body
  * velocity.  ft is the post-collision field (the tilde of Eq. MMEL). */
-void orc_momentum_exchange(const orc_params *p, const double *ft, const uint8_t *solid,
-                           const orc_body *b, double out[3]) {
-  double Fx = 0.0, Fy = 0.0, T = 0.0;
+void orc_momentum_exchange(const orc_params *p, const double *ft, const uint8_t *ids,
+                           const orc_body *bodies, int nbody, double *out) {
+  /* ids: body id of each cell (0 = fluid, 1..nbody); a link belongs to the
+   * body of its solid node, its torque is taken about that body's reference
+   * point and u_Gamma is that body's rigid velocity.  out[3 (b - 1) + k]. */
+  for (int k = 0; k < 3 * nbody; ++k) out[k] = 0.0;
   int nx = p->nx, ny = p->ny;
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
-      if (solid[(size_t)y * nx + x]) continue;
+      if (ids[(size_t)y * nx + x]) continue;
       for (int a = 1; a < Q; ++a) {
         int sx, sy;
         if (!neighbour(p, x, y, CX[a], CY[a], &sx, &sy)) continue;
-        if (!solid[(size_t)sy * nx + sx]) continue;
+        int id = ids[(size_t)sy * nx + sx];
+        if (!id) continue;
+        const orc_body *b = &bodies[id - 1];
         double gx = x + 0.5 * CX[a], gy = y + 0.5 * CY[a];
         double ugx, ugy;
         rigid_velocity(b, gx, gy, &ugx, &ugy);
@@ -253,14 +258,12 @@ void orc_momentum_exchange(const orc_params *p, const double *ft, const uint8_t 
         double fi = ft[((size_t)sy * nx + sx) * Q + OPP[a]];
         double lx = (CX[a] - ugx) * fo - (CX[OPP[a]] - ugx) * fi;
         double ly = (CY[a] - ugy) * fo - (CY[OPP[a]] - ugy) * fi;
-        Fx += lx;
-        Fy += ly;
-        T += (gx - b->x) * ly - (gy - b->y) * lx;
+        double *o = &out[3 * (id - 1)];
+        o[0] += lx;
+        o[1] += ly;
+        o[2] += (gx - b->x) * ly - (gy - b->y) * lx;
       }
     }
-  out[0] = Fx;
-  out[1] = Fy;
-  out[2] = T;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -295,8 +298,9 @@ void orc_node_stress(const orc_params *p, const double f[Q], double s[3]) {
  * y*nx + x, -1 = unused) with weights w4 (see orc_si_stencils). */
 void orc_stress_integration(const orc_params *p, const double *f, int npts, const double *xy,
                             const double *nrm, const double *ds, const int *node4, const double *w4,
-                            const orc_body *b, double out[3]) {
-  double Fx = 0.0, Fy = 0.0, T = 0.0;
+                            const int *pbody, const orc_body *bodies, int nbody, double *out) {
+  /* pbody[i]: body (1..nbody) point i belongs to; out[3 (b - 1) + k] */
+  for (int k = 0; k < 3 * nbody; ++k) out[k] = 0.0;
   for (int i = 0; i < npts; ++i) {
     double s[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < 4; ++k) {
@@ -305,17 +309,16 @@ void orc_stress_integration(const orc_params *p, const double *f, int npts, cons
       orc_node_stress(p, &f[(size_t)node4[4 * i + k] * Q], sk);
       for (int m = 0; m < 3; ++m) s[m] += w4[4 * i + k] * sk[m];
     }
+    const orc_body *b = &bodies[pbody[i] - 1];
     double nx_ = nrm[2 * i], ny_ = nrm[2 * i + 1];
     double tx = ds[i] * (s[0] * nx_ + s[1] * ny_);
     double ty = ds[i] * (s[1] * nx_ + s[2] * ny_);
     double rx = xy[2 * i] - b->x, ry = xy[2 * i + 1] - b->y;
-    Fx += tx;
-    Fy += ty;
-    T += rx * ty - ry * tx;
+    double *o = &out[3 * (pbody[i] - 1)];
+    o[0] += tx;
+    o[1] += ty;
+    o[2] += rx * ty - ry * tx;
   }
-  out[0] = Fx;
-  out[1] = Fy;
-  out[2] = T;
 }
 
 /* Sample node of each integration point.  The paper takes f "from the
@@ -403,25 +406,28 @@ int orc_si_stencils(int nx, int ny, const uint8_t *solid, int npts, const double
 /* one full step                                                              */
 /* ------------------------------------------------------------------------ */
 
-/* ft_prev: post-collision field of step n-1 (input)
+/* solid  : body id of each cell (0 = fluid, 1..nbody), chi = (id != 0)
+ * bodies : the nbody rigid bodies (reference point, velocities)
+ * ft_prev: post-collision field of step n-1 (input)
  * f_prev : streamed field of step n-1 (convective edges only; may be NULL)
  * f_work : scratch, receives the streamed pre-collision field f^n
  * ft_next: post-collision field of step n (output)
  * rho/ux/uy: macroscopic fields of step n (may be NULL)
- * me/si  : forces of step n (ME of ft^{n-1}, SI of f^n); si may be NULL.  */
+ * me/si  : forces of step n per body, 3 each (ME of ft^{n-1}, SI of f^n);
+ *          si may be NULL.  */
 int orc_step(const orc_params *p, const double *ft_prev, const double *f_prev, double *f_work,
-             double *ft_next, const uint8_t *solid, const orc_body *b, int npts, const double *si_xy,
-             const double *si_n, const double *si_ds, const int *si_node4, const double *si_w4,
-             double *rho_out,
-             double *ux_out, double *uy_out, double me[3], double si[3]) {
+             double *ft_next, const uint8_t *solid, const orc_body *bodies, int nbody, int npts,
+             const double *si_xy, const double *si_n, const double *si_ds, const int *si_body,
+             const int *si_node4, const double *si_w4, double *rho_out, double *ux_out, double *uy_out,
+             double *me, double *si) {
   int nx = p->nx, ny = p->ny;
-  orc_momentum_exchange(p, ft_prev, solid, b, me);
+  orc_momentum_exchange(p, ft_prev, solid, bodies, nbody, me);
   orc_stream(p, ft_prev, f_prev, f_work);
   if (si) {
     if (npts > 0)
-      orc_stress_integration(p, f_work, npts, si_xy, si_n, si_ds, si_node4, si_w4, b, si);
+      orc_stress_integration(p, f_work, npts, si_xy, si_n, si_ds, si_node4, si_w4, si_body, bodies, nbody, si);
     else
-      si[0] = si[1] = si[2] = 0.0;
+      for (int k = 0; k < 3 * nbody; ++k) si[k] = 0.0;
   }
   double fac = 1.0 - 1.0 / (2.0 * p->tau);
   /* TRT (Eq. TRT): tau+ = tau sets the viscosity, tau- = Lambda/(tau+ - 1/2) + 1/2 */
@@ -433,7 +439,7 @@ int orc_step(const orc_params *p, const double *ft_prev, const double *f_prev, d
       const double *f = &f_work[c * Q];
       int chi = solid[c] ? 1 : 0;
       double usx = 0.0, usy = 0.0;
-      if (chi) rigid_velocity(b, (double)x, (double)y, &usx, &usy);
+      if (chi) rigid_velocity(&bodies[solid[c] - 1], (double)x, (double)y, &usx, &usy);
       double rho, ux, uy, Fx, Fy, feq[Q], Fa[Q];
       orc_cell_macro(p, f, chi, usx, usy, &rho, &ux, &uy, &Fx, &Fy);
       orc_equilibrium(rho, ux, uy, feq);

@@ -50,7 +50,7 @@ def test_me_momentum_balance_identity():
         before = solid_momentum(lat.ft, lat.solid)
         lat.step(1)
         after = solid_momentum(lat.streamed(), lat.solid)
-        me = lat.hist_me[-1]
+        me = lat.me()[-1]
         assert np.abs((after - before) - me[:2]).max() <= 1e-14 * max(1.0, np.abs(me[:2]).max())
 
 
@@ -89,7 +89,7 @@ def test_me_link_form_equals_pulled_form_moving_body():
     random_state(lat, 31)
     body = lat.body_state().copy()
     lat.step(1)
-    me = lat.hist_me[-1]
+    me = lat.me()[-1]
     ref = pulled_form(lat, lat.streamed(), body)
     assert np.abs(me - ref).max() <= 1e-14 * np.abs(ref).max()
 
@@ -156,14 +156,14 @@ def test_si_poiseuille_shear():
     lat.set_si_points(xy, n, np.ones(nx))
     lat.init_uniform(1.0, 0.0, 0.0)
     lat.step(int(30 * ny * ny / nu))
-    Fx = lat.hist_si[-1][0]
+    Fx = lat.si()[-1][0]
     assert abs(Fx - nx * G / 2 * (ny - 1 - 2 * y0)) <= 1e-9 * abs(Fx)
     # lower wall line, normal pointing down: the fluid pulls the wall along +x
     xy[:, 1] = 0
     n[:, 1] = -1.0
     lat.set_si_points(xy, n, np.ones(nx))
     lat.step(1)
-    assert abs(lat.hist_si[-1][0] + nx * G / 2 * (ny - 1)) <= 1e-9 * nx * G * ny
+    assert abs(lat.si()[-1][0] + nx * G / 2 * (ny - 1)) <= 1e-9 * nx * G * ny
 
 
 def test_si_taylor_green_stress():
@@ -228,7 +228,7 @@ def test_si_interpolated_poiseuille_shear_exact():
     lat.step(int(30 * ny * ny / nu))
     yp = y0 + 1.5
     ref = len(xy) * G / 2 * (ny - 1 - 2 * yp)
-    assert abs(lat.hist_si[-1][0] - ref) <= 1e-9 * abs(ref)
+    assert abs(lat.si()[-1][0] - ref) <= 1e-9 * abs(ref)
 
 
 def test_si_interpolated_stencil_properties():
@@ -264,3 +264,102 @@ def test_si_interpolated_zero_force_uniform_flow():
     lat.set_fields(one, U[0] * one, U[1] * one)
     lat.step(10)
     assert np.abs(lat.si()).max() <= 1e-13
+
+
+# ----------------------------------------------------------------------------
+# several bodies in one lattice: ids in the mask, forces per body
+# ----------------------------------------------------------------------------
+
+def three_bodies(nx=72, ny=40):
+    ids = np.zeros((ny, nx), np.uint8)
+    ids[O.mask_disk(nx, ny, 16.3, 20.2, 5.6) != 0] = 1
+    ids[O.mask_disk(nx, ny, 38.1, 12.7, 4.4) != 0] = 2
+    poly = np.array([[50.2, 22.1], [62.7, 24.3], [58.4, 33.8], [49.6, 30.2]])
+    ids[O.mask_polygon(nx, ny, poly) != 0] = 3
+    pts = {1: W.disk_si_points(16.3, 20.2, 5.6, 40), 2: W.disk_si_points(38.1, 12.7, 4.4, 32),
+           3: W.polygon_si_points(poly)}
+    return ids, pts
+
+
+def multi_lattice(ids, refs, pts, seed=7, nx=72, ny=40):
+    lat = O.RefLattice(nx, ny, 0.65, 1e-3, west=(O.VELOCITY, 0.03, 0), east=(O.OUTFLOW, 0, 0),
+                       south=(O.FREESLIP, 0, 0), north=(O.FREESLIP, 0, 0))
+    lat.set_body_ids(ids, refs)
+    for b, (xy, n, ds) in pts.items():
+        lat.set_si_points_body(b, xy, n, ds)
+    random_state(lat, seed)
+    return lat
+
+
+def test_multibody_forces_add_up_to_the_union():
+    ids, pts = three_bodies()
+    Z = (40.0, 20.0)
+    a = multi_lattice(ids, [Z] * 3, pts)
+    allp = tuple(np.concatenate([pts[b][k] for b in (1, 2, 3)]) for k in range(3))
+    b = multi_lattice((ids > 0).astype(np.uint8), [Z], {1: allp})
+    a.step(12)
+    b.step(12)
+    me = sum(a.me(k) for k in (1, 2, 3))
+    si = sum(a.si(k) for k in (1, 2, 3))
+    assert np.abs(me - b.me(1)).max() <= 1e-13 * np.abs(b.me(1)).max()
+    assert np.abs(si - b.si(1)).max() <= 1e-13 * np.abs(b.si(1)).max()
+    assert np.abs(a.ft - b.ft).max() == 0.0  # attribution does not touch the flow
+
+
+def test_multibody_torque_about_each_reference():
+    # T about r_b = T about Z + (Z - r_b) x F, for both methods
+    ids, pts = three_bodies()
+    Z = (40.0, 20.0)
+    refs = [(16.3, 20.2), (38.1, 12.7), (55.0, 27.0)]
+    a = multi_lattice(ids, refs, pts)
+    z = multi_lattice(ids, [Z] * 3, pts)
+    a.step(6)
+    z.step(6)
+    for k, (rx, ry) in enumerate(refs, start=1):
+        for ha, hz in ((a.me(k), z.me(k)), (a.si(k), z.si(k))):
+            F = hz[:, :2]
+            expect = hz[:, 2] + (Z[0] - rx) * F[:, 1] - (Z[1] - ry) * F[:, 0]
+            assert np.abs(ha[:, :2] - F).max() <= 1e-15 * np.abs(F).max() + 1e-300
+            assert np.abs(ha[:, 2] - expect).max() <= 1e-12 * np.abs(hz[:, 2]).max()
+
+
+def test_multibody_first_step_me_ignores_other_bodies():
+    # the ME of step 1 depends on the initial state only: body 1's value is
+    # the one of the same state with body 1 alone
+    ids, pts = three_bodies()
+    refs = [(16.3, 20.2), (38.1, 12.7), (55.0, 27.0)]
+    a = multi_lattice(ids, refs, pts)
+    one = np.where(ids == 1, 1, 0).astype(np.uint8)
+    b = multi_lattice(one, refs[:1], {1: pts[1]})
+    a.step(1)
+    b.step(1)
+    assert np.abs(a.me(1) - b.me(1)).max() <= 1e-15 * np.abs(b.me(1)).max()
+    assert np.abs(a.si(1) - b.si(1)).max() <= 1e-15 * np.abs(b.si(1)).max()
+
+
+def test_multibody_mirror_twins():
+    # two equal disks mirrored about the channel's mid-line in a symmetric
+    # flow: equal drag, opposite lift and torque
+    nx, ny = 64, 41
+    yc = 20.0
+    ids = np.zeros((ny, nx), np.uint8)
+    ids[O.mask_disk(nx, ny, 20.0, yc + 7.0, 4.5) != 0] = 1
+    ids[O.mask_disk(nx, ny, 20.0, yc - 7.0, 4.5) != 0] = 2
+    lat = O.RefLattice(nx, ny, 0.7, 1e-3, west=(O.VELOCITY, 0.03, 0), east=(O.OUTFLOW, 0, 0),
+                       south=(O.FREESLIP, 0, 0), north=(O.FREESLIP, 0, 0))
+    lat.set_body_ids(ids, [(20.0, yc + 7.0), (20.0, yc - 7.0)])
+    p1 = W.disk_si_points(20.0, yc + 7.0, 4.5, 36)
+    xy2 = p1[0].copy()
+    xy2[:, 1] = 2 * yc - xy2[:, 1]
+    n2 = p1[1].copy()
+    n2[:, 1] = -n2[:, 1]
+    lat.set_si_points_body(1, *p1)
+    lat.set_si_points_body(2, xy2, n2, p1[2])
+    lat.init_uniform(1.0, 0.03, 0.0)
+    lat.step(300)
+    for h1, h2 in ((lat.me(1), lat.me(2)), (lat.si(1), lat.si(2))):
+        scale = np.abs(h1).max()
+        assert np.abs(h1[:, 0] - h2[:, 0]).max() <= 1e-12 * scale
+        assert np.abs(h1[:, 1] + h2[:, 1]).max() <= 1e-12 * scale
+        assert np.abs(h1[:, 2] + h2[:, 2]).max() <= 1e-12 * scale
+    assert np.abs(lat.me(1)[-1, 1]) > 1e-3 * np.abs(lat.me(1)[-1, 0])  # a real lift to mirror
