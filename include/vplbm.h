@@ -96,6 +96,11 @@ typedef struct {
                         x + 1.5 n, falling back to rule 0 when a node is solid;
                         rule 1 needs max_si_points in 1..1024 and keeps
                         up to 4 sample records per point */
+  int max_bodies;    /* bodies one lattice can hold (ids 1..max_bodies in the
+                        mask, see vplbm_set_body_ids); 0 = 1, max 63 */
+  int max_interface_cells; /* momentum-exchange slots, one per interface cell
+                        (a cell with a lattice link to the other phase);
+                        0 = min(nx ny, 32 (nx + ny)) */
 } vplbm_params;
 
 /* Rigid-body state in lattice units: reference point (centre of a disk,
@@ -157,6 +162,14 @@ int vplbm_set_body_polygon(vplbm_lattice *lat, const double *xy, int nvert, doub
                            double yref);
 /* Arbitrary solid indicator (host, [ny][nx], nonzero = solid), static. */
 int vplbm_set_mask(vplbm_lattice *lat, const uint8_t *solid);
+/* Several static bodies in one lattice: ids [ny][nx] host bytes, 0 = fluid,
+ * b in 1..nbody = solid cell of body b (nbody <= max_bodies); ref_xy[2*nbody]
+ * the reference point of each body (its torques are taken about it).  Every
+ * momentum-exchange link belongs to the body of its solid node, so a fluid
+ * cell may be linked to one body only (bodies at least two cells apart;
+ * VPLBM_EINVAL otherwise).  Replaces any previous body and removes all
+ * stress-integration points.  Bodies set this way are static. */
+int vplbm_set_body_ids(vplbm_lattice *lat, const uint8_t *ids, int nbody, const double *ref_xy);
 
 /* Prescribed rigid motion: the state is applied now, and each step advances
  * the position and angle by the (constant) velocities; the disk's mask and
@@ -183,6 +196,12 @@ int vplbm_set_body_dynamics(vplbm_lattice *lat, double rho_s, double gx, double 
  * points. */
 int vplbm_set_si_points(vplbm_lattice *lat, const double *xy, const double *nrm, const double *ds,
                         int npts);
+/* The same for body `body` (1..nbody) of a multi-body lattice; the points of
+ * the other bodies stay.  All bodies' points together must fit
+ * max_si_points, and a sample node may serve one body only (VPLBM_EINVAL).
+ * vplbm_set_si_points is this call for body 1. */
+int vplbm_set_si_points_body(vplbm_lattice *lat, int body, const double *xy, const double *nrm,
+                             const double *ds, int npts);
 
 /* Advance nsteps time steps (asynchronous).  flags: VPLBM_STEP_MACRO makes
  * the last step also store rho and the penalized velocity u for
@@ -213,6 +232,12 @@ int vplbm_forces_si_at(vplbm_lattice *lat, const double *xy, const double *nrm, 
 /* History: out[3*k..3*k+2] = forces of step first_step + k, k < n.  The
  * ring keeps the last hist_capacity steps (VPLBM_EINVAL outside it). */
 int vplbm_force_history(vplbm_lattice *lat, int which, long long first_step, int n, double *out);
+/* Per body (1..nbody) of a multi-body lattice: forces of the last step
+ * (which = VPLBM_FORCE_ME or VPLBM_FORCE_SI) and their history.  The
+ * single-body calls above are these for body 1. */
+int vplbm_forces_body(vplbm_lattice *lat, int body, int which, double out[3]);
+int vplbm_force_history_body(vplbm_lattice *lat, int body, int which, long long first_step, int n,
+                             double *out);
 int vplbm_get_body_state(vplbm_lattice *lat, vplbm_body_state *out);
 
 /* rho and penalized u of the last step (which must have been run with
@@ -226,8 +251,9 @@ int vplbm_read_macro_window(vplbm_lattice *lat, int x0, int y0, int w, int h, do
 int vplbm_read_populations(vplbm_lattice *lat, double *f);
 /* The same for a window, host array [9][h][w]. */
 int vplbm_read_populations_window(vplbm_lattice *lat, int x0, int y0, int w, int h, double *f);
-/* Mask bytes [ny][nx]: bit 0 solid, bit 6 stress-integration sample node,
- * bit 7 interface cell (a neighbour has the other phase). */
+/* Mask bytes [ny][nx]: bits 0-5 body id (0 = fluid), bit 6
+ * stress-integration sample node, bit 7 interface cell (a neighbour has the
+ * other phase). */
 int vplbm_read_mask(vplbm_lattice *lat, uint8_t *out);
 
 /* ---- batches --------------------------------------------------------------

@@ -37,7 +37,8 @@ static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "opp axi
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "opp diag");
 
 // mask byte layout
-constexpr uint8_t M_SOLID = 0x01;   // chi = 1 (Eq. fcar)
+constexpr uint8_t M_BODY = 0x3F;    // body id 1..63 of a solid cell, 0 = fluid (chi = id != 0, Eq. fcar)
+constexpr int MAX_BODIES = 63;
 constexpr uint8_t M_SAMPLE = 0x40;  // stress-integration sample node
 constexpr uint8_t M_IFACE = 0x80;   // a lattice neighbour has the other phase
 
@@ -125,17 +126,26 @@ struct BodyDev {
 };
 
 // Device-resident control block (one per lattice).
+// Per-body ranges of the force terms the finalize sums: interface slots
+// [me0, me1) and stress-integration records [rec0, rec1).
+struct BodyTab {
+  int me0, me1, rec0, rec1;
+};
+
 struct Ctl {
-  BodyDev body;        // state used by the next step
+  BodyDev body;        // body 1: state used by the next step (bodies 2.. are static, in a table)
   int win[4];          // cell window x0, y0, x1, y1 (exclusive) holding every
-                       // interface and sample cell: the force reductions run there
+                       // interface and sample cell
   int region[4];       // last mask region rebuilt for a moving body
   int nrec;            // stress-integration records
+  int nslot;           // interface cells (momentum-exchange slots)
+  int nbody;           // bodies, ids 1..nbody
   int npts;            // registered stress-integration points
   int si_moving;       // points stored in the body frame
-  int err;             // bit 0: a point without sample node
+  int err;             // bit 0: a point without sample node; bit 1: a fluid cell
+                       // linked to two bodies; bit 2: a sample node shared by two bodies
   long long step;      // steps completed since initialization
-  double last[6];      // forces of the last step: ME (Fx, Fy, T), SI (Fx, Fy, T)
+  double last[6];      // forces of body 1 in the last step: ME (Fx, Fy, T), SI (Fx, Fy, T)
   int mode, shape, source;
   int si_rule;         // 0: nearest fluid node along n; 1: interpolated at x + 1.5 n
   double r;            // disk radius
@@ -152,7 +162,7 @@ struct SiRec {
   double ax, ay, txx, txy, tyy;
 };
 
-constexpr int PART_STRIDE = 8;  // doubles per partial-sum slot (3 used: ME Fx, Fy, T)
+constexpr int ME_STRIDE = 4;    // doubles per interface slot (ME Fx, Fy, T of one cell)
 constexpr int SIG_STRIDE = 4;   // doubles per stress slot of a sample node (xx, xy, yy)
 constexpr int FIXQ = 4096;      // fixed-point grid of geometry coordinates
 

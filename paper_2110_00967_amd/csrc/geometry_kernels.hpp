@@ -32,7 +32,7 @@ __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int 
     rho = rho_u;
     ux = ux_u;
     uy = uy_u;
-    if (mask[c] & M_SOLID) {  // solid cells start at the body velocity
+    if ((mask[c] & M_BODY) == 1) {  // body 1's cells start at its velocity (the others are static)
       const BodyDev B = ctl->body;
       ux = B.u - B.omega * (double(y) - B.y);
       uy = B.v + B.omega * (double(x) - B.x);
@@ -45,6 +45,12 @@ __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int 
     const double d = wgt(a) * (rho - rho0) + wgt(a) * rho * (3.0 * cu + 4.5 * cu * cu - uu);
     Store<S>::st(f + a * plane + c, (typename Store<S>::T)d);
   }
+}
+
+// interface slots from (cell, slot) pairs numbered on the host
+__global__ void k_scatter_slots(const int *__restrict__ pairs, int n, int *__restrict__ imap) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) imap[pairs[2 * k]] = pairs[2 * k + 1];
 }
 
 // convective-edge state <- the current populations entering through each
@@ -134,7 +140,7 @@ __global__ void k_mask_disk(uint8_t *__restrict__ mask, int pitch, int x0, int y
   const int i = x0 + blockIdx.x * blockDim.x + threadIdx.x;
   const int j = y0 + blockIdx.y;
   if (i >= x1 || j >= y1) return;
-  mask[(long long)j * pitch + i] = disk_inside(X, Y, R, i, j) ? M_SOLID : 0;
+  mask[(long long)j * pitch + i] = disk_inside(X, Y, R, i, j) ? 1 : 0;  // body 1
 }
 
 __global__ void k_mask_polygon(uint8_t *__restrict__ mask, int pitch, int x0, int y0, int x1, int y1,
@@ -143,19 +149,23 @@ __global__ void k_mask_polygon(uint8_t *__restrict__ mask, int pitch, int x0, in
   const int i = x0 + blockIdx.x * blockDim.x + threadIdx.x;
   const int j = y0 + blockIdx.y;
   if (i >= x1 || j >= y1) return;
-  mask[(long long)j * pitch + i] = polygon_inside(vx, vy, nv, i, j) ? M_SOLID : 0;
+  mask[(long long)j * pitch + i] = polygon_inside(vx, vy, nv, i, j) ? 1 : 0;  // body 1
 }
 
 // interface bit over a region: some lattice neighbour (periodic edges wrap,
-// none beyond other edges) has the other phase; clears the sample bit
+// none beyond other edges) has the other phase; keeps the body id, clears
+// the sample bit.  A fluid cell linked to two different bodies sets bit 1
+// of *err (its links could not be attributed to one body).
 __global__ void k_mask_flags(uint8_t *__restrict__ mask, int nx, int ny, int pitch, int x0, int y0,
-                             int x1, int y1, int perx, int pery) {
+                             int x1, int y1, int perx, int pery, int *__restrict__ err) {
   const int i = x0 + blockIdx.x * blockDim.x + threadIdx.x;
   const int j = y0 + blockIdx.y;
   if (i >= x1 || j >= y1) return;
   const long long c = (long long)j * pitch + i;
-  const uint8_t own = mask[c] & M_SOLID;
+  const int own = mask[c] & M_BODY;
   bool iface = false;
+  int other = 0;
+  bool two = false;
 #pragma unroll
   for (int a = 1; a < Q; ++a) {
     int X = i + cx(a), Y = j + cy(a);
@@ -167,9 +177,15 @@ __global__ void k_mask_flags(uint8_t *__restrict__ mask, int nx, int ny, int pit
       if (!pery) continue;
       Y = Y < 0 ? Y + ny : Y - ny;
     }
-    if ((mask[(long long)Y * pitch + X] & M_SOLID) != own) iface = true;
+    const int nid = mask[(long long)Y * pitch + X] & M_BODY;
+    if ((nid != 0) != (own != 0)) iface = true;
+    if (!own && nid) {
+      two = two || (other && other != nid);
+      other = nid;
+    }
   }
-  mask[c] = own | (iface ? M_IFACE : 0);
+  if (two) atomicOr(err, 2);
+  mask[c] = (uint8_t)(own | (iface ? M_IFACE : 0));
 }
 
 // ----------------------------------------------------------------------------
@@ -205,7 +221,7 @@ __device__ __forceinline__ int si_node(const uint8_t *__restrict__ mask, int nx,
   for (int k = 0; k <= 4; ++k) {
     const int X = ix + k * bx, Y = iy + k * by;
     if (X < 0 || X >= nx || Y < 0 || Y >= ny) continue;
-    if (!(mask[(long long)Y * pitch + X] & M_SOLID)) return Y * nx + X;
+    if (!(mask[(long long)Y * pitch + X] & M_BODY)) return Y * nx + X;
   }
   return -1;
 }
@@ -229,7 +245,7 @@ __device__ __forceinline__ int si_stencil(const uint8_t *__restrict__ mask, int 
       for (int k = 0; k < 4; ++k) {
         const int X = i0 + (k & 1), Y = j0 + (k >> 1);
         node[k] = Y * nx + X;
-        if (mask[(long long)Y * pitch + X] & M_SOLID) ok = false;
+        if (mask[(long long)Y * pitch + X] & M_BODY) ok = false;
         w[k] = __dmul_rn((k & 1) ? fx : __dsub_rn(1.0, fx), (k >> 1) ? fy : __dsub_rn(1.0, fy));
       }
       if (ok) return 4;
@@ -286,12 +302,16 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *wsum /*[SI_NT/64
 // of k_body_step after the mask was rebuilt).
 __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
                                 const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
-                                int *__restrict__ si_map, int nx, int ny, int pitch) {
+                                int *__restrict__ si_map, BodyTab *__restrict__ bt,
+                                const BodyDev *__restrict__ bodies, int nx, int ny, int pitch) {
+  // key = (body, node, entry): records come out grouped by body, then by node
+  constexpr int NODE_SHIFT = 14, BODY_SHIFT = 45;  // entry < 2^14, node < 2^31
   __shared__ unsigned long long key[SI_MAX];
+  __shared__ unsigned char recbody[SI_MAX];
   __shared__ int wsum[SI_NT / 64];
   __shared__ int nrec_total;
   __shared__ int bb[4];
-  __shared__ int missing;
+  __shared__ int missing, shared_node;
   const int npts = ctl->npts;
   const int moving = ctl->si_moving;
   const int rule = ctl->si_rule;
@@ -303,20 +323,27 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
   if (threadIdx.x == 0) {
     bb[0] = nx; bb[1] = ny; bb[2] = -1; bb[3] = -1;
     missing = 0;
+    shared_node = 0;
+  }
+  if (threadIdx.x < MAX_BODIES) {
+    bt[threadIdx.x].rec0 = 0;
+    bt[threadIdx.x].rec1 = 0;
   }
   __syncthreads();
-  // one key (node, entry) per stencil entry; entry = point * per_pt + k
+  // one key per stencil entry; entry = point * per_pt + k
   for (int i = threadIdx.x; i < N / per_pt; i += SI_NT) {
     unsigned long long kk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     if (i < npts) {
       double px, py, n0, n1;
       si_world(pts, maxp, i, moving, B, px, py, n0, n1);
+      const unsigned long long body = (unsigned long long)pts[5 * maxp + i];
       int node[4];
       double w[4];
       const int c = si_stencil(mask, nx, ny, pitch, rule, px, py, n0, n1, node, w);
       if (c == 0) atomicAdd(&missing, 1);
       for (int k = 0; k < c; ++k) {
-        kk[k] = ((unsigned long long)(unsigned)node[k] << 32) | (unsigned)(i * per_pt + k);
+        kk[k] = (body << BODY_SHIFT) | ((unsigned long long)(unsigned)node[k] << NODE_SHIFT) |
+                (unsigned)(i * per_pt + k);
         const int X = node[k] % nx, Y = node[k] / nx;
         atomicMin(&bb[0], X);
         atomicMin(&bb[1], Y);
@@ -327,7 +354,7 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
     for (int k = 0; k < per_pt; ++k) key[i * per_pt + k] = kk[k];
   }
   __syncthreads();
-  // bitonic sort of (node, point) keys
+  // bitonic sort of the keys
   for (int size = 2; size <= N; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int t = threadIdx.x; t < N / 2; t += SI_NT) {
@@ -343,21 +370,24 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
       __syncthreads();
     }
   }
-  // segment heads -> record indices (each thread owns a contiguous chunk)
+  // segment heads (one record per body and node) -> record indices (each
+  // thread owns a contiguous chunk)
+  const unsigned long long INVALID = ~0ull;
+  auto group = [&](int j) { return key[j] >> NODE_SHIFT; };  // (body, node)
   const int per = (N + SI_NT - 1) / SI_NT;
   const int j0 = threadIdx.x * per, j1 = min(j0 + per, N);
   int cnt = 0;
-  for (int j = j0; j < j1; ++j) {
-    const unsigned node = (unsigned)(key[j] >> 32);
-    if (node != 0xFFFFFFFFu && (j == 0 || (unsigned)(key[j - 1] >> 32) != node)) ++cnt;
-  }
+  for (int j = j0; j < j1; ++j)
+    if (key[j] != INVALID && (j == 0 || group(j - 1) != group(j))) ++cnt;
   int r = block_exclusive_scan(cnt, wsum, &nrec_total);
   for (int j = j0; j < j1; ++j) {
-    const unsigned node = (unsigned)(key[j] >> 32);
-    if (node == 0xFFFFFFFFu || (j > 0 && (unsigned)(key[j - 1] >> 32) == node)) continue;
+    if (key[j] == INVALID || (j > 0 && group(j - 1) == group(j))) continue;
+    const int body = (int)(key[j] >> BODY_SHIFT);
+    const unsigned node = (unsigned)((key[j] >> NODE_SHIFT) & 0x7FFFFFFFu);
+    const BodyDev Bb = body <= 1 ? B : bodies[body];  // torque reference of the record's body
     double ax = 0.0, ay = 0.0, txx = 0.0, txy = 0.0, tyy = 0.0;
-    for (int k = j; k < N && (unsigned)(key[k] >> 32) == node; ++k) {
-      const int e = (int)(key[k] & 0xFFFFFFFFu);
+    for (int k = j; k < N && key[k] != INVALID && group(k) == group(j); ++k) {
+      const int e = (int)(key[k] & ((1u << NODE_SHIFT) - 1));
       const int i = e / per_pt;
       double px, py, n0, n1;
       si_world(pts, maxp, i, moving, B, px, py, n0, n1);
@@ -365,7 +395,7 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
       double w[4];
       si_stencil(mask, nx, ny, pitch, rule, px, py, n0, n1, nd, w);
       const double s = pts[4 * maxp + i] * w[e % per_pt];
-      const double rx = px - B.x, ry = py - B.y;
+      const double rx = px - Bb.x, ry = py - Bb.y;
       ax += s * n0;
       ay += s * n1;
       txx += s * (-ry * n0);
@@ -377,15 +407,27 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
     R.pad = 0;
     R.ax = ax; R.ay = ay; R.txx = txx; R.txy = txy; R.tyy = tyy;
     recs[r] = R;
+    recbody[r] = (unsigned char)body;
     const int X = (int)node % nx, Y = (int)node / nx;
-    si_map[(long long)Y * pitch + X] = r;
-    mask[(long long)Y * pitch + X] |= M_SAMPLE;
+    const long long cc = (long long)Y * pitch + X;
+    si_map[cc] = r;
+    // sample bit (a node sampled for two bodies would need two slots)
+    unsigned *wd = (unsigned *)(mask + (cc & ~3LL));
+    const unsigned bit = (unsigned)M_SAMPLE << (8 * (cc & 3));
+    if (atomicOr(wd, bit) & bit) atomicOr(&shared_node, 1);
     ++r;
   }
   __syncthreads();
+  // each body's record range (records are grouped by body)
+  for (int k = threadIdx.x; k < nrec_total; k += SI_NT) {
+    const int b = recbody[k] - 1;
+    if (k == 0 || recbody[k - 1] != recbody[k]) bt[b].rec0 = k;
+    if (k == nrec_total - 1 || recbody[k + 1] != recbody[k]) bt[b].rec1 = k + 1;
+  }
   if (threadIdx.x == 0) {
     ctl->nrec = nrec_total;
     if (missing) ctl->err |= 1;
+    if (shared_node) ctl->err |= 4;
     if (bb[2] >= 0) {
       if (ctl->win[2] <= ctl->win[0] || ctl->win[3] <= ctl->win[1]) {
         ctl->win[0] = bb[0]; ctl->win[1] = bb[1]; ctl->win[2] = bb[2] + 1; ctl->win[3] = bb[3] + 1;
@@ -401,9 +443,9 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
 
 __global__ void __launch_bounds__(SI_NT)
     k_si_select(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ pts,
-                int maxp, SiRec *__restrict__ recs, int *__restrict__ si_map, int nx, int ny,
-                int pitch) {
-  si_select_block(mask, ctl, pts, maxp, recs, si_map, nx, ny, pitch);
+                int maxp, SiRec *__restrict__ recs, int *__restrict__ si_map, BodyTab *__restrict__ bt,
+                const BodyDev *__restrict__ bodies, int nx, int ny, int pitch) {
+  si_select_block(mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch);
 }
 
 // ----------------------------------------------------------------------------
@@ -414,20 +456,20 @@ constexpr int BODY_NT = 1024;
 constexpr int REGION_MARGIN = 6;  // covers links (1) and sample walks (5)
 
 __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
-                                const double *__restrict__ part, const double *__restrict__ sig,
-                                double *__restrict__ hist, int cap, int BX,
-                                int BY, int nx, int ny, int pitch, int perx, int pery,
-                                const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
-                                int *__restrict__ si_map) {
+                                const double *__restrict__ me, const double *__restrict__ sig,
+                                double *__restrict__ hist, int cap, int maxb, int nx, int ny, int pitch,
+                                int perx, int pery, const double *__restrict__ pts, int maxp,
+                                SiRec *__restrict__ recs, int *__restrict__ si_map, int *__restrict__ imap,
+                                int maxslot, BodyTab *__restrict__ bt, const BodyDev *__restrict__ bodies) {
+  static_assert(BODY_NT == SI_NT, "the block scan assumes SI_NT threads");
   __shared__ int reg[4];   // union region to rewrite
   __shared__ long long q[3];
   __shared__ double lds[(BODY_NT / 64) * 6];
-  {
-    // forces of the step just taken (its window), needed by the update below
-    const int wx0 = ctl->win[0] / BX, wy0 = ctl->win[1] / BY;
-    const int wx1 = (ctl->win[2] + BX - 1) / BX, wy1 = (ctl->win[3] + BY - 1) / BY;
-    finalize_block<BODY_NT>(part, wx1 - wx0, wy1 - wy0, sig, recs, ctl, hist, cap, lds);
-  }
+  __shared__ int wsum[BODY_NT / 64];
+  __shared__ int nslot;
+  // forces of the step just taken, needed by the update below (the only
+  // body: a moving disk is alone in its lattice)
+  finalize_block<BODY_NT>(me, sig, recs, bt, ctl, hist, cap, maxb, lds);
   __syncthreads();
   if (threadIdx.x == 0) {
     BodyDev B = ctl->body;
@@ -492,22 +534,54 @@ __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
       }
       if (disk_inside(X, Y, R, I, J) != own) iface = true;
     }
-    mask[(long long)j * pitch + i] = (own ? M_SOLID : 0) | (iface ? M_IFACE : 0);
+    mask[(long long)j * pitch + i] = (own ? 1 : 0) | (iface ? M_IFACE : 0);
+  }
+  // the rebuilt mask must be visible to every thread of the block
+  __threadfence_block();
+  __syncthreads();
+  {
+    // interface slots: the region's interface cells in row-major order (all
+    // of the disk's interface cells lie in its region); each thread numbers a
+    // contiguous chunk.  A slot beyond the capacity drops its interface bit
+    // and flags the error (bit 3) instead of writing out of bounds.
+    const int n = w * h, per = (n + BODY_NT - 1) / BODY_NT;
+    const int t0 = threadIdx.x * per, t1 = min(t0 + per, n);
+    int cnt = 0;
+    for (int t = t0; t < t1; ++t)
+      if (mask[(long long)(y0 + t / w) * pitch + x0 + t % w] & M_IFACE) ++cnt;
+    int slot = block_exclusive_scan(cnt, wsum, &nslot);
+    for (int t = t0; t < t1; ++t) {
+      const long long c = (long long)(y0 + t / w) * pitch + x0 + t % w;
+      if (!(mask[c] & M_IFACE)) continue;
+      if (slot < maxslot) {
+        imap[c] = slot;
+      } else {
+        mask[c] &= (uint8_t)~M_IFACE;
+        atomicOr(&ctl->err, 8);
+      }
+      ++slot;
+    }
+    if (threadIdx.x == 0) {
+      ctl->nslot = min(nslot, maxslot);
+      bt[0].me0 = 0;
+      bt[0].me1 = min(nslot, maxslot);
+    }
   }
   if (ctl->npts > 0) {
-    // the rebuilt mask must be visible to every thread of the block
     __threadfence_block();
     __syncthreads();
-    si_select_block(mask, ctl, pts, maxp, recs, si_map, nx, ny, pitch);
+    si_select_block(mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch);
   }
 }
 
 __global__ void __launch_bounds__(BODY_NT)
-    k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ part,
-                const double *__restrict__ sig, double *__restrict__ hist, int cap, int BX, int BY, int nx,
-                int ny, int pitch, int perx, int pery, const double *__restrict__ pts, int maxp,
-                SiRec *__restrict__ recs, int *__restrict__ si_map) {
-  body_step_block(mask, ctl, part, sig, hist, cap, BX, BY, nx, ny, pitch, perx, pery, pts, maxp, recs, si_map);
+    k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ me,
+                const double *__restrict__ sig, double *__restrict__ hist, int cap, int maxb, int nx, int ny,
+                int pitch, int perx, int pery, const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
+                int *__restrict__ si_map, int *__restrict__ imap, int maxslot, BodyTab *__restrict__ bt,
+                const BodyDev *__restrict__ bodies) {
+  body_step_block(mask, ctl, me, sig, hist, cap, maxb, nx, ny, pitch, perx, pery, pts, maxp, recs, si_map, imap,
+                  maxslot, bt, bodies);
 }
 
 // body kernel of a batched launch: one workgroup per moving lattice
@@ -515,9 +589,9 @@ template <typename T>
 __global__ void __launch_bounds__(BODY_NT)
     k_body_step_batch(const CaseDesc<T> *__restrict__ cases, const int *__restrict__ moving, int flip) {
   const CaseDesc<T> &C = cases[moving[blockIdx.x]];
-  body_step_block(C.mask, C.ctl, C.part[C.pbit0 ^ flip], C.sig[C.pbit0 ^ flip], C.hist, C.cap, C.tw, C.by,
-                  C.P.nx, C.P.ny, C.P.pitch,
-                  C.perx, C.pery, C.pts, C.maxp, const_cast<SiRec *>(C.recs), const_cast<int *>(C.si_map));
+  body_step_block(C.mask, C.ctl, C.me[C.pbit0 ^ flip], C.sig[C.pbit0 ^ flip], C.hist, C.cap, C.maxb, C.P.nx,
+                  C.P.ny, C.P.pitch, C.perx, C.pery, C.pts, C.maxp, const_cast<SiRec *>(C.recs),
+                  const_cast<int *>(C.si_map), const_cast<int *>(C.imap), C.maxslot, C.bt, C.P.bodies);
 }
 
 // ----------------------------------------------------------------------------

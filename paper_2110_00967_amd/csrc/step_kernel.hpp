@@ -4,24 +4,26 @@
 // post-collision deviations d~^{n-1} in buffer A, structure of arrays
 // [9][ny][pitch]):
 //   1. pull streaming  f^n_a(x) = f~^{n-1}_a(x - c_a)   (Eq. eqBd) with the
-//      edge rules (periodic, half-way bounce-back, specular, zero-gradient);
+//      edge rules (periodic, half-way bounce-back, specular, zero-gradient,
+//      convective);
 //   2. rho = sum f, m = sum c f; penalized velocity
 //      u = (m + G/2 + k/2 rho u_s) / (rho (1 + k/2)), k = chi/eta
 //      (Eqs. updatestep, updatestep3, updatestepm) and force density
 //      F = G - rho k (u - u_s)  (penalization term of Eq. 1);
 //   3. f^eq (Sec. 2.2), forcing term in the form of Guo et al. (cited for
 //      F_alpha in Eq. eqBd) with the (1 - 1/(2 tau)) prefactor of Eq. TRT,
-//      BGK relaxation, store into buffer B;
+//      BGK or TRT relaxation, store into buffer B;
 //   4. interface cells: momentum exchange (Eq. MMEL) of every pulled
 //      population that crossed the solid/fluid boundary -- the same link sum
-//      as Sec. 2.3.1 evaluated on f~^{n-1}, gathered per destination;
-//   5. sample cells: stress (Sec. 2.3.2 sigma) of the streamed populations,
-//      contracted with the node's aggregated integration weights (Eq. defFf);
-//   6. blocks inside the force window reduce (ME, SI) in FP64 with wave
-//      shuffles and LDS and write one partial per block (two partial buffers,
-//      alternating by step); block 0 of the next step -- after the kernel
-//      boundary made them visible -- sums the previous step's partials in
-//      window order (deterministic) into the force-history ring.
+//      as Sec. 2.3.1 evaluated on f~^{n-1}, gathered per destination -- into
+//      the cell's own slot (numbered body by body);
+//   5. sample cells: stress (Sec. 2.3.2 sigma) of the streamed populations
+//      into the node's record slot;
+//   6. block 0 of the next step -- after the kernel boundary made them
+//      visible -- sums each body's slots, and contracts its records with the
+//      aggregated integration weights (Eq. defFf), in fixed order
+//      (deterministic), into the force-history ring.  Slots alternate
+//      between two buffers by step parity.
 // HBM traffic per cell: 9 loads + 9 stores of the storage type + 1 mask byte.
 #pragma once
 
@@ -43,6 +45,7 @@ template <typename T> struct StepArgs {
   T omega_m, fac_m;     // TRT: 1/tau- and 1 - 1/(2 tau-) (BGK: the same as omega, fac)
   T fo, fo9, fo3;       // tau+ - 1/2, 9 (tau+ - 1/2), 3 (tau- - 1/2)
   double facd, rho0d;
+  const BodyDev *bodies;  // static bodies 2..: bodies[id] (body 1 lives in the control block)
   T *cbc;               // convective-edge state (see cbc_offset)
   T cbu[4];             // convection speed U of each convective edge
   T cbi[4];             // 1 / (1 + U)
@@ -203,39 +206,58 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], double *lds /*[NT/6
   }
 }
 
-// Forces of one step -> its force-history slot (deterministic: fixed
-// assignment and order).  ME: the window partials of the step kernel.  SI:
-// the stress each sample node stored (sig), contracted with the node's
-// aggregated weights, record by record.
+// Forces of one step -> its force-history slots, body by body
+// (deterministic: fixed assignment and order).  ME: the contributions the
+// interface cells stored in their slots.  SI: the stress each sample node
+// stored (sig), contracted with the node's aggregated weights, record by
+// record.  hist[(n mod cap) * maxb + b][6]; the control block keeps body 1's.
 template <int NT>
-__device__ __forceinline__ void finalize_block(const double *__restrict__ part, int nwx, int nwy,
-                                               const double *__restrict__ sig, const SiRec *__restrict__ recs,
-                                               Ctl *__restrict__ ctl, double *__restrict__ hist, int cap,
+__device__ __forceinline__ void finalize_block(const double *__restrict__ me, const double *__restrict__ sig,
+                                               const SiRec *__restrict__ recs, const BodyTab *__restrict__ bt,
+                                               Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb,
                                                double *lds) {
-  const int nwin = (nwx > 0 && nwy > 0) ? nwx * nwy : 0;
-  const int nrec = ctl->nrec;
-  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int t = threadIdx.x; t < nwin; t += NT) {
+  const long long n = ctl->step + 1;
+  const int nb = ctl->nbody;
+  for (int b = 0; b < nb; ++b) {
+    const BodyTab T = bt[b];
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int r = T.me0 + threadIdx.x; r < T.me1; r += NT) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) v[i] += part[(long long)t * PART_STRIDE + i];
-  }
-  for (int r = threadIdx.x; r < nrec; r += NT) {
-    const double *g = sig + (long long)r * SIG_STRIDE;
-    const SiRec R = recs[r];
-    v[3] += g[0] * R.ax + g[1] * R.ay;
-    v[4] += g[1] * R.ax + g[2] * R.ay;
-    v[5] += g[0] * R.txx + g[1] * R.txy + g[2] * R.tyy;
-  }
-  block_reduce<NT, 6>(v, lds);
-  if (threadIdx.x == 0) {
-    const long long n = ctl->step + 1;
-    double *h = hist + (n % cap) * 6;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      h[i] = v[i];
-      ctl->last[i] = v[i];
+      for (int i = 0; i < 3; ++i) v[i] += me[(long long)r * ME_STRIDE + i];
     }
-    ctl->step = n;
+    for (int r = T.rec0 + threadIdx.x; r < T.rec1; r += NT) {
+      const double *g = sig + (long long)r * SIG_STRIDE;
+      const SiRec R = recs[r];
+      v[3] += g[0] * R.ax + g[1] * R.ay;
+      v[4] += g[1] * R.ax + g[2] * R.ay;
+      v[5] += g[0] * R.txx + g[1] * R.txy + g[2] * R.tyy;
+    }
+    block_reduce<NT, 6>(v, lds);
+    if (threadIdx.x == 0) {
+      double *h = hist + ((n % cap) * maxb + b) * 6;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        h[i] = v[i];
+        if (b == 0) ctl->last[i] = v[i];
+      }
+    }
+    __syncthreads();  // lds is reused by the next body
+  }
+  if (threadIdx.x == 0) ctl->step = n;
+}
+
+// Torque reference point of body id (1..63): body 1's from the control block
+// (it may move), the others' from the static table.  Only body 1 has a
+// velocity; bodies 2.. are static.
+template <typename T>
+__device__ __forceinline__ void body_ref(const Ctl *__restrict__ ctl, const StepArgs<T> &P, int id, double &bx,
+                                         double &by) {
+  if (id <= 1) {
+    bx = ctl->body.x;
+    by = ctl->body.y;
+  } else {
+    bx = P.bodies[id].x;
+    by = P.bodies[id].y;
   }
 }
 
@@ -260,9 +282,10 @@ template <typename S, int BX, int BY, bool MACRO, bool TRT>
 __device__ __forceinline__ void step_tile(
     int tile, const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
     const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl, const SiRec *__restrict__ recs,
-    const int *__restrict__ si_map, double *__restrict__ part_out, const double *__restrict__ part_prev,
-    double *__restrict__ sig_out, const double *__restrict__ sig_prev, int fin_prev, double *__restrict__ hist,
-    int cap, typename Store<S>::T *__restrict__ mrho, typename Store<S>::T *__restrict__ mux,
+    const int *__restrict__ si_map, const int *__restrict__ imap, const BodyTab *__restrict__ bt,
+    double *__restrict__ me_out, const double *__restrict__ me_prev, double *__restrict__ sig_out,
+    const double *__restrict__ sig_prev, int fin_prev, double *__restrict__ hist, int cap, int maxb,
+    typename Store<S>::T *__restrict__ mrho, typename Store<S>::T *__restrict__ mux,
     typename Store<S>::T *__restrict__ muy) {
   using T = typename Store<S>::T;
   constexpr int NT = BX * BY;
@@ -273,7 +296,6 @@ __device__ __forceinline__ void step_tile(
   const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
   const int x = tx * BX + lx, y = ty * BY + ly;
 
-  double acc[3] = {0.0, 0.0, 0.0};  // momentum exchange Fx, Fy, T of this thread
 
   // Every cell of the tile has all 8 neighbours inside the lattice: the
   // workgroup-uniform fast path.  A plane holds fewer than 2^31 / 9 cells, so
@@ -304,14 +326,17 @@ __device__ __forceinline__ void step_tile(
 
     // penalized velocity (Eq. updatestepm) and force; k = 0 in fluid cells
     T khalf = T(0), a1 = T(1), kk = T(0), usx = T(0), usy = T(0);
-    const bool chi = (m & M_SOLID) != 0;
+    const int id = m & M_BODY;
+    const bool chi = id != 0;
     if (chi) {
       khalf = P.khalf;
       a1 = P.a1;
       kk = P.kk;
-      const BodyDev B = ctl->body;
-      usx = T(B.u - B.omega * (double(y) - B.y));
-      usy = T(B.v + B.omega * (double(x) - B.x));
+      if (id == 1) {  // the only body that can move (u_s = 0 in the static ones)
+        const BodyDev B = ctl->body;
+        usx = T(B.u - B.omega * (double(y) - B.y));
+        usy = T(B.v + B.omega * (double(x) - B.x));
+      }
     }
     const T hx = mx + T(0.5) * P.gx, hy = my + T(0.5) * P.gy;
     const T den = a1 * recip(rho);  // 1 / (rho (1 + k/2))
@@ -372,9 +397,17 @@ __device__ __forceinline__ void step_tile(
       // the link's interface point is its midpoint seen from its fluid node.
       // The 8 neighbour masks are loaded all at once (a load inside the
       // divergent loop below would cost one memory round trip per link).
-      const BodyDev B = ctl->body;
+      // The cell's links all belong to one body: its own if solid, else that
+      // of its solid neighbours (a fluid cell is linked to one body at most).
       uint8_t nm[Q];
       nbr_masks(mask, P, x, y, nm);
+      int bid = id;
+#pragma unroll
+      for (int a = 1; a < Q; ++a) bid = bid ? bid : (nm[a] & M_BODY);
+      double bx, by;
+      body_ref(ctl, P, bid, bx, by);
+      const bool moving = bid == 1;  // u_s = 0 on the links of the static bodies
+      double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int a = 1; a < Q; ++a) {
         int sx = x - cx(a), sy = y - cy(a);
@@ -387,18 +420,28 @@ __device__ __forceinline__ void step_tile(
           if ((sy < 0 ? P.kind[SOUTH] : P.kind[NORTH]) != EDGE_PERIODIC) link = false;
           sy = sy < 0 ? sy + P.ny : sy - P.ny;
         }
-        const bool schi = (nm[a] & M_SOLID) != 0;
+        const bool schi = (nm[a] & M_BODY) != 0;
         if (!link || schi == chi) continue;
         double gx, gy, s;
         if (chi) { gx = sx + 0.5 * cx(a); gy = sy + 0.5 * cy(a); s = 1.0; }
         else { gx = x - 0.5 * cx(a); gy = y - 0.5 * cy(a); s = -1.0; }
-        const double ugx = B.u - B.omega * (gy - B.y), ugy = B.v + B.omega * (gx - B.x);
+        double ugx = 0.0, ugy = 0.0;
+        if (moving) {
+          const BodyDev &B = ctl->body;
+          ugx = B.u - B.omega * (gy - B.y);
+          ugy = B.v + B.omega * (gx - B.x);
+        }
         const double fa = wgt(a) * P.rho0d + double(d[a]);
         const double lx = s * (cx(a) - ugx) * fa, ly = s * (cy(a) - ugy) * fa;
         acc[0] += lx;
         acc[1] += ly;
-        acc[2] += (gx - B.x) * ly - (gy - B.y) * lx;
+        acc[2] += (gx - bx) * ly - (gy - by) * lx;
       }
+      // this cell's contribution goes to its slot; the finalize sums them
+      double *o = me_out + (long long)imap[(uint32_t)c] * ME_STRIDE;
+      o[0] = acc[0];
+      o[1] = acc[1];
+      o[2] = acc[2];
     }
     if (m & M_SAMPLE) {
       // stress of the streamed populations at a (fluid) sample node
@@ -425,25 +468,11 @@ __device__ __forceinline__ void step_tile(
     }
   }
 
-  // the force window is read only now, so that its load does not delay the
-  // population loads above
-  const int wx0 = ctl->win[0] / BX, wy0 = ctl->win[1] / BY;
-  const int wx1 = (ctl->win[2] + BX - 1) / BX, wy1 = (ctl->win[3] + BY - 1) / BY;
-  const bool inwin = tx >= wx0 && tx < wx1 && ty >= wy0 && ty < wy1;
-  __shared__ double lds[(NT / 64) * 6];
-  if (inwin) {
-    block_reduce<NT, 3>(acc, lds);
-    if (threadIdx.x == 0) {
-      double *o = part_out + (long long)((ty - wy0) * (wx1 - wx0) + (tx - wx0)) * PART_STRIDE;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) o[i] = acc[i];
-    }
-  }
   if (fin_prev && tile == 0) {
-    // forces of the previous step (same window and records: only static
+    // forces of the previous step (same slots and records: only static
     // bodies defer)
-    __syncthreads();
-    finalize_block<NT>(part_prev, wx1 - wx0, wy1 - wy0, sig_prev, recs, ctl, hist, cap, lds);
+    __shared__ double lds[(NT / 64) * 6];
+    finalize_block<NT>(me_prev, sig_prev, recs, bt, ctl, hist, cap, maxb, lds);
   }
 }
 
@@ -457,10 +486,10 @@ __global__ void __launch_bounds__(BX *BY, step_waves<S>())
     k_step(const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
            const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl,
            const SiRec *__restrict__ recs, const int *__restrict__ si_map,
-           double *__restrict__ part_out, const double *__restrict__ part_prev, double *__restrict__ sig_out,
-           const double *__restrict__ sig_prev, int fin_prev, double *__restrict__ hist, int cap,
-           typename Store<S>::T *__restrict__ mrho, typename Store<S>::T *__restrict__ mux,
-           typename Store<S>::T *__restrict__ muy) {
+           const int *__restrict__ imap, const BodyTab *__restrict__ bt, double *__restrict__ me_out,
+           const double *__restrict__ me_prev, double *__restrict__ sig_out, const double *__restrict__ sig_prev,
+           int fin_prev, double *__restrict__ hist, int cap, int maxb, typename Store<S>::T *__restrict__ mrho,
+           typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy) {
   // XCD-aware tile order: consecutive workgroups go round-robin over the 8
   // XCDs, so give each XCD a contiguous band of tiles (shared halo lines stay
   // in that XCD's L2).  A band only a few rounds of workgroups deep is
@@ -473,8 +502,8 @@ __global__ void __launch_bounds__(BX *BY, step_waves<S>())
   int t = i + P.rot[xcd];
   t -= t >= len ? len : 0;
   const int tile = start + t;
-  step_tile<S, BX, BY, MACRO, TRT>(tile, fin, fout, mask, P, ctl, recs, si_map, part_out, part_prev, sig_out,
-                                   sig_prev, fin_prev, hist, cap, mrho, mux, muy);
+  step_tile<S, BX, BY, MACRO, TRT>(tile, fin, fout, mask, P, ctl, recs, si_map, imap, bt, me_out, me_prev, sig_out,
+                                   sig_prev, fin_prev, hist, cap, maxb, mrho, mux, muy);
 }
 
 // Per-lattice description for the batched step: one launch covers the tiles
@@ -486,17 +515,19 @@ template <typename T> struct CaseDesc {
   Ctl *ctl;
   const SiRec *recs;
   const int *si_map;
-  double *part[2];        // partial sums of steps with parity 0 and 1
+  const int *imap;        // interface slot of each interface cell
+  BodyTab *bt;
+  double *me[2];          // interface contributions of steps with parity 0 and 1
   double *sig[2];         // sample-node stresses of steps with parity 0 and 1
   double *hist;
-  int cap;
+  int cap, maxb;
   int tile0;              // first global tile of this lattice
   int cur0;               // parity of the buffer holding the state at launch 0
   int pbit0;              // parity of the step computed by launch 0
   int pending0;           // launch 0 finalizes the forces of the step before it
   int moving;             // forces are finalized by the body kernel instead
   // body-kernel arguments
-  int tw, by, perx, pery, maxp;
+  int tw, by, perx, pery, maxp, maxslot;
   const double *pts;
 };
 
@@ -517,21 +548,17 @@ __global__ void __launch_bounds__(BX *BY, step_waves<S>())
   const int fin_prev = C->moving ? 0 : (first ? C->pending0 : 1);
   const S *fin = (const S *)C->buf[par];
   S *fout = (S *)C->buf[par ^ 1];
-  double *pout = C->part[pb];
-  const double *pprev = C->part[pb ^ 1];
-  step_tile<S, BX, BY, false, TRT>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map, pout, pprev,
-                                   C->sig[pb], C->sig[pb ^ 1], fin_prev, C->hist, C->cap, nullptr, nullptr,
-                                   nullptr);
+  step_tile<S, BX, BY, false, TRT>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map, C->imap,
+                                   C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1], fin_prev, C->hist,
+                                   C->cap, C->maxb, nullptr, nullptr, nullptr);
 }
 
 template <int NT>
 __global__ void __launch_bounds__(NT)
-    k_finalize(const double *__restrict__ part, const double *__restrict__ sig, const SiRec *__restrict__ recs,
-               Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int BX, int BY) {
+    k_finalize(const double *__restrict__ me, const double *__restrict__ sig, const SiRec *__restrict__ recs,
+               const BodyTab *__restrict__ bt, Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb) {
   __shared__ double lds[(NT / 64) * 6];
-  const int wx0 = ctl->win[0] / BX, wy0 = ctl->win[1] / BY;
-  const int wx1 = (ctl->win[2] + BX - 1) / BX, wy1 = (ctl->win[3] + BY - 1) / BY;
-  finalize_block<NT>(part, wx1 - wx0, wy1 - wy0, sig, recs, ctl, hist, cap, lds);
+  finalize_block<NT>(me, sig, recs, bt, ctl, hist, cap, maxb, lds);
 }
 
 }  // namespace vp

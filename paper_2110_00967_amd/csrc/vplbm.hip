@@ -43,7 +43,6 @@ constexpr size_t STAGE_DOUBLES = 1 << 18;  // 2 MiB staging
 constexpr int DEFAULT_HIST = 4096;
 constexpr int DEFAULT_PTS = 4096;
 constexpr int DEFAULT_VERTS = 4096;
-constexpr int MIN_TILE_CELLS = 64;
 constexpr int WG_SLOTS_PER_XCD = 256;  // 32 CUs x 8 resident workgroups of the step kernel
 constexpr int ROT_MAX_ROUNDS = 16;
 constexpr int MAX_NX = 16384;  // one row of 9 planes fits the staging buffer
@@ -60,10 +59,17 @@ int pitch_of(const vplbm_params &p) {
 }
 
 struct Layout {
-  size_t A, B, mask, mrho, mux, muy, si_map, partials, partials_stride, sig, sig_stride, cbc, hist, ctl, recs, pts,
-      verts, staging,
-      siout, total;
+  size_t A, B, mask, mrho, mux, muy, si_map, imap, me, me_stride, sig, sig_stride, cbc, hist, ctl, bt, bodies,
+      recs, pts, verts, staging, siout, total;
 };
+
+int max_bodies_of(const vplbm_params &p) { return p.max_bodies > 0 ? p.max_bodies : 1; }
+// interface cells (momentum-exchange slots): the given capacity, or room for
+// a boundary 16 cells thick along the whole lattice perimeter
+long long max_slots_of(const vplbm_params &p) {
+  if (p.max_interface_cells > 0) return p.max_interface_cells;
+  return std::min<long long>((long long)p.nx * p.ny, 32LL * ((long long)p.nx + p.ny));
+}
 
 Layout layout_of(const vplbm_params &p) {
   Layout L{};
@@ -72,14 +78,14 @@ Layout layout_of(const vplbm_params &p) {
   const int cap = p.hist_capacity > 0 ? p.hist_capacity : DEFAULT_HIST;
   const int maxp = p.max_si_points > 0 ? p.max_si_points : DEFAULT_PTS;
   const int maxv = p.max_vertices > 0 ? p.max_vertices : DEFAULT_VERTS;
-  const size_t ntiles = (size_t)p.ny * ((p.nx + MIN_TILE_CELLS - 1) / MIN_TILE_CELLS);
+  const size_t maxb = (size_t)max_bodies_of(p);
+  const size_t maxslot = (size_t)max_slots_of(p);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
     o = align_up(o + bytes, ALIGN);
     return at;
   };
-  L.partials_stride = ntiles * PART_STRIDE * sizeof(double);
   L.A = take(9 * cells * elem_size(p.precision));
   L.B = take(9 * cells * elem_size(p.precision));
   L.mask = take(cells);
@@ -87,9 +93,14 @@ Layout layout_of(const vplbm_params &p) {
   L.mux = take(cells * compute_size(p.precision));
   L.muy = take(cells * compute_size(p.precision));
   L.si_map = take(cells * sizeof(int));
-  L.partials = take(2 * ntiles * PART_STRIDE * sizeof(double));  // two buffers, by step parity
-  L.hist = take((size_t)cap * 6 * sizeof(double));
+  L.imap = take(cells * sizeof(int));
+  // momentum exchange of each interface cell, by step parity
+  L.me_stride = maxslot * ME_STRIDE * sizeof(double);
+  L.me = take(2 * L.me_stride);
+  L.hist = take((size_t)cap * maxb * 6 * sizeof(double));
   L.ctl = take(sizeof(Ctl));
+  L.bt = take((size_t)MAX_BODIES * sizeof(BodyTab));
+  L.bodies = take((size_t)(MAX_BODIES + 1) * sizeof(BodyDev));
   // one record per distinct sample node: up to 4 per point with the interpolated rule
   const size_t maxrec = (size_t)maxp * (p.si_rule == 1 ? 4 : 1);
   L.recs = take(maxrec * sizeof(SiRec));
@@ -98,7 +109,7 @@ Layout layout_of(const vplbm_params &p) {
   L.sig = take(2 * L.sig_stride);
   // convective-edge state: 3 incoming populations along each of the 4 edges
   L.cbc = take((size_t)3 * (2 * (size_t)p.ny + 2 * (size_t)p.nx) * compute_size(p.precision));
-  L.pts = take((size_t)5 * maxp * sizeof(double));
+  L.pts = take((size_t)6 * maxp * sizeof(double));  // x, y, nx, ny, ds, body
   L.verts = take((size_t)2 * maxv * sizeof(long long));
   L.staging = take(STAGE_DOUBLES * sizeof(double));
   L.siout = take(8 * sizeof(double));
@@ -126,8 +137,10 @@ const char *check_params(const vplbm_params *p) {
   if ((p->south.kind == VPLBM_BC_PERIODIC) != (p->north.kind == VPLBM_BC_PERIODIC))
     return "south and north must both be periodic or both not";
   if (!(p->trt_lambda >= 0.0) || !std::isfinite(p->trt_lambda)) return "trt_lambda must be finite and >= 0";
-  if (p->hist_capacity < 0 || p->max_si_points < 0 || p->max_vertices < 0)
+  if (p->hist_capacity < 0 || p->max_si_points < 0 || p->max_vertices < 0 || p->max_bodies < 0 ||
+      p->max_interface_cells < 0)
     return "capacities must be >= 0";
+  if (p->max_bodies > MAX_BODIES) return "max_bodies exceeds 63";
   if (p->max_si_points > SI_MAX) return "max_si_points exceeds 4096";
   if (p->si_rule != 0 && p->si_rule != 1) return "si_rule must be 0 or 1";
   if (p->si_rule == 1 && (p->max_si_points == 0 || p->max_si_points > SI_MAX / 4))
@@ -156,13 +169,20 @@ struct vplbm_lattice {
   bool pwin_ok = false;
   bool initialized = false;
   bool macro_valid = false;
-  int cap = 0, maxp = 0, maxv = 0;
+  int cap = 0, maxp = 0, maxv = 0, maxb = 1;
+  long long maxslot = 0;
+  int nbody = 1;                          // bodies in the mask (ids 1..nbody)
+  std::vector<double> refs;               // static multi-body: reference point of each body [2][nbody]
+  // points registered per body, [5][n] each (index = body id); only body 1
+  // when the lattice holds one body
+  std::vector<std::vector<double>> si_sets = std::vector<std::vector<double>>(MAX_BODIES + 1);
   int bx = 64, by = 4;  // step tile shape
   double gx = 0.0, gy = 0.0;
   int shape = SHAPE_NONE, mode = MODE_STATIC;
   double disk_r = 0.0;
   int npts = 0;
   std::vector<double> si_world;  // host copy of the registered world points [5][npts]
+  std::vector<int> si_body;      // body of each registered point (1..nbody)
   std::string err;
 
   char *at(size_t off) const { return base + off; }
@@ -170,8 +190,12 @@ struct vplbm_lattice {
   void *Bbuf() const { return at(cur == 0 ? L.B : L.A); }
   uint8_t *mask() const { return (uint8_t *)at(L.mask); }
   Ctl *ctl() const { return (Ctl *)at(L.ctl); }
-  // partial sums written by step n live in buffer n % 2
-  double *part(long long n) const { return (double *)at(L.partials + (size_t)(n & 1) * L.partials_stride); }
+  // interface contributions and sample stresses written by step n live in buffer n % 2
+  double *me(long long n) const { return (double *)at(L.me + (size_t)(n & 1) * L.me_stride); }
+  int *imap() const { return (int *)at(L.imap); }
+  BodyTab *bt() const { return (BodyTab *)at(L.bt); }
+  BodyDev *bodies() const { return (BodyDev *)at(L.bodies); }
+  int *err_dev() const { return (int *)((char *)ctl() + offsetof(Ctl, err)); }
   double *sig(long long n) const { return (double *)at(L.sig + (size_t)(n & 1) * L.sig_stride); }
   const SiRec *recs() const { return (const SiRec *)at(L.recs); }
 
@@ -257,6 +281,7 @@ struct vplbm_lattice {
     a.gx = T(gx);
     a.gy = T(gy);
     a.cbc = (T *)at(L.cbc);
+    a.bodies = bodies();
     for (int e = 0; e < 4; ++e) {
       const double U = E[e]->kind == VPLBM_BC_CONVECTIVE ? E[e]->ux : 0.0;
       a.cbu[e] = T(U);
@@ -298,26 +323,28 @@ int launch_step_t(vplbm_lattice *L, bool macro) {
   const SiRec *recs = (const SiRec *)L->at(L->L.recs);
   const int *smap = (const int *)L->at(L->L.si_map);
   const long long n = L->nstep + 1;  // the step this launch computes
-  double *pout = L->part(n);
-  const double *pprev = L->part(n - 1);
+  double *mout = L->me(n);
+  const double *mprev = L->me(n - 1);
   double *gout = L->sig(n);
   const double *gprev = L->sig(n - 1);
   const int fin_prev = L->pending ? 1 : 0;
   double *hist = (double *)L->at(L->L.hist);
+  const int *imap = L->imap();
+  const BodyTab *bt = L->bt();
   if (macro) {
     if (a.trt)
       VP_LAUNCH((k_step<S, BX, BY, true, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
-                L->ctl(), recs, smap, pout, pprev, gout, gprev, fin_prev, hist, L->cap, r, u, v);
+                L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
     else
       VP_LAUNCH((k_step<S, BX, BY, true, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
-                L->ctl(), recs, smap, pout, pprev, gout, gprev, fin_prev, hist, L->cap, r, u, v);
+                L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
   } else {
     if (a.trt)
       VP_LAUNCH((k_step<S, BX, BY, false, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
-                L->ctl(), recs, smap, pout, pprev, gout, gprev, fin_prev, hist, L->cap, r, u, v);
+                L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
     else
       VP_LAUNCH((k_step<S, BX, BY, false, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(),
-                a, L->ctl(), recs, smap, pout, pprev, gout, gprev, fin_prev, hist, L->cap, r, u, v);
+                a, L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
   }
   return L->launched("k_step");
 }
@@ -408,14 +435,15 @@ int launch_flags(vplbm_lattice *L, int x0, int y0, int x1, int y1) {
   if (x1 <= x0 || y1 <= y0) return VPLBM_OK;
   dim3 blk(256), grd((x1 - x0 + 255) / 256, y1 - y0);
   VP_LAUNCH(k_mask_flags, grd, blk, 0, L->stream, L->mask(), L->p.nx, L->p.ny, L->pitch, x0,
-                     y0, x1, y1, (int)L->periodic_x(), (int)L->periodic_y());
+                     y0, x1, y1, (int)L->periodic_x(), (int)L->periodic_y(), L->err_dev());
   return L->launched("k_mask_flags");
 }
 
 int launch_si_select(vplbm_lattice *L) {
   VP_LAUNCH(k_si_select, dim3(1), dim3(SI_NT), 0, L->stream, L->mask(), L->ctl(),
                      (const double *)L->at(L->L.pts), L->maxp, (SiRec *)L->at(L->L.recs),
-                     (int *)L->at(L->L.si_map), L->p.nx, L->p.ny, L->pitch);
+                     (int *)L->at(L->L.si_map), L->bt(), (const BodyDev *)L->bodies(), L->p.nx, L->p.ny,
+                     L->pitch);
   return L->launched("k_si_select");
 }
 
@@ -423,20 +451,20 @@ int launch_si_select(vplbm_lattice *L) {
 // body, rebuild the mask
 int launch_body_step(vplbm_lattice *L) {
   VP_LAUNCH(k_body_step, dim3(1), dim3(BODY_NT), 0, L->stream, L->mask(), L->ctl(),
-                     (const double *)L->part(L->nstep + 1), (const double *)L->sig(L->nstep + 1),
-                     (double *)L->at(L->L.hist), L->cap, L->bx, L->by,
-                     L->p.nx, L->p.ny, L->pitch, (int)L->periodic_x(), (int)L->periodic_y(),
-                     (const double *)L->at(L->L.pts), L->maxp, (SiRec *)L->at(L->L.recs),
-                     (int *)L->at(L->L.si_map));
+                     (const double *)L->me(L->nstep + 1), (const double *)L->sig(L->nstep + 1),
+                     (double *)L->at(L->L.hist), L->cap, L->maxb, L->p.nx, L->p.ny, L->pitch,
+                     (int)L->periodic_x(), (int)L->periodic_y(), (const double *)L->at(L->L.pts), L->maxp,
+                     (SiRec *)L->at(L->L.recs), (int *)L->at(L->L.si_map), L->imap(), (int)L->maxslot, L->bt(),
+                     (const BodyDev *)L->bodies());
   return L->launched("k_body_step");
 }
 
 // sum the partials of the last step into the history (forces readable)
 int flush(vplbm_lattice *L) {
   if (!L->pending) return VPLBM_OK;
-  VP_LAUNCH((k_finalize<256>), dim3(1), dim3(256), 0, L->stream, (const double *)L->part(L->nstep),
-                     (const double *)L->sig(L->nstep), L->recs(), L->ctl(), (double *)L->at(L->L.hist), L->cap,
-                     L->bx, L->by);
+  VP_LAUNCH((k_finalize<256>), dim3(1), dim3(256), 0, L->stream, (const double *)L->me(L->nstep),
+                     (const double *)L->sig(L->nstep), L->recs(), (const BodyTab *)L->bt(), L->ctl(),
+                     (double *)L->at(L->L.hist), L->cap, L->maxb);
   int rc = L->launched("k_finalize");
   if (!rc) L->pending = false;
   return rc;
@@ -462,6 +490,35 @@ int one_step(vplbm_lattice *L, bool macro) {
 
 long long fixq(double v) { return llround(v * FIXQ); }
 
+// a moving disk renumbers its interface cells inside its rebuilt region
+// every step: the slots must hold the largest such region
+int check_moving_capacity(vplbm_lattice *L) {
+  const long long side = (long long)std::ceil(2.0 * L->disk_r) + 2 * REGION_MARGIN + 8;
+  if (side * side > L->maxslot)
+    return L->fail(VPLBM_EINVAL, "max_interface_cells = %lld is below a moving disk's region (%lld cells)",
+                   L->maxslot, side * side);
+  return VPLBM_OK;
+}
+
+// the registered points of bodies 1..nbody, concatenated body by body
+void rebuild_points(vplbm_lattice *L) {
+  int n = 0;
+  for (int b = 1; b <= L->nbody; ++b) n += (int)(L->si_sets[b].size() / 5);
+  L->si_world.assign((size_t)5 * n, 0.0);
+  L->si_body.assign(n, 1);
+  int o = 0;
+  for (int b = 1; b <= L->nbody; ++b) {
+    const std::vector<double> &v = L->si_sets[b];
+    const int m = (int)(v.size() / 5);
+    for (int i = 0; i < m; ++i) {
+      for (int k = 0; k < 5; ++k) L->si_world[(size_t)k * n + o + i] = v[(size_t)k * m + i];
+      L->si_body[o + i] = b;
+    }
+    o += m;
+  }
+  L->npts = n;
+}
+
 // clear the mask and SI tables, reset the force window
 int reset_geometry(vplbm_lattice *L, Ctl &c) {
   int rc = L->hip(hipMemsetAsync(L->mask(), 0, (size_t)L->p.ny * L->pitch, L->stream), "mask clear");
@@ -472,7 +529,23 @@ int reset_geometry(vplbm_lattice *L, Ctl &c) {
   c.win[2] = c.win[3] = 1;
   c.region[0] = c.region[1] = c.region[2] = c.region[3] = 0;
   c.nrec = 0;
-  return VPLBM_OK;
+  c.nslot = 0;
+  c.nbody = 1;
+  L->nbody = 1;
+  L->refs.clear();
+  bool others = false;  // points of bodies 2.. go with their bodies
+  for (int b = 2; b <= MAX_BODIES; ++b) {
+    others = others || !L->si_sets[b].empty();
+    L->si_sets[b].clear();
+  }
+  if (others) {
+    rebuild_points(L);
+    c.npts = L->npts;
+  }
+  rc = L->hip(hipMemsetAsync(L->bt(), 0, (size_t)MAX_BODIES * sizeof(BodyTab), L->stream), "body table clear");
+  if (!rc) rc = L->hip(hipMemsetAsync(L->bodies(), 0, (size_t)(MAX_BODIES + 1) * sizeof(BodyDev), L->stream),
+                       "bodies clear");
+  return rc;
 }
 
 // reselect sample nodes after the mask or the points changed
@@ -485,20 +558,97 @@ int check_sample_error(vplbm_lattice *L) {
   Ctl c;
   int rc = L->ctl_pull(c);
   if (rc) return rc;
-  if (c.err & 1) {
+  const int e = c.err;
+  if (e & 7) {
     c.err = 0;
     rc = L->ctl_push(c);
     if (rc) return rc;
+  }
+  if (e & 2) return L->fail(VPLBM_EINVAL, "a fluid cell is linked to two different bodies");
+  if (e & 4) return L->fail(VPLBM_EINVAL, "a sample node serves two different bodies");
+  if (e & 1)
     return L->fail(VPLBM_ENOSAMPLE, "a stress-integration point has no fluid sample node within 4 "
                                     "nodes along its normal");
-  }
   return VPLBM_OK;
+}
+
+// Number the interface cells (one momentum-exchange slot each), body by
+// body and row-major inside a body, from the current mask: a solid cell
+// belongs to its own body, a fluid one to the body of its solid lattice
+// neighbours.  Writes imap, each body's slot range and nslot.
+int number_interfaces(vplbm_lattice *L) {
+  const int nx = L->p.nx, ny = L->p.ny, pitch = L->pitch;
+  std::vector<uint8_t> m((size_t)ny * pitch);
+  int rc = L->hip(hipMemcpyAsync(m.data(), L->mask(), m.size(), hipMemcpyDeviceToHost, L->stream), "mask read");
+  if (!rc) rc = L->sync();
+  if (rc) return rc;
+  const bool px = L->periodic_x(), py = L->periodic_y();
+  std::vector<std::vector<int>> cells(MAX_BODIES + 1);
+  static const int CXH[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, CYH[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const uint8_t v = m[(size_t)j * pitch + i];
+      if (!(v & M_IFACE)) continue;
+      int b = v & M_BODY;
+      for (int a = 1; a < 9 && !b; ++a) {
+        int X = i + CXH[a], Y = j + CYH[a];
+        if (X < 0 || X >= nx) {
+          if (!px) continue;
+          X = (X + nx) % nx;
+        }
+        if (Y < 0 || Y >= ny) {
+          if (!py) continue;
+          Y = (Y + ny) % ny;
+        }
+        b = m[(size_t)Y * pitch + X] & M_BODY;
+      }
+      if (b) cells[b].push_back(j * pitch + i);
+    }
+  std::vector<BodyTab> bt(MAX_BODIES);
+  rc = L->hip(hipMemcpyAsync(bt.data(), L->bt(), bt.size() * sizeof(BodyTab), hipMemcpyDeviceToHost, L->stream),
+              "body table read");
+  if (!rc) rc = L->sync();
+  if (rc) return rc;
+  std::vector<int> pairs;
+  int slot = 0;
+  for (int b = 1; b <= MAX_BODIES; ++b) {
+    bt[b - 1].me0 = slot;
+    for (int c : cells[b]) {
+      pairs.push_back(c);
+      pairs.push_back(slot++);
+    }
+    bt[b - 1].me1 = slot;
+  }
+  if (slot > L->maxslot)
+    return L->fail(VPLBM_EINVAL, "%d interface cells exceed max_interface_cells = %lld", slot, L->maxslot);
+  // scatter the slot numbers through the staging buffer, in chunks
+  int *stage = (int *)L->at(L->L.staging);
+  const size_t chunk = STAGE_DOUBLES;  // pairs of ints per chunk (8 bytes each)
+  for (size_t k = 0; k < pairs.size() / 2; k += chunk) {
+    const size_t nk = std::min(chunk, pairs.size() / 2 - k);
+    rc = L->hip(hipMemcpyAsync(stage, pairs.data() + 2 * k, nk * 2 * sizeof(int), hipMemcpyHostToDevice, L->stream),
+                "slot upload");
+    if (rc) return rc;
+    VP_LAUNCH(k_scatter_slots, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, L->stream, (const int *)stage,
+              (int)nk, L->imap());
+    rc = L->launched("k_scatter_slots");
+    if (!rc) rc = L->sync();
+    if (rc) return rc;
+  }
+  rc = L->hip(hipMemcpyAsync(L->bt(), bt.data(), bt.size() * sizeof(BodyTab), hipMemcpyHostToDevice, L->stream),
+              "body table write");
+  if (rc) return rc;
+  Ctl c;
+  rc = L->ctl_pull(c);
+  if (rc) return rc;
+  c.nslot = slot;
+  return L->ctl_push(c);
 }
 
 // store SI points (world frame or, for a moving body, body frame) in device memory
 int upload_points(vplbm_lattice *L, const Ctl &c) {
   const int n = L->npts, mp = L->maxp;
-  std::vector<double> buf((size_t)5 * mp, 0.0);
+  std::vector<double> buf((size_t)6 * mp, 0.0);
   const bool moving = L->mode != MODE_STATIC;
   const double co = std::cos(-c.body.theta), sn = std::sin(-c.body.theta);
   for (int i = 0; i < n; ++i) {
@@ -517,6 +667,7 @@ int upload_points(vplbm_lattice *L, const Ctl &c) {
       buf[3 * mp + i] = ny;
     }
     buf[4 * mp + i] = L->si_world[4 * n + i];
+    buf[5 * mp + i] = L->si_body.empty() ? 1.0 : (double)L->si_body[i];
   }
   int rc = L->hip(hipMemcpyAsync(L->at(L->L.pts), buf.data(), buf.size() * sizeof(double),
                                  hipMemcpyHostToDevice, L->stream),
@@ -562,6 +713,8 @@ int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *h
   L->cap = p->hist_capacity > 0 ? p->hist_capacity : DEFAULT_HIST;
   L->maxp = p->max_si_points > 0 ? p->max_si_points : DEFAULT_PTS;
   L->maxv = p->max_vertices > 0 ? p->max_vertices : DEFAULT_VERTS;
+  L->maxb = max_bodies_of(*p);
+  L->maxslot = max_slots_of(*p);
   if (dev_mem) {
     if (dev_bytes < L->L.total || ((uintptr_t)dev_mem % ALIGN) != 0) {
       g_create_err = "device buffer smaller than vplbm_required_bytes or not 256-byte aligned";
@@ -679,7 +832,10 @@ static int finish_geometry(vplbm_lattice *L, Ctl &c, int fx0, int fy0, int fx1, 
   d.nrec = 0;
   d.si_moving = L->mode != MODE_STATIC;
   for (int k = 0; k < 3; ++k) d.fq[k] = c.fq[k];
+  d.nbody = L->nbody;
   rc = L->ctl_push(d);
+  if (!rc) rc = check_sample_error(L);  // a fluid cell linked to two bodies
+  if (!rc) rc = number_interfaces(L);
   if (rc) return rc;
   if (L->npts) {
     rc = upload_points(L, d);
@@ -796,7 +952,7 @@ int vplbm_set_mask(vplbm_lattice *L, const uint8_t *solid) {
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i)
       if (solid[(size_t)j * nx + i]) {
-        rows[(size_t)j * L->pitch + i] = M_SOLID;
+        rows[(size_t)j * L->pitch + i] = 1;  // body 1
         x0 = std::min(x0, i); x1 = std::max(x1, i);
         y0 = std::min(y0, j); y1 = std::max(y1, j);
       }
@@ -840,6 +996,10 @@ int vplbm_set_body_motion(vplbm_lattice *L, const vplbm_body_state *s) {
   if (L->shape == SHAPE_NONE) return L->fail(VPLBM_ESTATE, "no body");
   if (L->shape != SHAPE_DISK && moves)
     return L->fail(VPLBM_EINVAL, "only disks can move; polygons and masks are static");
+  if (moves) {
+    const int rc = check_moving_capacity(L);
+    if (rc) return rc;
+  }
   Ctl c;
   int rc = L->ctl_pull(c);
   if (rc) return rc;
@@ -886,6 +1046,10 @@ int vplbm_set_body_dynamics(vplbm_lattice *L, double rho_s, double gx, double gy
   }
   L->pwin_ok = false;
   if (L->shape != SHAPE_DISK) return L->fail(VPLBM_ESTATE, "free bodies must be disks");
+  {
+    const int rc = check_moving_capacity(L);
+    if (rc) return rc;
+  }
   if (!(rho_s > 0.0) || !std::isfinite(rho_s) || !std::isfinite(gx) || !std::isfinite(gy))
     return L->fail(VPLBM_EINVAL, "rho_s > 0 and finite gravity required");
   if (source != VPLBM_FORCE_ME && source != VPLBM_FORCE_SI)
@@ -908,32 +1072,39 @@ int vplbm_set_body_dynamics(vplbm_lattice *L, double rho_s, double gx, double gy
   return rc;
 }
 
-int vplbm_set_si_points(vplbm_lattice *L, const double *xy, const double *nrm, const double *ds, int npts) {
+int vplbm_set_si_points_body(vplbm_lattice *L, int body, const double *xy, const double *nrm, const double *ds,
+                             int npts) {
   if (!L) return VPLBM_EINVAL;
   {
     const int frc = flush(L);
     if (frc) return frc;
   }
   L->pwin_ok = false;
+  if (body < 1 || body > L->nbody) return L->fail(VPLBM_EINVAL, "body must be in 1..%d", L->nbody);
   if (npts < 0 || npts > L->maxp) return L->fail(VPLBM_EINVAL, "npts must be in 0..%d", L->maxp);
   if (npts > 0 && (!xy || !nrm || !ds)) return L->fail(VPLBM_EINVAL, "NULL point arrays");
   for (int i = 0; i < npts; ++i)
     if (!std::isfinite(xy[2 * i]) || !std::isfinite(xy[2 * i + 1]) || !std::isfinite(nrm[2 * i]) ||
         !std::isfinite(nrm[2 * i + 1]) || !std::isfinite(ds[i]))
       return L->fail(VPLBM_EINVAL, "point %d not finite", i);
-  L->si_world.assign((size_t)5 * npts, 0.0);
+  int total = npts;
+  for (int b = 1; b <= L->nbody; ++b)
+    if (b != body) total += (int)(L->si_sets[b].size() / 5);
+  if (total > L->maxp) return L->fail(VPLBM_EINVAL, "%d points in all exceed max_si_points = %d", total, L->maxp);
+  std::vector<double> &v = L->si_sets[body];
+  v.assign((size_t)5 * npts, 0.0);
   for (int i = 0; i < npts; ++i) {
-    L->si_world[i] = xy[2 * i];
-    L->si_world[npts + i] = xy[2 * i + 1];
-    L->si_world[2 * npts + i] = nrm[2 * i];
-    L->si_world[3 * npts + i] = nrm[2 * i + 1];
-    L->si_world[4 * npts + i] = ds[i];
+    v[i] = xy[2 * i];
+    v[npts + i] = xy[2 * i + 1];
+    v[2 * npts + i] = nrm[2 * i];
+    v[3 * npts + i] = nrm[2 * i + 1];
+    v[4 * npts + i] = ds[i];
   }
-  L->npts = npts;
+  rebuild_points(L);
   Ctl c;
   int rc = L->ctl_pull(c);
   if (rc) return rc;
-  c.npts = npts;
+  c.npts = L->npts;
   c.si_moving = L->mode != MODE_STATIC;
   c.nrec = 0;
   rc = L->ctl_push(c);
@@ -942,12 +1113,88 @@ int vplbm_set_si_points(vplbm_lattice *L, const double *xy, const double *nrm, c
   const int x0 = std::min(c.win[0], c.region[0]), y0 = std::min(c.win[1], c.region[1]);
   const int x1 = std::max(c.win[2], c.region[2]), y1 = std::max(c.win[3], c.region[3]);
   rc = launch_flags(L, x0, y0, x1, y1);
+  if (!rc) rc = L->sync();
   if (rc) return rc;
-  if (npts == 0) return L->sync();
+  if (L->npts == 0) {
+    // no records: every body's record range empty
+    std::vector<BodyTab> bt(MAX_BODIES);
+    rc = L->hip(hipMemcpyAsync(bt.data(), L->bt(), bt.size() * sizeof(BodyTab), hipMemcpyDeviceToHost, L->stream),
+                "body table read");
+    if (!rc) rc = L->sync();
+    if (rc) return rc;
+    for (BodyTab &t : bt) t.rec0 = t.rec1 = 0;
+    rc = L->hip(hipMemcpyAsync(L->bt(), bt.data(), bt.size() * sizeof(BodyTab), hipMemcpyHostToDevice, L->stream),
+                "body table write");
+    if (!rc) rc = L->sync();
+    return rc;
+  }
   rc = upload_points(L, c);
   if (!rc) rc = refresh_si(L);
   if (!rc) rc = check_sample_error(L);
   return rc;
+}
+
+int vplbm_set_si_points(vplbm_lattice *L, const double *xy, const double *nrm, const double *ds, int npts) {
+  return vplbm_set_si_points_body(L, 1, xy, nrm, ds, npts);
+}
+
+int vplbm_set_body_ids(vplbm_lattice *L, const uint8_t *ids, int nbody, const double *ref_xy) {
+  if (!L || !ids || !ref_xy) return L ? L->fail(VPLBM_EINVAL, "NULL argument") : VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
+  L->pwin_ok = false;
+  if (nbody < 1 || nbody > L->maxb) return L->fail(VPLBM_EINVAL, "nbody must be in 1..max_bodies = %d", L->maxb);
+  for (int k = 0; k < 2 * nbody; ++k)
+    if (!std::isfinite(ref_xy[k])) return L->fail(VPLBM_EINVAL, "reference point %d not finite", k / 2);
+  const int nx = L->p.nx, ny = L->p.ny;
+  std::vector<uint8_t> rows((size_t)ny * L->pitch, 0);
+  int x0 = nx, y0 = ny, x1 = -1, y1 = -1;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int id = ids[(size_t)j * nx + i];
+      if (!id) continue;
+      if (id > nbody) return L->fail(VPLBM_EINVAL, "cell (%d, %d) has body id %d > nbody = %d", i, j, id, nbody);
+      rows[(size_t)j * L->pitch + i] = (uint8_t)id;
+      x0 = std::min(x0, i); x1 = std::max(x1, i);
+      y0 = std::min(y0, j); y1 = std::max(y1, j);
+    }
+  Ctl c;
+  int rc = L->ctl_pull(c);
+  if (rc) return rc;
+  // the points of the previous geometry go with it
+  for (auto &v : L->si_sets) v.clear();
+  L->si_world.clear();
+  L->si_body.clear();
+  L->npts = 0;
+  c.npts = 0;
+  rc = reset_geometry(L, c);
+  if (rc) return rc;
+  std::vector<BodyDev> tab(MAX_BODIES + 1, BodyDev{0.0, 0.0, 0.0, 0.0, 0.0, 0.0});
+  for (int b = 1; b <= nbody; ++b) tab[b] = BodyDev{ref_xy[2 * (b - 1)], ref_xy[2 * (b - 1) + 1], 0.0, 0.0, 0.0, 0.0};
+  rc = L->hip(hipMemcpyAsync(L->mask(), rows.data(), rows.size(), hipMemcpyHostToDevice, L->stream), "mask upload");
+  if (!rc)
+    rc = L->hip(hipMemcpyAsync(L->bodies(), tab.data(), tab.size() * sizeof(BodyDev), hipMemcpyHostToDevice,
+                               L->stream),
+                "bodies upload");
+  if (!rc) rc = L->sync();
+  if (rc) return rc;
+  c.body = tab[1];
+  c.shape = SHAPE_MASK;
+  c.mode = MODE_STATIC;
+  if (x1 >= 0) {
+    int w0 = x0 - 1, w1 = x1 + 2, h0 = y0 - 1, h1 = y1 + 2;
+    if (w0 < 0 || w1 > nx) { if (L->periodic_x()) { w0 = 0; w1 = nx; } else { w0 = std::max(w0, 0); w1 = std::min(w1, nx); } }
+    if (h0 < 0 || h1 > ny) { if (L->periodic_y()) { h0 = 0; h1 = ny; } else { h0 = std::max(h0, 0); h1 = std::min(h1, ny); } }
+    c.win[0] = w0; c.win[1] = h0; c.win[2] = w1; c.win[3] = h1;
+  }
+  for (int k = 0; k < 4; ++k) c.region[k] = c.win[k];
+  L->shape = SHAPE_MASK;
+  L->mode = MODE_STATIC;
+  L->nbody = nbody;
+  L->refs.assign(ref_xy, ref_xy + 2 * nbody);
+  return finish_geometry(L, c, 0, 0, nx, ny);
 }
 
 int vplbm_step(vplbm_lattice *L, int nsteps, int flags) {
@@ -1084,8 +1331,9 @@ int vplbm_forces_si_at(vplbm_lattice *L, const double *xy, const double *nrm, co
   return VPLBM_OK;
 }
 
-int vplbm_force_history(vplbm_lattice *L, int which, long long first, int n, double *out) {
+int vplbm_force_history_body(vplbm_lattice *L, int body, int which, long long first, int n, double *out) {
   if (!L || !out || n < 0) return VPLBM_EINVAL;
+  if (body < 1 || body > L->nbody) return L->fail(VPLBM_EINVAL, "body must be in 1..%d", L->nbody);
   {
     const int frc = flush(L);
     if (frc) return frc;
@@ -1093,16 +1341,33 @@ int vplbm_force_history(vplbm_lattice *L, int which, long long first, int n, dou
   if (which != VPLBM_FORCE_ME && which != VPLBM_FORCE_SI) return L->fail(VPLBM_EINVAL, "which");
   if (first < 1 || first + n - 1 > L->nstep || first <= L->nstep - L->cap)
     return L->fail(VPLBM_EINVAL, "steps %lld..%lld outside the kept history", first, first + n - 1);
-  std::vector<double> h((size_t)L->cap * 6);
+  std::vector<double> h((size_t)L->cap * L->maxb * 6);
   int rc = L->hip(hipMemcpyAsync(h.data(), L->at(L->L.hist), h.size() * 8, hipMemcpyDeviceToHost, L->stream),
                   "history read");
   if (!rc) rc = L->sync();
   if (rc) return rc;
   for (int k = 0; k < n; ++k) {
     const long long s = (first + k) % L->cap;
-    for (int i = 0; i < 3; ++i) out[3 * k + i] = h[s * 6 + 3 * which + i];
+    for (int i = 0; i < 3; ++i) out[3 * k + i] = h[(s * L->maxb + (body - 1)) * 6 + 3 * which + i];
   }
   return VPLBM_OK;
+}
+
+int vplbm_force_history(vplbm_lattice *L, int which, long long first, int n, double *out) {
+  return vplbm_force_history_body(L, 1, which, first, n, out);
+}
+
+int vplbm_forces_body(vplbm_lattice *L, int body, int which, double out[3]) {
+  if (!L || !out) return VPLBM_EINVAL;
+  if (body < 1 || body > L->nbody) return L->fail(VPLBM_EINVAL, "body must be in 1..%d", L->nbody);
+  if (which != VPLBM_FORCE_ME && which != VPLBM_FORCE_SI) return L->fail(VPLBM_EINVAL, "which");
+  if (body == 1) return read_last(L, which, out);
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
+  if (L->nstep == 0) return L->fail(VPLBM_ESTATE, "no step taken yet");
+  return vplbm_force_history_body(L, body, which, L->nstep, 1, out);
 }
 
 int vplbm_get_body_state(vplbm_lattice *L, vplbm_body_state *out) {
@@ -1242,12 +1507,16 @@ void fill_desc(vplbm_lattice *L, int tile0, void *out) {
   d.ctl = L->ctl();
   d.recs = (const SiRec *)L->at(L->L.recs);
   d.si_map = (const int *)L->at(L->L.si_map);
-  d.part[0] = L->part(0);
-  d.part[1] = L->part(1);
+  d.imap = L->imap();
+  d.bt = L->bt();
+  d.me[0] = L->me(0);
+  d.me[1] = L->me(1);
   d.sig[0] = L->sig(0);
   d.sig[1] = L->sig(1);
   d.hist = (double *)L->at(L->L.hist);
   d.cap = L->cap;
+  d.maxb = L->maxb;
+  d.maxslot = (int)L->maxslot;
   d.tile0 = tile0;
   d.cur0 = L->cur;
   d.pbit0 = (int)((L->nstep + 1) & 1);

@@ -36,6 +36,7 @@ EXPORTS = [
     "vplbm_forces_si_at", "vplbm_force_history", "vplbm_get_body_state", "vplbm_read_macro",
     "vplbm_read_populations", "vplbm_read_mask", "vplbm_read_macro_window", "vplbm_read_populations_window",
     "vplbm_batch_create", "vplbm_batch_destroy", "vplbm_batch_last_error", "vplbm_batch_step",
+    "vplbm_set_body_ids", "vplbm_set_si_points_body", "vplbm_forces_body", "vplbm_force_history_body",
 ]
 
 
@@ -54,7 +55,7 @@ class Params(C.Structure):
                 ("rho0", C.c_double), ("precision", C.c_int), ("west", Edge), ("east", Edge),
                 ("south", Edge), ("north", Edge), ("hist_capacity", C.c_int),
                 ("max_si_points", C.c_int), ("max_vertices", C.c_int), ("trt_lambda", C.c_double),
-                ("si_rule", C.c_int)]
+                ("si_rule", C.c_int), ("max_bodies", C.c_int), ("max_interface_cells", C.c_int)]
 
 
 class BodyState(C.Structure):
@@ -94,6 +95,10 @@ def load_library(path: str = LIB_PATH):
     L.vplbm_set_body_motion.argtypes = [vp, P(BodyState)]
     L.vplbm_set_body_dynamics.argtypes = [vp, C.c_double, C.c_double, C.c_double, ip]
     L.vplbm_set_si_points.argtypes = [vp, dp, dp, dp, ip]
+    L.vplbm_set_si_points_body.argtypes = [vp, ip, dp, dp, dp, ip]
+    L.vplbm_set_body_ids.argtypes = [vp, P(C.c_uint8), ip, dp]
+    L.vplbm_forces_body.argtypes = [vp, ip, ip, dp]
+    L.vplbm_force_history_body.argtypes = [vp, ip, ip, C.c_longlong, ip, dp]
     L.vplbm_step.argtypes = [vp, ip, ip]
     L.vplbm_step_timed.argtypes = [vp, ip, ip, dp]
     L.vplbm_sync.argtypes = [vp]
@@ -135,7 +140,7 @@ def _f64(a, shape=None):
 
 def make_params(nx, ny, tau, eta, rho0=1.0, precision="f32", west=(PERIODIC, 0, 0), east=(PERIODIC, 0, 0),
                 south=(PERIODIC, 0, 0), north=(PERIODIC, 0, 0), hist_capacity=0, max_si_points=0,
-                max_vertices=0, trt_lambda=0.0, si_rule=0) -> Params:
+                max_vertices=0, trt_lambda=0.0, si_rule=0, max_bodies=0, max_interface_cells=0) -> Params:
     p = Params()
     p.nx, p.ny, p.tau, p.eta, p.rho0 = int(nx), int(ny), float(tau), float(eta), float(rho0)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -144,6 +149,8 @@ def make_params(nx, ny, tau, eta, rho0=1.0, precision="f32", west=(PERIODIC, 0, 
     p.hist_capacity, p.max_si_points, p.max_vertices = hist_capacity, max_si_points, max_vertices
     p.trt_lambda = float(trt_lambda)
     p.si_rule = int(si_rule)
+    p.max_bodies = int(max_bodies)
+    p.max_interface_cells = int(max_interface_cells)
     return p
 
 
@@ -243,6 +250,18 @@ class Lattice:
         m = np.ascontiguousarray((np.asarray(solid) != 0).astype(np.uint8).reshape(self.ny, self.nx))
         self._chk(self._lib.vplbm_set_mask(self._h, m.ctypes.data_as(C.POINTER(C.c_uint8))))
 
+    def set_body_ids(self, ids, refs):
+        """Several static bodies: ids [ny][nx] (0 fluid, 1..nbody) and each body's reference point."""
+        m = np.ascontiguousarray(np.asarray(ids, dtype=np.uint8).reshape(self.ny, self.nx))
+        r = _f64(refs).reshape(-1, 2)
+        self._chk(self._lib.vplbm_set_body_ids(self._h, m.ctypes.data_as(C.POINTER(C.c_uint8)), len(r),
+                                               _dptr(np.ascontiguousarray(r))))
+
+    def set_si_points_body(self, body, xy, nrm, ds):
+        xy, nrm, ds = _f64(xy), _f64(nrm), _f64(ds)
+        self._chk(self._lib.vplbm_set_si_points_body(self._h, int(body), _dptr(xy), _dptr(nrm), _dptr(ds),
+                                                     len(ds)))
+
     def set_motion(self, x, y, theta, u, v, omega):
         s = BodyState(x, y, theta, u, v, omega)
         self._chk(self._lib.vplbm_set_body_motion(self._h, C.byref(s)))
@@ -292,17 +311,22 @@ class Lattice:
         self._chk(self._lib.vplbm_forces_si_at(self._h, _dptr(xy), _dptr(nrm), _dptr(ds), len(ds), _dptr(o)))
         return o
 
-    def force_history(self, which, first, n):
-        o = np.zeros((n, 3))
-        self._chk(self._lib.vplbm_force_history(self._h, int(which), int(first), int(n), _dptr(o)))
+    def forces_body(self, body, which):
+        o = np.zeros(3)
+        self._chk(self._lib.vplbm_forces_body(self._h, int(body), int(which), _dptr(o)))
         return o
 
-    def history(self, which):
+    def force_history(self, which, first, n, body=1):
+        o = np.zeros((n, 3))
+        self._chk(self._lib.vplbm_force_history_body(self._h, int(body), int(which), int(first), int(n), _dptr(o)))
+        return o
+
+    def history(self, which, body=1):
         """All kept forces of steps 1..step_count (up to the ring capacity)."""
         n = self.step_count
         cap = self.params.hist_capacity or 4096
         first = max(1, n - cap + 1)
-        return self.force_history(which, first, n - first + 1)
+        return self.force_history(which, first, n - first + 1, body)
 
     def body_state(self):
         s = BodyState()

@@ -66,6 +66,7 @@ def test_required_bytes_valid():
     dict(trt_lambda=-0.1), dict(trt_lambda=float("nan")), dict(nx=20000), dict(si_rule=2), dict(si_rule=-1),
     dict(si_rule=1, max_si_points=1025), dict(si_rule=1, max_si_points=0),
     dict(east=(V.CONVECTIVE, -0.01, 0)), dict(east=(V.CONVECTIVE, float("nan"), 0)), dict(east=(5, 0, 0)),
+    dict(max_bodies=64), dict(max_bodies=-1), dict(max_interface_cells=-1),
 ])
 def test_required_bytes_rejects(kw):
     assert V.required_bytes(base(**kw)) == 0
@@ -76,6 +77,20 @@ def test_si_rule_interpolated_accepts_up_to_1024_points():
     n0 = V.required_bytes(base(si_rule=0, max_si_points=1024))
     # room for 4 sample records (48 bytes each) per point instead of 1
     assert n1 - n0 >= 3 * 1024 * 48
+
+
+def test_more_bodies_take_more_history_room():
+    n1 = V.required_bytes(base(max_bodies=1, hist_capacity=1000))
+    n63 = V.required_bytes(base(max_bodies=63, hist_capacity=1000))
+    assert V.required_bytes(base(hist_capacity=1000)) == n1
+    # one (steps x 6) FP64 history per body
+    assert n63 - n1 >= 62 * 6 * 8 * 1000
+
+
+def test_interface_slots_are_sized_by_the_caller():
+    a = V.required_bytes(base(max_interface_cells=100))
+    b = V.required_bytes(base(max_interface_cells=100000))
+    assert 0 < a < b
 
 
 def test_convective_edge_accepted():

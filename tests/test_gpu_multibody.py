@@ -1,0 +1,115 @@
+"""Several static bodies in one lattice (body ids in mask bits 0-5), forces
+per body, against the oracle.  FP64 bars as in test_gpu_parity: populations
+within 1e-12, each body's force histories within 1e-10 of its largest
+force; body ids and sample nodes bit-exact."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_cases import say
+
+pytestmark = pytest.mark.gpu
+
+NX, NY = 96, 48
+
+
+def scene():
+    ids = np.zeros((NY, NX), np.uint8)
+    ids[O.mask_disk(NX, NY, 20.3, 24.2, 6.1) != 0] = 1
+    ids[O.mask_disk(NX, NY, 47.1, 14.7, 4.9) != 0] = 2
+    poly = np.array([[62.2, 25.1], [80.7, 27.3], [74.4, 38.8], [61.6, 34.2]])
+    ids[O.mask_polygon(NX, NY, poly) != 0] = 3
+    refs = [(20.3, 24.2), (47.1, 14.7), (69.0, 31.0)]
+    pts = {1: W.disk_si_points(20.3, 24.2, 6.1, 44), 2: W.disk_si_points(47.1, 14.7, 4.9, 36),
+           3: W.polygon_si_points(poly)}
+    return ids, refs, pts
+
+
+def fields(seed):
+    ux, uy = W.smooth_random_velocity(NX, NY, seed=seed, amp=0.02)
+    return W.random_density(NX, NY, seed=seed + 1, amp=1e-3), 0.03 + ux, uy
+
+
+EDGES = ((O.VELOCITY, 0.03, 0.0), (O.OUTFLOW, 0, 0), (O.FREESLIP, 0, 0), (O.FREESLIP, 0, 0))
+
+
+def build(precision="f64", tau=0.65, trt=0.0, edges=EDGES, seed=11):
+    from paper_2110_00967_amd import vplbm as V
+    ids, refs, pts = scene()
+    p = V.make_params(NX, NY, tau, 1e-3, 1.0, precision, *edges, max_si_points=256, trt_lambda=trt,
+                      max_bodies=4)
+    g = V.Lattice(p)
+    g.set_body_ids(ids, refs)
+    for b, (xy, n, ds) in pts.items():
+        g.set_si_points_body(b, xy, n, ds)
+    g.set_fields(*fields(seed))
+    o = O.RefLattice(NX, NY, tau, 1e-3, 1.0, *edges, trt_lambda=trt)
+    o.set_body_ids(ids, refs)
+    for b, (xy, n, ds) in pts.items():
+        o.set_si_points_body(b, xy, n, ds)
+    o.set_fields(*fields(seed))
+    return g, o, ids
+
+
+@pytest.mark.parametrize("trt", [0.0, 3.0 / 16.0])
+def test_three_bodies_fp64_against_oracle(trt):
+    from gpu_cases import oracle_pops
+    from paper_2110_00967_amd import vplbm as V
+    say("three static bodies 96x48 fp64, TRT" if trt else "three static bodies 96x48 fp64")
+    g, o, ids = build(trt=trt)
+    m = g.mask()
+    assert np.array_equal(m & 0x3F, ids)
+    sample = np.zeros(NX * NY, bool)
+    sample[o.si_node] = True
+    assert np.array_equal((m.ravel() & 0x40) != 0, sample)
+    for _ in range(3):
+        g.step(20)
+        o.step(20)
+        assert np.abs(g.populations() - oracle_pops(o)).max() <= 1e-12
+    for b in (1, 2, 3):
+        for which, ref in ((V.FORCE_ME, o.me(b)), (V.FORCE_SI, o.si(b))):
+            h = g.history(which, body=b)
+            e = np.abs(h - ref).max() / np.abs(ref).max()
+            assert e <= 1e-10, (b, which, e)
+        last = g.forces_body(b, V.FORCE_ME)
+        assert np.abs(last - o.me(b)[-1]).max() <= 1e-10 * np.abs(o.me(b)).max()
+    # body 1 through the single-body calls
+    assert np.array_equal(g.forces_me(), g.forces_body(1, V.FORCE_ME))
+
+
+def test_bodies_too_close_are_rejected():
+    from paper_2110_00967_amd import vplbm as V
+    say("bodies one cell apart")
+    p = V.make_params(40, 20, 0.7, 1e-3, 1.0, "f32", max_bodies=2)
+    g = V.Lattice(p)
+    ids = np.zeros((20, 40), np.uint8)
+    ids[5:10, 5:10] = 1
+    ids[5:10, 11:15] = 2  # column 10 is fluid and linked to both
+    with pytest.raises(V.VplbmError) as e:
+        g.set_body_ids(ids, [(7, 7), (12, 7)])
+    assert e.value.code == V.EINVAL
+    ids[5:10, 11:15] = 0
+    ids[5:10, 12:15] = 2  # two fluid columns between them: fine
+    g.set_body_ids(ids, [(7, 7), (13, 7)])
+    with pytest.raises(V.VplbmError):
+        g.set_body_ids(ids, [(7, 7)])  # id 2 > nbody
+
+
+def test_multibody_in_batch_equals_alone():
+    from paper_2110_00967_amd import vplbm as V
+    say("multi-body lattice inside a batch, fp32")
+    g, _, _ = build("f32")
+    g.step(37)
+    alone = [g.history(w, body=b) for b in (1, 2, 3) for w in (V.FORCE_ME, V.FORCE_SI)]
+    pops = g.populations()
+    g.close()
+    a, _, _ = build("f32")
+    other = V.Lattice.from_case(W.case_disk_channel(), precision="f32")
+    bt = V.Batch([other, a])
+    bt.step([20, 37])
+    assert np.array_equal(a.populations(), pops)
+    got = [a.history(w, body=b) for b in (1, 2, 3) for w in (V.FORCE_ME, V.FORCE_SI)]
+    for x, y in zip(got, alone):
+        assert np.array_equal(x, y)
+    bt.close()
