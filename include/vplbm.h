@@ -100,7 +100,10 @@ typedef struct {
                         mask, see vplbm_set_body_ids); 0 = 1, max 63 */
   int max_interface_cells; /* momentum-exchange slots, one per interface cell
                         (a cell with a lattice link to the other phase);
-                        0 = min(nx ny, 32 (nx + ny)) */
+                        0 = min(nx ny, 32 (nx + ny)).  Set-up fails with
+                        VPLBM_EINVAL when the geometry has more, and a
+                        moving disk needs at least (ceil(2r) + 20)^2, the
+                        square it renumbers every step */
 } vplbm_params;
 
 /* Rigid-body state in lattice units: reference point (centre of a disk,
@@ -216,7 +219,8 @@ int vplbm_sync(vplbm_lattice *lat);
 long long vplbm_step_count(const vplbm_lattice *lat);
 /* Workgroup tile of the step kernel, bx cells along x times by rows:
  * 64x1, 64x2, 64x4 (default), 128x1, 128x2 or 256x1.  Results do not depend
- * on it except for the order of the per-tile force partial sums. */
+ * on it, forces included: they are summed per interface cell and per sample
+ * record, in an order fixed at geometry set-up. */
 int vplbm_set_tile(vplbm_lattice *lat, int bx, int by);
 
 /* Forces of the last step, out = (Fx, Fy, Tz) on the body, torque about the

@@ -464,7 +464,7 @@ __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
   static_assert(BODY_NT == SI_NT, "the block scan assumes SI_NT threads");
   __shared__ int reg[4];   // union region to rewrite
   __shared__ long long q[3];
-  __shared__ double lds[(BODY_NT / 64) * 6];
+  __shared__ double lds[FIN_WAVES * 6];
   __shared__ int wsum[BODY_NT / 64];
   __shared__ int nslot;
   // forces of the step just taken, needed by the update below (the only

@@ -206,39 +206,63 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], double *lds /*[NT/6
   }
 }
 
+// Width of the force finalize's summation order: FIN_W virtual lanes, lane v
+// summing slots v, v + FIN_W, ...; each virtual wave of 64 lanes reduced by a
+// butterfly, the FIN_W / 64 wave sums added in order.  Every workgroup size
+// runs the same order (a block of NT threads takes the virtual waves
+// w, w + NT/64, ... with its waves w), so forces do not depend on the tile
+// shape or on which kernel finalizes.
+constexpr int FIN_W = 256;
+constexpr int FIN_WAVES = FIN_W / 64;
+
 // Forces of one step -> its force-history slots, body by body
 // (deterministic: fixed assignment and order).  ME: the contributions the
 // interface cells stored in their slots.  SI: the stress each sample node
 // stored (sig), contracted with the node's aggregated weights, record by
 // record.  hist[(n mod cap) * maxb + b][6]; the control block keeps body 1's.
+// lds holds FIN_WAVES * 6 doubles.
 template <int NT>
 __device__ __forceinline__ void finalize_block(const double *__restrict__ me, const double *__restrict__ sig,
                                                const SiRec *__restrict__ recs, const BodyTab *__restrict__ bt,
                                                Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb,
                                                double *lds) {
+  static_assert(NT % 64 == 0, "whole waves");
   const long long n = ctl->step + 1;
   const int nb = ctl->nbody;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int b = 0; b < nb; ++b) {
     const BodyTab T = bt[b];
-    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int r = T.me0 + threadIdx.x; r < T.me1; r += NT) {
+    for (int k = wave; k < FIN_WAVES; k += NT / 64) {
+      const int v0 = k * 64 + lane;  // this thread's virtual lane
+      double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int r = T.me0 + v0; r < T.me1; r += FIN_W) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) v[i] += me[(long long)r * ME_STRIDE + i];
+        for (int i = 0; i < 3; ++i) v[i] += me[(long long)r * ME_STRIDE + i];
+      }
+      for (int r = T.rec0 + v0; r < T.rec1; r += FIN_W) {
+        const double *g = sig + (long long)r * SIG_STRIDE;
+        const SiRec R = recs[r];
+        v[3] += g[0] * R.ax + g[1] * R.ay;
+        v[4] += g[1] * R.ax + g[2] * R.ay;
+        v[5] += g[0] * R.txx + g[1] * R.txy + g[2] * R.tyy;
+      }
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        double x = v[i];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) lds[k * 6 + i] = x;
+      }
     }
-    for (int r = T.rec0 + threadIdx.x; r < T.rec1; r += NT) {
-      const double *g = sig + (long long)r * SIG_STRIDE;
-      const SiRec R = recs[r];
-      v[3] += g[0] * R.ax + g[1] * R.ay;
-      v[4] += g[1] * R.ax + g[2] * R.ay;
-      v[5] += g[0] * R.txx + g[1] * R.txy + g[2] * R.tyy;
-    }
-    block_reduce<NT, 6>(v, lds);
+    __syncthreads();
     if (threadIdx.x == 0) {
       double *h = hist + ((n % cap) * maxb + b) * 6;
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        h[i] = v[i];
-        if (b == 0) ctl->last[i] = v[i];
+        double x = 0.0;
+        for (int k = 0; k < FIN_WAVES; ++k) x += lds[k * 6 + i];
+        h[i] = x;
+        if (b == 0) ctl->last[i] = x;
       }
     }
     __syncthreads();  // lds is reused by the next body
@@ -471,7 +495,7 @@ __device__ __forceinline__ void step_tile(
   if (fin_prev && tile == 0) {
     // forces of the previous step (same slots and records: only static
     // bodies defer)
-    __shared__ double lds[(NT / 64) * 6];
+    __shared__ double lds[FIN_WAVES * 6];
     finalize_block<NT>(me_prev, sig_prev, recs, bt, ctl, hist, cap, maxb, lds);
   }
 }
@@ -557,7 +581,7 @@ template <int NT>
 __global__ void __launch_bounds__(NT)
     k_finalize(const double *__restrict__ me, const double *__restrict__ sig, const SiRec *__restrict__ recs,
                const BodyTab *__restrict__ bt, Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb) {
-  __shared__ double lds[(NT / 64) * 6];
+  __shared__ double lds[FIN_WAVES * 6];
   finalize_block<NT>(me, sig, recs, bt, ctl, hist, cap, maxb, lds);
 }
 

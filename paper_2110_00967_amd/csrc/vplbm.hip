@@ -559,11 +559,15 @@ int check_sample_error(vplbm_lattice *L) {
   int rc = L->ctl_pull(c);
   if (rc) return rc;
   const int e = c.err;
-  if (e & 7) {
+  if (e & 15) {
     c.err = 0;
     rc = L->ctl_push(c);
     if (rc) return rc;
   }
+  if (e & 8)
+    return L->fail(VPLBM_ESTATE, "more interface cells than max_interface_cells = %lld: the momentum exchange "
+                                 "dropped some",
+                   L->maxslot);
   if (e & 2) return L->fail(VPLBM_EINVAL, "a fluid cell is linked to two different bodies");
   if (e & 4) return L->fail(VPLBM_EINVAL, "a sample node serves two different bodies");
   if (e & 1)
@@ -1290,6 +1294,10 @@ static int read_last(vplbm_lattice *L, int which, double out[3]) {
   int rc = L->ctl_pull(c);
   if (rc) return rc;
   for (int i = 0; i < 3; ++i) out[i] = c.last[3 * which + i];
+  if (c.err & 8)
+    return L->fail(VPLBM_ESTATE, "more interface cells than max_interface_cells = %lld: the momentum exchange "
+                                 "dropped some",
+                   L->maxslot);
   if (c.err & 1) return L->fail(VPLBM_ENOSAMPLE, "a stress-integration point lost its sample node");
   return VPLBM_OK;
 }

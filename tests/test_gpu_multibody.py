@@ -113,3 +113,45 @@ def test_multibody_in_batch_equals_alone():
     for x, y in zip(got, alone):
         assert np.array_equal(x, y)
     bt.close()
+
+
+def test_forces_do_not_depend_on_the_tile():
+    # ME is summed per interface cell and SI per sample record, in an order
+    # fixed at set-up: every tile shape gives the same bits
+    from paper_2110_00967_amd import vplbm as V
+    say("tile shapes 64x4 / 128x2 / 256x1 / 64x1, three bodies fp32")
+    runs = []
+    for bx, by in ((64, 4), (128, 2), (256, 1), (64, 1)):
+        g, _, _ = build("f32", trt=3.0 / 16.0)
+        g.set_tile(bx, by)
+        g.step(25)
+        runs.append([g.populations()] + [g.history(w, body=b) for b in (1, 2, 3)
+                                         for w in (V.FORCE_ME, V.FORCE_SI)])
+        g.close()
+    for r in runs[1:]:
+        for a, b in zip(r, runs[0]):
+            assert np.array_equal(a, b)
+
+
+def test_interface_slot_capacity():
+    from paper_2110_00967_amd import vplbm as V
+    say("interface slot capacity")
+    g = V.Lattice(V.make_params(96, 48, 0.65, 1e-3, 1.0, "f32", max_interface_cells=20))
+    with pytest.raises(V.VplbmError) as e:
+        g.set_disk(40.0, 24.0, 8.0)  # about 60 interface cells
+    assert e.value.code == V.EINVAL
+    g.close()
+    g = V.Lattice(V.make_params(96, 48, 0.65, 1e-3, 1.0, "f32", max_interface_cells=500))
+    g.set_disk(40.0, 24.0, 3.0)
+    with pytest.raises(V.VplbmError) as e:
+        g.set_motion(40.0, 24.0, 0.0, 0.01, 0.0, 0.0)  # moving: needs (6 + 20)^2 = 676 slots
+    assert e.value.code == V.EINVAL
+    g.close()
+    g = V.Lattice(V.make_params(96, 48, 0.65, 1e-3, 1.0, "f32", max_interface_cells=676))
+    g.set_disk(40.0, 24.0, 3.0)
+    g.set_motion(40.0, 24.0, 0.0, 0.01, 0.0, 0.0)
+    g.init_uniform(1.0, 0.0, 0.0)
+    g.step(40)
+    g.sync()
+    assert np.isfinite(g.forces_me()).all()
+    g.close()
