@@ -194,11 +194,27 @@ __global__ void k_mask_flags(uint8_t *__restrict__ mask, int nx, int ny, int pit
 constexpr int SI_NT = 1024;
 constexpr int SI_MAX = 4096;
 
+// Solid test of a lattice node for the sample-node search: the mask (any
+// geometry), or, for a moving disk alone in its lattice, the disk rule that
+// has just built its mask (the same answer without a memory round trip).
+struct MaskSolid {
+  const uint8_t *mask;
+  int pitch;
+  __device__ __forceinline__ bool operator()(int X, int Y) const {
+    return (mask[(long long)Y * pitch + X] & M_BODY) != 0;
+  }
+};
+struct DiskSolid {
+  long long X, Y, R;  // centre and radius on the 1/FIXQ grid
+  __device__ __forceinline__ bool operator()(int i, int j) const { return disk_inside(X, Y, R, i, j); }
+};
+
 // Sample node of a point: the lattice direction beta maximizing
 // (c_beta . n)/|c_beta| (first on ties), then the first fluid node inside the
 // lattice among r_0 + k c_beta, k = 0..4, r_0 the node nearest to the point.
-__device__ __forceinline__ int si_node(const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
-                                       double px, double py, double n0, double n1) {
+template <typename Solid>
+__device__ __forceinline__ int si_node(const Solid &solid, int nx, int ny, double px, double py, double n0,
+                                       double n1) {
   const double S = 0.70710678118654752440;
   double sc[Q];
   sc[1] = n0;
@@ -221,7 +237,7 @@ __device__ __forceinline__ int si_node(const uint8_t *__restrict__ mask, int nx,
   for (int k = 0; k <= 4; ++k) {
     const int X = ix + k * bx, Y = iy + k * by;
     if (X < 0 || X >= nx || Y < 0 || Y >= ny) continue;
-    if (!(mask[(long long)Y * pitch + X] & M_BODY)) return Y * nx + X;
+    if (!solid(X, Y)) return Y * nx + X;
   }
   return -1;
 }
@@ -232,9 +248,9 @@ __device__ __forceinline__ int si_node(const uint8_t *__restrict__ mask, int nx,
 // Returns the number of (node, weight) pairs, 0 when there is no sample node.
 // The interpolation point is formed without FMA contraction so the floor()
 // decisions match a plain evaluation.
-__device__ __forceinline__ int si_stencil(const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
-                                          int rule, double px, double py, double n0, double n1, int (&node)[4],
-                                          double (&w)[4]) {
+template <typename Solid>
+__device__ __forceinline__ int si_stencil(const Solid &solid, int nx, int ny, int rule, double px, double py,
+                                          double n0, double n1, int (&node)[4], double (&w)[4]) {
   if (rule == 1) {
     const double qx = __dadd_rn(px, __dmul_rn(1.5, n0)), qy = __dadd_rn(py, __dmul_rn(1.5, n1));
     const int i0 = (int)floor(qx), j0 = (int)floor(qy);
@@ -245,32 +261,58 @@ __device__ __forceinline__ int si_stencil(const uint8_t *__restrict__ mask, int 
       for (int k = 0; k < 4; ++k) {
         const int X = i0 + (k & 1), Y = j0 + (k >> 1);
         node[k] = Y * nx + X;
-        if (mask[(long long)Y * pitch + X] & M_BODY) ok = false;
+        if (solid(X, Y)) ok = false;
         w[k] = __dmul_rn((k & 1) ? fx : __dsub_rn(1.0, fx), (k >> 1) ? fy : __dsub_rn(1.0, fy));
       }
       if (ok) return 4;
     }
   }
-  node[0] = si_node(mask, nx, ny, pitch, px, py, n0, n1);
+  node[0] = si_node(solid, nx, ny, px, py, n0, n1);
   w[0] = 1.0;
   return node[0] >= 0 ? 1 : 0;
 }
 
-// world position and normal of point i (points of a moving body are kept in
-// the body frame and placed with the current state)
-__device__ __forceinline__ void si_world(const double *__restrict__ pts, int maxp, int i, int moving,
-                                         const BodyDev &B, double &px, double &py, double &n0,
-                                         double &n1) {
-  const double a = pts[i], b = pts[maxp + i], c = pts[2 * maxp + i], d = pts[3 * maxp + i];
+// world position and normal of a point stored as (a, b) and normal (c, d)
+// (points of a moving body are kept in the body frame and placed with the
+// current state; co, sn = cos, sin of its angle)
+__device__ __forceinline__ void si_place(double a, double b, double c, double d, int moving, const BodyDev &B,
+                                         double co, double sn, double &px, double &py, double &n0, double &n1) {
   if (!moving) {
     px = a; py = b; n0 = c; n1 = d;
     return;
   }
-  const double co = cos(B.theta), sn = sin(B.theta);
   px = B.x + (co * a - sn * b);
   py = B.y + (sn * a + co * b);
   n0 = co * c - sn * d;
   n1 = sn * c + co * d;
+}
+
+// the same for registered point i
+__device__ __forceinline__ void si_world(const double *__restrict__ pts, int maxp, int i, int moving,
+                                         const BodyDev &B, double co, double sn, double &px, double &py,
+                                         double &n0, double &n1) {
+  si_place(pts[i], pts[maxp + i], pts[2 * maxp + i], pts[3 * maxp + i], moving, B, co, sn, px, py, n0, n1);
+}
+
+// Point threadIdx.x (position, normal, body), loaded ahead by a caller that
+// has other work to overlap with the loads; ok = false when not loaded.
+struct PtPre {
+  double a, b, c, d, body;
+  bool ok;
+};
+
+__device__ __forceinline__ PtPre si_prefetch(const double *__restrict__ pts, int maxp, int npts) {
+  PtPre p{0.0, 0.0, 0.0, 0.0, 0.0, false};
+  const int i = threadIdx.x;
+  if (i < npts) {
+    p.a = pts[i];
+    p.b = pts[maxp + i];
+    p.c = pts[2 * maxp + i];
+    p.d = pts[3 * maxp + i];
+    p.body = pts[5 * maxp + i];
+    p.ok = true;
+  }
+  return p;
 }
 
 // exclusive prefix sum over the SI_NT threads of the block; *total gets the sum
@@ -297,10 +339,112 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *wsum /*[SI_NT/64
   return wsum[wave] + incl - v;
 }
 
+// Bitonic sort of key[0, N), N a power of two <= SI_MAX, by the SI_NT threads
+// of the block; on return key[] holds the sorted keys.  Element e lives in a
+// register of thread e % SI_NT (register e / SI_NT), so the compare-exchange
+// partner e ^ stride is: for stride < 64, a lane of the same wave (a
+// shuffle, no barrier); for stride >= SI_NT, another register of the same
+// thread; in between, another wave (through LDS, two barriers).
+__device__ __forceinline__ void block_bitonic_sort(unsigned long long *key, int N) {
+  constexpr int NJ = SI_MAX / SI_NT;
+  unsigned long long v[NJ];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nj = N > SI_NT ? N / SI_NT : 1;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int e = tid + j * SI_NT;
+    v[j] = (j < nj && e < N) ? key[e] : ~0ull;  // lanes beyond N only meet each other
+  }
+  for (int size = 2; size <= N; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= SI_NT) {
+        // register pairs (j, j ^ js); both indices compile-time after unrolling
+        const int js = stride / SI_NT;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+          for (int jp = j + 1; jp < NJ; ++jp) {
+            if ((j ^ jp) == js && jp < nj) {
+              const bool up = ((tid + j * SI_NT) & size) == 0;
+              const unsigned long long a = v[j], b = v[jp];
+              if ((a > b) == up) {
+                v[j] = b;
+                v[jp] = a;
+              }
+            }
+          }
+        }
+      } else if (stride >= 64) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          if (j < nj) key[tid + j * SI_NT] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int e = tid + j * SI_NT;
+          if (j < nj && e < N) {
+            const unsigned long long p = key[e ^ stride];
+            const bool keep_min = ((e & stride) == 0) == ((e & size) == 0);
+            v[j] = keep_min ? (v[j] < p ? v[j] : p) : (v[j] < p ? p : v[j]);
+          }
+        }
+        __syncthreads();
+      } else {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          // N >= 64 here (N <= RANK_SORT_MAX goes to block_rank_sort), so a
+          // wave holds N's elements entirely or not at all
+          if (j >= nj || (tid & ~63) + j * SI_NT >= N) continue;
+          const unsigned long long p = __shfl_xor(v[j], stride, 64);
+          const int e = tid + j * SI_NT;
+          const bool keep_min = ((lane & stride) == 0) == ((e & size) == 0);
+          v[j] = keep_min ? (v[j] < p ? v[j] : p) : (v[j] < p ? p : v[j]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int e = tid + j * SI_NT;
+    if (j < nj && e < N) key[e] = v[j];
+  }
+  __syncthreads();
+}
+
+// Sort of key[0, N), N <= RANK_SORT_MAX <= SI_NT, by ranks: element t goes to
+// the number of keys below it (ties by index).  One pass of broadcast LDS
+// reads instead of the log^2 N stages of the bitonic network.
+constexpr int RANK_SORT_MAX = 256;
+__device__ __forceinline__ void block_rank_sort(unsigned long long *key, int N) {
+  const int t = threadIdx.x;
+  unsigned long long k = 0;
+  int r = 0;
+  if (t < N) {
+    k = key[t];
+    for (int j = 0; j < N; ++j) {
+      const unsigned long long q = key[j];
+      r += (q < k) | ((q == k) & (j < t));
+    }
+  }
+  __syncthreads();
+  if (t < N) key[r] = k;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void block_sort_keys(unsigned long long *key, int N) {
+  if (N <= RANK_SORT_MAX)
+    block_rank_sort(key, N);
+  else
+    block_bitonic_sort(key, N);
+}
+
 // Sample nodes and per-node weights of all registered points (one workgroup
 // of SI_NT threads; called by k_si_select and, for a moving disk, at the end
-// of k_body_step after the mask was rebuilt).
-__device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
+// of k_body_step after the mask was rebuilt).  solid: the solid test the
+// sample-node search uses (see MaskSolid, DiskSolid).
+template <typename Solid>
+__device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre &pre, uint8_t *__restrict__ mask,
+                                                Ctl *__restrict__ ctl,
                                 const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
                                 int *__restrict__ si_map, BodyTab *__restrict__ bt,
                                 const BodyDev *__restrict__ bodies, int nx, int ny, int pitch) {
@@ -317,6 +461,7 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
   const int rule = ctl->si_rule;
   const int per_pt = rule == 1 ? 4 : 1;  // stencil entries per point
   const BodyDev B = ctl->body;
+  const double co = moving ? cos(B.theta) : 1.0, sn = moving ? sin(B.theta) : 0.0;
   const int nent = npts * per_pt;
   int N = 4;  // >= per_pt, so every key slot below is written
   while (N < nent) N <<= 1;
@@ -330,46 +475,52 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
     bt[threadIdx.x].rec1 = 0;
   }
   __syncthreads();
-  // one key per stencil entry; entry = point * per_pt + k
+  // one key per stencil entry; entry = point * per_pt + k.  The sample
+  // nodes' bounding box is reduced per wave, then merged in LDS.
+  int bx0 = nx, by0 = ny, bx1 = -1, by1 = -1;
   for (int i = threadIdx.x; i < N / per_pt; i += SI_NT) {
     unsigned long long kk[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     if (i < npts) {
       double px, py, n0, n1;
-      si_world(pts, maxp, i, moving, B, px, py, n0, n1);
-      const unsigned long long body = (unsigned long long)pts[5 * maxp + i];
+      unsigned long long body;
+      if (pre.ok && i == (int)threadIdx.x) {
+        si_place(pre.a, pre.b, pre.c, pre.d, moving, B, co, sn, px, py, n0, n1);
+        body = (unsigned long long)pre.body;
+      } else {
+        si_world(pts, maxp, i, moving, B, co, sn, px, py, n0, n1);
+        body = (unsigned long long)pts[5 * maxp + i];
+      }
       int node[4];
       double w[4];
-      const int c = si_stencil(mask, nx, ny, pitch, rule, px, py, n0, n1, node, w);
+      const int c = si_stencil(solid, nx, ny, rule, px, py, n0, n1, node, w);
       if (c == 0) atomicAdd(&missing, 1);
       for (int k = 0; k < c; ++k) {
         kk[k] = (body << BODY_SHIFT) | ((unsigned long long)(unsigned)node[k] << NODE_SHIFT) |
                 (unsigned)(i * per_pt + k);
         const int X = node[k] % nx, Y = node[k] / nx;
-        atomicMin(&bb[0], X);
-        atomicMin(&bb[1], Y);
-        atomicMax(&bb[2], X);
-        atomicMax(&bb[3], Y);
+        bx0 = min(bx0, X);
+        by0 = min(by0, Y);
+        bx1 = max(bx1, X);
+        by1 = max(by1, Y);
       }
     }
     for (int k = 0; k < per_pt; ++k) key[i * per_pt + k] = kk[k];
   }
-  __syncthreads();
-  // bitonic sort of the keys
-  for (int size = 2; size <= N; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = threadIdx.x; t < N / 2; t += SI_NT) {
-        const int lo = 2 * t - (t & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const unsigned long long a = key[lo], b = key[hi];
-        if ((a > b) == up) {
-          key[lo] = b;
-          key[hi] = a;
-        }
-      }
-      __syncthreads();
-    }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    bx0 = min(bx0, __shfl_xor(bx0, off, 64));
+    by0 = min(by0, __shfl_xor(by0, off, 64));
+    bx1 = max(bx1, __shfl_xor(bx1, off, 64));
+    by1 = max(by1, __shfl_xor(by1, off, 64));
   }
+  if ((threadIdx.x & 63) == 0 && bx1 >= 0) {
+    atomicMin(&bb[0], bx0);
+    atomicMin(&bb[1], by0);
+    atomicMax(&bb[2], bx1);
+    atomicMax(&bb[3], by1);
+  }
+  __syncthreads();
+  block_sort_keys(key, N);
   // segment heads (one record per body and node) -> record indices (each
   // thread owns a contiguous chunk)
   const unsigned long long INVALID = ~0ull;
@@ -390,11 +541,16 @@ __device__ void si_select_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
       const int e = (int)(key[k] & ((1u << NODE_SHIFT) - 1));
       const int i = e / per_pt;
       double px, py, n0, n1;
-      si_world(pts, maxp, i, moving, B, px, py, n0, n1);
+      si_world(pts, maxp, i, moving, B, co, sn, px, py, n0, n1);
       int nd[4];
       double w[4];
-      si_stencil(mask, nx, ny, pitch, rule, px, py, n0, n1, nd, w);
-      const double s = pts[4 * maxp + i] * w[e % per_pt];
+      si_stencil(solid, nx, ny, rule, px, py, n0, n1, nd, w);
+      const int ke = e % per_pt;
+      double we = w[0];
+#pragma unroll
+      for (int k = 1; k < 4; ++k)
+        if (k == ke) we = w[k];  // register select (no indexed private array)
+      const double s = pts[4 * maxp + i] * we;
       const double rx = px - Bb.x, ry = py - Bb.y;
       ax += s * n0;
       ay += s * n1;
@@ -445,7 +601,7 @@ __global__ void __launch_bounds__(SI_NT)
     k_si_select(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ pts,
                 int maxp, SiRec *__restrict__ recs, int *__restrict__ si_map, BodyTab *__restrict__ bt,
                 const BodyDev *__restrict__ bodies, int nx, int ny, int pitch) {
-  si_select_block(mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch);
+  si_select_block(MaskSolid{mask, pitch}, PtPre{0.0, 0.0, 0.0, 0.0, 0.0, false}, mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch);
 }
 
 // ----------------------------------------------------------------------------
@@ -455,7 +611,7 @@ __global__ void __launch_bounds__(SI_NT)
 constexpr int BODY_NT = 1024;
 constexpr int REGION_MARGIN = 6;  // covers links (1) and sample walks (5)
 
-__device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
+__device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
                                 const double *__restrict__ me, const double *__restrict__ sig,
                                 double *__restrict__ hist, int cap, int maxb, int nx, int ny, int pitch,
                                 int perx, int pery, const double *__restrict__ pts, int maxp,
@@ -467,24 +623,35 @@ __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
   __shared__ double lds[FIN_WAVES * 6];
   __shared__ int wsum[BODY_NT / 64];
   __shared__ int nslot;
+  __shared__ double flast[6];  // forces of the step just taken (ME, SI)
+  // Loads that do not depend on the finalize, issued first so their latency
+  // overlaps it: the control-block fields of the update (the finalize does
+  // not write them) and this thread's stress-integration point.
+  const BodyDev B0 = ctl->body;
+  const int mode = ctl->mode, source = ctl->source;
+  const double mass = ctl->mass, inertia = ctl->inertia, buoy = ctl->buoy, cgx = ctl->gx, cgy = ctl->gy;
+  const double crad = ctl->r;
+  const int oreg0 = ctl->region[0], oreg1 = ctl->region[1], oreg2 = ctl->region[2], oreg3 = ctl->region[3];
+  const int npts0 = ctl->npts;
+  const PtPre pre = si_prefetch(pts, maxp, npts0);
   // forces of the step just taken, needed by the update below (the only
   // body: a moving disk is alone in its lattice)
-  finalize_block<BODY_NT>(me, sig, recs, bt, ctl, hist, cap, maxb, lds);
+  finalize_block<BODY_NT>(me, sig, recs, bt, ctl, hist, cap, maxb, lds, flast);
   __syncthreads();
   if (threadIdx.x == 0) {
-    BodyDev B = ctl->body;
-    if (ctl->mode == MODE_FREE) {
+    BodyDev B = B0;
+    if (mode == MODE_FREE) {
       // Eqs. dep1/theta2, semi-implicit Euler, dt = 1
-      const double *F = ctl->last + 3 * ctl->source;
-      B.u += F[0] / ctl->mass + ctl->buoy * ctl->gx;
-      B.v += F[1] / ctl->mass + ctl->buoy * ctl->gy;
-      B.omega += F[2] / ctl->inertia;
+      const double *F = flast + 3 * source;
+      B.u += F[0] / mass + buoy * cgx;
+      B.v += F[1] / mass + buoy * cgy;
+      B.omega += F[2] / inertia;
     }
     B.x += B.u;
     B.y += B.v;
     B.theta += B.omega;
     ctl->body = B;
-    const long long X = llround(B.x * FIXQ), Y = llround(B.y * FIXQ), R = llround(ctl->r * FIXQ);
+    const long long X = llround(B.x * FIXQ), Y = llround(B.y * FIXQ), R = llround(crad * FIXQ);
     ctl->fq[0] = X;
     ctl->fq[1] = Y;
     ctl->fq[2] = R;
@@ -496,10 +663,10 @@ __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
     const int by0 = (int)((Y - R) / FIXQ) - 1, by1 = (int)((Y + R) / FIXQ) + 2;
     int nr[4] = {max(bx0 - REGION_MARGIN, 0), max(by0 - REGION_MARGIN, 0),
                  min(bx1 + REGION_MARGIN, nx), min(by1 + REGION_MARGIN, ny)};
-    reg[0] = min(nr[0], ctl->region[0]);
-    reg[1] = min(nr[1], ctl->region[1]);
-    reg[2] = max(nr[2], ctl->region[2]);
-    reg[3] = max(nr[3], ctl->region[3]);
+    reg[0] = min(nr[0], oreg0);
+    reg[1] = min(nr[1], oreg1);
+    reg[2] = max(nr[2], oreg2);
+    reg[3] = max(nr[3], oreg3);
 #pragma unroll
     for (int k = 0; k < 4; ++k) ctl->region[k] = nr[k];
     // force window: interface cells lie within one cell of the disk's box;
@@ -517,7 +684,11 @@ __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
   __syncthreads();
   const int x0 = reg[0], y0 = reg[1], w = reg[2] - reg[0], h = reg[3] - reg[1];
   const long long X = q[0], Y = q[1], R = q[2];
-  for (int t = threadIdx.x; t < w * h; t += BODY_NT) {
+  // this thread's cells are t = threadIdx.x + k BODY_NT; bit k of ifbits
+  // records an interface cell (rounds past 64 read the mask back)
+  unsigned long long ifbits = 0;
+  int cnt = 0;
+  for (int t = threadIdx.x, k = 0; t < w * h; t += BODY_NT, ++k) {
     const int i = x0 + t % w, j = y0 + t / w;
     const bool own = disk_inside(X, Y, R, i, j);
     bool iface = false;
@@ -535,24 +706,23 @@ __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
       if (disk_inside(X, Y, R, I, J) != own) iface = true;
     }
     mask[(long long)j * pitch + i] = (own ? 1 : 0) | (iface ? M_IFACE : 0);
+    if (iface) {
+      ++cnt;
+      if (k < 64) ifbits |= 1ull << k;
+    }
   }
   // the rebuilt mask must be visible to every thread of the block
   __threadfence_block();
   __syncthreads();
   {
-    // interface slots: the region's interface cells in row-major order (all
-    // of the disk's interface cells lie in its region); each thread numbers a
-    // contiguous chunk.  A slot beyond the capacity drops its interface bit
-    // and flags the error (bit 3) instead of writing out of bounds.
-    const int n = w * h, per = (n + BODY_NT - 1) / BODY_NT;
-    const int t0 = threadIdx.x * per, t1 = min(t0 + per, n);
-    int cnt = 0;
-    for (int t = t0; t < t1; ++t)
-      if (mask[(long long)(y0 + t / w) * pitch + x0 + t % w] & M_IFACE) ++cnt;
+    // interface slots, thread by thread and each thread's cells in order (all
+    // of the disk's interface cells lie in its region).  A slot beyond the
+    // capacity drops its interface bit and flags the error (bit 3) instead of
+    // writing out of bounds.
     int slot = block_exclusive_scan(cnt, wsum, &nslot);
-    for (int t = t0; t < t1; ++t) {
+    for (int t = threadIdx.x, k = 0; t < w * h; t += BODY_NT, ++k) {
       const long long c = (long long)(y0 + t / w) * pitch + x0 + t % w;
-      if (!(mask[c] & M_IFACE)) continue;
+      if (!(k < 64 ? (ifbits >> k) & 1 : (mask[c] & M_IFACE))) continue;
       if (slot < maxslot) {
         imap[c] = slot;
       } else {
@@ -567,10 +737,11 @@ __device__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ct
       bt[0].me1 = min(nslot, maxslot);
     }
   }
-  if (ctl->npts > 0) {
+  if (npts0 > 0) {
     __threadfence_block();
     __syncthreads();
-    si_select_block(mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch);
+    // the disk is the lattice's only body: its rule is the mask just built
+    si_select_block(DiskSolid{q[0], q[1], q[2]}, pre, mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch);
   }
 }
 
@@ -612,7 +783,7 @@ __global__ void __launch_bounds__(SI_NT)
     const double s = pts[4 * maxp + i];
     int nodes[4];
     double wts[4];
-    const int cnt = si_stencil(mask, P.nx, P.ny, P.pitch, rule, px, py, n0, n1, nodes, wts);
+    const int cnt = si_stencil(MaskSolid{mask, P.pitch}, P.nx, P.ny, rule, px, py, n0, n1, nodes, wts);
     if (cnt == 0) {
       v[5] += 1.0;  // counts points without a sample node
       continue;

@@ -220,18 +220,20 @@ constexpr int FIN_WAVES = FIN_W / 64;
 // interface cells stored in their slots.  SI: the stress each sample node
 // stored (sig), contracted with the node's aggregated weights, record by
 // record.  hist[(n mod cap) * maxb + b][6]; the control block keeps body 1's.
-// lds holds FIN_WAVES * 6 doubles.
+// lds holds FIN_WAVES * 6 doubles; out0, when given (LDS, 6 doubles), gets
+// body 1's forces from thread 0.
 template <int NT>
 __device__ __forceinline__ void finalize_block(const double *__restrict__ me, const double *__restrict__ sig,
                                                const SiRec *__restrict__ recs, const BodyTab *__restrict__ bt,
                                                Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb,
-                                               double *lds) {
+                                               double *lds, double *out0 = nullptr) {
   static_assert(NT % 64 == 0, "whole waves");
   const long long n = ctl->step + 1;
   const int nb = ctl->nbody;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const BodyTab T0 = bt[0];  // issued with the control-block loads
   for (int b = 0; b < nb; ++b) {
-    const BodyTab T = bt[b];
+    const BodyTab T = b == 0 ? T0 : bt[b];
     for (int k = wave; k < FIN_WAVES; k += NT / 64) {
       const int v0 = k * 64 + lane;  // this thread's virtual lane
       double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -262,7 +264,10 @@ __device__ __forceinline__ void finalize_block(const double *__restrict__ me, co
         double x = 0.0;
         for (int k = 0; k < FIN_WAVES; ++k) x += lds[k * 6 + i];
         h[i] = x;
-        if (b == 0) ctl->last[i] = x;
+        if (b == 0) {
+          ctl->last[i] = x;
+          if (out0) out0[i] = x;
+        }
       }
     }
     __syncthreads();  // lds is reused by the next body
