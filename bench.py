@@ -148,6 +148,78 @@ def run_sweep(args, torch, W, V, paper=False):
     return out
 
 
+def run_sed_paper(args, torch, W, V):
+    """The paper's sedimentation runs at full scale: one free disk (D = 26,
+    tau = 0.6, eta = 1e-6) per printed density ratio and per force source
+    driving it (SI and ME, the paper's comparison), stepped together by one
+    batched step launch and one batched body launch per step.
+    --sed-seconds > 0 also runs the cases to that physical time and reports
+    each disk's trajectory every 0.1 s."""
+    cases = W.paper_sedimentation_sweep(force_source=1) + W.paper_sedimentation_sweep(force_source=0)
+    lats = [V.Lattice.from_case(c, precision=args.precision) for c in cases]
+    cells = sum(c.nx * c.ny for c in cases)
+    batch = V.Batch(lats)
+    n = len(lats)
+    batch.step([args.warmup] * n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    batch.step([args.steps] * n)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    _, dt, g = W.paper_sedimentation_units()
+    nu = (0.6 - 0.5) / 3.0
+
+    def state(c, lat):
+        x, y, th, u, v, om = lat.body_state()
+        return {"t_s": round(lat.step_count * dt, 4), "x_over_D": round((x + 0.5) / c.length_scale, 4),
+                "fall_over_D": round((c.disk[1] - y) / c.length_scale, 4),
+                "Re": round(math.hypot(u, v) * c.length_scale / nu, 4), "omega": om}
+
+    traj = [[] for _ in cases]
+    if args.sed_seconds > 0:
+        # the rest of the run to the given physical time, sampled every 0.1 s
+        total = int(round(args.sed_seconds / dt))
+        every = int(round(0.1 / dt))
+        while lats[0].step_count < total:
+            k = min(every - lats[0].step_count % every, total - lats[0].step_count)
+            batch.step([k] * n)
+            torch.cuda.synchronize()
+            if lats[0].step_count % every == 0:
+                for t, c, lat in zip(traj, cases, lats):
+                    t.append(state(c, lat))
+                print(f"[sediment-paper] {lats[0].step_count} steps", file=sys.stderr, flush=True)
+    bodies = []
+    for c, lat, t in zip(cases, lats, traj):
+        b = {"rho_r": c.rho_s, "source": "SI" if c.force_source == 1 else "ME", "steps": lat.step_count,
+             **state(c, lat)}
+        if t:
+            b["trajectory"] = t
+        bodies.append(b)
+    bpc = BYTES_PER_CELL[args.precision]
+    achieved = bpc * cells / (ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(cells / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16dev": "f32 (f16 storage)", "f64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "sediment_paper_d26_104x1040_3ratios_SI_and_ME", "cases": n, "cells": cells,
+                   "rho_r": list(W.PAPER_SED_RATIOS), "tau": 0.6, "eta": 1e-6, "g_lattice": g,
+                   "si_points": len(cases[0].si_ds), "force_source": ["SI", "ME"], "storage": args.precision,
+                   "parallelism": "single GPU, one batched step and one batched body launch per step"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_step_batch",
+                     "kernel_us": round(ms * 1e3, 3), "bytes_per_cell": bpc, "cells_per_launch": cells},
+        "bodies": bodies,
+    }
+    batch.close()
+    for lat in lats:
+        lat.close()
+    return out
+
+
 def run_serve(args, W):
     """Continuous batching of a Poisson request mix under an HBM budget, and
     the same trace served one request at a time."""
@@ -188,8 +260,10 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=10.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serve: HBM budget for resident lattices")
+    ap.add_argument("--sed-seconds", type=float, default=0.0,
+                    help="sediment-paper: also run to this physical time and report each disk's Reynolds number")
     ap.add_argument("--workload", default="naca",
-                    choices=["naca", "sediment", "roofline", "disk", "sweep", "paper", "serve"],
+                    choices=["naca", "sediment", "roofline", "disk", "sweep", "paper", "sediment-paper", "serve"],
                     help="naca: NACA 0012 2000x1000 (default); sediment: free disk 400x2000; "
                          "roofline: NACA 0012 chord 819 on 8192x8192; disk: 128x64 disk channel; "
                          "sweep: 64 airfoils (chords 100/150/200, AoA 0-20 deg) in one batched launch; "
@@ -214,6 +288,9 @@ def main():
 
     if args.workload in ("sweep", "paper"):
         print(json.dumps(run_sweep(args, torch, W, V, paper=args.workload == "paper")), flush=True)
+        return
+    if args.workload == "sediment-paper":
+        print(json.dumps(run_sed_paper(args, torch, W, V)), flush=True)
         return
     if args.workload == "serve":
         print(json.dumps(run_serve(args, W)), flush=True)

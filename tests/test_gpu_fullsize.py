@@ -92,6 +92,32 @@ def test_sedimentation_full_size_fp32():
     assert err_u <= 1e-5
 
 
+def test_sedimentation_paper_scale_fp32():
+    # the paper's sedimentation scale: D = 26, tau = 0.6, eta = 1e-6, SI as
+    # the force source, density ratio 1.03, 104 x 1040
+    from paper_2110_00967_amd import vplbm as V
+    case = W.case_sedimentation_paper(rho_r=1.03, steps=300)
+    say("sedimentation paper scale 104x1040 D=26 SI-driven fp32 vs oracle, 300 steps")
+    g = V.Lattice.from_case(case, precision="f32")
+    o = O.RefLattice.from_case(case)
+    g.step(300, macro=True)
+    o.step(300)
+    bg, bo = g.body_state(), o.body_state()
+    say(f"body gpu {bg}, oracle {bo}")
+    assert abs(bg[4] - bo[4]) <= 5e-3 * abs(bo[4])
+    assert abs(bg[1] - bo[1]) <= 5e-3 * abs(bo[1] - case.disk[1]) + 1e-9
+    assert np.array_equal(g.mask() & 1, o.solid)
+    for which, ref in ((V.FORCE_ME, o.me()), (V.FORCE_SI, o.si())):
+        h = g.history(which)
+        e = np.abs(h[:, :2] - ref[:, :2]).max() / np.abs(ref[:, :2]).max()
+        say(f"paper sedimentation force {which} max rel err {e:.2e}")
+        assert e <= 2e-3
+    r, u, v = g.macro()
+    err_u = rel_l2(np.stack([u, v]), np.stack([o.ux, o.uy]))
+    say(f"paper sedimentation u relL2 {err_u:.2e}")
+    assert err_u <= 1e-4
+
+
 def test_largest_lattice_sampled_fp32():
     from paper_2110_00967_amd import vplbm as V
     nx, ny = 16384, 14563
