@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=10.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serve: HBM budget for resident lattices")
+    ap.add_argument("--streaming", default="ab", choices=["ab", "aa"],
+                    help="population storage of single-lattice workloads: two buffers or one (AA pattern)")
     ap.add_argument("--sed-seconds", type=float, default=0.0,
                     help="sediment-paper: also run to this physical time and report each disk's Reynolds number")
     ap.add_argument("--workload", default="naca",
@@ -305,7 +307,8 @@ def main():
     else:
         case = W.case_disk_channel()
     cells = case.nx * case.ny
-    lat = V.Lattice.from_case(case, precision=args.precision)
+    aa = args.streaming == "aa"
+    lat = V.Lattice.from_case(case, precision=args.precision, streaming=V.STREAM_AA if aa else V.STREAM_AB)
     if args.tile:
         bx, by = (int(v) for v in args.tile.split("x"))
         lat.set_tile(bx, by)
@@ -335,7 +338,7 @@ def main():
     k_us = ms_per_step * 1e3 if case.rho_s is None else k_pairs_us
     bpc = BYTES_PER_CELL[args.precision]
     achieved = bpc * cells / (k_us * 1e-6) / 1e9
-    traffic_bytes = measured_traffic() if (args.workload, args.precision) == ("naca", "f32") else None
+    traffic_bytes = measured_traffic() if (args.workload, args.precision, aa) == ("naca", "f32", False) else None
     traffic = None if traffic_bytes is None else round(traffic_bytes / (k_us * 1e-6) / 1e9, 1)
     me, si = lat.forces_me(), lat.forces_si()
     q = 0.5 * case.u_ref ** 2 * case.length_scale
@@ -356,7 +359,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{case.name}_{case.nx}x{case.ny}", "nx": case.nx, "ny": case.ny,
                    "storage": args.precision, "si_points": len(case.si_ds), "tau": round(case.tau, 4),
-                   "eta": case.eta, "parallelism": "single GPU"},
+                   "eta": case.eta, "streaming": "AA (one buffer)" if aa else "AB (two buffers)",
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_bytes_per_launch": traffic_bytes, "algorithmic_bytes_per_launch": bpc * cells,

@@ -104,7 +104,20 @@ typedef struct {
                         VPLBM_EINVAL when the geometry has more, and a
                         moving disk needs at least (ceil(2r) + 20)^2, the
                         square it renumbers every step */
+  int streaming;     /* population storage (not a choice the paper makes):
+                        VPLBM_STREAM_AB (0) = two buffers, one read and one
+                        written per step; VPLBM_STREAM_AA (1) = one buffer
+                        updated in place, odd and even steps alternating
+                        (half the population memory, the same bytes moved
+                        per cell update, the same arithmetic per cell: the
+                        results agree with VPLBM_STREAM_AB to rounding).
+                        AA runs with the 64x4 tile only and not in a batch */
 } vplbm_params;
+
+enum {
+  VPLBM_STREAM_AB = 0,
+  VPLBM_STREAM_AA = 1
+};
 
 /* Rigid-body state in lattice units: reference point (centre of a disk,
  * the given torque reference of a polygon), angle, translational and
@@ -220,7 +233,8 @@ long long vplbm_step_count(const vplbm_lattice *lat);
 /* Workgroup tile of the step kernel, bx cells along x times by rows:
  * 64x1, 64x2, 64x4 (default), 128x1, 128x2 or 256x1.  Results do not depend
  * on it, forces included: they are summed per interface cell and per sample
- * record, in an order fixed at geometry set-up. */
+ * record, in an order fixed at geometry set-up.  A lattice with
+ * VPLBM_STREAM_AA accepts 64x4 only (VPLBM_EINVAL otherwise). */
 int vplbm_set_tile(vplbm_lattice *lat, int bx, int by);
 
 /* Forces of the last step, out = (Fx, Fy, Tz) on the body, torque about the
@@ -251,7 +265,8 @@ int vplbm_read_macro(vplbm_lattice *lat, double *rho, double *ux, double *uy);
  * (host arrays [h][w]); VPLBM_EINVAL if it leaves the lattice. */
 int vplbm_read_macro_window(vplbm_lattice *lat, int x0, int y0, int w, int h, double *rho, double *ux,
                             double *uy);
-/* Post-collision populations f_a = w_a rho0 + d_a as host doubles [9][ny][nx]. */
+/* Post-collision populations f_a = w_a rho0 + d_a of the last step (or of the
+ * initialization) as host doubles [9][ny][nx], in either storage mode. */
 int vplbm_read_populations(vplbm_lattice *lat, double *f);
 /* The same for a window, host array [9][h][w]. */
 int vplbm_read_populations_window(vplbm_lattice *lat, int x0, int y0, int w, int h, double *f);
@@ -271,7 +286,8 @@ int vplbm_read_mask(vplbm_lattice *lat, uint8_t *out);
 typedef struct vplbm_batch vplbm_batch;
 
 /* All lattices must share the precision, the collision (BGK or TRT), the
- * HIP stream and the default 64x4 tile; a lattice appears once.  The handles stay owned by the caller
+ * HIP stream and the default 64x4 tile, and use VPLBM_STREAM_AB storage
+ * (VPLBM_EINVAL otherwise); a lattice appears once.  The handles stay owned by the caller
  * and must outlive the batch; they must not be stepped concurrently. */
 int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out);
 int vplbm_batch_destroy(vplbm_batch *b);

@@ -48,6 +48,17 @@ enum { EDGE_PERIODIC = 0, EDGE_VELOCITY = 1, EDGE_FREESLIP = 2, EDGE_OUTFLOW = 3
 // population at each edge cell, [edge][slot][cell along the edge] with the
 // west and east blocks ny long and the south and north blocks nx long.  The
 // slot of a population is its velocity component along the edge (0, +1, -1).
+// Index of a perimeter cell (x == 0, x == nx - 1, y == 0 or y == ny - 1):
+// the west column, the east column, then the south and the north row
+// without their corners; 2 ny + 2 (nx - 2) cells in all.
+__host__ __device__ inline int perim_index(int x, int y, int nx, int ny) {
+  if (x == 0) return y;
+  if (x == nx - 1) return ny + y;
+  if (y == 0) return 2 * ny + (x - 1);
+  return 2 * ny + (nx - 2) + (x - 1);
+}
+__host__ __device__ inline int perim_count(int nx, int ny) { return 2 * ny + 2 * (nx - 2); }
+
 __host__ __device__ constexpr int cbc_slot(int along) { return along == 0 ? 0 : (along > 0 ? 1 : 2); }
 __host__ __device__ inline long long cbc_offset(int edge, int nx, int ny) {
   return edge < 2 ? (long long)edge * 3 * ny : 6LL * ny + (long long)(edge - 2) * 3 * nx;

@@ -10,13 +10,54 @@
 namespace vp {
 
 // ----------------------------------------------------------------------------
-// initialization: d_a = f^eq_a(rho, u) - w_a rho0 (second-order equilibrium)
+// Post-collision deviation a of cell (x, y) in the layout `lay` the
+// population buffer holds: 0, two buffers (slot a of the cell); 1, AA after
+// an even launch or the initialization (slot opp(a) of the cell); 2, AA after
+// an odd launch (slot a of x + c_a, or the perimeter copy ec when that
+// leaves the lattice).  For readers that run between steps.
+// ----------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ typename Store<S>::T load_post(const S *F, const S *ec, int lay, int nx, int ny,
+                                                          int pitch, long long plane, int nper, int x, int y,
+                                                          int a) {
+  if (lay == 0) return Store<S>::ld(F + a * plane + (long long)y * pitch + x);
+  if (lay == 1) return Store<S>::ld(F + opp(a) * plane + (long long)y * pitch + x);
+  const int tx = x + cx(a), ty = y + cy(a);
+  if (tx >= 0 && tx < nx && ty >= 0 && ty < ny) return Store<S>::ld(F + a * plane + (long long)ty * pitch + tx);
+  return Store<S>::ld(ec + (long long)a * nper + perim_index(x, y, nx, ny));
+}
+
+// The 9 deviations streaming into (x, y) from a post-collision state in any
+// layout, with the edge rules and the convective blend (state not updated)
+template <typename S, typename T>
+__device__ __forceinline__ void pull_post(const S *F, const S *ec, int lay, const StepArgs<T> &P, int x, int y,
+                                          T (&d)[Q]) {
+  unsigned conv = 0;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    int pop, sx, sy;
+    T add;
+    bool cv;
+    edge_source(P, x, y, a, pop, sx, sy, add, cv);
+    d[a] = load_post(F, ec, lay, P.nx, P.ny, P.pitch, P.plane, P.nper, sx, sy, pop) + add;
+    conv |= cv ? 1u << a : 0u;
+  }
+#pragma unroll
+  for (int a = 1; a < Q; ++a)
+    if (conv >> a & 1u) d[a] = (*cbc_slot_ptr(P, x, y, a) + cbc_speed(P, x, a, false) * d[a]) * cbc_speed(P, x, a, true);
+}
+
+// ----------------------------------------------------------------------------
+// initialization: d_a = f^eq_a(rho, u) - w_a rho0 (second-order equilibrium),
+// stored in slot a (two buffers) or, for the AA pattern (swapped), in slot
+// opp(a) with the perimeter copy in ec
 // ----------------------------------------------------------------------------
 template <typename S>
 __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
                        long long plane, int row0, int nrows, const double *__restrict__ rho_in,
                        const double *__restrict__ ux_in, const double *__restrict__ uy_in,
-                       double rho_u, double ux_u, double uy_u, const Ctl *__restrict__ ctl, double rho0) {
+                       double rho_u, double ux_u, double uy_u, const Ctl *__restrict__ ctl, double rho0,
+                       int swapped, S *__restrict__ ec, int nper) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int yl = blockIdx.y;
   if (x >= nx || yl >= nrows) return;
@@ -43,7 +84,9 @@ __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int 
   for (int a = 0; a < Q; ++a) {
     const double cu = cx(a) * ux + cy(a) * uy;
     const double d = wgt(a) * (rho - rho0) + wgt(a) * rho * (3.0 * cu + 4.5 * cu * cu - uu);
-    Store<S>::st(f + a * plane + c, (typename Store<S>::T)d);
+    Store<S>::st(f + (swapped ? opp(a) : a) * plane + c, (typename Store<S>::T)d);
+    if (swapped && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1))
+      Store<S>::st(ec + (long long)a * nper + perim_index(x, y, nx, ny), (typename Store<S>::T)d);
   }
 }
 
@@ -56,7 +99,7 @@ __global__ void k_scatter_slots(const int *__restrict__ pairs, int n, int *__res
 // convective-edge state <- the current populations entering through each
 // convective edge (one thread per cell along an edge, all 4 edges)
 template <typename S>
-__global__ void k_cbc_init(const S *__restrict__ f, const StepArgs<typename Store<S>::T> P) {
+__global__ void k_cbc_init(const S *__restrict__ f, const StepArgs<typename Store<S>::T> P, int swapped) {
   using T = typename Store<S>::T;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, e = blockIdx.y;
   if (P.kind[e] != EDGE_CONVECTIVE) return;
@@ -70,22 +113,24 @@ __global__ void k_cbc_init(const S *__restrict__ f, const StepArgs<typename Stor
     const int cn = e < 2 ? cx(a) : cy(a), ca = e < 2 ? cy(a) : cx(a);
     if (cn != in) continue;
     P.cbc[cbc_offset(e, P.nx, P.ny) + (long long)cbc_slot(ca) * len + i] =
-        T(Store<S>::ld(f + (long long)a * P.plane + (long long)y * P.pitch + x));
+        T(Store<S>::ld(f + (long long)(swapped ? opp(a) : a) * P.plane + (long long)y * P.pitch + x));
   }
 }
 
-// populations f_a = w_a rho0 + d_a of the window columns [x0, x0 + w), rows
-// [row0, row0 + nrows) -> out[9][nrows][w]
+// post-collision populations f_a = w_a rho0 + d_a of the window columns
+// [x0, x0 + w), rows [row0, row0 + nrows) -> out[9][nrows][w] (layouts as in
+// load_post)
 template <typename S>
-__global__ void k_read_pop(const S *__restrict__ f, int x0, int w, int pitch, long long plane, int row0,
-                           int nrows, double rho0, double *__restrict__ out) {
+__global__ void k_read_pop(const S *__restrict__ f, const S *__restrict__ ec, int lay, int nx, int ny, int nper,
+                           int x0, int w, int pitch, long long plane, int row0, int nrows, double rho0,
+                           double *__restrict__ out) {
   const int xl = blockIdx.x * blockDim.x + threadIdx.x;
   const int yl = blockIdx.y;
   if (xl >= w || yl >= nrows) return;
-  const long long c = (long long)(row0 + yl) * pitch + x0 + xl;
 #pragma unroll
   for (int a = 0; a < Q; ++a)
-    out[((long long)a * nrows + yl) * w + xl] = wgt(a) * rho0 + double(Store<S>::ld(f + a * plane + c));
+    out[((long long)a * nrows + yl) * w + xl] =
+        wgt(a) * rho0 + double(load_post(f, ec, lay, nx, ny, pitch, plane, nper, x0 + xl, row0 + yl, a));
 }
 
 template <typename T>
@@ -771,7 +816,7 @@ __global__ void __launch_bounds__(BODY_NT)
 // ----------------------------------------------------------------------------
 template <typename S>
 __global__ void __launch_bounds__(SI_NT)
-    k_si_at(const S *__restrict__ fin, const uint8_t *__restrict__ mask,
+    k_si_at(const S *__restrict__ fin, const S *__restrict__ ec, int lay, const uint8_t *__restrict__ mask,
             const StepArgs<typename Store<S>::T> P, const Ctl *__restrict__ ctl,
             const double *__restrict__ pts, int maxp, int npts, double *__restrict__ out) {
   using T = typename Store<S>::T;
@@ -794,7 +839,10 @@ __global__ void __launch_bounds__(SI_NT)
       double d[Q];
       {
         T dt[Q];
-        pull_edge_all<S, T, false>(fin, P, x, y, dt);
+        if (lay == 0)
+          pull_edge_all<S, T, false>(fin, P, x, y, dt);
+        else
+          pull_post<S, T>(fin, ec, lay, P, x, y, dt);
 #pragma unroll
         for (int a = 0; a < Q; ++a) d[a] = double(dt[a]);
       }

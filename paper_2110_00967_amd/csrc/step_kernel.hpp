@@ -49,6 +49,12 @@ template <typename T> struct StepArgs {
   T *cbc;               // convective-edge state (see cbc_offset)
   T cbu[4];             // convection speed U of each convective edge
   T cbi[4];             // 1 / (1 + U)
+  // AA pattern: the perimeter cells' post-collision populations kept by the
+  // previous launch (read) and by this one (written), [9][nper] of the
+  // storage type (see aa_pull_edge)
+  const void *ec_in;
+  void *ec_out;
+  int nper;
 };
 
 // Source of deviation a arriving at (x, y) (any cell, edge or not): axis by
@@ -181,6 +187,73 @@ __device__ __forceinline__ void pull_edge_all(const S *__restrict__ fin, const S
   }
 }
 
+// AA pattern (one population buffer F, updated in place; Bailey et al.'s
+// alternating scheme).  The odd launch of a pair pulls d~_a from slot
+// opp(a) of x - c_a, where the even launch left it, and pushes its result to
+// slot a of x + c_a; the even launch reads slot a of x and writes slot
+// opp(a) of x.  Every slot is read and written by one thread only, which
+// reads all of its slots before it writes any.  A source outside the lattice
+// goes through the edge rules above; their sources are perimeter cells, so
+// every launch also keeps the post-collision populations of its perimeter
+// cells (ec_out) and the next launch reads the edge sources there (ec_in):
+// the same stored values the two-buffer path reads from its source buffer.
+template <typename S, typename T, int AA>
+__device__ __forceinline__ void aa_pull_edge(const S *F, const StepArgs<T> &P, int x, int y, T (&d)[Q]) {
+  const S *ec = (const S *)P.ec_in;
+  unsigned conv = 0;
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int rx = x - cx(a), ry = y - cy(a);
+    const bool in = rx >= 0 && rx < P.nx && ry >= 0 && ry < P.ny;
+    int pop, sx, sy;
+    T add;
+    bool cv;
+    edge_source(P, x, y, a, pop, sx, sy, add, cv);
+    const int k = in ? (AA == 1 ? opp(a) * (int)P.plane + ry * P.pitch + rx : a * (int)P.plane + y * P.pitch + x)
+                     : pop * P.nper + perim_index(sx, sy, P.nx, P.ny);
+    d[a] = Store<S>::ld((in ? F : ec) + k) + (in ? T(0) : add);
+    conv |= (!in && cv) ? 1u << a : 0u;
+  }
+  if (conv) {  // only convective edge cells (as in pull_edge_all)
+    T st[Q];
+#pragma unroll
+    for (int a = 1; a < Q; ++a)
+      if (conv >> a & 1u) st[a] = *cbc_slot_ptr(P, x, y, a);
+#pragma unroll
+    for (int a = 1; a < Q; ++a)
+      if (conv >> a & 1u) {
+        d[a] = (st[a] + cbc_speed(P, x, a, false) * d[a]) * cbc_speed(P, x, a, true);
+        *cbc_slot_ptr(P, x, y, a) = d[a];
+      }
+  }
+}
+
+// Store the post-collision deviation v of population a of cell (x, y) at
+// byte offset cb of its plane: two-buffer (AA = 0) in place; even AA launch
+// (AA = 2) into slot opp(a) of the cell; odd AA launch (AA = 1) into slot a
+// of x + c_a, dropped when that leaves the lattice (its consumers read the
+// perimeter copy).  A perimeter cell (eidx >= 0) of an AA launch also keeps
+// v in ec_out.  interior: the workgroup-uniform fast-path flag.
+template <typename S, int AA, typename T>
+__device__ __forceinline__ void put_pop(S *F, const StepArgs<T> &P, uint32_t cb, bool interior, int x, int y,
+                                        int a, T v, int eidx) {
+  if constexpr (AA == 0) {
+    Store<S>::st_at(F + (long long)a * P.plane, cb, v);
+  } else if constexpr (AA == 2) {
+    Store<S>::st_at(F + (long long)opp(a) * P.plane, cb, v);
+  } else {
+    if (interior) {
+      Store<S>::st_at(F + (long long)a * P.plane + (long long)cy(a) * P.pitch + cx(a), cb, v);
+    } else {
+      const int tx = x + cx(a), ty = y + cy(a);
+      if (tx >= 0 && tx < P.nx && ty >= 0 && ty < P.ny) Store<S>::st(F + (a * (int)P.plane + ty * P.pitch + tx), v);
+    }
+  }
+  if constexpr (AA != 0) {
+    if (!interior && eidx >= 0) Store<S>::st((S *)P.ec_out + (a * P.nper + eidx), v);
+  }
+}
+
 template <int NT, int N>
 __device__ __forceinline__ void block_reduce(double (&v)[N], double *lds /*[NT/64][N]*/) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -307,7 +380,7 @@ __device__ __forceinline__ void nbr_masks(const uint8_t *__restrict__ mask, cons
 // One workgroup's tile of the step (tile < P.ntiles): the body of the step
 // kernel, shared by the single-lattice and the batched launch.  The
 // workgroup of tile 0 also finalizes the previous step's forces (fin_prev).
-template <typename S, int BX, int BY, bool MACRO, bool TRT>
+template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA>
 __device__ __forceinline__ void step_tile(
     int tile, const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
     const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl, const SiRec *__restrict__ recs,
@@ -339,13 +412,28 @@ __device__ __forceinline__ void step_tile(
     const uint32_t cb = (uint32_t)c * (uint32_t)sizeof(S);
     const uint8_t m = mask[(uint32_t)c];
     T d[Q];
+    // AA launches read through fout, the pointer they write through: the
+    // thread's own stores overwrite the slots it read (a read-only view of
+    // the buffer would let the compiler re-load a value after such a store)
+    const S *src = AA == 0 ? fin : (const S *)fout;
     if (tile_interior) {
 #pragma unroll
-      for (int a = 0; a < Q; ++a)
-        d[a] = Store<S>::ld(at(fin + (long long)a * P.plane - (long long)cy(a) * P.pitch - cx(a), cb));
+      for (int a = 0; a < Q; ++a) {
+        if constexpr (AA == 0)
+          d[a] = Store<S>::ld(at(src + (long long)a * P.plane - (long long)cy(a) * P.pitch - cx(a), cb));
+        else if constexpr (AA == 1)
+          d[a] = Store<S>::ld(at(src + (long long)opp(a) * P.plane - (long long)cy(a) * P.pitch - cx(a), cb));
+        else
+          d[a] = Store<S>::ld(at(src + (long long)a * P.plane, cb));
+      }
+    } else if constexpr (AA == 0) {
+      pull_edge_all<S, T, true>(src, P, x, y, d);
     } else {
-      pull_edge_all<S, T, true>(fin, P, x, y, d);
+      aa_pull_edge<S, T, AA>(src, P, x, y, d);
     }
+    const int eidx = (AA != 0 && !tile_interior && (x == 0 || x == P.nx - 1 || y == 0 || y == P.ny - 1))
+                         ? perim_index(x, y, P.nx, P.ny)
+                         : -1;
 
     // moments (of the deviations: sum w = 1, sum w c = 0)
     const T drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
@@ -391,7 +479,7 @@ __device__ __forceinline__ void step_tile(
       // keeps the FP32 rounding of mass and momentum unbiased.
       const T C1 = drho - rho * uu15 - P.fo * uF3;
       const T R45 = T(4.5) * rho, R3 = T(3) * rho;
-      Store<S>::st_at(fout, cb, d[0] - P.omega * (d[0] - T(wgt(0)) * C1));
+      put_pop<S, AA>(fout, P, cb, tile_interior, x, y, 0, d[0] - P.omega * (d[0] - T(wgt(0)) * C1), eidx);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int a = k < 2 ? k + 1 : k + 3;  // 1, 2, 5, 6; a' = 3, 4, 7, 8
@@ -411,8 +499,8 @@ __device__ __forceinline__ void step_tile(
           oa = d[a] - P.omega * se - P.omega_m * so;
           oo = d[o] - P.omega * se + P.omega_m * so;
         }
-        Store<S>::st_at(fout + (long long)a * P.plane, cb, oa);
-        Store<S>::st_at(fout + (long long)o * P.plane, cb, oo);
+        put_pop<S, AA>(fout, P, cb, tile_interior, x, y, a, oa, eidx);
+        put_pop<S, AA>(fout, P, cb, tile_interior, x, y, o, oo, eidx);
       }
     }
     if (MACRO) {
@@ -510,7 +598,7 @@ __device__ __forceinline__ void step_tile(
 // FP64 needs more VGPRs and is left to the compiler.
 template <typename S> constexpr int step_waves() { return sizeof(typename Store<S>::T) == 8 ? 1 : 8; }
 
-template <typename S, int BX, int BY, bool MACRO, bool TRT>
+template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA>
 __global__ void __launch_bounds__(BX *BY, step_waves<S>())
     k_step(const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
            const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl,
@@ -531,7 +619,7 @@ __global__ void __launch_bounds__(BX *BY, step_waves<S>())
   int t = i + P.rot[xcd];
   t -= t >= len ? len : 0;
   const int tile = start + t;
-  step_tile<S, BX, BY, MACRO, TRT>(tile, fin, fout, mask, P, ctl, recs, si_map, imap, bt, me_out, me_prev, sig_out,
+  step_tile<S, BX, BY, MACRO, TRT, AA>(tile, fin, fout, mask, P, ctl, recs, si_map, imap, bt, me_out, me_prev, sig_out,
                                    sig_prev, fin_prev, hist, cap, maxb, mrho, mux, muy);
 }
 
@@ -577,7 +665,7 @@ __global__ void __launch_bounds__(BX *BY, step_waves<S>())
   const int fin_prev = C->moving ? 0 : (first ? C->pending0 : 1);
   const S *fin = (const S *)C->buf[par];
   S *fout = (S *)C->buf[par ^ 1];
-  step_tile<S, BX, BY, false, TRT>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map, C->imap,
+  step_tile<S, BX, BY, false, TRT, 0>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map, C->imap,
                                    C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1], fin_prev, C->hist,
                                    C->cap, C->maxb, nullptr, nullptr, nullptr);
 }

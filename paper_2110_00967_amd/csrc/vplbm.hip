@@ -59,7 +59,7 @@ int pitch_of(const vplbm_params &p) {
 }
 
 struct Layout {
-  size_t A, B, mask, mrho, mux, muy, si_map, imap, me, me_stride, sig, sig_stride, cbc, hist, ctl, bt, bodies,
+  size_t A, B, ec, ec_stride, mask, mrho, mux, muy, si_map, imap, me, me_stride, sig, sig_stride, cbc, hist, ctl, bt, bodies,
       recs, pts, verts, staging, siout, total;
 };
 
@@ -87,7 +87,12 @@ Layout layout_of(const vplbm_params &p) {
     return at;
   };
   L.A = take(9 * cells * elem_size(p.precision));
-  L.B = take(9 * cells * elem_size(p.precision));
+  // the AA pattern keeps one population buffer, plus its perimeter cells'
+  // post-collision populations from the last two launches
+  const bool aa = p.streaming == VPLBM_STREAM_AA;
+  L.B = aa ? L.A : take(9 * cells * elem_size(p.precision));
+  L.ec_stride = aa ? align_up((size_t)9 * perim_count(p.nx, p.ny) * elem_size(p.precision), ALIGN) : 0;
+  L.ec = take(2 * L.ec_stride);
   L.mask = take(cells);
   L.mrho = take(cells * compute_size(p.precision));
   L.mux = take(cells * compute_size(p.precision));
@@ -141,6 +146,8 @@ const char *check_params(const vplbm_params *p) {
       p->max_interface_cells < 0)
     return "capacities must be >= 0";
   if (p->max_bodies > MAX_BODIES) return "max_bodies exceeds 63";
+  if (p->streaming != VPLBM_STREAM_AB && p->streaming != VPLBM_STREAM_AA)
+    return "streaming must be VPLBM_STREAM_AB or VPLBM_STREAM_AA";
   if (p->max_si_points > SI_MAX) return "max_si_points exceeds 4096";
   if (p->si_rule != 0 && p->si_rule != 1) return "si_rule must be 0 or 1";
   if (p->si_rule == 1 && (p->max_si_points == 0 || p->max_si_points > SI_MAX / 4))
@@ -186,6 +193,12 @@ struct vplbm_lattice {
   std::string err;
 
   char *at(size_t off) const { return base + off; }
+  bool aa() const { return p.streaming == VPLBM_STREAM_AA; }
+  // AA: perimeter copy written by the launch of step n (the initialization
+  // counts as step 0)
+  void *ec(long long n) const { return at(L.ec + (size_t)(n & 1) * L.ec_stride); }
+  // layout of the post-collision state between steps (see load_post)
+  int layout() const { return aa() ? ((nstep & 1) ? 2 : 1) : 0; }
   void *A() const { return at(cur == 0 ? L.A : L.B); }
   void *Bbuf() const { return at(cur == 0 ? L.B : L.A); }
   uint8_t *mask() const { return (uint8_t *)at(L.mask); }
@@ -282,6 +295,9 @@ struct vplbm_lattice {
     a.gy = T(gy);
     a.cbc = (T *)at(L.cbc);
     a.bodies = bodies();
+    a.nper = perim_count(p.nx, p.ny);
+    a.ec_in = ec(nstep);
+    a.ec_out = ec(nstep + 1);
     for (int e = 0; e < 4; ++e) {
       const double U = E[e]->kind == VPLBM_BC_CONVECTIVE ? E[e]->ux : 0.0;
       a.cbu[e] = T(U);
@@ -312,12 +328,13 @@ int resolve_pwin(vplbm_lattice *L) {
   return VPLBM_OK;
 }
 
-template <typename S, int BX, int BY>
+template <typename S, int BX, int BY, int AA>
 int launch_step_t(vplbm_lattice *L, bool macro) {
   using T = typename Store<S>::T;
   const StepArgs<T> a = L->step_args<T>();
   const int grid = 8 * a.per_xcd;
-  const S *fin = (const S *)L->A();
+  // AA launches read and write the one buffer through fout
+  const S *fin = AA == 0 ? (const S *)L->A() : nullptr;
   S *fout = (S *)L->Bbuf();
   T *r = (T *)L->at(L->L.mrho), *u = (T *)L->at(L->L.mux), *v = (T *)L->at(L->L.muy);
   const SiRec *recs = (const SiRec *)L->at(L->L.recs);
@@ -333,29 +350,33 @@ int launch_step_t(vplbm_lattice *L, bool macro) {
   const BodyTab *bt = L->bt();
   if (macro) {
     if (a.trt)
-      VP_LAUNCH((k_step<S, BX, BY, true, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
+      VP_LAUNCH((k_step<S, BX, BY, true, true, AA>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
                 L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
     else
-      VP_LAUNCH((k_step<S, BX, BY, true, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
+      VP_LAUNCH((k_step<S, BX, BY, true, false, AA>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
                 L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
   } else {
     if (a.trt)
-      VP_LAUNCH((k_step<S, BX, BY, false, true>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
+      VP_LAUNCH((k_step<S, BX, BY, false, true, AA>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
                 L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
     else
-      VP_LAUNCH((k_step<S, BX, BY, false, false>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(),
+      VP_LAUNCH((k_step<S, BX, BY, false, false, AA>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(),
                 a, L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
   }
   return L->launched("k_step");
 }
 
 template <typename S> int launch_step_s(vplbm_lattice *L, bool macro) {
-  if (L->bx == 64 && L->by == 4) return launch_step_t<S, 64, 4>(L, macro);
-  if (L->bx == 128 && L->by == 2) return launch_step_t<S, 128, 2>(L, macro);
-  if (L->bx == 256 && L->by == 1) return launch_step_t<S, 256, 1>(L, macro);
-  if (L->bx == 64 && L->by == 1) return launch_step_t<S, 64, 1>(L, macro);
-  if (L->bx == 64 && L->by == 2) return launch_step_t<S, 64, 2>(L, macro);
-  if (L->bx == 128 && L->by == 1) return launch_step_t<S, 128, 1>(L, macro);
+  if (L->aa()) {  // odd steps pull and push, even steps stay in the cell (64x4 tiles)
+    if (L->bx != 64 || L->by != 4) return L->fail(VPLBM_EINVAL, "the AA pattern runs with the 64x4 tile only");
+    return ((L->nstep + 1) & 1) ? launch_step_t<S, 64, 4, 1>(L, macro) : launch_step_t<S, 64, 4, 2>(L, macro);
+  }
+  if (L->bx == 64 && L->by == 4) return launch_step_t<S, 64, 4, 0>(L, macro);
+  if (L->bx == 128 && L->by == 2) return launch_step_t<S, 128, 2, 0>(L, macro);
+  if (L->bx == 256 && L->by == 1) return launch_step_t<S, 256, 1, 0>(L, macro);
+  if (L->bx == 64 && L->by == 1) return launch_step_t<S, 64, 1, 0>(L, macro);
+  if (L->bx == 64 && L->by == 2) return launch_step_t<S, 64, 2, 0>(L, macro);
+  if (L->bx == 128 && L->by == 1) return launch_step_t<S, 128, 1, 0>(L, macro);
   return L->fail(VPLBM_EINVAL, "unsupported tile shape %dx%d", L->bx, L->by);
 }
 
@@ -374,7 +395,8 @@ int launch_init_s(vplbm_lattice *L, int row0, int nrows, const double *r, const 
                   const double *v, double ru, double uu, double vu) {
   dim3 blk(256), grd((L->p.nx + 255) / 256, nrows);
   VP_LAUNCH((k_init<S>), grd, blk, 0, L->stream, (S *)L->A(), L->mask(), L->p.nx, L->p.ny,
-                     L->pitch, L->plane, row0, nrows, r, u, v, ru, uu, vu, L->ctl(), L->p.rho0);
+                     L->pitch, L->plane, row0, nrows, r, u, v, ru, uu, vu, L->ctl(), L->p.rho0, (int)L->aa(),
+                     (S *)L->ec(0), perim_count(L->p.nx, L->p.ny));
   return L->launched("k_init");
 }
 
@@ -391,7 +413,8 @@ int launch_init(vplbm_lattice *L, int row0, int nrows, const double *r, const do
 template <typename S> int launch_cbc_init_s(vplbm_lattice *L) {
   const StepArgs<typename Store<S>::T> a = L->step_args<typename Store<S>::T>();
   const int len = std::max(L->p.nx, L->p.ny);
-  VP_LAUNCH((k_cbc_init<S>), dim3((len + 255) / 256, 4), dim3(256), 0, L->stream, (const S *)L->A(), a);
+  VP_LAUNCH((k_cbc_init<S>), dim3((len + 255) / 256, 4), dim3(256), 0, L->stream, (const S *)L->A(), a,
+            (int)L->aa());
   return L->launched("k_cbc_init");
 }
 
@@ -410,8 +433,9 @@ int init_cbc(vplbm_lattice *L) {
 template <typename S>
 int launch_read_pop_s(vplbm_lattice *L, int x0, int w, int row0, int nrows, double *out) {
   dim3 blk(256), grd((w + 255) / 256, nrows);
-  VP_LAUNCH((k_read_pop<S>), grd, blk, 0, L->stream, (const S *)L->A(), x0, w, L->pitch, L->plane,
-                     row0, nrows, L->p.rho0, out);
+  VP_LAUNCH((k_read_pop<S>), grd, blk, 0, L->stream, (const S *)L->A(), (const S *)L->ec(L->nstep),
+            L->layout(), L->p.nx, L->p.ny, perim_count(L->p.nx, L->p.ny), x0, w, L->pitch, L->plane, row0, nrows,
+            L->p.rho0, out);
   return L->launched("k_read_pop");
 }
 
@@ -426,7 +450,8 @@ int launch_read_pop(vplbm_lattice *L, int x0, int w, int row0, int nrows, double
 template <typename S> int launch_si_at_s(vplbm_lattice *L, int npts, double *out) {
   using T = typename Store<S>::T;
   const StepArgs<T> a = L->step_args<T>();
-  VP_LAUNCH((k_si_at<S>), dim3(1), dim3(SI_NT), 0, L->stream, (const S *)L->A(), L->mask(),
+  VP_LAUNCH((k_si_at<S>), dim3(1), dim3(SI_NT), 0, L->stream, (const S *)L->A(), (const S *)L->ec(L->nstep),
+            L->layout(), L->mask(),
                      a, L->ctl(), (const double *)L->at(L->L.staging), L->maxp, npts, out);
   return L->launched("k_si_at");
 }
@@ -1278,6 +1303,7 @@ int vplbm_set_tile(vplbm_lattice *L, int bx, int by) {
   const bool ok = (bx == 64 && (by == 1 || by == 2 || by == 4)) || (bx == 128 && (by == 1 || by == 2)) ||
                   (bx == 256 && by == 1);
   if (!ok) return L->fail(VPLBM_EINVAL, "unsupported tile %dx%d", bx, by);
+  if (L->aa() && (bx != 64 || by != 4)) return L->fail(VPLBM_EINVAL, "the AA pattern runs with the 64x4 tile only");
   L->bx = bx;
   L->by = by;
   return VPLBM_OK;
@@ -1575,6 +1601,7 @@ int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out) {
     if (!lats[k] || lats[k]->p.precision != prec || lats[k]->stream != lats[0]->stream) return VPLBM_EINVAL;
     if ((lats[k]->p.trt_lambda > 0.0) != (lats[0]->p.trt_lambda > 0.0)) return VPLBM_EINVAL;
     if (lats[k]->bx != 64 || lats[k]->by != 4) return VPLBM_EINVAL;  // batched launches use the 64x4 tile
+    if (lats[k]->aa()) return lats[k]->fail(VPLBM_EINVAL, "a batch takes two-buffer (AB) lattices only");
     for (int j = 0; j < k; ++j)
       if (lats[j] == lats[k]) return VPLBM_EINVAL;
   }

@@ -23,6 +23,7 @@ PRECISIONS = {"f64": F64, "f32": F32, "f16dev": F16DEV}
 PERIODIC, VELOCITY, FREESLIP, OUTFLOW, CONVECTIVE = 0, 1, 2, 3, 4
 FORCE_ME, FORCE_SI = 0, 1
 STEP_MACRO = 1
+STREAM_AB, STREAM_AA = 0, 1
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ENOSAMPLE = 0, -1, -2, -3, -4, -6
 _ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ESTATE: "ESTATE", ENOSAMPLE: "ENOSAMPLE"}
@@ -55,7 +56,8 @@ class Params(C.Structure):
                 ("rho0", C.c_double), ("precision", C.c_int), ("west", Edge), ("east", Edge),
                 ("south", Edge), ("north", Edge), ("hist_capacity", C.c_int),
                 ("max_si_points", C.c_int), ("max_vertices", C.c_int), ("trt_lambda", C.c_double),
-                ("si_rule", C.c_int), ("max_bodies", C.c_int), ("max_interface_cells", C.c_int)]
+                ("si_rule", C.c_int), ("max_bodies", C.c_int), ("max_interface_cells", C.c_int),
+                ("streaming", C.c_int)]
 
 
 class BodyState(C.Structure):
@@ -140,7 +142,8 @@ def _f64(a, shape=None):
 
 def make_params(nx, ny, tau, eta, rho0=1.0, precision="f32", west=(PERIODIC, 0, 0), east=(PERIODIC, 0, 0),
                 south=(PERIODIC, 0, 0), north=(PERIODIC, 0, 0), hist_capacity=0, max_si_points=0,
-                max_vertices=0, trt_lambda=0.0, si_rule=0, max_bodies=0, max_interface_cells=0) -> Params:
+                max_vertices=0, trt_lambda=0.0, si_rule=0, max_bodies=0, max_interface_cells=0,
+                streaming=0) -> Params:
     p = Params()
     p.nx, p.ny, p.tau, p.eta, p.rho0 = int(nx), int(ny), float(tau), float(eta), float(rho0)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -151,6 +154,7 @@ def make_params(nx, ny, tau, eta, rho0=1.0, precision="f32", west=(PERIODIC, 0, 
     p.si_rule = int(si_rule)
     p.max_bodies = int(max_bodies)
     p.max_interface_cells = int(max_interface_cells)
+    p.streaming = int(streaming)
     return p
 
 

@@ -66,7 +66,7 @@ def test_required_bytes_valid():
     dict(trt_lambda=-0.1), dict(trt_lambda=float("nan")), dict(nx=20000), dict(si_rule=2), dict(si_rule=-1),
     dict(si_rule=1, max_si_points=1025), dict(si_rule=1, max_si_points=0),
     dict(east=(V.CONVECTIVE, -0.01, 0)), dict(east=(V.CONVECTIVE, float("nan"), 0)), dict(east=(5, 0, 0)),
-    dict(max_bodies=64), dict(max_bodies=-1), dict(max_interface_cells=-1),
+    dict(max_bodies=64), dict(max_bodies=-1), dict(max_interface_cells=-1), dict(streaming=2), dict(streaming=-1),
 ])
 def test_required_bytes_rejects(kw):
     assert V.required_bytes(base(**kw)) == 0
@@ -91,6 +91,16 @@ def test_interface_slots_are_sized_by_the_caller():
     a = V.required_bytes(base(max_interface_cells=100))
     b = V.required_bytes(base(max_interface_cells=100000))
     assert 0 < a < b
+
+
+def test_aa_storage_keeps_one_population_buffer():
+    for prec, es in (("f64", 8), ("f32", 4), ("f16dev", 2)):
+        ab = V.required_bytes(base(precision=prec, nx=2000, ny=1000))
+        aa = V.required_bytes(base(precision=prec, nx=2000, ny=1000, streaming=V.STREAM_AA))
+        pop = 9 * 1000 * 2048 * es  # one [9][ny][pitch] buffer
+        # one buffer less, plus the two perimeter copies (9 x 5996 cells each)
+        assert ab - aa >= pop - 2 * 9 * 6000 * es - 4096
+        assert ab - aa <= pop
 
 
 def test_convective_edge_accepted():
