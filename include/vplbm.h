@@ -140,7 +140,8 @@ enum { VPLBM_FORCE_ME = 0, VPLBM_FORCE_SI = 1 };
 enum { VPLBM_STEP_MACRO = 1 }; /* vplbm_step flag: write rho, u on the last step */
 
 /* Exact device bytes a lattice with these parameters needs (populations
- * A and B, mask, macroscopic fields, partial sums, force history, tables);
+ * A and B, or one buffer with the AA pattern; mask, macroscopic fields,
+ * per-cell force slots, force history, tables);
  * 0 if the parameters are invalid. */
 size_t vplbm_required_bytes(const vplbm_params *p);
 

@@ -1,14 +1,16 @@
 // vplbm.hip -- host side of the VP-LBM library: the C ABI of include/vplbm.h.
 //
 // Device memory of one lattice (carved from one buffer, 256-byte aligned):
-//   A, B     : populations, [9][ny][pitch] of the storage type (ping-pong)
-//   mask     : [ny][pitch] bytes (bit 0 chi, bit 6 SI sample, bit 7 interface)
+//   A, B     : populations, [9][ny][pitch] of the storage type (ping-pong;
+//              one buffer only with the AA pattern, plus its perimeter copies)
+//   mask     : [ny][pitch] bytes (bits 0-5 body id, 6 SI sample, 7 interface)
 //   macro    : rho, ux, uy [ny][pitch] of the compute type (written on request)
 //   si_map   : [ny][pitch] int, record index of a sample node
-//   partials : per-block force partial sums (8 doubles per tile)
-//   hist     : force-history ring [cap][6] doubles
-//   ctl      : control block (body state, window, counters)
-//   recs     : stress-integration records, pts: SI points [5][maxp]
+//   imap     : [ny][pitch] int, momentum-exchange slot of an interface cell
+//   me, sig  : per-interface-cell ME sums and per-record stresses, by parity
+//   hist     : force-history ring [cap][max_bodies][6] doubles
+//   ctl, bt  : control block (body 1 state, window, counters), per-body ranges
+//   recs     : stress-integration records, pts: SI points [6][maxp]
 //   verts    : polygon vertices on the 1/4096 grid [2][maxv] int64
 //   staging  : bounded host<->device staging for setup and readback
 #include <hip/hip_runtime.h>
@@ -484,7 +486,7 @@ int launch_body_step(vplbm_lattice *L) {
   return L->launched("k_body_step");
 }
 
-// sum the partials of the last step into the history (forces readable)
+// sum the last step's force slots into the history (forces readable)
 int flush(vplbm_lattice *L) {
   if (!L->pending) return VPLBM_OK;
   VP_LAUNCH((k_finalize<256>), dim3(1), dim3(256), 0, L->stream, (const double *)L->me(L->nstep),
