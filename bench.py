@@ -235,7 +235,8 @@ def run_serve(args, W):
     eng.sync()
     eng.release(h)
     budget = int(args.budget_gib * 2 ** 30)
-    served = summarize(Server(eng, budget, chunk=1000).run(items))
+    served = summarize(Server(eng, budget, chunk=args.chunk, policy=args.policy,
+                              saturate_cells=args.saturate_cells).run(items))
     serial = summarize(serial_run(eng, items))
     return {
         "metric": METRIC, "value": round(served["aggregate_MLUPS"], 1), "unit": "MLUPS", "n_gpus": 1,
@@ -244,7 +245,9 @@ def run_serve(args, W):
         "dtype": {"f32": "f32", "f16dev": "f32 (f16 storage)", "f64": "f64"}[args.precision], "data": "synthetic",
         "config": {"workload": "serving_poisson_mix", "requests": args.requests, "rate_per_s": args.rate,
                    "grids": [[256, 256], [512, 256], [1024, 512], [2048, 1024]], "steps_range": [2000, 20000],
-                   "hbm_budget_GiB": args.budget_gib, "chunk_steps": 1000, "storage": args.precision},
+                   "hbm_budget_GiB": args.budget_gib, "chunk_steps": args.chunk, "policy": args.policy,
+                   "saturate_cells": args.saturate_cells if args.policy == "srpt" else None,
+                   "storage": args.precision},
         "serving": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in served.items()},
         "serial": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in serial.items()},
     }
@@ -260,6 +263,11 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=10.0, help="serve: Poisson arrival rate (requests/s)")
     ap.add_argument("--budget-gib", type=float, default=4.0, help="serve: HBM budget for resident lattices")
+    ap.add_argument("--policy", default="fair", choices=["fair", "srpt"],
+                    help="serve: run all resident lattices each chunk, or least remaining work first")
+    ap.add_argument("--saturate-cells", type=int, default=4 << 20,
+                    help="serve, srpt: cells a chunk's lattices must hold before the policy stops adding")
+    ap.add_argument("--chunk", type=int, default=1000, help="serve: steps per chunk")
     ap.add_argument("--streaming", default="ab", choices=["ab", "aa"],
                     help="population storage of single-lattice workloads: two buffers or one (AA pattern)")
     ap.add_argument("--sed-seconds", type=float, default=0.0,

@@ -5,9 +5,14 @@ The server:
   * admits a waiting request as soon as its device bytes
     (``vplbm_required_bytes``) fit in the HBM budget, keeping its lattice
     resident until it finishes;
-  * advances all resident lattices together, a chunk of steps at a time, with
+  * advances resident lattices together, a chunk of steps at a time, with
     one batched launch per step (``vplbm_batch_step``); a request whose step
-    count ends inside a chunk drops out of the launches at that point;
+    count ends inside a chunk drops out of the launches at that point.  Which
+    resident lattices run in a chunk is the policy: ``fair`` runs all of them;
+    ``srpt`` runs those with the least remaining work (cells x steps) first,
+    adding more until the chunk's lattices hold ``saturate_cells`` cells
+    (enough to keep the GPU's memory system busy), while the others wait,
+    resident, for a later chunk;
   * between chunks, retires finished requests (frees their memory, records the
     result) and admits newly arrived ones -- requests that arrive while
     others run join them at the next chunk boundary.
@@ -105,14 +110,34 @@ class Server:
     """Continuous batching under an HBM budget (see the module docstring)."""
 
     def __init__(self, engine, budget_bytes: int, chunk: int = 1000, max_resident: int = 256,
-                 clock: Optional[Callable[[], float]] = None, sleep: Optional[Callable[[float], None]] = None):
+                 clock: Optional[Callable[[], float]] = None, sleep: Optional[Callable[[float], None]] = None,
+                 policy: str = "fair", saturate_cells: int = 4 << 20):
+        if policy not in ("fair", "srpt"):
+            raise ValueError(f"unknown policy {policy!r}")
         self.engine = engine
         self.budget = int(budget_bytes)
         self.chunk = int(chunk)
         self.max_resident = int(max_resident)
+        self.policy = policy
+        self.saturate_cells = int(saturate_cells)
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
         self.events: List[tuple] = []   # (time, kind, rid) for inspection
+
+    def _chunk_steps(self, resident: List[Request]) -> List[int]:
+        """Steps each resident request advances in the next chunk (0 = waits)."""
+        if self.policy == "fair":
+            return [min(r.remaining, self.chunk) for r in resident]
+        order = sorted(range(len(resident)),
+                       key=lambda i: (resident[i].remaining * resident[i].cells, resident[i].arrival, resident[i].rid))
+        n = [0] * len(resident)
+        cells = 0
+        for i in order:
+            n[i] = min(resident[i].remaining, self.chunk)
+            cells += resident[i].cells
+            if cells >= self.saturate_cells:
+                break
+        return n
 
     def run(self, items) -> List[Request]:
         """items: iterable of (rid, arrival_s, case, steps). Returns the requests."""
@@ -148,7 +173,7 @@ class Server:
                 if future:
                     self.sleep(max(0.0, future[0].arrival - now()))
                 continue
-            n = [min(r.remaining, self.chunk) for r in resident]
+            n = self._chunk_steps(resident)
             self.engine.step([r.handle for r in resident], n)
             self.engine.sync()
             t = now()

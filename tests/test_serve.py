@@ -36,6 +36,7 @@ class CountingEngine:
         self.peak = 0
         self.bytes_live = 0
         self.launches = []
+        self.active = []
 
     def nbytes(self, case):
         return case.nx * case.ny * 100
@@ -50,6 +51,7 @@ class CountingEngine:
 
     def step(self, handles, nsteps):
         self.launches.append(len(handles))
+        self.active.append(sum(1 for n in nsteps if n))
         work = 0
         for h, n in zip(handles, nsteps):
             self.steps[h.id] += n
@@ -130,6 +132,45 @@ def test_serial_run_one_at_a_time():
     reqs = serial_run(eng, items_from([(0.0, 16, 16, 100), (0.0, 16, 16, 100)]), clock=clk, sleep=clk.sleep)
     assert reqs[1].t_admit >= reqs[0].t_finish
     assert eng.launches == [1, 1]
+
+
+def test_srpt_short_request_overtakes_and_everything_finishes():
+    # a long request, then short ones arriving while it runs: under srpt the
+    # short ones run alone (each fills the saturation threshold) and finish
+    # sooner than under fair sharing; the long one still finishes and every
+    # request gets exactly its steps
+    spec = [(0.0, 64, 64, 20000), (1.0, 16, 16, 300), (1.5, 16, 16, 300), (2.0, 32, 32, 500)]
+    out = {}
+    for policy in ("fair", "srpt"):
+        clk = Clock()
+        eng = CountingEngine(clk, rate=1e5)
+        srv = Server(eng, 10 ** 9, chunk=100, clock=clk, sleep=clk.sleep, policy=policy, saturate_cells=16 * 16)
+        reqs = srv.run(items_from(spec))
+        assert all(r.result["steps"] == r.steps for r in reqs)
+        out[policy] = (reqs, eng)
+    fair, srpt = out["fair"][0], out["srpt"][0]
+    for k in (1, 2, 3):
+        assert srpt[k].latency < fair[k].latency
+    assert srpt[0].t_finish is not None
+    # the same total work: the last request finishes at the same time
+    assert math.isclose(max(r.t_finish for r in srpt), max(r.t_finish for r in fair), rel_tol=1e-9)
+    # srpt ran one request per chunk here (each one reaches the threshold)
+    assert max(out["srpt"][1].active) == 1 and max(out["fair"][1].active) >= 2
+
+
+def test_srpt_fills_the_saturation_threshold():
+    clk = Clock()
+    eng = CountingEngine(clk)
+    spec = [(0.0, 16, 16, 1000 + 10 * i) for i in range(8)]
+    srv = Server(eng, 10 ** 9, chunk=100, clock=clk, sleep=clk.sleep, policy="srpt", saturate_cells=3 * 256)
+    reqs = srv.run(items_from(spec))
+    assert all(r.result["steps"] == r.steps for r in reqs)
+    assert max(eng.active) == 3  # three 16 x 16 lattices reach 768 cells
+    # least remaining work first: finishing order follows the step counts
+    order = sorted(reqs, key=lambda r: r.t_finish)
+    assert [r.rid for r in order] == list(range(8))
+    with pytest.raises(ValueError):
+        Server(eng, 1, policy="lifo")
 
 
 def test_percentile():
