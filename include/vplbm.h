@@ -133,6 +133,9 @@ enum {
   VPLBM_ENOMEM = -2,   /* device memory too small or allocation failed */
   VPLBM_EHIP = -3,     /* HIP runtime error (including asynchronous kernel faults) */
   VPLBM_ESTATE = -4,   /* call not valid in the current state */
+  VPLBM_EUNSTABLE = -5, /* the solution diverged: a step met a non-finite density
+                           (reported by the next vplbm_sync or force read;
+                           the state is then meaningless until re-initialized) */
   VPLBM_ENOSAMPLE = -6 /* a stress-integration point found no fluid sample node */
 };
 
@@ -262,6 +265,10 @@ int vplbm_get_body_state(vplbm_lattice *lat, vplbm_body_state *out);
 /* rho and penalized u of the last step (which must have been run with
  * VPLBM_STEP_MACRO), host arrays [ny][nx]. */
 int vplbm_read_macro(vplbm_lattice *lat, double *rho, double *ux, double *uy);
+/* The same into caller-owned device arrays [ny][nx] of the compute type (double
+ * for VPLBM_F64, float for VPLBM_F32 and VPLBM_F16DEV), asynchronously on the
+ * lattice's stream (no host transfer). */
+int vplbm_read_macro_device(vplbm_lattice *lat, void *rho, void *ux, void *uy);
 /* The same restricted to the window of w columns from x0 and h rows from y0
  * (host arrays [h][w]); VPLBM_EINVAL if it leaves the lattice. */
 int vplbm_read_macro_window(vplbm_lattice *lat, int x0, int y0, int w, int h, double *rho, double *ux,

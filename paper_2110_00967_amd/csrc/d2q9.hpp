@@ -154,7 +154,8 @@ struct Ctl {
   int npts;            // registered stress-integration points
   int si_moving;       // points stored in the body frame
   int err;             // bit 0: a point without sample node; bit 1: a fluid cell
-                       // linked to two bodies; bit 2: a sample node shared by two bodies
+                       // linked to two bodies; bit 2: a sample node shared by two bodies;
+                       // bit 3: interface slots exhausted; bit 4: a non-finite density
   long long step;      // steps completed since initialization
   double last[6];      // forces of body 1 in the last step: ME (Fx, Fy, T), SI (Fx, Fy, T)
   int mode, shape, source;

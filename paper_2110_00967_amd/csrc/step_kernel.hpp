@@ -440,6 +440,12 @@ __device__ __forceinline__ void step_tile(
     const T mx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
     const T my = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
     const T rho = P.rho0 + drho;
+    // a non-finite density means the run diverged: one lane per such wave
+    // flags it (error bit 4) for the host's next check
+    {
+      const unsigned long long bad = __ballot(!(fabs(drho) <= T(1e30)));
+      if (bad && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)bad) - 1)) atomicOr(&ctl->err, 16);
+    }
 
     // penalized velocity (Eq. updatestepm) and force; k = 0 in fluid cells
     T khalf = T(0), a1 = T(1), kk = T(0), usx = T(0), usy = T(0);

@@ -586,6 +586,7 @@ int check_sample_error(vplbm_lattice *L) {
   int rc = L->ctl_pull(c);
   if (rc) return rc;
   const int e = c.err;
+  if (e & 16) return L->fail(VPLBM_EUNSTABLE, "the solution diverged (a non-finite density at some step)");
   if (e & 15) {
     c.err = 0;
     rc = L->ctl_push(c);
@@ -1290,8 +1291,7 @@ int vplbm_sync(vplbm_lattice *L) {
   int rc = flush(L);
   if (!rc) rc = L->sync();
   if (rc) return rc;
-  if (L->npts && L->mode != MODE_STATIC) return check_sample_error(L);
-  return VPLBM_OK;
+  return check_sample_error(L);  // divergence flag; lost sample nodes of a moving body
 }
 
 long long vplbm_step_count(const vplbm_lattice *L) { return L ? L->nstep : -1; }
@@ -1322,6 +1322,7 @@ static int read_last(vplbm_lattice *L, int which, double out[3]) {
   int rc = L->ctl_pull(c);
   if (rc) return rc;
   for (int i = 0; i < 3; ++i) out[i] = c.last[3 * which + i];
+  if (c.err & 16) return L->fail(VPLBM_EUNSTABLE, "the solution diverged (a non-finite density at some step)");
   if (c.err & 8)
     return L->fail(VPLBM_ESTATE, "more interface cells than max_interface_cells = %lld: the momentum exchange "
                                  "dropped some",
@@ -1447,6 +1448,22 @@ int vplbm_read_macro_window(vplbm_lattice *L, int x0, int y0, int w, int h, doub
     std::memcpy(rho + (size_t)r0 * w, hb.data(), n * 8);
     std::memcpy(ux + (size_t)r0 * w, hb.data() + n, n * 8);
     std::memcpy(uy + (size_t)r0 * w, hb.data() + 2 * n, n * 8);
+  }
+  return VPLBM_OK;
+}
+
+int vplbm_read_macro_device(vplbm_lattice *L, void *rho, void *ux, void *uy) {
+  if (!L || !rho || !ux || !uy) return L ? L->fail(VPLBM_EINVAL, "NULL output") : VPLBM_EINVAL;
+  if (!L->macro_valid) return L->fail(VPLBM_ESTATE, "last step did not store rho and u (VPLBM_STEP_MACRO)");
+  const size_t es = compute_size(L->p.precision);
+  const size_t off[3] = {L->L.mrho, L->L.mux, L->L.muy};
+  void *dst[3] = {rho, ux, uy};
+  for (int k = 0; k < 3; ++k) {
+    const int rc = L->hip(hipMemcpy2DAsync(dst[k], (size_t)L->p.nx * es, L->at(off[k]), (size_t)L->pitch * es,
+                                           (size_t)L->p.nx * es, (size_t)L->p.ny, hipMemcpyDeviceToDevice,
+                                           L->stream),
+                          "macro device copy");
+    if (rc) return rc;
   }
   return VPLBM_OK;
 }

@@ -25,8 +25,9 @@ FORCE_ME, FORCE_SI = 0, 1
 STEP_MACRO = 1
 STREAM_AB, STREAM_AA = 0, 1
 
-OK, EINVAL, ENOMEM, EHIP, ESTATE, ENOSAMPLE = 0, -1, -2, -3, -4, -6
-_ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ESTATE: "ESTATE", ENOSAMPLE: "ENOSAMPLE"}
+OK, EINVAL, ENOMEM, EHIP, ESTATE, EUNSTABLE, ENOSAMPLE = 0, -1, -2, -3, -4, -5, -6
+_ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ESTATE: "ESTATE", EUNSTABLE: "EUNSTABLE",
+             ENOSAMPLE: "ENOSAMPLE"}
 
 # every entry point of include/vplbm.h
 EXPORTS = [
@@ -38,6 +39,7 @@ EXPORTS = [
     "vplbm_read_populations", "vplbm_read_mask", "vplbm_read_macro_window", "vplbm_read_populations_window",
     "vplbm_batch_create", "vplbm_batch_destroy", "vplbm_batch_last_error", "vplbm_batch_step",
     "vplbm_set_body_ids", "vplbm_set_si_points_body", "vplbm_forces_body", "vplbm_force_history_body",
+    "vplbm_read_macro_device",
 ]
 
 
@@ -336,6 +338,16 @@ class Lattice:
         s = BodyState()
         self._chk(self._lib.vplbm_get_body_state(self._h, C.byref(s)))
         return np.array([s.x, s.y, s.theta, s.u, s.v, s.omega])
+
+    def macro_device(self):
+        """rho, ux, uy of the last VPLBM_STEP_MACRO step as new device tensors
+        [ny][nx] of the compute type, filled on the lattice's stream."""
+        import torch
+
+        dt = torch.float64 if self.params.precision == F64 else torch.float32
+        out = [torch.empty((self.ny, self.nx), dtype=dt, device="cuda") for _ in range(3)]
+        self._chk(self._lib.vplbm_read_macro_device(self._h, *(C.c_void_p(t.data_ptr()) for t in out)))
+        return out
 
     def macro(self):
         r = np.zeros((self.ny, self.nx))
