@@ -654,6 +654,7 @@ __global__ void __launch_bounds__(SI_NT)
 // the old and new regions (one workgroup)
 // ----------------------------------------------------------------------------
 constexpr int BODY_NT = 1024;
+constexpr int INSIDE_LDS = 32768;  // bytes of disk tests the body kernel stages in LDS
 constexpr int REGION_MARGIN = 6;  // covers links (1) and sample walks (5)
 
 __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
@@ -669,6 +670,7 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
   __shared__ int wsum[BODY_NT / 64];
   __shared__ int nslot;
   __shared__ double flast[6];  // forces of the step just taken (ME, SI)
+  __shared__ uint8_t inside[INSIDE_LDS];
   // Loads that do not depend on the finalize, issued first so their latency
   // overlaps it: the control-block fields of the update (the finalize does
   // not write them) and this thread's stress-integration point.
@@ -733,22 +735,53 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
   // records an interface cell (rounds past 64 read the mask back)
   unsigned long long ifbits = 0;
   int cnt = 0;
-  for (int t = threadIdx.x, k = 0; t < w * h; t += BODY_NT, ++k) {
-    const int i = x0 + t % w, j = y0 + t / w;
-    const bool own = disk_inside(X, Y, R, i, j);
-    bool iface = false;
-#pragma unroll
-    for (int a = 1; a < Q; ++a) {
-      int I = i + cx(a), J = j + cy(a);
+  // the disk test of every cell of the region and a one-cell ring around it
+  // (neighbours wrapped across periodic edges; 2 = no such neighbour), once
+  // per cell in LDS when it fits, instead of once per link
+  const int W2 = w + 2, H2 = h + 2;
+  const bool staged = W2 * H2 <= INSIDE_LDS;
+  if (staged) {
+    for (int t = threadIdx.x; t < W2 * H2; t += BODY_NT) {
+      int I = x0 - 1 + t % W2, J = y0 - 1 + t / W2;
+      bool there = true;
       if (I < 0 || I >= nx) {
-        if (!perx) continue;
+        there = perx != 0;
         I = I < 0 ? I + nx : I - nx;
       }
       if (J < 0 || J >= ny) {
-        if (!pery) continue;
+        there = there && pery != 0;
         J = J < 0 ? J + ny : J - ny;
       }
-      if (disk_inside(X, Y, R, I, J) != own) iface = true;
+      inside[t] = there ? (disk_inside(X, Y, R, I, J) ? 1 : 0) : 2;
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x, k = 0; t < w * h; t += BODY_NT, ++k) {
+    const int i = x0 + t % w, j = y0 + t / w;
+    bool own, iface = false;
+    if (staged) {
+      const int c = (t / w + 1) * W2 + t % w + 1;
+      own = inside[c] == 1;
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        const uint8_t nb = inside[c + cy(a) * W2 + cx(a)];
+        if (nb != 2 && (nb == 1) != own) iface = true;
+      }
+    } else {
+      own = disk_inside(X, Y, R, i, j);
+#pragma unroll
+      for (int a = 1; a < Q; ++a) {
+        int I = i + cx(a), J = j + cy(a);
+        if (I < 0 || I >= nx) {
+          if (!perx) continue;
+          I = I < 0 ? I + nx : I - nx;
+        }
+        if (J < 0 || J >= ny) {
+          if (!pery) continue;
+          J = J < 0 ? J + ny : J - ny;
+        }
+        if (disk_inside(X, Y, R, I, J) != own) iface = true;
+      }
     }
     mask[(long long)j * pitch + i] = (own ? 1 : 0) | (iface ? M_IFACE : 0);
     if (iface) {
