@@ -48,6 +48,17 @@ enum { EDGE_PERIODIC = 0, EDGE_VELOCITY = 1, EDGE_FREESLIP = 2, EDGE_OUTFLOW = 3
 // population at each edge cell, [edge][slot][cell along the edge] with the
 // west and east blocks ny long and the south and north blocks nx long.  The
 // slot of a population is its velocity component along the edge (0, +1, -1).
+// Population layout (array of structures of arrays): the 9 deviations of
+// each run of 64 cells along a row are stored together, plane by plane, so
+// one cell update touches 9 neighbouring 64-element blocks instead of 9
+// planes a lattice apart.  Element (a, x, y), with pitch a multiple of 64:
+//   ((y * (pitch / 64) + x / 64) * 9 + a) * 64 + x % 64.
+// 9 ny pitch < 2^31, so the index fits an int.
+__host__ __device__ inline int pop_index(int a, int x, int y, int pitch) {
+  return ((y * (pitch >> 6) + (x >> 6)) * Q + a) * 64 + (x & 63);
+}
+constexpr int CHUNK_ELEMS = 64 * 9;  // one run of 64 cells, all populations
+
 // Index of a perimeter cell (x == 0, x == nx - 1, y == 0 or y == ny - 1):
 // the west column, the east column, then the south and the north row
 // without their corners; 2 ny + 2 (nx - 2) cells in all.

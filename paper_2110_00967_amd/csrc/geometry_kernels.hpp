@@ -18,12 +18,11 @@ namespace vp {
 // ----------------------------------------------------------------------------
 template <typename S>
 __device__ __forceinline__ typename Store<S>::T load_post(const S *F, const S *ec, int lay, int nx, int ny,
-                                                          int pitch, long long plane, int nper, int x, int y,
-                                                          int a) {
-  if (lay == 0) return Store<S>::ld(F + a * plane + (long long)y * pitch + x);
-  if (lay == 1) return Store<S>::ld(F + opp(a) * plane + (long long)y * pitch + x);
+                                                          int pitch, int nper, int x, int y, int a) {
+  if (lay == 0) return Store<S>::ld(F + pop_index(a, x, y, pitch));
+  if (lay == 1) return Store<S>::ld(F + pop_index(opp(a), x, y, pitch));
   const int tx = x + cx(a), ty = y + cy(a);
-  if (tx >= 0 && tx < nx && ty >= 0 && ty < ny) return Store<S>::ld(F + a * plane + (long long)ty * pitch + tx);
+  if (tx >= 0 && tx < nx && ty >= 0 && ty < ny) return Store<S>::ld(F + pop_index(a, tx, ty, pitch));
   return Store<S>::ld(ec + (long long)a * nper + perim_index(x, y, nx, ny));
 }
 
@@ -39,7 +38,7 @@ __device__ __forceinline__ void pull_post(const S *F, const S *ec, int lay, cons
     T add;
     bool cv;
     edge_source(P, x, y, a, pop, sx, sy, add, cv);
-    d[a] = load_post(F, ec, lay, P.nx, P.ny, P.pitch, P.plane, P.nper, sx, sy, pop) + add;
+    d[a] = load_post(F, ec, lay, P.nx, P.ny, P.pitch, P.nper, sx, sy, pop) + add;
     conv |= cv ? 1u << a : 0u;
   }
 #pragma unroll
@@ -54,7 +53,7 @@ __device__ __forceinline__ void pull_post(const S *F, const S *ec, int lay, cons
 // ----------------------------------------------------------------------------
 template <typename S>
 __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
-                       long long plane, int row0, int nrows, const double *__restrict__ rho_in,
+                       int row0, int nrows, const double *__restrict__ rho_in,
                        const double *__restrict__ ux_in, const double *__restrict__ uy_in,
                        double rho_u, double ux_u, double uy_u, const Ctl *__restrict__ ctl, double rho0,
                        int swapped, S *__restrict__ ec, int nper) {
@@ -84,7 +83,7 @@ __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int 
   for (int a = 0; a < Q; ++a) {
     const double cu = cx(a) * ux + cy(a) * uy;
     const double d = wgt(a) * (rho - rho0) + wgt(a) * rho * (3.0 * cu + 4.5 * cu * cu - uu);
-    Store<S>::st(f + (swapped ? opp(a) : a) * plane + c, (typename Store<S>::T)d);
+    Store<S>::st(f + pop_index(swapped ? opp(a) : a, x, y, pitch), (typename Store<S>::T)d);
     if (swapped && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1))
       Store<S>::st(ec + (long long)a * nper + perim_index(x, y, nx, ny), (typename Store<S>::T)d);
   }
@@ -113,7 +112,7 @@ __global__ void k_cbc_init(const S *__restrict__ f, const StepArgs<typename Stor
     const int cn = e < 2 ? cx(a) : cy(a), ca = e < 2 ? cy(a) : cx(a);
     if (cn != in) continue;
     P.cbc[cbc_offset(e, P.nx, P.ny) + (long long)cbc_slot(ca) * len + i] =
-        T(Store<S>::ld(f + (long long)(swapped ? opp(a) : a) * P.plane + (long long)y * P.pitch + x));
+        T(Store<S>::ld(f + pop_index(swapped ? opp(a) : a, x, y, P.pitch)));
   }
 }
 
@@ -122,7 +121,7 @@ __global__ void k_cbc_init(const S *__restrict__ f, const StepArgs<typename Stor
 // load_post)
 template <typename S>
 __global__ void k_read_pop(const S *__restrict__ f, const S *__restrict__ ec, int lay, int nx, int ny, int nper,
-                           int x0, int w, int pitch, long long plane, int row0, int nrows, double rho0,
+                           int x0, int w, int pitch, int row0, int nrows, double rho0,
                            double *__restrict__ out) {
   const int xl = blockIdx.x * blockDim.x + threadIdx.x;
   const int yl = blockIdx.y;
@@ -130,7 +129,7 @@ __global__ void k_read_pop(const S *__restrict__ f, const S *__restrict__ ec, in
 #pragma unroll
   for (int a = 0; a < Q; ++a)
     out[((long long)a * nrows + yl) * w + xl] =
-        wgt(a) * rho0 + double(load_post(f, ec, lay, nx, ny, pitch, plane, nper, x0 + xl, row0 + yl, a));
+        wgt(a) * rho0 + double(load_post(f, ec, lay, nx, ny, pitch, nper, x0 + xl, row0 + yl, a));
 }
 
 template <typename T>

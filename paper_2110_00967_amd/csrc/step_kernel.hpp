@@ -1,8 +1,8 @@
 // step_kernel.hpp -- the fused VP-LBM time step for gfx950.
 //
 // One thread updates one cell x of step n (state between steps: the
-// post-collision deviations d~^{n-1} in buffer A, structure of arrays
-// [9][ny][pitch]):
+// post-collision deviations d~^{n-1} in buffer A, the 9 populations of each
+// run of 64 cells along a row stored together, see pop_index):
 //   1. pull streaming  f^n_a(x) = f~^{n-1}_a(x - c_a)   (Eq. eqBd) with the
 //      edge rules (periodic, half-way bounce-back, specular, zero-gradient,
 //      convective);
@@ -170,7 +170,7 @@ __device__ __forceinline__ void pull_edge_all(const S *__restrict__ fin, const S
     bool cv;
     edge_source(P, x, y, a, pop, sx, sy, add, cv);
     // element index in 32 bits: 9 ny pitch < 2^31 for every accepted lattice
-    d[a] = Store<S>::ld(fin + (pop * (int)P.plane + sy * P.pitch + sx)) + add;
+    d[a] = Store<S>::ld(fin + pop_index(pop, sx, sy, P.pitch)) + add;
     conv |= cv ? 1u << a : 0u;
   }
   if (conv) {  // only convective edge cells
@@ -209,7 +209,7 @@ __device__ __forceinline__ void aa_pull_edge(const S *F, const StepArgs<T> &P, i
     T add;
     bool cv;
     edge_source(P, x, y, a, pop, sx, sy, add, cv);
-    const int k = in ? (AA == 1 ? opp(a) * (int)P.plane + ry * P.pitch + rx : a * (int)P.plane + y * P.pitch + x)
+    const int k = in ? (AA == 1 ? pop_index(opp(a), rx, ry, P.pitch) : pop_index(a, x, y, P.pitch))
                      : pop * P.nper + perim_index(sx, sy, P.nx, P.ny);
     d[a] = Store<S>::ld((in ? F : ec) + k) + (in ? T(0) : add);
     conv |= (!in && cv) ? 1u << a : 0u;
@@ -228,25 +228,42 @@ __device__ __forceinline__ void aa_pull_edge(const S *F, const StepArgs<T> &P, i
   }
 }
 
-// Store the post-collision deviation v of population a of cell (x, y) at
-// byte offset cb of its plane: two-buffer (AA = 0) in place; even AA launch
-// (AA = 2) into slot opp(a) of the cell; odd AA launch (AA = 1) into slot a
-// of x + c_a, dropped when that leaves the lattice (its consumers read the
-// perimeter copy).  A perimeter cell (eidx >= 0) of an AA launch also keeps
-// v in ec_out.  interior: the workgroup-uniform fast-path flag.
+// Fast path addressing (interior tiles, where a wave is one aligned run of
+// 64 cells of one row): population a of row `row` at chunk `cw` (both
+// wave-uniform), as a scalar base shifted back one chunk, so that the lane
+// offsets lo[s + 1] of the elements at x + s (s = -1, 0, +1, crossing into
+// the neighbouring chunk at the run's ends) are all non-negative.
+template <typename S, typename T>
+__device__ __forceinline__ S *fast_base(S *F, const StepArgs<T> &P, int row, int cw, int a) {
+  return F + ((long long)row * (P.pitch >> 6) + cw) * CHUNK_ELEMS + a * 64 - CHUNK_ELEMS;
+}
+
+// Population a of the wave's own run of 64 cells (row `row`, chunk `cw`,
+// both wave-uniform in every tile): scalar base + lane * sizeof(S)
+template <typename S, typename T>
+__device__ __forceinline__ S *own_base(S *F, const StepArgs<T> &P, int row, int cw, int a) {
+  return F + ((long long)row * (P.pitch >> 6) + cw) * CHUNK_ELEMS + a * 64;
+}
+
+// Store the post-collision deviation v of population a of cell (x, y):
+// two-buffer (AA = 0) in place; even AA launch (AA = 2) into slot opp(a) of
+// the cell; odd AA launch (AA = 1) into slot a of x + c_a, dropped when that
+// leaves the lattice (its consumers read the perimeter copy).  A perimeter
+// cell (eidx >= 0) of an AA launch also keeps v in ec_out.  interior: the
+// workgroup-uniform fast-path flag, with the wave's row yw, chunk cw, lane
+// byte offset lb (own cell) and lane offsets lo (see fast_base).
 template <typename S, int AA, typename T>
-__device__ __forceinline__ void put_pop(S *F, const StepArgs<T> &P, uint32_t cb, bool interior, int x, int y,
-                                        int a, T v, int eidx) {
-  if constexpr (AA == 0) {
-    Store<S>::st_at(F + (long long)a * P.plane, cb, v);
-  } else if constexpr (AA == 2) {
-    Store<S>::st_at(F + (long long)opp(a) * P.plane, cb, v);
+__device__ __forceinline__ void put_pop(S *F, const StepArgs<T> &P, bool interior, uint32_t lb,
+                                        const uint32_t (&lo)[3], int yw, int cw, int x, int y, int a, T v,
+                                        int eidx) {
+  if constexpr (AA == 0 || AA == 2) {
+    Store<S>::st_at(own_base(F, P, yw, cw, AA == 0 ? a : opp(a)), lb, v);
   } else {
     if (interior) {
-      Store<S>::st_at(F + (long long)a * P.plane + (long long)cy(a) * P.pitch + cx(a), cb, v);
+      Store<S>::st_at(fast_base(F, P, yw + cy(a), cw, a), lo[1 + cx(a)], v);
     } else {
       const int tx = x + cx(a), ty = y + cy(a);
-      if (tx >= 0 && tx < P.nx && ty >= 0 && ty < P.ny) Store<S>::st(F + (a * (int)P.plane + ty * P.pitch + tx), v);
+      if (tx >= 0 && tx < P.nx && ty >= 0 && ty < P.ny) Store<S>::st(F + pop_index(a, tx, ty, P.pitch), v);
     }
   }
   if constexpr (AA != 0) {
@@ -400,16 +417,21 @@ __device__ __forceinline__ void step_tile(
 
 
   // Every cell of the tile has all 8 neighbours inside the lattice: the
-  // workgroup-uniform fast path.  A plane holds fewer than 2^31 / 9 cells, so
-  // byte offsets inside one plane fit 32 bits; each population then loads
-  // from (plane base shifted by -c_a, a scalar pointer) + the cell's one
-  // 32-bit byte offset, and stores to its plane base + the same offset.
+  // workgroup-uniform fast path.  A wave is then one run of 64 cells of one
+  // row (tiles are 64, 128 or 256 cells wide), so its row and chunk are
+  // scalars; each population loads from a scalar base (fast_base) + one of
+  // three small lane offsets, and stores the same way.
   const bool tile_interior = (tx * BX >= 1) & (tx * BX + BX <= P.nx - 1) & (ty * BY >= 1) &
                              (ty * BY + BY <= P.ny - 1);
 
   if (x < P.nx && y < P.ny) {
     const int c = y * P.pitch + x;
-    const uint32_t cb = (uint32_t)c * (uint32_t)sizeof(S);
+    const int lane = x & 63;
+    const uint32_t lb = (uint32_t)(lane * sizeof(S));
+    const uint32_t lo[3] = {(uint32_t)((lane > 0 ? lane + CHUNK_ELEMS - 1 : 63) * sizeof(S)),
+                            (uint32_t)((lane + CHUNK_ELEMS) * sizeof(S)),
+                            (uint32_t)((lane < 63 ? lane + CHUNK_ELEMS + 1 : 2 * CHUNK_ELEMS) * sizeof(S))};
+    const int yw = __builtin_amdgcn_readfirstlane(y), cw = __builtin_amdgcn_readfirstlane(x >> 6);
     const uint8_t m = mask[(uint32_t)c];
     T d[Q];
     // AA launches read through fout, the pointer they write through: the
@@ -420,11 +442,11 @@ __device__ __forceinline__ void step_tile(
 #pragma unroll
       for (int a = 0; a < Q; ++a) {
         if constexpr (AA == 0)
-          d[a] = Store<S>::ld(at(src + (long long)a * P.plane - (long long)cy(a) * P.pitch - cx(a), cb));
+          d[a] = Store<S>::ld(at(fast_base(src, P, yw - cy(a), cw, a), lo[1 - cx(a)]));
         else if constexpr (AA == 1)
-          d[a] = Store<S>::ld(at(src + (long long)opp(a) * P.plane - (long long)cy(a) * P.pitch - cx(a), cb));
+          d[a] = Store<S>::ld(at(fast_base(src, P, yw - cy(a), cw, opp(a)), lo[1 - cx(a)]));
         else
-          d[a] = Store<S>::ld(at(src + (long long)a * P.plane, cb));
+          d[a] = Store<S>::ld(at(fast_base(src, P, yw, cw, a), lo[1]));
       }
     } else if constexpr (AA == 0) {
       pull_edge_all<S, T, true>(src, P, x, y, d);
@@ -485,7 +507,8 @@ __device__ __forceinline__ void step_tile(
       // keeps the FP32 rounding of mass and momentum unbiased.
       const T C1 = drho - rho * uu15 - P.fo * uF3;
       const T R45 = T(4.5) * rho, R3 = T(3) * rho;
-      put_pop<S, AA>(fout, P, cb, tile_interior, x, y, 0, d[0] - P.omega * (d[0] - T(wgt(0)) * C1), eidx);
+      put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, 0, d[0] - P.omega * (d[0] - T(wgt(0)) * C1),
+                     eidx);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int a = k < 2 ? k + 1 : k + 3;  // 1, 2, 5, 6; a' = 3, 4, 7, 8
@@ -505,8 +528,8 @@ __device__ __forceinline__ void step_tile(
           oa = d[a] - P.omega * se - P.omega_m * so;
           oo = d[o] - P.omega * se + P.omega_m * so;
         }
-        put_pop<S, AA>(fout, P, cb, tile_interior, x, y, a, oa, eidx);
-        put_pop<S, AA>(fout, P, cb, tile_interior, x, y, o, oo, eidx);
+        put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, a, oa, eidx);
+        put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, o, oo, eidx);
       }
     }
     if (MACRO) {

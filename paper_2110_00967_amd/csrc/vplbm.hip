@@ -1,7 +1,8 @@
 // vplbm.hip -- host side of the VP-LBM library: the C ABI of include/vplbm.h.
 //
 // Device memory of one lattice (carved from one buffer, 256-byte aligned):
-//   A, B     : populations, [9][ny][pitch] of the storage type (ping-pong;
+//   A, B     : populations, 9 ny pitch elements of the storage type, runs of
+//              64 cells x 9 populations (pop_index; ping-pong;
 //              one buffer only with the AA pattern, plus its perimeter copies)
 //   mask     : [ny][pitch] bytes (bits 0-5 body id, 6 SI sample, 7 interface)
 //   macro    : rho, ux, uy [ny][pitch] of the compute type (written on request)
@@ -397,7 +398,7 @@ int launch_init_s(vplbm_lattice *L, int row0, int nrows, const double *r, const 
                   const double *v, double ru, double uu, double vu) {
   dim3 blk(256), grd((L->p.nx + 255) / 256, nrows);
   VP_LAUNCH((k_init<S>), grd, blk, 0, L->stream, (S *)L->A(), L->mask(), L->p.nx, L->p.ny,
-                     L->pitch, L->plane, row0, nrows, r, u, v, ru, uu, vu, L->ctl(), L->p.rho0, (int)L->aa(),
+                     L->pitch, row0, nrows, r, u, v, ru, uu, vu, L->ctl(), L->p.rho0, (int)L->aa(),
                      (S *)L->ec(0), perim_count(L->p.nx, L->p.ny));
   return L->launched("k_init");
 }
@@ -436,7 +437,7 @@ template <typename S>
 int launch_read_pop_s(vplbm_lattice *L, int x0, int w, int row0, int nrows, double *out) {
   dim3 blk(256), grd((w + 255) / 256, nrows);
   VP_LAUNCH((k_read_pop<S>), grd, blk, 0, L->stream, (const S *)L->A(), (const S *)L->ec(L->nstep),
-            L->layout(), L->p.nx, L->p.ny, perim_count(L->p.nx, L->p.ny), x0, w, L->pitch, L->plane, row0, nrows,
+            L->layout(), L->p.nx, L->p.ny, perim_count(L->p.nx, L->p.ny), x0, w, L->pitch, row0, nrows,
             L->p.rho0, out);
   return L->launched("k_read_pop");
 }
