@@ -521,6 +521,10 @@ static int point_in_polygon(long long px, long long py, int nv, const long long 
 }
 
 int orc_mask_polygon(int nx, int ny, const double *xy, int nvert, uint8_t *solid) {
+  if (nvert < 3) { /* no area: no cell inside */
+    for (size_t c = 0; c < (size_t)nx * ny; ++c) solid[c] = 0;
+    return 0;
+  }
   long long *vx = (long long *)malloc(sizeof(long long) * nvert);
   long long *vy = (long long *)malloc(sizeof(long long) * nvert);
   for (int v = 0; v < nvert; ++v) {
