@@ -1660,6 +1660,10 @@ int vplbm_batch_destroy(vplbm_batch *B) {
 
 const char *vplbm_batch_last_error(const vplbm_batch *B) { return B ? B->err.c_str() : "null batch"; }
 
+// step pairs per captured graph: one launch call per group keeps the host
+// ahead of short kernels
+constexpr int GRAPH_PAIRS = 16;
+
 int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
   if (!B || !nsteps) return VPLBM_EINVAL;
   const int n = (int)B->cases.size();
@@ -1730,7 +1734,10 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
     if (rc) return rc;
     long long done = 1;
     const long long pairs = (chunk - 1) / 2;
-    if (pairs > 0) {
+    // whole groups of GRAPH_PAIRS pairs replay from the graph (one launch
+    // call per group); the remaining pairs are launched directly
+    const long long groups = pairs / GRAPH_PAIRS;
+    if (groups > 0) {
       const long long key = ((long long)nact << 40) ^ ((long long)total << 12) ^ nmov;
       if (!B->graph || B->graph_key != key) {
         if (B->graph) (void)hipGraphExecDestroy(B->graph);
@@ -1738,17 +1745,26 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
         hipGraph_t g = nullptr;
         rc = B->hip(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
         if (rc) return rc;
-        launch_batch(B, B->cap_stream, nact, total, nmov, 1, 0);
-        launch_batch(B, B->cap_stream, nact, total, nmov, 0, 0);
+        for (int q = 0; q < GRAPH_PAIRS; ++q) {
+          launch_batch(B, B->cap_stream, nact, total, nmov, 1, 0);
+          launch_batch(B, B->cap_stream, nact, total, nmov, 0, 0);
+        }
         rc = B->hip(hipStreamEndCapture(B->cap_stream, &g), "end capture");
         if (!rc) rc = B->hip(hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0), "graph instantiate");
         if (g) (void)hipGraphDestroy(g);
         if (rc) return rc;
         B->graph_key = key;
       }
-      for (long long p = 0; p < pairs && !rc; ++p) rc = B->hip(hipGraphLaunch(B->graph, B->stream), "graph launch");
+      for (long long p = 0; p < groups && !rc; ++p) rc = B->hip(hipGraphLaunch(B->graph, B->stream), "graph launch");
       if (rc) return rc;
-      done += 2 * pairs;
+      done += 2 * GRAPH_PAIRS * groups;
+    }
+    for (long long p = groups * GRAPH_PAIRS; p < pairs; ++p) {
+      launch_batch(B, B->stream, nact, total, nmov, 1, 0);
+      launch_batch(B, B->stream, nact, total, nmov, 0, 0);
+      rc = B->hip(hipGetLastError(), "k_step_batch");
+      if (rc) return rc;
+      done += 2;
     }
     if (done < chunk) {
       launch_batch(B, B->stream, nact, total, nmov, 1, 0);

@@ -12,6 +12,12 @@ from gpu_cases import CV, F, OUT, P, V_, build_gpu, build_oracle, oracle_pops, r
 pytestmark = pytest.mark.gpu
 
 
+
+def step_eager(g, n):
+    """n steps, one call each: the plain per-step launches, never a graph."""
+    for _ in range(n):
+        g.step(1)
+
 def mixed_specs():
     poly, ref, si = small_naca(nx=150, ny=75, chord=30.0, aoa=8.0)
     return [
@@ -43,7 +49,7 @@ def test_batch_equals_alone_bitwise(precision):
     alone = []
     for s, n in zip(specs, nsteps):
         g = build_gpu(s, precision)
-        g.step(n)
+        step_eager(g, n)
         alone.append(state(g) if n else None)
         g.close()
     lats = [build_gpu(s, precision) for s in specs]
@@ -78,7 +84,7 @@ def test_trt_batch_equals_alone_bitwise():
     alone = []
     for s, n in zip(specs, nsteps):
         g = build_gpu(s, "f64")
-        g.step(n)
+        step_eager(g, n)
         alone.append(state(g))
         g.close()
     lats = [build_gpu(s, "f64") for s in specs]
@@ -125,3 +131,39 @@ def test_batch_rejects_mixed_precision():
         V.Batch([a, c])
     with pytest.raises(V.VplbmError):
         V.Batch([a, a])
+
+
+@pytest.mark.parametrize("name", ["periodic_disk_random", "convective_trt_naca", "couette_walls_force"])
+def test_one_lattice_batch_equals_eager_steps(name):
+    # 57 steps: one eager launch, one captured group of 16 step pairs, then
+    # 12 pairs launched directly -- bitwise the same as one call per step
+    from paper_2110_00967_amd import vplbm as V
+    from test_gpu_parity import RAGGED
+    s = RAGGED[name]
+    say("one-lattice batch vs eager steps", name)
+    a, b = build_gpu(s, "f32"), build_gpu(s, "f32")
+    bt = V.Batch([a])
+    bt.step([57])
+    step_eager(b, 57)
+    for x, y in zip(state(a), state(b)):
+        assert np.array_equal(x, y), name
+    bt.close()
+    a.close()
+    b.close()
+
+
+def test_one_lattice_batch_moving_disk_equals_eager_steps():
+    from paper_2110_00967_amd import vplbm as V
+    case = W.case_sedimentation(nx=96, ny=320, d=16.0, rho_r=1.5, g=2e-4, npts=48, force_source=1)
+    say("one-lattice batch vs eager steps, free disk")
+    a = V.Lattice.from_case(case, precision="f32")
+    b = V.Lattice.from_case(case, precision="f32")
+    bt = V.Batch([a])
+    bt.step([75])
+    step_eager(b, 75)
+    assert np.array_equal(a.body_state(), b.body_state())
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.history(1), b.history(1))
+    bt.close()
+    a.close()
+    b.close()

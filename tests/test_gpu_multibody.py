@@ -100,7 +100,8 @@ def test_multibody_in_batch_equals_alone():
     from paper_2110_00967_amd import vplbm as V
     say("multi-body lattice inside a batch, fp32")
     g, _, _ = build("f32")
-    g.step(37)
+    for _ in range(37):  # plain per-step launches
+        g.step(1)
     alone = [g.history(w, body=b) for b in (1, 2, 3) for w in (V.FORCE_ME, V.FORCE_SI)]
     pops = g.populations()
     g.close()
