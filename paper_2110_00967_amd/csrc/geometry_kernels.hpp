@@ -341,18 +341,19 @@ __device__ __forceinline__ void si_world(const double *__restrict__ pts, int max
 // Point threadIdx.x (position, normal, body), loaded ahead by a caller that
 // has other work to overlap with the loads; ok = false when not loaded.
 struct PtPre {
-  double a, b, c, d, body;
+  double a, b, c, d, ds, body;
   bool ok;
 };
 
 __device__ __forceinline__ PtPre si_prefetch(const double *__restrict__ pts, int maxp, int npts) {
-  PtPre p{0.0, 0.0, 0.0, 0.0, 0.0, false};
+  PtPre p{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, false};
   const int i = threadIdx.x;
   if (i < npts) {
     p.a = pts[i];
     p.b = pts[maxp + i];
     p.c = pts[2 * maxp + i];
     p.d = pts[3 * maxp + i];
+    p.ds = pts[4 * maxp + i];
     p.body = pts[5 * maxp + i];
     p.ok = true;
   }
@@ -485,13 +486,21 @@ __device__ __forceinline__ void block_sort_keys(unsigned long long *key, int N) 
 // Sample nodes and per-node weights of all registered points (one workgroup
 // of SI_NT threads; called by k_si_select and, for a moving disk, at the end
 // of k_body_step after the mask was rebuilt).  solid: the solid test the
-// sample-node search uses (see MaskSolid, DiskSolid).
+// sample-node search uses (see MaskSolid, DiskSolid).  npts, moving, rule
+// and B are the control block's point count, point frame flag, stencil rule
+// and body-1 state, passed in by the caller.  stage (LDS, 5 x stage_pts
+// doubles, or null) keeps the world position, normal and length of points
+// below stage_pts from the key pass for the record pass.  check_shared:
+// flag a sample node claimed by two bodies (error bit 2); a lattice with a
+// single body cannot have one.
 template <typename Solid>
 __device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre &pre, uint8_t *__restrict__ mask,
                                                 Ctl *__restrict__ ctl,
                                 const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
                                 int *__restrict__ si_map, BodyTab *__restrict__ bt,
-                                const BodyDev *__restrict__ bodies, int nx, int ny, int pitch) {
+                                const BodyDev *__restrict__ bodies, int nx, int ny, int pitch, const int npts,
+                                const int moving, const int rule, const BodyDev &B, double *stage, int stage_pts,
+                                bool check_shared, const int *win_now = nullptr) {
   // key = (body, node, entry): records come out grouped by body, then by node
   constexpr int NODE_SHIFT = 14, BODY_SHIFT = 45;  // entry < 2^14, node < 2^31
   __shared__ unsigned long long key[SI_MAX];
@@ -500,11 +509,7 @@ __device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre 
   __shared__ int nrec_total;
   __shared__ int bb[4];
   __shared__ int missing, shared_node;
-  const int npts = ctl->npts;
-  const int moving = ctl->si_moving;
-  const int rule = ctl->si_rule;
   const int per_pt = rule == 1 ? 4 : 1;  // stencil entries per point
-  const BodyDev B = ctl->body;
   const double co = moving ? cos(B.theta) : 1.0, sn = moving ? sin(B.theta) : 0.0;
   const int nent = npts * per_pt;
   int N = 4;  // >= per_pt, so every key slot below is written
@@ -527,12 +532,22 @@ __device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre 
     if (i < npts) {
       double px, py, n0, n1;
       unsigned long long body;
+      double ds;
       if (pre.ok && i == (int)threadIdx.x) {
         si_place(pre.a, pre.b, pre.c, pre.d, moving, B, co, sn, px, py, n0, n1);
         body = (unsigned long long)pre.body;
+        ds = pre.ds;
       } else {
         si_world(pts, maxp, i, moving, B, co, sn, px, py, n0, n1);
         body = (unsigned long long)pts[5 * maxp + i];
+        ds = stage ? pts[4 * maxp + i] : 0.0;
+      }
+      if (stage && i < stage_pts) {
+        stage[i] = px;
+        stage[stage_pts + i] = py;
+        stage[2 * stage_pts + i] = n0;
+        stage[3 * stage_pts + i] = n1;
+        stage[4 * stage_pts + i] = ds;
       }
       int node[4];
       double w[4];
@@ -584,8 +599,17 @@ __device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre 
     for (int k = j; k < N && key[k] != INVALID && group(k) == group(j); ++k) {
       const int e = (int)(key[k] & ((1u << NODE_SHIFT) - 1));
       const int i = e / per_pt;
-      double px, py, n0, n1;
-      si_world(pts, maxp, i, moving, B, co, sn, px, py, n0, n1);
+      double px, py, n0, n1, ds;
+      if (stage && i < stage_pts) {
+        px = stage[i];
+        py = stage[stage_pts + i];
+        n0 = stage[2 * stage_pts + i];
+        n1 = stage[3 * stage_pts + i];
+        ds = stage[4 * stage_pts + i];
+      } else {
+        si_world(pts, maxp, i, moving, B, co, sn, px, py, n0, n1);
+        ds = pts[4 * maxp + i];
+      }
       int nd[4];
       double w[4];
       si_stencil(solid, nx, ny, rule, px, py, n0, n1, nd, w);
@@ -594,7 +618,7 @@ __device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre 
 #pragma unroll
       for (int k = 1; k < 4; ++k)
         if (k == ke) we = w[k];  // register select (no indexed private array)
-      const double s = pts[4 * maxp + i] * we;
+      const double s = ds * we;
       const double rx = px - Bb.x, ry = py - Bb.y;
       ax += s * n0;
       ay += s * n1;
@@ -614,7 +638,11 @@ __device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre 
     // sample bit (a node sampled for two bodies would need two slots)
     unsigned *wd = (unsigned *)(mask + (cc & ~3LL));
     const unsigned bit = (unsigned)M_SAMPLE << (8 * (cc & 3));
-    if (atomicOr(wd, bit) & bit) atomicOr(&shared_node, 1);
+    if (check_shared) {
+      if (atomicOr(wd, bit) & bit) atomicOr(&shared_node, 1);
+    } else {
+      atomicOr(wd, bit);
+    }
     ++r;
   }
   __syncthreads();
@@ -629,13 +657,17 @@ __device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre 
     if (missing) ctl->err |= 1;
     if (shared_node) ctl->err |= 4;
     if (bb[2] >= 0) {
-      if (ctl->win[2] <= ctl->win[0] || ctl->win[3] <= ctl->win[1]) {
+      // the force window so far (win_now: the caller's copy of what it wrote)
+      int wn[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wn[k] = win_now ? win_now[k] : ctl->win[k];
+      if (wn[2] <= wn[0] || wn[3] <= wn[1]) {
         ctl->win[0] = bb[0]; ctl->win[1] = bb[1]; ctl->win[2] = bb[2] + 1; ctl->win[3] = bb[3] + 1;
       } else {
-        ctl->win[0] = min(ctl->win[0], bb[0]);
-        ctl->win[1] = min(ctl->win[1], bb[1]);
-        ctl->win[2] = max(ctl->win[2], bb[2] + 1);
-        ctl->win[3] = max(ctl->win[3], bb[3] + 1);
+        ctl->win[0] = min(wn[0], bb[0]);
+        ctl->win[1] = min(wn[1], bb[1]);
+        ctl->win[2] = max(wn[2], bb[2] + 1);
+        ctl->win[3] = max(wn[3], bb[3] + 1);
       }
     }
   }
@@ -645,7 +677,9 @@ __global__ void __launch_bounds__(SI_NT)
     k_si_select(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ pts,
                 int maxp, SiRec *__restrict__ recs, int *__restrict__ si_map, BodyTab *__restrict__ bt,
                 const BodyDev *__restrict__ bodies, int nx, int ny, int pitch) {
-  si_select_block(MaskSolid{mask, pitch}, PtPre{0.0, 0.0, 0.0, 0.0, 0.0, false}, mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch);
+  const BodyDev B = ctl->body;
+  si_select_block(MaskSolid{mask, pitch}, PtPre{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, false}, mask, ctl, pts, maxp, recs,
+                  si_map, bt, bodies, nx, ny, pitch, ctl->npts, ctl->si_moving, ctl->si_rule, B, nullptr, 0, true);
 }
 
 // ----------------------------------------------------------------------------
@@ -669,7 +703,11 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
   __shared__ int wsum[BODY_NT / 64];
   __shared__ int nslot;
   __shared__ double flast[6];  // forces of the step just taken (ME, SI)
-  __shared__ uint8_t inside[INSIDE_LDS];
+  __shared__ BodyDev Bnew;     // body state after the update
+  __shared__ int winsh[4];     // force window written by the update
+  // disk tests of the rebuild, then the points staged by the sample selection
+  __shared__ double lds_stage[INSIDE_LDS / sizeof(double)];
+  uint8_t *inside = (uint8_t *)lds_stage;
   // Loads that do not depend on the finalize, issued first so their latency
   // overlaps it: the control-block fields of the update (the finalize does
   // not write them) and this thread's stress-integration point.
@@ -678,11 +716,31 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
   const double mass = ctl->mass, inertia = ctl->inertia, buoy = ctl->buoy, cgx = ctl->gx, cgy = ctl->gy;
   const double crad = ctl->r;
   const int oreg0 = ctl->region[0], oreg1 = ctl->region[1], oreg2 = ctl->region[2], oreg3 = ctl->region[3];
-  const int npts0 = ctl->npts;
+  const int npts0 = ctl->npts, si_moving = ctl->si_moving, si_rule = ctl->si_rule;
   const PtPre pre = si_prefetch(pts, maxp, npts0);
+  // the finalize's first slot and record per virtual lane, loaded with the
+  // control block instead of after the slot ranges (the disk is body 1 and
+  // the only body: its ranges start at 0; records fit maxp at least)
+  FinPre fp;
+  fp.me_ok = false;
+  fp.rec_ok = false;
+  if (threadIdx.x < FIN_W) {
+    const int t = threadIdx.x;
+    if (t < maxslot) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) fp.me[i] = me[(long long)t * ME_STRIDE + i];
+      fp.me_ok = true;
+    }
+    if (t < maxp) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) fp.g[i] = sig[(long long)t * SIG_STRIDE + i];
+      fp.R = recs[t];
+      fp.rec_ok = true;
+    }
+  }
   // forces of the step just taken, needed by the update below (the only
   // body: a moving disk is alone in its lattice)
-  finalize_block<BODY_NT>(me, sig, recs, bt, ctl, hist, cap, maxb, lds, flast);
+  finalize_block<BODY_NT>(me, sig, recs, bt, ctl, hist, cap, maxb, lds, flast, &fp);
   __syncthreads();
   if (threadIdx.x == 0) {
     BodyDev B = B0;
@@ -697,6 +755,7 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
     B.y += B.v;
     B.theta += B.omega;
     ctl->body = B;
+    Bnew = B;
     const long long X = llround(B.x * FIXQ), Y = llround(B.y * FIXQ), R = llround(crad * FIXQ);
     ctl->fq[0] = X;
     ctl->fq[1] = Y;
@@ -717,14 +776,16 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
     for (int k = 0; k < 4; ++k) ctl->region[k] = nr[k];
     // force window: interface cells lie within one cell of the disk's box;
     // the sample-node selection extends it afterwards
-    ctl->win[0] = max(bx0 - 1, 0);
-    ctl->win[1] = max(by0 - 1, 0);
-    ctl->win[2] = min(bx1 + 1, nx);
-    ctl->win[3] = min(by1 + 1, ny);
-    if (ctl->win[2] <= ctl->win[0] || ctl->win[3] <= ctl->win[1]) {
+    int wn[4] = {max(bx0 - 1, 0), max(by0 - 1, 0), min(bx1 + 1, nx), min(by1 + 1, ny)};
+    if (wn[2] <= wn[0] || wn[3] <= wn[1]) {
       // body outside the lattice: keep a one-cell window so forces are still published
-      ctl->win[0] = ctl->win[1] = 0;
-      ctl->win[2] = ctl->win[3] = 1;
+      wn[0] = wn[1] = 0;
+      wn[2] = wn[3] = 1;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ctl->win[k] = wn[k];
+      winsh[k] = wn[k];
     }
   }
   __syncthreads();
@@ -818,7 +879,9 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
     __threadfence_block();
     __syncthreads();
     // the disk is the lattice's only body: its rule is the mask just built
-    si_select_block(DiskSolid{q[0], q[1], q[2]}, pre, mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch);
+    si_select_block(DiskSolid{q[0], q[1], q[2]}, pre, mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch,
+                    npts0, si_moving, si_rule, Bnew, lds_stage, (int)(INSIDE_LDS / sizeof(double) / 5), false,
+                    winsh);
   }
 }
 

@@ -305,18 +305,31 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], double *lds /*[NT/6
 constexpr int FIN_W = 256;
 constexpr int FIN_WAVES = FIN_W / 64;
 
+// The first ME slot and SI record of a thread's virtual lane v0 (slot and
+// record v0 of body 1's ranges, which start at 0 in a lattice with a single
+// body), loaded before the ranges are known so that the two loads do not
+// wait for one another.
+struct FinPre {
+  double me[3], g[3];
+  SiRec R;
+  bool me_ok, rec_ok;  // v0 within the slot / record capacity, values loaded
+};
+
 // Forces of one step -> its force-history slots, body by body
 // (deterministic: fixed assignment and order).  ME: the contributions the
 // interface cells stored in their slots.  SI: the stress each sample node
 // stored (sig), contracted with the node's aggregated weights, record by
 // record.  hist[(n mod cap) * maxb + b][6]; the control block keeps body 1's.
 // lds holds FIN_WAVES * 6 doubles; out0, when given (LDS, 6 doubles), gets
-// body 1's forces from thread 0.
+// body 1's forces from thread 0.  pre, when given, holds this thread's first
+// slot and record of body 1 (NT >= FIN_W: one virtual lane per thread); they
+// enter the sums exactly where the loads would have.
 template <int NT>
 __device__ __forceinline__ void finalize_block(const double *__restrict__ me, const double *__restrict__ sig,
                                                const SiRec *__restrict__ recs, const BodyTab *__restrict__ bt,
                                                Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb,
-                                               double *lds, double *out0 = nullptr) {
+                                               double *lds, double *out0 = nullptr,
+                                               const FinPre *pre = nullptr) {
   static_assert(NT % 64 == 0, "whole waves");
   const long long n = ctl->step + 1;
   const int nb = ctl->nbody;
@@ -327,11 +340,27 @@ __device__ __forceinline__ void finalize_block(const double *__restrict__ me, co
     for (int k = wave; k < FIN_WAVES; k += NT / 64) {
       const int v0 = k * 64 + lane;  // this thread's virtual lane
       double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      for (int r = T.me0 + v0; r < T.me1; r += FIN_W) {
+      const bool first = pre != nullptr && NT >= FIN_W && b == 0;
+      int r0 = T.me0 + v0;
+      if (first && T.me0 == 0 && r0 < T.me1 && pre->me_ok) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[i] += pre->me[i];
+        r0 += FIN_W;
+      }
+      for (int r = r0; r < T.me1; r += FIN_W) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) v[i] += me[(long long)r * ME_STRIDE + i];
       }
-      for (int r = T.rec0 + v0; r < T.rec1; r += FIN_W) {
+      int q0 = T.rec0 + v0;
+      if (first && T.rec0 == 0 && q0 < T.rec1 && pre->rec_ok) {
+        const double *g = pre->g;
+        const SiRec &R = pre->R;
+        v[3] += g[0] * R.ax + g[1] * R.ay;
+        v[4] += g[1] * R.ax + g[2] * R.ay;
+        v[5] += g[0] * R.txx + g[1] * R.txy + g[2] * R.tyy;
+        q0 += FIN_W;
+      }
+      for (int r = q0; r < T.rec1; r += FIN_W) {
         const double *g = sig + (long long)r * SIG_STRIDE;
         const SiRec R = recs[r];
         v[3] += g[0] * R.ax + g[1] * R.ay;
