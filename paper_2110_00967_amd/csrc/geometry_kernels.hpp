@@ -488,7 +488,8 @@ __device__ __forceinline__ void block_sort_keys(unsigned long long *key, int N) 
 // of k_body_step after the mask was rebuilt).  solid: the solid test the
 // sample-node search uses (see MaskSolid, DiskSolid).  npts, moving, rule
 // and B are the control block's point count, point frame flag, stencil rule
-// and body-1 state, passed in by the caller.  stage (LDS, 5 x stage_pts
+// and body-1 state, passed in by the caller with co, sn = cos, sin of
+// B.theta (1, 0 for points stored in the world frame).  stage (LDS, 5 x stage_pts
 // doubles, or null) keeps the world position, normal and length of points
 // below stage_pts from the key pass for the record pass.  check_shared:
 // flag a sample node claimed by two bodies (error bit 2); a lattice with a
@@ -499,8 +500,9 @@ __device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre 
                                 const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
                                 int *__restrict__ si_map, BodyTab *__restrict__ bt,
                                 const BodyDev *__restrict__ bodies, int nx, int ny, int pitch, const int npts,
-                                const int moving, const int rule, const BodyDev &B, double *stage, int stage_pts,
-                                bool check_shared, const int *win_now = nullptr) {
+                                const int moving, const int rule, const BodyDev &B, const double co,
+                                const double sn, double *stage, int stage_pts, bool check_shared,
+                                const int *win_now = nullptr) {
   // key = (body, node, entry): records come out grouped by body, then by node
   constexpr int NODE_SHIFT = 14, BODY_SHIFT = 45;  // entry < 2^14, node < 2^31
   __shared__ unsigned long long key[SI_MAX];
@@ -510,7 +512,6 @@ __device__ __forceinline__ void si_select_block(const Solid &solid, const PtPre 
   __shared__ int bb[4];
   __shared__ int missing, shared_node;
   const int per_pt = rule == 1 ? 4 : 1;  // stencil entries per point
-  const double co = moving ? cos(B.theta) : 1.0, sn = moving ? sin(B.theta) : 0.0;
   const int nent = npts * per_pt;
   int N = 4;  // >= per_pt, so every key slot below is written
   while (N < nent) N <<= 1;
@@ -678,8 +679,10 @@ __global__ void __launch_bounds__(SI_NT)
                 int maxp, SiRec *__restrict__ recs, int *__restrict__ si_map, BodyTab *__restrict__ bt,
                 const BodyDev *__restrict__ bodies, int nx, int ny, int pitch) {
   const BodyDev B = ctl->body;
+  const int moving = ctl->si_moving;
+  const double co = moving ? cos(B.theta) : 1.0, sn = moving ? sin(B.theta) : 0.0;
   si_select_block(MaskSolid{mask, pitch}, PtPre{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, false}, mask, ctl, pts, maxp, recs,
-                  si_map, bt, bodies, nx, ny, pitch, ctl->npts, ctl->si_moving, ctl->si_rule, B, nullptr, 0, true);
+                  si_map, bt, bodies, nx, ny, pitch, ctl->npts, moving, ctl->si_rule, B, co, sn, nullptr, 0, true);
 }
 
 // ----------------------------------------------------------------------------
@@ -704,6 +707,7 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
   __shared__ int nslot;
   __shared__ double flast[6];  // forces of the step just taken (ME, SI)
   __shared__ BodyDev Bnew;     // body state after the update
+  __shared__ double cs[2];     // cos, sin of its angle (for points in the body frame)
   __shared__ int winsh[4];     // force window written by the update
   // disk tests of the rebuild, then the points staged by the sample selection
   __shared__ double lds_stage[INSIDE_LDS / sizeof(double)];
@@ -787,6 +791,14 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
       ctl->win[k] = wn[k];
       winsh[k] = wn[k];
     }
+  } else if (threadIdx.x == 64) {
+    // the new angle as thread 0 forms it, and its cos and sin (in another
+    // wave, in parallel with the update)
+    double om = B0.omega;
+    if (mode == MODE_FREE) om += flast[3 * source + 2] / inertia;
+    const double th = B0.theta + om;
+    cs[0] = si_moving ? cos(th) : 1.0;
+    cs[1] = si_moving ? sin(th) : 0.0;
   }
   __syncthreads();
   const int x0 = reg[0], y0 = reg[1], w = reg[2] - reg[0], h = reg[3] - reg[1];
@@ -880,8 +892,8 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
     __syncthreads();
     // the disk is the lattice's only body: its rule is the mask just built
     si_select_block(DiskSolid{q[0], q[1], q[2]}, pre, mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch,
-                    npts0, si_moving, si_rule, Bnew, lds_stage, (int)(INSIDE_LDS / sizeof(double) / 5), false,
-                    winsh);
+                    npts0, si_moving, si_rule, Bnew, cs[0], cs[1], lds_stage,
+                    (int)(INSIDE_LDS / sizeof(double) / 5), false, winsh);
   }
 }
 
