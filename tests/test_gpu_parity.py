@@ -167,6 +167,28 @@ def test_prescribed_motion_galilean_fp64():
     assert abs(g.body_state()[0] - (20.0 + 60 * U[0])) < 1e-12
 
 
+@pytest.mark.parametrize("npts,rule", [(1000, 0), (300, 1)])
+def test_rotating_translating_disk_many_points_fp64(npts, rule):
+    # a spinning, translating disk with many points: the sample selection
+    # after each move sorts more than 256 keys (bitonic network) and, with
+    # 1000 points, reads the points beyond its LDS staging from memory
+    U, om = (0.02, -0.015), 0.01
+    s = spec(96, 80, tau=0.68, eta=1e-3, disk=(40.0, 44.0, 12.5), si_rule=rule,
+             si=W.disk_si_points(40.0, 44.0, 12.5, npts), motion=(40.0, 44.0, 0.3, U[0], U[1], om),
+             init=("fields",) + random_fields(96, 80, 29, amp=0.01))
+    say(f"rotating disk 96x80 fp64, {npts} points, rule {rule}")
+    g = build_gpu(s)
+    o = build_oracle(s)
+    for k in range(3):
+        g.step(15)
+        o.step(15)
+        compare_fp64(g, o, f"rotating disk after {g.step_count}")
+        sample = np.zeros(o.nx * o.ny, bool)
+        sample[o.si_node] = True
+        assert np.array_equal((g.mask().ravel() & 0x40) != 0, sample)
+    assert np.abs(g.body_state()[2] - (0.3 + 45 * om)) < 1e-12
+
+
 @pytest.mark.parametrize("rule", [0, 1])
 def test_si_at_matches_registered_points(rule):
     import dataclasses
