@@ -235,10 +235,12 @@ int vplbm_step_timed(vplbm_lattice *lat, int nsteps, int flags, double *kernel_m
 int vplbm_sync(vplbm_lattice *lat);
 long long vplbm_step_count(const vplbm_lattice *lat);
 /* Workgroup tile of the step kernel, bx cells along x times by rows:
- * 64x1, 64x2, 64x4 (default), 128x1, 128x2 or 256x1.  Results do not depend
- * on it, forces included: they are summed per interface cell and per sample
- * record, in an order fixed at geometry set-up.  A lattice with
- * VPLBM_STREAM_AA accepts 64x4 only (VPLBM_EINVAL otherwise). */
+ * 64x1, 64x2, 64x4, 128x1, 128x2 or 256x1.  The default is 64x4 while the
+ * two population buffers fit in 256 MB (the Infinity Cache), else 128x2.
+ * Results do not depend on it, forces included: they are summed per
+ * interface cell and per sample record, in an order fixed at geometry
+ * set-up.  A lattice with VPLBM_STREAM_AA accepts 64x4 only (VPLBM_EINVAL
+ * otherwise).  Batched launches use 64x4 tiles whatever this setting. */
 int vplbm_set_tile(vplbm_lattice *lat, int bx, int by);
 
 /* Forces of the last step, out = (Fx, Fy, Tz) on the body, torque about the
@@ -293,8 +295,8 @@ int vplbm_read_mask(vplbm_lattice *lat, uint8_t *out);
  * are replayed from a captured HIP graph. */
 typedef struct vplbm_batch vplbm_batch;
 
-/* All lattices must share the precision, the collision (BGK or TRT), the
- * HIP stream and the default 64x4 tile, and use VPLBM_STREAM_AB storage
+/* All lattices must share the precision, the collision (BGK or TRT) and the
+ * HIP stream, and use VPLBM_STREAM_AB storage
  * (VPLBM_EINVAL otherwise); a lattice appears once.  The handles stay owned by the caller
  * and must outlive the batch; they must not be stepped concurrently. */
 int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out);

@@ -748,6 +748,13 @@ int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *h
   L->maxv = p->max_vertices > 0 ? p->max_vertices : DEFAULT_VERTS;
   L->maxb = max_bodies_of(*p);
   L->maxslot = max_slots_of(*p);
+  // default step tile: 64x4 while both population buffers fit the 256 MB
+  // Infinity Cache, 128x2 beyond it (the faster shape on either side, as
+  // measured on MI355X); the AA pattern runs with 64x4
+  if (!L->aa() && 2.0 * 9.0 * (double)elem_size(p->precision) * (double)L->plane > 256.0 * (1 << 20)) {
+    L->bx = 128;
+    L->by = 2;
+  }
   if (dev_mem) {
     if (dev_bytes < L->L.total || ((uintptr_t)dev_mem % ALIGN) != 0) {
       g_create_err = "device buffer smaller than vplbm_required_bytes or not 256-byte aligned";
@@ -1576,7 +1583,7 @@ void fill_desc(vplbm_lattice *L, int tile0, void *out) {
   d.pbit0 = (int)((L->nstep + 1) & 1);
   d.pending0 = L->pending ? 1 : 0;
   d.moving = L->mode != MODE_STATIC ? 1 : 0;
-  d.tw = L->bx;
+  d.tw = 64;  // batched launches run 64x4 tiles, whatever tile the lattice runs alone
   d.by = L->by;
   d.perx = (int)L->periodic_x();
   d.pery = (int)L->periodic_y();
@@ -1620,7 +1627,6 @@ int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out) {
   for (int k = 0; k < n; ++k) {
     if (!lats[k] || lats[k]->p.precision != prec || lats[k]->stream != lats[0]->stream) return VPLBM_EINVAL;
     if ((lats[k]->p.trt_lambda > 0.0) != (lats[0]->p.trt_lambda > 0.0)) return VPLBM_EINVAL;
-    if (lats[k]->bx != 64 || lats[k]->by != 4) return VPLBM_EINVAL;  // batched launches use the 64x4 tile
     if (lats[k]->aa()) return lats[k]->fail(VPLBM_EINVAL, "a batch takes two-buffer (AB) lattices only");
     for (int j = 0; j < k; ++j)
       if (lats[j] == lats[k]) return VPLBM_EINVAL;

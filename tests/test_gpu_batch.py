@@ -167,3 +167,31 @@ def test_one_lattice_batch_moving_disk_equals_eager_steps():
     bt.close()
     a.close()
     b.close()
+
+
+def test_lattice_beyond_the_cache_default_tile_and_batch():
+    # two FP32 buffers of 2048 x 2048 exceed 256 MB: the lattice steps with
+    # 128x2 tiles by default, and a batch still takes it (batched launches
+    # use 64x4 tiles); all three runs give the same bits
+    from paper_2110_00967_amd import vplbm as V
+    nx = ny = 2048
+    s = spec(nx, ny, tau=0.6, edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)), disk=(500.3, 1024.6, 40.2),
+             si=W.disk_si_points(500.3, 1024.6, 40.2, 256), init=("uniform", 1.0, 0.05, 0.0))
+    say("2048x2048 fp32: default tile, 64x4 tile, batch")
+    runs = []
+    for mode in ("default", "64x4", "batch"):
+        g = build_gpu(s, "f32")
+        if mode == "64x4":
+            g.set_tile(64, 4)
+        if mode == "batch":
+            b = V.Batch([g])
+            b.step([12])
+            b.close()
+        else:
+            g.step(12)
+        g.step(1, macro=True)
+        runs.append([*g.macro(), g.history(0), g.history(1)])
+        g.close()
+    for r in runs[1:]:
+        for a, b_ in zip(r, runs[0]):
+            assert np.array_equal(a, b_)
