@@ -247,7 +247,10 @@ struct vplbm_lattice {
   bool periodic_x() const { return p.west.kind == VPLBM_BC_PERIODIC; }
   bool periodic_y() const { return p.south.kind == VPLBM_BC_PERIODIC; }
 
-  template <typename T> StepArgs<T> step_args() const {
+  // arguments of a step launch with tiles of tbx x tby cells (by default the
+  // lattice's own tile; batched launches pass 64x4)
+  template <typename T> StepArgs<T> step_args(int tbx = 0, int tby = 0) const {
+    const int bx = tbx > 0 ? tbx : this->bx, by = tby > 0 ? tby : this->by;
     StepArgs<T> a{};
     a.nx = p.nx;
     a.ny = p.ny;
@@ -1557,11 +1560,14 @@ size_t desc_size_of(int prec) {
   return prec == VPLBM_F64 ? desc_size<double>() : (prec == VPLBM_F32 ? desc_size<float>() : desc_size<__half>());
 }
 
+// tile of the batched step kernel (k_step_batch is instantiated for it only)
+constexpr int BATCH_BX = 64, BATCH_BY = 4;
+
 template <typename S>
 void fill_desc(vplbm_lattice *L, int tile0, void *out) {
   using T = typename Store<S>::T;
   CaseDesc<T> d{};
-  d.P = L->step_args<T>();
+  d.P = L->step_args<T>(BATCH_BX, BATCH_BY);
   d.buf[0] = L->at(L->L.A);
   d.buf[1] = L->at(L->L.B);
   d.mask = L->mask();
@@ -1583,8 +1589,8 @@ void fill_desc(vplbm_lattice *L, int tile0, void *out) {
   d.pbit0 = (int)((L->nstep + 1) & 1);
   d.pending0 = L->pending ? 1 : 0;
   d.moving = L->mode != MODE_STATIC ? 1 : 0;
-  d.tw = 64;  // batched launches run 64x4 tiles, whatever tile the lattice runs alone
-  d.by = L->by;
+  d.tw = BATCH_BX;  // batched launches run 64x4 tiles, whatever tile the lattice runs alone
+  d.by = BATCH_BY;
   d.perx = (int)L->periodic_x();
   d.pery = (int)L->periodic_y();
   d.maxp = L->maxp;
@@ -1598,11 +1604,12 @@ void launch_batch_pair(vplbm_batch *B, hipStream_t st, int nact, int total, int 
   (void)nact;
   const int per = (total + 7) / 8;
   const auto *descs = (const CaseDesc<T> *)B->desc_dev;
+  const dim3 grid(8 * per), block(BATCH_BX * BATCH_BY);
   if (B->trt)
-    hipLaunchKernelGGL((k_step_batch<S, 64, 4, true>), dim3(8 * per), dim3(256), 0, st, descs, B->tile_case_dev,
+    hipLaunchKernelGGL((k_step_batch<S, BATCH_BX, BATCH_BY, true>), grid, block, 0, st, descs, B->tile_case_dev,
                        total, per, flip, first);
   else
-    hipLaunchKernelGGL((k_step_batch<S, 64, 4, false>), dim3(8 * per), dim3(256), 0, st, descs, B->tile_case_dev,
+    hipLaunchKernelGGL((k_step_batch<S, BATCH_BX, BATCH_BY, false>), grid, block, 0, st, descs, B->tile_case_dev,
                        total, per, flip, first);
   if (nmov)
     hipLaunchKernelGGL((k_body_step_batch<T>), dim3(nmov), dim3(BODY_NT), 0, st, descs, B->moving_dev, flip);
@@ -1696,7 +1703,7 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
       vplbm_lattice *L = B->cases[act[i]];
       rc = resolve_pwin(L);
       if (rc) return B->fail(rc, "lattice " + std::to_string(act[i]) + ": " + L->err);
-      const int tiles = L->step_args<float>().ntiles;
+      const int tiles = L->step_args<float>(BATCH_BX, BATCH_BY).ntiles;
       switch (B->prec) {
         case VPLBM_F64: fill_desc<double>(L, total, &B->desc_host[i * dsz]); break;
         case VPLBM_F32: fill_desc<float>(L, total, &B->desc_host[i * dsz]); break;
@@ -1708,7 +1715,7 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
     const int nact = (int)act.size();
     B->tile_case_host.resize(total);
     for (int i = 0, t = 0; i < nact; ++i) {
-      const int tiles = B->cases[act[i]]->step_args<float>().ntiles;
+      const int tiles = B->cases[act[i]]->step_args<float>(BATCH_BX, BATCH_BY).ntiles;
       for (int j = 0; j < tiles; ++j) B->tile_case_host[t++] = i;
     }
     if ((size_t)total > B->tile_case_cap) {

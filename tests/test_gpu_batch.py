@@ -175,8 +175,10 @@ def test_lattice_beyond_the_cache_default_tile_and_batch():
     # use 64x4 tiles); all three runs give the same bits
     from paper_2110_00967_amd import vplbm as V
     nx = ny = 2048
-    s = spec(nx, ny, tau=0.6, edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)), disk=(500.3, 1024.6, 40.2),
-             si=W.disk_si_points(500.3, 1024.6, 40.2, 256), init=("uniform", 1.0, 0.05, 0.0))
+    # random fields: every cell changes at every step, so a tile left out
+    # anywhere shows in the comparison
+    s = spec(nx, ny, tau=0.6, edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)), disk=(1500.3, 1024.6, 40.2),
+             si=W.disk_si_points(1500.3, 1024.6, 40.2, 256), init=("fields",) + random_fields(nx, ny, 7, amp=0.03))
     say("2048x2048 fp32: default tile, 64x4 tile, batch")
     runs = []
     for mode in ("default", "64x4", "batch"):
@@ -190,8 +192,13 @@ def test_lattice_beyond_the_cache_default_tile_and_batch():
         else:
             g.step(12)
         g.step(1, macro=True)
-        runs.append([*g.macro(), g.history(0), g.history(1)])
+        runs.append([g.populations(), *g.macro(), g.history(0), g.history(1)])
         g.close()
     for r in runs[1:]:
         for a, b_ in zip(r, runs[0]):
             assert np.array_equal(a, b_)
+    # and the run moved every cell away from its initial state
+    g = build_gpu(s, "f32")
+    first = g.populations()
+    g.close()
+    assert (runs[0][0] != first).any(axis=0).mean() > 0.99
