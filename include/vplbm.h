@@ -235,8 +235,8 @@ int vplbm_step_timed(vplbm_lattice *lat, int nsteps, int flags, double *kernel_m
 int vplbm_sync(vplbm_lattice *lat);
 long long vplbm_step_count(const vplbm_lattice *lat);
 /* Workgroup tile of the step kernel, bx cells along x times by rows:
- * 64x1, 64x2, 64x4, 128x1, 128x2 or 256x1.  The default is 64x4 while the
- * two population buffers fit in 256 MB (the Infinity Cache), else 128x2.
+ * 64x1, 64x2, 64x4, 128x1, 128x2 or 256x1.  The default is 64x4, or 128x2
+ * when the two population buffers exceed 1 GiB (FP64: 256 MB).
  * Results do not depend on it, forces included: they are summed per
  * interface cell and per sample record, in an order fixed at geometry
  * set-up.  A lattice with VPLBM_STREAM_AA accepts 64x4 only (VPLBM_EINVAL

@@ -751,10 +751,13 @@ int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *h
   L->maxv = p->max_vertices > 0 ? p->max_vertices : DEFAULT_VERTS;
   L->maxb = max_bodies_of(*p);
   L->maxslot = max_slots_of(*p);
-  // default step tile: 64x4 while both population buffers fit the 256 MB
-  // Infinity Cache, 128x2 beyond it (the faster shape on either side, as
-  // measured on MI355X); the AA pattern runs with 64x4
-  if (!L->aa() && 2.0 * 9.0 * (double)elem_size(p->precision) * (double)L->plane > 256.0 * (1 << 20)) {
+  // default step tile, the faster shape as measured on MI355X: 64x4, or
+  // 128x2 for population buffers far beyond the 256 MB Infinity Cache (over
+  // 1 GiB; FP64, at 6 waves per SIMD, from 256 MB).  The AA pattern runs
+  // with 64x4.
+  const double pop_bytes = 2.0 * 9.0 * (double)elem_size(p->precision) * (double)L->plane;
+  const double wide_from = (p->precision == VPLBM_F64 ? 256.0 : 1024.0) * (1 << 20);
+  if (!L->aa() && pop_bytes > wide_from) {
     L->bx = 128;
     L->by = 2;
   }

@@ -170,19 +170,19 @@ def test_one_lattice_batch_moving_disk_equals_eager_steps():
 
 
 def test_lattice_beyond_the_cache_default_tile_and_batch():
-    # two FP32 buffers of 2048 x 2048 exceed 256 MB: the lattice steps with
-    # 128x2 tiles by default, and a batch still takes it (batched launches
-    # use 64x4 tiles); all three runs give the same bits
+    # two FP64 buffers of 2048 x 2048 (604 MB) exceed 256 MB: the lattice
+    # steps with 128x2 tiles by default, and a batch still takes it (batched
+    # launches use 64x4 tiles); all three runs give the same bits
     from paper_2110_00967_amd import vplbm as V
     nx = ny = 2048
     # random fields: every cell changes at every step, so a tile left out
     # anywhere shows in the comparison
     s = spec(nx, ny, tau=0.6, edges=((V_, 0.05, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)), disk=(1500.3, 1024.6, 40.2),
              si=W.disk_si_points(1500.3, 1024.6, 40.2, 256), init=("fields",) + random_fields(nx, ny, 7, amp=0.03))
-    say("2048x2048 fp32: default tile, 64x4 tile, batch")
+    say("2048x2048 fp64: default tile, 64x4 tile, batch")
     runs = []
     for mode in ("default", "64x4", "batch"):
-        g = build_gpu(s, "f32")
+        g = build_gpu(s, "f64")
         if mode == "64x4":
             g.set_tile(64, 4)
         if mode == "batch":
@@ -198,7 +198,7 @@ def test_lattice_beyond_the_cache_default_tile_and_batch():
         for a, b_ in zip(r, runs[0]):
             assert np.array_equal(a, b_)
     # and the run moved every cell away from its initial state
-    g = build_gpu(s, "f32")
+    g = build_gpu(s, "f64")
     first = g.populations()
     g.close()
     assert (runs[0][0] != first).any(axis=0).mean() > 0.99
