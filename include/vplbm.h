@@ -242,6 +242,8 @@ long long vplbm_step_count(const vplbm_lattice *lat);
  * set-up.  A lattice with VPLBM_STREAM_AA accepts 64x4 only (VPLBM_EINVAL
  * otherwise).  Batched launches use 64x4 tiles whatever this setting. */
 int vplbm_set_tile(vplbm_lattice *lat, int bx, int by);
+/* The tile the lattice's own steps use (*bx cells along x, *by rows). */
+int vplbm_get_tile(const vplbm_lattice *lat, int *bx, int *by);
 
 /* Forces of the last step, out = (Fx, Fy, Tz) on the body, torque about the
  * reference point.  Momentum exchange of step n is evaluated on the

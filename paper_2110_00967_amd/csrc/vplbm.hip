@@ -1325,6 +1325,13 @@ int vplbm_set_tile(vplbm_lattice *L, int bx, int by) {
   return VPLBM_OK;
 }
 
+int vplbm_get_tile(const vplbm_lattice *L, int *bx, int *by) {
+  if (!L || !bx || !by) return VPLBM_EINVAL;
+  *bx = L->bx;
+  *by = L->by;
+  return VPLBM_OK;
+}
+
 static int read_last(vplbm_lattice *L, int which, double out[3]) {
   if (!L || !out) return VPLBM_EINVAL;
   {

@@ -34,7 +34,8 @@ EXPORTS = [
     "vplbm_required_bytes", "vplbm_create", "vplbm_destroy", "vplbm_last_error", "vplbm_init_uniform",
     "vplbm_set_fields", "vplbm_set_body_force", "vplbm_set_body_disk", "vplbm_set_body_polygon",
     "vplbm_set_mask", "vplbm_set_body_motion", "vplbm_set_body_dynamics", "vplbm_set_si_points",
-    "vplbm_step", "vplbm_step_timed", "vplbm_sync", "vplbm_step_count", "vplbm_set_tile", "vplbm_forces_me", "vplbm_forces_si",
+    "vplbm_step", "vplbm_step_timed", "vplbm_sync", "vplbm_step_count", "vplbm_set_tile",
+    "vplbm_get_tile", "vplbm_forces_me", "vplbm_forces_si",
     "vplbm_forces_si_at", "vplbm_force_history", "vplbm_get_body_state", "vplbm_read_macro",
     "vplbm_read_populations", "vplbm_read_mask", "vplbm_read_macro_window", "vplbm_read_populations_window",
     "vplbm_batch_create", "vplbm_batch_destroy", "vplbm_batch_last_error", "vplbm_batch_step",
@@ -109,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     L.vplbm_step_count.argtypes = [vp]
     L.vplbm_step_count.restype = C.c_longlong
     L.vplbm_set_tile.argtypes = [vp, ip, ip]
+    L.vplbm_get_tile.argtypes = [vp, P(C.c_int), P(C.c_int)]
     L.vplbm_forces_me.argtypes = [vp, dp]
     L.vplbm_forces_si.argtypes = [vp, dp]
     L.vplbm_forces_si_at.argtypes = [vp, dp, dp, dp, ip, dp]
@@ -295,6 +297,13 @@ class Lattice:
 
     def set_tile(self, bx, by):
         self._chk(self._lib.vplbm_set_tile(self._h, int(bx), int(by)))
+
+    @property
+    def tile(self):
+        """(bx, by): the step tile this lattice's own steps use."""
+        bx, by = C.c_int(0), C.c_int(0)
+        self._chk(self._lib.vplbm_get_tile(self._h, C.byref(bx), C.byref(by)))
+        return bx.value, by.value
 
     @property
     def step_count(self):

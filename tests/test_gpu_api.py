@@ -47,3 +47,19 @@ def test_divergence_is_reported(precision):
     g.step(50)
     g.sync()
     g.close()
+
+
+def test_default_tile_follows_the_footprint():
+    # 64x4 unless the two population buffers exceed 1 GiB (FP64: 256 MB);
+    # the AA pattern always runs 64x4
+    from paper_2110_00967_amd import vplbm as V
+    say("default step tile by footprint")
+    cases = [((2000, 1000, "f32", 0), (64, 4)),    # 146 MB
+             ((2000, 1000, "f64", 0), (128, 2)),   # 292 MB
+             ((1600, 1000, "f64", 0), (64, 4)),    # 234 MB
+             ((6000, 6000, "f32", 0), (128, 2)),   # 2.6 GB
+             ((6000, 6000, "f32", 1), (64, 4))]    # AA
+    for (nx, ny, prec, aa), tile in cases:
+        g = V.Lattice(V.make_params(nx, ny, 0.6, 1e-3, 1.0, prec, streaming=aa))
+        assert g.tile == tile, (nx, ny, prec, aa, g.tile)
+        g.close()

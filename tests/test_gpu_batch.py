@@ -183,8 +183,10 @@ def test_lattice_beyond_the_cache_default_tile_and_batch():
     runs = []
     for mode in ("default", "64x4", "batch"):
         g = build_gpu(s, "f64")
+        assert g.tile == (128, 2)  # 604 MB of FP64 populations
         if mode == "64x4":
             g.set_tile(64, 4)
+            assert g.tile == (64, 4)
         if mode == "batch":
             b = V.Batch([g])
             b.step([12])
