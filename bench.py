@@ -86,7 +86,8 @@ def run_sweep(args, torch, W, V, paper=False):
     cases (chords 100/150/200, AoA 0-20 deg).  paper: the paper's full-scale
     runs, chord 278 on 3614 x 1946, TRT, AoA 0-28 deg in steps of 2."""
     cases = W.paper_aoa_sweep() if paper else W.sweep_cases()
-    lats = [V.Lattice.from_case(c, precision=args.precision) for c in cases]
+    st = V.STREAM_AA if args.streaming == "aa" else V.STREAM_AB
+    lats = [V.Lattice.from_case(c, precision=args.precision, streaming=st) for c in cases]
     cells = sum(c.nx * c.ny for c in cases)
     batch = V.Batch(lats)
     n = len(lats)
@@ -115,11 +116,12 @@ def run_sweep(args, torch, W, V, paper=False):
         config = {"workload": "naca0012_paper_c278_3614x1946_trt_aoa_sweep", "cases": n, "cells": cells,
                   "chord": 278, "aoa_deg": [0.0, 2.0 * (n - 1)],
                   "tau": 0.55, "trt_lambda": round(1.0 / 6.0, 6), "eta": 1e-6, "si_points": len(cases[0].si_ds),
-                  "storage": args.precision, "parallelism": "single GPU, one batched launch per step"}
+                  "storage": args.precision, "streaming": args.streaming.upper(),
+                  "parallelism": "single GPU, one batched launch per step"}
     else:
         config = {"workload": "naca0012_aoa_sweep_64cases", "cases": n, "cells": cells,
                   "chords": [100, 150, 200], "aoa_deg": [0.0, 20.0], "storage": args.precision,
-                  "parallelism": "single GPU, one batched launch per step"}
+                  "streaming": args.streaming.upper(), "parallelism": "single GPU, one batched launch per step"}
     out = {
         "metric": METRIC, "value": round(cells / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
@@ -156,7 +158,8 @@ def run_sed_paper(args, torch, W, V):
     --sed-seconds > 0 also runs the cases to that physical time and reports
     each disk's trajectory every 0.1 s."""
     cases = W.paper_sedimentation_sweep(force_source=1) + W.paper_sedimentation_sweep(force_source=0)
-    lats = [V.Lattice.from_case(c, precision=args.precision) for c in cases]
+    st = V.STREAM_AA if args.streaming == "aa" else V.STREAM_AB
+    lats = [V.Lattice.from_case(c, precision=args.precision, streaming=st) for c in cases]
     cells = sum(c.nx * c.ny for c in cases)
     batch = V.Batch(lats)
     n = len(lats)
@@ -208,6 +211,7 @@ def run_sed_paper(args, torch, W, V):
         "config": {"workload": "sediment_paper_d26_104x1040_3ratios_SI_and_ME", "cases": n, "cells": cells,
                    "rho_r": list(W.PAPER_SED_RATIOS), "tau": 0.6, "eta": 1e-6, "g_lattice": g,
                    "si_points": len(cases[0].si_ds), "force_source": ["SI", "ME"], "storage": args.precision,
+                   "streaming": args.streaming.upper(),
                    "parallelism": "single GPU, one batched step and one batched body launch per step"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_step_batch",

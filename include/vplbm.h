@@ -111,7 +111,8 @@ typedef struct {
                         (half the population memory, the same bytes moved
                         per cell update, the same arithmetic per cell: the
                         results agree with VPLBM_STREAM_AB to rounding).
-                        AA runs with the 64x4 tile only and not in a batch */
+                        AA runs with the 64x4 tile only; a batch takes
+                        AA lattices when all of its lattices are AA */
 } vplbm_params;
 
 enum {
@@ -297,9 +298,9 @@ int vplbm_read_mask(vplbm_lattice *lat, uint8_t *out);
  * are replayed from a captured HIP graph. */
 typedef struct vplbm_batch vplbm_batch;
 
-/* All lattices must share the precision, the collision (BGK or TRT) and the
- * HIP stream, and use VPLBM_STREAM_AB storage
- * (VPLBM_EINVAL otherwise); a lattice appears once.  The handles stay owned by the caller
+/* All lattices must share the precision, the collision (BGK or TRT), the
+ * HIP stream and the storage scheme (all VPLBM_STREAM_AB or all
+ * VPLBM_STREAM_AA; VPLBM_EINVAL otherwise); a lattice appears once.  The handles stay owned by the caller
  * and must outlive the batch; they must not be stepped concurrently. */
 int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out);
 int vplbm_batch_destroy(vplbm_batch *b);

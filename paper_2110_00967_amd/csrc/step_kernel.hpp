@@ -704,6 +704,8 @@ template <typename T> struct CaseDesc {
   // body-kernel arguments
   int tw, by, perx, pery, maxp, maxslot;
   const double *pts;
+  // AA pattern: the perimeter copies kept by the steps of parity 0 and 1
+  void *ec[2];
 };
 
 // Batched step: launch number `flip` (0 or 1, alternating) of a run over
@@ -726,6 +728,36 @@ __global__ void __launch_bounds__(BX *BY, step_waves<S>())
   step_tile<S, BX, BY, false, TRT, 0>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map, C->imap,
                                    C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1], fin_prev, C->hist,
                                    C->cap, C->maxb, nullptr, nullptr, nullptr);
+}
+
+// Batched step of lattices in the AA pattern (one population buffer each):
+// the launch computing an odd step pulls and pushes (AA = 1), an even step
+// stays in the cell (AA = 2), per lattice by its own step parity; the
+// perimeter copies alternate with it (read: the previous step's, written:
+// this step's).
+template <typename S, bool TRT>
+__global__ void __launch_bounds__(256, step_waves<S>())
+    k_step_batch_aa(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
+                    const int *__restrict__ tile_case, int total_tiles, int per_xcd, int flip, int first) {
+  using T = typename Store<S>::T;
+  const int b = blockIdx.x;
+  const int gtile = (b & 7) * per_xcd + (b >> 3);
+  if (gtile >= total_tiles) return;
+  const CaseDesc<T> *__restrict__ C = cases + tile_case[gtile];
+  StepArgs<T> P = C->P;
+  const int pb = C->pbit0 ^ flip;
+  P.ec_in = C->ec[pb ^ 1];
+  P.ec_out = C->ec[pb];
+  const int fin_prev = C->moving ? 0 : (first ? C->pending0 : 1);
+  S *F = (S *)C->buf[0];
+  if (pb)
+    step_tile<S, 64, 4, false, TRT, 1>(gtile - C->tile0, nullptr, F, C->mask, P, C->ctl, C->recs, C->si_map,
+                                       C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
+                                       fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr);
+  else
+    step_tile<S, 64, 4, false, TRT, 2>(gtile - C->tile0, nullptr, F, C->mask, P, C->ctl, C->recs, C->si_map,
+                                       C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
+                                       fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr);
 }
 
 template <int NT>

@@ -1543,6 +1543,7 @@ struct vplbm_batch {
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
   int prec = 0;
   bool trt = false;  // collision of every lattice of the batch
+  bool aa = false;   // storage scheme of every lattice of the batch
   char *desc_dev = nullptr;
   int *moving_dev = nullptr;
   int *tile_case_dev = nullptr;  // lattice index of every global tile
@@ -1605,6 +1606,8 @@ void fill_desc(vplbm_lattice *L, int tile0, void *out) {
   d.pery = (int)L->periodic_y();
   d.maxp = L->maxp;
   d.pts = (const double *)L->at(L->L.pts);
+  d.ec[0] = L->aa() ? L->ec(0) : nullptr;
+  d.ec[1] = L->aa() ? L->ec(1) : nullptr;
   std::memcpy(out, &d, sizeof d);
 }
 
@@ -1615,7 +1618,15 @@ void launch_batch_pair(vplbm_batch *B, hipStream_t st, int nact, int total, int 
   const int per = (total + 7) / 8;
   const auto *descs = (const CaseDesc<T> *)B->desc_dev;
   const dim3 grid(8 * per), block(BATCH_BX * BATCH_BY);
-  if (B->trt)
+  static_assert(BATCH_BX * BATCH_BY == 256, "k_step_batch_aa runs 64x4 tiles");
+  if (B->aa) {
+    if (B->trt)
+      hipLaunchKernelGGL((k_step_batch_aa<S, true>), grid, block, 0, st, descs, B->tile_case_dev, total, per, flip,
+                         first);
+    else
+      hipLaunchKernelGGL((k_step_batch_aa<S, false>), grid, block, 0, st, descs, B->tile_case_dev, total, per, flip,
+                         first);
+  } else if (B->trt)
     hipLaunchKernelGGL((k_step_batch<S, BATCH_BX, BATCH_BY, true>), grid, block, 0, st, descs, B->tile_case_dev,
                        total, per, flip, first);
   else
@@ -1644,7 +1655,8 @@ int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out) {
   for (int k = 0; k < n; ++k) {
     if (!lats[k] || lats[k]->p.precision != prec || lats[k]->stream != lats[0]->stream) return VPLBM_EINVAL;
     if ((lats[k]->p.trt_lambda > 0.0) != (lats[0]->p.trt_lambda > 0.0)) return VPLBM_EINVAL;
-    if (lats[k]->aa()) return lats[k]->fail(VPLBM_EINVAL, "a batch takes two-buffer (AB) lattices only");
+    if (lats[k]->aa() != lats[0]->aa())
+      return lats[k]->fail(VPLBM_EINVAL, "a batch takes lattices of one storage scheme (all AB or all AA)");
     for (int j = 0; j < k; ++j)
       if (lats[j] == lats[k]) return VPLBM_EINVAL;
   }
@@ -1654,6 +1666,7 @@ int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out) {
   B->stream = lats[0]->stream;
   B->prec = prec;
   B->trt = lats[0]->p.trt_lambda > 0.0;
+  B->aa = lats[0]->aa();
   B->desc_host.assign(desc_size_of(prec) * n, 0);
   B->moving_host.assign(n, 0);
   if (hipMalloc((void **)&B->desc_dev, B->desc_host.size()) != hipSuccess ||

@@ -398,7 +398,8 @@ class Batch:
         h = C.c_void_p()
         rc = self._lib.vplbm_batch_create(arr, len(self.lattices), C.byref(h))
         if rc != OK:
-            raise VplbmError(rc, "vplbm_batch_create failed (same precision, stream and default tile required)")
+            raise VplbmError(rc, "vplbm_batch_create failed (same precision, collision, stream and storage "
+                                 "scheme required)")
         self._h = h
 
     def step(self, nsteps):

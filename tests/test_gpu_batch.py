@@ -204,3 +204,47 @@ def test_lattice_beyond_the_cache_default_tile_and_batch():
     first = g.populations()
     g.close()
     assert (runs[0][0] != first).any(axis=0).mean() > 0.99
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16dev"])
+def test_aa_batch_equals_alone_bitwise(precision):
+    # lattices in the AA pattern, batched: odd and even launches per lattice
+    # by its own step parity, perimeter copies alternating; chunks long
+    # enough for the captured-graph path, odd and even step counts
+    from paper_2110_00967_amd import vplbm as V
+    specs = mixed_specs()
+    nsteps = [41, 17, 36, 0, 26, 35]
+    say("AA batch of", len(specs), "lattices,", precision, "steps", nsteps)
+    alone = []
+    for s, n in zip(specs, nsteps):
+        g = build_gpu(s, precision, streaming=V.STREAM_AA)
+        step_eager(g, n)
+        alone.append(state(g) if n else None)
+        g.close()
+    lats = [build_gpu(s, precision, streaming=V.STREAM_AA) for s in specs]
+    b = V.Batch(lats)
+    b.step(nsteps)
+    for k, (g, ref) in enumerate(zip(lats, alone)):
+        assert g.step_count == nsteps[k]
+        if ref is None:
+            continue
+        for a, r in zip(state(g), ref):
+            assert np.array_equal(a, r), (precision, k)
+    # a second round that starts every lattice on the other parity
+    b.step([3, 1, 2, 7, 0, 4])
+    for g, n in zip(lats, [44, 18, 38, 7, 26, 39]):
+        assert g.step_count == n
+    b.close()
+
+
+def test_batch_rejects_mixed_storage():
+    from paper_2110_00967_amd import vplbm as V
+    specs = mixed_specs()[:2]
+    say("AA and AB lattices in one batch")
+    a = build_gpu(specs[0], "f32", streaming=V.STREAM_AA)
+    c = build_gpu(specs[1], "f32")
+    with pytest.raises(V.VplbmError) as e:
+        V.Batch([a, c])
+    assert e.value.code == V.EINVAL
+    a.close()
+    c.close()
