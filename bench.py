@@ -231,7 +231,7 @@ def run_serve(args, W):
 
     reqs = W.serving_trace(nreq=args.requests, seed=0, rate=args.rate, steps_range=(2e3, 2e4))
     items = W.serving_items(reqs)
-    eng = GpuEngine(args.precision)
+    eng = GpuEngine(args.precision, streaming=1 if args.streaming == "aa" else 0)
     # warm the kernels up once (first launches pay code-object loading)
     warm = items[0][2]
     h = eng.create(warm)
@@ -251,7 +251,7 @@ def run_serve(args, W):
                    "grids": [[256, 256], [512, 256], [1024, 512], [2048, 1024]], "steps_range": [2000, 20000],
                    "hbm_budget_GiB": args.budget_gib, "chunk_steps": args.chunk, "policy": args.policy,
                    "saturate_cells": args.saturate_cells if args.policy == "srpt" else None,
-                   "storage": args.precision},
+                   "storage": args.precision, "streaming": args.streaming.upper()},
         "serving": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in served.items()},
         "serial": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in serial.items()},
     }

@@ -57,12 +57,13 @@ class Request:
 class GpuEngine:
     """Lattices in torch-allocated HBM, stepped through the C ABI."""
 
-    def __init__(self, precision="f32"):
+    def __init__(self, precision="f32", streaming=0):
         import torch
 
         from . import vplbm as V
 
         self.V, self.torch, self.precision = V, torch, precision
+        self.streaming = int(streaming)  # STREAM_AB or STREAM_AA (half the population memory)
         self._batch = None
         self._batch_key = None
 
@@ -74,13 +75,13 @@ class GpuEngine:
         return V.make_params(case.nx, case.ny, case.tau, case.eta, case.rho0, self.precision, e(case.west),
                              e(case.east), e(case.south), e(case.north), max_si_points=max(npts, 16),
                              max_vertices=max(nv, 16), trt_lambda=getattr(case, "trt_lambda", 0.0),
-                             hist_capacity=16)
+                             si_rule=getattr(case, "si_rule", 0), hist_capacity=16, streaming=self.streaming)
 
     def nbytes(self, case):
         return self.V.required_bytes(self._params(case))
 
     def create(self, case):
-        return self.V.Lattice.from_case(case, precision=self.precision, hist_capacity=16)
+        return self.V.Lattice.from_case(case, precision=self.precision, hist_capacity=16, streaming=self.streaming)
 
     def step(self, handles, nsteps):
         key = tuple(id(h) for h in handles)

@@ -180,20 +180,21 @@ def test_percentile():
 
 
 @pytest.mark.gpu
-def test_gpu_mix_equals_alone():
+@pytest.mark.parametrize("streaming", [0, 1])
+def test_gpu_mix_equals_alone(streaming):
     from gpu_cases import say
     from paper_2110_00967_amd import vplbm as V
     from paper_2110_00967_amd.serve import GpuEngine
     reqs = W.serving_trace(nreq=8, seed=3, rate=50.0, grids=((64, 64), (128, 64), (96, 96)),
                            steps_range=(60, 400))
     items = W.serving_items(reqs)
-    say("serve 8 mixed requests (airfoil + sedimentation), fp32")
-    eng = GpuEngine("f32")
+    say("serve 8 mixed requests (airfoil + sedimentation), fp32, storage", "AA" if streaming else "AB")
+    eng = GpuEngine("f32", streaming=streaming)
     budget = 3 * eng.nbytes(items[0][2])
     out = Server(eng, budget, chunk=64).run(items)
     assert all(r.t_finish is not None for r in out)
     for r, (_, _, case, n) in zip(sorted(out, key=lambda r: r.rid), sorted(items, key=lambda i: i[0])):
-        g = V.Lattice.from_case(case, precision="f32", hist_capacity=16)
+        g = V.Lattice.from_case(case, precision="f32", hist_capacity=16, streaming=streaming)
         g.step(n)
         alone = {"me": g.forces_me().tolist(), "si": g.forces_si().tolist(), "body": g.body_state().tolist()}
         assert r.result["me"] == alone["me"] and r.result["si"] == alone["si"], r.rid
