@@ -292,7 +292,8 @@ int vplbm_read_mask(vplbm_lattice *lat, uint8_t *out);
  * A batch steps several lattices with one launch of the fused step kernel per
  * time step: the tiles of all active lattices are laid end to end and each
  * workgroup finds its lattice from a device table.  Each lattice computes
- * exactly what vplbm_step would (same tiles, same reduction order), so its
+ * exactly what vplbm_step would (the same per-cell arithmetic and reduction
+ * order, whatever its own tile: batched launches run 64x4 tiles), so its
  * results do not depend on what else is in the batch.  Moving disks add one
  * body kernel per step (one workgroup per moving lattice).  Runs of steps
  * are replayed from a captured HIP graph. */
