@@ -68,14 +68,8 @@ class GpuEngine:
         self._batch_key = None
 
     def _params(self, case):
-        V = self.V
-        e = lambda E: (E.kind, E.ux, E.uy)
-        npts = 0 if case.si_xy is None else len(case.si_xy)
-        nv = 0 if case.polygon is None else len(case.polygon)
-        return V.make_params(case.nx, case.ny, case.tau, case.eta, case.rho0, self.precision, e(case.west),
-                             e(case.east), e(case.south), e(case.north), max_si_points=max(npts, 16),
-                             max_vertices=max(nv, 16), trt_lambda=getattr(case, "trt_lambda", 0.0),
-                             si_rule=getattr(case, "si_rule", 0), hist_capacity=16, streaming=self.streaming)
+        # the parameters create() builds its lattice from
+        return self.V.case_params(case, self.precision, hist_capacity=16, streaming=self.streaming)
 
     def nbytes(self, case):
         return self.V.required_bytes(self._params(case))

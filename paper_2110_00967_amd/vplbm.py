@@ -166,6 +166,19 @@ def required_bytes(params: Params) -> int:
     return int(load_library().vplbm_required_bytes(C.byref(params)))
 
 
+def case_params(case, precision="f32", **kw) -> Params:
+    """Parameters of a workload description (grid, relaxation, edges, point
+    and vertex capacities, collision, stencil rule); kw adds any other
+    make_params argument.  Lattice.from_case creates its lattice from them,
+    so required_bytes(case_params(...)) is that lattice's device size."""
+    e = lambda E: (E.kind, E.ux, E.uy)
+    npts = 0 if case.si_xy is None else len(case.si_xy)
+    nv = 0 if case.polygon is None else len(case.polygon)
+    return make_params(case.nx, case.ny, case.tau, case.eta, case.rho0, precision, e(case.west), e(case.east),
+                       e(case.south), e(case.north), max_si_points=max(npts, 16), max_vertices=max(nv, 16),
+                       trt_lambda=getattr(case, "trt_lambda", 0.0), si_rule=getattr(case, "si_rule", 0), **kw)
+
+
 class Lattice:
     """One VP-LBM lattice on the current GPU, memory from a torch tensor."""
 
@@ -198,13 +211,7 @@ class Lattice:
 
     @classmethod
     def from_case(cls, case, precision="f32", **kw):
-        e = lambda E: (E.kind, E.ux, E.uy)
-        npts = 0 if case.si_xy is None else len(case.si_xy)
-        nv = 0 if case.polygon is None else len(case.polygon)
-        p = make_params(case.nx, case.ny, case.tau, case.eta, case.rho0, precision, e(case.west), e(case.east),
-                        e(case.south), e(case.north), max_si_points=max(npts, 16), max_vertices=max(nv, 16),
-                        trt_lambda=case.trt_lambda, si_rule=getattr(case, "si_rule", 0), **kw)
-        lat = cls(p)
+        lat = cls(case_params(case, precision, **kw))
         if case.gx or case.gy:
             lat.set_body_force(case.gx, case.gy)
         if case.disk is not None:
