@@ -215,26 +215,32 @@ def test_aa_batch_equals_alone_bitwise(precision):
     specs = mixed_specs()
     nsteps = [41, 17, 36, 0, 26, 35]
     say("AA batch of", len(specs), "lattices,", precision, "steps", nsteps)
-    alone = []
-    for s, n in zip(specs, nsteps):
-        g = build_gpu(s, precision, streaming=V.STREAM_AA)
+    solo = [build_gpu(s, precision, streaming=V.STREAM_AA) for s in specs]
+    for g, n in zip(solo, nsteps):
         step_eager(g, n)
-        alone.append(state(g) if n else None)
-        g.close()
     lats = [build_gpu(s, precision, streaming=V.STREAM_AA) for s in specs]
     b = V.Batch(lats)
     b.step(nsteps)
-    for k, (g, ref) in enumerate(zip(lats, alone)):
+    for k, (g, ref) in enumerate(zip(lats, solo)):
         assert g.step_count == nsteps[k]
-        if ref is None:
+        if nsteps[k] == 0:
             continue
-        for a, r in zip(state(g), ref):
+        for a, r in zip(state(g), state(ref)):
             assert np.array_equal(a, r), (precision, k)
+    # the batched lattices go on with direct steps (perimeter copies and
+    # layout handed over by the batch) and still match the direct runs
+    for g, ref in zip(lats, solo):
+        step_eager(g, 3)
+        step_eager(ref, 3)
+        for a, r in zip(state(g), state(ref)):
+            assert np.array_equal(a, r), precision
     # a second round that starts every lattice on the other parity
     b.step([3, 1, 2, 7, 0, 4])
-    for g, n in zip(lats, [44, 18, 38, 7, 26, 39]):
+    for g, n in zip(lats, [47, 21, 41, 10, 29, 42]):
         assert g.step_count == n
     b.close()
+    for g in solo + lats:
+        g.close()
 
 
 def test_batch_rejects_mixed_storage():
