@@ -63,3 +63,30 @@ def test_default_tile_follows_the_footprint():
         g = V.Lattice(V.make_params(nx, ny, 0.6, 1e-3, 1.0, prec, streaming=aa))
         assert g.tile == tile, (nx, ny, prec, aa, g.tile)
         g.close()
+
+
+def test_degenerate_calls():
+    # zero steps (alone and batched) change nothing; a negative count is
+    # rejected; removing every stress-integration point leaves SI forces of
+    # exactly zero while ME goes on
+    import numpy as np
+    from paper_2110_00967_amd import vplbm as V
+    say("degenerate calls: zero steps, empty point set")
+    g = build_gpu(RAGGED["periodic_disk_random"], "f32")
+    g.step(5)
+    pops, h_me, h_si = g.populations(), g.history(0), g.history(1)
+    g.step(0)
+    b = V.Batch([g])
+    b.step([0])
+    b.close()
+    assert g.step_count == 5
+    assert np.array_equal(g.populations(), pops)
+    assert np.array_equal(g.history(0), h_me) and np.array_equal(g.history(1), h_si)
+    with pytest.raises(V.VplbmError) as e:
+        g.step(-1)
+    assert e.value.code == V.EINVAL
+    g.set_si_points(np.zeros((0, 2)), np.zeros((0, 2)), np.zeros(0))
+    g.step(2)
+    assert np.all(g.forces_si() == 0.0)
+    assert np.abs(g.forces_me()).max() > 0.0
+    g.close()
