@@ -146,17 +146,25 @@ enum { VPLBM_STEP_MACRO = 1 }; /* vplbm_step flag: write rho, u on the last step
 /* Exact device bytes a lattice with these parameters needs (populations
  * A and B, or one buffer with the AA pattern; mask, macroscopic fields,
  * per-cell force slots, force history, tables);
- * 0 if the parameters are invalid. */
+ * 0 if the parameters are invalid.  Sizes follow the D2Q9 lattice of
+ * Sec. 2.2 (9 populations per cell). */
 size_t vplbm_required_bytes(const vplbm_params *p);
 
-/* Create a lattice.  dev_mem: device buffer of at least
- * vplbm_required_bytes(p) bytes, borrowed for the lifetime of the handle
- * (the caller frees it after vplbm_destroy), or NULL to let the library
- * allocate (and free) it.  hip_stream: a hipStream_t, or NULL for the
- * default stream.  Populations start at rest (rho0, u = 0), the mask is
- * all fluid, the body at rest at the origin. */
+/* Create a lattice: the fluid domain Omega of Sec. 2.1 discretized as the
+ * D2Q9 lattice of Sec. 2.2, with relaxation time tau (Eq. tauvisco gives the
+ * viscosity) and penalization factor eta (Eq. 1, Eq. fcar).  dev_mem: device
+ * buffer of at least vplbm_required_bytes(p) bytes, 256-byte aligned,
+ * borrowed for the lifetime of the handle (the caller frees it after
+ * vplbm_destroy), or NULL to let the library allocate (and free) it.
+ * hip_stream: a hipStream_t, or NULL for the default stream.  Populations
+ * start at rest (f = f^eq(rho0, 0), Sec. 2.2), the mask is all fluid, the
+ * body at rest at the origin.  VPLBM_EINVAL for invalid parameters (message
+ * in vplbm_last_error(NULL)), VPLBM_ENOMEM for a buffer that is too small or
+ * misaligned or a failed allocation. */
 int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *hip_stream,
                  vplbm_lattice **out);
+/* Release a lattice (waits for its stream; frees the device buffer only if
+ * the library allocated it).  VPLBM_EINVAL for NULL. */
 int vplbm_destroy(vplbm_lattice *lat);
 /* Message of the last failed call on the handle; with lat == NULL, the
  * message of the last failed vplbm_create on the calling thread. */
@@ -224,16 +232,27 @@ int vplbm_set_si_points(vplbm_lattice *lat, const double *xy, const double *nrm,
 int vplbm_set_si_points_body(vplbm_lattice *lat, int body, const double *xy, const double *nrm,
                              const double *ds, int npts);
 
-/* Advance nsteps time steps (asynchronous).  flags: VPLBM_STEP_MACRO makes
- * the last step also store rho and the penalized velocity u for
- * vplbm_read_macro. */
+/* Advance nsteps time steps (asynchronous).  One step n is the update of
+ * Sec. 2.2 with the penalization of Eqs. updatestep..updatestepm: pull
+ * streaming (Eq. eqBd), moments, penalized velocity and force density,
+ * collision with the forcing term (Eq. TRT prefactor), and, fused into the
+ * same kernel, the momentum exchange (Eqs. MMEL, fluidtorque) and stress
+ * integration (Eq. defFf) of that step; a moving disk then follows Eqs.
+ * dep1/theta2.  flags: VPLBM_STEP_MACRO makes the last step also store rho
+ * and the penalized velocity u for vplbm_read_macro.  VPLBM_EINVAL for
+ * nsteps < 0; nsteps = 0 does nothing. */
 int vplbm_step(vplbm_lattice *lat, int nsteps, int flags);
 /* Same as vplbm_step, for measurement: HIP events bracket every launch of
  * the fused step kernel on the lattice's stream; on return (the stream is
  * synchronized) *kernel_ms holds the summed duration of those launches in
  * milliseconds. */
 int vplbm_step_timed(vplbm_lattice *lat, int nsteps, int flags, double *kernel_ms);
+/* Wait for the lattice's queued work and publish the last step's forces.
+ * Returns VPLBM_EUNSTABLE once a step met a non-finite density,
+ * VPLBM_ENOSAMPLE when a moving body's point lost its sample node, VPLBM_EHIP
+ * for a kernel fault. */
 int vplbm_sync(vplbm_lattice *lat);
+/* Steps taken since the last initialization (-1 for NULL). */
 long long vplbm_step_count(const vplbm_lattice *lat);
 /* Workgroup tile of the step kernel, bx cells along x times by rows:
  * 64x1, 64x2, 64x4, 128x1, 128x2 or 256x1.  The default is 64x4, or 128x2
@@ -246,10 +265,13 @@ int vplbm_set_tile(vplbm_lattice *lat, int bx, int by);
 /* The tile the lattice's own steps use (*bx cells along x, *by rows). */
 int vplbm_get_tile(const vplbm_lattice *lat, int *bx, int *by);
 
-/* Forces of the last step, out = (Fx, Fy, Tz) on the body, torque about the
- * reference point.  Momentum exchange of step n is evaluated on the
- * post-collision populations of step n-1; stress integration of step n on
- * the streamed (pre-collision) populations of step n. */
+/* Forces of the last step on body 1, out = (Fx, Fy, Tz), torque about the
+ * body's reference point: vplbm_forces_me by momentum exchange (Sec. 2.3.1,
+ * Eqs. MMEL and fluidtorque, summed over the links), evaluated on the
+ * post-collision populations of step n-1; vplbm_forces_si by stress
+ * integration (Sec. 2.3.2, Eq. defFf as the discrete sum over the registered
+ * points, sigma of the streamed (pre-collision) populations of step n).
+ * VPLBM_ESTATE before the first step. */
 int vplbm_forces_me(vplbm_lattice *lat, double out[3]);
 int vplbm_forces_si(vplbm_lattice *lat, double out[3]);
 /* Stress integration over the given points on the current streamed state
@@ -265,10 +287,13 @@ int vplbm_force_history(vplbm_lattice *lat, int which, long long first_step, int
 int vplbm_forces_body(vplbm_lattice *lat, int body, int which, double out[3]);
 int vplbm_force_history_body(vplbm_lattice *lat, int body, int which, long long first_step, int n,
                              double *out);
+/* State of body 1 for the next step: position, angle and velocities of the
+ * rigid-body motion of Eqs. dep1 and theta2 (prescribed or free). */
 int vplbm_get_body_state(vplbm_lattice *lat, vplbm_body_state *out);
 
-/* rho and penalized u of the last step (which must have been run with
- * VPLBM_STEP_MACRO), host arrays [ny][nx]. */
+/* rho (Eq. updatestep) and the penalized velocity u (Eq. updatestepm) of
+ * the last step, which must have been run with VPLBM_STEP_MACRO
+ * (VPLBM_ESTATE otherwise); host arrays [ny][nx], caller-owned. */
 int vplbm_read_macro(vplbm_lattice *lat, double *rho, double *ux, double *uy);
 /* The same into caller-owned device arrays [ny][nx] of the compute type (double
  * for VPLBM_F64, float for VPLBM_F32 and VPLBM_F16DEV), asynchronously on the

@@ -28,7 +28,9 @@ PERIODIC, VELOCITY, FREESLIP, OUTFLOW, CONVECTIVE = 0, 1, 2, 3, 4
 # D2Q9 of Sec. 2.2 (restated here only for test-side moment checks)
 CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
 CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
-W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+# the rest weight is the exact remainder 1 - 4/9 - ... of the two other
+# (nearest-double) weights, as in vplbm_oracle.c, so that they sum to one
+W = np.array([float.fromhex("0x1.c71c71c71c71dp-2")] + [1 / 9] * 4 + [1 / 36] * 4)
 
 
 class _Params(C.Structure):

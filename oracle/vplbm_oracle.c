@@ -31,8 +31,14 @@
 /* D2Q9 velocity set, Sec. 2.2: c_0 = 0, c_1..4 axis, c_5..8 diagonals. */
 static const int CX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int CY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-/* weights omega_alpha, Sec. 2.2 */
-static const double W[Q] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+/* weights omega_alpha, Sec. 2.2: 4/9, 1/9 (axes), 1/36 (diagonals), summing
+ * to one.  1/9 and 1/36 are the nearest doubles; the rest weight is the
+ * double just above the one nearest to 4/9, the exact remainder
+ * 1 - 4 w_1 - 4 w_5, so that the weights sum to exactly one in binary as they
+ * do in the paper.  With the nearest double for 4/9 as well the sum falls
+ * short by 2^-54, and every collision would remove that fraction of the
+ * cell's mass divided by tau. */
+static const double W[Q] = {0x1.c71c71c71c71dp-2, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 /* opposite direction alpha-bar, c_abar = -c_a (Sec. 2.2, TRT paragraph) */
 static const int OPP[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
@@ -321,9 +327,9 @@ void orc_stress_integration(const orc_params *p, const double *f, int npts, cons
   }
 }
 
-/* Sample node of each integration point.  The paper takes f "from the
- * closest point in the relevant direction (close to n) in the fluid domain";
- * read here as: the lattice direction beta with the largest (c_beta . n)/|c_beta|
+/* Sample node of each integration point.  Sec. 2.3.2 takes the populations
+ * at the nearest fluid node in a lattice direction near the normal n; read
+ * here as: the lattice direction beta with the largest (c_beta . n)/|c_beta|
  * (first one on ties), then, starting from the node nearest to x_i, the first
  * of up to five nodes along c_beta that is fluid and inside the domain.
  * Returns the number of points without a sample node (node = -1). */

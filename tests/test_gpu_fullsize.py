@@ -2,8 +2,10 @@
 configuration bench.py times (FP32 deviation storage, default tile).
 
 * NACA 0012, 2000 x 1000: bit-exact solid indicator and sample nodes; 200
-  steps against the FP64 oracle (velocity relative L2 <= 1e-5, force
-  histories within 0.5% of the largest force).
+  steps against the FP64 oracle (velocity relative L2 <= 1e-5; drag and
+  lift each within 0.5%: their means over the last 50 steps, and every step
+  against the largest value of the same component; the torque on its own
+  bar).
 * The paper's own airfoil runs (chord 278 on 3614 x 1946, TRT with
   Lambda = 1/6, eta = 1e-6, 849 SI points): 50 steps at 20 degrees.
 * Sedimenting disk, 400 x 2000: 200 steps of the free body driven by the
@@ -23,6 +25,22 @@ from gpu_cases import rel_l2, say
 pytestmark = pytest.mark.gpu
 
 
+def check_force_components(g, o, tag, window=50, bar=5e-3):
+    """C_D and C_L parity: drag (F_x) and lift (F_y) separately, the mean of
+    the last `window` steps within `bar` of the oracle's, and every step within
+    `bar` of the component's largest oracle value.  The torque about the
+    quarter chord (the pitching moment, near zero for a symmetric airfoil) is
+    held to its own largest value in both checks."""
+    for which, ref in ((0, o.me()), (1, o.si())):
+        h = g.history(which)
+        for k, name in enumerate(("Fx", "Fy", "T")):
+            mh, mr = h[-window:, k].mean(), ref[-window:, k].mean()
+            e_mean = abs(mh - mr) / (abs(mr) if k < 2 else np.abs(ref[:, k]).max())
+            e_step = np.abs(h[:, k] - ref[:, k]).max() / np.abs(ref[:, k]).max()
+            say(f"{tag} force {which} {name}: mean rel err {e_mean:.2e}, per-step {e_step:.2e}")
+            assert e_mean <= bar and e_step <= bar
+
+
 def test_naca_full_size_fp32():
     from paper_2110_00967_amd import vplbm as V
     case = W.case_naca(chord=200, aoa_deg=10.0)
@@ -40,11 +58,7 @@ def test_naca_full_size_fp32():
     err_r = rel_l2(r - 1.0, o.rho - 1.0)
     say(f"naca u relL2 {err_u:.2e}, (rho-1) relL2 {err_r:.2e}")
     assert err_u <= 1e-5
-    for which, ref in ((0, o.me()), (1, o.si())):
-        h = g.history(which)
-        e = np.abs(h - ref).max() / np.abs(ref).max()
-        say(f"naca force {which} max rel err {e:.2e}")
-        assert e <= 5e-3
+    check_force_components(g, o, "naca")
 
 
 def test_naca_paper_scale_trt_fp32():
@@ -65,11 +79,7 @@ def test_naca_paper_scale_trt_fp32():
     err_u = rel_l2(np.stack([u, v]), np.stack([o.ux, o.uy]))
     say(f"paper-scale u relL2 {err_u:.2e}")
     assert err_u <= 1e-5
-    for which, ref in ((0, o.me()), (1, o.si())):
-        h = g.history(which)
-        e = np.abs(h - ref).max() / np.abs(ref).max()
-        say(f"paper-scale force {which} max rel err {e:.2e}")
-        assert e <= 5e-3
+    check_force_components(g, o, "paper-scale")
 
 
 def test_sedimentation_full_size_fp32():

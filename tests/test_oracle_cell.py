@@ -12,6 +12,8 @@ not a retyping of the oracle's own formula:
 import ctypes as C
 import math
 
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -31,6 +33,13 @@ def rng_cells(n, seed):
 def test_weights_and_velocity_set():
     # sum w = 1, isotropy sum w c c = cs^2 I, sum w c_x^2 c_y^2 = cs^4
     assert abs(O.W.sum() - 1.0) < 1e-15
+    # the stored weights sum to one exactly (rational arithmetic on the
+    # doubles), so f^eq carries exactly rho: the zeroth moment that defines it
+    assert sum(Fraction(float(w)) for w in O.W) == 1
+    for k, ref in ((0, Fraction(4, 9)), (1, Fraction(1, 9)), (5, Fraction(1, 36))):
+        assert abs(Fraction(float(O.W[k])) - ref) <= Fraction(1, 2 ** 53) * ref
+    f = O.equilibrium(1.0, 0.0, 0.0)  # the oracle's own weights
+    assert sum(Fraction(float(v)) for v in f) == 1
     assert abs((O.W * CX * CX).sum() - 1 / 3) < 1e-15
     assert abs((O.W * CX * CY).sum()) < 1e-15
     assert abs((O.W * CX ** 2 * CY ** 2).sum() - 1 / 9) < 1e-15

@@ -188,11 +188,13 @@ def test_mass_conservation_with_penalized_disk():
     m0 = math.fsum(lat.ft.ravel())
     lat.step(2000)
     m1 = math.fsum(lat.ft.ravel())
-    # Exact arithmetic conserves mass exactly.  In FP64 the weights 4/9, 1/9,
-    # 1/36 are rounded, so a state near rest drifts linearly by about 1e-17
-    # per cell and step (~1e-13 relative over 2000 steps); a dropped or
-    # misplaced mass term would show up orders of magnitude above this bound.
-    assert abs(m1 - m0) / m0 <= 5e-13
+    # Exact arithmetic conserves mass exactly, and so does the oracle up to
+    # unbiased rounding (a few 1e-16 over 2000 steps): its weights sum to one
+    # exactly in binary.  With the nearest doubles of 4/9, 1/9 and 1/36 the
+    # sum falls 2^-54 short and the mass would drift by 2000 * 2^-54 / tau =
+    # 1.85e-13.  A dropped or misplaced mass term would show up orders of
+    # magnitude above the bound, which is 10x tighter than 1e-13.
+    assert abs(m1 - m0) / m0 <= 1e-14
 
 
 # ---------------------------------------------------------------------------

@@ -13,7 +13,15 @@ Stress integration (Eq. defFf and the sigma definition):
   * Poiseuille: sigma_xy = rho0 nu du/dy = G/2 (ny - 1 - 2y) at any node;
   * Taylor-Green: deviatoric normal stress 2 rho nu du/dx and zero shear;
   * the same zero-force and symmetry cases as above.
-Rigid body (Eqs. dep1, theta2): closed forms of uniform acceleration.
+Hydrostatics (a disk at rest in a closed box under a uniform force density):
+  * stress integration gives the Archimedes force of the pressure part of
+    sigma, -(rho - rho0) c_s^2 I, in closed form for the interpolated stencil
+    and from the sample nodes' heights for the nearest-node rule;
+  * momentum exchange balances the force density on the solid cells.
+Rigid body (Eqs. dep1, theta2): closed forms of uniform acceleration; the
+stress-integration points of a rotating, translating body follow the rigid
+motion (a quarter turn maps them exactly, one step moves them with the body's
+velocity field).
 """
 import ctypes as C
 import math
@@ -363,3 +371,125 @@ def test_multibody_mirror_twins():
         assert np.abs(h1[:, 1] + h2[:, 1]).max() <= 1e-12 * scale
         assert np.abs(h1[:, 2] + h2[:, 2]).max() <= 1e-12 * scale
     assert np.abs(lat.me(1)[-1, 1]) > 1e-3 * np.abs(lat.me(1)[-1, 0])  # a real lift to mirror
+
+
+# ----------------------------------------------------------------------------
+# hydrostatics: the pressure part of sigma and the momentum balance of ME
+# ----------------------------------------------------------------------------
+
+def hydrostatic_box(rule, L=32, g=2e-5, r=7.5, npts=64, steps=3000, eta=1e-4):
+    """A penalized disk at rest in a closed box of fluid at rest under a
+    uniform force density G = (0, -g).  The steady state is hydrostatic:
+    u = 0 and c_s^2 grad rho = G, so rho falls linearly with height and the
+    stress is the pressure alone, sigma = -(rho - rho0) c_s^2 I.  Started
+    from that profile, the box settles within a few thousand steps."""
+    lat = O.RefLattice(L, L, 1.0, eta, west=(O.VELOCITY, 0, 0), east=(O.VELOCITY, 0, 0),
+                       south=(O.VELOCITY, 0, 0), north=(O.VELOCITY, 0, 0), gy=-g, si_rule=rule)
+    xc, yc = L / 2 - 0.3, L / 2 + 0.2
+    lat.set_disk(xc, yc, r)
+    xy, n, ds = W.disk_si_points(xc, yc, r, npts)
+    lat.set_si_points(xy, n, ds)
+    y = np.arange(L)[:, None] * np.ones((1, L))
+    lat.set_fields(1.0 - 3.0 * g * (y - yc), 0.0 * y, 0.0 * y)
+    lat.step(steps)
+    assert np.abs(lat.ux).max() <= 1e-9 and np.abs(lat.uy).max() <= 1e-9  # at rest
+    return lat, (xc, yc, r), (xy, n, ds), g
+
+
+def test_hydrostatic_archimedes_stress_integration_interpolated():
+    # Rule 1 samples sigma at p_i = x_i + 1.5 n_i, bilinear -- exact for the
+    # linear pressure.  With rho = rho_c - 3 g (y - y_c):
+    #   F = -sum_i S_i (rho(p_i) - rho0)/3 n_i = g sum_i S_i (p_iy - y_c) n_i
+    # (the constant part cancels: sum S_i n_i = 0), and for N equally spaced
+    # points on the circle, sum S (y - y_c) n_y = pi r^2 and
+    # sum S n_y^2 = pi r: F_y = g pi r (r + 1.5), the Archimedes force on the
+    # disk grown by the 1.5-cell sampling offset; F_x = 0, and no torque
+    # about the centre (the pressure acts along the radius).
+    lat, (xc, yc, r), _, g = hydrostatic_box(1)
+    assert (lat.si_node4.reshape(-1, 4) >= 0).all()  # every point interpolates
+    si = lat.si()[-1]
+    fy = g * math.pi * r * (r + 1.5)
+    assert abs(si[1] - fy) <= 1e-6 * fy
+    assert abs(si[0]) <= 1e-6 * fy and abs(si[2]) <= 1e-6 * fy * r
+
+
+def test_hydrostatic_archimedes_stress_integration_nearest_node():
+    # Rule 0 takes sigma at the sample node r_i itself:
+    #   F = g sum_i S_i (y(r_i) - y_c) n_i   (both components)
+    lat, (xc, yc, r), (xy, n, ds), g = hydrostatic_box(0)
+    node = lat.si_node4.reshape(-1, 4)[:, 0]
+    ys = (node // lat.nx).astype(float)
+    ref = g * np.array([(ds * (ys - yc) * n[:, 0]).sum(), (ds * (ys - yc) * n[:, 1]).sum()])
+    si = lat.si()[-1]
+    assert ref[1] > g * math.pi * r * r  # the samples lie outside the disk
+    assert np.abs(si[:2] - ref).max() <= 1e-6 * ref[1]
+
+
+def test_hydrostatic_momentum_exchange_balances_the_body_force():
+    # At rest the solid cells' momentum is steady: what streaming brings into
+    # them each step (the ME force, Eq. MMEL summed) cancels what their
+    # collision adds, the force density G in every solid cell (penalization
+    # is idle at u = u_s = 0): F_ME = -G N_solid = (0, g N_solid).
+    lat, _, _, g = hydrostatic_box(0)
+    nsolid = int((lat.solid != 0).sum())
+    me = lat.me()[-1]
+    assert abs(me[1] - g * nsolid) <= 1e-6 * g * nsolid
+    assert abs(me[0]) <= 1e-6 * g * nsolid
+
+
+# ----------------------------------------------------------------------------
+# stress-integration points of a rotating body (Eqs. dep1, theta2)
+# ----------------------------------------------------------------------------
+
+def asymmetric_points(xc, yc, r, npts, seed):
+    # points on the circle at random angles, so that no rotation maps the set
+    # onto itself with other indices
+    th = np.sort(np.random.default_rng(seed).uniform(0.0, 2.0 * math.pi, npts))
+    n = np.stack([np.cos(th), np.sin(th)], 1)
+    return np.stack([xc + r * n[:, 0], yc + r * n[:, 1]], 1), n, np.full(npts, 2 * math.pi * r / npts)
+
+
+@pytest.mark.parametrize("theta0", [0.0, 0.3])
+def test_rotating_points_quarter_turn(theta0):
+    # prescribed rotation by pi/2 in N steps, plus a translation: every
+    # registered point and normal (given in the world frame at the body's
+    # current angle theta0) is carried rigidly,
+    #   x_i -> x_G(N) + R(pi/2) (x_i - x_G(0)),  n_i -> R(pi/2) n_i,
+    # R(pi/2) (a, b) = (-b, a): counter-clockwise for omega > 0, the sense of
+    # the body's velocity field u_G + omega e_z x (x - x_G)
+    xc, yc, r, N = 30.25, 28.5, 6.3, 40
+    u, v = 0.011, -0.007
+    lat = O.RefLattice(64, 60, 0.8, 1e-3)
+    lat.set_disk(xc, yc, r)
+    xy, n, ds = asymmetric_points(xc, yc, r, 48, seed=5)
+    lat.set_motion(xc, yc, theta0, 0.0, 0.0, 0.0)
+    lat.set_si_points(xy, n, ds)
+    lat.set_motion(xc, yc, theta0, u, v, (math.pi / 2) / N)
+    lat.init_uniform(1.0, 0.0, 0.0)
+    lat.step(N)
+    assert abs(lat.body.theta - theta0 - math.pi / 2) <= 1e-14
+    gx, gy = xc + N * u, yc + N * v
+    assert abs(lat.body.x - gx) <= 1e-12 and abs(lat.body.y - gy) <= 1e-12
+    want = np.stack([gx - (xy[:, 1] - yc), gy + (xy[:, 0] - xc)], 1)
+    assert np.abs(lat.si_xy - want).max() <= 1e-12
+    assert np.abs(lat.si_n - np.stack([-n[:, 1], n[:, 0]], 1)).max() <= 1e-14
+    assert np.abs(lat.si_ds - ds).max() == 0.0
+
+
+def test_rotating_points_move_with_the_body_velocity():
+    # one step of a spinning, translating body moves each point by the rigid
+    # velocity at the point, u_G + omega e_z x (x_i - x_G), up to the
+    # second-order term of the rotation (|omega|^2 r / 2)
+    xc, yc, r = 30.0, 28.0, 6.0
+    u, v, w = 0.02, 0.013, 0.004
+    lat = O.RefLattice(64, 60, 0.8, 1e-3)
+    lat.set_disk(xc, yc, r)
+    xy, n, ds = asymmetric_points(xc, yc, r, 40, seed=9)
+    lat.set_si_points(xy, n, ds)
+    lat.set_motion(xc, yc, 0.0, u, v, w)
+    lat.init_uniform(1.0, 0.0, 0.0)
+    lat.step(1)
+    vel = np.stack([u - w * (xy[:, 1] - yc), v + w * (xy[:, 0] - xc)], 1)
+    err = np.abs(lat.si_xy - xy - vel).max()
+    assert err <= 0.5 * w * w * r * (1 + 1e-9)
+    assert err >= 0.1 * w * w * r  # the rotation really is of order omega^2 off the chord
