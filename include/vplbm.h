@@ -335,6 +335,12 @@ const char *vplbm_batch_last_error(const vplbm_batch *b);
  * with steps left run together; a lattice drops out when its count is
  * reached.  Forces, histories and states are read per lattice afterwards. */
 int vplbm_batch_step(vplbm_batch *b, const int *nsteps);
+/* Tile of the batched launches (workgroup shape, not a choice the paper
+ * makes): 64x4 (default), 128x2 or 256x1 cells; a batch of AA lattices runs
+ * 64x4 only (VPLBM_EINVAL otherwise).  Results do not depend on it (forces
+ * are summed per interface cell and sample record in a fixed order). */
+int vplbm_batch_set_tile(vplbm_batch *b, int bx, int by);
+int vplbm_batch_get_tile(const vplbm_batch *b, int *bx, int *by);
 
 #ifdef __cplusplus
 }

@@ -697,19 +697,36 @@ template <typename T> struct CaseDesc {
   double *hist;
   int cap, maxb;
   int tile0;              // first global tile of this lattice
+  int ntiles;             // its tiles
   int cur0;               // parity of the buffer holding the state at launch 0
   int pbit0;              // parity of the step computed by launch 0
   int pending0;           // launch 0 finalizes the forces of the step before it
   int moving;             // forces are finalized by the body kernel instead
   // body-kernel arguments
-  int tw, by, perx, pery, maxp, maxslot;
+  int perx, pery, maxp, maxslot;
   const double *pts;
   // AA pattern: the perimeter copies kept by the steps of parity 0 and 1
   void *ec[2];
 };
 
+// Lattice of every global tile of a batched launch, from the descriptors
+// (tiles of lattice i are [tile0, tile0 + ntiles), in order): one thread per
+// tile, binary search on tile0.
+template <typename T>
+__global__ void k_fill_tile_case(const CaseDesc<T> *__restrict__ cases, int ncases, int total,
+                                 int *__restrict__ tile_case) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  int lo = 0, hi = ncases - 1;  // last lattice with tile0 <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cases[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+  }
+  tile_case[t] = lo;
+}
+
 // Batched step: launch number `flip` (0 or 1, alternating) of a run over
-// ncases lattices; the lattice of a tile is found by binary search on tile0.
+// ncases lattices; the lattice of each tile comes from the tile table.
 template <typename S, int BX, int BY, bool TRT>
 __global__ void __launch_bounds__(BX *BY, step_waves<S>())
     k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,

@@ -1539,18 +1539,19 @@ int vplbm_read_mask(vplbm_lattice *L, uint8_t *out) {
 
 struct vplbm_batch {
   std::vector<vplbm_lattice *> cases;
-  hipStream_t stream = nullptr;  // the lattices' stream
+  hipStream_t stream = nullptr;      // the lattices' stream
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
   int prec = 0;
   bool trt = false;  // collision of every lattice of the batch
   bool aa = false;   // storage scheme of every lattice of the batch
+  int bx = 64, by = 4;  // tile of the batched launches
   char *desc_dev = nullptr;
   int *moving_dev = nullptr;
   int *tile_case_dev = nullptr;  // lattice index of every global tile
-  size_t tile_case_cap = 0;
+  long long tile_case_cap = 0;
   std::vector<char> desc_host;
-  std::vector<int> moving_host, tile_case_host;
-  hipGraphExec_t graph = nullptr;  // two steps (launch parities 1, 0) of the current active set
+  std::vector<int> moving_host;
+  hipGraphExec_t graph = nullptr;  // groups of launch pairs (parities 1, 0) of the current active set
   long long graph_key = -1;
   std::string err;
   int fail(int code, const std::string &m) {
@@ -1565,20 +1566,39 @@ struct vplbm_batch {
 
 namespace {
 
-template <typename S> size_t desc_size() { return sizeof(CaseDesc<typename Store<S>::T>); }
+template <typename S> constexpr size_t desc_size() { return sizeof(CaseDesc<typename Store<S>::T>); }
 
 size_t desc_size_of(int prec) {
   return prec == VPLBM_F64 ? desc_size<double>() : (prec == VPLBM_F32 ? desc_size<float>() : desc_size<__half>());
 }
 
-// tile of the batched step kernel (k_step_batch is instantiated for it only)
-constexpr int BATCH_BX = 64, BATCH_BY = 4;
+// tiles k_step_batch is instantiated for (AA batches: 64x4 only)
+bool batch_tile_ok(int bx, int by) { return (bx == 64 && by == 4) || (bx == 128 && by == 2) || (bx == 256 && by == 1); }
+
+// What one run of batched launches needs: the lattices' common settings,
+// the device tables with their capacity, host staging for the descriptors,
+// and, when allowed, graph replay.
+struct BatchExec {
+  int prec = 0;
+  bool trt = false, aa = false;
+  int bx = 64, by = 4;
+  hipStream_t stream = nullptr;
+  char *desc_dev = nullptr;   // descriptors, one per active lattice
+  int *moving_dev = nullptr;  // active indices of the moving lattices
+  int *tile_dev = nullptr;    // lattice of every global tile
+  long long tile_cap = 0;
+  char *desc_host = nullptr;  // host staging, room for every lattice
+  int *moving_host = nullptr;
+  hipStream_t cap_stream = nullptr;  // graph capture (null: direct launches only)
+  hipGraphExec_t *graph = nullptr;
+  long long *graph_key = nullptr;
+};
 
 template <typename S>
-void fill_desc(vplbm_lattice *L, int tile0, void *out) {
+void fill_desc(vplbm_lattice *L, int tile0, int bx, int by, void *out) {
   using T = typename Store<S>::T;
   CaseDesc<T> d{};
-  d.P = L->step_args<T>(BATCH_BX, BATCH_BY);
+  d.P = L->step_args<T>(bx, by);
   d.buf[0] = L->at(L->L.A);
   d.buf[1] = L->at(L->L.B);
   d.mask = L->mask();
@@ -1596,12 +1616,11 @@ void fill_desc(vplbm_lattice *L, int tile0, void *out) {
   d.maxb = L->maxb;
   d.maxslot = (int)L->maxslot;
   d.tile0 = tile0;
+  d.ntiles = d.P.ntiles;
   d.cur0 = L->cur;
   d.pbit0 = (int)((L->nstep + 1) & 1);
   d.pending0 = L->pending ? 1 : 0;
   d.moving = L->mode != MODE_STATIC ? 1 : 0;
-  d.tw = BATCH_BX;  // batched launches run 64x4 tiles, whatever tile the lattice runs alone
-  d.by = BATCH_BY;
   d.perx = (int)L->periodic_x();
   d.pery = (int)L->periodic_y();
   d.maxp = L->maxp;
@@ -1611,37 +1630,207 @@ void fill_desc(vplbm_lattice *L, int tile0, void *out) {
   std::memcpy(out, &d, sizeof d);
 }
 
-template <typename S>
-void launch_batch_pair(vplbm_batch *B, hipStream_t st, int nact, int total, int nmov, int flip, int first) {
-  using T = typename Store<S>::T;
-  (void)nact;
-  const int per = (total + 7) / 8;
-  const auto *descs = (const CaseDesc<T> *)B->desc_dev;
-  const dim3 grid(8 * per), block(BATCH_BX * BATCH_BY);
-  static_assert(BATCH_BX * BATCH_BY == 256, "k_step_batch_aa runs 64x4 tiles");
-  if (B->aa) {
-    if (B->trt)
-      hipLaunchKernelGGL((k_step_batch_aa<S, true>), grid, block, 0, st, descs, B->tile_case_dev, total, per, flip,
-                         first);
-    else
-      hipLaunchKernelGGL((k_step_batch_aa<S, false>), grid, block, 0, st, descs, B->tile_case_dev, total, per, flip,
-                         first);
-  } else if (B->trt)
-    hipLaunchKernelGGL((k_step_batch<S, BATCH_BX, BATCH_BY, true>), grid, block, 0, st, descs, B->tile_case_dev,
-                       total, per, flip, first);
-  else
-    hipLaunchKernelGGL((k_step_batch<S, BATCH_BX, BATCH_BY, false>), grid, block, 0, st, descs, B->tile_case_dev,
-                       total, per, flip, first);
-  if (nmov)
-    hipLaunchKernelGGL((k_body_step_batch<T>), dim3(nmov), dim3(BODY_NT), 0, st, descs, B->moving_dev, flip);
+int batch_tiles(vplbm_lattice *L, int bx, int by) { return L->step_args<float>(bx, by).ntiles; }
+
+// lattices that can share one batched launch: one precision, collision,
+// stream and storage scheme, each once
+const char *batch_check(vplbm_lattice *const *lats, int n) {
+  if (!lats || n < 1) return "no lattices";
+  for (int k = 0; k < n; ++k) {
+    if (!lats[k]) return "NULL lattice";
+    if (lats[k]->p.precision != lats[0]->p.precision) return "lattices of different precisions";
+    if (lats[k]->stream != lats[0]->stream) return "lattices on different streams";
+    if ((lats[k]->p.trt_lambda > 0.0) != (lats[0]->p.trt_lambda > 0.0)) return "BGK and TRT lattices mixed";
+    if (lats[k]->aa() != lats[0]->aa()) return "a batch takes lattices of one storage scheme (all AB or all AA)";
+    for (int j = 0; j < k; ++j)
+      if (lats[j] == lats[k]) return "a lattice appears twice";
+  }
+  return nullptr;
 }
 
-void launch_batch(vplbm_batch *B, hipStream_t st, int nact, int total, int nmov, int flip, int first) {
-  switch (B->prec) {
-    case VPLBM_F64: launch_batch_pair<double>(B, st, nact, total, nmov, flip, first); break;
-    case VPLBM_F32: launch_batch_pair<float>(B, st, nact, total, nmov, flip, first); break;
-    default: launch_batch_pair<__half>(B, st, nact, total, nmov, flip, first); break;
+template <typename S, int BX, int BY>
+void launch_batch_ab(const BatchExec &X, hipStream_t st, dim3 grid, int total, int per, int flip, int first) {
+  const auto *descs = (const CaseDesc<typename Store<S>::T> *)X.desc_dev;
+  if (X.trt)
+    hipLaunchKernelGGL((k_step_batch<S, BX, BY, true>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total, per,
+                       flip, first);
+  else
+    hipLaunchKernelGGL((k_step_batch<S, BX, BY, false>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total, per,
+                       flip, first);
+}
+
+template <typename S>
+void launch_batch_pair(const BatchExec &X, hipStream_t st, int total, int nmov, int flip, int first) {
+  using T = typename Store<S>::T;
+  const int per = (total + 7) / 8;
+  const auto *descs = (const CaseDesc<T> *)X.desc_dev;
+  const dim3 grid(8 * per);
+  if (X.aa) {  // 64x4 tiles
+    if (X.trt)
+      hipLaunchKernelGGL((k_step_batch_aa<S, true>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per, flip,
+                         first);
+    else
+      hipLaunchKernelGGL((k_step_batch_aa<S, false>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per, flip,
+                         first);
+  } else if (X.bx == 128) {
+    launch_batch_ab<S, 128, 2>(X, st, grid, total, per, flip, first);
+  } else if (X.bx == 256) {
+    launch_batch_ab<S, 256, 1>(X, st, grid, total, per, flip, first);
+  } else {
+    launch_batch_ab<S, 64, 4>(X, st, grid, total, per, flip, first);
   }
+  if (nmov)
+    hipLaunchKernelGGL((k_body_step_batch<T>), dim3(nmov), dim3(BODY_NT), 0, st, descs, X.moving_dev, flip);
+}
+
+void launch_batch(const BatchExec &X, hipStream_t st, int total, int nmov, int flip, int first) {
+  switch (X.prec) {
+    case VPLBM_F64: launch_batch_pair<double>(X, st, total, nmov, flip, first); break;
+    case VPLBM_F32: launch_batch_pair<float>(X, st, total, nmov, flip, first); break;
+    default: launch_batch_pair<__half>(X, st, total, nmov, flip, first); break;
+  }
+}
+
+// the tile table (lattice of every global tile) from the descriptors just
+// uploaded, on the device
+void launch_fill_tiles(const BatchExec &X, int nact, int total) {
+  const dim3 grid((total + 255) / 256), block(256);
+  switch (X.prec) {
+    case VPLBM_F64:
+      hipLaunchKernelGGL((k_fill_tile_case<double>), grid, block, 0, X.stream, (const CaseDesc<double> *)X.desc_dev,
+                         nact, total, X.tile_dev);
+      break;
+    case VPLBM_F32:
+      hipLaunchKernelGGL((k_fill_tile_case<float>), grid, block, 0, X.stream, (const CaseDesc<float> *)X.desc_dev,
+                         nact, total, X.tile_dev);
+      break;
+    default:
+      hipLaunchKernelGGL((k_fill_tile_case<float>), grid, block, 0, X.stream, (const CaseDesc<float> *)X.desc_dev,
+                         nact, total, X.tile_dev);
+      break;
+  }
+}
+
+// step pairs per captured graph: one launch call per group keeps the host
+// ahead of short kernels
+constexpr int GRAPH_PAIRS = 16;
+
+// Advance lattice k by nsteps[k] steps with batched launches (see
+// vplbm_batch_step).  Chunks run while some lattice has steps left; a chunk
+// advances every active lattice by the smallest remaining count.
+int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps, std::string &err) {
+  auto fail = [&](int code, const std::string &m) {
+    err = m;
+    return code;
+  };
+  auto hipck = [&](hipError_t e, const char *what) {
+    return e == hipSuccess ? VPLBM_OK : fail(VPLBM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  std::vector<long long> rem(n);
+  for (int k = 0; k < n; ++k) {
+    if (nsteps[k] < 0) return fail(VPLBM_EINVAL, "negative step count");
+    rem[k] = nsteps[k];
+  }
+  const size_t dsz = desc_size_of(X.prec);
+  std::vector<int> act;
+  act.reserve(n);
+  for (;;) {
+    act.clear();
+    long long chunk = 0;
+    for (int k = 0; k < n; ++k)
+      if (rem[k] > 0) {
+        act.push_back(k);
+        chunk = chunk == 0 ? rem[k] : std::min(chunk, rem[k]);
+      }
+    if (act.empty()) break;
+    // the host staging is rewritten below: the last chunk's copies must be done
+    int rc = hipck(hipStreamSynchronize(X.stream), "hipStreamSynchronize");
+    if (rc) return rc;
+    long long total = 0;
+    int nmov = 0;
+    for (size_t i = 0; i < act.size(); ++i) {
+      vplbm_lattice *L = lats[act[i]];
+      rc = resolve_pwin(L);
+      if (rc) return fail(rc, "lattice " + std::to_string(act[i]) + ": " + L->err);
+      void *slot = X.desc_host + i * dsz;
+      switch (X.prec) {
+        case VPLBM_F64: fill_desc<double>(L, (int)total, X.bx, X.by, slot); break;
+        case VPLBM_F32: fill_desc<float>(L, (int)total, X.bx, X.by, slot); break;
+        default: fill_desc<__half>(L, (int)total, X.bx, X.by, slot); break;
+      }
+      if (L->mode != MODE_STATIC) X.moving_host[nmov++] = (int)i;
+      total += batch_tiles(L, X.bx, X.by);
+    }
+    if (total > X.tile_cap)
+      return fail(VPLBM_EINVAL, "the batch's " + std::to_string(total) + " tiles exceed the tile table (" +
+                                    std::to_string(X.tile_cap) + ")");
+    const int nact = (int)act.size();
+    rc = hipck(hipMemcpyAsync(X.desc_dev, X.desc_host, dsz * nact, hipMemcpyHostToDevice, X.stream),
+               "batch descriptors");
+    if (!rc && nmov)
+      rc = hipck(hipMemcpyAsync(X.moving_dev, X.moving_host, sizeof(int) * nmov, hipMemcpyHostToDevice, X.stream),
+                 "batch moving list");
+    if (rc) return rc;
+    (void)hipGetLastError();
+    launch_fill_tiles(X, nact, (int)total);
+    rc = hipck(hipGetLastError(), "k_fill_tile_case");
+    if (rc) return rc;
+    // launch 0 eagerly (it finalizes what the lattices left pending), then
+    // pairs of launches (parities 1, 0), from a captured graph when allowed,
+    // then a last one
+    launch_batch(X, X.stream, (int)total, nmov, 0, 1);
+    rc = hipck(hipGetLastError(), "k_step_batch");
+    if (rc) return rc;
+    long long done = 1;
+    const long long pairs = (chunk - 1) / 2;
+    // whole groups of GRAPH_PAIRS pairs replay from the graph (one launch
+    // call per group); the remaining pairs are launched directly
+    const long long groups = X.graph ? pairs / GRAPH_PAIRS : 0;
+    if (groups > 0) {
+      const long long key = ((long long)nact << 40) ^ (total << 12) ^ ((long long)X.bx << 4) ^ nmov;
+      if (!*X.graph || *X.graph_key != key) {
+        if (*X.graph) (void)hipGraphExecDestroy(*X.graph);
+        *X.graph = nullptr;
+        hipGraph_t g = nullptr;
+        rc = hipck(hipStreamBeginCapture(X.cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (rc) return rc;
+        for (int q = 0; q < GRAPH_PAIRS; ++q) {
+          launch_batch(X, X.cap_stream, (int)total, nmov, 1, 0);
+          launch_batch(X, X.cap_stream, (int)total, nmov, 0, 0);
+        }
+        rc = hipck(hipStreamEndCapture(X.cap_stream, &g), "end capture");
+        if (!rc) rc = hipck(hipGraphInstantiate(X.graph, g, nullptr, nullptr, 0), "graph instantiate");
+        if (g) (void)hipGraphDestroy(g);
+        if (rc) return rc;
+        *X.graph_key = key;
+      }
+      for (long long p = 0; p < groups && !rc; ++p) rc = hipck(hipGraphLaunch(*X.graph, X.stream), "graph launch");
+      if (rc) return rc;
+      done += 2 * GRAPH_PAIRS * groups;
+    }
+    for (long long p = groups * GRAPH_PAIRS; p < pairs; ++p) {
+      launch_batch(X, X.stream, (int)total, nmov, 1, 0);
+      launch_batch(X, X.stream, (int)total, nmov, 0, 0);
+      rc = hipck(hipGetLastError(), "k_step_batch");
+      if (rc) return rc;
+      done += 2;
+    }
+    if (done < chunk) {
+      launch_batch(X, X.stream, (int)total, nmov, 1, 0);
+      rc = hipck(hipGetLastError(), "k_step_batch");
+      if (rc) return rc;
+      ++done;
+    }
+    for (int k : act) {
+      vplbm_lattice *L = lats[k];
+      L->nstep += chunk;
+      L->cur ^= (int)(chunk & 1);
+      L->pending = L->mode == MODE_STATIC;
+      L->macro_valid = false;
+      rem[k] -= chunk;
+    }
+  }
+  return VPLBM_OK;
 }
 
 }  // namespace
@@ -1649,17 +1838,13 @@ void launch_batch(vplbm_batch *B, hipStream_t st, int nact, int total, int nmov,
 extern "C" {
 
 int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out) {
-  if (!out || !lats || n < 1) return VPLBM_EINVAL;
+  if (!out) return VPLBM_EINVAL;
   *out = nullptr;
-  const int prec = lats[0]->p.precision;
-  for (int k = 0; k < n; ++k) {
-    if (!lats[k] || lats[k]->p.precision != prec || lats[k]->stream != lats[0]->stream) return VPLBM_EINVAL;
-    if ((lats[k]->p.trt_lambda > 0.0) != (lats[0]->p.trt_lambda > 0.0)) return VPLBM_EINVAL;
-    if (lats[k]->aa() != lats[0]->aa())
-      return lats[k]->fail(VPLBM_EINVAL, "a batch takes lattices of one storage scheme (all AB or all AA)");
-    for (int j = 0; j < k; ++j)
-      if (lats[j] == lats[k]) return VPLBM_EINVAL;
+  if (const char *why = batch_check(lats, n)) {
+    if (lats && n >= 1 && lats[0]) lats[0]->fail(VPLBM_EINVAL, "%s", why);
+    return VPLBM_EINVAL;
   }
+  const int prec = lats[0]->p.precision;
   auto *B = new (std::nothrow) vplbm_batch();
   if (!B) return VPLBM_ENOMEM;
   B->cases.assign(lats, lats + n);
@@ -1696,128 +1881,66 @@ int vplbm_batch_destroy(vplbm_batch *B) {
 
 const char *vplbm_batch_last_error(const vplbm_batch *B) { return B ? B->err.c_str() : "null batch"; }
 
-// step pairs per captured graph: one launch call per group keeps the host
-// ahead of short kernels
-constexpr int GRAPH_PAIRS = 16;
+int vplbm_batch_set_tile(vplbm_batch *B, int bx, int by) {
+  if (!B) return VPLBM_EINVAL;
+  if (!batch_tile_ok(bx, by)) return B->fail(VPLBM_EINVAL, "batched launches run 64x4, 128x2 or 256x1 tiles");
+  if (B->aa && (bx != 64 || by != 4)) return B->fail(VPLBM_EINVAL, "a batch of AA lattices runs 64x4 tiles");
+  if (bx != B->bx || by != B->by) {
+    if (B->graph) (void)hipGraphExecDestroy(B->graph);
+    B->graph = nullptr;
+    B->graph_key = -1;
+  }
+  B->bx = bx;
+  B->by = by;
+  return VPLBM_OK;
+}
+
+int vplbm_batch_get_tile(const vplbm_batch *B, int *bx, int *by) {
+  if (!B || !bx || !by) return VPLBM_EINVAL;
+  *bx = B->bx;
+  *by = B->by;
+  return VPLBM_OK;
+}
 
 int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
   if (!B || !nsteps) return VPLBM_EINVAL;
   const int n = (int)B->cases.size();
-  std::vector<long long> rem(n);
-  for (int k = 0; k < n; ++k) {
-    if (nsteps[k] < 0) return B->fail(VPLBM_EINVAL, "negative step count");
-    rem[k] = nsteps[k];
+  // the tile table holds the tiles of every lattice (its size when all are active)
+  long long need = 0;
+  for (vplbm_lattice *L : B->cases) need += batch_tiles(L, B->bx, B->by);
+  if (need > B->tile_case_cap) {
+    int rc = B->hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");
+    if (rc) return rc;
+    if (B->tile_case_dev) (void)hipFree(B->tile_case_dev);
+    B->tile_case_dev = nullptr;
+    B->tile_case_cap = 0;
+    if (B->graph) (void)hipGraphExecDestroy(B->graph);  // it holds the old table's address
+    B->graph = nullptr;
+    B->graph_key = -1;
+    rc = B->hip(hipMalloc((void **)&B->tile_case_dev, sizeof(int) * (size_t)need), "tile table");
+    if (rc) return rc;
+    B->tile_case_cap = need;
   }
-  const size_t dsz = desc_size_of(B->prec);
-  for (;;) {
-    // active set of this chunk and its length (every active lattice advances)
-    std::vector<int> act;
-    long long chunk = 0;
-    for (int k = 0; k < n; ++k)
-      if (rem[k] > 0) {
-        act.push_back(k);
-        chunk = chunk == 0 ? rem[k] : std::min(chunk, rem[k]);
-      }
-    if (act.empty()) break;
-    int rc = B->hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");  // host buffers reusable
-    if (rc) return rc;
-    int total = 0, nmov = 0;
-    for (size_t i = 0; i < act.size(); ++i) {
-      vplbm_lattice *L = B->cases[act[i]];
-      rc = resolve_pwin(L);
-      if (rc) return B->fail(rc, "lattice " + std::to_string(act[i]) + ": " + L->err);
-      const int tiles = L->step_args<float>(BATCH_BX, BATCH_BY).ntiles;
-      switch (B->prec) {
-        case VPLBM_F64: fill_desc<double>(L, total, &B->desc_host[i * dsz]); break;
-        case VPLBM_F32: fill_desc<float>(L, total, &B->desc_host[i * dsz]); break;
-        default: fill_desc<__half>(L, total, &B->desc_host[i * dsz]); break;
-      }
-      if (L->mode != MODE_STATIC) B->moving_host[nmov++] = (int)i;
-      total += tiles;
-    }
-    const int nact = (int)act.size();
-    B->tile_case_host.resize(total);
-    for (int i = 0, t = 0; i < nact; ++i) {
-      const int tiles = B->cases[act[i]]->step_args<float>(BATCH_BX, BATCH_BY).ntiles;
-      for (int j = 0; j < tiles; ++j) B->tile_case_host[t++] = i;
-    }
-    if ((size_t)total > B->tile_case_cap) {
-      if (B->tile_case_dev) (void)hipFree(B->tile_case_dev);
-      B->tile_case_dev = nullptr;
-      B->tile_case_cap = 0;
-      if (B->graph) (void)hipGraphExecDestroy(B->graph);
-      B->graph = nullptr;
-      rc = B->hip(hipMalloc((void **)&B->tile_case_dev, sizeof(int) * (size_t)total), "tile table");
-      if (rc) return rc;
-      B->tile_case_cap = total;
-    }
-    rc = B->hip(hipMemcpyAsync(B->tile_case_dev, B->tile_case_host.data(), sizeof(int) * (size_t)total,
-                               hipMemcpyHostToDevice, B->stream),
-                "tile table");
-    if (rc) return rc;
-    rc = B->hip(hipMemcpyAsync(B->desc_dev, B->desc_host.data(), dsz * nact, hipMemcpyHostToDevice, B->stream),
-                "batch descriptors");
-    if (!rc && nmov)
-      rc = B->hip(hipMemcpyAsync(B->moving_dev, B->moving_host.data(), sizeof(int) * nmov, hipMemcpyHostToDevice,
-                                 B->stream),
-                  "batch moving list");
-    if (rc) return rc;
-    // launch 0 eagerly (it finalizes what the lattices left pending), then
-    // pairs of launches (parities 1, 0) from a captured graph, then a last one
-    (void)hipGetLastError();
-    launch_batch(B, B->stream, nact, total, nmov, 0, 1);
-    rc = B->hip(hipGetLastError(), "k_step_batch");
-    if (rc) return rc;
-    long long done = 1;
-    const long long pairs = (chunk - 1) / 2;
-    // whole groups of GRAPH_PAIRS pairs replay from the graph (one launch
-    // call per group); the remaining pairs are launched directly
-    const long long groups = pairs / GRAPH_PAIRS;
-    if (groups > 0) {
-      const long long key = ((long long)nact << 40) ^ ((long long)total << 12) ^ nmov;
-      if (!B->graph || B->graph_key != key) {
-        if (B->graph) (void)hipGraphExecDestroy(B->graph);
-        B->graph = nullptr;
-        hipGraph_t g = nullptr;
-        rc = B->hip(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-        if (rc) return rc;
-        for (int q = 0; q < GRAPH_PAIRS; ++q) {
-          launch_batch(B, B->cap_stream, nact, total, nmov, 1, 0);
-          launch_batch(B, B->cap_stream, nact, total, nmov, 0, 0);
-        }
-        rc = B->hip(hipStreamEndCapture(B->cap_stream, &g), "end capture");
-        if (!rc) rc = B->hip(hipGraphInstantiate(&B->graph, g, nullptr, nullptr, 0), "graph instantiate");
-        if (g) (void)hipGraphDestroy(g);
-        if (rc) return rc;
-        B->graph_key = key;
-      }
-      for (long long p = 0; p < groups && !rc; ++p) rc = B->hip(hipGraphLaunch(B->graph, B->stream), "graph launch");
-      if (rc) return rc;
-      done += 2 * GRAPH_PAIRS * groups;
-    }
-    for (long long p = groups * GRAPH_PAIRS; p < pairs; ++p) {
-      launch_batch(B, B->stream, nact, total, nmov, 1, 0);
-      launch_batch(B, B->stream, nact, total, nmov, 0, 0);
-      rc = B->hip(hipGetLastError(), "k_step_batch");
-      if (rc) return rc;
-      done += 2;
-    }
-    if (done < chunk) {
-      launch_batch(B, B->stream, nact, total, nmov, 1, 0);
-      rc = B->hip(hipGetLastError(), "k_step_batch");
-      if (rc) return rc;
-      ++done;
-    }
-    for (int k : act) {
-      vplbm_lattice *L = B->cases[k];
-      L->nstep += chunk;
-      L->cur ^= (int)(chunk & 1);
-      L->pending = L->mode == MODE_STATIC;
-      L->macro_valid = false;
-      rem[k] -= chunk;
-    }
-  }
-  return VPLBM_OK;
+  BatchExec X;
+  X.prec = B->prec;
+  X.trt = B->trt;
+  X.aa = B->aa;
+  X.bx = B->bx;
+  X.by = B->by;
+  X.stream = B->stream;
+  X.desc_dev = B->desc_dev;
+  X.moving_dev = B->moving_dev;
+  X.tile_dev = B->tile_case_dev;
+  X.tile_cap = B->tile_case_cap;
+  X.desc_host = B->desc_host.data();
+  X.moving_host = B->moving_host.data();
+  X.cap_stream = B->cap_stream;
+  X.graph = &B->graph;
+  X.graph_key = &B->graph_key;
+  std::string err;
+  const int rc = batch_run(X, B->cases.data(), n, nsteps, err);
+  if (rc) B->err = err;
+  return rc;
 }
 
 }  // extern "C"

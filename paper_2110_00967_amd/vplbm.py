@@ -40,7 +40,7 @@ EXPORTS = [
     "vplbm_read_populations", "vplbm_read_mask", "vplbm_read_macro_window", "vplbm_read_populations_window",
     "vplbm_batch_create", "vplbm_batch_destroy", "vplbm_batch_last_error", "vplbm_batch_step",
     "vplbm_set_body_ids", "vplbm_set_si_points_body", "vplbm_forces_body", "vplbm_force_history_body",
-    "vplbm_read_macro_device",
+    "vplbm_read_macro_device", "vplbm_batch_set_tile", "vplbm_batch_get_tile",
 ]
 
 
@@ -126,6 +126,8 @@ def load_library(path: str = LIB_PATH):
     L.vplbm_batch_last_error.argtypes = [vp]
     L.vplbm_batch_last_error.restype = C.c_char_p
     L.vplbm_batch_step.argtypes = [vp, P(C.c_int)]
+    L.vplbm_batch_set_tile.argtypes = [vp, ip, ip]
+    L.vplbm_batch_get_tile.argtypes = [vp, P(C.c_int), P(C.c_int)]
     for name in EXPORTS:
         if name not in ("vplbm_required_bytes", "vplbm_last_error", "vplbm_step_count", "vplbm_batch_last_error"):
             getattr(L, name).restype = C.c_int
@@ -415,6 +417,20 @@ class Batch:
         if rc != OK:
             raise VplbmError(rc, self._lib.vplbm_batch_last_error(self._h).decode(errors="replace"))
 
+    def set_tile(self, bx, by):
+        rc = self._lib.vplbm_batch_set_tile(self._h, int(bx), int(by))
+        if rc != OK:
+            raise VplbmError(rc, self._lib.vplbm_batch_last_error(self._h).decode(errors="replace"))
+
+    @property
+    def tile(self):
+        """(bx, by): the tile of the batched launches."""
+        bx, by = C.c_int(0), C.c_int(0)
+        rc = self._lib.vplbm_batch_get_tile(self._h, C.byref(bx), C.byref(by))
+        if rc != OK:
+            raise VplbmError(rc, "vplbm_batch_get_tile failed")
+        return bx.value, by.value
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.vplbm_batch_destroy(self._h)
@@ -425,3 +441,4 @@ class Batch:
             self.close()
         except Exception:
             pass
+

@@ -259,3 +259,51 @@ def test_batch_rejects_mixed_storage():
     assert e.value.code == V.EINVAL
     a.close()
     c.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16dev"])
+def test_batch_tiles_give_the_same_bits(precision):
+    # the tile of the batched launches (vplbm_batch_set_tile) changes the
+    # workgroup shape only: every tile gives the 64x4 result bit for bit,
+    # through the captured-graph path (40 steps) and a short chunk
+    from paper_2110_00967_amd import vplbm as V
+    specs = mixed_specs()
+    nsteps = [40, 17, 33, 5, 26, 35]
+    runs = {}
+    for tile in ((64, 4), (128, 2), (256, 1)):
+        say("batch tile", tile, precision)
+        lats = [build_gpu(s, precision) for s in specs]
+        b = V.Batch(lats)
+        b.set_tile(*tile)
+        assert b.tile == tile
+        b.step(nsteps)
+        runs[tile] = [state(g) for g in lats]
+        b.close()
+        for g in lats:
+            g.close()
+    for tile in ((128, 2), (256, 1)):
+        for k, (a, r) in enumerate(zip(runs[tile], runs[(64, 4)])):
+            for x, y in zip(a, r):
+                assert np.array_equal(x, y), (tile, k)
+
+
+def test_batch_tile_rules():
+    from paper_2110_00967_amd import vplbm as V
+    specs = mixed_specs()[:2]
+    say("batch tile rules")
+    lats = [build_gpu(s, "f32") for s in specs]
+    b = V.Batch(lats)
+    assert b.tile == (64, 4)
+    for bad in ((64, 2), (32, 8), (128, 4)):
+        with pytest.raises(V.VplbmError) as e:
+            b.set_tile(*bad)
+        assert e.value.code == V.EINVAL
+    assert b.tile == (64, 4)
+    b.close()
+    aa = [build_gpu(s, "f32", streaming=V.STREAM_AA) for s in specs]
+    b = V.Batch(aa)
+    with pytest.raises(V.VplbmError):
+        b.set_tile(128, 2)
+    b.close()
+    for g in lats + aa:
+        g.close()
