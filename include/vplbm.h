@@ -342,6 +342,22 @@ int vplbm_batch_step(vplbm_batch *b, const int *nsteps);
 int vplbm_batch_set_tile(vplbm_batch *b, int bx, int by);
 int vplbm_batch_get_tile(const vplbm_batch *b, int *bx, int *by);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work
+ * of vplbm_batch_step on lats[0..n) with nsteps[k] steps each, with 64x4
+ * tiles and direct launches (no graph), without allocating anything.  Its
+ * tables (lattice descriptors, moving list, the lattice of every tile) live
+ * in one static device array of the library, about 4.1 MiB per GPU, held
+ * until the process ends; limits: n <= 256 lattices, 2^20 tiles of 64x4
+ * cells in all (VPLBM_EINVAL beyond, message on lats[0]).  The lattices obey
+ * the rules of vplbm_batch_create and are stepped on their common stream,
+ * which must belong to the current device.  Every call shares that device's
+ * array: calls are serialized inside the library (each returns after its
+ * queued work has finished), and work of another thread that uses the same
+ * lattices at the same time races.  Results are those of vplbm_batch_step,
+ * bit for bit. */
+int vplbm_batch_step_noalloc(vplbm_lattice *const *lats, int n, const int *nsteps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1833,6 +1834,32 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
   return VPLBM_OK;
 }
 
+// ---- scratch of the allocation-free batched step --------------------------
+// Descriptors, moving list and tile table of vplbm_batch_step_noalloc live in
+// one file-scope device array; every GPU the library runs on holds its own
+// copy until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr int NOALLOC_MAX_CASES = 256;
+constexpr long long NOALLOC_MAX_TILES = 1 << 20;
+constexpr size_t NOALLOC_DESC_BYTES = (size_t)NOALLOC_MAX_CASES * desc_size<double>();
+constexpr size_t NOALLOC_MOV_OFF = (NOALLOC_DESC_BYTES + 255) / 256 * 256;
+constexpr size_t NOALLOC_TILE_OFF = NOALLOC_MOV_OFF + 256 * ((NOALLOC_MAX_CASES * sizeof(int) + 255) / 256);
+constexpr size_t NOALLOC_BYTES = NOALLOC_TILE_OFF + (size_t)NOALLOC_MAX_TILES * sizeof(int);
+static_assert(desc_size<double>() >= desc_size<float>() && desc_size<double>() >= desc_size<__half>(),
+              "descriptor slots sized for the largest descriptor");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;  // guards the per-device addresses and the host staging below
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+unsigned char g_noalloc_desc_host[NOALLOC_DESC_BYTES];
+int g_noalloc_mov_host[NOALLOC_MAX_CASES];
+
 }  // namespace
 
 extern "C" {
@@ -1940,6 +1967,58 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
   std::string err;
   const int rc = batch_run(X, B->cases.data(), n, nsteps, err);
   if (rc) B->err = err;
+  return rc;
+}
+
+int vplbm_batch_step_noalloc(vplbm_lattice *const *lats, int n, const int *nsteps) {
+  if (!lats || n < 1 || !lats[0]) return VPLBM_EINVAL;
+  vplbm_lattice *L0 = lats[0];
+  if (!nsteps) return L0->fail(VPLBM_EINVAL, "NULL step counts");
+  if (const char *why = batch_check(lats, n)) return L0->fail(VPLBM_EINVAL, "%s", why);
+  if (n > NOALLOC_MAX_CASES)
+    return L0->fail(VPLBM_EINVAL, "vplbm_batch_step_noalloc takes at most %d lattices", NOALLOC_MAX_CASES);
+  long long need = 0;
+  for (int k = 0; k < n; ++k) need += batch_tiles(lats[k], 64, 4);
+  if (need > NOALLOC_MAX_TILES)
+    return L0->fail(VPLBM_EINVAL, "%lld tiles of 64x4 cells exceed the %lld of vplbm_batch_step_noalloc", need,
+                    NOALLOC_MAX_TILES);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    (void)hipGetLastError();
+    return L0->fail(VPLBM_EHIP, "no usable current device");
+  }
+  if (!g_scratch_ptr[dev]) {
+    // once per device, with that device current: the array's device address
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return L0->fail(VPLBM_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  char *base = (char *)g_scratch_ptr[dev];
+  BatchExec X;
+  X.prec = L0->p.precision;
+  X.trt = L0->p.trt_lambda > 0.0;
+  X.aa = L0->aa();
+  X.stream = L0->stream;
+  X.desc_dev = base;
+  X.moving_dev = (int *)(base + NOALLOC_MOV_OFF);
+  X.tile_dev = (int *)(base + NOALLOC_TILE_OFF);
+  X.tile_cap = NOALLOC_MAX_TILES;
+  X.desc_host = (char *)g_noalloc_desc_host;
+  X.moving_host = g_noalloc_mov_host;
+  std::string err;
+  const int rc = batch_run(X, lats, n, nsteps, err);
+  if (rc) L0->err = err;
+  if (!rc) {
+    // the host staging is reused by the next call: its copies must be done
+    // before the lock is released
+    const hipError_t e = hipStreamSynchronize(X.stream);
+    if (e != hipSuccess) return L0->fail(VPLBM_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  }
   return rc;
 }
 

@@ -40,7 +40,7 @@ EXPORTS = [
     "vplbm_read_populations", "vplbm_read_mask", "vplbm_read_macro_window", "vplbm_read_populations_window",
     "vplbm_batch_create", "vplbm_batch_destroy", "vplbm_batch_last_error", "vplbm_batch_step",
     "vplbm_set_body_ids", "vplbm_set_si_points_body", "vplbm_forces_body", "vplbm_force_history_body",
-    "vplbm_read_macro_device", "vplbm_batch_set_tile", "vplbm_batch_get_tile",
+    "vplbm_read_macro_device", "vplbm_batch_set_tile", "vplbm_batch_get_tile", "vplbm_batch_step_noalloc",
 ]
 
 
@@ -128,6 +128,7 @@ def load_library(path: str = LIB_PATH):
     L.vplbm_batch_step.argtypes = [vp, P(C.c_int)]
     L.vplbm_batch_set_tile.argtypes = [vp, ip, ip]
     L.vplbm_batch_get_tile.argtypes = [vp, P(C.c_int), P(C.c_int)]
+    L.vplbm_batch_step_noalloc.argtypes = [P(vp), ip, P(C.c_int)]
     for name in EXPORTS:
         if name not in ("vplbm_required_bytes", "vplbm_last_error", "vplbm_step_count", "vplbm_batch_last_error"):
             getattr(L, name).restype = C.c_int
@@ -442,3 +443,14 @@ class Batch:
         except Exception:
             pass
 
+
+def batch_step_noalloc(lattices, nsteps):
+    """vplbm_batch_step_noalloc: step the lattices together without any
+    device allocation (the library's static tables; see include/vplbm.h)."""
+    lib = load_library()
+    lats = list(lattices)
+    arr = (C.c_void_p * len(lats))(*[l._h.value for l in lats])
+    n = (C.c_int * len(lats))(*[int(v) for v in nsteps])
+    rc = lib.vplbm_batch_step_noalloc(arr, len(lats), n)
+    if rc != OK:
+        raise VplbmError(rc, lib.vplbm_last_error(lats[0]._h).decode(errors="replace"))
