@@ -335,6 +335,13 @@ const char *vplbm_batch_last_error(const vplbm_batch *b);
  * with steps left run together; a lattice drops out when its count is
  * reached.  Forces, histories and states are read per lattice afterwards. */
 int vplbm_batch_step(vplbm_batch *b, const int *nsteps);
+/* Replace the lattices of a batch (the rules of vplbm_batch_create; the
+ * same precision, collision, stream and storage as the batch's first
+ * lattices).  The device tables grow only when n exceeds every earlier
+ * count, and a captured graph of the same launch shape is reused: a
+ * continuous-batching server changes the resident set without rebuilding
+ * the batch. */
+int vplbm_batch_set_lattices(vplbm_batch *b, vplbm_lattice *const *lats, int n);
 /* Tile of the batched launches (workgroup shape, not a choice the paper
  * makes): 64x4 (default), 128x2 or 256x1 cells; a batch of AA lattices runs
  * 64x4 only (VPLBM_EINVAL otherwise).  Results do not depend on it (forces

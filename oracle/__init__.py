@@ -87,6 +87,22 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops (streaming and collision rows);
+    returns the number now in effect.  For timing the oracle on the host."""
+    L = lib()
+    L.omp_set_num_threads.argtypes = [C.c_int]
+    L.omp_get_max_threads.restype = C.c_int
+    L.omp_set_num_threads(int(n))
+    return int(L.omp_get_max_threads())
+
+
+def max_threads() -> int:
+    L = lib()
+    L.omp_get_max_threads.restype = C.c_int
+    return int(L.omp_get_max_threads())
+
+
 # ----------------------------------------------------------------------------
 # thin per-cell helpers (used by the pins)
 # ----------------------------------------------------------------------------

@@ -1908,6 +1908,38 @@ int vplbm_batch_destroy(vplbm_batch *B) {
 
 const char *vplbm_batch_last_error(const vplbm_batch *B) { return B ? B->err.c_str() : "null batch"; }
 
+int vplbm_batch_set_lattices(vplbm_batch *B, vplbm_lattice *const *lats, int n) {
+  if (!B) return VPLBM_EINVAL;
+  if (const char *why = batch_check(lats, n)) return B->fail(VPLBM_EINVAL, why);
+  if (lats[0]->p.precision != B->prec || lats[0]->stream != B->stream ||
+      (lats[0]->p.trt_lambda > 0.0) != B->trt || lats[0]->aa() != B->aa)
+    return B->fail(VPLBM_EINVAL, "the lattices differ from the batch's precision, stream, collision or storage");
+  if ((size_t)n > B->moving_host.size()) {
+    // room for n descriptors: wait for the work that reads the old tables
+    int rc = B->hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");
+    if (rc) return rc;
+    char *d = nullptr;
+    int *m = nullptr;
+    if (hipMalloc((void **)&d, desc_size_of(B->prec) * n) != hipSuccess ||
+        hipMalloc((void **)&m, sizeof(int) * n) != hipSuccess) {
+      (void)hipGetLastError();
+      if (d) (void)hipFree(d);
+      return B->fail(VPLBM_ENOMEM, "batch tables");
+    }
+    (void)hipFree(B->desc_dev);
+    (void)hipFree(B->moving_dev);
+    B->desc_dev = d;
+    B->moving_dev = m;
+    B->desc_host.assign(desc_size_of(B->prec) * n, 0);
+    B->moving_host.assign(n, 0);
+    if (B->graph) (void)hipGraphExecDestroy(B->graph);  // it holds the old tables' addresses
+    B->graph = nullptr;
+    B->graph_key = -1;
+  }
+  B->cases.assign(lats, lats + n);
+  return VPLBM_OK;
+}
+
 int vplbm_batch_set_tile(vplbm_batch *B, int bx, int by) {
   if (!B) return VPLBM_EINVAL;
   if (!batch_tile_ok(bx, by)) return B->fail(VPLBM_EINVAL, "batched launches run 64x4, 128x2 or 256x1 tiles");

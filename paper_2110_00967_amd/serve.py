@@ -57,7 +57,7 @@ class Request:
 class GpuEngine:
     """Lattices in torch-allocated HBM, stepped through the C ABI."""
 
-    def __init__(self, precision="f32", streaming=0):
+    def __init__(self, precision="f32", streaming=0, tile=None):
         import torch
 
         from . import vplbm as V
@@ -66,6 +66,8 @@ class GpuEngine:
         self.streaming = int(streaming)  # STREAM_AB or STREAM_AA (half the population memory)
         self._batch = None
         self._batch_key = None
+        self.tile = tile  # tile of the batched launches (None: the library's default)
+        self.batches_created = 0
 
     def _params(self, case):
         # the parameters create() builds its lattice from
@@ -78,12 +80,19 @@ class GpuEngine:
         return self.V.Lattice.from_case(case, precision=self.precision, hist_capacity=16, streaming=self.streaming)
 
     def step(self, handles, nsteps):
+        # one batch for the engine's lifetime: a new resident set only
+        # replaces its lattices (vplbm_batch_set_lattices), so membership
+        # changes cost no device allocation, stream or graph rebuild beyond
+        # a new launch shape
         key = tuple(id(h) for h in handles)
-        if key != self._batch_key:
-            if self._batch is not None:
-                self._batch.close()
+        if self._batch is None:
             self._batch = self.V.Batch(handles)
-            self._batch_key = key
+            self.batches_created += 1
+            if self.tile is not None:
+                self._batch.set_tile(*self.tile)
+        elif key != self._batch_key:
+            self._batch.set_lattices(handles)
+        self._batch_key = key
         self._batch.step(nsteps)
 
     def sync(self):
@@ -95,10 +104,16 @@ class GpuEngine:
 
     def release(self, h):
         if self._batch is not None and id(h) in (self._batch_key or ()):
-            self._batch.close()
-            self._batch, self._batch_key = None, None
+            # the batch must not keep a destroyed lattice: the next step()
+            # hands it the new resident set
+            self._batch_key = None
         h.close()
         h._buf = None
+
+    def close(self):
+        if self._batch is not None:
+            self._batch.close()
+            self._batch, self._batch_key = None, None
 
 
 class Server:
@@ -118,6 +133,8 @@ class Server:
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
         self.events: List[tuple] = []   # (time, kind, rid) for inspection
+        self.peak_bytes = 0             # most resident bytes at any time
+        self.peak_resident = 0          # most resident requests at any time
 
     def _chunk_steps(self, resident: List[Request]) -> List[int]:
         """Steps each resident request advances in the next chunk (0 = waits)."""
@@ -163,6 +180,8 @@ class Server:
                 r.t_admit = now()
                 used += r.nbytes
                 resident.append(r)
+                self.peak_bytes = max(self.peak_bytes, used)
+                self.peak_resident = max(self.peak_resident, len(resident))
                 self.events.append((r.t_admit, "admit", r.rid))
             if not resident:
                 if future:

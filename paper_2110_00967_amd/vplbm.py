@@ -40,7 +40,7 @@ EXPORTS = [
     "vplbm_read_populations", "vplbm_read_mask", "vplbm_read_macro_window", "vplbm_read_populations_window",
     "vplbm_batch_create", "vplbm_batch_destroy", "vplbm_batch_last_error", "vplbm_batch_step",
     "vplbm_set_body_ids", "vplbm_set_si_points_body", "vplbm_forces_body", "vplbm_force_history_body",
-    "vplbm_read_macro_device", "vplbm_batch_set_tile", "vplbm_batch_get_tile", "vplbm_batch_step_noalloc",
+    "vplbm_read_macro_device", "vplbm_batch_set_tile", "vplbm_batch_get_tile", "vplbm_batch_set_lattices", "vplbm_batch_step_noalloc",
 ]
 
 
@@ -127,6 +127,7 @@ def load_library(path: str = LIB_PATH):
     L.vplbm_batch_last_error.restype = C.c_char_p
     L.vplbm_batch_step.argtypes = [vp, P(C.c_int)]
     L.vplbm_batch_set_tile.argtypes = [vp, ip, ip]
+    L.vplbm_batch_set_lattices.argtypes = [vp, P(vp), ip]
     L.vplbm_batch_get_tile.argtypes = [vp, P(C.c_int), P(C.c_int)]
     L.vplbm_batch_step_noalloc.argtypes = [P(vp), ip, P(C.c_int)]
     for name in EXPORTS:
@@ -417,6 +418,15 @@ class Batch:
         rc = self._lib.vplbm_batch_step(self._h, n)
         if rc != OK:
             raise VplbmError(rc, self._lib.vplbm_batch_last_error(self._h).decode(errors="replace"))
+
+    def set_lattices(self, lattices):
+        """Replace the batch's lattices (same precision, collision, stream, storage)."""
+        lats = list(lattices)
+        arr = (C.c_void_p * len(lats))(*[l._h.value for l in lats])
+        rc = self._lib.vplbm_batch_set_lattices(self._h, arr, len(lats))
+        if rc != OK:
+            raise VplbmError(rc, self._lib.vplbm_batch_last_error(self._h).decode(errors="replace"))
+        self.lattices = lats
 
     def set_tile(self, bx, by):
         rc = self._lib.vplbm_batch_set_tile(self._h, int(bx), int(by))

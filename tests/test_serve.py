@@ -202,3 +202,6 @@ def test_gpu_mix_equals_alone(streaming):
         g.close()
     s = summarize(out)
     say(f"served: p50 {s['p50_latency_s'] * 1e3:.1f} ms, p99 {s['p99_latency_s'] * 1e3:.1f} ms")
+    # one batch served every resident set (membership changes replace its lattices)
+    assert eng.batches_created == 1
+    eng.close()
