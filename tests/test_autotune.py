@@ -19,21 +19,21 @@ def fake_measure(table, calls=None):
 
 def test_record_and_lookup_persist_per_arch(tmp_path):
     path = str(tmp_path / "tiles.json")
-    t = AT.TileTuner(path=path, arch="gfx950")
+    t = AT.TileTuner(path=path, arch="gfx950", defaults=None)
     assert t.lookup("batch/f32/AB/pop8192MiB/n9-64") is None
     best = AT.tune(AT.BATCH_TILES, fake_measure({(64, 4): 1000.7, (128, 2): 998.2, (256, 1): 1003.6}), t,
                    "batch/f32/AB/pop8192MiB/n9-64")
     assert best == (128, 2)
     # a new tuner on the same file sees it; another architecture does not
-    again = AT.TileTuner(path=path, arch="gfx950")
+    again = AT.TileTuner(path=path, arch="gfx950", defaults=None)
     assert again.lookup("batch/f32/AB/pop8192MiB/n9-64") == (128, 2)
     assert again.timings("batch/f32/AB/pop8192MiB/n9-64") == {"64x4": 1000.7, "128x2": 998.2, "256x1": 1003.6}
-    other = AT.TileTuner(path=path, arch="gfx942")
+    other = AT.TileTuner(path=path, arch="gfx942", defaults=None)
     assert other.lookup("batch/f32/AB/pop8192MiB/n9-64") is None
     # recording for the other architecture keeps the first one's entry
     AT.tune(AT.BATCH_TILES, fake_measure({(64, 4): 1.0, (128, 2): 2.0, (256, 1): 3.0}), other, "k")
-    assert AT.TileTuner(path=path, arch="gfx950").lookup("batch/f32/AB/pop8192MiB/n9-64") == (128, 2)
-    assert AT.TileTuner(path=path, arch="gfx942").lookup("k") == (64, 4)
+    assert AT.TileTuner(path=path, arch="gfx950", defaults=None).lookup("batch/f32/AB/pop8192MiB/n9-64") == (128, 2)
+    assert AT.TileTuner(path=path, arch="gfx942", defaults=None).lookup("k") == (64, 4)
 
 
 def test_tune_times_each_candidate_per_round_and_keeps_the_best(tmp_path):
@@ -58,10 +58,10 @@ def test_ties_go_to_the_first_candidate(tmp_path):
 def test_corrupt_or_foreign_cache_starts_empty(tmp_path):
     path = tmp_path / "tiles.json"
     path.write_text("{not json")
-    t = AT.TileTuner(path=str(path), arch="gfx950")
+    t = AT.TileTuner(path=str(path), arch="gfx950", defaults=None)
     assert t.lookup("x") is None
     path.write_text(json.dumps({"version": 99, "arch": {"gfx950": {"x": {"tile": [64, 4]}}}}))
-    assert AT.TileTuner(path=str(path), arch="gfx950").lookup("x") is None
+    assert AT.TileTuner(path=str(path), arch="gfx950", defaults=None).lookup("x") is None
     # and it is rewritten in the current format on the next record
     AT.tune([(64, 4)], fake_measure({(64, 4): 1.0}), t, "x", rounds=1)
     d = json.loads(path.read_text())
@@ -105,3 +105,22 @@ def test_default_cache_path_follows_the_environment(monkeypatch, tmp_path):
     monkeypatch.delenv("VPLBM_TILE_CACHE")
     monkeypatch.setenv("XDG_CACHE_HOME", str(tmp_path))
     assert AT.default_cache_path() == os.path.join(str(tmp_path), "vplbm", "tiles.json")
+
+
+def test_shipped_defaults_are_the_fallback(tmp_path):
+    # classes missing from the user cache come from the shipped table; a
+    # user entry of the same class wins
+    t = AT.TileTuner(path=str(tmp_path / "tiles.json"), arch="gfx950")
+    shipped = t.shipped["arch"]["gfx950"]
+    assert "batch/f32/AB/pop8192MiB/n9-64" in shipped
+    for key, e in shipped.items():
+        assert tuple(e["tile"]) in AT.LATTICE_TILES
+        assert AT.tile_name(e["tile"]) in e["us"] and min(e["us"].values()) == e["us"][AT.tile_name(e["tile"])]
+        if key.startswith("batch/"):
+            assert tuple(e["tile"]) in AT.BATCH_TILES
+    key = "batch/f32/AB/pop8192MiB/n9-64"
+    assert t.lookup(key) == tuple(shipped[key]["tile"]) and t.entry(key)["source"] == "shipped"
+    AT.tune([(256, 1)], fake_measure({(256, 1): 1.0}), t, key, rounds=1)
+    assert t.lookup(key) == (256, 1) and t.entry(key)["source"] == "cache"
+    # another architecture sees none of the shipped gfx950 choices
+    assert AT.TileTuner(path=str(tmp_path / "tiles.json"), arch="gfx942").lookup(key) is None
