@@ -101,9 +101,13 @@ typedef struct {
   int max_interface_cells; /* momentum-exchange slots, one per interface cell
                         (a cell with a lattice link to the other phase);
                         0 = min(nx ny, 32 (nx + ny)).  Set-up fails with
-                        VPLBM_EINVAL when the geometry has more, and a
-                        moving disk needs at least (ceil(2r) + 20)^2, the
-                        square it renumbers every step */
+                        VPLBM_EINVAL when the geometry has more.  A moving
+                        disk keeps per-tile force sums here instead, for the
+                        64 x 4 tiles its window of 2 h + 1 cells a side can
+                        meet: 2 (ceil(2 h / 64) + 1) (ceil(2 h / 4) + 1)
+                        slots, h = ceil(the larger of its radius and its
+                        points' largest distance from its reference point)
+                        + 8 */
   int streaming;     /* population storage (not a choice the paper makes):
                         VPLBM_STREAM_AB (0) = two buffers, one read and one
                         written per step; VPLBM_STREAM_AA (1) = one buffer

@@ -185,6 +185,31 @@ struct SiRec {
   double ax, ay, txx, txy, tyy;
 };
 
+// A moving rigid disk (Eqs. dep1, theta2), stepped inside the step kernel:
+// the step that uses state S computes the disk's solid cells, interface
+// cells and sample nodes from S on the fly, inside a square window around
+// it, and every tile of the window stores the sums of its cells' force
+// terms (momentum exchange and stress integration); the next launch adds
+// those partial sums into the step's forces and advances the state.  States
+// alternate between two slots by the number of updates applied (see the step
+// kernel).
+constexpr int MAX_MOVERS = 4;
+constexpr int WIN_MARGIN = 8;   // window half size = ceil(largest radius of disk and points) + WIN_MARGIN
+constexpr int PART_ENTRY = 8;   // doubles per tile partial: ME Fx, Fy, T, SI Fx, Fy, T, -, -
+constexpr int MOV_BX = 64, MOV_BY = 4;  // the tile of the moving-disk step kernels
+struct MoverDev {
+  BodyDev B[2];        // state after k updates in slot k & 1
+  double r, mass, inertia, gx, gy, buoy;
+  long long R;         // radius on the 1/FIXQ grid
+  long long nfin;      // steps of this disk whose forces are in the history
+  int mode, source;    // MODE_PRESCRIBED or MODE_FREE; force driving a free disk (0 ME, 1 SI)
+  int half;            // window: (2 half + 1)^2 cells, lower corner at floor(x_G) - half
+  int pt0, pt1;        // its stress-integration points [pt0, pt1) (body frame)
+  int part0;           // its first tile partial in the partial buffers
+  int ptx, pty;        // its partials: a grid of ptx x pty tiles (room for any window position)
+  int mwin[4];         // mask bytes written by the last flush: x0, y0, x1, y1 (exclusive)
+};
+
 constexpr int ME_STRIDE = 4;    // doubles per interface slot (ME Fx, Fy, T of one cell)
 constexpr int SIG_STRIDE = 4;   // doubles per stress slot of a sample node (xx, xy, yy)
 constexpr int FIXQ = 4096;      // fixed-point grid of geometry coordinates

@@ -147,13 +147,9 @@ __global__ void k_read_macro(const T *__restrict__ r, const T *__restrict__ u, c
 }
 
 // ----------------------------------------------------------------------------
-// chi: exact inside tests on the 1/4096 grid (integer arithmetic)
+// chi: exact inside tests on the 1/4096 grid (integer arithmetic; disk_inside
+// is in sample.hpp)
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ bool disk_inside(long long X, long long Y, long long R, int i, int j) {
-  const long long dx = (long long)i * FIXQ - X, dy = (long long)j * FIXQ - Y;
-  return dx * dx + dy * dy <= R * R;
-}
-
 // even-odd rule; a centre exactly on an edge counts as inside
 __device__ __forceinline__ bool polygon_inside(const long long *__restrict__ vx,
                                                const long long *__restrict__ vy, int nv, int i, int j) {
@@ -237,106 +233,6 @@ __global__ void k_mask_flags(uint8_t *__restrict__ mask, int nx, int ny, int pit
 // ----------------------------------------------------------------------------
 constexpr int SI_NT = 1024;
 constexpr int SI_MAX = 4096;
-
-// Solid test of a lattice node for the sample-node search: the mask (any
-// geometry), or, for a moving disk alone in its lattice, the disk rule that
-// has just built its mask (the same answer without a memory round trip).
-struct MaskSolid {
-  const uint8_t *mask;
-  int pitch;
-  __device__ __forceinline__ bool operator()(int X, int Y) const {
-    return (mask[(long long)Y * pitch + X] & M_BODY) != 0;
-  }
-};
-struct DiskSolid {
-  long long X, Y, R;  // centre and radius on the 1/FIXQ grid
-  __device__ __forceinline__ bool operator()(int i, int j) const { return disk_inside(X, Y, R, i, j); }
-};
-
-// Sample node of a point: the lattice direction beta maximizing
-// (c_beta . n)/|c_beta| (first on ties), then the first fluid node inside the
-// lattice among r_0 + k c_beta, k = 0..4, r_0 the node nearest to the point.
-template <typename Solid>
-__device__ __forceinline__ int si_node(const Solid &solid, int nx, int ny, double px, double py, double n0,
-                                       double n1) {
-  const double S = 0.70710678118654752440;
-  double sc[Q];
-  sc[1] = n0;
-  sc[2] = n1;
-  sc[3] = -n0;
-  sc[4] = -n1;
-  sc[5] = (n0 + n1) * S;
-  sc[6] = (-n0 + n1) * S;
-  sc[7] = (-n0 - n1) * S;
-  sc[8] = (n0 - n1) * S;
-  int best = 1;
-#pragma unroll
-  for (int a = 2; a < Q; ++a)
-    if (sc[a] > sc[best]) best = a;
-  int bx = 0, by = 0;
-#pragma unroll
-  for (int a = 1; a < Q; ++a)
-    if (a == best) { bx = cx(a); by = cy(a); }
-  const int ix = (int)floor(px + 0.5), iy = (int)floor(py + 0.5);
-  for (int k = 0; k <= 4; ++k) {
-    const int X = ix + k * bx, Y = iy + k * by;
-    if (X < 0 || X >= nx || Y < 0 || Y >= ny) continue;
-    if (!solid(X, Y)) return Y * nx + X;
-  }
-  return -1;
-}
-
-// Stencil of an integration point: rule 0, the sample node above with weight
-// 1; rule 1, the bilinear interpolation at p = x + 1.5 n over the 4 nodes
-// around p when all are fluid and inside the lattice (rule 0 otherwise).
-// Returns the number of (node, weight) pairs, 0 when there is no sample node.
-// The interpolation point is formed without FMA contraction so the floor()
-// decisions match a plain evaluation.
-template <typename Solid>
-__device__ __forceinline__ int si_stencil(const Solid &solid, int nx, int ny, int rule, double px, double py,
-                                          double n0, double n1, int (&node)[4], double (&w)[4]) {
-  if (rule == 1) {
-    const double qx = __dadd_rn(px, __dmul_rn(1.5, n0)), qy = __dadd_rn(py, __dmul_rn(1.5, n1));
-    const int i0 = (int)floor(qx), j0 = (int)floor(qy);
-    if (i0 >= 0 && j0 >= 0 && i0 + 1 < nx && j0 + 1 < ny) {
-      const double fx = __dsub_rn(qx, (double)i0), fy = __dsub_rn(qy, (double)j0);
-      bool ok = true;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int X = i0 + (k & 1), Y = j0 + (k >> 1);
-        node[k] = Y * nx + X;
-        if (solid(X, Y)) ok = false;
-        w[k] = __dmul_rn((k & 1) ? fx : __dsub_rn(1.0, fx), (k >> 1) ? fy : __dsub_rn(1.0, fy));
-      }
-      if (ok) return 4;
-    }
-  }
-  node[0] = si_node(solid, nx, ny, px, py, n0, n1);
-  w[0] = 1.0;
-  return node[0] >= 0 ? 1 : 0;
-}
-
-// world position and normal of a point stored as (a, b) and normal (c, d)
-// (points of a moving body are kept in the body frame and placed with the
-// current state; co, sn = cos, sin of its angle)
-__device__ __forceinline__ void si_place(double a, double b, double c, double d, int moving, const BodyDev &B,
-                                         double co, double sn, double &px, double &py, double &n0, double &n1) {
-  if (!moving) {
-    px = a; py = b; n0 = c; n1 = d;
-    return;
-  }
-  px = B.x + (co * a - sn * b);
-  py = B.y + (sn * a + co * b);
-  n0 = co * c - sn * d;
-  n1 = sn * c + co * d;
-}
-
-// the same for registered point i
-__device__ __forceinline__ void si_world(const double *__restrict__ pts, int maxp, int i, int moving,
-                                         const BodyDev &B, double co, double sn, double &px, double &py,
-                                         double &n0, double &n1) {
-  si_place(pts[i], pts[maxp + i], pts[2 * maxp + i], pts[3 * maxp + i], moving, B, co, sn, px, py, n0, n1);
-}
 
 // Point threadIdx.x (position, normal, body), loaded ahead by a caller that
 // has other work to overlap with the loads; ok = false when not loaded.
@@ -686,161 +582,95 @@ __global__ void __launch_bounds__(SI_NT)
 }
 
 // ----------------------------------------------------------------------------
-// moving disk: rigid-body update, then rebuild chi and flags over the union of
-// the old and new regions (one workgroup)
+// moving disks between steps (one workgroup)
 // ----------------------------------------------------------------------------
-constexpr int BODY_NT = 1024;
-constexpr int INSIDE_LDS = 32768;  // bytes of disk tests the body kernel stages in LDS
-constexpr int REGION_MARGIN = 6;  // covers links (1) and sample walks (5)
+constexpr int REGION_MARGIN = 6;  // set-up: a disk's mask region around its box (links 1, sample walks 5)
+constexpr int FLUSH_NT = 256;
 
-__device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl,
-                                const double *__restrict__ me, const double *__restrict__ sig,
-                                double *__restrict__ hist, int cap, int maxb, int nx, int ny, int pitch,
-                                int perx, int pery, const double *__restrict__ pts, int maxp,
-                                SiRec *__restrict__ recs, int *__restrict__ si_map, int *__restrict__ imap,
-                                int maxslot, BodyTab *__restrict__ bt, const BodyDev *__restrict__ bodies) {
-  static_assert(BODY_NT == SI_NT, "the block scan assumes SI_NT threads");
-  __shared__ int reg[4];   // union region to rewrite
-  __shared__ long long q[3];
-  __shared__ double lds[FIN_WAVES * 6];
-  __shared__ int wsum[BODY_NT / 64];
-  __shared__ int nslot;
-  __shared__ double flast[6];  // forces of the step just taken (ME, SI)
-  __shared__ BodyDev Bnew;     // body state after the update
-  __shared__ double cs[2];     // cos, sin of its angle (for points in the body frame)
-  __shared__ int winsh[4];     // force window written by the update
-  // disk tests of the rebuild, then the points staged by the sample selection
-  __shared__ double lds_stage[INSIDE_LDS / sizeof(double)];
-  uint8_t *inside = (uint8_t *)lds_stage;
-  // Loads that do not depend on the finalize, issued first so their latency
-  // overlaps it: the control-block fields of the update (the finalize does
-  // not write them) and this thread's stress-integration point.
-  const BodyDev B0 = ctl->body;
-  const int mode = ctl->mode, source = ctl->source;
-  const double mass = ctl->mass, inertia = ctl->inertia, buoy = ctl->buoy, cgx = ctl->gx, cgy = ctl->gy;
-  const double crad = ctl->r;
-  const int oreg0 = ctl->region[0], oreg1 = ctl->region[1], oreg2 = ctl->region[2], oreg3 = ctl->region[3];
-  const int npts0 = ctl->npts, si_moving = ctl->si_moving, si_rule = ctl->si_rule;
-  const PtPre pre = si_prefetch(pts, maxp, npts0);
-  // the finalize's first slot and record per virtual lane, loaded with the
-  // control block instead of after the slot ranges (the disk is body 1 and
-  // the only body: its ranges start at 0; records fit maxp at least)
-  FinPre fp;
-  fp.me_ok = false;
-  fp.rec_ok = false;
-  if (threadIdx.x < FIN_W) {
-    const int t = threadIdx.x;
-    if (t < maxslot) {
+// After the launch of step N (pb = N & 1): the disks' forces of step N are
+// summed and their states advanced exactly as the next step launch would do
+// it (mover_prologue: the same sums in the same order, the same update), so
+// that forces, states and the mask can be read between steps; the next
+// launch then starts from these states.  The mask bytes of each disk's
+// window -- which the step launches never read for a lattice with moving
+// disks -- are rewritten from the new states: the bytes the last flush (or
+// the set-up) wrote are cleared, then solid ids and interface bits over
+// every window, then the sample bits of every point.
+__global__ void __launch_bounds__(FLUSH_NT)
+    k_mover_flush(MoverDev *__restrict__ mov, int nmov, const double *__restrict__ win, int pb,
+                  const double *__restrict__ pts, int maxp, int rule, int nx, int ny, int pitch, int perx, int pery,
+                  uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb) {
+  __shared__ double red[FIN_WAVES * 6];
+  __shared__ double cs[2];
+  __shared__ BodyDev st[MAX_MOVERS];
+  __shared__ long long fx[MAX_MOVERS], fy[MAX_MOVERS];
+  const int sread = pb ^ 1;
+  const int tiles_x = (nx + MOV_BX - 1) / MOV_BX, tiles_y = (ny + MOV_BY - 1) / MOV_BY;
+  for (int k = 0; k < nmov; ++k) {
+    MoverDev &M = mov[k];
+    const BodyDev B = M.B[sread];
+    double F[6];
+    mover_forces<FLUSH_NT>(M, B, win, tiles_x, tiles_y, red, F);
+    const BodyDev S = mover_update(M, B, F);
+    if (threadIdx.x == 0) {
+      st[k] = S;
+      fx[k] = fixq_of(S.x);
+      fy[k] = fixq_of(S.y);
+      M.B[pb] = S;
+      const long long n = M.nfin + 1;
+      double *hh = hist + ((n % cap) * maxb + k) * 6;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) fp.me[i] = me[(long long)t * ME_STRIDE + i];
-      fp.me_ok = true;
-    }
-    if (t < maxp) {
+      for (int i = 0; i < 6; ++i) hh[i] = F[i];
+      M.nfin = n;
+      if (k == 0) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) fp.g[i] = sig[(long long)t * SIG_STRIDE + i];
-      fp.R = recs[t];
-      fp.rec_ok = true;
+        for (int i = 0; i < 6; ++i) ctl->last[i] = F[i];
+        ctl->step = n;
+        ctl->body = S;
+      }
+      if (fabs(S.x - B.x) >= 1.0 || fabs(S.y - B.y) >= 1.0) atomicOr(&ctl->err, 32);
     }
-  }
-  // forces of the step just taken, needed by the update below (the only
-  // body: a moving disk is alone in its lattice)
-  finalize_block<BODY_NT>(me, sig, recs, bt, ctl, hist, cap, maxb, lds, flast, &fp);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    BodyDev B = B0;
-    if (mode == MODE_FREE) {
-      // Eqs. dep1/theta2, semi-implicit Euler, dt = 1
-      const double *F = flast + 3 * source;
-      B.u += F[0] / mass + buoy * cgx;
-      B.v += F[1] / mass + buoy * cgy;
-      B.omega += F[2] / inertia;
-    }
-    B.x += B.u;
-    B.y += B.v;
-    B.theta += B.omega;
-    ctl->body = B;
-    Bnew = B;
-    const long long X = llround(B.x * FIXQ), Y = llround(B.y * FIXQ), R = llround(crad * FIXQ);
-    ctl->fq[0] = X;
-    ctl->fq[1] = Y;
-    ctl->fq[2] = R;
-    q[0] = X;
-    q[1] = Y;
-    q[2] = R;
-    // bounding box of the disk (cells whose centre can be inside)
-    const int bx0 = (int)((X - R) / FIXQ) - 1, bx1 = (int)((X + R) / FIXQ) + 2;
-    const int by0 = (int)((Y - R) / FIXQ) - 1, by1 = (int)((Y + R) / FIXQ) + 2;
-    int nr[4] = {max(bx0 - REGION_MARGIN, 0), max(by0 - REGION_MARGIN, 0),
-                 min(bx1 + REGION_MARGIN, nx), min(by1 + REGION_MARGIN, ny)};
-    reg[0] = min(nr[0], oreg0);
-    reg[1] = min(nr[1], oreg1);
-    reg[2] = max(nr[2], oreg2);
-    reg[3] = max(nr[3], oreg3);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) ctl->region[k] = nr[k];
-    // force window: interface cells lie within one cell of the disk's box;
-    // the sample-node selection extends it afterwards
-    int wn[4] = {max(bx0 - 1, 0), max(by0 - 1, 0), min(bx1 + 1, nx), min(by1 + 1, ny)};
-    if (wn[2] <= wn[0] || wn[3] <= wn[1]) {
-      // body outside the lattice: keep a one-cell window so forces are still published
-      wn[0] = wn[1] = 0;
-      wn[2] = wn[3] = 1;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      ctl->win[k] = wn[k];
-      winsh[k] = wn[k];
-    }
-  } else if (threadIdx.x == 64) {
-    // the new angle as thread 0 forms it, and its cos and sin (in another
-    // wave, in parallel with the update)
-    double om = B0.omega;
-    if (mode == MODE_FREE) om += flast[3 * source + 2] / inertia;
-    const double th = B0.theta + om;
-    cs[0] = si_moving ? cos(th) : 1.0;
-    cs[1] = si_moving ? sin(th) : 0.0;
   }
   __syncthreads();
-  const int x0 = reg[0], y0 = reg[1], w = reg[2] - reg[0], h = reg[3] - reg[1];
-  const long long X = q[0], Y = q[1], R = q[2];
-  // this thread's cells are t = threadIdx.x + k BODY_NT; bit k of ifbits
-  // records an interface cell (rounds past 64 read the mask back)
-  unsigned long long ifbits = 0;
-  int cnt = 0;
-  // the disk test of every cell of the region and a one-cell ring around it
-  // (neighbours wrapped across periodic edges; 2 = no such neighbour), once
-  // per cell in LDS when it fits, instead of once per link
-  const int W2 = w + 2, H2 = h + 2;
-  const bool staged = W2 * H2 <= INSIDE_LDS;
-  if (staged) {
-    for (int t = threadIdx.x; t < W2 * H2; t += BODY_NT) {
-      int I = x0 - 1 + t % W2, J = y0 - 1 + t / W2;
-      bool there = true;
-      if (I < 0 || I >= nx) {
-        there = perx != 0;
-        I = I < 0 ? I + nx : I - nx;
-      }
-      if (J < 0 || J >= ny) {
-        there = there && pery != 0;
-        J = J < 0 ? J + ny : J - ny;
-      }
-      inside[t] = there ? (disk_inside(X, Y, R, I, J) ? 1 : 0) : 2;
-    }
-    __syncthreads();
-  }
-  for (int t = threadIdx.x, k = 0; t < w * h; t += BODY_NT, ++k) {
-    const int i = x0 + t % w, j = y0 + t / w;
-    bool own, iface = false;
-    if (staged) {
-      const int c = (t / w + 1) * W2 + t % w + 1;
-      own = inside[c] == 1;
+  MultiDiskSolid cur;
+  cur.n = nmov;
 #pragma unroll
-      for (int a = 1; a < Q; ++a) {
-        const uint8_t nb = inside[c + cy(a) * W2 + cx(a)];
-        if (nb != 2 && (nb == 1) != own) iface = true;
-      }
-    } else {
-      own = disk_inside(X, Y, R, i, j);
+  for (int k = 0; k < MAX_MOVERS; ++k) {
+    cur.X[k] = fx[k < nmov ? k : 0];
+    cur.Y[k] = fy[k < nmov ? k : 0];
+    cur.R[k] = mov[k < nmov ? k : 0].R;
+  }
+  // clear what the last flush wrote
+  for (int k = 0; k < nmov; ++k) {
+    const int x0 = mov[k].mwin[0], y0 = mov[k].mwin[1], w = mov[k].mwin[2] - x0, h = mov[k].mwin[3] - y0;
+    for (int t = threadIdx.x; t < w * h; t += FLUSH_NT) mask[(long long)(y0 + t / w) * pitch + x0 + t % w] = 0;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // solid ids and interface bits over every window at the new states
+  int wr[MAX_MOVERS][4];
+#pragma unroll
+  for (int k = 0; k < MAX_MOVERS; ++k) {
+    const int kk = k < nmov ? k : 0;
+    const int h = mov[kk].half;
+    int ox, oy;
+    mover_origin(st[kk], h, ox, oy);
+    wr[k][0] = max(ox, 0);
+    wr[k][1] = max(oy, 0);
+    wr[k][2] = min(ox + 2 * h + 1, nx);
+    wr[k][3] = min(oy + 2 * h + 1, ny);
+  }
+  for (int k = 0; k < nmov; ++k) {
+    int x0 = 0, y0 = 0, x1 = 0, y1 = 0;
+#pragma unroll
+    for (int q = 0; q < MAX_MOVERS; ++q)
+      if (q == k) { x0 = wr[q][0]; y0 = wr[q][1]; x1 = wr[q][2]; y1 = wr[q][3]; }
+    const int w = x1 - x0, h = y1 - y0;
+    for (int t = threadIdx.x; t < w * h; t += FLUSH_NT) {
+      const int i = x0 + t % w, j = y0 + t / w;
+      const int own = cur.id(i, j);
+      bool iface = false, two = false;
+      int other = 0;
 #pragma unroll
       for (int a = 1; a < Q; ++a) {
         int I = i + cx(a), J = j + cy(a);
@@ -852,69 +682,51 @@ __device__ __forceinline__ void body_step_block(uint8_t *__restrict__ mask, Ctl 
           if (!pery) continue;
           J = J < 0 ? J + ny : J - ny;
         }
-        if (disk_inside(X, Y, R, I, J) != own) iface = true;
+        const int nid = cur.id(I, J);
+        iface = iface || ((nid != 0) != (own != 0));
+        if (!own && nid) {
+          two = two || (other && other != nid);
+          other = nid;
+        }
       }
-    }
-    mask[(long long)j * pitch + i] = (own ? 1 : 0) | (iface ? M_IFACE : 0);
-    if (iface) {
-      ++cnt;
-      if (k < 64) ifbits |= 1ull << k;
-    }
-  }
-  // the rebuilt mask must be visible to every thread of the block
-  __threadfence_block();
-  __syncthreads();
-  {
-    // interface slots, thread by thread and each thread's cells in order (all
-    // of the disk's interface cells lie in its region).  A slot beyond the
-    // capacity drops its interface bit and flags the error (bit 3) instead of
-    // writing out of bounds.
-    int slot = block_exclusive_scan(cnt, wsum, &nslot);
-    for (int t = threadIdx.x, k = 0; t < w * h; t += BODY_NT, ++k) {
-      const long long c = (long long)(y0 + t / w) * pitch + x0 + t % w;
-      if (!(k < 64 ? (ifbits >> k) & 1 : (mask[c] & M_IFACE))) continue;
-      if (slot < maxslot) {
-        imap[c] = slot;
-      } else {
-        mask[c] &= (uint8_t)~M_IFACE;
-        atomicOr(&ctl->err, 8);
-      }
-      ++slot;
+      if (two) atomicOr(&ctl->err, 2);
+      mask[(long long)j * pitch + i] = (uint8_t)(own | (iface ? M_IFACE : 0));
     }
     if (threadIdx.x == 0) {
-      ctl->nslot = min(nslot, maxslot);
-      bt[0].me0 = 0;
-      bt[0].me1 = min(nslot, maxslot);
+      mov[k].mwin[0] = x0;
+      mov[k].mwin[1] = y0;
+      mov[k].mwin[2] = x1;
+      mov[k].mwin[3] = y1;
     }
   }
-  if (npts0 > 0) {
-    __threadfence_block();
+  __threadfence_block();
+  __syncthreads();
+  // sample bits of every point at the new states
+  for (int k = 0; k < nmov; ++k) {
+    const BodyDev S = st[k];
+    if (threadIdx.x == 0) {
+      cs[0] = cos(S.theta);
+      cs[1] = sin(S.theta);
+    }
     __syncthreads();
-    // the disk is the lattice's only body: its rule is the mask just built
-    si_select_block(DiskSolid{q[0], q[1], q[2]}, pre, mask, ctl, pts, maxp, recs, si_map, bt, bodies, nx, ny, pitch,
-                    npts0, si_moving, si_rule, Bnew, cs[0], cs[1], lds_stage,
-                    (int)(INSIDE_LDS / sizeof(double) / 5), false, winsh);
+    const double co = cs[0], sn = cs[1];
+    for (int i = mov[k].pt0 + (int)threadIdx.x; i < mov[k].pt1; i += FLUSH_NT) {
+      double px, py, n0, n1;
+      si_world(pts, maxp, i, 1, S, co, sn, px, py, n0, n1);
+      int node[4];
+      double wt[4];
+      const int c = si_stencil(cur, nx, ny, rule, px, py, n0, n1, node, wt);
+      if (c == 0) atomicOr(&ctl->err, 1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < c) {
+          const long long cc = (long long)(node[q] / nx) * pitch + node[q] % nx;
+          atomicOr((unsigned *)(mask + (cc & ~3LL)), (unsigned)M_SAMPLE << (8 * (cc & 3)));
+        }
+      }
+    }
+    __syncthreads();
   }
-}
-
-__global__ void __launch_bounds__(BODY_NT)
-    k_body_step(uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, const double *__restrict__ me,
-                const double *__restrict__ sig, double *__restrict__ hist, int cap, int maxb, int nx, int ny,
-                int pitch, int perx, int pery, const double *__restrict__ pts, int maxp, SiRec *__restrict__ recs,
-                int *__restrict__ si_map, int *__restrict__ imap, int maxslot, BodyTab *__restrict__ bt,
-                const BodyDev *__restrict__ bodies) {
-  body_step_block(mask, ctl, me, sig, hist, cap, maxb, nx, ny, pitch, perx, pery, pts, maxp, recs, si_map, imap,
-                  maxslot, bt, bodies);
-}
-
-// body kernel of a batched launch: one workgroup per moving lattice
-template <typename T>
-__global__ void __launch_bounds__(BODY_NT)
-    k_body_step_batch(const CaseDesc<T> *__restrict__ cases, const int *__restrict__ moving, int flip) {
-  const CaseDesc<T> &C = cases[moving[blockIdx.x]];
-  body_step_block(C.mask, C.ctl, C.me[C.pbit0 ^ flip], C.sig[C.pbit0 ^ flip], C.hist, C.cap, C.maxb, C.P.nx,
-                  C.P.ny, C.P.pitch, C.perx, C.pery, C.pts, C.maxp, const_cast<SiRec *>(C.recs),
-                  const_cast<int *>(C.si_map), const_cast<int *>(C.imap), C.maxslot, C.bt, C.P.bodies);
 }
 
 // ----------------------------------------------------------------------------

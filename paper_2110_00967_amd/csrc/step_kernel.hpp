@@ -27,7 +27,7 @@
 // HBM traffic per cell: 9 loads + 9 stores of the storage type + 1 mask byte.
 #pragma once
 
-#include "d2q9.hpp"
+#include "mover.hpp"
 
 namespace vp {
 
@@ -55,6 +55,13 @@ template <typename T> struct StepArgs {
   const void *ec_in;
   void *ec_out;
   int nper;
+  // moving disks (mover.hpp): nmov of them in mov, their points in pts
+  // ([6][maxp], body frame), the lattice's stencil rule
+  MoverDev *mov;
+  int nmov;
+  const double *pts;
+  int maxp, si_rule;
+  int wblocks;          // single-lattice launch: workgroups of the disks' hit boxes (see k_step)
 };
 
 // Source of deviation a arriving at (x, y) (any cell, edge or not): axis by
@@ -296,14 +303,8 @@ __device__ __forceinline__ void block_reduce(double (&v)[N], double *lds /*[NT/6
   }
 }
 
-// Width of the force finalize's summation order: FIN_W virtual lanes, lane v
-// summing slots v, v + FIN_W, ...; each virtual wave of 64 lanes reduced by a
-// butterfly, the FIN_W / 64 wave sums added in order.  Every workgroup size
-// runs the same order (a block of NT threads takes the virtual waves
-// w, w + NT/64, ... with its waves w), so forces do not depend on the tile
-// shape or on which kernel finalizes.
-constexpr int FIN_W = 256;
-constexpr int FIN_WAVES = FIN_W / 64;
+// The force finalize sums in the order of FIN_W virtual lanes (mover.hpp),
+// so forces do not depend on the tile shape or on which kernel finalizes.
 
 // The first ME slot and SI record of a thread's virtual lane v0 (slot and
 // record v0 of body 1's ranges, which start at 0 in a lattice with a single
@@ -409,24 +410,652 @@ __device__ __forceinline__ void body_ref(const Ctl *__restrict__ ctl, const Step
   }
 }
 
-// Masks of the 8 lattice neighbours of (x, y), wrapped into the lattice (the
-// momentum exchange decides separately which links are real)
+// Masks of the 8 lattice neighbours x - c_a of (x, y): wrapped across
+// periodic edges; a neighbour beyond another edge does not exist and reads
+// as fluid (0), so that it can neither link to the cell nor lend it a body.
 template <typename T>
 __device__ __forceinline__ void nbr_masks(const uint8_t *__restrict__ mask, const StepArgs<T> &P, int x, int y,
                                           uint8_t (&nm)[Q]) {
 #pragma unroll
   for (int a = 1; a < Q; ++a) {
     int sx = x - cx(a), sy = y - cy(a);
+    bool there = true;
+    if (cx(a) != 0) {
+      const bool out = cx(a) > 0 ? sx < 0 : sx >= P.nx;
+      there = !out || (cx(a) > 0 ? P.kind[WEST] : P.kind[EAST]) == EDGE_PERIODIC;
+    }
+    if (cy(a) != 0) {
+      const bool out = cy(a) > 0 ? sy < 0 : sy >= P.ny;
+      there = there && (!out || (cy(a) > 0 ? P.kind[SOUTH] : P.kind[NORTH]) == EDGE_PERIODIC);
+    }
     sx = sx < 0 ? sx + P.nx : (sx >= P.nx ? sx - P.nx : sx);
     sy = sy < 0 ? sy + P.ny : (sy >= P.ny ? sy - P.ny : sy);
-    nm[a] = mask[(uint32_t)(sy * P.pitch + sx)];
+    nm[a] = there ? mask[(uint32_t)(sy * P.pitch + sx)] : (uint8_t)0;
+  }
+}
+
+// One stress-integration point placed at its disk's state of this step, as
+// the tile sees it: its stencil nodes inside the tile and their weights.
+struct PtPlace {
+  int in;          // bit q: stencil node q lies in the tile
+  unsigned cell;   // tile cell of node q in bits 8q..8q+7
+  double n0, n1;   // normal
+  double rx, ry;   // lever arm from the disk's centre
+  double s[4];     // ds times the stencil weight of node q
+};
+
+// A workgroup's view of the moving disks for one step (LDS).
+template <int BX, int BY> struct MovLds {
+  BodyDev st[MAX_MOVERS];  // state each disk uses in this step
+  double cs[MAX_MOVERS][2];  // cos, sin of its angle
+  long long fx[MAX_MOVERS], fy[MAX_MOVERS], fr[MAX_MOVERS];  // its centre and radius on the 1/FIXQ grid
+  double red[FIN_WAVES * 6];  // force sums
+  double sg[BX * BY][3];      // stress of the tile's sample nodes
+  int anyme, anys;            // bit k: the tile has interface cells / sample nodes of disk k
+  int smp[BX * BY];           // per tile cell: bit k = sample node of disk k
+  uint8_t sid[(BX + 2) * (BY + 2)];  // tile and a one-cell ring: disk id (1..), 0 fluid, 0xFF no cell
+  PtPlace pl[BX * BY];               // point t of the disks as placed by thread t
+};
+
+// The points of all moving disks are numbered disk by disk: disk k holds
+// [pt1 of disk k - 1, pt1 of disk k).  The disk of point i:
+__device__ __forceinline__ int point_disk(const int (&pt1)[MAX_MOVERS], int nmov, int i) {
+  int k = 0;
+#pragma unroll
+  for (int q = 0; q < MAX_MOVERS - 1; ++q) k += (q + 1 < nmov && i >= pt1[q]) ? 1 : 0;
+  return k;
+}
+
+// Point (a, b), normal (c, d), length ds of disk k placed at the disk's
+// state of this step (ml.st, ml.cs), with its sample stencil among the disks
+// cur; returns the stencil size (0: no sample node).
+template <typename T, int BX, int BY>
+__device__ __forceinline__ int place_point(const StepArgs<T> &P, const MovLds<BX, BY> &ml, const DiskSetRef &cur,
+                                           int k, double a, double b, double c, double d, double ds, int x0, int y0,
+                                           PtPlace &pp) {
+  const BodyDev S = ml.st[k];
+  double px, py, n0, n1;
+  si_place(a, b, c, d, 1, S, ml.cs[k][0], ml.cs[k][1], px, py, n0, n1);
+  int node[4];
+  double wt[4];
+  const int cnt = si_stencil(cur, P.nx, P.ny, P.si_rule, px, py, n0, n1, node, wt);
+  pp.in = 0;
+  pp.cell = 0;
+  pp.n0 = n0;
+  pp.n1 = n1;
+  pp.rx = px - S.x;
+  pp.ry = py - S.y;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    pp.s[q] = ds * wt[q];
+    if (q < cnt) {
+      const int X = node[q] % P.nx - x0, Y = node[q] / P.nx - y0;
+      if (X >= 0 && X < BX && Y >= 0 && Y < BY) {
+        pp.in |= 1 << q;
+        pp.cell |= (unsigned)(Y * BX + X) << (8 * q);
+      }
+    }
+  }
+  return cnt;
+}
+
+// The stress-integration terms of a placed point over its nodes in the
+// tile (stress ml.sg): force s (sigma . n), torque r x that force.
+template <int BX, int BY>
+__device__ __forceinline__ void point_terms(const PtPlace &pp, const MovLds<BX, BY> &ml, double (&v)[6]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (pp.in & (1 << q)) {
+      const double *g = ml.sg[(pp.cell >> (8 * q)) & 0xFF];
+      const double s = pp.s[q];
+      const double fx = s * (g[0] * pp.n0 + g[1] * pp.n1), fy = s * (g[1] * pp.n0 + g[2] * pp.n1);
+      v[3] += fx;
+      v[4] += fy;
+      v[5] += pp.rx * fy - pp.ry * fx;
+    }
+  }
+}
+
+// The tiles whose workgroups take part in a disk's step: those whose tile
+// and one-cell ring meet the disk's window grown by two cells (a disk moves
+// less than a cell per step), at the state (bx, by) the launch starts from --
+// the box of tile indices [hx0, hx1] x [hy0, hy1].  It spans at most
+// hit_tiles(h, BX) x hit_tiles(h, BY) tiles.
+template <int BX, int BY>
+__device__ __forceinline__ void hit_box(double bx, double by, int h, int &hx0, int &hy0, int &hx1, int &hy1) {
+  const int ox = (int)floor(bx) - h, oy = (int)floor(by) - h, side = 2 * h + 1;
+  hx0 = floordiv(ox - 3, BX);
+  hx1 = floordiv(ox + side + 2, BX);
+  hy0 = floordiv(oy - 3, BY);
+  hy1 = floordiv(oy + side + 2, BY);
+}
+__host__ __device__ constexpr int hit_tiles(int h, int B) { return (2 * h + 6 + B - 1) / B + 1; }
+template <int BX, int BY>
+__device__ __forceinline__ bool in_hit_box(double bx, double by, int h, int tx, int ty) {
+  int hx0, hy0, hx1, hy1;
+  hit_box<BX, BY>(bx, by, h, hx0, hy0, hx1, hy1);
+  return tx >= hx0 && tx <= hx1 && ty >= hy0 && ty <= hy1;
+}
+
+// The moving disks' part of one workgroup of the launch that computes step N
+// (parity pb = N & 1; pending: the forces of step N - 1 are still to be
+// summed and the states advanced by them).  States: slot k & 1 of
+// MoverDev::B holds the state after k updates, so the state this launch
+// starts from is in slot pb when pending, else in slot pb ^ 1.  Returns false
+// (and touches no LDS) when the tile is outside every disk's hit box (known:
+// the caller has found it inside one); then no cell of the tile is solid,
+// interface or sample node of a moving disk, and the tile is outside every
+// window of this step.  Otherwise, with every thread of the workgroup:
+//   1. pending: the forces of step N - 1 of every disk (mover_forces on the
+//      tile partials of step N - 1, part_prev), its new state (mover_update);
+//      the workgroup of the tile holding the disk's centre cell writes the
+//      state to the other slot, the forces to the history ring, and flags a
+//      disk that moved a cell or more (error bit 5);
+//   2. the solid ids of the tile and its ring, and the sample nodes of every
+//      point that fall in the tile, at the states of this step (error bit 0
+//      for a point without sample node).  Thread t places points t, t + NT,
+//      ... and keeps the first in ml.pl[t] for mover_epilogue.
+// The loads that do not depend on one another are issued together: the
+// disks' positions first, then the partial sums with the points.
+template <typename T, int BX, int BY>
+__device__ __forceinline__ bool mover_prologue(int tx, int ty, const StepArgs<T> &P, Ctl *__restrict__ ctl,
+                                               const double *__restrict__ part_prev, double *__restrict__ hist,
+                                               int cap, int maxb, int pb, int pending, bool known,
+                                               MovLds<BX, BY> &ml) {
+  constexpr int NT = BX * BY;
+  static_assert(BX == MOV_BX && BY == MOV_BY, "moving disks run the tile of their partials");
+  const int x0 = tx * BX, y0 = ty * BY;
+  const int sread = pending ? pb : pb ^ 1;
+  const int nmov = P.nmov;
+  bool hit = known;
+  int pt1[MAX_MOVERS];
+  int ptot = 0;
+#pragma unroll
+  for (int k = 0; k < MAX_MOVERS; ++k) {
+    pt1[k] = 0;
+    if (k < nmov) {
+      const MoverDev &M = P.mov[k];
+      pt1[k] = M.pt1;
+      ptot = pt1[k];
+      if (!known) hit = hit || in_hit_box<BX, BY>(M.B[sread].x, M.B[sread].y, M.half, tx, ty);
+    }
+  }
+  if (!hit) return false;
+  // this thread's first point and its disk's radius, in flight with the sums
+  const int i0 = threadIdx.x;
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0, q4 = 0.0;
+  if (i0 < ptot) {
+    q0 = P.pts[i0];
+    q1 = P.pts[P.maxp + i0];
+    q2 = P.pts[2 * P.maxp + i0];
+    q3 = P.pts[3 * P.maxp + i0];
+    q4 = P.pts[4 * P.maxp + i0];
+  }
+  const long long rk = (int)threadIdx.x < nmov ? P.mov[threadIdx.x].R : 0;
+  if (pending) {
+    const int tiles_x = (P.nx + BX - 1) / BX, tiles_y = (P.ny + BY - 1) / BY;
+    for (int k = 0; k < nmov; ++k) {
+      MoverDev &M = P.mov[k];
+      const BodyDev B = M.B[sread];
+      double F[6];
+      mover_forces<NT>(M, B, part_prev, tiles_x, tiles_y, ml.red, F);
+      const BodyDev S = mover_update(M, B, F);
+      if (threadIdx.x == 0) ml.st[k] = S;
+      const int ci = min(max((int)floor(B.x), 0), P.nx - 1), cj = min(max((int)floor(B.y), 0), P.ny - 1);
+      if (threadIdx.x == 0 && ci >= x0 && ci < x0 + BX && cj >= y0 && cj < y0 + BY) {
+        // the recording workgroup of this disk (exactly one per launch)
+        M.B[sread ^ 1] = S;
+        const long long n = M.nfin + 1;
+        double *hh = hist + ((n % cap) * maxb + k) * 6;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) hh[i] = F[i];
+        M.nfin = n;
+        if (k == 0) {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) ctl->last[i] = F[i];
+          ctl->step = n;
+          ctl->body = S;
+        }
+        if (fabs(S.x - B.x) >= 1.0 || fabs(S.y - B.y) >= 1.0) atomicOr(&ctl->err, 32);
+      }
+    }
+  } else if ((int)threadIdx.x < nmov) {
+    ml.st[threadIdx.x] = P.mov[threadIdx.x].B[sread];
+  }
+  if (threadIdx.x == 0) {
+    ml.anyme = 0;
+    ml.anys = 0;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nmov) {
+    const int k = threadIdx.x;
+    const BodyDev S = ml.st[k];
+    double sn, co;
+    sincos(S.theta, &sn, &co);
+    ml.cs[k][0] = co;
+    ml.cs[k][1] = sn;
+    ml.fx[k] = fixq_of(S.x);
+    ml.fy[k] = fixq_of(S.y);
+    ml.fr[k] = rk;
+  }
+  for (int t = threadIdx.x; t < BX * BY; t += NT) ml.smp[t] = 0;
+  __syncthreads();
+  const DiskSetRef cur{nmov, ml.fx, ml.fy, ml.fr};
+  const bool perx = P.kind[WEST] == EDGE_PERIODIC, pery = P.kind[SOUTH] == EDGE_PERIODIC;
+  for (int t = threadIdx.x; t < (BX + 2) * (BY + 2); t += NT) {
+    int X = x0 - 1 + t % (BX + 2), Y = y0 - 1 + t / (BX + 2);
+    bool there = true;
+    if (X < 0 || X >= P.nx) {
+      there = perx;
+      X = X < 0 ? X + P.nx : X - P.nx;
+    }
+    if (Y < 0 || Y >= P.ny) {
+      there = there && pery;
+      Y = Y < 0 ? Y + P.ny : Y - P.ny;
+    }
+    ml.sid[t] = there ? (uint8_t)cur.id(X, Y) : (uint8_t)0xFF;
+  }
+  // point i0 of the disks (thread i0), kept in ml.pl for mover_epilogue;
+  // more than NT points in all: the others after it, placed again there
+  for (int i = i0; i < ptot; i += NT) {
+    const bool first = i == i0;
+    double a = q0, b = q1, cn = q2, dn = q3, ds = q4;
+    if (!first) {
+      a = P.pts[i];
+      b = P.pts[P.maxp + i];
+      cn = P.pts[2 * P.maxp + i];
+      dn = P.pts[3 * P.maxp + i];
+      ds = P.pts[4 * P.maxp + i];
+    }
+    const int k = point_disk(pt1, nmov, i);
+    PtPlace t;
+    if (place_point(P, ml, cur, k, a, b, cn, dn, ds, x0, y0, t) == 0) atomicOr(&ctl->err, 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (t.in & (1 << q)) {
+        atomicOr(&ml.smp[(t.cell >> (8 * q)) & 0xFF], 1 << k);
+        atomicOr(&ml.anys, 1 << k);
+      }
+    }
+    if (first) ml.pl[threadIdx.x] = t;
+  }
+  if (i0 >= ptot) ml.pl[threadIdx.x].in = 0;
+  __syncthreads();
+  return true;
+}
+
+// The tile's partial sums of the step for every disk whose window (at the
+// disk's state of this step) covers the tile: the momentum exchange of the
+// cells linked to the disk (acc, bid), and the stress integration of the
+// disk's points over the sample nodes in the tile (each node's stress sg,
+// weighted by the point's stencil weight and ds, contracted with its normal;
+// torque about the disk's centre).  Thread t adds the terms of points t (as
+// mover_prologue placed it, ml.pl[t]), t + NT, ..., then each sum is
+// reduced in one fixed order (a butterfly per wave, the waves in order) and
+// written by thread 0 to the disk's slot of the tile in part.  Uniform over
+// the workgroup (mover_prologue returned true).
+template <typename T, int BX, int BY>
+__device__ __forceinline__ void mover_epilogue(int tx, int ty, const StepArgs<T> &P, const double (&acc)[3], int bid,
+                                               const double (&sg)[3], double *__restrict__ part,
+                                               MovLds<BX, BY> &ml) {
+  constexpr int NT = BX * BY, NW = NT / 64;
+  static_assert(NW <= FIN_WAVES, "one partial per wave in ml.red");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  ml.sg[threadIdx.x][0] = sg[0];
+  ml.sg[threadIdx.x][1] = sg[1];
+  ml.sg[threadIdx.x][2] = sg[2];
+  if (bid) atomicOr(&ml.anyme, 1 << (bid - 1));
+  __syncthreads();
+  const int anyme = ml.anyme, anys = ml.anys;
+  const int nmov = P.nmov;
+  int pt1[MAX_MOVERS];
+  int ptot = 0;
+#pragma unroll
+  for (int k = 0; k < MAX_MOVERS; ++k) {
+    pt1[k] = k < nmov ? P.mov[k].pt1 : 0;
+    if (k < nmov) ptot = pt1[k];
+  }
+  for (int k = 0; k < nmov; ++k) {
+    const MoverDev &M = P.mov[k];
+    int tx0, ty0, ntx, nty;
+    mover_tile_box(ml.st[k], M.half, tx0, ty0, ntx, nty);
+    if (tx < tx0 || tx >= tx0 + ntx || ty < ty0 || ty >= ty0 + nty) continue;
+    double *w = part + (long long)(M.part0 + (ty - ty0) * M.ptx + (tx - tx0)) * PART_ENTRY;
+    if (!((anyme | anys) & (1 << k))) {
+      if (threadIdx.x < 6) w[threadIdx.x] = 0.0;
+      continue;
+    }
+    const bool mine = bid == k + 1;
+    double v[6] = {mine ? acc[0] : 0.0, mine ? acc[1] : 0.0, mine ? acc[2] : 0.0, 0.0, 0.0, 0.0};
+    if (anys & (1 << k)) {
+      if ((int)threadIdx.x < ptot && point_disk(pt1, nmov, threadIdx.x) == k) point_terms(ml.pl[threadIdx.x], ml, v);
+      if (ptot > NT) {
+        // points t + NT, ...: placed again
+        const DiskSetRef cur{P.nmov, ml.fx, ml.fy, ml.fr};
+        for (int i = (int)threadIdx.x + NT; i < ptot; i += NT) {
+          if (point_disk(pt1, nmov, i) != k) continue;
+          PtPlace t;
+          place_point(P, ml, cur, k, P.pts[i], P.pts[P.maxp + i], P.pts[2 * P.maxp + i], P.pts[3 * P.maxp + i],
+                      P.pts[4 * P.maxp + i], tx * BX, ty * BY, t);
+          point_terms(t, ml, v);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      double x = v[i];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+      if (lane == 0) ml.red[wave * 6 + i] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      double x = 0.0;
+      for (int q = 0; q < NW; ++q) x += ml.red[q * 6 + threadIdx.x];
+      w[threadIdx.x] = x;
+    }
+    __syncthreads();
+  }
+}
+
+// One thread's cell of a tile: its place and how its populations are
+// addressed.  A tile's cells all have their 8 neighbours inside the lattice
+// (interior): the workgroup-uniform fast path, where a wave is one run of 64
+// cells of one row (tiles are 64, 128 or 256 cells wide), so its row and
+// chunk are scalars and each population loads from a scalar base
+// (fast_base) + one of three small lane offsets, and stores the same way.
+struct TileCell {
+  int tx, ty, lx, ly, x, y, c, yw, cw;
+  bool interior, live;
+  uint32_t lb, lo[3];
+};
+
+template <typename S, int BX, int BY, typename T>
+__device__ __forceinline__ TileCell tile_cell(int tile, const StepArgs<T> &P) {
+  TileCell t;
+  // tile / tiles_x by multiply-high (exact while tile * tiles_x < 2^32, which
+  // every accepted lattice satisfies: tiles_x^2 * ny <= 58,255 * pitch < 2^30)
+  t.ty = P.tx_magic ? (int)__umulhi((unsigned)tile, P.tx_magic) : tile;
+  t.tx = tile - t.ty * P.tiles_x;
+  t.lx = threadIdx.x % BX;
+  t.ly = threadIdx.x / BX;
+  t.x = t.tx * BX + t.lx;
+  t.y = t.ty * BY + t.ly;
+  t.interior = (t.tx * BX >= 1) & (t.tx * BX + BX <= P.nx - 1) & (t.ty * BY >= 1) & (t.ty * BY + BY <= P.ny - 1);
+  t.live = t.x < P.nx && t.y < P.ny;
+  t.c = t.y * P.pitch + t.x;
+  const int lane = t.x & 63;
+  t.lb = (uint32_t)(lane * sizeof(S));
+  t.lo[0] = (uint32_t)((lane > 0 ? lane + CHUNK_ELEMS - 1 : 63) * sizeof(S));
+  t.lo[1] = (uint32_t)((lane + CHUNK_ELEMS) * sizeof(S));
+  t.lo[2] = (uint32_t)((lane < 63 ? lane + CHUNK_ELEMS + 1 : 2 * CHUNK_ELEMS) * sizeof(S));
+  t.yw = __builtin_amdgcn_readfirstlane(t.y);
+  t.cw = __builtin_amdgcn_readfirstlane(t.x >> 6);
+  return t;
+}
+
+// The streamed populations of a live cell.  AA launches read through fout,
+// the pointer they write through: the thread's own stores overwrite the
+// slots it read (a read-only view of the buffer would let the compiler
+// re-load a value after such a store).
+template <typename S, int AA, typename T>
+__device__ __forceinline__ void load_cell(const TileCell &t, const S *__restrict__ fin, S *__restrict__ fout,
+                                          const StepArgs<T> &P, T (&d)[Q]) {
+  const S *src = AA == 0 ? fin : (const S *)fout;
+  if (t.interior) {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      if constexpr (AA == 0)
+        d[a] = Store<S>::ld(at(fast_base(src, P, t.yw - cy(a), t.cw, a), t.lo[1 - cx(a)]));
+      else if constexpr (AA == 1)
+        d[a] = Store<S>::ld(at(fast_base(src, P, t.yw - cy(a), t.cw, opp(a)), t.lo[1 - cx(a)]));
+      else
+        d[a] = Store<S>::ld(at(fast_base(src, P, t.yw, t.cw, a), t.lo[1]));
+    }
+  } else if constexpr (AA == 0) {
+    pull_edge_all<S, T, true>(src, P, t.x, t.y, d);
+  } else {
+    aa_pull_edge<S, T, AA>(src, P, t.x, t.y, d);
+  }
+}
+
+// The update of a live cell with flags m (body id, interface, sample node)
+// from its streamed populations d: moments, penalization, collision and the
+// stores of the post-collision populations (and the macroscopic fields when
+// MACRO); at an interface cell its momentum-exchange terms (acc, and the
+// body bid its links belong to), at a sample node its stress (sg).  Static
+// bodies store them in their slots for the finalize; moving disks (MOV with
+// P.nmov > 0) keep them for mover_epilogue and take their states and the
+// neighbours' ids from ml.
+template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA, bool MOV, typename T, typename ML>
+__device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], uint8_t m, S *__restrict__ fout,
+                                            const uint8_t *__restrict__ mask, const StepArgs<T> &P,
+                                            Ctl *__restrict__ ctl, const int *__restrict__ si_map,
+                                            const int *__restrict__ imap, double *__restrict__ me_out,
+                                            double *__restrict__ sig_out, T *__restrict__ mrho, T *__restrict__ mux,
+                                            T *__restrict__ muy, const ML &ml, double (&acc)[3], int &bid,
+                                            double (&sg)[3]) {
+  const int x = t.x, y = t.y, c = t.c, yw = t.yw, cw = t.cw;
+  const bool tile_interior = t.interior;
+  const uint32_t lb = t.lb;
+  const uint32_t(&lo)[3] = t.lo;
+  const int sc = (t.ly + 1) * (BX + 2) + t.lx + 1;  // the cell in the ring array ml.sid
+  const int eidx = (AA != 0 && !tile_interior && (x == 0 || x == P.nx - 1 || y == 0 || y == P.ny - 1))
+                       ? perim_index(x, y, P.nx, P.ny)
+                       : -1;
+
+  // moments (of the deviations: sum w = 1, sum w c = 0)
+  const T drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+  const T mx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+  const T my = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+  const T rho = P.rho0 + drho;
+  // a non-finite density means the run diverged: one lane per such wave
+  // flags it (error bit 4) for the host's next check
+  {
+    const unsigned long long bad = __ballot(!(fabs(drho) <= T(1e30)));
+    if (bad && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)bad) - 1)) atomicOr(&ctl->err, 16);
+  }
+
+  // penalized velocity (Eq. updatestepm) and force; k = 0 in fluid cells
+  T khalf = T(0), a1 = T(1), kk = T(0), usx = T(0), usy = T(0);
+  const int id = m & M_BODY;
+  const bool chi = id != 0;
+  if (chi) {
+    khalf = P.khalf;
+    a1 = P.a1;
+    kk = P.kk;
+    if (MOV && P.nmov > 0) {  // a moving disk: its state of this step
+      const BodyDev B = ml.st[id - 1];
+      usx = T(B.u - B.omega * (double(y) - B.y));
+      usy = T(B.v + B.omega * (double(x) - B.x));
+    } else if (id == 1) {  // the only static-lattice body that can move (u_s = 0 in the static ones)
+      const BodyDev B = ctl->body;
+      usx = T(B.u - B.omega * (double(y) - B.y));
+      usy = T(B.v + B.omega * (double(x) - B.x));
+    }
+  }
+  const T hx = mx + T(0.5) * P.gx, hy = my + T(0.5) * P.gy;
+  const T den = a1 * recip(rho);  // 1 / (rho (1 + k/2))
+  const T ux = (hx + khalf * rho * usx) * den;
+  const T uy = (hy + khalf * rho * usy) * den;
+  const T Fx = P.gx - kk * (hx - rho * usx);
+  const T Fy = P.gy - kk * (hy - rho * usy);
+
+  const T uu15 = T(1.5) * (ux * ux + uy * uy);
+  const T uF3 = T(3) * (ux * Fx + uy * Fy);
+  {
+    // Collision with the forcing term (Eqs. TRT and eqBd; BGK is tau- =
+    // tau+), per pair (a, a') with c_a' = -c_a.  Since 1 - 1/(2 tau) =
+    // (tau - 1/2) / tau, the forcing term enters as a shift of the
+    // equilibrium, even part by (tau+ - 1/2) F_even and odd part by
+    // (tau- - 1/2) F_odd:
+    //   q_a = wgt_a (De + Do),  q_a' = wgt_a (De - Do),
+    //   De = drho - 1.5 rho u.u - 3 (tau+ - 1/2) u.F
+    //        + (c.u) (4.5 rho (c.u) + 9 (tau+ - 1/2) (c.F)),
+    //   Do = 3 rho (c.u) + 3 (tau- - 1/2) (c.F),
+    // and out = d - (d - q)_even / tau+ - (d - q)_odd / tau-.  The
+    // non-equilibrium part d - q is formed before it is scaled, which
+    // keeps the FP32 rounding of mass and momentum unbiased.
+    const T C1 = drho - rho * uu15 - P.fo * uF3;
+    const T R45 = T(4.5) * rho, R3 = T(3) * rho;
+    put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, 0, d[0] - P.omega * (d[0] - T(wgt(0)) * C1),
+                   eidx);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int a = k < 2 ? k + 1 : k + 3;  // 1, 2, 5, 6; a' = 3, 4, 7, 8
+      const int o = opp(a);
+      const T w = T(wgt(a));
+      const T cu = dotc(a, ux, uy);
+      const T cF = dotc(a, Fx, Fy);
+      const T De = cu * (R45 * cu + P.fo9 * cF) + C1;
+      const T Do = R3 * cu + P.fo3 * cF;
+      T oa, oo;
+      if constexpr (!TRT) {
+        oa = d[a] - P.omega * (d[a] - w * (De + Do));
+        oo = d[o] - P.omega * (d[o] - w * (De - Do));
+      } else {
+        const T se = T(0.5) * (d[a] + d[o]) - w * De;
+        const T so = T(0.5) * (d[a] - d[o]) - w * Do;
+        oa = d[a] - P.omega * se - P.omega_m * so;
+        oo = d[o] - P.omega * se + P.omega_m * so;
+      }
+      put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, a, oa, eidx);
+      put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, o, oo, eidx);
+    }
+  }
+  if (MACRO) {
+    mrho[(uint32_t)c] = rho;
+    mux[(uint32_t)c] = ux;
+    muy[(uint32_t)c] = uy;
+  }
+
+  if (m & M_IFACE) {
+    // momentum exchange: every population pulled across the interface;
+    // the link's interface point is its midpoint seen from its fluid node.
+    // The 8 neighbour masks are loaded all at once (a load inside the
+    // divergent loop below would cost one memory round trip per link).
+    // The cell's links all belong to one body: its own if solid, else that
+    // of its solid neighbours (a fluid cell is linked to one body at most).
+    bool movl = false;  // a lattice with moving disks: every body moves
+    if constexpr (MOV) movl = P.nmov > 0;
+    uint8_t nm[Q];
+    if constexpr (MOV) {
+      if (movl) {
+#pragma unroll
+        for (int a = 1; a < Q; ++a) {
+          const uint8_t nb = ml.sid[sc - cy(a) * (BX + 2) - cx(a)];
+          nm[a] = nb == 0xFF ? 0 : nb;
+        }
+      } else {
+        nbr_masks(mask, P, x, y, nm);
+      }
+    } else {
+      nbr_masks(mask, P, x, y, nm);
+    }
+    bid = id;
+#pragma unroll
+    for (int a = 1; a < Q; ++a) bid = bid ? bid : (nm[a] & M_BODY);
+    double bx, by;
+    if constexpr (MOV) {
+      if (movl) {
+        bx = ml.st[bid - 1].x;
+        by = ml.st[bid - 1].y;
+      } else {
+        body_ref(ctl, P, bid, bx, by);
+      }
+    } else {
+      body_ref(ctl, P, bid, bx, by);
+    }
+    const bool moving = movl || bid == 1;  // u_s = 0 on the links of static bodies 2..
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      int sx = x - cx(a), sy = y - cy(a);
+      bool link = true;
+      if (sx < 0 || sx >= P.nx) {
+        if ((sx < 0 ? P.kind[WEST] : P.kind[EAST]) != EDGE_PERIODIC) link = false;
+        sx = sx < 0 ? sx + P.nx : sx - P.nx;
+      }
+      if (sy < 0 || sy >= P.ny) {
+        if ((sy < 0 ? P.kind[SOUTH] : P.kind[NORTH]) != EDGE_PERIODIC) link = false;
+        sy = sy < 0 ? sy + P.ny : sy - P.ny;
+      }
+      const bool schi = (nm[a] & M_BODY) != 0;
+      if (!link || schi == chi) continue;
+      double gx, gy, s;
+      if (chi) { gx = sx + 0.5 * cx(a); gy = sy + 0.5 * cy(a); s = 1.0; }
+      else { gx = x - 0.5 * cx(a); gy = y - 0.5 * cy(a); s = -1.0; }
+      double ugx = 0.0, ugy = 0.0;
+      if (moving) {
+        if constexpr (MOV) {
+          if (movl) {
+            const BodyDev &B = ml.st[bid - 1];
+            ugx = B.u - B.omega * (gy - B.y);
+            ugy = B.v + B.omega * (gx - B.x);
+          } else {
+            const BodyDev &B = ctl->body;
+            ugx = B.u - B.omega * (gy - B.y);
+            ugy = B.v + B.omega * (gx - B.x);
+          }
+        } else {
+          const BodyDev &B = ctl->body;
+          ugx = B.u - B.omega * (gy - B.y);
+          ugy = B.v + B.omega * (gx - B.x);
+        }
+      }
+      const double fa = wgt(a) * P.rho0d + double(d[a]);
+      const double lx_ = s * (cx(a) - ugx) * fa, ly_ = s * (cy(a) - ugy) * fa;
+      acc[0] += lx_;
+      acc[1] += ly_;
+      acc[2] += (gx - bx) * ly_ - (gy - by) * lx_;
+    }
+    if (!movl) {
+      // this cell's contribution goes to its slot; the finalize sums them
+      double *o = me_out + (long long)imap[(uint32_t)c] * ME_STRIDE;
+      o[0] = acc[0];
+      o[1] = acc[1];
+      o[2] = acc[2];
+    }
+  }
+  if (m & M_SAMPLE) {
+    // stress of the streamed populations at a (fluid) sample node
+    T pxx = T(0), pxy = T(0), pyy = T(0);
+#pragma unroll
+    for (int a = 1; a < Q; ++a) {
+      const T w = T(wgt(a));
+      const T cu = dotc(a, ux, uy);
+      const T ne = d[a] - (w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - uu15));
+      pxx += T(cx(a) * cx(a)) * ne;
+      pxy += T(cx(a) * cy(a)) * ne;
+      pyy += T(cy(a) * cy(a)) * ne;
+    }
+    const double pr = double(drho) / 3.0;
+    sg[0] = -pr - P.facd * double(pxx);
+    sg[1] = -P.facd * double(pxy);
+    sg[2] = -pr - P.facd * double(pyy);
+    if (!(MOV && P.nmov > 0)) {
+      // the node's stress goes to its record's slot; the finalize
+      // contracts it with the aggregated weights
+      double *g = sig_out + (long long)si_map[(uint32_t)c] * SIG_STRIDE;
+      g[0] = sg[0];
+      g[1] = sg[1];
+      g[2] = sg[2];
+    }
   }
 }
 
 // One workgroup's tile of the step (tile < P.ntiles): the body of the step
 // kernel, shared by the single-lattice and the batched launch.  The
 // workgroup of tile 0 also finalizes the previous step's forces (fin_prev).
-template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA>
+// MOV: the lattice may hold moving disks (P.nmov > 0; no static bodies
+// then): their cells take solid, interface and sample flags from the disks'
+// states (mover_prologue) instead of the mask, and their force terms go to
+// per-tile partial sums in me_out (mover_epilogue); pb is the parity of the
+// step, mov_pending tells that the previous step's disk forces are still to
+// be summed.  SPLIT (the single-lattice launch): win tells that the tile is
+// one of a disk's hit box (taken by the workgroups that come first); a
+// plain workgroup leaves the hit boxes' tiles alone.  Otherwise every
+// workgroup tests its tile itself.
+template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA, bool MOV = false, bool SPLIT = false>
 __device__ __forceinline__ void step_tile(
     int tile, const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
     const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl, const SiRec *__restrict__ recs,
@@ -434,213 +1063,71 @@ __device__ __forceinline__ void step_tile(
     double *__restrict__ me_out, const double *__restrict__ me_prev, double *__restrict__ sig_out,
     const double *__restrict__ sig_prev, int fin_prev, double *__restrict__ hist, int cap, int maxb,
     typename Store<S>::T *__restrict__ mrho, typename Store<S>::T *__restrict__ mux,
-    typename Store<S>::T *__restrict__ muy) {
+    typename Store<S>::T *__restrict__ muy, int pb = 0, int mov_pending = 0, bool win = false) {
   using T = typename Store<S>::T;
   constexpr int NT = BX * BY;
-  // tile / tiles_x by multiply-high (exact while tile * tiles_x < 2^32, which
-  // every accepted lattice satisfies: tiles_x^2 * ny <= 58,255 * pitch < 2^30)
-  const int ty = P.tx_magic ? (int)__umulhi((unsigned)tile, P.tx_magic) : tile;
-  const int tx = tile - ty * P.tiles_x;
-  const int lx = threadIdx.x % BX, ly = threadIdx.x / BX;
-  const int x = tx * BX + lx, y = ty * BY + ly;
+  const TileCell t = tile_cell<S, BX, BY>(tile, P);
 
+  // the streamed populations, loaded first: with moving disks they are in
+  // flight while the disks' states are read
+  T d[Q];
+  if (t.live) load_cell<S, AA>(t, fin, fout, P, d);
 
-  // Every cell of the tile has all 8 neighbours inside the lattice: the
-  // workgroup-uniform fast path.  A wave is then one run of 64 cells of one
-  // row (tiles are 64, 128 or 256 cells wide), so its row and chunk are
-  // scalars; each population loads from a scalar base (fast_base) + one of
-  // three small lane offsets, and stores the same way.
-  const bool tile_interior = (tx * BX >= 1) & (tx * BX + BX <= P.nx - 1) & (ty * BY >= 1) &
-                             (ty * BY + BY <= P.ny - 1);
-
-  if (x < P.nx && y < P.ny) {
-    const int c = y * P.pitch + x;
-    const int lane = x & 63;
-    const uint32_t lb = (uint32_t)(lane * sizeof(S));
-    const uint32_t lo[3] = {(uint32_t)((lane > 0 ? lane + CHUNK_ELEMS - 1 : 63) * sizeof(S)),
-                            (uint32_t)((lane + CHUNK_ELEMS) * sizeof(S)),
-                            (uint32_t)((lane < 63 ? lane + CHUNK_ELEMS + 1 : 2 * CHUNK_ELEMS) * sizeof(S))};
-    const int yw = __builtin_amdgcn_readfirstlane(y), cw = __builtin_amdgcn_readfirstlane(x >> 6);
-    const uint8_t m = mask[(uint32_t)c];
-    T d[Q];
-    // AA launches read through fout, the pointer they write through: the
-    // thread's own stores overwrite the slots it read (a read-only view of
-    // the buffer would let the compiler re-load a value after such a store)
-    const S *src = AA == 0 ? fin : (const S *)fout;
-    if (tile_interior) {
-#pragma unroll
-      for (int a = 0; a < Q; ++a) {
-        if constexpr (AA == 0)
-          d[a] = Store<S>::ld(at(fast_base(src, P, yw - cy(a), cw, a), lo[1 - cx(a)]));
-        else if constexpr (AA == 1)
-          d[a] = Store<S>::ld(at(fast_base(src, P, yw - cy(a), cw, opp(a)), lo[1 - cx(a)]));
-        else
-          d[a] = Store<S>::ld(at(fast_base(src, P, yw, cw, a), lo[1]));
-      }
-    } else if constexpr (AA == 0) {
-      pull_edge_all<S, T, true>(src, P, x, y, d);
-    } else {
-      aa_pull_edge<S, T, AA>(src, P, x, y, d);
-    }
-    const int eidx = (AA != 0 && !tile_interior && (x == 0 || x == P.nx - 1 || y == 0 || y == P.ny - 1))
-                         ? perim_index(x, y, P.nx, P.ny)
-                         : -1;
-
-    // moments (of the deviations: sum w = 1, sum w c = 0)
-    const T drho = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
-    const T mx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
-    const T my = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-    const T rho = P.rho0 + drho;
-    // a non-finite density means the run diverged: one lane per such wave
-    // flags it (error bit 4) for the host's next check
-    {
-      const unsigned long long bad = __ballot(!(fabs(drho) <= T(1e30)));
-      if (bad && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)bad) - 1)) atomicOr(&ctl->err, 16);
-    }
-
-    // penalized velocity (Eq. updatestepm) and force; k = 0 in fluid cells
-    T khalf = T(0), a1 = T(1), kk = T(0), usx = T(0), usy = T(0);
-    const int id = m & M_BODY;
-    const bool chi = id != 0;
-    if (chi) {
-      khalf = P.khalf;
-      a1 = P.a1;
-      kk = P.kk;
-      if (id == 1) {  // the only body that can move (u_s = 0 in the static ones)
-        const BodyDev B = ctl->body;
-        usx = T(B.u - B.omega * (double(y) - B.y));
-        usy = T(B.v + B.omega * (double(x) - B.x));
+  // moving disks: the states of this step and the tile's flags (LDS)
+  bool mwg = false;  // the tile meets a disk's window
+  __shared__ MovLds<(MOV ? BX : 1), (MOV ? BY : 1)> ml;
+  if constexpr (MOV) {
+    if (P.nmov > 0) {
+      if (SPLIT && !win) {
+        // a plain workgroup of the split launch: a tile of a hit box is the
+        // hit boxes' workgroups' (nothing stored here), any other tile holds
+        // plain fluid cells
+        const int sread = mov_pending ? pb : pb ^ 1;
+        bool hit = false;
+        for (int k = 0; k < P.nmov; ++k)
+          hit = hit || in_hit_box<BX, BY>(P.mov[k].B[sread].x, P.mov[k].B[sread].y, P.mov[k].half, t.tx, t.ty);
+        if (hit) return;
+      } else {
+        mwg = mover_prologue<T, BX, BY>(t.tx, t.ty, P, ctl, me_prev, hist, cap, maxb, pb, mov_pending, SPLIT, ml);
       }
     }
-    const T hx = mx + T(0.5) * P.gx, hy = my + T(0.5) * P.gy;
-    const T den = a1 * recip(rho);  // 1 / (rho (1 + k/2))
-    const T ux = (hx + khalf * rho * usx) * den;
-    const T uy = (hy + khalf * rho * usy) * den;
-    const T Fx = P.gx - kk * (hx - rho * usx);
-    const T Fy = P.gy - kk * (hy - rho * usy);
+  }
 
-    const T uu15 = T(1.5) * (ux * ux + uy * uy);
-    const T uF3 = T(3) * (ux * Fx + uy * Fy);
-    {
-      // Collision with the forcing term (Eqs. TRT and eqBd; BGK is tau- =
-      // tau+), per pair (a, a') with c_a' = -c_a.  Since 1 - 1/(2 tau) =
-      // (tau - 1/2) / tau, the forcing term enters as a shift of the
-      // equilibrium, even part by (tau+ - 1/2) F_even and odd part by
-      // (tau- - 1/2) F_odd:
-      //   q_a = wgt_a (De + Do),  q_a' = wgt_a (De - Do),
-      //   De = drho - 1.5 rho u.u - 3 (tau+ - 1/2) u.F
-      //        + (c.u) (4.5 rho (c.u) + 9 (tau+ - 1/2) (c.F)),
-      //   Do = 3 rho (c.u) + 3 (tau- - 1/2) (c.F),
-      // and out = d - (d - q)_even / tau+ - (d - q)_odd / tau-.  The
-      // non-equilibrium part d - q is formed before it is scaled, which
-      // keeps the FP32 rounding of mass and momentum unbiased.
-      const T C1 = drho - rho * uu15 - P.fo * uF3;
-      const T R45 = T(4.5) * rho, R3 = T(3) * rho;
-      put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, 0, d[0] - P.omega * (d[0] - T(wgt(0)) * C1),
-                     eidx);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int a = k < 2 ? k + 1 : k + 3;  // 1, 2, 5, 6; a' = 3, 4, 7, 8
-        const int o = opp(a);
-        const T w = T(wgt(a));
-        const T cu = dotc(a, ux, uy);
-        const T cF = dotc(a, Fx, Fy);
-        const T De = cu * (R45 * cu + P.fo9 * cF) + C1;
-        const T Do = R3 * cu + P.fo3 * cF;
-        T oa, oo;
-        if constexpr (!TRT) {
-          oa = d[a] - P.omega * (d[a] - w * (De + Do));
-          oo = d[o] - P.omega * (d[o] - w * (De - Do));
-        } else {
-          const T se = T(0.5) * (d[a] + d[o]) - w * De;
-          const T so = T(0.5) * (d[a] - d[o]) - w * Do;
-          oa = d[a] - P.omega * se - P.omega_m * so;
-          oo = d[o] - P.omega * se + P.omega_m * so;
-        }
-        put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, a, oa, eidx);
-        put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, o, oo, eidx);
-      }
-    }
-    if (MACRO) {
-      mrho[(uint32_t)c] = rho;
-      mux[(uint32_t)c] = ux;
-      muy[(uint32_t)c] = uy;
-    }
-
-    if (m & M_IFACE) {
-      // momentum exchange: every population pulled across the interface;
-      // the link's interface point is its midpoint seen from its fluid node.
-      // The 8 neighbour masks are loaded all at once (a load inside the
-      // divergent loop below would cost one memory round trip per link).
-      // The cell's links all belong to one body: its own if solid, else that
-      // of its solid neighbours (a fluid cell is linked to one body at most).
-      uint8_t nm[Q];
-      nbr_masks(mask, P, x, y, nm);
-      int bid = id;
-#pragma unroll
-      for (int a = 1; a < Q; ++a) bid = bid ? bid : (nm[a] & M_BODY);
-      double bx, by;
-      body_ref(ctl, P, bid, bx, by);
-      const bool moving = bid == 1;  // u_s = 0 on the links of the static bodies
-      double acc[3] = {0.0, 0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};  // the cell's momentum exchange
+  int bid = 0;                      // the body its links belong to
+  double sg[3] = {0.0, 0.0, 0.0};   // its stress, at a sample node
+  if (t.live) {
+    // the cell's flags: the mask, or for a lattice with moving disks the
+    // disks' ids around the cell (its tile ring index sc)
+    uint8_t m = 0;
+    if (!MOV || P.nmov == 0) {
+      m = mask[(uint32_t)t.c];
+    } else if (mwg) {
+      const int sc = (t.ly + 1) * (BX + 2) + t.lx + 1;
+      const uint8_t own = ml.sid[sc];
+      bool iface = false;
+      int other = 0;
+      bool two = false;
 #pragma unroll
       for (int a = 1; a < Q; ++a) {
-        int sx = x - cx(a), sy = y - cy(a);
-        bool link = true;
-        if (sx < 0 || sx >= P.nx) {
-          if ((sx < 0 ? P.kind[WEST] : P.kind[EAST]) != EDGE_PERIODIC) link = false;
-          sx = sx < 0 ? sx + P.nx : sx - P.nx;
+        const uint8_t nb = ml.sid[sc - cy(a) * (BX + 2) - cx(a)];
+        if (nb == 0xFF) continue;
+        iface = iface || ((nb != 0) != (own != 0));
+        if (!own && nb) {
+          two = two || (other && other != nb);
+          other = nb;
         }
-        if (sy < 0 || sy >= P.ny) {
-          if ((sy < 0 ? P.kind[SOUTH] : P.kind[NORTH]) != EDGE_PERIODIC) link = false;
-          sy = sy < 0 ? sy + P.ny : sy - P.ny;
-        }
-        const bool schi = (nm[a] & M_BODY) != 0;
-        if (!link || schi == chi) continue;
-        double gx, gy, s;
-        if (chi) { gx = sx + 0.5 * cx(a); gy = sy + 0.5 * cy(a); s = 1.0; }
-        else { gx = x - 0.5 * cx(a); gy = y - 0.5 * cy(a); s = -1.0; }
-        double ugx = 0.0, ugy = 0.0;
-        if (moving) {
-          const BodyDev &B = ctl->body;
-          ugx = B.u - B.omega * (gy - B.y);
-          ugy = B.v + B.omega * (gx - B.x);
-        }
-        const double fa = wgt(a) * P.rho0d + double(d[a]);
-        const double lx = s * (cx(a) - ugx) * fa, ly = s * (cy(a) - ugy) * fa;
-        acc[0] += lx;
-        acc[1] += ly;
-        acc[2] += (gx - bx) * ly - (gy - by) * lx;
       }
-      // this cell's contribution goes to its slot; the finalize sums them
-      double *o = me_out + (long long)imap[(uint32_t)c] * ME_STRIDE;
-      o[0] = acc[0];
-      o[1] = acc[1];
-      o[2] = acc[2];
+      if (two) atomicOr(&ctl->err, 2);
+      const int sb = ml.smp[t.ly * BX + t.lx];
+      if (sb & (sb - 1)) atomicOr(&ctl->err, 4);  // a node sampled for two disks
+      m = (uint8_t)(own | (iface ? M_IFACE : 0) | (sb ? M_SAMPLE : 0));
     }
-    if (m & M_SAMPLE) {
-      // stress of the streamed populations at a (fluid) sample node
-      T pxx = T(0), pxy = T(0), pyy = T(0);
-#pragma unroll
-      for (int a = 1; a < Q; ++a) {
-        const T w = T(wgt(a));
-        const T cu = dotc(a, ux, uy);
-        const T ne = d[a] - (w * drho + w * rho * (T(3) * cu + T(4.5) * cu * cu - uu15));
-        pxx += T(cx(a) * cx(a)) * ne;
-        pxy += T(cx(a) * cy(a)) * ne;
-        pyy += T(cy(a) * cy(a)) * ne;
-      }
-      const double pr = double(drho) / 3.0;
-      const double sxx = -pr - P.facd * double(pxx);
-      const double sxy = -P.facd * double(pxy);
-      const double syy = -pr - P.facd * double(pyy);
-      // the node's stress goes to its record's slot; the finalize contracts
-      // it with the aggregated weights
-      double *g = sig_out + (long long)si_map[(uint32_t)c] * SIG_STRIDE;
-      g[0] = sxx;
-      g[1] = sxy;
-      g[2] = syy;
-    }
+    cell_update<S, BX, BY, MACRO, TRT, AA, MOV>(t, d, m, fout, mask, P, ctl, si_map, imap, me_out, sig_out, mrho,
+                                                 mux, muy, ml, acc, bid, sg);
+  }
+  if constexpr (MOV) {
+    if (mwg) mover_epilogue<T, BX, BY>(t.tx, t.ty, P, acc, bid, sg, me_out, ml);
   }
 
   if (fin_prev && tile == 0) {
@@ -651,20 +1138,91 @@ __device__ __forceinline__ void step_tile(
   }
 }
 
+// Launch with moving disks (P.nmov > 0): workgroup b < P.wblocks takes tile
+// b of the disks' hit boxes laid end to end, disk by disk, each box as
+// hit_tiles(h, BX) x hit_tiles(h, BY) tiles from its lower corner; -1 for a
+// place outside the box or the lattice, or a tile an earlier disk's box
+// already holds.
+template <int BX, int BY, typename T>
+__device__ __forceinline__ int window_block_tile(int b, const StepArgs<T> &P, int sread) {
+  const int tiles_y = (P.ny + BY - 1) / BY;
+  // every disk's reference point and window, read at once (one round trip)
+  int h[MAX_MOVERS];
+  double bx[MAX_MOVERS], by[MAX_MOVERS];
+#pragma unroll
+  for (int k = 0; k < MAX_MOVERS; ++k) {
+    const int kk = k < P.nmov ? k : 0;
+    h[k] = P.mov[kk].half;
+    bx[k] = P.mov[kk].B[sread].x;
+    by[k] = P.mov[kk].B[sread].y;
+  }
+  int tile = -1, j = b;
+  bool found = false;
+#pragma unroll
+  for (int k = 0; k < MAX_MOVERS; ++k) {
+    if (k >= P.nmov || found) continue;
+    const int n = hit_tiles(h[k], BX) * hit_tiles(h[k], BY);
+    if (j >= n) {
+      j -= n;
+      continue;
+    }
+    found = true;
+    int hx0, hy0, hx1, hy1;
+    hit_box<BX, BY>(bx[k], by[k], h[k], hx0, hy0, hx1, hy1);
+    const int w = hit_tiles(h[k], BX);
+    const int tx = hx0 + j % w, ty = hy0 + j / w;
+    if (tx > hx1 || ty > hy1 || tx < 0 || ty < 0 || tx >= P.tiles_x || ty >= tiles_y) continue;
+    bool earlier = false;
+#pragma unroll
+    for (int q = 0; q < k; ++q) earlier = earlier || in_hit_box<BX, BY>(bx[q], by[q], h[q], tx, ty);
+    if (!earlier) tile = ty * P.tiles_x + tx;
+  }
+  return tile;
+}
+
 // Resident waves per SIMD the step kernels are compiled for: 8 for 4- and
 // 2-byte storage (register budget 64 VGPRs and the SGPRs that allow 8 waves);
 // FP64 needs more VGPRs and is left to the compiler.
 template <typename S> constexpr int step_waves() { return sizeof(typename Store<S>::T) == 8 ? 1 : 8; }
+// With moving disks the workgroups of the disks' windows run a long serial
+// prologue and epilogue (force sums, state update, point stencils); the
+// register budget of 4 waves per SIMD keeps them free of spills.
+template <typename S, bool MOV> constexpr int step_waves_mov() { return MOV && step_waves<S>() > 4 ? 4 : step_waves<S>(); }
 
-template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA>
-__global__ void __launch_bounds__(BX *BY, step_waves<S>())
+template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA, bool MOV = false>
+__global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
     k_step(const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
            const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl,
            const SiRec *__restrict__ recs, const int *__restrict__ si_map,
            const int *__restrict__ imap, const BodyTab *__restrict__ bt, double *__restrict__ me_out,
            const double *__restrict__ me_prev, double *__restrict__ sig_out, const double *__restrict__ sig_prev,
            int fin_prev, double *__restrict__ hist, int cap, int maxb, typename Store<S>::T *__restrict__ mrho,
-           typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy) {
+           typename Store<S>::T *__restrict__ mux, typename Store<S>::T *__restrict__ muy, int pb, int mov_pending) {
+  if constexpr (MOV) {
+    // moving disks (P.nmov > 0): the first P.wblocks workgroups (a multiple
+    // of 8) take the tiles of the disks' hit boxes, so that their long serial
+    // work starts first; the others take the tiles XCD by XCD as below and
+    // leave those of the hit boxes alone
+    const int b = blockIdx.x;
+    int tile;
+    const bool win = b < P.wblocks;
+    if (win) {
+      // these workgroups share their compute units with plain tiles; their
+      // waves go first in instruction issue
+      __builtin_amdgcn_s_setprio(3);
+      tile = window_block_tile<BX, BY>(b, P, mov_pending ? pb : pb ^ 1);
+      if (tile < 0) return;
+    } else {
+      const int bb = b - P.wblocks, xcd = bb & 7, i = bb >> 3;
+      const int start = xcd * P.per_xcd, len = min(P.per_xcd, P.ntiles - start);
+      if (i >= len) return;
+      tile = start + i;
+    }
+    step_tile<S, BX, BY, MACRO, TRT, AA, true, true>(tile, fin, fout, mask, P, ctl, recs, si_map, imap, bt, me_out,
+                                                     me_prev, sig_out, sig_prev, 0, hist, cap, maxb, mrho, mux, muy,
+                                                     pb, mov_pending, win);
+    return;
+  }
   // XCD-aware tile order: consecutive workgroups go round-robin over the 8
   // XCDs, so give each XCD a contiguous band of tiles (shared halo lines stay
   // in that XCD's L2).  A band only a few rounds of workgroups deep is
@@ -677,8 +1235,9 @@ __global__ void __launch_bounds__(BX *BY, step_waves<S>())
   int t = i + P.rot[xcd];
   t -= t >= len ? len : 0;
   const int tile = start + t;
-  step_tile<S, BX, BY, MACRO, TRT, AA>(tile, fin, fout, mask, P, ctl, recs, si_map, imap, bt, me_out, me_prev, sig_out,
-                                   sig_prev, fin_prev, hist, cap, maxb, mrho, mux, muy);
+  step_tile<S, BX, BY, MACRO, TRT, AA, MOV>(tile, fin, fout, mask, P, ctl, recs, si_map, imap, bt, me_out, me_prev,
+                                            sig_out, sig_prev, fin_prev, hist, cap, maxb, mrho, mux, muy, pb,
+                                            mov_pending);
 }
 
 // Per-lattice description for the batched step: one launch covers the tiles
@@ -700,11 +1259,8 @@ template <typename T> struct CaseDesc {
   int ntiles;             // its tiles
   int cur0;               // parity of the buffer holding the state at launch 0
   int pbit0;              // parity of the step computed by launch 0
-  int pending0;           // launch 0 finalizes the forces of the step before it
-  int moving;             // forces are finalized by the body kernel instead
-  // body-kernel arguments
-  int perx, pery, maxp, maxslot;
-  const double *pts;
+  int pending0;           // launch 0 finalizes the static bodies' forces of the step before it
+  int mov_pending0;       // launch 0 sums the moving disks' forces of the step before it
   // AA pattern: the perimeter copies kept by the steps of parity 0 and 1
   void *ec[2];
 };
@@ -727,8 +1283,9 @@ __global__ void k_fill_tile_case(const CaseDesc<T> *__restrict__ cases, int ncas
 
 // Batched step: launch number `flip` (0 or 1, alternating) of a run over
 // ncases lattices; the lattice of each tile comes from the tile table.
-template <typename S, int BX, int BY, bool TRT>
-__global__ void __launch_bounds__(BX *BY, step_waves<S>())
+// MOV: some lattice of the batch has moving disks.
+template <typename S, int BX, int BY, bool TRT, bool MOV = false>
+__global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
     k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
                  const int *__restrict__ tile_case, int total_tiles, int per_xcd, int flip, int first) {
   using T = typename Store<S>::T;
@@ -739,12 +1296,14 @@ __global__ void __launch_bounds__(BX *BY, step_waves<S>())
   const CaseDesc<T> *__restrict__ C = cases + tile_case[gtile];
   const StepArgs<T> P = C->P;
   const int par = C->cur0 ^ flip, pb = C->pbit0 ^ flip;
-  const int fin_prev = C->moving ? 0 : (first ? C->pending0 : 1);
+  const int fin_prev = P.nmov ? 0 : (first ? C->pending0 : 1);
+  const int mov_pending = first ? C->mov_pending0 : 1;
   const S *fin = (const S *)C->buf[par];
   S *fout = (S *)C->buf[par ^ 1];
-  step_tile<S, BX, BY, false, TRT, 0>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map, C->imap,
-                                   C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1], fin_prev, C->hist,
-                                   C->cap, C->maxb, nullptr, nullptr, nullptr);
+  step_tile<S, BX, BY, false, TRT, 0, MOV>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map,
+                                           C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
+                                           fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
+                                           mov_pending);
 }
 
 // Batched step of lattices in the AA pattern (one population buffer each):
@@ -752,8 +1311,8 @@ __global__ void __launch_bounds__(BX *BY, step_waves<S>())
 // stays in the cell (AA = 2), per lattice by its own step parity; the
 // perimeter copies alternate with it (read: the previous step's, written:
 // this step's).
-template <typename S, bool TRT>
-__global__ void __launch_bounds__(256, step_waves<S>())
+template <typename S, bool TRT, bool MOV = false>
+__global__ void __launch_bounds__(256, (step_waves_mov<S, MOV>()))
     k_step_batch_aa(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
                     const int *__restrict__ tile_case, int total_tiles, int per_xcd, int flip, int first) {
   using T = typename Store<S>::T;
@@ -765,16 +1324,19 @@ __global__ void __launch_bounds__(256, step_waves<S>())
   const int pb = C->pbit0 ^ flip;
   P.ec_in = C->ec[pb ^ 1];
   P.ec_out = C->ec[pb];
-  const int fin_prev = C->moving ? 0 : (first ? C->pending0 : 1);
+  const int fin_prev = P.nmov ? 0 : (first ? C->pending0 : 1);
+  const int mov_pending = first ? C->mov_pending0 : 1;
   S *F = (S *)C->buf[0];
   if (pb)
-    step_tile<S, 64, 4, false, TRT, 1>(gtile - C->tile0, nullptr, F, C->mask, P, C->ctl, C->recs, C->si_map,
-                                       C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
-                                       fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr);
+    step_tile<S, 64, 4, false, TRT, 1, MOV>(gtile - C->tile0, nullptr, F, C->mask, P, C->ctl, C->recs, C->si_map,
+                                            C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
+                                            fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
+                                            mov_pending);
   else
-    step_tile<S, 64, 4, false, TRT, 2>(gtile - C->tile0, nullptr, F, C->mask, P, C->ctl, C->recs, C->si_map,
-                                       C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
-                                       fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr);
+    step_tile<S, 64, 4, false, TRT, 2, MOV>(gtile - C->tile0, nullptr, F, C->mask, P, C->ctl, C->recs, C->si_map,
+                                            C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
+                                            fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
+                                            mov_pending);
 }
 
 template <int NT>

@@ -64,7 +64,7 @@ int pitch_of(const vplbm_params &p) {
 
 struct Layout {
   size_t A, B, ec, ec_stride, mask, mrho, mux, muy, si_map, imap, me, me_stride, sig, sig_stride, cbc, hist, ctl, bt, bodies,
-      recs, pts, verts, staging, siout, total;
+      movers, recs, pts, verts, staging, siout, total;
 };
 
 int max_bodies_of(const vplbm_params &p) { return p.max_bodies > 0 ? p.max_bodies : 1; }
@@ -110,6 +110,7 @@ Layout layout_of(const vplbm_params &p) {
   L.ctl = take(sizeof(Ctl));
   L.bt = take((size_t)MAX_BODIES * sizeof(BodyTab));
   L.bodies = take((size_t)(MAX_BODIES + 1) * sizeof(BodyDev));
+  L.movers = take((size_t)MAX_MOVERS * sizeof(MoverDev));
   // one record per distinct sample node: up to 4 per point with the interpolated rule
   const size_t maxrec = (size_t)maxp * (p.si_rule == 1 ? 4 : 1);
   L.recs = take(maxrec * sizeof(SiRec));
@@ -191,6 +192,12 @@ struct vplbm_lattice {
   double gx = 0.0, gy = 0.0;
   int shape = SHAPE_NONE, mode = MODE_STATIC;
   double disk_r = 0.0;
+  // moving disks (mover.hpp): their number, host copies of their set-up, and
+  // whether the forces of the last step are still to be summed into their
+  // states (vplbm_sync and every read do it)
+  int nmov = 0;
+  std::vector<MoverDev> movers;
+  bool mov_pending = false;
   int npts = 0;
   std::vector<double> si_world;  // host copy of the registered world points [5][npts]
   std::vector<int> si_body;      // body of each registered point (1..nbody)
@@ -215,6 +222,7 @@ struct vplbm_lattice {
   int *err_dev() const { return (int *)((char *)ctl() + offsetof(Ctl, err)); }
   double *sig(long long n) const { return (double *)at(L.sig + (size_t)(n & 1) * L.sig_stride); }
   const SiRec *recs() const { return (const SiRec *)at(L.recs); }
+  MoverDev *movers_dev() const { return (MoverDev *)at(L.movers); }
 
   int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -310,6 +318,14 @@ struct vplbm_lattice {
       a.cbu[e] = T(U);
       a.cbi[e] = T(1.0 / (1.0 + U));
     }
+    a.mov = movers_dev();
+    a.nmov = nmov;
+    a.pts = (const double *)at(L.pts);
+    a.maxp = maxp;
+    a.si_rule = p.si_rule;
+    a.wblocks = 0;
+    for (int k = 0; k < nmov; ++k) a.wblocks += hit_tiles(movers[k].half, MOV_BX) * hit_tiles(movers[k].half, MOV_BY);
+    a.wblocks = (a.wblocks + 7) / 8 * 8;
     return a;
   }
 };
@@ -335,11 +351,12 @@ int resolve_pwin(vplbm_lattice *L) {
   return VPLBM_OK;
 }
 
-template <typename S, int BX, int BY, int AA>
+template <typename S, int BX, int BY, int AA, bool MOV>
 int launch_step_t(vplbm_lattice *L, bool macro) {
   using T = typename Store<S>::T;
   const StepArgs<T> a = L->step_args<T>();
-  const int grid = 8 * a.per_xcd;
+  // with moving disks: the hit boxes' workgroups first (see k_step)
+  const int grid = (MOV ? a.wblocks : 0) + 8 * a.per_xcd;
   // AA launches read and write the one buffer through fout
   const S *fin = AA == 0 ? (const S *)L->A() : nullptr;
   S *fout = (S *)L->Bbuf();
@@ -352,38 +369,45 @@ int launch_step_t(vplbm_lattice *L, bool macro) {
   double *gout = L->sig(n);
   const double *gprev = L->sig(n - 1);
   const int fin_prev = L->pending ? 1 : 0;
+  const int pb = (int)(n & 1), mpend = L->mov_pending ? 1 : 0;
   double *hist = (double *)L->at(L->L.hist);
   const int *imap = L->imap();
   const BodyTab *bt = L->bt();
+#define VP_STEP_ARGS                                                                                              \
+  dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a, L->ctl(), recs, smap, imap, bt, mout, mprev, gout, \
+      gprev, fin_prev, hist, L->cap, L->maxb, r, u, v, pb, mpend
   if (macro) {
     if (a.trt)
-      VP_LAUNCH((k_step<S, BX, BY, true, true, AA>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
-                L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
+      VP_LAUNCH((k_step<S, BX, BY, true, true, AA, MOV>), VP_STEP_ARGS);
     else
-      VP_LAUNCH((k_step<S, BX, BY, true, false, AA>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
-                L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
+      VP_LAUNCH((k_step<S, BX, BY, true, false, AA, MOV>), VP_STEP_ARGS);
   } else {
     if (a.trt)
-      VP_LAUNCH((k_step<S, BX, BY, false, true, AA>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(), a,
-                L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
+      VP_LAUNCH((k_step<S, BX, BY, false, true, AA, MOV>), VP_STEP_ARGS);
     else
-      VP_LAUNCH((k_step<S, BX, BY, false, false, AA>), dim3(grid), dim3(BX * BY), 0, L->stream, fin, fout, L->mask(),
-                a, L->ctl(), recs, smap, imap, bt, mout, mprev, gout, gprev, fin_prev, hist, L->cap, L->maxb, r, u, v);
+      VP_LAUNCH((k_step<S, BX, BY, false, false, AA, MOV>), VP_STEP_ARGS);
   }
+#undef VP_STEP_ARGS
   return L->launched("k_step");
 }
 
 template <typename S> int launch_step_s(vplbm_lattice *L, bool macro) {
+  if (L->nmov) {  // moving disks: 64x4 tiles (see vplbm_set_tile)
+    if (L->bx != 64 || L->by != 4) return L->fail(VPLBM_EINVAL, "a lattice with moving disks runs the 64x4 tile only");
+    if (!L->aa()) return launch_step_t<S, 64, 4, 0, true>(L, macro);
+    return ((L->nstep + 1) & 1) ? launch_step_t<S, 64, 4, 1, true>(L, macro) : launch_step_t<S, 64, 4, 2, true>(L, macro);
+  }
   if (L->aa()) {  // odd steps pull and push, even steps stay in the cell (64x4 tiles)
     if (L->bx != 64 || L->by != 4) return L->fail(VPLBM_EINVAL, "the AA pattern runs with the 64x4 tile only");
-    return ((L->nstep + 1) & 1) ? launch_step_t<S, 64, 4, 1>(L, macro) : launch_step_t<S, 64, 4, 2>(L, macro);
+    return ((L->nstep + 1) & 1) ? launch_step_t<S, 64, 4, 1, false>(L, macro)
+                                : launch_step_t<S, 64, 4, 2, false>(L, macro);
   }
-  if (L->bx == 64 && L->by == 4) return launch_step_t<S, 64, 4, 0>(L, macro);
-  if (L->bx == 128 && L->by == 2) return launch_step_t<S, 128, 2, 0>(L, macro);
-  if (L->bx == 256 && L->by == 1) return launch_step_t<S, 256, 1, 0>(L, macro);
-  if (L->bx == 64 && L->by == 1) return launch_step_t<S, 64, 1, 0>(L, macro);
-  if (L->bx == 64 && L->by == 2) return launch_step_t<S, 64, 2, 0>(L, macro);
-  if (L->bx == 128 && L->by == 1) return launch_step_t<S, 128, 1, 0>(L, macro);
+  if (L->bx == 64 && L->by == 4) return launch_step_t<S, 64, 4, 0, false>(L, macro);
+  if (L->bx == 128 && L->by == 2) return launch_step_t<S, 128, 2, 0, false>(L, macro);
+  if (L->bx == 256 && L->by == 1) return launch_step_t<S, 256, 1, 0, false>(L, macro);
+  if (L->bx == 64 && L->by == 1) return launch_step_t<S, 64, 1, 0, false>(L, macro);
+  if (L->bx == 64 && L->by == 2) return launch_step_t<S, 64, 2, 0, false>(L, macro);
+  if (L->bx == 128 && L->by == 1) return launch_step_t<S, 128, 1, 0, false>(L, macro);
   return L->fail(VPLBM_EINVAL, "unsupported tile shape %dx%d", L->bx, L->by);
 }
 
@@ -479,42 +503,43 @@ int launch_si_select(vplbm_lattice *L) {
   return L->launched("k_si_select");
 }
 
-// after the step kernel of step n (= nstep + 1): finalize its forces, move the
-// body, rebuild the mask
-int launch_body_step(vplbm_lattice *L) {
-  VP_LAUNCH(k_body_step, dim3(1), dim3(BODY_NT), 0, L->stream, L->mask(), L->ctl(),
-                     (const double *)L->me(L->nstep + 1), (const double *)L->sig(L->nstep + 1),
-                     (double *)L->at(L->L.hist), L->cap, L->maxb, L->p.nx, L->p.ny, L->pitch,
-                     (int)L->periodic_x(), (int)L->periodic_y(), (const double *)L->at(L->L.pts), L->maxp,
-                     (SiRec *)L->at(L->L.recs), (int *)L->at(L->L.si_map), L->imap(), (int)L->maxslot, L->bt(),
-                     (const BodyDev *)L->bodies());
-  return L->launched("k_body_step");
+// The moving disks' forces of the last step summed and their states advanced
+// (between steps, as the next step launch would do it), the mask bytes of
+// their windows rewritten from the new states.
+int flush_movers(vplbm_lattice *L) {
+  if (!L->nmov || !L->mov_pending) return VPLBM_OK;
+  const long long n = L->nstep;
+  VP_LAUNCH(k_mover_flush, dim3(1), dim3(FLUSH_NT), 0, L->stream, L->movers_dev(), L->nmov,
+            (const double *)L->me(n), (int)(n & 1), (const double *)L->at(L->L.pts), L->maxp, L->p.si_rule, L->p.nx,
+            L->p.ny, L->pitch, (int)L->periodic_x(), (int)L->periodic_y(), L->mask(), L->ctl(),
+            (double *)L->at(L->L.hist), L->cap, L->maxb);
+  const int rc = L->launched("k_mover_flush");
+  if (!rc) L->mov_pending = false;
+  return rc;
 }
 
-// sum the last step's force slots into the history (forces readable)
+// sum the last step's force terms into the history (forces readable)
 int flush(vplbm_lattice *L) {
-  if (!L->pending) return VPLBM_OK;
+  int rc = flush_movers(L);
+  if (rc || !L->pending) return rc;
   VP_LAUNCH((k_finalize<256>), dim3(1), dim3(256), 0, L->stream, (const double *)L->me(L->nstep),
                      (const double *)L->sig(L->nstep), L->recs(), (const BodyTab *)L->bt(), L->ctl(),
                      (double *)L->at(L->L.hist), L->cap, L->maxb);
-  int rc = L->launched("k_finalize");
+  rc = L->launched("k_finalize");
   if (!rc) L->pending = false;
   return rc;
 }
 
-// one time step: the step kernel, then for a moving disk the body kernel
-// (which finalizes this step's forces) and the sample reselection; a static
-// body leaves its forces to the next step kernel or to flush()
+// one time step: the step kernel.  Its force terms are summed by the next
+// step launch (or by flush()): static bodies' by its first workgroup, moving
+// disks' by every workgroup near them, which also advance the disks.
 int one_step(vplbm_lattice *L, bool macro) {
-  int rc = launch_step(L, macro);
+  const int rc = launch_step(L, macro);
   if (rc) return rc;
-  if (L->mode != MODE_STATIC) {  // only disks move
-    rc = launch_body_step(L);  // also reselects the sample nodes
-    if (rc) return rc;
-    L->pending = false;
-  } else {
+  if (L->nmov)
+    L->mov_pending = true;
+  else
     L->pending = true;
-  }
   L->cur ^= 1;
   L->nstep += 1;
   return VPLBM_OK;
@@ -522,14 +547,131 @@ int one_step(vplbm_lattice *L, bool macro) {
 
 long long fixq(double v) { return llround(v * FIXQ); }
 
-// a moving disk renumbers its interface cells inside its rebuilt region
-// every step: the slots must hold the largest such region
-int check_moving_capacity(vplbm_lattice *L) {
-  const long long side = (long long)std::ceil(2.0 * L->disk_r) + 2 * REGION_MARGIN + 8;
-  if (side * side > L->maxslot)
-    return L->fail(VPLBM_EINVAL, "max_interface_cells = %lld is below a moving disk's region (%lld cells)",
-                   L->maxslot, side * side);
+int pull_movers(vplbm_lattice *L) {
+  L->movers.resize(MAX_MOVERS);
+  if (!L->nmov) return VPLBM_OK;
+  int rc = L->hip(hipMemcpyAsync(L->movers.data(), L->movers_dev(), sizeof(MoverDev) * L->nmov,
+                                 hipMemcpyDeviceToHost, L->stream),
+                  "movers read");
+  if (!rc) rc = L->sync();
+  return rc;
+}
+
+int push_movers(vplbm_lattice *L) {
+  if (!L->nmov) return VPLBM_OK;
+  int rc = L->hip(hipMemcpyAsync(L->movers_dev(), L->movers.data(), sizeof(MoverDev) * L->nmov,
+                                 hipMemcpyHostToDevice, L->stream),
+                  "movers write");
+  if (!rc) rc = L->sync();
+  return rc;
+}
+
+// Window half size of a moving disk: its radius or its farthest point from
+// the reference point, whichever is larger, plus WIN_MARGIN (interface
+// links, sample walks of up to four nodes along a diagonal, a cell of motion).
+// (xr, yr): the reference point at which the points were registered.
+int mover_half(const vplbm_lattice *L, double r, double xr, double yr, int pt0, int pt1) {
+  double rmax = r;
+  const int n = L->npts;
+  for (int i = pt0; i < pt1; ++i) {
+    const double dx = L->si_world[i] - xr, dy = L->si_world[n + i] - yr;
+    rmax = std::max(rmax, std::sqrt(dx * dx + dy * dy));
+  }
+  return (int)std::ceil(rmax) + WIN_MARGIN;
+}
+
+// The tiles (MOV_BX x MOV_BY) a window of 2 h + 1 cells a side can meet,
+// wherever it lies: its partial-sum grid, gx x gy.
+void mover_grid(int h, int &gx, int &gy) {
+  const int side = 2 * h + 1;
+  gx = (side - 1 + MOV_BX - 1) / MOV_BX + 1;
+  gy = (side - 1 + MOV_BY - 1) / MOV_BY + 1;
+}
+
+// The disks' tile partials live in the interface-slot buffers (one set per
+// step parity): PART_ENTRY doubles per tile of each disk's grid, in slots of
+// ME_STRIDE doubles.
+int check_moving_capacity(vplbm_lattice *L, int nmov, const int *half) {
+  long long need = 0;
+  for (int k = 0; k < nmov; ++k) {
+    int gx, gy;
+    mover_grid(half[k], gx, gy);
+    need += (long long)gx * gy;
+  }
+  need = need * PART_ENTRY / ME_STRIDE;
+  if (need > L->maxslot)
+    return L->fail(VPLBM_EINVAL, "max_interface_cells = %lld is below the moving disks' tile partials (%lld slots)",
+                   L->maxslot, need);
   return VPLBM_OK;
+}
+
+// the window rectangle (clipped to the lattice) of a disk at (x, y)
+void mover_rect(const vplbm_lattice *L, double x, double y, int h, int (&r)[4]) {
+  const int ox = (int)std::floor(x) - h, oy = (int)std::floor(y) - h;
+  r[0] = std::max(ox, 0);
+  r[1] = std::max(oy, 0);
+  r[2] = std::min(ox + 2 * h + 1, L->p.nx);
+  r[3] = std::min(oy + 2 * h + 1, L->p.ny);
+}
+
+// Body 1, a disk with the motion c.mode (prescribed or free) and the state
+// c.body, becomes a moving disk of the step kernel (mover.hpp): its states,
+// dynamics, window and points go to the device.  The caller has checked the
+// window capacity.
+int become_mover(vplbm_lattice *L, const Ctl &c) {
+  MoverDev m{};
+  m.B[0] = m.B[1] = c.body;
+  m.r = L->disk_r;
+  m.mass = c.mass;
+  m.inertia = c.inertia;
+  m.gx = c.gx;
+  m.gy = c.gy;
+  m.buoy = c.buoy;
+  m.R = fixq(L->disk_r);
+  m.nfin = c.step;
+  m.mode = c.mode;
+  m.source = c.source;
+  m.half = mover_half(L, L->disk_r, c.body.x, c.body.y, 0, L->npts);
+  m.pt0 = 0;
+  m.pt1 = L->npts;
+  m.part0 = 0;
+  mover_grid(m.half, m.ptx, m.pty);
+  // the mask bytes the set-up wrote (the disk's region, the sample nodes):
+  // within the window, which the first flush clears
+  int r[4];
+  mover_rect(L, c.body.x, c.body.y, m.half, r);
+  for (int k = 0; k < 4; ++k) m.mwin[k] = r[k];
+  m.mwin[0] = std::min(m.mwin[0], c.region[0]);
+  m.mwin[1] = std::min(m.mwin[1], c.region[1]);
+  m.mwin[2] = std::max(m.mwin[2], c.region[2]);
+  m.mwin[3] = std::max(m.mwin[3], c.region[3]);
+  L->movers.assign(MAX_MOVERS, MoverDev{});
+  L->movers[0] = m;
+  L->nmov = 1;
+  L->mov_pending = false;
+  L->bx = 64;  // the moving-disk step kernels run 64x4 tiles
+  L->by = 4;
+  return push_movers(L);
+}
+
+// new points of a moving disk (body 1): its point range and window; the next
+// flush clears the old window's mask bytes too
+int update_mover_points(vplbm_lattice *L, const Ctl &c) {
+  if (!L->nmov) return VPLBM_OK;
+  int rc = pull_movers(L);
+  if (rc) return rc;
+  MoverDev &m = L->movers[0];
+  m.pt0 = 0;
+  m.pt1 = L->npts;
+  m.half = mover_half(L, L->disk_r, c.body.x, c.body.y, 0, L->npts);
+  mover_grid(m.half, m.ptx, m.pty);
+  int r[4];
+  mover_rect(L, c.body.x, c.body.y, m.half, r);
+  m.mwin[0] = std::min(m.mwin[0], r[0]);
+  m.mwin[1] = std::min(m.mwin[1], r[1]);
+  m.mwin[2] = std::max(m.mwin[2], r[2]);
+  m.mwin[3] = std::max(m.mwin[3], r[3]);
+  return push_movers(L);
 }
 
 // the registered points of bodies 1..nbody, concatenated body by body
@@ -565,6 +707,8 @@ int reset_geometry(vplbm_lattice *L, Ctl &c) {
   c.nbody = 1;
   L->nbody = 1;
   L->refs.clear();
+  L->nmov = 0;  // a new geometry is static until a motion is set
+  L->mov_pending = false;
   bool others = false;  // points of bodies 2.. go with their bodies
   for (int b = 2; b <= MAX_BODIES; ++b) {
     others = others || !L->si_sets[b].empty();
@@ -592,6 +736,8 @@ int check_sample_error(vplbm_lattice *L) {
   if (rc) return rc;
   const int e = c.err;
   if (e & 16) return L->fail(VPLBM_EUNSTABLE, "the solution diverged (a non-finite density at some step)");
+  if (e & 32)
+    return L->fail(VPLBM_EUNSTABLE, "a moving disk moved a cell or more in one step (or left the lattice)");
   if (e & 15) {
     c.err = 0;
     rc = L->ctl_push(c);
@@ -818,8 +964,22 @@ static int reset_counters(vplbm_lattice *L) {
   c.err = 0;
   rc = L->ctl_push(c);
   if (rc) return rc;
+  if (L->nmov) {
+    // moving disks restart from their current state (both slots), no step taken
+    rc = pull_movers(L);
+    if (rc) return rc;
+    for (int k = 0; k < L->nmov; ++k) {
+      MoverDev &m = L->movers[k];
+      const BodyDev now = m.B[L->nstep & 1];
+      m.B[0] = m.B[1] = now;
+      m.nfin = 0;
+    }
+    rc = push_movers(L);
+    if (rc) return rc;
+  }
   L->nstep = 0;
   L->pending = false;
+  L->mov_pending = false;
   L->macro_valid = false;
   return VPLBM_OK;
 }
@@ -828,13 +988,18 @@ int vplbm_init_uniform(vplbm_lattice *L, double rho, double ux, double uy) {
   if (!L) return VPLBM_EINVAL;
   if (!(rho > 0.0) || !std::isfinite(rho) || !std::isfinite(ux) || !std::isfinite(uy))
     return L->fail(VPLBM_EINVAL, "rho must be > 0 and velocities finite");
-  int rc = launch_init(L, 0, L->p.ny, nullptr, nullptr, nullptr, rho, ux, uy);
+  int rc = flush(L);  // a moving disk's state and mask as of the last step
+  if (!rc) rc = launch_init(L, 0, L->p.ny, nullptr, nullptr, nullptr, rho, ux, uy);
   if (!rc) rc = reset_counters(L);
   return rc;
 }
 
 int vplbm_set_fields(vplbm_lattice *L, const double *rho, const double *ux, const double *uy) {
   if (!L || !rho || !ux || !uy) return L ? L->fail(VPLBM_EINVAL, "NULL field") : VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
   const int nx = L->p.nx, ny = L->p.ny;
   for (long long k = 0; k < (long long)nx * ny; ++k)
     if (!(rho[k] > 0.0) || !std::isfinite(rho[k]) || !std::isfinite(ux[k]) || !std::isfinite(uy[k]))
@@ -1044,7 +1209,8 @@ int vplbm_set_body_motion(vplbm_lattice *L, const vplbm_body_state *s) {
   if (L->shape != SHAPE_DISK && moves)
     return L->fail(VPLBM_EINVAL, "only disks can move; polygons and masks are static");
   if (moves) {
-    const int rc = check_moving_capacity(L);
+    const int h = mover_half(L, L->disk_r, s->x, s->y, 0, L->npts);
+    const int rc = check_moving_capacity(L, 1, &h);
     if (rc) return rc;
   }
   Ctl c;
@@ -1082,6 +1248,10 @@ int vplbm_set_body_motion(vplbm_lattice *L, const vplbm_body_state *s) {
     if (!rc) rc = refresh_si(L);
     if (!rc) rc = check_sample_error(L);
   }
+  if (!rc && moves) {
+    rc = L->ctl_pull(c);
+    if (!rc) rc = become_mover(L, c);
+  }
   return rc;
 }
 
@@ -1094,7 +1264,11 @@ int vplbm_set_body_dynamics(vplbm_lattice *L, double rho_s, double gx, double gy
   L->pwin_ok = false;
   if (L->shape != SHAPE_DISK) return L->fail(VPLBM_ESTATE, "free bodies must be disks");
   {
-    const int rc = check_moving_capacity(L);
+    Ctl c0;
+    int rc = L->ctl_pull(c0);
+    if (rc) return rc;
+    const int h = mover_half(L, L->disk_r, c0.body.x, c0.body.y, 0, L->npts);
+    rc = check_moving_capacity(L, 1, &h);
     if (rc) return rc;
   }
   if (!(rho_s > 0.0) || !std::isfinite(rho_s) || !std::isfinite(gx) || !std::isfinite(gy))
@@ -1116,6 +1290,7 @@ int vplbm_set_body_dynamics(vplbm_lattice *L, double rho_s, double gx, double gy
   L->mode = MODE_FREE;
   rc = L->ctl_push(c);
   if (!rc && L->npts) rc = upload_points(L, c);
+  if (!rc) rc = become_mover(L, c);
   return rc;
 }
 
@@ -1138,6 +1313,18 @@ int vplbm_set_si_points_body(vplbm_lattice *L, int body, const double *xy, const
   for (int b = 1; b <= L->nbody; ++b)
     if (b != body) total += (int)(L->si_sets[b].size() / 5);
   if (total > L->maxp) return L->fail(VPLBM_EINVAL, "%d points in all exceed max_si_points = %d", total, L->maxp);
+  if (L->nmov) {
+    // a moving disk's window grows with its farthest point
+    Ctl c0;
+    int rc = L->ctl_pull(c0);
+    if (rc) return rc;
+    double rmax = L->disk_r;
+    for (int i = 0; i < npts; ++i)
+      rmax = std::max(rmax, std::hypot(xy[2 * i] - c0.body.x, xy[2 * i + 1] - c0.body.y));
+    const int h = (int)std::ceil(rmax) + WIN_MARGIN;
+    rc = check_moving_capacity(L, 1, &h);
+    if (rc) return rc;
+  }
   std::vector<double> &v = L->si_sets[body];
   v.assign((size_t)5 * npts, 0.0);
   for (int i = 0; i < npts; ++i) {
@@ -1156,9 +1343,18 @@ int vplbm_set_si_points_body(vplbm_lattice *L, int body, const double *xy, const
   c.nrec = 0;
   rc = L->ctl_push(c);
   if (rc) return rc;
-  // clear old sample bits: recompute flags over the window and region
-  const int x0 = std::min(c.win[0], c.region[0]), y0 = std::min(c.win[1], c.region[1]);
-  const int x1 = std::max(c.win[2], c.region[2]), y1 = std::max(c.win[3], c.region[3]);
+  // clear old sample bits: recompute flags over the window and region (for
+  // a moving disk, the window its last flush wrote)
+  int x0 = std::min(c.win[0], c.region[0]), y0 = std::min(c.win[1], c.region[1]);
+  int x1 = std::max(c.win[2], c.region[2]), y1 = std::max(c.win[3], c.region[3]);
+  if (L->nmov) {
+    rc = pull_movers(L);
+    if (rc) return rc;
+    x0 = L->movers[0].mwin[0];
+    y0 = L->movers[0].mwin[1];
+    x1 = L->movers[0].mwin[2];
+    y1 = L->movers[0].mwin[3];
+  }
   rc = launch_flags(L, x0, y0, x1, y1);
   if (!rc) rc = L->sync();
   if (rc) return rc;
@@ -1173,11 +1369,13 @@ int vplbm_set_si_points_body(vplbm_lattice *L, int body, const double *xy, const
     rc = L->hip(hipMemcpyAsync(L->bt(), bt.data(), bt.size() * sizeof(BodyTab), hipMemcpyHostToDevice, L->stream),
                 "body table write");
     if (!rc) rc = L->sync();
+    if (!rc) rc = update_mover_points(L, c);
     return rc;
   }
   rc = upload_points(L, c);
   if (!rc) rc = refresh_si(L);
   if (!rc) rc = check_sample_error(L);
+  if (!rc) rc = update_mover_points(L, c);
   return rc;
 }
 
@@ -1267,7 +1465,6 @@ int vplbm_step_timed(vplbm_lattice *L, int nsteps, int flags, double *kernel_ms)
   int rc = VPLBM_OK;
   for (auto &e : ev)
     if (!rc) rc = L->hip(hipEventCreate(&e), "hipEventCreate");
-  const bool moving = L->mode != MODE_STATIC;
   int done = 0;
   L->macro_valid = false;
   for (int i = 0; i < nsteps && !rc; ++i) {
@@ -1275,13 +1472,11 @@ int vplbm_step_timed(vplbm_lattice *L, int nsteps, int flags, double *kernel_ms)
     rc = L->hip(hipEventRecord(ev[2 * i], L->stream), "hipEventRecord");
     if (!rc) rc = launch_step(L, macro);
     if (!rc) rc = L->hip(hipEventRecord(ev[2 * i + 1], L->stream), "hipEventRecord");
-    if (!rc && moving) {
-      rc = launch_body_step(L);  // only disks move; also reselects the sample nodes
-      L->pending = false;
-    } else if (!rc) {
-      L->pending = true;
-    }
     if (!rc) {
+      if (L->nmov)
+        L->mov_pending = true;
+      else
+        L->pending = true;
       L->cur ^= 1;
       L->nstep += 1;
       ++done;
@@ -1321,6 +1516,8 @@ int vplbm_set_tile(vplbm_lattice *L, int bx, int by) {
                   (bx == 256 && by == 1);
   if (!ok) return L->fail(VPLBM_EINVAL, "unsupported tile %dx%d", bx, by);
   if (L->aa() && (bx != 64 || by != 4)) return L->fail(VPLBM_EINVAL, "the AA pattern runs with the 64x4 tile only");
+  if (L->nmov && (bx != 64 || by != 4))
+    return L->fail(VPLBM_EINVAL, "a lattice with moving disks runs the 64x4 tile only");
   L->bx = bx;
   L->by = by;
   return VPLBM_OK;
@@ -1345,6 +1542,8 @@ static int read_last(vplbm_lattice *L, int which, double out[3]) {
   if (rc) return rc;
   for (int i = 0; i < 3; ++i) out[i] = c.last[3 * which + i];
   if (c.err & 16) return L->fail(VPLBM_EUNSTABLE, "the solution diverged (a non-finite density at some step)");
+  if (c.err & 32)
+    return L->fail(VPLBM_EUNSTABLE, "a moving disk moved a cell or more in one step (or left the lattice)");
   if (c.err & 8)
     return L->fail(VPLBM_ESTATE, "more interface cells than max_interface_cells = %lld: the momentum exchange "
                                  "dropped some",
@@ -1361,6 +1560,10 @@ int vplbm_forces_si_at(vplbm_lattice *L, const double *xy, const double *nrm, co
   if (!L || !out) return VPLBM_EINVAL;
   if (npts < 0 || npts > L->maxp || (npts > 0 && (!xy || !nrm || !ds)))
     return L->fail(VPLBM_EINVAL, "bad points");
+  {
+    const int frc = flush_movers(L);  // moving disks' mask and state after the last step
+    if (frc) return frc;
+  }
   const int mp = L->maxp;
   std::vector<double> buf((size_t)5 * mp, 0.0);
   for (int i = 0; i < npts; ++i) {
@@ -1431,6 +1634,10 @@ int vplbm_forces_body(vplbm_lattice *L, int body, int which, double out[3]) {
 
 int vplbm_get_body_state(vplbm_lattice *L, vplbm_body_state *out) {
   if (!L || !out) return VPLBM_EINVAL;
+  {
+    const int frc = flush_movers(L);  // a moving disk's state after the last step
+    if (frc) return frc;
+  }
   Ctl c;
   int rc = L->ctl_pull(c);
   if (rc) return rc;
@@ -1526,6 +1733,10 @@ int vplbm_read_populations(vplbm_lattice *L, double *f) {
 
 int vplbm_read_mask(vplbm_lattice *L, uint8_t *out) {
   if (!L || !out) return VPLBM_EINVAL;
+  {
+    const int frc = flush_movers(L);  // moving disks' mask bytes after the last step
+    if (frc) return frc;
+  }
   int rc = L->hip(hipMemcpy2DAsync(out, L->p.nx, L->mask(), L->pitch, L->p.nx, L->p.ny,
                                    hipMemcpyDeviceToHost, L->stream),
                   "mask read");
@@ -1547,11 +1758,10 @@ struct vplbm_batch {
   bool aa = false;   // storage scheme of every lattice of the batch
   int bx = 64, by = 4;  // tile of the batched launches
   char *desc_dev = nullptr;
-  int *moving_dev = nullptr;
+  int ncap = 0;                  // descriptors the device table holds
   int *tile_case_dev = nullptr;  // lattice index of every global tile
   long long tile_case_cap = 0;
   std::vector<char> desc_host;
-  std::vector<int> moving_host;
   hipGraphExec_t graph = nullptr;  // groups of launch pairs (parities 1, 0) of the current active set
   long long graph_key = -1;
   std::string err;
@@ -1582,14 +1792,13 @@ bool batch_tile_ok(int bx, int by) { return (bx == 64 && by == 4) || (bx == 128 
 struct BatchExec {
   int prec = 0;
   bool trt = false, aa = false;
+  bool mov = false;  // some active lattice has moving disks (the chunk's kernels handle them; 64x4 tiles)
   int bx = 64, by = 4;
   hipStream_t stream = nullptr;
   char *desc_dev = nullptr;   // descriptors, one per active lattice
-  int *moving_dev = nullptr;  // active indices of the moving lattices
   int *tile_dev = nullptr;    // lattice of every global tile
   long long tile_cap = 0;
   char *desc_host = nullptr;  // host staging, room for every lattice
-  int *moving_host = nullptr;
   hipStream_t cap_stream = nullptr;  // graph capture (null: direct launches only)
   hipGraphExec_t *graph = nullptr;
   long long *graph_key = nullptr;
@@ -1615,17 +1824,12 @@ void fill_desc(vplbm_lattice *L, int tile0, int bx, int by, void *out) {
   d.hist = (double *)L->at(L->L.hist);
   d.cap = L->cap;
   d.maxb = L->maxb;
-  d.maxslot = (int)L->maxslot;
   d.tile0 = tile0;
   d.ntiles = d.P.ntiles;
   d.cur0 = L->cur;
   d.pbit0 = (int)((L->nstep + 1) & 1);
   d.pending0 = L->pending ? 1 : 0;
-  d.moving = L->mode != MODE_STATIC ? 1 : 0;
-  d.perx = (int)L->periodic_x();
-  d.pery = (int)L->periodic_y();
-  d.maxp = L->maxp;
-  d.pts = (const double *)L->at(L->L.pts);
+  d.mov_pending0 = L->mov_pending ? 1 : 0;
   d.ec[0] = L->aa() ? L->ec(0) : nullptr;
   d.ec[1] = L->aa() ? L->ec(1) : nullptr;
   std::memcpy(out, &d, sizeof d);
@@ -1649,46 +1853,58 @@ const char *batch_check(vplbm_lattice *const *lats, int n) {
   return nullptr;
 }
 
-template <typename S, int BX, int BY>
+template <typename S, int BX, int BY, bool MOV>
 void launch_batch_ab(const BatchExec &X, hipStream_t st, dim3 grid, int total, int per, int flip, int first) {
   const auto *descs = (const CaseDesc<typename Store<S>::T> *)X.desc_dev;
   if (X.trt)
-    hipLaunchKernelGGL((k_step_batch<S, BX, BY, true>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total, per,
-                       flip, first);
+    hipLaunchKernelGGL((k_step_batch<S, BX, BY, true, MOV>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total,
+                       per, flip, first);
   else
-    hipLaunchKernelGGL((k_step_batch<S, BX, BY, false>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total, per,
-                       flip, first);
+    hipLaunchKernelGGL((k_step_batch<S, BX, BY, false, MOV>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total,
+                       per, flip, first);
 }
+
+template <typename S, bool MOV>
+void launch_batch_aa(const BatchExec &X, hipStream_t st, dim3 grid, int total, int per, int flip, int first) {
+  const auto *descs = (const CaseDesc<typename Store<S>::T> *)X.desc_dev;
+  if (X.trt)
+    hipLaunchKernelGGL((k_step_batch_aa<S, true, MOV>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per, flip,
+                       first);
+  else
+    hipLaunchKernelGGL((k_step_batch_aa<S, false, MOV>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per, flip,
+                       first);
+}
+
+// the tile a chunk's launches run: the batch's, or 64x4 when a lattice has
+// moving disks or the lattices are in the AA pattern
+int chunk_bx(const BatchExec &X) { return (X.mov || X.aa) ? 64 : X.bx; }
+int chunk_by(const BatchExec &X) { return (X.mov || X.aa) ? 4 : X.by; }
 
 template <typename S>
-void launch_batch_pair(const BatchExec &X, hipStream_t st, int total, int nmov, int flip, int first) {
-  using T = typename Store<S>::T;
+void launch_batch_s(const BatchExec &X, hipStream_t st, int total, int flip, int first) {
   const int per = (total + 7) / 8;
-  const auto *descs = (const CaseDesc<T> *)X.desc_dev;
   const dim3 grid(8 * per);
   if (X.aa) {  // 64x4 tiles
-    if (X.trt)
-      hipLaunchKernelGGL((k_step_batch_aa<S, true>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per, flip,
-                         first);
+    if (X.mov)
+      launch_batch_aa<S, true>(X, st, grid, total, per, flip, first);
     else
-      hipLaunchKernelGGL((k_step_batch_aa<S, false>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per, flip,
-                         first);
+      launch_batch_aa<S, false>(X, st, grid, total, per, flip, first);
+  } else if (X.mov) {
+    launch_batch_ab<S, 64, 4, true>(X, st, grid, total, per, flip, first);
   } else if (X.bx == 128) {
-    launch_batch_ab<S, 128, 2>(X, st, grid, total, per, flip, first);
+    launch_batch_ab<S, 128, 2, false>(X, st, grid, total, per, flip, first);
   } else if (X.bx == 256) {
-    launch_batch_ab<S, 256, 1>(X, st, grid, total, per, flip, first);
+    launch_batch_ab<S, 256, 1, false>(X, st, grid, total, per, flip, first);
   } else {
-    launch_batch_ab<S, 64, 4>(X, st, grid, total, per, flip, first);
+    launch_batch_ab<S, 64, 4, false>(X, st, grid, total, per, flip, first);
   }
-  if (nmov)
-    hipLaunchKernelGGL((k_body_step_batch<T>), dim3(nmov), dim3(BODY_NT), 0, st, descs, X.moving_dev, flip);
 }
 
-void launch_batch(const BatchExec &X, hipStream_t st, int total, int nmov, int flip, int first) {
+void launch_batch(const BatchExec &X, hipStream_t st, int total, int flip, int first) {
   switch (X.prec) {
-    case VPLBM_F64: launch_batch_pair<double>(X, st, total, nmov, flip, first); break;
-    case VPLBM_F32: launch_batch_pair<float>(X, st, total, nmov, flip, first); break;
-    default: launch_batch_pair<__half>(X, st, total, nmov, flip, first); break;
+    case VPLBM_F64: launch_batch_s<double>(X, st, total, flip, first); break;
+    case VPLBM_F32: launch_batch_s<float>(X, st, total, flip, first); break;
+    default: launch_batch_s<__half>(X, st, total, flip, first); break;
   }
 }
 
@@ -1748,19 +1964,20 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
     int rc = hipck(hipStreamSynchronize(X.stream), "hipStreamSynchronize");
     if (rc) return rc;
     long long total = 0;
-    int nmov = 0;
+    X.mov = false;
+    for (int k : act) X.mov = X.mov || lats[k]->nmov > 0;
+    const int bx = chunk_bx(X), by = chunk_by(X);
     for (size_t i = 0; i < act.size(); ++i) {
       vplbm_lattice *L = lats[act[i]];
       rc = resolve_pwin(L);
       if (rc) return fail(rc, "lattice " + std::to_string(act[i]) + ": " + L->err);
       void *slot = X.desc_host + i * dsz;
       switch (X.prec) {
-        case VPLBM_F64: fill_desc<double>(L, (int)total, X.bx, X.by, slot); break;
-        case VPLBM_F32: fill_desc<float>(L, (int)total, X.bx, X.by, slot); break;
-        default: fill_desc<__half>(L, (int)total, X.bx, X.by, slot); break;
+        case VPLBM_F64: fill_desc<double>(L, (int)total, bx, by, slot); break;
+        case VPLBM_F32: fill_desc<float>(L, (int)total, bx, by, slot); break;
+        default: fill_desc<__half>(L, (int)total, bx, by, slot); break;
       }
-      if (L->mode != MODE_STATIC) X.moving_host[nmov++] = (int)i;
-      total += batch_tiles(L, X.bx, X.by);
+      total += batch_tiles(L, bx, by);
     }
     if (total > X.tile_cap)
       return fail(VPLBM_EINVAL, "the batch's " + std::to_string(total) + " tiles exceed the tile table (" +
@@ -1768,9 +1985,6 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
     const int nact = (int)act.size();
     rc = hipck(hipMemcpyAsync(X.desc_dev, X.desc_host, dsz * nact, hipMemcpyHostToDevice, X.stream),
                "batch descriptors");
-    if (!rc && nmov)
-      rc = hipck(hipMemcpyAsync(X.moving_dev, X.moving_host, sizeof(int) * nmov, hipMemcpyHostToDevice, X.stream),
-                 "batch moving list");
     if (rc) return rc;
     (void)hipGetLastError();
     launch_fill_tiles(X, nact, (int)total);
@@ -1779,7 +1993,7 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
     // launch 0 eagerly (it finalizes what the lattices left pending), then
     // pairs of launches (parities 1, 0), from a captured graph when allowed,
     // then a last one
-    launch_batch(X, X.stream, (int)total, nmov, 0, 1);
+    launch_batch(X, X.stream, (int)total, 0, 1);
     rc = hipck(hipGetLastError(), "k_step_batch");
     if (rc) return rc;
     long long done = 1;
@@ -1788,7 +2002,7 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
     // call per group); the remaining pairs are launched directly
     const long long groups = X.graph ? pairs / GRAPH_PAIRS : 0;
     if (groups > 0) {
-      const long long key = ((long long)nact << 40) ^ (total << 12) ^ ((long long)X.bx << 4) ^ nmov;
+      const long long key = ((long long)nact << 40) ^ (total << 12) ^ ((long long)bx << 4) ^ (X.mov ? 1 : 0);
       if (!*X.graph || *X.graph_key != key) {
         if (*X.graph) (void)hipGraphExecDestroy(*X.graph);
         *X.graph = nullptr;
@@ -1796,8 +2010,8 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
         rc = hipck(hipStreamBeginCapture(X.cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
         if (rc) return rc;
         for (int q = 0; q < GRAPH_PAIRS; ++q) {
-          launch_batch(X, X.cap_stream, (int)total, nmov, 1, 0);
-          launch_batch(X, X.cap_stream, (int)total, nmov, 0, 0);
+          launch_batch(X, X.cap_stream, (int)total, 1, 0);
+          launch_batch(X, X.cap_stream, (int)total, 0, 0);
         }
         rc = hipck(hipStreamEndCapture(X.cap_stream, &g), "end capture");
         if (!rc) rc = hipck(hipGraphInstantiate(X.graph, g, nullptr, nullptr, 0), "graph instantiate");
@@ -1810,14 +2024,14 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
       done += 2 * GRAPH_PAIRS * groups;
     }
     for (long long p = groups * GRAPH_PAIRS; p < pairs; ++p) {
-      launch_batch(X, X.stream, (int)total, nmov, 1, 0);
-      launch_batch(X, X.stream, (int)total, nmov, 0, 0);
+      launch_batch(X, X.stream, (int)total, 1, 0);
+      launch_batch(X, X.stream, (int)total, 0, 0);
       rc = hipck(hipGetLastError(), "k_step_batch");
       if (rc) return rc;
       done += 2;
     }
     if (done < chunk) {
-      launch_batch(X, X.stream, (int)total, nmov, 1, 0);
+      launch_batch(X, X.stream, (int)total, 1, 0);
       rc = hipck(hipGetLastError(), "k_step_batch");
       if (rc) return rc;
       ++done;
@@ -1826,7 +2040,8 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
       vplbm_lattice *L = lats[k];
       L->nstep += chunk;
       L->cur ^= (int)(chunk & 1);
-      L->pending = L->mode == MODE_STATIC;
+      L->pending = L->nmov == 0;  // the static bodies' forces, or the moving disks'
+      L->mov_pending = L->nmov > 0;
       L->macro_valid = false;
       rem[k] -= chunk;
     }
@@ -1842,8 +2057,7 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
 constexpr int NOALLOC_MAX_CASES = 256;
 constexpr long long NOALLOC_MAX_TILES = 1 << 20;
 constexpr size_t NOALLOC_DESC_BYTES = (size_t)NOALLOC_MAX_CASES * desc_size<double>();
-constexpr size_t NOALLOC_MOV_OFF = (NOALLOC_DESC_BYTES + 255) / 256 * 256;
-constexpr size_t NOALLOC_TILE_OFF = NOALLOC_MOV_OFF + 256 * ((NOALLOC_MAX_CASES * sizeof(int) + 255) / 256);
+constexpr size_t NOALLOC_TILE_OFF = (NOALLOC_DESC_BYTES + 255) / 256 * 256;
 constexpr size_t NOALLOC_BYTES = NOALLOC_TILE_OFF + (size_t)NOALLOC_MAX_TILES * sizeof(int);
 static_assert(desc_size<double>() >= desc_size<float>() && desc_size<double>() >= desc_size<__half>(),
               "descriptor slots sized for the largest descriptor");
@@ -1858,7 +2072,6 @@ constexpr int NOALLOC_MAX_DEVICES = 64;
 std::mutex g_noalloc_mu;  // guards the per-device addresses and the host staging below
 void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
 unsigned char g_noalloc_desc_host[NOALLOC_DESC_BYTES];
-int g_noalloc_mov_host[NOALLOC_MAX_CASES];
 
 }  // namespace
 
@@ -1880,13 +2093,11 @@ int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out) {
   B->trt = lats[0]->p.trt_lambda > 0.0;
   B->aa = lats[0]->aa();
   B->desc_host.assign(desc_size_of(prec) * n, 0);
-  B->moving_host.assign(n, 0);
+  B->ncap = n;
   if (hipMalloc((void **)&B->desc_dev, B->desc_host.size()) != hipSuccess ||
-      hipMalloc((void **)&B->moving_dev, sizeof(int) * n) != hipSuccess ||
       hipStreamCreate(&B->cap_stream) != hipSuccess) {
     (void)hipGetLastError();
     if (B->desc_dev) (void)hipFree(B->desc_dev);
-    if (B->moving_dev) (void)hipFree(B->moving_dev);
     delete B;
     return VPLBM_ENOMEM;
   }
@@ -1899,7 +2110,6 @@ int vplbm_batch_destroy(vplbm_batch *B) {
   (void)hipStreamSynchronize(B->stream);
   if (B->graph) (void)hipGraphExecDestroy(B->graph);
   (void)hipFree(B->desc_dev);
-  (void)hipFree(B->moving_dev);
   if (B->tile_case_dev) (void)hipFree(B->tile_case_dev);
   (void)hipStreamDestroy(B->cap_stream);
   delete B;
@@ -1914,24 +2124,19 @@ int vplbm_batch_set_lattices(vplbm_batch *B, vplbm_lattice *const *lats, int n) 
   if (lats[0]->p.precision != B->prec || lats[0]->stream != B->stream ||
       (lats[0]->p.trt_lambda > 0.0) != B->trt || lats[0]->aa() != B->aa)
     return B->fail(VPLBM_EINVAL, "the lattices differ from the batch's precision, stream, collision or storage");
-  if ((size_t)n > B->moving_host.size()) {
-    // room for n descriptors: wait for the work that reads the old tables
+  if (n > B->ncap) {
+    // room for n descriptors: wait for the work that reads the old table
     int rc = B->hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");
     if (rc) return rc;
     char *d = nullptr;
-    int *m = nullptr;
-    if (hipMalloc((void **)&d, desc_size_of(B->prec) * n) != hipSuccess ||
-        hipMalloc((void **)&m, sizeof(int) * n) != hipSuccess) {
+    if (hipMalloc((void **)&d, desc_size_of(B->prec) * n) != hipSuccess) {
       (void)hipGetLastError();
-      if (d) (void)hipFree(d);
       return B->fail(VPLBM_ENOMEM, "batch tables");
     }
     (void)hipFree(B->desc_dev);
-    (void)hipFree(B->moving_dev);
     B->desc_dev = d;
-    B->moving_dev = m;
+    B->ncap = n;
     B->desc_host.assign(desc_size_of(B->prec) * n, 0);
-    B->moving_host.assign(n, 0);
     if (B->graph) (void)hipGraphExecDestroy(B->graph);  // it holds the old tables' addresses
     B->graph = nullptr;
     B->graph_key = -1;
@@ -1966,7 +2171,8 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
   const int n = (int)B->cases.size();
   // the tile table holds the tiles of every lattice (its size when all are active)
   long long need = 0;
-  for (vplbm_lattice *L : B->cases) need += batch_tiles(L, B->bx, B->by);
+  // (chunks with moving disks or AA lattices run 64x4 tiles)
+  for (vplbm_lattice *L : B->cases) need += std::max(batch_tiles(L, B->bx, B->by), batch_tiles(L, 64, 4));
   if (need > B->tile_case_cap) {
     int rc = B->hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");
     if (rc) return rc;
@@ -1988,11 +2194,9 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
   X.by = B->by;
   X.stream = B->stream;
   X.desc_dev = B->desc_dev;
-  X.moving_dev = B->moving_dev;
   X.tile_dev = B->tile_case_dev;
   X.tile_cap = B->tile_case_cap;
   X.desc_host = B->desc_host.data();
-  X.moving_host = B->moving_host.data();
   X.cap_stream = B->cap_stream;
   X.graph = &B->graph;
   X.graph_key = &B->graph_key;
@@ -2037,11 +2241,9 @@ int vplbm_batch_step_noalloc(vplbm_lattice *const *lats, int n, const int *nstep
   X.aa = L0->aa();
   X.stream = L0->stream;
   X.desc_dev = base;
-  X.moving_dev = (int *)(base + NOALLOC_MOV_OFF);
   X.tile_dev = (int *)(base + NOALLOC_TILE_OFF);
   X.tile_cap = NOALLOC_MAX_TILES;
   X.desc_host = (char *)g_noalloc_desc_host;
-  X.moving_host = g_noalloc_mov_host;
   std::string err;
   const int rc = batch_run(X, lats, n, nsteps, err);
   if (rc) L0->err = err;

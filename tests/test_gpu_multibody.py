@@ -142,15 +142,29 @@ def test_interface_slot_capacity():
         g.set_disk(40.0, 24.0, 8.0)  # about 60 interface cells
     assert e.value.code == V.EINVAL
     g.close()
-    g = V.Lattice(V.make_params(96, 48, 0.65, 1e-3, 1.0, "f32", max_interface_cells=500))
-    g.set_disk(40.0, 24.0, 3.0)
+    # a moving disk keeps per-tile force sums in these slots: its points at
+    # radius 39.5 give a window half size h = 40 + 8, 97 cells a side, which can
+    # meet (ceil(96 / 64) + 1) x (ceil(96 / 4) + 1) = 3 x 25 tiles of 64 x 4;
+    # 8 doubles a tile, 150 slots of 4 (the disk alone has 52 interface cells)
+    th = np.arange(64) * (2 * np.pi / 64)
+    xy = np.stack([64 + 39.5 * np.cos(th), 64 + 39.5 * np.sin(th)], 1)
+    nrm = np.stack([np.cos(th), np.sin(th)], 1)
+    ds = np.full(64, 2 * np.pi * 39.5 / 64)
+
+    def lattice(cap):
+        g = V.Lattice(V.make_params(128, 128, 0.65, 1e-3, 1.0, "f32", max_interface_cells=cap,
+                                    max_si_points=64))
+        g.set_disk(64.0, 64.0, 3.0)
+        g.set_si_points(xy, nrm, ds)
+        return g
+
+    g = lattice(149)
     with pytest.raises(V.VplbmError) as e:
-        g.set_motion(40.0, 24.0, 0.0, 0.01, 0.0, 0.0)  # moving: needs (6 + 20)^2 = 676 slots
+        g.set_motion(64.0, 64.0, 0.0, 0.01, 0.0, 0.0)
     assert e.value.code == V.EINVAL
     g.close()
-    g = V.Lattice(V.make_params(96, 48, 0.65, 1e-3, 1.0, "f32", max_interface_cells=676))
-    g.set_disk(40.0, 24.0, 3.0)
-    g.set_motion(40.0, 24.0, 0.0, 0.01, 0.0, 0.0)
+    g = lattice(150)
+    g.set_motion(64.0, 64.0, 0.0, 0.01, 0.0, 0.0)
     g.init_uniform(1.0, 0.0, 0.0)
     g.step(40)
     g.sync()
