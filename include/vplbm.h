@@ -219,6 +219,30 @@ int vplbm_set_body_motion(vplbm_lattice *lat, const vplbm_body_state *s);
 int vplbm_set_body_dynamics(vplbm_lattice *lat, double rho_s, double gx, double gy,
                             int force_source);
 
+/* One of several moving disks (vplbm_set_moving_disks): centre (x, y),
+ * radius r, angle theta, velocities (u, v, omega); rho_s > 0 makes it free
+ * (Eqs. dep1, theta2 with m = rho_s pi r^2, I = m r^2 / 2), rho_s = 0 gives
+ * it the prescribed motion of its velocities. */
+typedef struct {
+  double x, y, r, theta, u, v, omega, rho_s;
+} vplbm_disk;
+
+/* Several moving disks in one lattice (n in 1..4, n <= max_bodies): disk k
+ * becomes body k + 1.  Each follows its own motion (free or prescribed, as
+ * for body 1 in vplbm_set_body_motion and vplbm_set_body_dynamics) with its
+ * own momentum-exchange and stress-integration forces; the free ones share
+ * the gravity (gx, gy) and the force that drives them (force_source).  The
+ * paper moves one body at a time; this applies its single-body equations to
+ * each disk, with no contact model: the disks must start at least two cells
+ * apart and one cell inside the lattice, and a step that brings two of them
+ * within one cell flags VPLBM_EINVAL ("a fluid cell is linked to two
+ * different bodies") at the next check.  Replaces any previous body and
+ * removes all stress-integration points (set them per disk with
+ * vplbm_set_si_points_body).  The window each disk keeps must fit
+ * max_interface_cells (see vplbm_params). */
+int vplbm_set_moving_disks(vplbm_lattice *lat, const vplbm_disk *disks, int n, double gx, double gy,
+                           int force_source);
+
 /* Stress-integration points (Sec. 2.3.2): world coordinates xy[2*npts],
  * outward unit normals nrm[2*npts], integration lengths ds[npts], at the
  * current body state; they move rigidly with the body.  With si_rule 0 each
@@ -294,6 +318,9 @@ int vplbm_force_history_body(vplbm_lattice *lat, int body, int which, long long 
 /* State of body 1 for the next step: position, angle and velocities of the
  * rigid-body motion of Eqs. dep1 and theta2 (prescribed or free). */
 int vplbm_get_body_state(vplbm_lattice *lat, vplbm_body_state *out);
+/* The same for body `body` (1..nbody): a moving disk's state, or a static
+ * body's reference point with zero angle and velocities. */
+int vplbm_get_body_state_of(vplbm_lattice *lat, int body, vplbm_body_state *out);
 
 /* rho (Eq. updatestep) and the penalized velocity u (Eq. updatestepm) of
  * the last step, which must have been run with VPLBM_STEP_MACRO

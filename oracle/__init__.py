@@ -245,8 +245,63 @@ class RefLattice:
         self.si_xy = self.si_n = self.si_ds = self.si_pbody = None
         self.si_node = self.si_node4 = self.si_w4 = None
 
+    def set_moving_disks(self, disks, gx=0.0, gy=0.0, source=0):
+        """Several moving disks, each (x, y, r, theta, u, v, omega, rho_s).  Disk k
+        is body k + 1 and follows the single-body motion of Eqs. dep1 and theta2
+        on its own force of each step: free when rho_s > 0 (m = rho_s pi r^2,
+        I = m r^2 / 2, gravity (gx, gy) with buoyancy), prescribed (constant
+        velocities) when rho_s = 0.  A cell inside two disks takes the lower id."""
+        self.bodies = (_Body * len(disks))()
+        self.disks = []
+        for b, d in zip(self.bodies, disks):
+            x, y, r, th, u, v, om, rho_s = (float(q) for q in d)
+            b.x, b.y, b.theta, b.u, b.v, b.omega = x, y, th, u, v, om
+            m = rho_s * math.pi * r * r if rho_s > 0 else 0.0
+            self.disks.append({"r": r, "rho_s": rho_s, "mass": m, "inertia": 0.5 * m * r * r})
+        self.shape = ("disks",)
+        self.mode = "disks"
+        self.grav = (gx, gy)
+        self.source = source
+        self.si_sets = {}
+        self.si_frames = {}
+        self.si_xy = self.si_n = self.si_ds = self.si_pbody = None
+        self.si_node = self.si_node4 = self.si_w4 = None
+        self._rebuild_mask()
+
+    def _place_si_disks(self):
+        """World points of every moving disk from its body-frame points and state."""
+        keys = sorted(k for k in self.si_frames if len(self.si_frames[k][4]))
+        if not keys:
+            self.si_xy = None
+            return
+        xy, nn, dd, pb = [], [], [], []
+        for k in keys:
+            px, py, nx_, ny_, ds = self.si_frames[k]
+            b = self.bodies[k - 1]
+            c, s = math.cos(b.theta), math.sin(b.theta)
+            xy.append(np.stack([b.x + (c * px - s * py), b.y + (s * px + c * py)], 1))
+            nn.append(np.stack([c * nx_ - s * ny_, s * nx_ + c * ny_], 1))
+            dd.append(ds)
+            pb.append(np.full(len(ds), k, np.int32))
+        self.si_xy = np.ascontiguousarray(np.concatenate(xy))
+        self.si_n = np.ascontiguousarray(np.concatenate(nn))
+        self.si_ds = np.ascontiguousarray(np.concatenate(dd))
+        self.si_pbody = np.concatenate(pb)
+
     def set_si_points_body(self, body, xy, nrm, ds):
-        """Stress-integration points of one body of a static multi-body lattice."""
+        """Stress-integration points of one body: of a static multi-body lattice,
+        or of one of several moving disks (kept in that disk's frame)."""
+        if self.mode == "disks":
+            assert 1 <= body <= self.nbody
+            b = self.bodies[body - 1]
+            xy, nrm, ds = (np.asarray(a, dtype=np.float64) for a in (xy, nrm, ds))
+            c, s = math.cos(-b.theta), math.sin(-b.theta)
+            dx, dy = xy[:, 0] - b.x, xy[:, 1] - b.y
+            self.si_frames[body] = (c * dx - s * dy, s * dx + c * dy, c * nrm[:, 0] - s * nrm[:, 1],
+                                    s * nrm[:, 0] + c * nrm[:, 1], ds.copy())
+            self._place_si_disks()
+            self._select_si()
+            return
         assert self.mode == "static" and 1 <= body <= self.nbody
         self.si_sets[body] = tuple(np.ascontiguousarray(a, dtype=np.float64).copy() for a in (xy, nrm, ds))
         keys = sorted(k for k in self.si_sets if len(self.si_sets[k][2]))
@@ -261,7 +316,13 @@ class RefLattice:
 
     def _rebuild_mask(self):
         kind = self.shape[0]
-        if kind == "disk":
+        if kind == "disks":
+            ids = np.zeros_like(self.solid)
+            for k in reversed(range(len(self.disks))):
+                b = self.bodies[k]
+                ids[mask_disk(self.nx, self.ny, b.x, b.y, self.disks[k]["r"]) != 0] = k + 1
+            self.solid[:] = ids
+        elif kind == "disk":
             lib().orc_mask_disk(self.nx, self.ny, self.body.x, self.body.y, self.shape[1], self.solid)
         elif kind == "polygon":
             lib().orc_mask_polygon(self.nx, self.ny, self.shape[1], len(self.shape[1]), self.solid)
@@ -371,6 +432,20 @@ class RefLattice:
             self.hist_me.append(me.reshape(nb, 3))
             self.hist_si.append(si.reshape(nb, 3))
             self.nstep += 1
+            if self.mode == "disks":
+                F = (me if self.source == 0 else si).reshape(nb, 3)
+                for k, (b, d) in enumerate(zip(self.bodies, self.disks)):
+                    if d["rho_s"] > 0:
+                        L.orc_body_update(C.byref(b), np.ascontiguousarray(F[k]), d["mass"], d["inertia"],
+                                          self.p.rho0, d["rho_s"], self.grav[0], self.grav[1])
+                    else:
+                        b.x += b.u
+                        b.y += b.v
+                        b.theta += b.omega
+                if self.si_frames:
+                    self._place_si_disks()
+                self._rebuild_mask()
+                continue
             if self.mode == "free":
                 FT = np.ascontiguousarray((me if self.source == 0 else si)[:3])
                 L.orc_body_update(C.byref(self.body), FT, self.mass, self.inertia, self.p.rho0,
@@ -392,8 +467,8 @@ class RefLattice:
         """Pre-collision field f^n of the last step (the streamed state)."""
         return self.fw
 
-    def body_state(self):
-        b = self.body
+    def body_state(self, body=1):
+        b = self.bodies[body - 1]
         return np.array([b.x, b.y, b.theta, b.u, b.v, b.omega])
 
     def me(self, body=1):

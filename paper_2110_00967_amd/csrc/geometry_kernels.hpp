@@ -56,7 +56,8 @@ __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int 
                        int row0, int nrows, const double *__restrict__ rho_in,
                        const double *__restrict__ ux_in, const double *__restrict__ uy_in,
                        double rho_u, double ux_u, double uy_u, const Ctl *__restrict__ ctl, double rho0,
-                       int swapped, S *__restrict__ ec, int nper) {
+                       int swapped, S *__restrict__ ec, int nper, const MoverDev *__restrict__ mov, int nmov,
+                       int slot) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int yl = blockIdx.y;
   if (x >= nx || yl >= nrows) return;
@@ -72,7 +73,12 @@ __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int 
     rho = rho_u;
     ux = ux_u;
     uy = uy_u;
-    if ((mask[c] & M_BODY) == 1) {  // body 1's cells start at its velocity (the others are static)
+    const int id = mask[c] & M_BODY;
+    if (id != 0 && id <= nmov) {  // a moving disk's cells start at its rigid velocity
+      const BodyDev B = mov[id - 1].B[slot];
+      ux = B.u - B.omega * (double(y) - B.y);
+      uy = B.v + B.omega * (double(x) - B.x);
+    } else if (id == 1) {  // body 1's cells start at its velocity (static bodies 2.. at rest)
       const BodyDev B = ctl->body;
       ux = B.u - B.omega * (double(y) - B.y);
       uy = B.v + B.omega * (double(x) - B.x);
@@ -587,51 +593,17 @@ __global__ void __launch_bounds__(SI_NT)
 constexpr int REGION_MARGIN = 6;  // set-up: a disk's mask region around its box (links 1, sample walks 5)
 constexpr int FLUSH_NT = 256;
 
-// After the launch of step N (pb = N & 1): the disks' forces of step N are
-// summed and their states advanced exactly as the next step launch would do
-// it (mover_prologue: the same sums in the same order, the same update), so
-// that forces, states and the mask can be read between steps; the next
-// launch then starts from these states.  The mask bytes of each disk's
-// window -- which the step launches never read for a lattice with moving
-// disks -- are rewritten from the new states: the bytes the last flush (or
-// the set-up) wrote are cleared, then solid ids and interface bits over
-// every window, then the sample bits of every point.
-__global__ void __launch_bounds__(FLUSH_NT)
-    k_mover_flush(MoverDev *__restrict__ mov, int nmov, const double *__restrict__ win, int pb,
-                  const double *__restrict__ pts, int maxp, int rule, int nx, int ny, int pitch, int perx, int pery,
-                  uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb) {
-  __shared__ double red[FIN_WAVES * 6];
-  __shared__ double cs[2];
-  __shared__ BodyDev st[MAX_MOVERS];
-  __shared__ long long fx[MAX_MOVERS], fy[MAX_MOVERS];
-  const int sread = pb ^ 1;
-  const int tiles_x = (nx + MOV_BX - 1) / MOV_BX, tiles_y = (ny + MOV_BY - 1) / MOV_BY;
-  for (int k = 0; k < nmov; ++k) {
-    MoverDev &M = mov[k];
-    const BodyDev B = M.B[sread];
-    double F[6];
-    mover_forces<FLUSH_NT>(M, B, win, tiles_x, tiles_y, red, F);
-    const BodyDev S = mover_update(M, B, F);
-    if (threadIdx.x == 0) {
-      st[k] = S;
-      fx[k] = fixq_of(S.x);
-      fy[k] = fixq_of(S.y);
-      M.B[pb] = S;
-      const long long n = M.nfin + 1;
-      double *hh = hist + ((n % cap) * maxb + k) * 6;
-#pragma unroll
-      for (int i = 0; i < 6; ++i) hh[i] = F[i];
-      M.nfin = n;
-      if (k == 0) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) ctl->last[i] = F[i];
-        ctl->step = n;
-        ctl->body = S;
-      }
-      if (fabs(S.x - B.x) >= 1.0 || fabs(S.y - B.y) >= 1.0) atomicOr(&ctl->err, 32);
-    }
-  }
-  __syncthreads();
+// The mask bytes of the disks' windows from their states st (fx, fy: the
+// centres on the 1/FIXQ grid; cs: two doubles of LDS): the bytes the last
+// rewrite (or the set-up) wrote are cleared, then solid ids and interface
+// bits over every window, then the sample bits of every point; each disk's
+// rectangle is kept in mwin.  The step launches never read these bytes for
+// a lattice with moving disks: they serve reads of the mask between steps.
+// One workgroup of FLUSH_NT threads.
+__device__ __forceinline__ void mover_mask(MoverDev *__restrict__ mov, int nmov, const BodyDev *st,
+                                           const long long *fx, const long long *fy, const double *__restrict__ pts,
+                                           int maxp, int rule, int nx, int ny, int pitch, int perx, int pery,
+                                           uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, double *cs) {
   MultiDiskSolid cur;
   cur.n = nmov;
 #pragma unroll
@@ -704,10 +676,7 @@ __global__ void __launch_bounds__(FLUSH_NT)
   // sample bits of every point at the new states
   for (int k = 0; k < nmov; ++k) {
     const BodyDev S = st[k];
-    if (threadIdx.x == 0) {
-      cs[0] = cos(S.theta);
-      cs[1] = sin(S.theta);
-    }
+    if (threadIdx.x == 0) sincos(S.theta, &cs[1], &cs[0]);
     __syncthreads();
     const double co = cs[0], sn = cs[1];
     for (int i = mov[k].pt0 + (int)threadIdx.x; i < mov[k].pt1; i += FLUSH_NT) {
@@ -727,6 +696,69 @@ __global__ void __launch_bounds__(FLUSH_NT)
     }
     __syncthreads();
   }
+}
+
+// After the launch of step N (pb = N & 1): the disks' forces of step N are
+// summed and their states advanced exactly as the next step launch would do
+// it (mover_prologue: the same sums in the same order, the same update), so
+// that forces, states and the mask can be read between steps; the next
+// launch then starts from these states.  Then the mask of the disks'
+// windows is rewritten from the new states (mover_mask).
+__global__ void __launch_bounds__(FLUSH_NT)
+    k_mover_flush(MoverDev *__restrict__ mov, int nmov, const double *__restrict__ win, int pb,
+                  const double *__restrict__ pts, int maxp, int rule, int nx, int ny, int pitch, int perx, int pery,
+                  uint8_t *__restrict__ mask, Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb) {
+  __shared__ double red[FIN_WAVES * 6];
+  __shared__ double cs[2];
+  __shared__ BodyDev st[MAX_MOVERS];
+  __shared__ long long fx[MAX_MOVERS], fy[MAX_MOVERS];
+  const int sread = pb ^ 1;
+  const int tiles_x = (nx + MOV_BX - 1) / MOV_BX, tiles_y = (ny + MOV_BY - 1) / MOV_BY;
+  for (int k = 0; k < nmov; ++k) {
+    MoverDev &M = mov[k];
+    const BodyDev B = M.B[sread];
+    double F[6];
+    mover_forces<FLUSH_NT>(M, B, win, tiles_x, tiles_y, red, F);
+    const BodyDev S = mover_update(M, B, F);
+    if (threadIdx.x == 0) {
+      st[k] = S;
+      fx[k] = fixq_of(S.x);
+      fy[k] = fixq_of(S.y);
+      M.B[pb] = S;
+      const long long n = M.nfin + 1;
+      double *hh = hist + ((n % cap) * maxb + k) * 6;
+#pragma unroll
+      for (int i = 0; i < 6; ++i) hh[i] = F[i];
+      M.nfin = n;
+      if (k == 0) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) ctl->last[i] = F[i];
+        ctl->step = n;
+        ctl->body = S;
+      }
+      if (fabs(S.x - B.x) >= 1.0 || fabs(S.y - B.y) >= 1.0) atomicOr(&ctl->err, 32);
+    }
+  }
+  __syncthreads();
+  mover_mask(mov, nmov, st, fx, fy, pts, maxp, rule, nx, ny, pitch, perx, pery, mask, ctl, cs);
+}
+
+// The mask of the disks' windows from the states in slot `slot` (set-up and
+// changes of the points between steps).
+__global__ void __launch_bounds__(FLUSH_NT)
+    k_mover_mask(MoverDev *__restrict__ mov, int nmov, int slot, const double *__restrict__ pts, int maxp, int rule,
+                 int nx, int ny, int pitch, int perx, int pery, uint8_t *__restrict__ mask, Ctl *__restrict__ ctl) {
+  __shared__ double cs[2];
+  __shared__ BodyDev st[MAX_MOVERS];
+  __shared__ long long fx[MAX_MOVERS], fy[MAX_MOVERS];
+  if ((int)threadIdx.x < nmov) {
+    const BodyDev S = mov[threadIdx.x].B[slot];
+    st[threadIdx.x] = S;
+    fx[threadIdx.x] = fixq_of(S.x);
+    fy[threadIdx.x] = fixq_of(S.y);
+  }
+  __syncthreads();
+  mover_mask(mov, nmov, st, fx, fy, pts, maxp, rule, nx, ny, pitch, perx, pery, mask, ctl, cs);
 }
 
 // ----------------------------------------------------------------------------

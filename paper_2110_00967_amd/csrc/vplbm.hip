@@ -427,7 +427,8 @@ int launch_init_s(vplbm_lattice *L, int row0, int nrows, const double *r, const 
   dim3 blk(256), grd((L->p.nx + 255) / 256, nrows);
   VP_LAUNCH((k_init<S>), grd, blk, 0, L->stream, (S *)L->A(), L->mask(), L->p.nx, L->p.ny,
                      L->pitch, row0, nrows, r, u, v, ru, uu, vu, L->ctl(), L->p.rho0, (int)L->aa(),
-                     (S *)L->ec(0), perim_count(L->p.nx, L->p.ny));
+                     (S *)L->ec(0), perim_count(L->p.nx, L->p.ny), (const MoverDev *)L->movers_dev(), L->nmov,
+                     (int)(L->nstep & 1));
   return L->launched("k_init");
 }
 
@@ -516,6 +517,15 @@ int flush_movers(vplbm_lattice *L) {
   const int rc = L->launched("k_mover_flush");
   if (!rc) L->mov_pending = false;
   return rc;
+}
+
+// The mask of the moving disks' windows rewritten from their current
+// states (no step pending: the state after nstep updates, slot nstep & 1).
+int launch_mover_mask(vplbm_lattice *L) {
+  VP_LAUNCH(k_mover_mask, dim3(1), dim3(FLUSH_NT), 0, L->stream, L->movers_dev(), L->nmov, (int)(L->nstep & 1),
+            (const double *)L->at(L->L.pts), L->maxp, L->p.si_rule, L->p.nx, L->p.ny, L->pitch,
+            (int)L->periodic_x(), (int)L->periodic_y(), L->mask(), L->ctl());
+  return L->launched("k_mover_mask");
 }
 
 // sum the last step's force terms into the history (forces readable)
@@ -654,25 +664,6 @@ int become_mover(vplbm_lattice *L, const Ctl &c) {
   return push_movers(L);
 }
 
-// new points of a moving disk (body 1): its point range and window; the next
-// flush clears the old window's mask bytes too
-int update_mover_points(vplbm_lattice *L, const Ctl &c) {
-  if (!L->nmov) return VPLBM_OK;
-  int rc = pull_movers(L);
-  if (rc) return rc;
-  MoverDev &m = L->movers[0];
-  m.pt0 = 0;
-  m.pt1 = L->npts;
-  m.half = mover_half(L, L->disk_r, c.body.x, c.body.y, 0, L->npts);
-  mover_grid(m.half, m.ptx, m.pty);
-  int r[4];
-  mover_rect(L, c.body.x, c.body.y, m.half, r);
-  m.mwin[0] = std::min(m.mwin[0], r[0]);
-  m.mwin[1] = std::min(m.mwin[1], r[1]);
-  m.mwin[2] = std::max(m.mwin[2], r[2]);
-  m.mwin[3] = std::max(m.mwin[3], r[3]);
-  return push_movers(L);
-}
 
 // the registered points of bodies 1..nbody, concatenated body by body
 void rebuild_points(vplbm_lattice *L) {
@@ -829,16 +820,18 @@ int number_interfaces(vplbm_lattice *L) {
 }
 
 // store SI points (world frame or, for a moving body, body frame) in device memory
-int upload_points(vplbm_lattice *L, const Ctl &c) {
+int upload_points(vplbm_lattice *L, const Ctl &c, const BodyDev *refs = nullptr) {
   const int n = L->npts, mp = L->maxp;
   std::vector<double> buf((size_t)6 * mp, 0.0);
   const bool moving = L->mode != MODE_STATIC;
-  const double co = std::cos(-c.body.theta), sn = std::sin(-c.body.theta);
   for (int i = 0; i < n; ++i) {
     const double x = L->si_world[i], y = L->si_world[n + i];
     const double nx = L->si_world[2 * n + i], ny = L->si_world[3 * n + i];
+    const int b = L->si_body.empty() ? 1 : L->si_body[i];
+    const BodyDev &R = refs ? refs[b - 1] : c.body;  // the body's state the points are given at
+    const double co = std::cos(-R.theta), sn = std::sin(-R.theta);
     if (moving) {
-      const double dx = x - c.body.x, dy = y - c.body.y;
+      const double dx = x - R.x, dy = y - R.y;
       buf[i] = co * dx - sn * dy;
       buf[mp + i] = sn * dx + co * dy;
       buf[2 * mp + i] = co * nx - sn * ny;
@@ -1294,6 +1287,158 @@ int vplbm_set_body_dynamics(vplbm_lattice *L, double rho_s, double gx, double gy
   return rc;
 }
 
+int vplbm_set_moving_disks(vplbm_lattice *L, const vplbm_disk *d, int n, double gx, double gy, int source) {
+  if (!L) return VPLBM_EINVAL;
+  {
+    const int frc = flush(L);
+    if (frc) return frc;
+  }
+  L->pwin_ok = false;
+  if (!d) return L->fail(VPLBM_EINVAL, "NULL disks");
+  if (n < 1 || n > MAX_MOVERS) return L->fail(VPLBM_EINVAL, "n must be in 1..%d", MAX_MOVERS);
+  if (n > L->maxb) return L->fail(VPLBM_EINVAL, "n = %d exceeds max_bodies = %d", n, L->maxb);
+  if (source != VPLBM_FORCE_ME && source != VPLBM_FORCE_SI)
+    return L->fail(VPLBM_EINVAL, "force_source must be ME (0) or SI (1)");
+  if (!std::isfinite(gx) || !std::isfinite(gy)) return L->fail(VPLBM_EINVAL, "gravity must be finite");
+  const int nx = L->p.nx, ny = L->p.ny;
+  int half[MAX_MOVERS];
+  for (int k = 0; k < n; ++k) {
+    const vplbm_disk &e = d[k];
+    const double v[8] = {e.x, e.y, e.r, e.theta, e.u, e.v, e.omega, e.rho_s};
+    for (double q : v)
+      if (!std::isfinite(q)) return L->fail(VPLBM_EINVAL, "disk %d: values must be finite", k);
+    if (!(e.r > 0.0) || e.rho_s < 0.0) return L->fail(VPLBM_EINVAL, "disk %d: r > 0 and rho_s >= 0 required", k);
+    if (e.x - e.r < 1.0 || e.x + e.r > nx - 2.0 || e.y - e.r < 1.0 || e.y + e.r > ny - 2.0)
+      return L->fail(VPLBM_EINVAL, "disk %d must stay one cell inside the lattice", k);
+    for (int q = 0; q < k; ++q)
+      if (std::hypot(e.x - d[q].x, e.y - d[q].y) <= e.r + d[q].r + 2.0)
+        return L->fail(VPLBM_EINVAL, "disks %d and %d are less than two cells apart", q, k);
+    half[k] = (int)std::ceil(e.r) + WIN_MARGIN;
+  }
+  int rc = check_moving_capacity(L, n, half);
+  if (rc) return rc;
+  Ctl c;
+  rc = L->ctl_pull(c);
+  if (!rc) rc = reset_geometry(L, c);
+  if (rc) return rc;
+  for (int b = 1; b <= MAX_BODIES; ++b) L->si_sets[b].clear();
+  L->nbody = n;
+  rebuild_points(L);
+  const double rho0 = L->p.rho0;
+  std::vector<MoverDev> mv(MAX_MOVERS, MoverDev{});
+  int part = 0;
+  for (int k = 0; k < n; ++k) {
+    const vplbm_disk &e = d[k];
+    MoverDev &m = mv[k];
+    m.B[0] = m.B[1] = BodyDev{e.x, e.y, e.theta, e.u, e.v, e.omega};
+    m.r = e.r;
+    m.R = fixq(e.r);
+    m.mode = e.rho_s > 0.0 ? MODE_FREE : MODE_PRESCRIBED;
+    m.mass = e.rho_s > 0.0 ? e.rho_s * M_PI * e.r * e.r : 0.0;
+    m.inertia = 0.5 * m.mass * e.r * e.r;
+    m.gx = gx;
+    m.gy = gy;
+    m.buoy = e.rho_s > 0.0 ? 1.0 - rho0 / e.rho_s : 0.0;
+    m.source = source;
+    m.nfin = c.step;
+    m.half = half[k];
+    m.pt0 = m.pt1 = 0;
+    m.part0 = part;
+    mover_grid(half[k], m.ptx, m.pty);
+    part += m.ptx * m.pty;
+  }
+  // body 1 in the control block, as the single-body calls see it
+  c.nbody = n;
+  c.body = mv[0].B[0];
+  c.shape = SHAPE_DISK;
+  c.mode = mv[0].mode;
+  c.r = d[0].r;
+  c.mass = mv[0].mass;
+  c.inertia = mv[0].inertia;
+  c.gx = gx;
+  c.gy = gy;
+  c.buoy = mv[0].buoy;
+  c.source = source;
+  c.si_moving = 1;
+  c.npts = 0;
+  c.nrec = 0;
+  c.err = 0;
+  rc = L->ctl_push(c);
+  if (rc) return rc;
+  L->shape = SHAPE_DISK;
+  L->mode = c.mode;
+  L->disk_r = d[0].r;
+  L->movers = mv;
+  L->nmov = n;
+  L->mov_pending = false;
+  L->pending = false;
+  L->bx = 64;  // the moving-disk step kernels run 64x4 tiles
+  L->by = 4;
+  rc = push_movers(L);
+  if (!rc) rc = launch_mover_mask(L);
+  if (!rc) rc = L->sync();
+  if (!rc) rc = check_sample_error(L);
+  return rc;
+}
+
+// Points of moving disk `body` (the caller has checked them and flushed):
+// stored in the disk's frame at its current state; every disk's point
+// range, window and partial grid follow, and the mask of the windows is
+// rewritten.
+int set_points_moving(vplbm_lattice *L, int body, const double *xy, const double *nrm, const double *ds, int npts) {
+  if (body > L->nmov) return L->fail(VPLBM_EINVAL, "body %d is not a moving disk", body);
+  int rc = pull_movers(L);
+  if (rc) return rc;
+  const int slot = (int)(L->nstep & 1);  // the current states
+  int half[MAX_MOVERS];
+  for (int k = 0; k < L->nmov; ++k) half[k] = L->movers[k].half;
+  {
+    const BodyDev &B = L->movers[body - 1].B[slot];
+    double rmax = L->movers[body - 1].r;
+    for (int i = 0; i < npts; ++i) rmax = std::max(rmax, std::hypot(xy[2 * i] - B.x, xy[2 * i + 1] - B.y));
+    half[body - 1] = (int)std::ceil(rmax) + WIN_MARGIN;
+  }
+  rc = check_moving_capacity(L, L->nmov, half);
+  if (rc) return rc;
+  std::vector<double> &v = L->si_sets[body];
+  v.assign((size_t)5 * npts, 0.0);
+  for (int i = 0; i < npts; ++i) {
+    v[i] = xy[2 * i];
+    v[npts + i] = xy[2 * i + 1];
+    v[2 * npts + i] = nrm[2 * i];
+    v[3 * npts + i] = nrm[2 * i + 1];
+    v[4 * npts + i] = ds[i];
+  }
+  rebuild_points(L);  // body by body: disk k's points follow disk k - 1's
+  int o = 0, part = 0;
+  BodyDev refs[MAX_MOVERS];
+  for (int k = 0; k < L->nmov; ++k) {
+    MoverDev &m = L->movers[k];
+    const int nk = (int)(L->si_sets[k + 1].size() / 5);
+    m.pt0 = o;
+    m.pt1 = o + nk;
+    o += nk;
+    m.half = half[k];
+    mover_grid(half[k], m.ptx, m.pty);
+    m.part0 = part;
+    part += m.ptx * m.pty;
+    refs[k] = m.B[slot];
+  }
+  Ctl c;
+  rc = L->ctl_pull(c);
+  if (rc) return rc;
+  c.npts = L->npts;
+  c.si_moving = 1;
+  c.nrec = 0;
+  rc = L->ctl_push(c);
+  if (!rc) rc = upload_points(L, c, refs);
+  if (!rc) rc = push_movers(L);
+  if (!rc) rc = launch_mover_mask(L);
+  if (!rc) rc = L->sync();
+  if (!rc) rc = check_sample_error(L);
+  return rc;
+}
+
 int vplbm_set_si_points_body(vplbm_lattice *L, int body, const double *xy, const double *nrm, const double *ds,
                              int npts) {
   if (!L) return VPLBM_EINVAL;
@@ -1313,18 +1458,7 @@ int vplbm_set_si_points_body(vplbm_lattice *L, int body, const double *xy, const
   for (int b = 1; b <= L->nbody; ++b)
     if (b != body) total += (int)(L->si_sets[b].size() / 5);
   if (total > L->maxp) return L->fail(VPLBM_EINVAL, "%d points in all exceed max_si_points = %d", total, L->maxp);
-  if (L->nmov) {
-    // a moving disk's window grows with its farthest point
-    Ctl c0;
-    int rc = L->ctl_pull(c0);
-    if (rc) return rc;
-    double rmax = L->disk_r;
-    for (int i = 0; i < npts; ++i)
-      rmax = std::max(rmax, std::hypot(xy[2 * i] - c0.body.x, xy[2 * i + 1] - c0.body.y));
-    const int h = (int)std::ceil(rmax) + WIN_MARGIN;
-    rc = check_moving_capacity(L, 1, &h);
-    if (rc) return rc;
-  }
+  if (L->nmov) return set_points_moving(L, body, xy, nrm, ds, npts);
   std::vector<double> &v = L->si_sets[body];
   v.assign((size_t)5 * npts, 0.0);
   for (int i = 0; i < npts; ++i) {
@@ -1345,16 +1479,8 @@ int vplbm_set_si_points_body(vplbm_lattice *L, int body, const double *xy, const
   if (rc) return rc;
   // clear old sample bits: recompute flags over the window and region (for
   // a moving disk, the window its last flush wrote)
-  int x0 = std::min(c.win[0], c.region[0]), y0 = std::min(c.win[1], c.region[1]);
-  int x1 = std::max(c.win[2], c.region[2]), y1 = std::max(c.win[3], c.region[3]);
-  if (L->nmov) {
-    rc = pull_movers(L);
-    if (rc) return rc;
-    x0 = L->movers[0].mwin[0];
-    y0 = L->movers[0].mwin[1];
-    x1 = L->movers[0].mwin[2];
-    y1 = L->movers[0].mwin[3];
-  }
+  const int x0 = std::min(c.win[0], c.region[0]), y0 = std::min(c.win[1], c.region[1]);
+  const int x1 = std::max(c.win[2], c.region[2]), y1 = std::max(c.win[3], c.region[3]);
   rc = launch_flags(L, x0, y0, x1, y1);
   if (!rc) rc = L->sync();
   if (rc) return rc;
@@ -1369,13 +1495,11 @@ int vplbm_set_si_points_body(vplbm_lattice *L, int body, const double *xy, const
     rc = L->hip(hipMemcpyAsync(L->bt(), bt.data(), bt.size() * sizeof(BodyTab), hipMemcpyHostToDevice, L->stream),
                 "body table write");
     if (!rc) rc = L->sync();
-    if (!rc) rc = update_mover_points(L, c);
     return rc;
   }
   rc = upload_points(L, c);
   if (!rc) rc = refresh_si(L);
   if (!rc) rc = check_sample_error(L);
-  if (!rc) rc = update_mover_points(L, c);
   return rc;
 }
 
@@ -1642,6 +1766,30 @@ int vplbm_get_body_state(vplbm_lattice *L, vplbm_body_state *out) {
   int rc = L->ctl_pull(c);
   if (rc) return rc;
   *out = vplbm_body_state{c.body.x, c.body.y, c.body.theta, c.body.u, c.body.v, c.body.omega};
+  return VPLBM_OK;
+}
+
+int vplbm_get_body_state_of(vplbm_lattice *L, int body, vplbm_body_state *out) {
+  if (!L || !out) return VPLBM_EINVAL;
+  if (body < 1 || body > L->nbody) return L->fail(VPLBM_EINVAL, "body must be in 1..%d", L->nbody);
+  if (body == 1) return vplbm_get_body_state(L, out);
+  {
+    const int frc = flush_movers(L);  // the disks' states after the last step
+    if (frc) return frc;
+  }
+  BodyDev B;
+  if (body <= L->nmov) {
+    const int rc = pull_movers(L);
+    if (rc) return rc;
+    B = L->movers[body - 1].B[L->nstep & 1];
+  } else {
+    const int rc = L->hip(hipMemcpyAsync(&B, L->bodies() + body, sizeof(BodyDev), hipMemcpyDeviceToHost, L->stream),
+                          "body read");
+    if (rc) return rc;
+    const int src = L->sync();
+    if (src) return src;
+  }
+  *out = vplbm_body_state{B.x, B.y, B.theta, B.u, B.v, B.omega};
   return VPLBM_OK;
 }
 

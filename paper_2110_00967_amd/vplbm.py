@@ -40,7 +40,8 @@ EXPORTS = [
     "vplbm_read_populations", "vplbm_read_mask", "vplbm_read_macro_window", "vplbm_read_populations_window",
     "vplbm_batch_create", "vplbm_batch_destroy", "vplbm_batch_last_error", "vplbm_batch_step",
     "vplbm_set_body_ids", "vplbm_set_si_points_body", "vplbm_forces_body", "vplbm_force_history_body",
-    "vplbm_read_macro_device", "vplbm_batch_set_tile", "vplbm_batch_get_tile", "vplbm_batch_set_lattices", "vplbm_batch_step_noalloc",
+    "vplbm_read_macro_device", "vplbm_batch_set_tile", "vplbm_batch_get_tile", "vplbm_batch_set_lattices",
+    "vplbm_batch_step_noalloc", "vplbm_set_moving_disks", "vplbm_get_body_state_of",
 ]
 
 
@@ -66,6 +67,12 @@ class Params(C.Structure):
 class BodyState(C.Structure):
     _fields_ = [("x", C.c_double), ("y", C.c_double), ("theta", C.c_double), ("u", C.c_double),
                 ("v", C.c_double), ("omega", C.c_double)]
+
+
+class Disk(C.Structure):
+    """One of several moving disks: rho_s > 0 free, rho_s = 0 prescribed."""
+    _fields_ = [("x", C.c_double), ("y", C.c_double), ("r", C.c_double), ("theta", C.c_double),
+                ("u", C.c_double), ("v", C.c_double), ("omega", C.c_double), ("rho_s", C.c_double)]
 
 
 _lib = None
@@ -116,6 +123,8 @@ def load_library(path: str = LIB_PATH):
     L.vplbm_forces_si_at.argtypes = [vp, dp, dp, dp, ip, dp]
     L.vplbm_force_history.argtypes = [vp, ip, C.c_longlong, ip, dp]
     L.vplbm_get_body_state.argtypes = [vp, P(BodyState)]
+    L.vplbm_get_body_state_of.argtypes = [vp, ip, P(BodyState)]
+    L.vplbm_set_moving_disks.argtypes = [vp, P(Disk), ip, C.c_double, C.c_double, ip]
     L.vplbm_read_macro.argtypes = [vp, dp, dp, dp]
     L.vplbm_read_populations.argtypes = [vp, dp]
     L.vplbm_read_macro_window.argtypes = [vp, ip, ip, ip, ip, dp, dp, dp]
@@ -285,6 +294,11 @@ class Lattice:
         s = BodyState(x, y, theta, u, v, omega)
         self._chk(self._lib.vplbm_set_body_motion(self._h, C.byref(s)))
 
+    def set_moving_disks(self, disks, gx=0.0, gy=0.0, source=FORCE_ME):
+        """Several moving disks, each (x, y, r, theta, u, v, omega, rho_s); rho_s = 0: prescribed."""
+        arr = (Disk * len(disks))(*[Disk(*[float(v) for v in d]) for d in disks])
+        self._chk(self._lib.vplbm_set_moving_disks(self._h, arr, len(disks), gx, gy, int(source)))
+
     def set_dynamics(self, rho_s, gx, gy, source=FORCE_ME):
         self._chk(self._lib.vplbm_set_body_dynamics(self._h, rho_s, gx, gy, int(source)))
 
@@ -354,9 +368,9 @@ class Lattice:
         first = max(1, n - cap + 1)
         return self.force_history(which, first, n - first + 1, body)
 
-    def body_state(self):
+    def body_state(self, body=1):
         s = BodyState()
-        self._chk(self._lib.vplbm_get_body_state(self._h, C.byref(s)))
+        self._chk(self._lib.vplbm_get_body_state_of(self._h, int(body), C.byref(s)))
         return np.array([s.x, s.y, s.theta, s.u, s.v, s.omega])
 
     def macro_device(self):

@@ -170,3 +170,128 @@ def test_interface_slot_capacity():
     g.sync()
     assert np.isfinite(g.forces_me()).all()
     g.close()
+
+
+# -- several moving disks ------------------------------------------------------
+MOVING = [(30.2, 36.1, 6.1, 0.0, 0.0, 0.0, 0.0, 1.3),          # free
+          (64.4, 20.3, 5.2, 0.0, 0.0, 0.0, 0.0, 1.8),          # free, heavier
+          (96.3, 47.8, 5.6, 0.1, -0.004, 0.003, 0.008, 0.0)]   # prescribed: translating and spinning
+MEDGES = ((O.VELOCITY, 0.02, 0.0), (O.OUTFLOW, 0, 0), (O.FREESLIP, 0, 0), (O.FREESLIP, 0, 0))
+MNX, MNY, MG = 128, 72, (0.0, -2e-5)
+
+
+def moving_build(precision="f64", source=0, rule=0):
+    from paper_2110_00967_amd import vplbm as V
+    p = V.make_params(MNX, MNY, 0.7, 1e-4, 1.0, precision, *MEDGES, max_si_points=256, si_rule=rule,
+                      max_bodies=3)
+    g = V.Lattice(p)
+    g.set_moving_disks(MOVING, *MG, source)
+    o = O.RefLattice(MNX, MNY, 0.7, 1e-4, 1.0, *MEDGES, si_rule=rule)
+    o.set_moving_disks(MOVING, *MG, source)
+    for b, d, n in ((1, MOVING[0], 40), (2, MOVING[1], 32), (3, MOVING[2], 36)):
+        pts = W.disk_si_points(d[0], d[1], d[2], n)
+        g.set_si_points_body(b, *pts)
+        o.set_si_points_body(b, *pts)
+    g.init_uniform(1.0, 0.02, 0.0)
+    o.init_uniform(1.0, 0.02, 0.0)
+    return g, o
+
+
+@pytest.mark.parametrize("source,rule", [(0, 0), (1, 1)])
+def test_moving_disks_fp64_against_oracle(source, rule):
+    from gpu_cases import oracle_pops
+    from paper_2110_00967_amd import vplbm as V
+    say(f"three moving disks {MNX}x{MNY} fp64, source {source}, rule {rule}")
+    g, o = moving_build("f64", source, rule)
+    assert np.array_equal(g.mask() & 0x3F, o.solid)
+    for k in range(3):
+        g.step(50)
+        o.step(50)
+        assert np.abs(g.populations() - oracle_pops(o)).max() <= 1e-12, k
+        for b in (1, 2, 3):
+            bg, bo = g.body_state(b), o.body_state(b)
+            assert np.abs(bg - bo).max() <= 1e-10 * max(1.0, np.abs(bo).max()), (k, b, bg, bo)
+        m = g.mask()
+        assert np.array_equal(m & 0x3F, o.solid), k
+        sample = np.zeros(MNX * MNY, bool)
+        sample[o.si_node] = True
+        assert np.array_equal((m.ravel() & 0x40) != 0, sample), k
+    for b in (1, 2, 3):
+        for which, ref in ((V.FORCE_ME, o.me(b)), (V.FORCE_SI, o.si(b))):
+            e = np.abs(g.history(which, body=b) - ref).max() / np.abs(ref).max()
+            assert e <= 1e-10, (b, which, e)
+    # the free disks moved on their own forces; the prescribed one by its velocities
+    assert abs(o.body_state(1)[4]) > 1e-5 and abs(o.body_state(2)[4]) > 1e-5
+    assert abs(g.body_state(3)[0] - (MOVING[2][0] + 150 * MOVING[2][4])) < 1e-10
+
+
+def test_moving_disks_in_batch_equal_alone():
+    from paper_2110_00967_amd import vplbm as V
+    say("three moving disks inside a batch, fp32")
+    g, _ = moving_build("f32")
+    for _ in range(29):
+        g.step(1)
+    alone = [g.history(w, body=b) for b in (1, 2, 3) for w in (V.FORCE_ME, V.FORCE_SI)]
+    states = [g.body_state(b) for b in (1, 2, 3)]
+    pops = g.populations()
+    g.close()
+    a, _ = moving_build("f32")
+    other = V.Lattice.from_case(W.case_disk_channel(), precision="f32")
+    bt = V.Batch([other, a])
+    bt.step([11, 29])
+    assert np.array_equal(a.populations(), pops)
+    for x, y in zip([a.history(w, body=b) for b in (1, 2, 3) for w in (V.FORCE_ME, V.FORCE_SI)], alone):
+        assert np.array_equal(x, y)
+    for b in (1, 2, 3):
+        assert np.array_equal(a.body_state(b), states[b - 1])
+    bt.close()
+
+
+def test_moving_disks_too_close_are_rejected():
+    from paper_2110_00967_amd import vplbm as V
+    say("moving disks one cell apart")
+    g = V.Lattice(V.make_params(64, 40, 0.7, 1e-3, 1.0, "f32", max_bodies=2))
+    with pytest.raises(V.VplbmError) as e:
+        g.set_moving_disks([(20.0, 20.0, 5.0, 0, 0, 0, 0, 1.2), (31.5, 20.0, 5.0, 0, 0, 0, 0, 1.2)])
+    assert e.value.code == V.EINVAL
+    g.set_moving_disks([(20.0, 20.0, 5.0, 0, 0, 0, 0, 1.2), (32.5, 20.0, 5.0, 0, 0, 0, 0, 1.2)])
+    with pytest.raises(V.VplbmError):
+        g.set_moving_disks([(20.0, 20.0, 5.0, 0, 0, 0, 0, 1.2)] * 3)  # more than max_bodies
+
+
+# -- static bodies on non-periodic edges ----------------------------------------
+def test_bodies_on_walls_fp64():
+    # bodies whose cells lie on the south and north walls: a fluid cell on a
+    # wall takes its links' body from its own side, never from the solid
+    # cells across the wall (no neighbours there)
+    from gpu_cases import oracle_pops
+    from paper_2110_00967_amd import vplbm as V
+    nx, ny = 64, 40
+    edges = ((O.VELOCITY, 0.03, 0.0), (O.OUTFLOW, 0, 0), (O.FREESLIP, 0, 0), (O.VELOCITY, 0.0, 0.0))
+    ids = np.zeros((ny, nx), np.uint8)
+    ids[0:6, 20:30] = 1                      # on the south wall
+    ids[35:40, 16:34] = 2                    # on the north wall, over body 1 across the wrap
+    ids[O.mask_disk(nx, ny, 46.2, 20.4, 5.3) != 0] = 3
+    refs = [(24.5, 2.5), (24.5, 37.5), (46.2, 20.4)]
+    say("three static bodies on the walls 64x40 fp64")
+    p = V.make_params(nx, ny, 0.7, 1e-3, 1.0, "f64", *edges, max_si_points=64, max_bodies=3)
+    g = V.Lattice(p)
+    g.set_body_ids(ids, refs)
+    o = O.RefLattice(nx, ny, 0.7, 1e-3, 1.0, *edges)
+    o.set_body_ids(ids, refs)
+    pts = W.disk_si_points(46.2, 20.4, 5.3, 36)
+    g.set_si_points_body(3, *pts)
+    o.set_si_points_body(3, *pts)
+    rho, ux, uy = W.random_density(nx, ny, seed=5, amp=1e-3), *W.smooth_random_velocity(nx, ny, seed=6, amp=0.02)
+    g.set_fields(rho, ux, uy)
+    o.set_fields(rho, ux, uy)
+    for _ in range(3):
+        g.step(20)
+        o.step(20)
+        assert np.abs(g.populations() - oracle_pops(o)).max() <= 1e-12
+    for b in (1, 2, 3):
+        for which, ref in ((V.FORCE_ME, o.me(b)), (V.FORCE_SI, o.si(b))):
+            if not np.abs(ref).max():
+                continue
+            e = np.abs(g.history(which, body=b) - ref).max() / np.abs(ref).max()
+            assert e <= 1e-10, (b, which, e)
