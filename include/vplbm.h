@@ -77,7 +77,9 @@ typedef struct {
 } vplbm_edge;
 
 typedef struct {
-  int nx, ny;        /* lattice size, each >= 4, nx <= 16384, 9*ny*pitch < 2^31 */
+  int nx, ny;        /* lattice size, each >= 4, ny * pitch < 2^31 cells (pitch: nx
+                        rounded up to a multiple of 64); populations are
+                        indexed in 64 bits, cells in 32 */
   double tau;        /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3 (Eq. tauvisco) */
   double eta;        /* penalization factor, > 0; +inf switches penalization off */
   double rho0;       /* reference density (> 0; 1 in every workload here) */

@@ -52,10 +52,11 @@ enum { EDGE_PERIODIC = 0, EDGE_VELOCITY = 1, EDGE_FREESLIP = 2, EDGE_OUTFLOW = 3
 // each run of 64 cells along a row are stored together, plane by plane, so
 // one cell update touches 9 neighbouring 64-element blocks instead of 9
 // planes a lattice apart.  Element (a, x, y), with pitch a multiple of 64:
-//   ((y * (pitch / 64) + x / 64) * 9 + a) * 64 + x % 64.
-// 9 ny pitch < 2^31, so the index fits an int.
-__host__ __device__ inline int pop_index(int a, int x, int y, int pitch) {
-  return ((y * (pitch >> 6) + (x >> 6)) * Q + a) * 64 + (x & 63);
+//   ((y * (pitch / 64) + x / 64) * 9 + a) * 64 + x % 64,
+// in 64 bits (a lattice may hold more than 2^31 elements; cells ny pitch <
+// 2^31, so cell indices fit an int).
+__host__ __device__ inline long long pop_index(int a, int x, int y, int pitch) {
+  return (((long long)y * (pitch >> 6) + (x >> 6)) * Q + a) * 64 + (x & 63);
 }
 constexpr int CHUNK_ELEMS = 64 * 9;  // one run of 64 cells, all populations
 

@@ -53,19 +53,19 @@ __device__ __forceinline__ void pull_post(const S *F, const S *ec, int lay, cons
 // ----------------------------------------------------------------------------
 template <typename S>
 __global__ void k_init(S *__restrict__ f, const uint8_t *__restrict__ mask, int nx, int ny, int pitch,
-                       int row0, int nrows, const double *__restrict__ rho_in,
+                       int row0, int nrows, int col0, int ncols, const double *__restrict__ rho_in,
                        const double *__restrict__ ux_in, const double *__restrict__ uy_in,
                        double rho_u, double ux_u, double uy_u, const Ctl *__restrict__ ctl, double rho0,
                        int swapped, S *__restrict__ ec, int nper, const MoverDev *__restrict__ mov, int nmov,
                        int slot) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int xl = blockIdx.x * blockDim.x + threadIdx.x;
   const int yl = blockIdx.y;
-  if (x >= nx || yl >= nrows) return;
-  const int y = row0 + yl;
+  if (xl >= ncols || yl >= nrows) return;
+  const int x = col0 + xl, y = row0 + yl;
   const long long c = (long long)y * pitch + x;
   double rho, ux, uy;
-  if (rho_in) {
-    const long long k = (long long)yl * nx + x;
+  if (rho_in) {  // [nrows][ncols] staged values
+    const long long k = (long long)yl * ncols + xl;
     rho = rho_in[k];
     ux = ux_in[k];
     uy = uy_in[k];

@@ -35,7 +35,7 @@ template <typename T> struct StepArgs {
   int nx, ny, pitch;
   long long plane;      // ny * pitch
   int tiles_x, ntiles, per_xcd;
-  unsigned tx_magic;    // floor(2^32 / tiles_x) + 1 (0 when tiles_x = 1)
+  unsigned tx_magic;    // floor((2^32 - 1) / tiles_x) (0 when tiles_x = 1), see tile_cell
   int rot[8];           // per XCD: the band's tiles start this far in (see k_step)
   int kind[4];          // edge kinds W, E, S, N
   T wu[4][2];           // 6 rho0 u_w of each edge: bounce-back increment w_a c_a . wu
@@ -176,7 +176,6 @@ __device__ __forceinline__ void pull_edge_all(const S *__restrict__ fin, const S
     T add;
     bool cv;
     edge_source(P, x, y, a, pop, sx, sy, add, cv);
-    // element index in 32 bits: 9 ny pitch < 2^31 for every accepted lattice
     d[a] = Store<S>::ld(fin + pop_index(pop, sx, sy, P.pitch)) + add;
     conv |= cv ? 1u << a : 0u;
   }
@@ -216,8 +215,8 @@ __device__ __forceinline__ void aa_pull_edge(const S *F, const StepArgs<T> &P, i
     T add;
     bool cv;
     edge_source(P, x, y, a, pop, sx, sy, add, cv);
-    const int k = in ? (AA == 1 ? pop_index(opp(a), rx, ry, P.pitch) : pop_index(a, x, y, P.pitch))
-                     : pop * P.nper + perim_index(sx, sy, P.nx, P.ny);
+    const long long k = in ? (AA == 1 ? pop_index(opp(a), rx, ry, P.pitch) : pop_index(a, x, y, P.pitch))
+                           : (long long)(pop * P.nper + perim_index(sx, sy, P.nx, P.ny));
     d[a] = Store<S>::ld((in ? F : ec) + k) + (in ? T(0) : add);
     conv |= (!in && cv) ? 1u << a : 0u;
   }
@@ -773,10 +772,15 @@ struct TileCell {
 template <typename S, int BX, int BY, typename T>
 __device__ __forceinline__ TileCell tile_cell(int tile, const StepArgs<T> &P) {
   TileCell t;
-  // tile / tiles_x by multiply-high (exact while tile * tiles_x < 2^32, which
-  // every accepted lattice satisfies: tiles_x^2 * ny <= 58,255 * pitch < 2^30)
+  // tile / tiles_x by multiply-high with m = floor((2^32 - 1) / tiles_x):
+  // the estimate is the quotient or one less (tile < 2^31), fixed by one
+  // comparison; m = 0 stands for tiles_x = 1
   t.ty = P.tx_magic ? (int)__umulhi((unsigned)tile, P.tx_magic) : tile;
   t.tx = tile - t.ty * P.tiles_x;
+  if (t.tx >= P.tiles_x) {
+    t.tx -= P.tiles_x;
+    t.ty += 1;
+  }
   t.lx = threadIdx.x % BX;
   t.ly = threadIdx.x / BX;
   t.x = t.tx * BX + t.lx;

@@ -49,7 +49,6 @@ constexpr int DEFAULT_PTS = 4096;
 constexpr int DEFAULT_VERTS = 4096;
 constexpr int WG_SLOTS_PER_XCD = 256;  // 32 CUs x 8 resident workgroups of the step kernel
 constexpr int ROT_MAX_ROUNDS = 16;
-constexpr int MAX_NX = 16384;  // one row of 9 planes fits the staging buffer
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -135,7 +134,6 @@ bool valid_edge(const vplbm_edge &e) {
 const char *check_params(const vplbm_params *p) {
   if (!p) return "params is NULL";
   if (p->nx < 4 || p->ny < 4) return "nx and ny must be >= 4";
-  if (p->nx > MAX_NX) return "nx must be <= 16384";
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return "tau must be finite and > 1/2";
   if (!(p->eta > 0.0)) return "eta must be > 0 (or +inf)";
   if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return "rho0 must be finite and > 0";
@@ -158,7 +156,7 @@ const char *check_params(const vplbm_params *p) {
   if (p->si_rule == 1 && (p->max_si_points == 0 || p->max_si_points > SI_MAX / 4))
     return "si_rule 1 needs max_si_points in 1..1024";
   const long long pitch = pitch_of(*p);
-  if (9LL * p->ny * pitch >= (1LL << 31)) return "lattice too large (9*ny*pitch must be < 2^31)";
+  if ((long long)p->ny * pitch >= (1LL << 31)) return "lattice too large (ny * pitch cells must be < 2^31)";
   return nullptr;
 }
 
@@ -266,9 +264,8 @@ struct vplbm_lattice {
     a.pitch = pitch;
     a.plane = plane;
     a.tiles_x = (p.nx + bx - 1) / bx;
-    // tile / tiles_x = umulhi(tile, floor(2^32 / tiles_x) + 1): the error term,
-    // below tile / 2^32, stays under 1 / tiles_x while tile * tiles_x < 2^32
-    a.tx_magic = a.tiles_x == 1 ? 0u : (unsigned)((1ull << 32) / (unsigned)a.tiles_x + 1);
+    // tile / tiles_x by multiply-high and one correction (see tile_cell)
+    a.tx_magic = a.tiles_x == 1 ? 0u : (unsigned)(0xFFFFFFFFull / (unsigned)a.tiles_x);
     const int tiles_y = (p.ny + by - 1) / by;
     a.ntiles = a.tiles_x * tiles_y;
     a.per_xcd = (a.ntiles + 7) / 8;
@@ -422,22 +419,24 @@ int launch_step(vplbm_lattice *L, bool macro) {
 }
 
 template <typename S>
-int launch_init_s(vplbm_lattice *L, int row0, int nrows, const double *r, const double *u,
+int launch_init_s(vplbm_lattice *L, int row0, int nrows, int col0, int ncols, const double *r, const double *u,
                   const double *v, double ru, double uu, double vu) {
-  dim3 blk(256), grd((L->p.nx + 255) / 256, nrows);
+  dim3 blk(256), grd((ncols + 255) / 256, nrows);
   VP_LAUNCH((k_init<S>), grd, blk, 0, L->stream, (S *)L->A(), L->mask(), L->p.nx, L->p.ny,
-                     L->pitch, row0, nrows, r, u, v, ru, uu, vu, L->ctl(), L->p.rho0, (int)L->aa(),
+                     L->pitch, row0, nrows, col0, ncols, r, u, v, ru, uu, vu, L->ctl(), L->p.rho0, (int)L->aa(),
                      (S *)L->ec(0), perim_count(L->p.nx, L->p.ny), (const MoverDev *)L->movers_dev(), L->nmov,
                      (int)(L->nstep & 1));
   return L->launched("k_init");
 }
 
+// rows [row0, row0 + nrows) x columns [col0, col0 + ncols); ncols < 0: all
 int launch_init(vplbm_lattice *L, int row0, int nrows, const double *r, const double *u,
-                const double *v, double ru, double uu, double vu) {
+                const double *v, double ru, double uu, double vu, int col0 = 0, int ncols = -1) {
+  if (ncols < 0) ncols = L->p.nx;
   switch (L->p.precision) {
-    case VPLBM_F64: return launch_init_s<double>(L, row0, nrows, r, u, v, ru, uu, vu);
-    case VPLBM_F32: return launch_init_s<float>(L, row0, nrows, r, u, v, ru, uu, vu);
-    default: return launch_init_s<__half>(L, row0, nrows, r, u, v, ru, uu, vu);
+    case VPLBM_F64: return launch_init_s<double>(L, row0, nrows, col0, ncols, r, u, v, ru, uu, vu);
+    case VPLBM_F32: return launch_init_s<float>(L, row0, nrows, col0, ncols, r, u, v, ru, uu, vu);
+    default: return launch_init_s<__half>(L, row0, nrows, col0, ncols, r, u, v, ru, uu, vu);
   }
 }
 
@@ -997,17 +996,25 @@ int vplbm_set_fields(vplbm_lattice *L, const double *rho, const double *ux, cons
   for (long long k = 0; k < (long long)nx * ny; ++k)
     if (!(rho[k] > 0.0) || !std::isfinite(rho[k]) || !std::isfinite(ux[k]) || !std::isfinite(uy[k]))
       return L->fail(VPLBM_EINVAL, "field value at %lld is invalid", k);
-  const int rows = std::max(1, (int)(STAGE_DOUBLES / (3 * (size_t)nx)));
+  // staged in blocks of rows of a strip of columns (the whole width when it fits)
+  const int wmax = (int)(STAGE_DOUBLES / 3);
   double *st = (double *)L->at(L->L.staging);
-  for (int y0 = 0; y0 < ny; y0 += rows) {
-    const int nr = std::min(rows, ny - y0);
-    const size_t n = (size_t)nr * nx;
-    int rc = L->hip(hipMemcpyAsync(st, rho + (size_t)y0 * nx, n * 8, hipMemcpyHostToDevice, L->stream), "rho");
-    if (!rc) rc = L->hip(hipMemcpyAsync(st + n, ux + (size_t)y0 * nx, n * 8, hipMemcpyHostToDevice, L->stream), "ux");
-    if (!rc) rc = L->hip(hipMemcpyAsync(st + 2 * n, uy + (size_t)y0 * nx, n * 8, hipMemcpyHostToDevice, L->stream), "uy");
-    if (!rc) rc = launch_init(L, y0, nr, st, st + n, st + 2 * n, 0, 0, 0);
-    if (!rc) rc = L->sync();
-    if (rc) return rc;
+  for (int c0 = 0; c0 < nx; c0 += wmax) {
+    const int wc = std::min(wmax, nx - c0);
+    const int rows = std::max(1, (int)(STAGE_DOUBLES / (3 * (size_t)wc)));
+    for (int y0 = 0; y0 < ny; y0 += rows) {
+      const int nr = std::min(rows, ny - y0);
+      const size_t n = (size_t)nr * wc;
+      const double *src[3] = {rho, ux, uy};
+      int rc = VPLBM_OK;
+      for (int k = 0; k < 3 && !rc; ++k)
+        rc = L->hip(hipMemcpy2DAsync(st + k * n, (size_t)wc * 8, src[k] + (size_t)y0 * nx + c0, (size_t)nx * 8,
+                                     (size_t)wc * 8, (size_t)nr, hipMemcpyHostToDevice, L->stream),
+                    "field upload");
+      if (!rc) rc = launch_init(L, y0, nr, st, st + n, st + 2 * n, 0, 0, 0, c0, wc);
+      if (!rc) rc = L->sync();
+      if (rc) return rc;
+    }
   }
   return reset_counters(L);
 }
@@ -1802,6 +1809,23 @@ int vplbm_read_macro_window(vplbm_lattice *L, int x0, int y0, int w, int h, doub
   if (!L || !rho || !ux || !uy) return VPLBM_EINVAL;
   if (bad_window(L, x0, y0, w, h)) return L->fail(VPLBM_EINVAL, "window outside the lattice");
   if (!L->macro_valid) return L->fail(VPLBM_ESTATE, "last step did not store rho and u (VPLBM_STEP_MACRO)");
+  const int wmax = (int)(STAGE_DOUBLES / 3);
+  if (w > wmax) {  // wider than one staged row: strips of columns
+    std::vector<double> part;
+    for (int c0 = 0; c0 < w; c0 += wmax) {
+      const int wc = std::min(wmax, w - c0);
+      part.resize((size_t)3 * wc * h);
+      double *pr = part.data(), *pu = pr + (size_t)wc * h, *pv = pu + (size_t)wc * h;
+      const int rc = vplbm_read_macro_window(L, x0 + c0, y0, wc, h, pr, pu, pv);
+      if (rc) return rc;
+      for (int r = 0; r < h; ++r) {
+        std::memcpy(rho + (size_t)r * w + c0, pr + (size_t)r * wc, (size_t)wc * 8);
+        std::memcpy(ux + (size_t)r * w + c0, pu + (size_t)r * wc, (size_t)wc * 8);
+        std::memcpy(uy + (size_t)r * w + c0, pv + (size_t)r * wc, (size_t)wc * 8);
+      }
+    }
+    return VPLBM_OK;
+  }
   const int rows = std::max(1, (int)(STAGE_DOUBLES / (3 * (size_t)w)));
   double *st = (double *)L->at(L->L.staging);
   std::vector<double> hb;
@@ -1856,6 +1880,20 @@ int vplbm_read_populations_window(vplbm_lattice *L, int x0, int y0, int w, int h
   {
     const int frc = flush(L);
     if (frc) return frc;
+  }
+  const int wmax = (int)(STAGE_DOUBLES / Q);
+  if (w > wmax) {  // wider than one staged row: strips of columns
+    std::vector<double> part;
+    for (int c0 = 0; c0 < w; c0 += wmax) {
+      const int wc = std::min(wmax, w - c0);
+      part.resize((size_t)Q * wc * h);
+      const int rc = vplbm_read_populations_window(L, x0 + c0, y0, wc, h, part.data());
+      if (rc) return rc;
+      for (int a = 0; a < Q; ++a)
+        for (int r = 0; r < h; ++r)
+          std::memcpy(f + ((size_t)a * h + r) * w + c0, part.data() + ((size_t)a * h + r) * wc, (size_t)wc * 8);
+    }
+    return VPLBM_OK;
   }
   const int rows = std::max(1, (int)(STAGE_DOUBLES / (9 * (size_t)w)));
   double *st = (double *)L->at(L->L.staging);

@@ -63,13 +63,23 @@ def test_required_bytes_valid():
     dict(eta=-1.0), dict(eta=float("nan")), dict(precision=7), dict(west=(V.PERIODIC, 0, 0)),
     dict(south=(V.VELOCITY, 0, 0)), dict(north=(9, 0, 0)), dict(east=(V.VELOCITY, float("inf"), 0)),
     dict(nx=200000, ny=200000), dict(max_si_points=5000), dict(hist_capacity=-1),
-    dict(trt_lambda=-0.1), dict(trt_lambda=float("nan")), dict(nx=20000), dict(si_rule=2), dict(si_rule=-1),
+    dict(trt_lambda=-0.1), dict(trt_lambda=float("nan")), dict(si_rule=2), dict(si_rule=-1),
     dict(si_rule=1, max_si_points=1025), dict(si_rule=1, max_si_points=0),
     dict(east=(V.CONVECTIVE, -0.01, 0)), dict(east=(V.CONVECTIVE, float("nan"), 0)), dict(east=(5, 0, 0)),
     dict(max_bodies=64), dict(max_bodies=-1), dict(max_interface_cells=-1), dict(streaming=2), dict(streaming=-1),
 ])
 def test_required_bytes_rejects(kw):
     assert V.required_bytes(base(**kw)) == 0
+
+
+def test_size_limit_is_cells_below_2e31():
+    # populations are indexed in 64 bits, cells (ny * pitch) in 32: a lattice
+    # of 32768 x 65535 (2^31 - 32768 cells, 1.9e10 elements) is accepted, one
+    # more row is not; nx has no limit of its own
+    n = V.required_bytes(base(nx=32768, ny=65535))
+    assert n >= 2 * 9 * 32768 * 65535 * 4
+    assert V.required_bytes(base(nx=32768, ny=65536)) == 0
+    assert V.required_bytes(base(nx=100000, ny=64)) > 0
 
 
 def test_si_rule_interpolated_accepts_up_to_1024_points():
