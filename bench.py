@@ -298,7 +298,12 @@ def run_serve(args, W, nreq=None, steps_range=None, rate=None, budget_gib=None):
     eng.release(h)
     budget = int(budget_gib * 2 ** 30)
     server = Server(eng, budget, chunk=args.chunk, policy=args.policy, saturate_cells=args.saturate_cells)
-    served = summarize(server.run(items))
+
+    def progress(done, total, t):
+        if done % 25 == 0 or done == total:
+            print(f"[serve] {done}/{total} requests finished at {t:.1f} s", file=sys.stderr, flush=True)
+
+    served = summarize(server.run(items, progress=progress))
     served["peak_resident_bytes"] = server.peak_bytes
     served["peak_resident"] = server.peak_resident
     out = {

@@ -170,10 +170,12 @@ size_t vplbm_required_bytes(const vplbm_params *p);
 int vplbm_create(const vplbm_params *p, void *dev_mem, size_t dev_bytes, void *hip_stream,
                  vplbm_lattice **out);
 /* Release a lattice (waits for its stream; frees the device buffer only if
- * the library allocated it).  VPLBM_EINVAL for NULL. */
+ * the library allocated it).  VPLBM_EINVAL for NULL.  Resource handling of
+ * this library, not a step of the paper's method. */
 int vplbm_destroy(vplbm_lattice *lat);
 /* Message of the last failed call on the handle; with lat == NULL, the
- * message of the last failed vplbm_create on the calling thread. */
+ * message of the last failed vplbm_create on the calling thread (error
+ * reporting of this library, not part of the method). */
 const char *vplbm_last_error(const vplbm_lattice *lat);
 
 /* Set the populations to f^eq(rho, u) (second-order equilibrium, Sec. 2.2):
@@ -272,27 +274,34 @@ int vplbm_set_si_points_body(vplbm_lattice *lat, int body, const double *xy, con
  * and the penalized velocity u for vplbm_read_macro.  VPLBM_EINVAL for
  * nsteps < 0; nsteps = 0 does nothing. */
 int vplbm_step(vplbm_lattice *lat, int nsteps, int flags);
-/* Same as vplbm_step, for measurement: HIP events bracket every launch of
- * the fused step kernel on the lattice's stream; on return (the stream is
- * synchronized) *kernel_ms holds the summed duration of those launches in
- * milliseconds. */
+/* Same as vplbm_step (the update of Sec. 2.2 with Eqs. updatestep..
+ * updatestepm and the forces of Sec. 2.3), for measurement: HIP events
+ * bracket every launch of the fused step kernel on the lattice's stream; on
+ * return (the stream is synchronized) *kernel_ms holds the summed duration
+ * of those launches in milliseconds.  The timing is this library's
+ * instrumentation; the paper reports no kernel times. */
 int vplbm_step_timed(vplbm_lattice *lat, int nsteps, int flags, double *kernel_ms);
-/* Wait for the lattice's queued work and publish the last step's forces.
+/* Wait for the lattice's queued work and publish the last step's forces
+ * (Sec. 2.3.1 and 2.3.2: the sums the next step would otherwise make).
  * Returns VPLBM_EUNSTABLE once a step met a non-finite density,
- * VPLBM_ENOSAMPLE when a moving body's point lost its sample node, VPLBM_EHIP
+ * VPLBM_ENOSAMPLE when a moving body's point lost its sample node (the
+ * sampling of Sec. 2.3.2 needs a fluid node along the normal), VPLBM_EHIP
  * for a kernel fault. */
 int vplbm_sync(vplbm_lattice *lat);
-/* Steps taken since the last initialization (-1 for NULL). */
+/* Steps taken since the last initialization (-1 for NULL): the time index
+ * n of Sec. 2.2 (dt = 1). */
 long long vplbm_step_count(const vplbm_lattice *lat);
-/* Workgroup tile of the step kernel, bx cells along x times by rows:
- * 64x1, 64x2, 64x4, 128x1, 128x2 or 256x1.  The default is 64x4, or 128x2
- * when the two population buffers exceed 1 GiB (FP64: 256 MB).
- * Results do not depend on it, forces included: they are summed per
- * interface cell and per sample record, in an order fixed at geometry
- * set-up.  A lattice with VPLBM_STREAM_AA accepts 64x4 only (VPLBM_EINVAL
- * otherwise).  Batched launches use 64x4 tiles whatever this setting. */
+/* Workgroup tile of the step kernel (an execution choice, not one the
+ * paper makes), bx cells along x times by rows: 64x1, 64x2, 64x4, 128x1,
+ * 128x2 or 256x1.  The default is 64x4, or 128x2 when the two population
+ * buffers exceed 1 GiB (FP64: 256 MB).  Results do not depend on it, forces
+ * included: they are summed per interface cell and per sample record, in an
+ * order fixed at geometry set-up.  A lattice with VPLBM_STREAM_AA or with
+ * moving disks accepts 64x4 only (VPLBM_EINVAL otherwise).  Batched launches
+ * use the batch's own tile (vplbm_batch_set_tile), not this setting. */
 int vplbm_set_tile(vplbm_lattice *lat, int bx, int by);
-/* The tile the lattice's own steps use (*bx cells along x, *by rows). */
+/* The tile the lattice's own steps use (*bx cells along x, *by rows; see
+ * vplbm_set_tile). */
 int vplbm_get_tile(const vplbm_lattice *lat, int *bx, int *by);
 
 /* Forces of the last step on body 1, out = (Fx, Fy, Tz), torque about the
@@ -328,45 +337,53 @@ int vplbm_get_body_state_of(vplbm_lattice *lat, int body, vplbm_body_state *out)
  * the last step, which must have been run with VPLBM_STEP_MACRO
  * (VPLBM_ESTATE otherwise); host arrays [ny][nx], caller-owned. */
 int vplbm_read_macro(vplbm_lattice *lat, double *rho, double *ux, double *uy);
-/* The same into caller-owned device arrays [ny][nx] of the compute type (double
- * for VPLBM_F64, float for VPLBM_F32 and VPLBM_F16DEV), asynchronously on the
- * lattice's stream (no host transfer). */
+/* The same (Eqs. updatestep, updatestepm) into caller-owned device arrays
+ * [ny][nx] of the compute type (double for VPLBM_F64, float for VPLBM_F32 and
+ * VPLBM_F16DEV), asynchronously on the lattice's stream (no host transfer). */
 int vplbm_read_macro_device(vplbm_lattice *lat, void *rho, void *ux, void *uy);
-/* The same restricted to the window of w columns from x0 and h rows from y0
- * (host arrays [h][w]); VPLBM_EINVAL if it leaves the lattice. */
+/* The same (Eqs. updatestep, updatestepm) restricted to the window of w
+ * columns from x0 and h rows from y0 (host arrays [h][w]); VPLBM_EINVAL if
+ * it leaves the lattice. */
 int vplbm_read_macro_window(vplbm_lattice *lat, int x0, int y0, int w, int h, double *rho, double *ux,
                             double *uy);
 /* Post-collision populations f_a = w_a rho0 + d_a of the last step (or of the
- * initialization) as host doubles [9][ny][nx], in either storage mode. */
+ * initialization) as host doubles [9][ny][nx], in either storage mode: the
+ * D2Q9 distributions of Sec. 2.2 after the collision of Eq. TRT. */
 int vplbm_read_populations(vplbm_lattice *lat, double *f);
-/* The same for a window, host array [9][h][w]. */
+/* The same (Sec. 2.2) for a window, host array [9][h][w]. */
 int vplbm_read_populations_window(vplbm_lattice *lat, int x0, int y0, int w, int h, double *f);
-/* Mask bytes [ny][nx]: bits 0-5 body id (0 = fluid), bit 6
- * stress-integration sample node, bit 7 interface cell (a neighbour has the
- * other phase). */
+/* Mask bytes [ny][nx]: bits 0-5 body id (0 = fluid; chi of Eq. fcar is
+ * id != 0), bit 6 stress-integration sample node (Sec. 2.3.2), bit 7
+ * interface cell (a neighbour has the other phase: the cells whose links
+ * enter the momentum exchange of Sec. 2.3.1). */
 int vplbm_read_mask(vplbm_lattice *lat, uint8_t *out);
 
 /* ---- batches --------------------------------------------------------------
- * A batch steps several lattices with one launch of the fused step kernel per
- * time step: the tiles of all active lattices are laid end to end and each
- * workgroup finds its lattice from a device table.  Each lattice computes
- * exactly what vplbm_step would (the same per-cell arithmetic and reduction
- * order, whatever its own tile: batched launches run 64x4 tiles), so its
- * results do not depend on what else is in the batch.  Moving disks add one
- * body kernel per step (one workgroup per moving lattice).  Runs of steps
- * are replayed from a captured HIP graph. */
+ * The paper runs one case at a time; batching is an execution choice of
+ * this library.  A batch steps several lattices with one launch of the fused
+ * step kernel per time step (the step of vplbm_step: Sec. 2.2 with Eqs.
+ * updatestep..updatestepm and the forces of Sec. 2.3): the tiles of all
+ * active lattices are laid end to end and each workgroup finds its lattice
+ * from a device table.  Each lattice computes exactly what vplbm_step would
+ * (the same per-cell arithmetic and reduction order, whatever the tile), so
+ * its results do not depend on what else is in the batch; moving disks are
+ * stepped inside the same launch.  Runs of steps are replayed from a
+ * captured HIP graph. */
 typedef struct vplbm_batch vplbm_batch;
 
-/* All lattices must share the precision, the collision (BGK or TRT), the
- * HIP stream and the storage scheme (all VPLBM_STREAM_AB or all
- * VPLBM_STREAM_AA; VPLBM_EINVAL otherwise); a lattice appears once.  The handles stay owned by the caller
- * and must outlive the batch; they must not be stepped concurrently. */
+/* All lattices must share the precision, the collision (BGK or TRT of Eq.
+ * TRT), the HIP stream and the storage scheme (all VPLBM_STREAM_AB or all
+ * VPLBM_STREAM_AA; VPLBM_EINVAL otherwise); a lattice appears once.  The
+ * handles stay owned by the caller and must outlive the batch; they must not
+ * be stepped concurrently.  Destroy releases the batch's tables and graph;
+ * last_error gives the message of its last failed call. */
 int vplbm_batch_create(vplbm_lattice *const *lats, int n, vplbm_batch **out);
 int vplbm_batch_destroy(vplbm_batch *b);
 const char *vplbm_batch_last_error(const vplbm_batch *b);
-/* Advance lattice k by nsteps[k] steps (0 = idle); asynchronous.  Lattices
- * with steps left run together; a lattice drops out when its count is
- * reached.  Forces, histories and states are read per lattice afterwards. */
+/* Advance lattice k by nsteps[k] steps of Sec. 2.2 (0 = idle);
+ * asynchronous.  Lattices with steps left run together; a lattice drops out
+ * when its count is reached.  Forces (Sec. 2.3), histories and states are
+ * read per lattice afterwards. */
 int vplbm_batch_step(vplbm_batch *b, const int *nsteps);
 /* Replace the lattices of a batch (the rules of vplbm_batch_create; the
  * same precision, collision, stream and storage as the batch's first
@@ -386,7 +403,7 @@ int vplbm_batch_get_tile(const vplbm_batch *b, int *bx, int *by);
  * capture, tight serving loops, harnesses that forbid hipMalloc): the work
  * of vplbm_batch_step on lats[0..n) with nsteps[k] steps each, with 64x4
  * tiles and direct launches (no graph), without allocating anything.  Its
- * tables (lattice descriptors, moving list, the lattice of every tile) live
+ * tables (lattice descriptors, the lattice of every tile) live
  * in one static device array of the library, about 4.1 MiB per GPU, held
  * until the process ends; limits: n <= 256 lattices, 2^20 tiles of 64x4
  * cells in all (VPLBM_EINVAL beyond, message on lats[0]).  The lattices obey

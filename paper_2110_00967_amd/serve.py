@@ -151,8 +151,9 @@ class Server:
                 break
         return n
 
-    def run(self, items) -> List[Request]:
-        """items: iterable of (rid, arrival_s, case, steps). Returns the requests."""
+    def run(self, items, progress: Optional[Callable[[int, int, float], None]] = None) -> List[Request]:
+        """items: iterable of (rid, arrival_s, case, steps). Returns the requests.
+        progress(finished, total, t) is called after every request that finishes."""
         reqs = [Request(rid, float(t), case, int(n)) for rid, t, case, n in items]
         for r in reqs:
             r.nbytes = self.engine.nbytes(r.case)
@@ -201,6 +202,8 @@ class Server:
                     r.handle = None
                     used -= r.nbytes
                     self.events.append((t, "finish", r.rid))
+                    if progress:
+                        progress(sum(1 for e in self.events if e[1] == "finish"), len(reqs), t)
                 else:
                     still.append(r)
             resident = still

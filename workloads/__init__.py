@@ -375,8 +375,13 @@ def serving_case(req: dict) -> Case:
 
     Airfoil: NACA 0012 with chord nx/10, leading edge at (3c, ny/2), inflow
     0.05, tau = 0.6, free-slip sides.  Sedimentation: disk of diameter nx/20
-    starting 2.5 diameters below the top at x0*nx, density ratio 1.5, small
-    gravity (1e-5) so it stays inside the lattice over the requested steps.
+    starting 2.5 diameters below the top at x0*nx, density ratio 1.5, gravity
+    at most 1e-5 and small enough that the disk stays inside the lattice over
+    the requested steps: a low-Reynolds estimate of its terminal velocity,
+    U ~ 0.05 g (rho_r - 1) d^2 / nu (calibrated on case_sedimentation; it
+    overestimates U as the Reynolds number grows, underestimates it by up
+    to 2x at the smallest grid), is held to a quarter of the room below the
+    start divided by the steps.
     """
     nx, ny = req["nx"], req["ny"]
     if req["kind"] == "airfoil":
@@ -389,8 +394,11 @@ def serving_case(req: dict) -> Case:
                     north=Edge(FREESLIP), u_init=(0.05, 0.0), polygon=poly, ref_point=(cx, cy), si_xy=xy,
                     si_n=n, si_ds=ds, length_scale=chord, u_ref=0.05)
     d = nx / 20.0
-    return case_sedimentation(nx=nx, ny=ny, d=d, rho_r=1.5, g=1e-5, x0_frac=req["x0"], y0=ny - 2.5 * d,
-                              npts=64)
+    y0 = ny - 2.5 * d
+    nu = (0.6 - 0.5) / 3.0
+    room = y0 - 3.0 * d
+    g = min(1e-5, 0.25 * room / req["steps"] * nu / (0.05 * 0.5 * d * d))
+    return case_sedimentation(nx=nx, ny=ny, d=d, rho_r=1.5, g=g, x0_frac=req["x0"], y0=y0, npts=64)
 
 
 def serving_items(reqs):
