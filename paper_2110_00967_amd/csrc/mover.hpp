@@ -19,7 +19,7 @@
 namespace vp {
 
 // Width of the force sums' order: FIN_W virtual lanes, lane v summing terms
-// v, v + FIN_W, ...; each virtual wave of 64 lanes reduced by a butterfly,
+// v, v + FIN_W, ...; each virtual wave of 64 lanes reduced by wave_sum_f64,
 // the FIN_W / 64 wave sums added in order.  Every workgroup size runs the
 // same order (a block of NT threads takes the virtual waves w, w + NT/64,
 // ... with its waves w).
@@ -56,6 +56,32 @@ struct DiskSetRef {
 
 __device__ __forceinline__ long long fixq_of(double v) { return llround(v * FIXQ); }
 
+// x of the lane that DPP control `ctrl` selects (both halves of the double)
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                          __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+
+// Sum of x over the 64 lanes of a wave, in one fixed order, the same in
+// every lane: within each row of 16 lanes, lanes paired by swapping
+// neighbours, then pairs, then the two halves of each group of 8 (mirrored),
+// then the two halves of the row (mirrored) -- every step adds two equal-sized
+// partial sums, so all lanes of a row hold the same bits; then the four row
+// sums (r0 + r1) + (r2 + r3).  Data-parallel-primitive moves instead of LDS
+// permutes keep the chain short.
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+  x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+  x += dpp_f64<0x141>(x);  // row_half_mirror
+  x += dpp_f64<0x140>(x);  // row_mirror
+  return (readlane_f64(x, 0) + readlane_f64(x, 16)) + (readlane_f64(x, 32) + readlane_f64(x, 48));
+}
+
 // lower corner of the (2 h + 1)^2-cell window of a disk at state B
 __device__ __forceinline__ void mover_origin(const BodyDev &B, int h, int &ox, int &oy) {
   ox = (int)floor(B.x) - h;
@@ -79,9 +105,9 @@ __device__ __forceinline__ void mover_tile_box(const BodyDev &B, int h, int &tx0
 // (Fx, Fy, torque), F[3..5] stress integration, from the tile partials of
 // that step's window (part, slot (ty - ty0) * M.ptx + (tx - tx0)), tiles
 // outside the lattice skipped.  One fixed order whatever the workgroup size:
-// FIN_W virtual lanes, lane v taking slots v, v + FIN_W, ...; a butterfly per
-// virtual wave of 64, the wave sums added in order.  Every thread returns the
-// same six sums.  lds: FIN_WAVES * 6 doubles.
+// FIN_W virtual lanes, lane v taking slots v, v + FIN_W, ...; a fixed-order
+// sum per virtual wave of 64 (wave_sum_f64), the wave sums added in order.
+// Every thread returns the same six sums.  lds: FIN_WAVES * 6 doubles.
 template <int NT>
 __device__ __forceinline__ void mover_forces(const MoverDev &M, const BodyDev &B, const double *__restrict__ part,
                                              int tiles_x, int tiles_y, double *lds, double (&F)[6]) {
@@ -101,9 +127,7 @@ __device__ __forceinline__ void mover_forces(const MoverDev &M, const BodyDev &B
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      double x = v[i];
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+      const double x = wave_sum_f64(v[i]);
       if (lane == 0) lds[k * 6 + i] = x;
     }
   }

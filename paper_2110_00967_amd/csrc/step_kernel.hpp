@@ -690,7 +690,7 @@ __device__ __forceinline__ bool mover_prologue(int tx, int ty, const StepArgs<T>
 // weighted by the point's stencil weight and ds, contracted with its normal;
 // torque about the disk's centre).  Thread t adds the terms of points t (as
 // mover_prologue placed it, ml.pl[t]), t + NT, ..., then each sum is
-// reduced in one fixed order (a butterfly per wave, the waves in order) and
+// reduced in one fixed order (wave_sum_f64 per wave, the waves in order) and
 // written by thread 0 to the disk's slot of the tile in part.  Uniform over
 // the workgroup (mover_prologue returned true).
 template <typename T, int BX, int BY>
@@ -742,9 +742,7 @@ __device__ __forceinline__ void mover_epilogue(int tx, int ty, const StepArgs<T>
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      double x = v[i];
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+      const double x = wave_sum_f64(v[i]);
       if (lane == 0) ml.red[wave * 6 + i] = x;
     }
     __syncthreads();
