@@ -41,7 +41,8 @@ HBM_PEAK_GBS = 8000.0
 MALL_BYTES = 256 << 20
 BYTES_PER_CELL = {"f64": 9 * 8 * 2 + 1, "f32": 9 * 4 * 2 + 1, "f16dev": 9 * 2 * 2 + 1}
 DTYPE = {"f32": "f32", "f16dev": "f32 (f16 storage)", "f64": "f64"}
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2110_00967_amd", "csrc", f) for f in ("d2q9.hpp", "step_kernel.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2110_00967_amd", "csrc", f)
+                  for f in ("d2q9.hpp", "sample.hpp", "mover.hpp", "step_kernel.hpp")]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -368,12 +369,11 @@ def run_single(args, torch, W, V, workload, precision, steps=None, warmup=None, 
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
     lat, ms_per_step, k_pairs_us = time_single(args, torch, V, case, precision, steps, warmup, tile)
     mlups = cells / (ms_per_step * 1e-3) / 1e6
-    # A static body runs exactly one kernel per step (the fused step kernel;
-    # its forces are summed by the next launch), so the events around the
-    # timed region give that kernel's average duration per launch, launch
-    # gaps included.  A moving body adds its own kernel: use the per-launch
-    # event pairs of the step kernel then.
-    k_us = ms_per_step * 1e3 if case.rho_s is None else k_pairs_us
+    # Every step is exactly one kernel, the fused step kernel (forces are
+    # summed by the next launch; a moving disk advances inside it), so the
+    # events around the timed region give that kernel's average duration per
+    # launch, launch gaps included.
+    k_us = ms_per_step * 1e3
     bpc = BYTES_PER_CELL[precision]
     achieved = bpc * cells / (k_us * 1e-6) / 1e9
     me, si = lat.forces_me(), lat.forces_si()

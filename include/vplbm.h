@@ -393,7 +393,8 @@ int vplbm_batch_step(vplbm_batch *b, const int *nsteps);
  * the batch. */
 int vplbm_batch_set_lattices(vplbm_batch *b, vplbm_lattice *const *lats, int n);
 /* Tile of the batched launches (workgroup shape, not a choice the paper
- * makes): 64x4 (default), 128x2 or 256x1 cells; a batch of AA lattices runs
+ * makes): 64x4 (default), 128x2 or 256x1 cells (with moving disks a batch
+ * runs 64x4 whatever this setting); a batch of AA lattices runs
  * 64x4 only (VPLBM_EINVAL otherwise).  Results do not depend on it (forces
  * are summed per interface cell and sample record in a fixed order). */
 int vplbm_batch_set_tile(vplbm_batch *b, int bx, int by);
@@ -403,8 +404,8 @@ int vplbm_batch_get_tile(const vplbm_batch *b, int *bx, int *by);
  * capture, tight serving loops, harnesses that forbid hipMalloc): the work
  * of vplbm_batch_step on lats[0..n) with nsteps[k] steps each, with 64x4
  * tiles and direct launches (no graph), without allocating anything.  Its
- * tables (lattice descriptors, the lattice of every tile) live
- * in one static device array of the library, about 4.1 MiB per GPU, held
+ * tables (lattice descriptors, the lattice of every block of 64 tiles) live
+ * in one static device array of the library, 210 KiB per GPU, held
  * until the process ends; limits: n <= 256 lattices, 2^20 tiles of 64x4
  * cells in all (VPLBM_EINVAL beyond, message on lats[0]).  The lattices obey
  * the rules of vplbm_batch_create and are stepped on their common stream,

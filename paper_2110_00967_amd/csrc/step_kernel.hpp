@@ -1267,42 +1267,100 @@ template <typename T> struct CaseDesc {
   void *ec[2];
 };
 
-// Lattice of every global tile of a batched launch, from the descriptors
-// (tiles of lattice i are [tile0, tile0 + ntiles), in order): one thread per
-// tile, binary search on tile0.
+// The lattice table of a batched launch has one entry per block of
+// TILE_BLOCK consecutive global tiles: the lattice of the block's first tile
+// and the block's tiles that start a lattice.  Some kilobytes for millions
+// of tiles, it stays in the caches while the populations stream past (an
+// entry per tile would be evicted from L2 by every launch, and each
+// workgroup would wait for HBM before its first population load), and the
+// lattice of any tile follows from its block's entry alone, with no further
+// dependent read.
+constexpr int TILE_BLOCK = 64;
+struct BlockCase {
+  int first;                 // lattice of the block's first tile
+  int pad;
+  unsigned long long starts; // bit j (j >= 1): tile j of the block is a lattice's first
+};
+
+// The table from the descriptors (tiles of lattice i are [tile0, tile0 +
+// ntiles), in order, ntiles >= 1): one thread per block, binary search on
+// tile0 for the first tile's lattice, then the lattices starting inside.
 template <typename T>
-__global__ void k_fill_tile_case(const CaseDesc<T> *__restrict__ cases, int ncases, int total,
-                                 int *__restrict__ tile_case) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
+__global__ void k_fill_tile_case(const CaseDesc<T> *__restrict__ cases, int ncases, int nblocks,
+                                 BlockCase *__restrict__ table) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nblocks) return;
+  const int t = k * TILE_BLOCK;
   int lo = 0, hi = ncases - 1;  // last lattice with tile0 <= t
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (cases[mid].tile0 <= t) lo = mid; else hi = mid - 1;
   }
-  tile_case[t] = lo;
+  unsigned long long starts = 0;
+  for (int c = lo + 1; c < ncases && cases[c].tile0 < t + TILE_BLOCK; ++c) starts |= 1ull << (cases[c].tile0 - t);
+  BlockCase e;
+  e.first = lo;
+  e.pad = 0;
+  e.starts = starts;
+  table[k] = e;
+}
+
+// The lattice of global tile g: its block's first lattice plus the lattices
+// that start at tiles 1..j of the block (j = g's place in it).
+__device__ __forceinline__ int tile_lattice(const BlockCase *__restrict__ table, int g) {
+  const BlockCase e = table[g / TILE_BLOCK];
+  const int j = g % TILE_BLOCK;
+  return e.first + __popcll(e.starts & ((2ull << j) - 2ull));
+}
+
+// p as a global-memory pointer: pointers read from a descriptor in memory
+// would otherwise be generic, and every access through them a flat access
+// (slower to issue, and counted against both the vector-memory and the
+// scalar wait counters)
+template <typename U> __device__ __forceinline__ U *gp(U *p) {
+  // rebuilt from its (uniform) bits, so that the compiler cannot fold the
+  // global view away again
+  const uintptr_t x = (uintptr_t)p;
+  const uintptr_t lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
+  const uintptr_t hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(x >> 32));
+  return (U *)(VP_GLOBAL char *)((hi << 32) | lo);
+}
+
+// The description's pointers as global pointers.
+template <typename T> __device__ __forceinline__ void global_ptrs(StepArgs<T> &P) {
+  P.bodies = gp(P.bodies);
+  P.cbc = gp(P.cbc);
+  P.ec_in = gp(P.ec_in);
+  P.ec_out = gp(P.ec_out);
+  P.mov = gp(P.mov);
+  P.pts = gp(P.pts);
 }
 
 // Batched step: launch number `flip` (0 or 1, alternating) of a run over
-// ncases lattices; the lattice of each tile comes from the tile table.
+// ncases lattices; the lattice of each tile comes from the lattice table.
 // MOV: some lattice of the batch has moving disks.
 template <typename S, int BX, int BY, bool TRT, bool MOV = false>
 __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
     k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
-                 const int *__restrict__ tile_case, int total_tiles, int per_xcd, int flip, int first) {
+                 const BlockCase *__restrict__ table, int total_tiles, int per_xcd, int flip, int first) {
   using T = typename Store<S>::T;
   const int b = blockIdx.x;
   const int gtile = (b & 7) * per_xcd + (b >> 3);
   if (gtile >= total_tiles) return;
-  // the lattice of this tile, then its description, read once
-  const CaseDesc<T> *__restrict__ C = cases + tile_case[gtile];
-  const StepArgs<T> P = C->P;
+  // the lattice of this tile, then its description, read once (fields read
+  // unconditionally, so that the reads go out together)
+  const CaseDesc<T> *__restrict__ C = cases + tile_lattice(table, gtile);
+  StepArgs<T> P = C->P;
+  global_ptrs(P);
   const int par = C->cur0 ^ flip, pb = C->pbit0 ^ flip;
-  const int fin_prev = P.nmov ? 0 : (first ? C->pending0 : 1);
-  const int mov_pending = first ? C->mov_pending0 : 1;
-  const S *fin = (const S *)C->buf[par];
-  S *fout = (S *)C->buf[par ^ 1];
-  step_tile<S, BX, BY, false, TRT, 0, MOV>(gtile - C->tile0, fin, fout, C->mask, P, C->ctl, C->recs, C->si_map,
+  const int pend0 = C->pending0, mpend0 = C->mov_pending0;
+  const int fin_prev = P.nmov ? 0 : (first ? pend0 : 1);
+  const int mov_pending = first ? mpend0 : 1;
+  const S *fin = gp((const S *)C->buf[par]);
+  S *fout = gp((S *)C->buf[par ^ 1]);
+  // (the pointers of the force terms serve interface and sample cells only:
+  // read where used)
+  step_tile<S, BX, BY, false, TRT, 0, MOV>(gtile - C->tile0, fin, fout, gp(C->mask), P, C->ctl, C->recs, C->si_map,
                                            C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
                                            fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
                                            mov_pending);
@@ -1316,29 +1374,29 @@ __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
 template <typename S, bool TRT, bool MOV = false>
 __global__ void __launch_bounds__(256, (step_waves_mov<S, MOV>()))
     k_step_batch_aa(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
-                    const int *__restrict__ tile_case, int total_tiles, int per_xcd, int flip, int first) {
+                    const BlockCase *__restrict__ table, int total_tiles, int per_xcd, int flip, int first) {
   using T = typename Store<S>::T;
   const int b = blockIdx.x;
   const int gtile = (b & 7) * per_xcd + (b >> 3);
   if (gtile >= total_tiles) return;
-  const CaseDesc<T> *__restrict__ C = cases + tile_case[gtile];
+  const CaseDesc<T> *__restrict__ C = cases + tile_lattice(table, gtile);
   StepArgs<T> P = C->P;
+  global_ptrs(P);
   const int pb = C->pbit0 ^ flip;
-  P.ec_in = C->ec[pb ^ 1];
-  P.ec_out = C->ec[pb];
-  const int fin_prev = P.nmov ? 0 : (first ? C->pending0 : 1);
-  const int mov_pending = first ? C->mov_pending0 : 1;
-  S *F = (S *)C->buf[0];
+  P.ec_in = gp(C->ec[pb ^ 1]);
+  P.ec_out = gp(C->ec[pb]);
+  const int pend0 = C->pending0, mpend0 = C->mov_pending0;
+  const int fin_prev = P.nmov ? 0 : (first ? pend0 : 1);
+  const int mov_pending = first ? mpend0 : 1;
+  S *F = gp((S *)C->buf[0]);
   if (pb)
-    step_tile<S, 64, 4, false, TRT, 1, MOV>(gtile - C->tile0, nullptr, F, C->mask, P, C->ctl, C->recs, C->si_map,
-                                            C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
-                                            fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
-                                            mov_pending);
+    step_tile<S, 64, 4, false, TRT, 1, MOV>(gtile - C->tile0, nullptr, F, gp(C->mask), P, C->ctl, C->recs, C->si_map,
+                                            C->imap, C->bt, C->me[1], C->me[0], C->sig[1], C->sig[0], fin_prev,
+                                            C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb, mov_pending);
   else
-    step_tile<S, 64, 4, false, TRT, 2, MOV>(gtile - C->tile0, nullptr, F, C->mask, P, C->ctl, C->recs, C->si_map,
-                                            C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
-                                            fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
-                                            mov_pending);
+    step_tile<S, 64, 4, false, TRT, 2, MOV>(gtile - C->tile0, nullptr, F, gp(C->mask), P, C->ctl, C->recs, C->si_map,
+                                            C->imap, C->bt, C->me[0], C->me[1], C->sig[0], C->sig[1], fin_prev,
+                                            C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb, mov_pending);
 }
 
 template <int NT>

@@ -1945,7 +1945,7 @@ struct vplbm_batch {
   int bx = 64, by = 4;  // tile of the batched launches
   char *desc_dev = nullptr;
   int ncap = 0;                  // descriptors the device table holds
-  int *tile_case_dev = nullptr;  // lattice index of every global tile
+  BlockCase *tile_case_dev = nullptr;  // lattice table: one entry per block of TILE_BLOCK global tiles
   long long tile_case_cap = 0;
   std::vector<char> desc_host;
   hipGraphExec_t graph = nullptr;  // groups of launch pairs (parities 1, 0) of the current active set
@@ -1982,8 +1982,8 @@ struct BatchExec {
   int bx = 64, by = 4;
   hipStream_t stream = nullptr;
   char *desc_dev = nullptr;   // descriptors, one per active lattice
-  int *tile_dev = nullptr;    // lattice of every global tile
-  long long tile_cap = 0;
+  BlockCase *tile_dev = nullptr;  // lattice table (one entry per TILE_BLOCK global tiles)
+  long long tile_cap = 0;     // global tiles it has room for
   char *desc_host = nullptr;  // host staging, room for every lattice
   hipStream_t cap_stream = nullptr;  // graph capture (null: direct launches only)
   hipGraphExec_t *graph = nullptr;
@@ -2077,7 +2077,7 @@ void launch_batch_s(const BatchExec &X, hipStream_t st, int total, int flip, int
       launch_batch_aa<S, false>(X, st, grid, total, per, flip, first);
   } else if (X.mov) {
     launch_batch_ab<S, 64, 4, true>(X, st, grid, total, per, flip, first);
-  } else if (X.bx == 128) {
+  } else if (X.bx == 128 && X.by == 2) {
     launch_batch_ab<S, 128, 2, false>(X, st, grid, total, per, flip, first);
   } else if (X.bx == 256) {
     launch_batch_ab<S, 256, 1, false>(X, st, grid, total, per, flip, first);
@@ -2094,22 +2094,25 @@ void launch_batch(const BatchExec &X, hipStream_t st, int total, int flip, int f
   }
 }
 
-// the tile table (lattice of every global tile) from the descriptors just
-// uploaded, on the device
+// entries of the lattice table for `tiles` global tiles
+long long table_entries(long long tiles) { return (tiles + TILE_BLOCK - 1) / TILE_BLOCK; }
+
+// the lattice table from the descriptors just uploaded, on the device
 void launch_fill_tiles(const BatchExec &X, int nact, int total) {
-  const dim3 grid((total + 255) / 256), block(256);
+  const int nblocks = (int)table_entries(total);
+  const dim3 grid((nblocks + 255) / 256), block(256);
   switch (X.prec) {
     case VPLBM_F64:
       hipLaunchKernelGGL((k_fill_tile_case<double>), grid, block, 0, X.stream, (const CaseDesc<double> *)X.desc_dev,
-                         nact, total, X.tile_dev);
+                         nact, nblocks, X.tile_dev);
       break;
     case VPLBM_F32:
       hipLaunchKernelGGL((k_fill_tile_case<float>), grid, block, 0, X.stream, (const CaseDesc<float> *)X.desc_dev,
-                         nact, total, X.tile_dev);
+                         nact, nblocks, X.tile_dev);
       break;
     default:
       hipLaunchKernelGGL((k_fill_tile_case<float>), grid, block, 0, X.stream, (const CaseDesc<float> *)X.desc_dev,
-                         nact, total, X.tile_dev);
+                         nact, nblocks, X.tile_dev);
       break;
   }
 }
@@ -2244,7 +2247,8 @@ constexpr int NOALLOC_MAX_CASES = 256;
 constexpr long long NOALLOC_MAX_TILES = 1 << 20;
 constexpr size_t NOALLOC_DESC_BYTES = (size_t)NOALLOC_MAX_CASES * desc_size<double>();
 constexpr size_t NOALLOC_TILE_OFF = (NOALLOC_DESC_BYTES + 255) / 256 * 256;
-constexpr size_t NOALLOC_BYTES = NOALLOC_TILE_OFF + (size_t)NOALLOC_MAX_TILES * sizeof(int);
+constexpr size_t NOALLOC_BYTES = NOALLOC_TILE_OFF + (size_t)(NOALLOC_MAX_TILES / TILE_BLOCK) * sizeof(BlockCase);
+static_assert(NOALLOC_MAX_TILES % TILE_BLOCK == 0, "whole table blocks");
 static_assert(desc_size<double>() >= desc_size<float>() && desc_size<double>() >= desc_size<__half>(),
               "descriptor slots sized for the largest descriptor");
 
@@ -2368,7 +2372,8 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
     if (B->graph) (void)hipGraphExecDestroy(B->graph);  // it holds the old table's address
     B->graph = nullptr;
     B->graph_key = -1;
-    rc = B->hip(hipMalloc((void **)&B->tile_case_dev, sizeof(int) * (size_t)need), "tile table");
+    rc = B->hip(hipMalloc((void **)&B->tile_case_dev, sizeof(BlockCase) * (size_t)table_entries(need)),
+                "lattice table");
     if (rc) return rc;
     B->tile_case_cap = need;
   }
@@ -2427,7 +2432,7 @@ int vplbm_batch_step_noalloc(vplbm_lattice *const *lats, int n, const int *nstep
   X.aa = L0->aa();
   X.stream = L0->stream;
   X.desc_dev = base;
-  X.tile_dev = (int *)(base + NOALLOC_TILE_OFF);
+  X.tile_dev = (BlockCase *)(base + NOALLOC_TILE_OFF);
   X.tile_cap = NOALLOC_MAX_TILES;
   X.desc_host = (char *)g_noalloc_desc_host;
   std::string err;

@@ -262,6 +262,39 @@ def test_batch_rejects_mixed_storage():
 
 
 @pytest.mark.parametrize("precision", ["f32", "f16dev"])
+def test_batch_of_many_tiny_lattices_equals_alone(precision):
+    # 70 lattices of one to three 64x4 tiles each: a block of the lattice
+    # table (64 global tiles) spans dozens of lattices, the last ones only
+    # partly; some hold a disk (their tile 0 sums the forces), the step counts
+    # differ, so the active set and the table change from chunk to chunk
+    from paper_2110_00967_amd import vplbm as V
+    rng = np.random.default_rng(11)
+    specs = []
+    for k in range(70):
+        nx, ny = int(rng.integers(8, 150)), int(rng.integers(4, 9))
+        if k % 7 == 3:
+            ny = 12
+            specs.append(spec(nx, ny, tau=0.7, disk=(nx / 2.0, 6.0, 2.5), init=("fields",) + random_fields(nx, ny, k)))
+        else:
+            specs.append(spec(nx, ny, tau=0.6 + 0.003 * k, init=("fields",) + random_fields(nx, ny, k)))
+    nsteps = [int(v) for v in rng.integers(0, 12, len(specs))]
+    say("batch of", len(specs), "tiny lattices,", precision, "steps", nsteps[:10], "...")
+    solo = [build_gpu(s, precision) for s in specs]
+    for g, n in zip(solo, nsteps):
+        step_eager(g, n)
+    lats = [build_gpu(s, precision) for s in specs]
+    b = V.Batch(lats)
+    b.step(nsteps)
+    for k, (g, ref) in enumerate(zip(lats, solo)):
+        got, want = (state(g), state(ref)) if specs[k]["disk"] else ((g.populations(),), (ref.populations(),))
+        for x, y in zip(got, want):
+            assert np.array_equal(x, y), k
+    b.close()
+    for g in lats + solo:
+        g.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16dev"])
 def test_batch_tiles_give_the_same_bits(precision):
     # the tile of the batched launches (vplbm_batch_set_tile) changes the
     # workgroup shape only: every tile gives the 64x4 result bit for bit,
@@ -294,7 +327,7 @@ def test_batch_tile_rules():
     lats = [build_gpu(s, "f32") for s in specs]
     b = V.Batch(lats)
     assert b.tile == (64, 4)
-    for bad in ((64, 2), (32, 8), (128, 4)):
+    for bad in ((64, 2), (32, 8), (128, 4), (64, 8)):
         with pytest.raises(V.VplbmError) as e:
             b.set_tile(*bad)
         assert e.value.code == V.EINVAL
