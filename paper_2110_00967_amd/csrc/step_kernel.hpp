@@ -234,9 +234,10 @@ __device__ __forceinline__ void aa_pull_edge(const S *F, const StepArgs<T> &P, i
   }
 }
 
-// Fast path addressing (interior tiles, where a wave is one aligned run of
-// 64 cells of one row): population a of row `row` at chunk `cw` (both
-// wave-uniform), as a scalar base shifted back one chunk, so that the lane
+// Fast path addressing (interior waves: a wave is one aligned run of 64
+// cells of one row, all with their neighbours inside the lattice):
+// population a of row `row` at chunk `cw` (both wave-uniform), as a scalar
+// base shifted back one chunk, so that the lane
 // offsets lo[s + 1] of the elements at x + s (s = -1, 0, +1, crossing into
 // the neighbouring chunk at the run's ends) are all non-negative.
 template <typename S, typename T>
@@ -256,7 +257,7 @@ __device__ __forceinline__ S *own_base(S *F, const StepArgs<T> &P, int row, int 
 // the cell; odd AA launch (AA = 1) into slot a of x + c_a, dropped when that
 // leaves the lattice (its consumers read the perimeter copy).  A perimeter
 // cell (eidx >= 0) of an AA launch also keeps v in ec_out.  interior: the
-// workgroup-uniform fast-path flag, with the wave's row yw, chunk cw, lane
+// wave-uniform fast-path flag, with the wave's row yw, chunk cw, lane
 // byte offset lb (own cell) and lane offsets lo (see fast_base).
 template <typename S, int AA, typename T>
 __device__ __forceinline__ void put_pop(S *F, const StepArgs<T> &P, bool interior, uint32_t lb,
@@ -756,11 +757,11 @@ __device__ __forceinline__ void mover_epilogue(int tx, int ty, const StepArgs<T>
 }
 
 // One thread's cell of a tile: its place and how its populations are
-// addressed.  A tile's cells all have their 8 neighbours inside the lattice
-// (interior): the workgroup-uniform fast path, where a wave is one run of 64
-// cells of one row (tiles are 64, 128 or 256 cells wide), so its row and
-// chunk are scalars and each population loads from a scalar base
-// (fast_base) + one of three small lane offsets, and stores the same way.
+// addressed.  A wave is one aligned run of 64 cells of one row (tiles are 64,
+// 128 or 256 cells wide), so its row and chunk are scalars; when the run's
+// cells all have their 8 neighbours inside the lattice (interior, decided
+// per wave), each population loads from a scalar base (fast_base) + one of
+// three small lane offsets, and stores the same way.
 struct TileCell {
   int tx, ty, lx, ly, x, y, c, yw, cw;
   bool interior, live;
@@ -783,7 +784,6 @@ __device__ __forceinline__ TileCell tile_cell(int tile, const StepArgs<T> &P) {
   t.ly = threadIdx.x / BX;
   t.x = t.tx * BX + t.lx;
   t.y = t.ty * BY + t.ly;
-  t.interior = (t.tx * BX >= 1) & (t.tx * BX + BX <= P.nx - 1) & (t.ty * BY >= 1) & (t.ty * BY + BY <= P.ny - 1);
   t.live = t.x < P.nx && t.y < P.ny;
   t.c = t.y * P.pitch + t.x;
   const int lane = t.x & 63;
@@ -793,6 +793,11 @@ __device__ __forceinline__ TileCell tile_cell(int tile, const StepArgs<T> &P) {
   t.lo[2] = (uint32_t)((lane < 63 ? lane + CHUNK_ELEMS + 1 : 2 * CHUNK_ELEMS) * sizeof(S));
   t.yw = __builtin_amdgcn_readfirstlane(t.y);
   t.cw = __builtin_amdgcn_readfirstlane(t.x >> 6);
+  // fast path per wave (one aligned run of 64 cells of one row): every cell
+  // of the run and all its neighbours inside the lattice; the waves of an
+  // edge tile whose own run is clear of the edges take it too
+  const int xw = t.cw * 64;
+  t.interior = (xw >= 1) & (xw + 64 <= P.nx - 1) & (t.yw >= 1) & (t.yw <= P.ny - 2);
   return t;
 }
 
@@ -1070,8 +1075,13 @@ __device__ __forceinline__ void step_tile(
   constexpr int NT = BX * BY;
   const TileCell t = tile_cell<S, BX, BY>(tile, P);
 
-  // the streamed populations, loaded first: with moving disks they are in
-  // flight while the disks' states are read
+  // the cell's mask byte, then its streamed populations, loaded first: with
+  // moving disks they are in flight while the disks' states are read.  The
+  // mask goes out before the populations, since 2-byte populations are
+  // converted as they arrive and a load issued after them would wait for
+  // all nine.
+  uint8_t mk = 0;
+  if (!MOV || P.nmov == 0) mk = t.live ? mask[(uint32_t)t.c] : 0;
   T d[Q];
   if (t.live) load_cell<S, AA>(t, fin, fout, P, d);
 
@@ -1101,10 +1111,8 @@ __device__ __forceinline__ void step_tile(
   if (t.live) {
     // the cell's flags: the mask, or for a lattice with moving disks the
     // disks' ids around the cell (its tile ring index sc)
-    uint8_t m = 0;
-    if (!MOV || P.nmov == 0) {
-      m = mask[(uint32_t)t.c];
-    } else if (mwg) {
+    uint8_t m = mk;
+    if (MOV && P.nmov > 0 && mwg) {
       const int sc = (t.ly + 1) * (BX + 2) + t.lx + 1;
       const uint8_t own = ml.sid[sc];
       bool iface = false;
