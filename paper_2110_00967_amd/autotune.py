@@ -183,6 +183,20 @@ def tune(candidates: Iterable[Tile], measure: Callable[[Tile], float], tuner: Ti
     return tuner.record(key, best)
 
 
+def _runs(lat, t: Tile) -> bool:
+    """Whether the lattice accepts tile t (a lattice with moving disks or in
+    the AA pattern runs 64x4 only)."""
+    from . import vplbm as V
+
+    try:
+        lat.set_tile(*t)
+    except V.VplbmError as e:
+        if e.code != V.EINVAL:
+            raise
+        return False
+    return True
+
+
 def tune_lattice(lat, tuner: TileTuner, key: Optional[str] = None, candidates: Optional[Iterable[Tile]] = None,
                  steps: int = 50, warmup: int = 5) -> Tile:
     """Time the tiles on a lattice (it advances by the steps timed) with
@@ -191,7 +205,7 @@ def tune_lattice(lat, tuner: TileTuner, key: Optional[str] = None, candidates: O
 
     aa = lat.params.streaming == V.STREAM_AA
     key = key or lattice_key(lat.params.precision, "AA" if aa else "AB", lat.nx, lat.ny)
-    cands = list(candidates or (AA_TILES if aa else LATTICE_TILES))
+    cands = [t for t in (candidates or (AA_TILES if aa else LATTICE_TILES)) if _runs(lat, t)]
 
     def measure(t: Tile) -> float:
         lat.set_tile(*t)

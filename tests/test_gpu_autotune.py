@@ -61,3 +61,18 @@ def test_tuned_batch_tile_gives_default_bits(tmp_path):
     for a, r in zip(*runs):
         for x, y in zip(a, r):
             assert np.array_equal(x, y)
+
+
+def test_tuning_a_lattice_with_moving_disks_times_its_one_tile(tmp_path):
+    # a lattice with moving disks runs 64x4 only: the tuner times that tile
+    # alone and records it
+    from paper_2110_00967_amd import autotune as AT
+    from paper_2110_00967_amd import vplbm as V
+    import workloads as W
+    say("tune a lattice with a moving disk")
+    g = V.Lattice.from_case(W.case_sedimentation(), precision="f32")
+    tuner = AT.TileTuner(path=str(tmp_path / "tiles.json"))
+    assert AT.tune_lattice(g, tuner, steps=10, warmup=2) == (64, 4)
+    key = AT.lattice_key(g.params.precision, "AB", g.nx, g.ny)
+    assert set(tuner.timings(key)) == {"64x4"} and g.tile == (64, 4)
+    g.close()
