@@ -254,27 +254,42 @@ __device__ __forceinline__ S *own_base(S *F, const StepArgs<T> &P, int row, int 
 
 // Store the post-collision deviation v of population a of cell (x, y):
 // two-buffer (AA = 0) in place; even AA launch (AA = 2) into slot opp(a) of
-// the cell; odd AA launch (AA = 1) into slot a of x + c_a, dropped when that
-// leaves the lattice (its consumers read the perimeter copy).  A perimeter
-// cell (eidx >= 0) of an AA launch also keeps v in ec_out.  interior: the
-// wave-uniform fast-path flag, with the wave's row yw, chunk cw, lane
-// byte offset lb (own cell) and lane offsets lo (see fast_base).
+// the cell.  A perimeter cell (eidx >= 0) of an AA launch also keeps v in
+// ec_out.  interior: the wave-uniform fast-path flag, with the wave's row
+// yw, chunk cw and lane byte offset lb (own cell).
 template <typename S, int AA, typename T>
-__device__ __forceinline__ void put_pop(S *F, const StepArgs<T> &P, bool interior, uint32_t lb,
-                                        const uint32_t (&lo)[3], int yw, int cw, int x, int y, int a, T v,
-                                        int eidx) {
-  if constexpr (AA == 0 || AA == 2) {
-    Store<S>::st_at(own_base(F, P, yw, cw, AA == 0 ? a : opp(a)), lb, v);
-  } else {
-    if (interior) {
-      Store<S>::st_at(fast_base(F, P, yw + cy(a), cw, a), lo[1 + cx(a)], v);
-    } else {
-      const int tx = x + cx(a), ty = y + cy(a);
-      if (tx >= 0 && tx < P.nx && ty >= 0 && ty < P.ny) Store<S>::st(F + pop_index(a, tx, ty, P.pitch), v);
-    }
-  }
+__device__ __forceinline__ void put_pop(S *F, const StepArgs<T> &P, bool interior, uint32_t lb, int yw, int cw,
+                                        int a, T v, int eidx) {
+  static_assert(AA != 1, "odd AA launches store through put_pops_odd");
+  Store<S>::st_at(own_base(F, P, yw, cw, AA == 0 ? a : opp(a)), lb, v);
   if constexpr (AA != 0) {
     if (!interior && eidx >= 0) Store<S>::st((S *)P.ec_out + (a * P.nper + eidx), v);
+  }
+}
+
+// The nine post-collision deviations v of an odd AA launch, each into slot a
+// of x + c_a (dropped when that leaves the lattice: its consumers read the
+// perimeter copy, which a perimeter cell, eidx >= 0, keeps in ec_out).  They
+// are stored together after the collision, in one wave-uniform branch: an
+// interior wave from the bases of rows yw - 1, yw, yw + 1 computed once, plus
+// the lane offsets lo (see fast_base).  Stores interleaved with the
+// collision, each behind its own branch, recomputed a row base per store.
+template <typename S, typename T>
+__device__ __forceinline__ void put_pops_odd(S *F, const StepArgs<T> &P, bool interior, const uint32_t (&lo)[3],
+                                             int yw, int cw, int x, int y, const T (&v)[Q], int eidx) {
+  if (interior) {
+    S *rb[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) rb[r] = fast_base(F, P, yw - 1 + r, cw, 0);
+#pragma unroll
+    for (int a = 0; a < Q; ++a) Store<S>::st_at(rb[1 + cy(a)] + a * 64, lo[1 + cx(a)], v[a]);
+  } else {
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+      const int tx = x + cx(a), ty = y + cy(a);
+      if (tx >= 0 && tx < P.nx && ty >= 0 && ty < P.ny) Store<S>::st(F + pop_index(a, tx, ty, P.pitch), v[a]);
+      if (eidx >= 0) Store<S>::st((S *)P.ec_out + (a * P.nper + eidx), v[a]);
+    }
   }
 }
 
@@ -890,6 +905,7 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
 
   const T uu15 = T(1.5) * (ux * ux + uy * uy);
   const T uF3 = T(3) * (ux * Fx + uy * Fy);
+  T ov[Q];  // odd AA launch: the results, stored together after the collision
   {
     // Collision with the forcing term (Eqs. TRT and eqBd; BGK is tau- =
     // tau+), per pair (a, a') with c_a' = -c_a.  Since 1 - 1/(2 tau) =
@@ -905,8 +921,11 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
     // keeps the FP32 rounding of mass and momentum unbiased.
     const T C1 = drho - rho * uu15 - P.fo * uF3;
     const T R45 = T(4.5) * rho, R3 = T(3) * rho;
-    put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, 0, d[0] - P.omega * (d[0] - T(wgt(0)) * C1),
-                   eidx);
+    const T o0 = d[0] - P.omega * (d[0] - T(wgt(0)) * C1);
+    if constexpr (AA == 1)
+      ov[0] = o0;
+    else
+      put_pop<S, AA>(fout, P, tile_interior, lb, yw, cw, 0, o0, eidx);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int a = k < 2 ? k + 1 : k + 3;  // 1, 2, 5, 6; a' = 3, 4, 7, 8
@@ -926,10 +945,16 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
         oa = d[a] - P.omega * se - P.omega_m * so;
         oo = d[o] - P.omega * se + P.omega_m * so;
       }
-      put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, a, oa, eidx);
-      put_pop<S, AA>(fout, P, tile_interior, lb, lo, yw, cw, x, y, o, oo, eidx);
+      if constexpr (AA == 1) {
+        ov[a] = oa;
+        ov[o] = oo;
+      } else {
+        put_pop<S, AA>(fout, P, tile_interior, lb, yw, cw, a, oa, eidx);
+        put_pop<S, AA>(fout, P, tile_interior, lb, yw, cw, o, oo, eidx);
+      }
     }
   }
+  if constexpr (AA == 1) put_pops_odd<S>(fout, P, tile_interior, lo, yw, cw, x, y, ov, eidx);
   if (MACRO) {
     mrho[(uint32_t)c] = rho;
     mux[(uint32_t)c] = ux;
