@@ -426,6 +426,27 @@ def copy_calibration(torch):
     return cal
 
 
+def copy_ceiling(torch, nbytes=2 << 30, launches=10):
+    """The HBM ceiling a plain streaming kernel reaches on this GPU: torch's
+    elementwise add over float32 (read nbytes, write nbytes per launch),
+    far beyond the Infinity Cache, HIP events around `launches` launches."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.add(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    c0, c1 = events(torch)
+    c0.record()
+    for _ in range(launches):
+        torch.add(src, 1.0, out=dst)
+    c1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * launches / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"kernel": "torch.add, float32, read n + write n bytes", "bytes_per_launch": 2 * nbytes,
+            "launches": launches, "GBps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def brief(d):
     """The figures of a sub-run that go into the headline line's extra keys."""
     r = d["roofline"]
@@ -546,6 +567,8 @@ def main():
         extras["serving_bounded"] = {"config": sv["config"], **sv["serving"],
                                      "note": "48 requests, steps 1e3-1e4 (C5 shape, 1/10 the steps); "
                                              "the full trace runs with --workload serve"}
+        say("copy ceiling")
+        extras["copy_ceiling"] = copy_ceiling(torch)
         out["extras"] = extras
     if args.copy_calibration:
         out["copy_calibration"] = copy_calibration(torch)
