@@ -111,6 +111,9 @@ __device__ __forceinline__ void mover_tile_box(const BodyDev &B, int h, int &tx0
 template <int NT>
 __device__ __forceinline__ void mover_forces(const MoverDev &M, const BodyDev &B, const double *__restrict__ part,
                                              int tiles_x, int tiles_y, double *lds, double (&F)[6]) {
+  // force and geometry arithmetic: no multiply-add fusion, so that every kernel
+  // that inlines this (alone, batched, any tile) rounds it the same way
+  #pragma clang fp contract(off)
   static_assert(NT % 64 == 0, "whole waves");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int tx0, ty0, ntx, nty;
@@ -147,6 +150,9 @@ __device__ __forceinline__ void mover_forces(const MoverDev &M, const BodyDev &B
 // velocities.  Each operation rounded on its own (no contraction), in the
 // order of the plain formulas.
 __device__ __forceinline__ BodyDev mover_update(const MoverDev &M, const BodyDev &B, const double (&F)[6]) {
+  // force and geometry arithmetic: no multiply-add fusion, so that every kernel
+  // that inlines this (alone, batched, any tile) rounds it the same way
+  #pragma clang fp contract(off)
   BodyDev S = B;
   if (M.mode == MODE_FREE) {
     const bool si = M.source != 0;

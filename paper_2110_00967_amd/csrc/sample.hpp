@@ -72,6 +72,9 @@ __device__ __forceinline__ int si_node(const Solid &solid, int nx, int ny, doubl
 template <typename Solid>
 __device__ __forceinline__ int si_stencil(const Solid &solid, int nx, int ny, int rule, double px, double py,
                                           double n0, double n1, int (&node)[4], double (&w)[4]) {
+  // force and geometry arithmetic: no multiply-add fusion, so that every kernel
+  // that inlines this (alone, batched, any tile) rounds it the same way
+  #pragma clang fp contract(off)
   if (rule == 1) {
     const double qx = __dadd_rn(px, __dmul_rn(1.5, n0)), qy = __dadd_rn(py, __dmul_rn(1.5, n1));
     const int i0 = (int)floor(qx), j0 = (int)floor(qy);
@@ -98,6 +101,9 @@ __device__ __forceinline__ int si_stencil(const Solid &solid, int nx, int ny, in
 // current state; co, sn = cos, sin of its angle)
 __device__ __forceinline__ void si_place(double a, double b, double c, double d, int moving, const BodyDev &B,
                                          double co, double sn, double &px, double &py, double &n0, double &n1) {
+  // force and geometry arithmetic: no multiply-add fusion, so that every kernel
+  // that inlines this (alone, batched, any tile) rounds it the same way
+  #pragma clang fp contract(off)
   if (!moving) {
     px = a; py = b; n0 = c; n1 = d;
     return;

@@ -346,6 +346,9 @@ __device__ __forceinline__ void finalize_block(const double *__restrict__ me, co
                                                Ctl *__restrict__ ctl, double *__restrict__ hist, int cap, int maxb,
                                                double *lds, double *out0 = nullptr,
                                                const FinPre *pre = nullptr) {
+  // force and geometry arithmetic: no multiply-add fusion, so that every kernel
+  // that inlines this (alone, batched, any tile) rounds it the same way
+  #pragma clang fp contract(off)
   static_assert(NT % 64 == 0, "whole waves");
   const long long n = ctl->step + 1;
   const int nb = ctl->nbody;
@@ -488,6 +491,9 @@ template <typename T, int BX, int BY>
 __device__ __forceinline__ int place_point(const StepArgs<T> &P, const MovLds<BX, BY> &ml, const DiskSetRef &cur,
                                            int k, double a, double b, double c, double d, double ds, int x0, int y0,
                                            PtPlace &pp) {
+  // force and geometry arithmetic: no multiply-add fusion, so that every kernel
+  // that inlines this (alone, batched, any tile) rounds it the same way
+  #pragma clang fp contract(off)
   const BodyDev S = ml.st[k];
   double px, py, n0, n1;
   si_place(a, b, c, d, 1, S, ml.cs[k][0], ml.cs[k][1], px, py, n0, n1);
@@ -518,6 +524,9 @@ __device__ __forceinline__ int place_point(const StepArgs<T> &P, const MovLds<BX
 // tile (stress ml.sg): force s (sigma . n), torque r x that force.
 template <int BX, int BY>
 __device__ __forceinline__ void point_terms(const PtPlace &pp, const MovLds<BX, BY> &ml, double (&v)[6]) {
+  // force and geometry arithmetic: no multiply-add fusion, so that every kernel
+  // that inlines this (alone, batched, any tile) rounds it the same way
+  #pragma clang fp contract(off)
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (pp.in & (1 << q)) {
@@ -577,6 +586,9 @@ __device__ __forceinline__ bool mover_prologue(int tx, int ty, const StepArgs<T>
                                                const double *__restrict__ part_prev, double *__restrict__ hist,
                                                int cap, int maxb, int pb, int pending, bool known,
                                                MovLds<BX, BY> &ml) {
+  // force and geometry arithmetic: no multiply-add fusion, so that every kernel
+  // that inlines this (alone, batched, any tile) rounds it the same way
+  #pragma clang fp contract(off)
   constexpr int NT = BX * BY;
   static_assert(BX == MOV_BX && BY == MOV_BY, "moving disks run the tile of their partials");
   const int x0 = tx * BX, y0 = ty * BY;
@@ -713,6 +725,9 @@ template <typename T, int BX, int BY>
 __device__ __forceinline__ void mover_epilogue(int tx, int ty, const StepArgs<T> &P, const double (&acc)[3], int bid,
                                                const double (&sg)[3], double *__restrict__ part,
                                                MovLds<BX, BY> &ml) {
+  // force and geometry arithmetic: no multiply-add fusion, so that every kernel
+  // that inlines this (alone, batched, any tile) rounds it the same way
+  #pragma clang fp contract(off)
   constexpr int NT = BX * BY, NW = NT / 64;
   static_assert(NW <= FIN_WAVES, "one partial per wave in ml.red");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -962,6 +977,7 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
   }
 
   if (m & M_IFACE) {
+#pragma clang fp contract(off)  // (see finalize_block)
     // momentum exchange: every population pulled across the interface;
     // the link's interface point is its midpoint seen from its fluid node.
     // The 8 neighbour masks are loaded all at once (a load inside the
@@ -1049,6 +1065,7 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
     }
   }
   if (m & M_SAMPLE) {
+#pragma clang fp contract(off)  // (see finalize_block)
     // stress of the streamed populations at a (fluid) sample node
     T pxx = T(0), pxy = T(0), pyy = T(0);
 #pragma unroll
@@ -1369,20 +1386,13 @@ template <typename T> __device__ __forceinline__ void global_ptrs(StepArgs<T> &P
   P.pts = gp(P.pts);
 }
 
-// Batched step: launch number `flip` (0 or 1, alternating) of a run over
-// ncases lattices; the lattice of each tile comes from the lattice table.
-// MOV: some lattice of the batch has moving disks.
-template <typename S, int BX, int BY, bool TRT, bool MOV = false>
-__global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
-    k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
-                 const BlockCase *__restrict__ table, int total_tiles, int per_xcd, int flip, int first) {
+// One tile of lattice C in a batched launch: the launch's parities and
+// pending flags from C's description (fields read unconditionally, so that
+// the reads go out together).  SPLIT, win: as in step_tile.
+template <typename S, int BX, int BY, bool TRT, bool MOV, bool SPLIT>
+__device__ __forceinline__ void batch_tile(const CaseDesc<typename Store<S>::T> *__restrict__ C, int tile, int flip,
+                                           int first, bool win) {
   using T = typename Store<S>::T;
-  const int b = blockIdx.x;
-  const int gtile = (b & 7) * per_xcd + (b >> 3);
-  if (gtile >= total_tiles) return;
-  // the lattice of this tile, then its description, read once (fields read
-  // unconditionally, so that the reads go out together)
-  const CaseDesc<T> *__restrict__ C = cases + tile_lattice(table, gtile);
   StepArgs<T> P = C->P;
   global_ptrs(P);
   const int par = C->cur0 ^ flip, pb = C->pbit0 ^ flip;
@@ -1393,10 +1403,51 @@ __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
   S *fout = gp((S *)C->buf[par ^ 1]);
   // (the pointers of the force terms serve interface and sample cells only:
   // read where used)
-  step_tile<S, BX, BY, false, TRT, 0, MOV>(gtile - C->tile0, fin, fout, gp(C->mask), P, C->ctl, C->recs, C->si_map,
-                                           C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
-                                           fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
-                                           mov_pending);
+  step_tile<S, BX, BY, false, TRT, 0, MOV, SPLIT>(tile, fin, fout, gp(C->mask), P, C->ctl, C->recs, C->si_map,
+                                                  C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb],
+                                                  C->sig[pb ^ 1], fin_prev, C->hist, C->cap, C->maxb, nullptr,
+                                                  nullptr, nullptr, pb, mov_pending, win);
+}
+
+// Batched step: launch number `flip` (0 or 1, alternating) of a run over
+// ncases lattices; the lattice of each tile comes from the lattice table.
+// MOV: some lattice of the batch has moving disks.  Then, as in the
+// single-lattice launch, the first nwin workgroups take the tiles of the
+// disks' hit boxes -- window workgroup w: lattice wtab[w] >> 16, slot
+// wtab[w] & 0xFFFF of that lattice's boxes (window_block_tile) -- so that
+// the disks' serial chains start first, and the other workgroups leave those
+// tiles alone.
+template <typename S, int BX, int BY, bool TRT, bool MOV = false>
+__global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
+    k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
+                 const BlockCase *__restrict__ table, int total_tiles, int per_xcd, int flip, int first,
+                 const int *__restrict__ wtab, int nwin) {
+  using T = typename Store<S>::T;
+  const int b = blockIdx.x;
+  const CaseDesc<T> *__restrict__ C;
+  int tile;
+  bool win = false;
+  if (MOV && b < nwin) {
+    // these workgroups share their compute units with plain tiles; their
+    // waves go first in instruction issue
+    __builtin_amdgcn_s_setprio(3);
+    const int e = wtab[b];
+    C = cases + (e >> 16);
+    StepArgs<T> PW = C->P;
+    global_ptrs(PW);
+    const int pb = C->pbit0 ^ flip, mov_pending = first ? C->mov_pending0 : 1;
+    tile = window_block_tile<BX, BY>(e & 0xFFFF, PW, mov_pending ? pb : pb ^ 1);
+    if (tile < 0) return;
+    win = true;
+  } else {
+    const int bb = MOV ? b - nwin : b;
+    const int gtile = (bb & 7) * per_xcd + (bb >> 3);
+    if (gtile >= total_tiles) return;
+    // the lattice of this tile, then its description, read once
+    C = cases + tile_lattice(table, gtile);
+    tile = gtile - C->tile0;
+  }
+  batch_tile<S, BX, BY, TRT, MOV, MOV>(C, tile, flip, first, win);
 }
 
 // Batched step of lattices in the AA pattern (one population buffer each):

@@ -247,6 +247,44 @@ def test_moving_disks_in_batch_equal_alone():
     bt.close()
 
 
+def test_several_lattices_with_moving_disks_in_one_batch():
+    # three lattices with moving disks (three disks; one sedimenting disk
+    # driven by SI; one by ME) and a static one, stepped different counts by
+    # one batch whose launches take the disks' hit boxes first: every lattice
+    # as alone, bit for bit
+    from paper_2110_00967_amd import vplbm as V
+    say("several lattices with moving disks in one batch, fp32")
+
+    def build():
+        a, _ = moving_build("f32")
+        c1 = W.case_sedimentation()
+        c2 = W.case_sedimentation()
+        c2.force_source = V.FORCE_SI if c1.force_source == V.FORCE_ME else V.FORCE_ME
+        return [a, V.Lattice.from_case(c1, precision="f32"), V.Lattice.from_case(W.case_disk_channel(),
+                precision="f32"), V.Lattice.from_case(c2, precision="f32")]
+
+    nsteps = [29, 40, 11, 35]
+    alone = build()
+    for g, n in zip(alone, nsteps):
+        for _ in range(n):
+            g.step(1)
+    lats = build()
+    bt = V.Batch(lats)
+    bt.step(nsteps)
+    nb = [3, 1, 1, 1]
+    for k, (g, r) in enumerate(zip(lats, alone)):
+        assert g.step_count == r.step_count == nsteps[k]
+        assert np.array_equal(g.populations(), r.populations()), k
+        for b in range(1, nb[k] + 1):
+            for w in (V.FORCE_ME, V.FORCE_SI):
+                assert np.array_equal(g.history(w, body=b), r.history(w, body=b)), (k, b, w)
+            if k != 2:
+                assert np.array_equal(g.body_state(b), r.body_state(b)), (k, b)
+    bt.close()
+    for g in lats + alone:
+        g.close()
+
+
 def test_moving_disks_too_close_are_rejected():
     from paper_2110_00967_amd import vplbm as V
     say("moving disks one cell apart")
