@@ -404,12 +404,10 @@ int vplbm_batch_get_tile(const vplbm_batch *b, int *bx, int *by);
  * capture, tight serving loops, harnesses that forbid hipMalloc): the work
  * of vplbm_batch_step on lats[0..n) with nsteps[k] steps each, with 64x4
  * tiles and direct launches (no graph), without allocating anything.  Its
- * tables (lattice descriptors, the lattice of every block of 64 tiles, the
- * window workgroups of moving disks) live
- * in one static device array of the library, 466 KiB per GPU, held
+ * tables (lattice descriptors, the lattice of every block of 64 tiles) live
+ * in one static device array of the library, 402 KiB per GPU, held
  * until the process ends; limits: n <= 256 lattices, 2^20 tiles of 64x4
- * cells and 2^14 tiles of moving disks' hit boxes in all (VPLBM_EINVAL
- * beyond, message on lats[0]).  The lattices obey
+ * cells in all (VPLBM_EINVAL beyond, message on lats[0]).  The lattices obey
  * the rules of vplbm_batch_create and are stepped on their common stream,
  * which must belong to the current device.  Every call shares that device's
  * array: calls are serialized inside the library (each returns after its

@@ -1386,13 +1386,20 @@ template <typename T> __device__ __forceinline__ void global_ptrs(StepArgs<T> &P
   P.pts = gp(P.pts);
 }
 
-// One tile of lattice C in a batched launch: the launch's parities and
-// pending flags from C's description (fields read unconditionally, so that
-// the reads go out together).  SPLIT, win: as in step_tile.
-template <typename S, int BX, int BY, bool TRT, bool MOV, bool SPLIT>
-__device__ __forceinline__ void batch_tile(const CaseDesc<typename Store<S>::T> *__restrict__ C, int tile, int flip,
-                                           int first, bool win) {
+// Batched step: launch number `flip` (0 or 1, alternating) of a run over
+// ncases lattices; the lattice of each tile comes from the lattice table.
+// MOV: some lattice of the batch has moving disks.
+template <typename S, int BX, int BY, bool TRT, bool MOV = false>
+__global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
+    k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
+                 const BlockCase *__restrict__ table, int total_tiles, int per_xcd, int flip, int first) {
   using T = typename Store<S>::T;
+  const int b = blockIdx.x;
+  const int gtile = (b & 7) * per_xcd + (b >> 3);
+  if (gtile >= total_tiles) return;
+  // the lattice of this tile, then its description, read once (fields read
+  // unconditionally, so that the reads go out together)
+  const CaseDesc<T> *__restrict__ C = cases + tile_lattice(table, gtile);
   StepArgs<T> P = C->P;
   global_ptrs(P);
   const int par = C->cur0 ^ flip, pb = C->pbit0 ^ flip;
@@ -1403,51 +1410,10 @@ __device__ __forceinline__ void batch_tile(const CaseDesc<typename Store<S>::T> 
   S *fout = gp((S *)C->buf[par ^ 1]);
   // (the pointers of the force terms serve interface and sample cells only:
   // read where used)
-  step_tile<S, BX, BY, false, TRT, 0, MOV, SPLIT>(tile, fin, fout, gp(C->mask), P, C->ctl, C->recs, C->si_map,
-                                                  C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb],
-                                                  C->sig[pb ^ 1], fin_prev, C->hist, C->cap, C->maxb, nullptr,
-                                                  nullptr, nullptr, pb, mov_pending, win);
-}
-
-// Batched step: launch number `flip` (0 or 1, alternating) of a run over
-// ncases lattices; the lattice of each tile comes from the lattice table.
-// MOV: some lattice of the batch has moving disks.  Then, as in the
-// single-lattice launch, the first nwin workgroups take the tiles of the
-// disks' hit boxes -- window workgroup w: lattice wtab[w] >> 16, slot
-// wtab[w] & 0xFFFF of that lattice's boxes (window_block_tile) -- so that
-// the disks' serial chains start first, and the other workgroups leave those
-// tiles alone.
-template <typename S, int BX, int BY, bool TRT, bool MOV = false>
-__global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
-    k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
-                 const BlockCase *__restrict__ table, int total_tiles, int per_xcd, int flip, int first,
-                 const int *__restrict__ wtab, int nwin) {
-  using T = typename Store<S>::T;
-  const int b = blockIdx.x;
-  const CaseDesc<T> *__restrict__ C;
-  int tile;
-  bool win = false;
-  if (MOV && b < nwin) {
-    // these workgroups share their compute units with plain tiles; their
-    // waves go first in instruction issue
-    __builtin_amdgcn_s_setprio(3);
-    const int e = wtab[b];
-    C = cases + (e >> 16);
-    StepArgs<T> PW = C->P;
-    global_ptrs(PW);
-    const int pb = C->pbit0 ^ flip, mov_pending = first ? C->mov_pending0 : 1;
-    tile = window_block_tile<BX, BY>(e & 0xFFFF, PW, mov_pending ? pb : pb ^ 1);
-    if (tile < 0) return;
-    win = true;
-  } else {
-    const int bb = MOV ? b - nwin : b;
-    const int gtile = (bb & 7) * per_xcd + (bb >> 3);
-    if (gtile >= total_tiles) return;
-    // the lattice of this tile, then its description, read once
-    C = cases + tile_lattice(table, gtile);
-    tile = gtile - C->tile0;
-  }
-  batch_tile<S, BX, BY, TRT, MOV, MOV>(C, tile, flip, first, win);
+  step_tile<S, BX, BY, false, TRT, 0, MOV>(gtile - C->tile0, fin, fout, gp(C->mask), P, C->ctl, C->recs, C->si_map,
+                                           C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
+                                           fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
+                                           mov_pending);
 }
 
 // Batched step of lattices in the AA pattern (one population buffer each):

@@ -1938,10 +1938,10 @@ int vplbm_read_mask(vplbm_lattice *L, uint8_t *out) {
 // What a captured graph of batched launch pairs bakes in besides the device
 // tables' contents: the launch shape and arguments.
 struct GraphKey {
-  int nact = -1, bx = 0, mov = 0, nwin = 0;
+  int nact = -1, bx = 0, mov = 0;
   long long total = 0;
   bool operator==(const GraphKey &o) const {
-    return nact == o.nact && bx == o.bx && mov == o.mov && nwin == o.nwin && total == o.total;
+    return nact == o.nact && bx == o.bx && mov == o.mov && total == o.total;
   }
   bool operator!=(const GraphKey &o) const { return !(*this == o); }
 };
@@ -1958,9 +1958,6 @@ struct vplbm_batch {
   int ncap = 0;                  // descriptors the device table holds
   BlockCase *tile_case_dev = nullptr;  // lattice table: one entry per block of TILE_BLOCK global tiles
   long long tile_case_cap = 0;
-  int *win_dev = nullptr;  // window table of launches with moving disks (see k_step_batch)
-  long long win_cap = 0;
-  std::vector<int> win_host;
   std::vector<char> desc_host;
   hipGraphExec_t graph = nullptr;  // groups of launch pairs (parities 1, 0) of the current active set
   GraphKey graph_key;
@@ -1999,10 +1996,6 @@ struct BatchExec {
   BlockCase *tile_dev = nullptr;  // lattice table (one entry per TILE_BLOCK global tiles)
   long long tile_cap = 0;     // global tiles it has room for
   char *desc_host = nullptr;  // host staging, room for every lattice
-  int *win_dev = nullptr;     // window table: (lattice << 16 | slot) of every window workgroup
-  int *win_host = nullptr;    // its host staging
-  long long win_cap = 0;      // entries it has room for
-  int nwin = 0;               // window workgroups of the chunk (moving disks, two buffers)
   hipStream_t cap_stream = nullptr;  // graph capture (null: direct launches only)
   hipGraphExec_t *graph = nullptr;
   GraphKey *graph_key = nullptr;
@@ -2062,10 +2055,10 @@ void launch_batch_ab(const BatchExec &X, hipStream_t st, dim3 grid, int total, i
   const auto *descs = (const CaseDesc<typename Store<S>::T> *)X.desc_dev;
   if (X.trt)
     hipLaunchKernelGGL((k_step_batch<S, BX, BY, true, MOV>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total,
-                       per, flip, first, (const int *)X.win_dev, MOV ? X.nwin : 0);
+                       per, flip, first);
   else
     hipLaunchKernelGGL((k_step_batch<S, BX, BY, false, MOV>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total,
-                       per, flip, first, (const int *)X.win_dev, MOV ? X.nwin : 0);
+                       per, flip, first);
 }
 
 template <typename S, bool MOV>
@@ -2088,14 +2081,13 @@ template <typename S>
 void launch_batch_s(const BatchExec &X, hipStream_t st, int total, int flip, int first) {
   const int per = (total + 7) / 8;
   const dim3 grid(8 * per);
-  if (X.aa) {  // 64x4 tiles (every workgroup tests its tile against the disks' windows)
+  if (X.aa) {  // 64x4 tiles
     if (X.mov)
       launch_batch_aa<S, true>(X, st, grid, total, per, flip, first);
     else
       launch_batch_aa<S, false>(X, st, grid, total, per, flip, first);
   } else if (X.mov) {
-    // the window workgroups first
-    launch_batch_ab<S, 64, 4, true>(X, st, dim3(X.nwin + 8 * per), total, per, flip, first);
+    launch_batch_ab<S, 64, 4, true>(X, st, grid, total, per, flip, first);
   } else if (X.bx == 128 && X.by == 2) {
     launch_batch_ab<S, 128, 2, false>(X, st, grid, total, per, flip, first);
   } else if (X.bx == 256) {
@@ -2194,27 +2186,6 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
     rc = hipck(hipMemcpyAsync(X.desc_dev, X.desc_host, dsz * nact, hipMemcpyHostToDevice, X.stream),
                "batch descriptors");
     if (rc) return rc;
-    // the window workgroups of the lattices with moving disks (two buffers)
-    X.nwin = 0;
-    if (X.mov && !X.aa) {
-      for (int i = 0; i < nact; ++i) {
-        vplbm_lattice *L = lats[act[i]];
-        const long long wb = L->nmov ? L->step_args<float>(bx, by).wblocks : 0;
-        if (wb > 0xFFFF || i > 0x7FFF)
-          return fail(VPLBM_EINVAL, "lattice " + std::to_string(act[i]) + ": too many window tiles for a batch");
-        if (X.nwin + wb > X.win_cap)
-          return fail(VPLBM_EINVAL, "the batch's " + std::to_string(X.nwin + wb) +
-                                        " window workgroups exceed the window table (" + std::to_string(X.win_cap) +
-                                        ")");
-        for (int j = 0; j < (int)wb; ++j) X.win_host[X.nwin++] = (i << 16) | j;
-      }
-      if (X.nwin > 0) {
-        rc = hipck(hipMemcpyAsync(X.win_dev, X.win_host, sizeof(int) * (size_t)X.nwin, hipMemcpyHostToDevice,
-                                  X.stream),
-                   "window table");
-        if (rc) return rc;
-      }
-    }
     (void)hipGetLastError();
     launch_fill_tiles(X, nact, (int)total);
     rc = hipck(hipGetLastError(), "k_fill_tile_case");
@@ -2235,7 +2206,6 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
       key.nact = nact;
       key.bx = bx;
       key.mov = X.mov ? 1 : 0;
-      key.nwin = X.nwin;
       key.total = total;
       if (!*X.graph || *X.graph_key != key) {
         if (*X.graph) (void)hipGraphExecDestroy(*X.graph);
@@ -2284,18 +2254,15 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
 }
 
 // ---- scratch of the allocation-free batched step --------------------------
-// Descriptors, lattice table and window table of vplbm_batch_step_noalloc
-// live in one file-scope device array; every GPU the library runs on holds
-// its own copy until the process ends.  Host code reaches it only through
-// the address hipGetSymbolAddress returns for the current device.
+// Descriptors, moving list and tile table of vplbm_batch_step_noalloc live in
+// one file-scope device array; every GPU the library runs on holds its own
+// copy until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
 constexpr int NOALLOC_MAX_CASES = 256;
 constexpr long long NOALLOC_MAX_TILES = 1 << 20;
-constexpr long long NOALLOC_MAX_WIN = 1 << 14;  // window workgroups (moving disks)
 constexpr size_t NOALLOC_DESC_BYTES = (size_t)NOALLOC_MAX_CASES * desc_size<double>();
 constexpr size_t NOALLOC_TILE_OFF = (NOALLOC_DESC_BYTES + 255) / 256 * 256;
-constexpr size_t NOALLOC_WIN_OFF =
-    NOALLOC_TILE_OFF + (size_t)(NOALLOC_MAX_TILES / TILE_BLOCK) * sizeof(BlockCase);
-constexpr size_t NOALLOC_BYTES = NOALLOC_WIN_OFF + (size_t)NOALLOC_MAX_WIN * sizeof(int);
+constexpr size_t NOALLOC_BYTES = NOALLOC_TILE_OFF + (size_t)(NOALLOC_MAX_TILES / TILE_BLOCK) * sizeof(BlockCase);
 static_assert(NOALLOC_MAX_TILES % TILE_BLOCK == 0, "whole table blocks");
 static_assert(desc_size<double>() >= desc_size<float>() && desc_size<double>() >= desc_size<__half>(),
               "descriptor slots sized for the largest descriptor");
@@ -2310,7 +2277,6 @@ constexpr int NOALLOC_MAX_DEVICES = 64;
 std::mutex g_noalloc_mu;  // guards the per-device addresses and the host staging below
 void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
 unsigned char g_noalloc_desc_host[NOALLOC_DESC_BYTES];
-int g_noalloc_win_host[NOALLOC_MAX_WIN];
 
 }  // namespace
 
@@ -2350,7 +2316,6 @@ int vplbm_batch_destroy(vplbm_batch *B) {
   if (B->graph) (void)hipGraphExecDestroy(B->graph);
   (void)hipFree(B->desc_dev);
   if (B->tile_case_dev) (void)hipFree(B->tile_case_dev);
-  if (B->win_dev) (void)hipFree(B->win_dev);
   (void)hipStreamDestroy(B->cap_stream);
   delete B;
   return VPLBM_OK;
@@ -2427,26 +2392,6 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
     if (rc) return rc;
     B->tile_case_cap = need;
   }
-  // the window table holds the window workgroups of every lattice with
-  // moving disks (two-buffer batches)
-  long long need_w = 0;
-  if (!B->aa)
-    for (vplbm_lattice *L : B->cases)
-      if (L->nmov) need_w += L->step_args<float>(64, 4).wblocks;
-  if (need_w > B->win_cap) {
-    int rc = B->hip(hipStreamSynchronize(B->stream), "hipStreamSynchronize");
-    if (rc) return rc;
-    if (B->win_dev) (void)hipFree(B->win_dev);
-    B->win_dev = nullptr;
-    B->win_cap = 0;
-    if (B->graph) (void)hipGraphExecDestroy(B->graph);  // it holds the old table's address
-    B->graph = nullptr;
-    B->graph_key = GraphKey();
-    rc = B->hip(hipMalloc((void **)&B->win_dev, sizeof(int) * (size_t)need_w), "window table");
-    if (rc) return rc;
-    B->win_host.assign((size_t)need_w, 0);
-    B->win_cap = need_w;
-  }
   BatchExec X;
   X.prec = B->prec;
   X.trt = B->trt;
@@ -2457,9 +2402,6 @@ int vplbm_batch_step(vplbm_batch *B, const int *nsteps) {
   X.desc_dev = B->desc_dev;
   X.tile_dev = B->tile_case_dev;
   X.tile_cap = B->tile_case_cap;
-  X.win_dev = B->win_dev;
-  X.win_host = B->win_host.data();
-  X.win_cap = B->win_cap;
   X.desc_host = B->desc_host.data();
   X.cap_stream = B->cap_stream;
   X.graph = &B->graph;
@@ -2507,9 +2449,6 @@ int vplbm_batch_step_noalloc(vplbm_lattice *const *lats, int n, const int *nstep
   X.desc_dev = base;
   X.tile_dev = (BlockCase *)(base + NOALLOC_TILE_OFF);
   X.tile_cap = NOALLOC_MAX_TILES;
-  X.win_dev = (int *)(base + NOALLOC_WIN_OFF);
-  X.win_host = g_noalloc_win_host;
-  X.win_cap = NOALLOC_MAX_WIN;
   X.desc_host = (char *)g_noalloc_desc_host;
   std::string err;
   const int rc = batch_run(X, lats, n, nsteps, err);
