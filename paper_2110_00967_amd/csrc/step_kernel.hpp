@@ -561,6 +561,42 @@ __device__ __forceinline__ bool in_hit_box(double bx, double by, int h, int tx, 
   return tx >= hx0 && tx <= hx1 && ty >= hy0 && ty <= hy1;
 }
 
+// Where a batched launch starts the XCD bands of the next one (see
+// batch_place).  A band's key holds an epoch (40 bits) over the inverted
+// rotation (24 bits), so that the largest key is the newest epoch's
+// smallest rotation, and zero (the initial state) the oldest.
+constexpr int ROT_BITS = 24;
+constexpr unsigned long long ROT_MASK = (1ull << ROT_BITS) - 1, EPOCH_MASK = (1ull << 40) - 1;
+__host__ __device__ constexpr unsigned long long band_key(unsigned long long epoch, long long rot) {
+  return (epoch & EPOCH_MASK) << ROT_BITS | (ROT_MASK - (unsigned long long)rot);
+}
+// A batched launch's part in the rotation (mover_prologue records the keys
+// of the launch after it): flip, the launch's flip (-1 outside batched
+// launches); tile0, the lattice's first global tile; per_xcd, the tiles of
+// a band.  Plain integers, so that nothing wide stays live through the tile
+// code for it.
+struct BandRot {
+  int flip = -1;
+  int tile0 = 0, per_xcd = 1;
+};
+
+// Band rotation state of the batched launches with moving disks on a
+// device: the keys recorded for the launches of flip 0 and 1, then their
+// epochs.  The launch of flip f reads keys[f] and epoch[f]; for the launch
+// after it, it sets epoch[f ^ 1] = epoch[f] + 1 and records keys[f ^ 1]
+// (atomic maximum: several disks in a band keep the earliest).  A slot is
+// never written by the launch that reads it.  One per device, at a fixed
+// address, so that a workgroup reads it together with its kernel
+// arguments (a pointer argument would cost a second dependent read before
+// the tile is known); zero at load.  Batches that run at the same time on
+// one device share it: their rotations then mix, which orders their work
+// less well and changes no result.
+struct BandState {
+  unsigned long long keys[2][8];
+  unsigned long long epoch[2];
+};
+__device__ BandState g_band;
+
 // The moving disks' part of one workgroup of the launch that computes step N
 // (parity pb = N & 1; pending: the forces of step N - 1 are still to be
 // summed and the states advanced by them).  States: slot k & 1 of
@@ -573,8 +609,9 @@ __device__ __forceinline__ bool in_hit_box(double bx, double by, int h, int tx, 
 //   1. pending: the forces of step N - 1 of every disk (mover_forces on the
 //      tile partials of step N - 1, part_prev), its new state (mover_update);
 //      the workgroup of the tile holding the disk's centre cell writes the
-//      state to the other slot, the forces to the history ring, and flags a
-//      disk that moved a cell or more (error bit 5);
+//      state to the other slot, the forces to the history ring, flags a
+//      disk that moved a cell or more (error bit 5) and, in a batched
+//      launch, records where the next launch starts the disk's band (xr);
 //   2. the solid ids of the tile and its ring, and the sample nodes of every
 //      point that fall in the tile, at the states of this step (error bit 0
 //      for a point without sample node).  Thread t places points t, t + NT,
@@ -585,7 +622,7 @@ template <typename T, int BX, int BY>
 __device__ __forceinline__ bool mover_prologue(int tx, int ty, const StepArgs<T> &P, Ctl *__restrict__ ctl,
                                                const double *__restrict__ part_prev, double *__restrict__ hist,
                                                int cap, int maxb, int pb, int pending, bool known,
-                                               MovLds<BX, BY> &ml) {
+                                               MovLds<BX, BY> &ml, const BandRot &xr = BandRot()) {
   // force and geometry arithmetic: no multiply-add fusion, so that every kernel
   // that inlines this (alone, batched, any tile) rounds it the same way
   #pragma clang fp contract(off)
@@ -608,6 +645,9 @@ __device__ __forceinline__ bool mover_prologue(int tx, int ty, const StepArgs<T>
     }
   }
   if (!hit) return false;
+  // the epoch of the launch after this one, for the band keys the recording
+  // workgroups write (read here, well before they need it)
+  const unsigned long long epoch_next = xr.flip >= 0 ? g_band.epoch[xr.flip] + 1 : 0;
   // this thread's first point and its disk's radius, in flight with the sums
   const int i0 = threadIdx.x;
   double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0, q4 = 0.0;
@@ -644,6 +684,20 @@ __device__ __forceinline__ bool mover_prologue(int tx, int ty, const StepArgs<T>
           ctl->body = S;
         }
         if (fabs(S.x - B.x) >= 1.0 || fabs(S.y - B.y) >= 1.0) atomicOr(&ctl->err, 32);
+        if (xr.flip >= 0) {
+          // the next launch starts the band holding this disk's hit box a
+          // tile row before the box (the disk moves less than a cell per
+          // step), so that the box's workgroups are among its first; of
+          // several disks in one band the earliest, so that the others
+          // follow it in order
+          int hx0, hy0, hx1, hy1;
+          hit_box<BX, BY>(S.x, S.y, M.half, hx0, hy0, hx1, hy1);
+          const long long g = xr.tile0 + (long long)max(hy0 - 1, 0) * tiles_x;
+          const long long band = g / xr.per_xcd;
+          const long long rot = g - band * xr.per_xcd;
+          if (band < 8 && rot <= (long long)ROT_MASK)
+            atomicMax(&g_band.keys[xr.flip ^ 1][band], band_key(epoch_next, rot));
+        }
       }
     }
   } else if ((int)threadIdx.x < nmov) {
@@ -1112,7 +1166,8 @@ __device__ __forceinline__ void step_tile(
     double *__restrict__ me_out, const double *__restrict__ me_prev, double *__restrict__ sig_out,
     const double *__restrict__ sig_prev, int fin_prev, double *__restrict__ hist, int cap, int maxb,
     typename Store<S>::T *__restrict__ mrho, typename Store<S>::T *__restrict__ mux,
-    typename Store<S>::T *__restrict__ muy, int pb = 0, int mov_pending = 0, bool win = false) {
+    typename Store<S>::T *__restrict__ muy, int pb = 0, int mov_pending = 0, bool win = false,
+    const BandRot &xr = BandRot()) {
   using T = typename Store<S>::T;
   constexpr int NT = BX * BY;
   const TileCell t = tile_cell<S, BX, BY>(tile, P);
@@ -1142,7 +1197,8 @@ __device__ __forceinline__ void step_tile(
           hit = hit || in_hit_box<BX, BY>(P.mov[k].B[sread].x, P.mov[k].B[sread].y, P.mov[k].half, t.tx, t.ty);
         if (hit) return;
       } else {
-        mwg = mover_prologue<T, BX, BY>(t.tx, t.ty, P, ctl, me_prev, hist, cap, maxb, pb, mov_pending, SPLIT, ml);
+        mwg = mover_prologue<T, BX, BY>(t.tx, t.ty, P, ctl, me_prev, hist, cap, maxb, pb, mov_pending, SPLIT, ml,
+                                        xr);
       }
     }
   }
@@ -1357,10 +1413,12 @@ __global__ void k_fill_tile_case(const CaseDesc<T> *__restrict__ cases, int ncas
 
 // The lattice of global tile g: its block's first lattice plus the lattices
 // that start at tiles 1..j of the block (j = g's place in it).
-__device__ __forceinline__ int tile_lattice(const BlockCase *__restrict__ table, int g) {
-  const BlockCase e = table[g / TILE_BLOCK];
+__device__ __forceinline__ int lattice_in(const BlockCase &e, int g) {
   const int j = g % TILE_BLOCK;
   return e.first + __popcll(e.starts & ((2ull << j) - 2ull));
+}
+__device__ __forceinline__ int tile_lattice(const BlockCase *__restrict__ table, int g) {
+  return lattice_in(table[g / TILE_BLOCK], g);
 }
 
 // p as a global-memory pointer: pointers read from a descriptor in memory
@@ -1386,20 +1444,65 @@ template <typename T> __device__ __forceinline__ void global_ptrs(StepArgs<T> &P
   P.pts = gp(P.pts);
 }
 
+// The place of workgroup b of a batched launch: its global tile (gtile) and
+// the lattice of that tile, or -1 for none.  The workgroups go round-robin
+// over the 8 XCDs, and XCD x takes the band of per_xcd consecutive tiles
+// from x * per_xcd (shared halo lines stay in its L2).  With moving disks
+// (ROT) band x starts r tiles in and wraps round, so that the long serial
+// work of a disk's hit-box workgroups starts among the band's first
+// workgroups instead of wherever the disk sits: r from the band's key
+// (band_key) the launch before recorded (mover_prologue); a key of another
+// epoch (stale, or none yet) or a rotation outside the band counts as r = 0.
+// The keys and epochs of both flips are read first, with the kernel
+// arguments.  Any r gives the same results: it only orders the work.
+template <bool ROT, typename CD>
+__device__ __forceinline__ const CD *batch_place(int b, int total_tiles, int per_xcd, const BlockCase *__restrict__ table,
+                                                 const CD *cases, int flip, int &gtile, unsigned long long &epoch) {
+  const int x = b & 7, i = b >> 3, start = x * per_xcd;
+  if constexpr (!ROT) {
+    gtile = start + i;
+    if (gtile >= total_tiles) return nullptr;
+    return cases + tile_lattice(table, gtile);
+  } else {
+    // no branch before the table read: the band state (both flips', at
+    // addresses that need nothing read first) then goes out with the kernel
+    // arguments, where a read the compiler moved below an early exit would
+    // wait for a round trip of its own; a workgroup without tile reads the
+    // table at the last tile and leaves after it
+    const unsigned long long k0 = g_band.keys[0][x], k1 = g_band.keys[1][x];
+    const unsigned long long e0 = g_band.epoch[0], e1 = g_band.epoch[1];
+    const unsigned long long key = flip ? k1 : k0;
+    epoch = flip ? e1 : e0;
+    const int len = min(per_xcd, total_tiles - start);
+    long long r = (key >> ROT_BITS) == (epoch & EPOCH_MASK) ? (long long)(ROT_MASK - (key & ROT_MASK)) : 0;
+    r = r < len ? r : 0;
+    const int t = i + (int)r;
+    gtile = min(start + (t >= len ? t - len : t), total_tiles - 1);
+    const CD *c = cases + tile_lattice(table, gtile);
+    return i < len ? c : nullptr;
+  }
+}
+
 // Batched step: launch number `flip` (0 or 1, alternating) of a run over
 // ncases lattices; the lattice of each tile comes from the lattice table.
-// MOV: some lattice of the batch has moving disks.
-template <typename S, int BX, int BY, bool TRT, bool MOV = false>
+// MOV: some lattice of the batch has moving disks.  ROT (with MOV): the
+// bands start at the disks' hit boxes (batch_place), for launches short
+// enough that a disk's serial work decides when they end; the form without
+// it keeps the plain tiles' code as it is for long launches (the rotation's
+// reads and records cost them some registers).
+template <typename S, int BX, int BY, bool TRT, bool MOV = false, bool ROT = false>
 __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
     k_step_batch(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
                  const BlockCase *__restrict__ table, int total_tiles, int per_xcd, int flip, int first) {
   using T = typename Store<S>::T;
-  const int b = blockIdx.x;
-  const int gtile = (b & 7) * per_xcd + (b >> 3);
-  if (gtile >= total_tiles) return;
-  // the lattice of this tile, then its description, read once (fields read
-  // unconditionally, so that the reads go out together)
-  const CaseDesc<T> *__restrict__ C = cases + tile_lattice(table, gtile);
+  // the tile and the description of its lattice, then the description's
+  // fields, read once (unconditionally, so that the reads go out together)
+  int gtile;
+  unsigned long long epoch = 0;
+  const CaseDesc<T> *__restrict__ C =
+      batch_place<MOV && ROT>(blockIdx.x, total_tiles, per_xcd, table, cases, flip, gtile, epoch);
+  if (!C) return;
+  if (MOV && ROT && blockIdx.x == 0 && threadIdx.x == 0) g_band.epoch[flip ^ 1] = epoch + 1;
   StepArgs<T> P = C->P;
   global_ptrs(P);
   const int par = C->cur0 ^ flip, pb = C->pbit0 ^ flip;
@@ -1413,7 +1516,8 @@ __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
   step_tile<S, BX, BY, false, TRT, 0, MOV>(gtile - C->tile0, fin, fout, gp(C->mask), P, C->ctl, C->recs, C->si_map,
                                            C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
                                            fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
-                                           mov_pending);
+                                           mov_pending, false,
+                                           (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));
 }
 
 // Batched step of lattices in the AA pattern (one population buffer each):
@@ -1421,15 +1525,17 @@ __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
 // stays in the cell (AA = 2), per lattice by its own step parity; the
 // perimeter copies alternate with it (read: the previous step's, written:
 // this step's).
-template <typename S, bool TRT, bool MOV = false>
+template <typename S, bool TRT, bool MOV = false, bool ROT = false>
 __global__ void __launch_bounds__(256, (step_waves_mov<S, MOV>()))
     k_step_batch_aa(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
                     const BlockCase *__restrict__ table, int total_tiles, int per_xcd, int flip, int first) {
   using T = typename Store<S>::T;
-  const int b = blockIdx.x;
-  const int gtile = (b & 7) * per_xcd + (b >> 3);
-  if (gtile >= total_tiles) return;
-  const CaseDesc<T> *__restrict__ C = cases + tile_lattice(table, gtile);
+  int gtile;
+  unsigned long long epoch = 0;
+  const CaseDesc<T> *__restrict__ C =
+      batch_place<MOV && ROT>(blockIdx.x, total_tiles, per_xcd, table, cases, flip, gtile, epoch);
+  if (!C) return;
+  if (MOV && ROT && blockIdx.x == 0 && threadIdx.x == 0) g_band.epoch[flip ^ 1] = epoch + 1;
   StepArgs<T> P = C->P;
   global_ptrs(P);
   const int pb = C->pbit0 ^ flip;
@@ -1442,11 +1548,13 @@ __global__ void __launch_bounds__(256, (step_waves_mov<S, MOV>()))
   if (pb)
     step_tile<S, 64, 4, false, TRT, 1, MOV>(gtile - C->tile0, nullptr, F, gp(C->mask), P, C->ctl, C->recs, C->si_map,
                                             C->imap, C->bt, C->me[1], C->me[0], C->sig[1], C->sig[0], fin_prev,
-                                            C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb, mov_pending);
+                                            C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb, mov_pending,
+                                            false, (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));
   else
     step_tile<S, 64, 4, false, TRT, 2, MOV>(gtile - C->tile0, nullptr, F, gp(C->mask), P, C->ctl, C->recs, C->si_map,
                                             C->imap, C->bt, C->me[0], C->me[1], C->sig[0], C->sig[1], fin_prev,
-                                            C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb, mov_pending);
+                                            C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb, mov_pending,
+                                            false, (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));
 }
 
 template <int NT>

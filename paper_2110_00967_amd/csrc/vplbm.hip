@@ -2050,27 +2050,37 @@ const char *batch_check(vplbm_lattice *const *lats, int n) {
   return nullptr;
 }
 
-template <typename S, int BX, int BY, bool MOV>
+template <typename S, int BX, int BY, bool MOV, bool ROT = false>
 void launch_batch_ab(const BatchExec &X, hipStream_t st, dim3 grid, int total, int per, int flip, int first) {
   const auto *descs = (const CaseDesc<typename Store<S>::T> *)X.desc_dev;
   if (X.trt)
-    hipLaunchKernelGGL((k_step_batch<S, BX, BY, true, MOV>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total,
-                       per, flip, first);
+    hipLaunchKernelGGL((k_step_batch<S, BX, BY, true, MOV, ROT>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev,
+                       total, per, flip, first);
   else
-    hipLaunchKernelGGL((k_step_batch<S, BX, BY, false, MOV>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev, total,
-                       per, flip, first);
+    hipLaunchKernelGGL((k_step_batch<S, BX, BY, false, MOV, ROT>), grid, dim3(BX * BY), 0, st, descs, X.tile_dev,
+                       total, per, flip, first);
 }
 
-template <typename S, bool MOV>
+template <typename S, bool MOV, bool ROT = false>
 void launch_batch_aa(const BatchExec &X, hipStream_t st, dim3 grid, int total, int per, int flip, int first) {
   const auto *descs = (const CaseDesc<typename Store<S>::T> *)X.desc_dev;
   if (X.trt)
-    hipLaunchKernelGGL((k_step_batch_aa<S, true, MOV>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per, flip,
-                       first);
+    hipLaunchKernelGGL((k_step_batch_aa<S, true, MOV, ROT>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per,
+                       flip, first);
   else
-    hipLaunchKernelGGL((k_step_batch_aa<S, false, MOV>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per, flip,
-                       first);
+    hipLaunchKernelGGL((k_step_batch_aa<S, false, MOV, ROT>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per,
+                       flip, first);
 }
+
+// Batched launches with moving disks of at most this many (64x4) tiles
+// start their XCD bands at the disks' hit boxes (k_step_batch's ROT).  About
+// 2 M cells: the plain tiles then take a few times the hit-box workgroups'
+// serial work (10-12 us), so that where that work starts decides when the
+// launch ends; the sedimenting disk (400 x 2000) batched alone 20.6 -> 17.0
+// us per step.  Longer launches keep the form without rotation, whose plain
+// tiles run 3-7% faster (a mix of 12 airfoil and sedimentation lattices,
+// 8.5 M cells).
+constexpr int ROT_MAX_TILES = 8192;
 
 // the tile a chunk's launches run: the batch's, or 64x4 when a lattice has
 // moving disks or the lattices are in the AA pattern
@@ -2081,11 +2091,16 @@ template <typename S>
 void launch_batch_s(const BatchExec &X, hipStream_t st, int total, int flip, int first) {
   const int per = (total + 7) / 8;
   const dim3 grid(8 * per);
+  const bool rot = total <= ROT_MAX_TILES;
   if (X.aa) {  // 64x4 tiles
-    if (X.mov)
+    if (X.mov && rot)
+      launch_batch_aa<S, true, true>(X, st, grid, total, per, flip, first);
+    else if (X.mov)
       launch_batch_aa<S, true>(X, st, grid, total, per, flip, first);
     else
       launch_batch_aa<S, false>(X, st, grid, total, per, flip, first);
+  } else if (X.mov && rot) {
+    launch_batch_ab<S, 64, 4, true, true>(X, st, grid, total, per, flip, first);
   } else if (X.mov) {
     launch_batch_ab<S, 64, 4, true>(X, st, grid, total, per, flip, first);
   } else if (X.bx == 128 && X.by == 2) {

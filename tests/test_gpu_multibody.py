@@ -247,31 +247,47 @@ def test_moving_disks_in_batch_equal_alone():
     bt.close()
 
 
-def test_several_lattices_with_moving_disks_in_one_batch():
+@pytest.mark.parametrize("big", [False, True])
+def test_several_lattices_with_moving_disks_in_one_batch(big):
     # three lattices with moving disks (three disks; one sedimenting disk
     # driven by SI; one by ME) and a static one, stepped different counts by
-    # one batch whose launches take the disks' hit boxes first: every lattice
-    # as alone, bit for bit
+    # one batch: every lattice as alone, bit for bit.  The batch's launches
+    # start their XCD bands at the disks' hit boxes (below 8192 tiles of
+    # 64x4); with a large static lattice added (big) they run the form
+    # without rotation until the last chunk, whose two lattices fall below
+    # the limit again
     from paper_2110_00967_amd import vplbm as V
-    say("several lattices with moving disks in one batch, fp32")
+    say(f"several lattices with moving disks in one batch, fp32, big={big}")
 
     def build():
         a, _ = moving_build("f32")
         c1 = W.case_sedimentation()
         c2 = W.case_sedimentation()
         c2.force_source = V.FORCE_SI if c1.force_source == V.FORCE_ME else V.FORCE_ME
-        return [a, V.Lattice.from_case(c1, precision="f32"), V.Lattice.from_case(W.case_disk_channel(),
+        lats = [a, V.Lattice.from_case(c1, precision="f32"), V.Lattice.from_case(W.case_disk_channel(),
                 precision="f32"), V.Lattice.from_case(c2, precision="f32")]
+        if big:
+            g = V.Lattice(V.make_params(1024, 512, 0.6, 1e-4, 1.0, "f32"))
+            g.init_uniform(1.0, 0.04, 0.01)
+            lats.append(g)
+        return lats
 
-    nsteps = [29, 40, 11, 35]
+    nsteps = [29, 40, 11, 35] + ([38] if big else [])
     alone = build()
     for g, n in zip(alone, nsteps):
         for _ in range(n):
             g.step(1)
     lats = build()
+    if big:
+        def tiles(g):
+            return -(-g.nx // 64) * -(-g.ny // 4)
+        # chunks of all five, four and three lattices above the limit, the
+        # last two (c1 and the static lattice, then c1) below it
+        assert sum(tiles(g) for g in lats if g is not lats[2]) - tiles(lats[0]) > 8192
+        assert tiles(lats[1]) + tiles(lats[4]) < 8192
     bt = V.Batch(lats)
     bt.step(nsteps)
-    nb = [3, 1, 1, 1]
+    nb = [3, 1, 1, 1, 0]
     for k, (g, r) in enumerate(zip(lats, alone)):
         assert g.step_count == r.step_count == nsteps[k]
         assert np.array_equal(g.populations(), r.populations()), k
