@@ -910,6 +910,39 @@ __device__ __forceinline__ void load_cell(const TileCell &t, const S *__restrict
   }
 }
 
+// The force terms' buffers and body tables of a lattice, as the tile code
+// reaches them (FB in step_tile and cell_update): ctl (counters, error bits,
+// body 1's state), recs (SI records), si_map / imap (slot of each sample /
+// interface cell), bt (body table), me_out / me_prev and sig_out / sig_prev
+// (interface and sample-node terms of this step and the step before), hist
+// (force history ring of cap entries of maxb bodies).  ArgBufs holds them as
+// the single-lattice kernel's arguments; a batched launch reads them from
+// the lattice's description only where a cell needs them (DescBufs).
+struct ArgBufs {
+  Ctl *ctl_;
+  const SiRec *recs_;
+  const int *si_map_, *imap_;
+  const BodyTab *bt_;
+  double *me_out_;
+  const double *me_prev_;
+  double *sig_out_;
+  const double *sig_prev_;
+  double *hist_;
+  int cap_, maxb_;
+  __device__ Ctl *ctl() const { return ctl_; }
+  __device__ const SiRec *recs() const { return recs_; }
+  __device__ const int *si_map() const { return si_map_; }
+  __device__ const int *imap() const { return imap_; }
+  __device__ const BodyTab *bt() const { return bt_; }
+  __device__ double *me_out() const { return me_out_; }
+  __device__ const double *me_prev() const { return me_prev_; }
+  __device__ double *sig_out() const { return sig_out_; }
+  __device__ const double *sig_prev() const { return sig_prev_; }
+  __device__ double *hist() const { return hist_; }
+  __device__ int cap() const { return cap_; }
+  __device__ int maxb() const { return maxb_; }
+};
+
 // The update of a live cell with flags m (body id, interface, sample node)
 // from its streamed populations d: moments, penalization, collision and the
 // stores of the post-collision populations (and the macroscopic fields when
@@ -918,14 +951,11 @@ __device__ __forceinline__ void load_cell(const TileCell &t, const S *__restrict
 // bodies store them in their slots for the finalize; moving disks (MOV with
 // P.nmov > 0) keep them for mover_epilogue and take their states and the
 // neighbours' ids from ml.
-template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA, bool MOV, typename T, typename ML>
+template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA, bool MOV, typename T, typename ML, typename FB>
 __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], uint8_t m, S *__restrict__ fout,
-                                            const uint8_t *__restrict__ mask, const StepArgs<T> &P,
-                                            Ctl *__restrict__ ctl, const int *__restrict__ si_map,
-                                            const int *__restrict__ imap, double *__restrict__ me_out,
-                                            double *__restrict__ sig_out, T *__restrict__ mrho, T *__restrict__ mux,
-                                            T *__restrict__ muy, const ML &ml, double (&acc)[3], int &bid,
-                                            double (&sg)[3]) {
+                                            const uint8_t *__restrict__ mask, const StepArgs<T> &P, const FB &fb,
+                                            T *__restrict__ mrho, T *__restrict__ mux, T *__restrict__ muy,
+                                            const ML &ml, double (&acc)[3], int &bid, double (&sg)[3]) {
   const int x = t.x, y = t.y, c = t.c, yw = t.yw, cw = t.cw;
   const bool tile_interior = t.interior;
   const uint32_t lb = t.lb;
@@ -944,7 +974,7 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
   // flags it (error bit 4) for the host's next check
   {
     const unsigned long long bad = __ballot(!(fabs(drho) <= T(1e30)));
-    if (bad && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)bad) - 1)) atomicOr(&ctl->err, 16);
+    if (bad && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)bad) - 1)) atomicOr(&fb.ctl()->err, 16);
   }
 
   // penalized velocity (Eq. updatestepm) and force; k = 0 in fluid cells
@@ -960,7 +990,7 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
       usx = T(B.u - B.omega * (double(y) - B.y));
       usy = T(B.v + B.omega * (double(x) - B.x));
     } else if (id == 1) {  // the only static-lattice body that can move (u_s = 0 in the static ones)
-      const BodyDev B = ctl->body;
+      const BodyDev B = fb.ctl()->body;
       usx = T(B.u - B.omega * (double(y) - B.y));
       usy = T(B.v + B.omega * (double(x) - B.x));
     }
@@ -1063,10 +1093,10 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
         bx = ml.st[bid - 1].x;
         by = ml.st[bid - 1].y;
       } else {
-        body_ref(ctl, P, bid, bx, by);
+        body_ref(fb.ctl(), P, bid, bx, by);
       }
     } else {
-      body_ref(ctl, P, bid, bx, by);
+      body_ref(fb.ctl(), P, bid, bx, by);
     }
     const bool moving = movl || bid == 1;  // u_s = 0 on the links of static bodies 2..
 #pragma unroll
@@ -1094,12 +1124,12 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
             ugx = B.u - B.omega * (gy - B.y);
             ugy = B.v + B.omega * (gx - B.x);
           } else {
-            const BodyDev &B = ctl->body;
+            const BodyDev &B = fb.ctl()->body;
             ugx = B.u - B.omega * (gy - B.y);
             ugy = B.v + B.omega * (gx - B.x);
           }
         } else {
-          const BodyDev &B = ctl->body;
+          const BodyDev &B = fb.ctl()->body;
           ugx = B.u - B.omega * (gy - B.y);
           ugy = B.v + B.omega * (gx - B.x);
         }
@@ -1112,7 +1142,7 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
     }
     if (!movl) {
       // this cell's contribution goes to its slot; the finalize sums them
-      double *o = me_out + (long long)imap[(uint32_t)c] * ME_STRIDE;
+      double *o = fb.me_out() + (long long)fb.imap()[(uint32_t)c] * ME_STRIDE;
       o[0] = acc[0];
       o[1] = acc[1];
       o[2] = acc[2];
@@ -1138,7 +1168,7 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
     if (!(MOV && P.nmov > 0)) {
       // the node's stress goes to its record's slot; the finalize
       // contracts it with the aggregated weights
-      double *g = sig_out + (long long)si_map[(uint32_t)c] * SIG_STRIDE;
+      double *g = fb.sig_out() + (long long)fb.si_map()[(uint32_t)c] * SIG_STRIDE;
       g[0] = sg[0];
       g[1] = sg[1];
       g[2] = sg[2];
@@ -1158,16 +1188,14 @@ __device__ __forceinline__ void cell_update(const TileCell &t, const T (&d)[Q], 
 // one of a disk's hit box (taken by the workgroups that come first); a
 // plain workgroup leaves the hit boxes' tiles alone.  Otherwise every
 // workgroup tests its tile itself.
-template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA, bool MOV = false, bool SPLIT = false>
-__device__ __forceinline__ void step_tile(
-    int tile, const S *__restrict__ fin, S *__restrict__ fout, const uint8_t *__restrict__ mask,
-    const StepArgs<typename Store<S>::T> P, Ctl *__restrict__ ctl, const SiRec *__restrict__ recs,
-    const int *__restrict__ si_map, const int *__restrict__ imap, const BodyTab *__restrict__ bt,
-    double *__restrict__ me_out, const double *__restrict__ me_prev, double *__restrict__ sig_out,
-    const double *__restrict__ sig_prev, int fin_prev, double *__restrict__ hist, int cap, int maxb,
-    typename Store<S>::T *__restrict__ mrho, typename Store<S>::T *__restrict__ mux,
-    typename Store<S>::T *__restrict__ muy, int pb = 0, int mov_pending = 0, bool win = false,
-    const BandRot &xr = BandRot()) {
+template <typename S, int BX, int BY, bool MACRO, bool TRT, int AA, bool MOV = false, bool SPLIT = false,
+          typename FB>
+__device__ __forceinline__ void step_tile(int tile, const S *__restrict__ fin, S *__restrict__ fout,
+                                          const uint8_t *__restrict__ mask, const StepArgs<typename Store<S>::T> P,
+                                          const FB &fb, int fin_prev, typename Store<S>::T *__restrict__ mrho,
+                                          typename Store<S>::T *__restrict__ mux,
+                                          typename Store<S>::T *__restrict__ muy, int pb = 0, int mov_pending = 0,
+                                          bool win = false, const BandRot &xr = BandRot()) {
   using T = typename Store<S>::T;
   constexpr int NT = BX * BY;
   const TileCell t = tile_cell<S, BX, BY>(tile, P);
@@ -1197,8 +1225,8 @@ __device__ __forceinline__ void step_tile(
           hit = hit || in_hit_box<BX, BY>(P.mov[k].B[sread].x, P.mov[k].B[sread].y, P.mov[k].half, t.tx, t.ty);
         if (hit) return;
       } else {
-        mwg = mover_prologue<T, BX, BY>(t.tx, t.ty, P, ctl, me_prev, hist, cap, maxb, pb, mov_pending, SPLIT, ml,
-                                        xr);
+        mwg = mover_prologue<T, BX, BY>(t.tx, t.ty, P, fb.ctl(), fb.me_prev(), fb.hist(), fb.cap(), fb.maxb(), pb,
+                                        mov_pending, SPLIT, ml, xr);
       }
     }
   }
@@ -1226,23 +1254,23 @@ __device__ __forceinline__ void step_tile(
           other = nb;
         }
       }
-      if (two) atomicOr(&ctl->err, 2);
+      if (two) atomicOr(&fb.ctl()->err, 2);
       const int sb = ml.smp[t.ly * BX + t.lx];
-      if (sb & (sb - 1)) atomicOr(&ctl->err, 4);  // a node sampled for two disks
+      if (sb & (sb - 1)) atomicOr(&fb.ctl()->err, 4);  // a node sampled for two disks
       m = (uint8_t)(own | (iface ? M_IFACE : 0) | (sb ? M_SAMPLE : 0));
     }
-    cell_update<S, BX, BY, MACRO, TRT, AA, MOV>(t, d, m, fout, mask, P, ctl, si_map, imap, me_out, sig_out, mrho,
-                                                 mux, muy, ml, acc, bid, sg);
+    cell_update<S, BX, BY, MACRO, TRT, AA, MOV>(t, d, m, fout, mask, P, fb, mrho, mux, muy, ml, acc, bid, sg);
   }
   if constexpr (MOV) {
-    if (mwg) mover_epilogue<T, BX, BY>(t.tx, t.ty, P, acc, bid, sg, me_out, ml);
+    if (mwg) mover_epilogue<T, BX, BY>(t.tx, t.ty, P, acc, bid, sg, fb.me_out(), ml);
   }
 
   if (fin_prev && tile == 0) {
     // forces of the previous step (same slots and records: only static
     // bodies defer)
     __shared__ double lds[FIN_WAVES * 6];
-    finalize_block<NT>(me_prev, sig_prev, recs, bt, ctl, hist, cap, maxb, lds);
+    finalize_block<NT>(fb.me_prev(), fb.sig_prev(), fb.recs(), fb.bt(), fb.ctl(), fb.hist(), fb.cap(), fb.maxb(),
+                       lds);
   }
 }
 
@@ -1326,9 +1354,9 @@ __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
       if (i >= len) return;
       tile = start + i;
     }
-    step_tile<S, BX, BY, MACRO, TRT, AA, true, true>(tile, fin, fout, mask, P, ctl, recs, si_map, imap, bt, me_out,
-                                                     me_prev, sig_out, sig_prev, 0, hist, cap, maxb, mrho, mux, muy,
-                                                     pb, mov_pending, win);
+    const ArgBufs fb{ctl, recs, si_map, imap, bt, me_out, me_prev, sig_out, sig_prev, hist, cap, maxb};
+    step_tile<S, BX, BY, MACRO, TRT, AA, true, true>(tile, fin, fout, mask, P, fb, 0, mrho, mux, muy, pb, mov_pending,
+                                                     win);
     return;
   }
   // XCD-aware tile order: consecutive workgroups go round-robin over the 8
@@ -1343,9 +1371,8 @@ __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
   int t = i + P.rot[xcd];
   t -= t >= len ? len : 0;
   const int tile = start + t;
-  step_tile<S, BX, BY, MACRO, TRT, AA, MOV>(tile, fin, fout, mask, P, ctl, recs, si_map, imap, bt, me_out, me_prev,
-                                            sig_out, sig_prev, fin_prev, hist, cap, maxb, mrho, mux, muy, pb,
-                                            mov_pending);
+  const ArgBufs fb{ctl, recs, si_map, imap, bt, me_out, me_prev, sig_out, sig_prev, hist, cap, maxb};
+  step_tile<S, BX, BY, MACRO, TRT, AA, MOV>(tile, fin, fout, mask, P, fb, fin_prev, mrho, mux, muy, pb, mov_pending);
 }
 
 // Per-lattice description for the batched step: one launch covers the tiles
@@ -1444,6 +1471,42 @@ template <typename T> __device__ __forceinline__ void global_ptrs(StepArgs<T> &P
   P.pts = gp(P.pts);
 }
 
+// The force terms' buffers and body tables of a batched launch's lattice
+// (see ArgBufs), read from its description where a cell needs them: held
+// from the workgroup's start they would take some twenty scalar registers,
+// which the compiler spills one read at a time before the first population
+// load.  pb: the parity of the step the launch computes.
+template <typename T> struct DescBufs {
+  const CaseDesc<T> *C;
+  int pb;
+  __device__ Ctl *ctl() const { return gp(C->ctl); }
+  __device__ const SiRec *recs() const { return gp(C->recs); }
+  __device__ const int *si_map() const { return gp(C->si_map); }
+  __device__ const int *imap() const { return gp(C->imap); }
+  __device__ const BodyTab *bt() const { return gp((const BodyTab *)C->bt); }
+  __device__ double *me_out() const { return gp(C->me[pb]); }
+  __device__ const double *me_prev() const { return gp((const double *)C->me[pb ^ 1]); }
+  __device__ double *sig_out() const { return gp(C->sig[pb]); }
+  __device__ const double *sig_prev() const { return gp((const double *)C->sig[pb ^ 1]); }
+  __device__ double *hist() const { return gp(C->hist); }
+  __device__ int cap() const { return C->cap; }
+  __device__ int maxb() const { return C->maxb; }
+};
+
+// The buffers a batched launch's tile code reaches: read where used
+// (DescBufs) without moving disks; with moving disks every workgroup of a
+// lattice with disks reaches some of them in its hit test, and reads made
+// there, one after another, cost more than reading all of them at the start
+// (ArgBufs).
+template <bool MOV, typename T>
+__device__ __forceinline__ auto batch_bufs(const CaseDesc<T> *__restrict__ C, int pb) {
+  if constexpr (MOV)
+    return ArgBufs{C->ctl, C->recs, C->si_map, C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
+                   C->hist, C->cap, C->maxb};
+  else
+    return DescBufs<T>{C, pb};
+}
+
 // The place of workgroup b of a batched launch: its global tile (gtile) and
 // the lattice of that tile, or -1 for none.  The workgroups go round-robin
 // over the 8 XCDs, and XCD x takes the band of per_xcd consecutive tiles
@@ -1511,12 +1574,10 @@ __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
   const int mov_pending = first ? mpend0 : 1;
   const S *fin = gp((const S *)C->buf[par]);
   S *fout = gp((S *)C->buf[par ^ 1]);
-  // (the pointers of the force terms serve interface and sample cells only:
-  // read where used)
-  step_tile<S, BX, BY, false, TRT, 0, MOV>(gtile - C->tile0, fin, fout, gp(C->mask), P, C->ctl, C->recs, C->si_map,
-                                           C->imap, C->bt, C->me[pb], C->me[pb ^ 1], C->sig[pb], C->sig[pb ^ 1],
-                                           fin_prev, C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb,
-                                           mov_pending, false,
+  // (the force terms' buffers serve interface and sample cells, the finalize
+  // and the disks' work only: read where used)
+  step_tile<S, BX, BY, false, TRT, 0, MOV>(gtile - C->tile0, fin, fout, gp(C->mask), P, batch_bufs<MOV>(C, pb),
+                                           fin_prev, nullptr, nullptr, nullptr, pb, mov_pending, false,
                                            (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));
 }
 
@@ -1546,15 +1607,13 @@ __global__ void __launch_bounds__(256, (step_waves_mov<S, MOV>()))
   const int mov_pending = first ? mpend0 : 1;
   S *F = gp((S *)C->buf[0]);
   if (pb)
-    step_tile<S, 64, 4, false, TRT, 1, MOV>(gtile - C->tile0, nullptr, F, gp(C->mask), P, C->ctl, C->recs, C->si_map,
-                                            C->imap, C->bt, C->me[1], C->me[0], C->sig[1], C->sig[0], fin_prev,
-                                            C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb, mov_pending,
-                                            false, (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));
+    step_tile<S, 64, 4, false, TRT, 1, MOV>(gtile - C->tile0, nullptr, F, gp(C->mask), P, batch_bufs<MOV>(C, pb),
+                                            fin_prev, nullptr, nullptr, nullptr, pb, mov_pending, false,
+                                            (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));
   else
-    step_tile<S, 64, 4, false, TRT, 2, MOV>(gtile - C->tile0, nullptr, F, gp(C->mask), P, C->ctl, C->recs, C->si_map,
-                                            C->imap, C->bt, C->me[0], C->me[1], C->sig[0], C->sig[1], fin_prev,
-                                            C->hist, C->cap, C->maxb, nullptr, nullptr, nullptr, pb, mov_pending,
-                                            false, (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));
+    step_tile<S, 64, 4, false, TRT, 2, MOV>(gtile - C->tile0, nullptr, F, gp(C->mask), P, batch_bufs<MOV>(C, pb),
+                                            fin_prev, nullptr, nullptr, nullptr, pb, mov_pending, false,
+                                            (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));
 }
 
 template <int NT>
