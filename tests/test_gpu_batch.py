@@ -248,6 +248,33 @@ def test_aa_batch_equals_alone_bitwise(precision):
         g.close()
 
 
+def test_aa_batch_with_a_moving_disk_above_the_rotation_limit():
+    # AA lattices with a moving disk batched with a static lattice of 8320
+    # tiles (64x4): the launches exceed the band rotation's 8192 tiles and
+    # run the moving-disk kernel without it until the static lattice is
+    # done, then with it; every lattice as alone, bit for bit
+    from paper_2110_00967_amd import vplbm as V
+    specs = [mixed_specs()[2],
+             spec(2048, 1040, tau=0.6, edges=((V_, 0.03, 0), (OUT, 0, 0), (F, 0, 0), (F, 0, 0)),
+                  init=("fields",) + random_fields(2048, 1040, 11, amp=0.01))]
+    assert specs[0]["dynamics"] is not None
+    nsteps = [23, 14]
+    say("AA batch, a moving disk and a 2048x1040 lattice, f32, steps", nsteps)
+    solo = [build_gpu(s, "f32", streaming=V.STREAM_AA) for s in specs]
+    for g, n in zip(solo, nsteps):
+        step_eager(g, n)
+    lats = [build_gpu(s, "f32", streaming=V.STREAM_AA) for s in specs]
+    b = V.Batch(lats)
+    b.step(nsteps)
+    for k, (g, ref) in enumerate(zip(lats, solo)):
+        assert g.step_count == nsteps[k]
+        for a, r in zip(state(g), state(ref)):
+            assert np.array_equal(a, r), k
+    b.close()
+    for g in solo + lats:
+        g.close()
+
+
 def test_batch_rejects_mixed_storage():
     from paper_2110_00967_amd import vplbm as V
     specs = mixed_specs()[:2]
