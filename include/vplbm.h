@@ -383,7 +383,11 @@ const char *vplbm_batch_last_error(const vplbm_batch *b);
 /* Advance lattice k by nsteps[k] steps of Sec. 2.2 (0 = idle);
  * asynchronous.  Lattices with steps left run together; a lattice drops out
  * when its count is reached.  Forces (Sec. 2.3), histories and states are
- * read per lattice afterwards. */
+ * read per lattice afterwards.  Launches with moving disks (Sec. 3.2) order
+ * their tiles by where the disks were a step before, kept in 144 bytes of
+ * static device memory per GPU that every batch shares: batches stepped at
+ * the same time on one GPU may order each other's work less well, with the
+ * same results. */
 int vplbm_batch_step(vplbm_batch *b, const int *nsteps);
 /* Replace the lattices of a batch (the rules of vplbm_batch_create; the
  * same precision, collision, stream and storage as the batch's first
