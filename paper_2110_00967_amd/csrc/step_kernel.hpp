@@ -586,9 +586,8 @@ struct BandRot {
 // after it, it sets epoch[f ^ 1] = epoch[f] + 1 and records keys[f ^ 1]
 // (atomic maximum: several disks in a band keep the earliest).  A slot is
 // never written by the launch that reads it.  One per device, at a fixed
-// address, so that a workgroup reads it together with its kernel
-// arguments (a pointer argument would cost a second dependent read before
-// the tile is known); zero at load.  Batches that run at the same time on
+// address, so that its reads need nothing read first (a pointer argument
+// would add a dependent read before the tile is known); zero at load.  Batches that run at the same time on
 // one device share it: their rotations then mix, which orders their work
 // less well and changes no result.
 struct BandState {
@@ -916,8 +915,10 @@ __device__ __forceinline__ void load_cell(const TileCell &t, const S *__restrict
 // interface cell), bt (body table), me_out / me_prev and sig_out / sig_prev
 // (interface and sample-node terms of this step and the step before), hist
 // (force history ring of cap entries of maxb bodies).  ArgBufs holds them as
-// the single-lattice kernel's arguments; a batched launch reads them from
-// the lattice's description only where a cell needs them (DescBufs).
+// values: the single-lattice kernel's arguments, or what a batched launch
+// with moving disks reads from the lattice's description at the start; a
+// batched launch without them reads each only where a cell needs it
+// (DescBufs; batch_bufs chooses).
 struct ArgBufs {
   Ctl *ctl_;
   const SiRec *recs_;
@@ -1508,7 +1509,7 @@ __device__ __forceinline__ auto batch_bufs(const CaseDesc<T> *__restrict__ C, in
 }
 
 // The place of workgroup b of a batched launch: its global tile (gtile) and
-// the lattice of that tile, or -1 for none.  The workgroups go round-robin
+// the description of that tile's lattice, or null for none.  The workgroups go round-robin
 // over the 8 XCDs, and XCD x takes the band of per_xcd consecutive tiles
 // from x * per_xcd (shared halo lines stay in its L2).  With moving disks
 // (ROT) band x starts r tiles in and wraps round, so that the long serial
@@ -1516,8 +1517,8 @@ __device__ __forceinline__ auto batch_bufs(const CaseDesc<T> *__restrict__ C, in
 // workgroups instead of wherever the disk sits: r from the band's key
 // (band_key) the launch before recorded (mover_prologue); a key of another
 // epoch (stale, or none yet) or a rotation outside the band counts as r = 0.
-// The keys and epochs of both flips are read first, with the kernel
-// arguments.  Any r gives the same results: it only orders the work.
+// The band state lives at a fixed address, so its reads need nothing read
+// before them.  Any r gives the same results: it only orders the work.
 template <bool ROT, typename CD>
 __device__ __forceinline__ const CD *batch_place(int b, int total_tiles, int per_xcd, const BlockCase *__restrict__ table,
                                                  const CD *cases, int flip, int &gtile, unsigned long long &epoch) {
@@ -1527,11 +1528,8 @@ __device__ __forceinline__ const CD *batch_place(int b, int total_tiles, int per
     if (gtile >= total_tiles) return nullptr;
     return cases + tile_lattice(table, gtile);
   } else {
-    // no branch before the table read: the band state (both flips', at
-    // addresses that need nothing read first) then goes out with the kernel
-    // arguments, where a read the compiler moved below an early exit would
-    // wait for a round trip of its own; a workgroup without tile reads the
-    // table at the last tile and leaves after it
+    // (both flips' keys and epochs, chosen by flip afterwards; a workgroup
+    // without tile reads the table at the last tile and leaves after it)
     const unsigned long long k0 = g_band.keys[0][x], k1 = g_band.keys[1][x];
     const unsigned long long e0 = g_band.epoch[0], e1 = g_band.epoch[1];
     const unsigned long long key = flip ? k1 : k0;
@@ -1575,7 +1573,7 @@ __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
   const S *fin = gp((const S *)C->buf[par]);
   S *fout = gp((S *)C->buf[par ^ 1]);
   // (the force terms' buffers serve interface and sample cells, the finalize
-  // and the disks' work only: read where used)
+  // and the disks' work only: read where used unless MOV, see batch_bufs)
   step_tile<S, BX, BY, false, TRT, 0, MOV>(gtile - C->tile0, fin, fout, gp(C->mask), P, batch_bufs<MOV>(C, pb),
                                            fin_prev, nullptr, nullptr, nullptr, pb, mov_pending, false,
                                            (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));
