@@ -475,6 +475,15 @@ template <int BX, int BY> struct MovLds {
   PtPlace pl[BX * BY];               // point t of the disks as placed by thread t
 };
 
+// The kernel's one MovLds of its tile shape.  A kernel that inlines the tile
+// code twice (the batched AA kernel: odd and even launches) shares it
+// between the copies instead of holding two, which would halve the
+// workgroups an LDS of 160 KB holds (26.7 KB each at 64x4).
+template <int BX, int BY> __device__ __forceinline__ MovLds<BX, BY> &mov_lds() {
+  __shared__ MovLds<BX, BY> ml;
+  return ml;
+}
+
 // The points of all moving disks are numbered disk by disk: disk k holds
 // [pt1 of disk k - 1, pt1 of disk k).  The disk of point i:
 __device__ __forceinline__ int point_disk(const int (&pt1)[MAX_MOVERS], int nmov, int i) {
@@ -1213,7 +1222,7 @@ __device__ __forceinline__ void step_tile(int tile, const S *__restrict__ fin, S
 
   // moving disks: the states of this step and the tile's flags (LDS)
   bool mwg = false;  // the tile meets a disk's window
-  __shared__ MovLds<(MOV ? BX : 1), (MOV ? BY : 1)> ml;
+  MovLds<(MOV ? BX : 1), (MOV ? BY : 1)> &ml = mov_lds<(MOV ? BX : 1), (MOV ? BY : 1)>();
   if constexpr (MOV) {
     if (P.nmov > 0) {
       if (SPLIT && !win) {
