@@ -1592,8 +1592,11 @@ __global__ void __launch_bounds__(BX *BY, (step_waves_mov<S, MOV>()))
 // the launch computing an odd step pulls and pushes (AA = 1), an even step
 // stays in the cell (AA = 2), per lattice by its own step parity; the
 // perimeter copies alternate with it (read: the previous step's, written:
-// this step's).
-template <typename S, bool TRT, bool MOV = false, bool ROT = false>
+// this step's).  PAR = 1 or 2: every lattice of the launch computes an odd
+// (1) or an even (2) step, and the kernel holds that tile code only; PAR = 0
+// (lattices of mixed parity) holds both, chosen per lattice, whose combined
+// register pressure makes the 2-byte kernel spill its scalars far more.
+template <typename S, bool TRT, bool MOV = false, bool ROT = false, int PAR = 0>
 __global__ void __launch_bounds__(256, (step_waves_mov<S, MOV>()))
     k_step_batch_aa(const CaseDesc<typename Store<S>::T> *__restrict__ cases,
                     const BlockCase *__restrict__ table, int total_tiles, int per_xcd, int flip, int first) {
@@ -1606,14 +1609,14 @@ __global__ void __launch_bounds__(256, (step_waves_mov<S, MOV>()))
   if (MOV && ROT && blockIdx.x == 0 && threadIdx.x == 0) g_band.epoch[flip ^ 1] = epoch + 1;
   StepArgs<T> P = C->P;
   global_ptrs(P);
-  const int pb = C->pbit0 ^ flip;
+  const int pb = PAR ? (PAR == 1 ? 1 : 0) : C->pbit0 ^ flip;
   P.ec_in = gp(C->ec[pb ^ 1]);
   P.ec_out = gp(C->ec[pb]);
   const int pend0 = C->pending0, mpend0 = C->mov_pending0;
   const int fin_prev = P.nmov ? 0 : (first ? pend0 : 1);
   const int mov_pending = first ? mpend0 : 1;
   S *F = gp((S *)C->buf[0]);
-  if (pb)
+  if (PAR == 1 || (PAR == 0 && pb))
     step_tile<S, 64, 4, false, TRT, 1, MOV>(gtile - C->tile0, nullptr, F, gp(C->mask), P, batch_bufs<MOV>(C, pb),
                                             fin_prev, nullptr, nullptr, nullptr, pb, mov_pending, false,
                                             (ROT ? BandRot{flip, C->tile0, per_xcd} : BandRot()));

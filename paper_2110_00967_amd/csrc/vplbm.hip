@@ -1939,9 +1939,10 @@ int vplbm_read_mask(vplbm_lattice *L, uint8_t *out) {
 // tables' contents: the launch shape and arguments.
 struct GraphKey {
   int nact = -1, bx = 0, mov = 0;
+  int aapar = -1;  // AA batches: the parity of the flip-0 launches' steps when every lattice shares it
   long long total = 0;
   bool operator==(const GraphKey &o) const {
-    return nact == o.nact && bx == o.bx && mov == o.mov && total == o.total;
+    return nact == o.nact && bx == o.bx && mov == o.mov && aapar == o.aapar && total == o.total;
   }
   bool operator!=(const GraphKey &o) const { return !(*this == o); }
 };
@@ -1990,6 +1991,7 @@ struct BatchExec {
   int prec = 0;
   bool trt = false, aa = false;
   bool mov = false;  // some active lattice has moving disks (the chunk's kernels handle them; 64x4 tiles)
+  int aapar0 = -1;   // AA: parity of the step every lattice computes in flip-0 launches (-1: mixed)
   int bx = 64, by = 4;
   hipStream_t stream = nullptr;
   char *desc_dev = nullptr;   // descriptors, one per active lattice
@@ -2061,15 +2063,31 @@ void launch_batch_ab(const BatchExec &X, hipStream_t st, dim3 grid, int total, i
                        total, per, flip, first);
 }
 
-template <typename S, bool MOV, bool ROT = false>
-void launch_batch_aa(const BatchExec &X, hipStream_t st, dim3 grid, int total, int per, int flip, int first) {
+template <typename S, bool TRT, bool MOV, bool ROT>
+void launch_aa_par(int par, const BatchExec &X, hipStream_t st, dim3 grid, int total, int per, int flip,
+                   int first) {
   const auto *descs = (const CaseDesc<typename Store<S>::T> *)X.desc_dev;
-  if (X.trt)
-    hipLaunchKernelGGL((k_step_batch_aa<S, true, MOV, ROT>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per,
+  if (par == 1)
+    hipLaunchKernelGGL((k_step_batch_aa<S, TRT, MOV, ROT, 1>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per,
+                       flip, first);
+  else if (par == 2)
+    hipLaunchKernelGGL((k_step_batch_aa<S, TRT, MOV, ROT, 2>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per,
                        flip, first);
   else
-    hipLaunchKernelGGL((k_step_batch_aa<S, false, MOV, ROT>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per,
+    hipLaunchKernelGGL((k_step_batch_aa<S, TRT, MOV, ROT, 0>), grid, dim3(256), 0, st, descs, X.tile_dev, total, per,
                        flip, first);
+}
+
+// AA batches: the kernel holding only the odd (1) or the even (2) tile code
+// when every lattice of the launch computes a step of that parity, else the
+// one that chooses per lattice (0)
+template <typename S, bool MOV, bool ROT = false>
+void launch_batch_aa(const BatchExec &X, hipStream_t st, dim3 grid, int total, int per, int flip, int first) {
+  const int par = X.aapar0 < 0 ? 0 : ((X.aapar0 ^ flip) ? 1 : 2);
+  if (X.trt)
+    launch_aa_par<S, true, MOV, ROT>(par, X, st, grid, total, per, flip, first);
+  else
+    launch_aa_par<S, false, MOV, ROT>(par, X, st, grid, total, per, flip, first);
 }
 
 // Batched launches with moving disks of at most this many (64x4) tiles
@@ -2194,6 +2212,13 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
       }
       total += batch_tiles(L, bx, by);
     }
+    X.aapar0 = -1;
+    if (X.aa) {
+      const int p0 = (int)((lats[act[0]]->nstep + 1) & 1);
+      bool same = true;
+      for (int k : act) same = same && (int)((lats[k]->nstep + 1) & 1) == p0;
+      X.aapar0 = same ? p0 : -1;
+    }
     if (total > X.tile_cap)
       return fail(VPLBM_EINVAL, "the batch's " + std::to_string(total) + " tiles exceed the tile table (" +
                                     std::to_string(X.tile_cap) + ")");
@@ -2221,6 +2246,7 @@ int batch_run(BatchExec &X, vplbm_lattice *const *lats, int n, const int *nsteps
       key.nact = nact;
       key.bx = bx;
       key.mov = X.mov ? 1 : 0;
+      key.aapar = X.aapar0;
       key.total = total;
       if (!*X.graph || *X.graph_key != key) {
         if (*X.graph) (void)hipGraphExecDestroy(*X.graph);
